@@ -1,0 +1,769 @@
+/*
+ * vsh_oracle.c -- serial FP64 reference ("oracle") for the parallel
+ * Sudakov-veto parton shower (Seymour & Sule, arXiv:2403.08692).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the product library, and
+ * sharing no source with it.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared vsh_oracle.c -lm
+ *
+ * Structure, in the paper's order:
+ *   random numbers ..... Philox4x32-10 from its published definition, keyed
+ *                        by (seed, event, cycle, purpose, slot)
+ *   matrix element ..... Appendix B: random flavour, LO |M|^2 for
+ *                        e+e- -> Z/gamma -> q qbar, differential cross-section
+ *   shower ............. Appendix A: SelectWinnerEmission (splitter x
+ *                        spectator x kernel, strict maximum above t_C),
+ *                        GenerateEmission (veto, kinematics, colours, append),
+ *                        main loop from t = s down to t_C
+ *   observables ........ Section 3.1: Durham y23/y34, exact thrust by the
+ *                        O(N^3) plane enumeration, heavy-jet mass, jet
+ *                        broadenings, C-parameter; event validation
+ *   histograms ......... 50 uniform bins + under/overflow, weighted
+ *
+ * Physics inputs the paper does not print (electroweak constants, the
+ * splitting kernels, the recoil map, the colour assignment, alpha_s running)
+ * are the Catani-Seymour final-final dipole shower in the leading-colour
+ * limit with one-loop running; each choice is named where it is used.
+ */
+#include "vsh_oracle.h"
+
+#include <math.h>
+#include <stddef.h>
+#include <string.h>
+
+#define OR_PI 3.14159265358979323846
+
+/* ---------------------------------------------------------------------- */
+/* Constants.  QCD colour factors; electroweak inputs at the Z pole.       */
+/* ---------------------------------------------------------------------- */
+static const double CF = 4.0 / 3.0;
+static const double CA = 3.0;
+static const double TR = 0.5;
+static const double NC = 3.0;
+static const int NF = 5;
+static const double MZ = 91.1876;
+static const double GAMMAZ = 2.4952;
+static const double MW = 80.385;
+static const double ALPHA_EM = 1.0 / 128.802;
+static const double ASMZ = 0.118;
+static const double GEV2_TO_PB = 0.389379656e9;
+
+/* ---------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies; the    */
+/* key is bumped by the Weyl constants between rounds.                      */
+/* ---------------------------------------------------------------------- */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t y0 = (uint32_t)(prod1 >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)prod1;
+    uint32_t y2 = (uint32_t)(prod0 >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)prod0;
+    x0 = y0;
+    x1 = y1;
+    x2 = y2;
+    x3 = y3;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+double or_uniform(uint32_t hi, uint32_t lo) {
+  uint64_t m = ((uint64_t)(hi >> 12) << 32) | (uint64_t)lo; /* 52 random bits */
+  return (double)(2 * m + 1) * 0x1p-53;
+}
+
+/* Random-number contract: every draw is one Philox block whose counter is
+   (event low word, event high word, cycle, purpose << 24 | slot) and whose
+   key is (seed low word, seed high word).  Draws therefore depend only on
+   what they are for, never on the order in which anything is evaluated. */
+void or_draw(uint64_t seed, uint64_t event, uint32_t cycle, uint32_t purpose,
+             uint32_t slot, uint32_t out[4]) {
+  uint32_t ctr[4] = {(uint32_t)event, (uint32_t)(event >> 32), cycle,
+                     (purpose << 24) | (slot & 0xFFFFFFu)};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  or_philox4x32_10(ctr, key, out);
+}
+
+/* Trial slot of kernel number j (0-based position in the splitter's kernel
+   list) of the dipole end with splitter i and spectator k: each Philox block
+   serves two consecutive kernels of the list, words (0,1) the even one and
+   words (2,3) the odd one. */
+static uint32_t trial_slot(int i, int k, int j) {
+  return ((uint32_t)i << 14) | ((uint32_t)k << 4) | (uint32_t)(j >> 1);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Strong coupling: one-loop running with five flavours, fixed at         */
+/* alpha_s(M_Z^2) = 0.118 (the value quoted with the jet-rate figure);    */
+/* evaluated at the transverse momentum squared of the emission.           */
+/* ---------------------------------------------------------------------- */
+double or_alpha_s(double t) {
+  double b0 = (33.0 - 2.0 * NF) / (12.0 * OR_PI);
+  return ASMZ / (1.0 + ASMZ * b0 * log(t / (MZ * MZ)));
+}
+
+/* ---------------------------------------------------------------------- */
+/* Splitting kernels.  Catani-Seymour final-final dipole kernels with the   */
+/* leading-colour split of a gluon's colour charge over its two colour      */
+/* partners; y is the dipole recoil variable, z the splitter's momentum     */
+/* fraction.  Each kernel has an overestimate that is analytically          */
+/* integrable and invertible in z (the P^over of Appendix A).               */
+/*   0-4   q -> q g     (splitter d, u, s, c, b)                            */
+/*   5-9   qbar -> qbar g                                                   */
+/*   10    g -> g g                                                         */
+/*   11-15 g -> f fbar  (f = d, u, s, c, b)                                 */
+/* ---------------------------------------------------------------------- */
+int or_kernel_list(int pid, int out[6]) {
+  if (pid >= 1 && pid <= 5) {
+    out[0] = pid - 1;
+    return 1;
+  }
+  if (pid <= -1 && pid >= -5) {
+    out[0] = 4 - pid;
+    return 1;
+  }
+  if (pid == 21) {
+    for (int j = 0; j < 6; ++j) out[j] = 10 + j;
+    return 6;
+  }
+  return 0;
+}
+
+double or_kernel_value(int K, double z, double y) {
+  if (K < 10) return CF * (2.0 / (1.0 - z * (1.0 - y)) - (1.0 + z));
+  if (K == 10) return 0.5 * CA * (2.0 / (1.0 - z * (1.0 - y)) - 2.0 + z * (1.0 - z));
+  return 0.5 * TR * (1.0 - 2.0 * z * (1.0 - z));
+}
+
+double or_kernel_over(int K, double z) {
+  if (K < 10) return 2.0 * CF / (1.0 - z);
+  if (K == 10) return CA / (1.0 - z);
+  return 0.5 * TR;
+}
+
+double or_kernel_integral(int K, double zm, double zp) {
+  if (K < 10) return 2.0 * CF * log((1.0 - zm) / (1.0 - zp));
+  if (K == 10) return CA * log((1.0 - zm) / (1.0 - zp));
+  return 0.5 * TR * (zp - zm);
+}
+
+/* inverse of the overestimate's normalised integral from zm (eq. for z) */
+double or_kernel_zgen(int K, double zm, double zp, double u) {
+  if (K <= 10) return 1.0 - (1.0 - zm) * pow((1.0 - zp) / (1.0 - zm), u);
+  return zm + (zp - zm) * u;
+}
+
+/* ---------------------------------------------------------------------- */
+/* LO matrix element for e+e- -> (gamma or Z) -> q qbar (Appendix B), massless   */
+/* quarks; e- along +z and theta the angle between the e- and the quark.   */
+/* Summed over final and averaged over initial helicities and colours.     */
+/* ---------------------------------------------------------------------- */
+static void fermion_couplings(int flavour, double sw2, double *q, double *v, double *a) {
+  int up_type = (flavour == 2 || flavour == 4);
+  double t3 = up_type ? 0.5 : -0.5;
+  *q = up_type ? 2.0 / 3.0 : -1.0 / 3.0;
+  *a = t3;
+  *v = t3 - 2.0 * (*q) * sw2;
+}
+
+static void ew_factors(double s, double *chi1, double *chi2, double *sw2_out) {
+  double sw2 = 1.0 - (MW / MZ) * (MW / MZ);
+  double kappa = 1.0 / (4.0 * sw2 * (1.0 - sw2));
+  double mz2 = MZ * MZ;
+  double den = (s - mz2) * (s - mz2) + GAMMAZ * GAMMAZ * mz2;
+  *chi1 = kappa * s * (s - mz2) / den;
+  *chi2 = kappa * kappa * s * s / den;
+  *sw2_out = sw2;
+}
+
+/* angular coefficients: |M|^2 = (4 pi alpha)^2 N_c [A (1 + c^2) + B c] */
+static void angular_coefficients(int flavour, double s, double *A, double *B) {
+  double chi1, chi2, sw2;
+  ew_factors(s, &chi1, &chi2, &sw2);
+  double qe, ve, ae, qf, vf, af;
+  qe = -1.0;
+  ae = -0.5;
+  ve = -0.5 + 2.0 * sw2;
+  fermion_couplings(flavour, sw2, &qf, &vf, &af);
+  *A = qe * qe * qf * qf + 2.0 * qe * qf * ve * vf * chi1 +
+       (ae * ae + ve * ve) * (af * af + vf * vf) * chi2;
+  *B = 4.0 * qe * qf * ae * af * chi1 + 8.0 * ae * af * ve * vf * chi2;
+}
+
+double or_me2(int flavour, double s, double cos_theta) {
+  double A, B;
+  angular_coefficients(flavour, s, &A, &B);
+  double e2 = 4.0 * OR_PI * ALPHA_EM;
+  return e2 * e2 * NC * (A * (1.0 + cos_theta * cos_theta) + B * cos_theta);
+}
+
+/* total LO cross-section over the five flavours, in pb: the integral of
+   |M|^2 / (32 pi s) over cos(theta) in [-1, 1] */
+double or_sigma_lo(double s) {
+  double total = 0.0;
+  for (int f = 1; f <= NF; ++f) {
+    double A, B;
+    angular_coefficients(f, s, &A, &B);
+    total += 4.0 * OR_PI * ALPHA_EM * ALPHA_EM * NC * A / (3.0 * s);
+  }
+  return total * GEV2_TO_PB;
+}
+
+/* One LO event: a uniform flavour (weight x5), uniform cos(theta) and phi;
+   the weight is the differential cross-section over the sampling density,
+   5 |M|^2 / (16 pi s), in pb.  Outputs p[0..3] quark, p[4..7] antiquark. */
+void or_me_event(uint64_t seed, uint64_t event, double ecm, int *flavour,
+                 double *cos_theta, double *phi, double *weight, double p[8]) {
+  uint32_t w[4];
+  or_draw(seed, event, 0, OR_P_ME, 0, w);
+  int f = 1 + (int)(((uint64_t)w[0] * 5u) >> 32);
+  double c = 2.0 * or_uniform(w[2], w[3]) - 1.0;
+  or_draw(seed, event, 0, OR_P_ME, 1, w);
+  double ph = 2.0 * OR_PI * or_uniform(w[0], w[1]);
+  double s = ecm * ecm;
+  double wt = 5.0 * or_me2(f, s, c) / (16.0 * OR_PI * s) * GEV2_TO_PB;
+  double st = sqrt((1.0 - c) * (1.0 + c));
+  double e = 0.5 * ecm;
+  double px = e * st * cos(ph), py = e * st * sin(ph), pz = e * c;
+  p[0] = e;
+  p[1] = px;
+  p[2] = py;
+  p[3] = pz;
+  p[4] = e;
+  p[5] = -px;
+  p[6] = -py;
+  p[7] = -pz;
+  *flavour = f;
+  *cos_theta = c;
+  *phi = ph;
+  *weight = wt;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Minkowski helpers, metric (+,-,-,-)                                      */
+/* ---------------------------------------------------------------------- */
+static double mdot(const double *a, const double *b) {
+  return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+
+/* v^mu = eps^{mu nu rho sigma} a_nu b_rho c_sigma with eps^{0123} = +1,
+   written with three-vectors:
+     v^0 = -a.(b x c),  v = -a0 (b x c) + b0 (a x c) - c0 (a x b)        */
+static void eps4(const double *a, const double *b, const double *c, double *v) {
+  double bc[3] = {b[2] * c[3] - b[3] * c[2], b[3] * c[1] - b[1] * c[3], b[1] * c[2] - b[2] * c[1]};
+  double ac[3] = {a[2] * c[3] - a[3] * c[2], a[3] * c[1] - a[1] * c[3], a[1] * c[2] - a[2] * c[1]};
+  double ab[3] = {a[2] * b[3] - a[3] * b[2], a[3] * b[1] - a[1] * b[3], a[1] * b[2] - a[2] * b[1]};
+  v[0] = -(a[1] * bc[0] + a[2] * bc[1] + a[3] * bc[2]);
+  for (int m = 0; m < 3; ++m) v[1 + m] = -a[0] * bc[m] + b[0] * ac[m] - c[0] * ab[m];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Catani-Seymour final-final map.  Emitter ~ij and spectator ~k, both    */
+/* massless, Q^2 = 2 p~ij.p~k; t = kT^2 = y z (1-z) Q^2:                   */
+/*   p_i = z p~ij + (1-z) y p~k + kT,  p_j = (1-z) p~ij + z y p~k - kT,     */
+/*   p_k = (1-y) p~k, with kT^2 = -t and kT orthogonal to both.             */
+/* The transverse basis: a reference axis r (the coordinate axis least      */
+/* aligned with E_k p_i - E_i p_k, the only spatial direction inside the    */
+/* span of the two momenta; ties to the lower axis), n1 = eps(pi,pk,r) and  */
+/* n2 = eps(pi,pk,n1), both normalised to n^2 = -1.                         */
+/* ---------------------------------------------------------------------- */
+void or_split_kinematics(const double pi[4], const double pk[4], double t,
+                         double z, double phi, double out_i[4],
+                         double out_j[4], double out_k[4]) {
+  double q2 = 2.0 * mdot(pi, pk);
+  double y = t / (q2 * z * (1.0 - z));
+  double kt = sqrt(t);
+  double d[3];
+  for (int m = 0; m < 3; ++m) d[m] = pk[0] * pi[1 + m] - pi[0] * pk[1 + m];
+  int ax = 0;
+  if (fabs(d[1]) < fabs(d[ax])) ax = 1;
+  if (fabs(d[2]) < fabs(d[ax])) ax = 2;
+  double r[4] = {0.0, 0.0, 0.0, 0.0};
+  r[1 + ax] = 1.0;
+  double n1[4], n2[4];
+  eps4(pi, pk, r, n1);
+  double norm1 = sqrt(-mdot(n1, n1));
+  for (int m = 0; m < 4; ++m) n1[m] /= norm1;
+  eps4(pi, pk, n1, n2);
+  double norm2 = sqrt(-mdot(n2, n2));
+  for (int m = 0; m < 4; ++m) n2[m] /= norm2;
+  double cphi = cos(phi), sphi = sin(phi);
+  for (int m = 0; m < 4; ++m) {
+    double kperp = kt * (cphi * n1[m] + sphi * n2[m]);
+    out_i[m] = z * pi[m] + (1.0 - z) * y * pk[m] + kperp;
+    out_j[m] = (1.0 - z) * pi[m] + z * y * pk[m] - kperp;
+    out_k[m] = (1.0 - y) * pk[m];
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Shower (Appendix A)                                                     */
+/* ---------------------------------------------------------------------- */
+/* leading-colour connection: i's colour flows into k's anticolour, or i's
+   anticolour into k's colour */
+static int colour_connected(int ci, int ai, int ck, int ak) {
+  return (ci != 0 && ci == ak) || (ai != 0 && ai == ck);
+}
+
+static uint64_t fnv_step(uint64_t h, uint32_t v) {
+  h ^= (uint64_t)v;
+  h *= 0x100000001b3ull;
+  return h;
+}
+
+int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
+              int max_emit, int *n, double *p, int *pid, int *col, int *acol,
+              int *cycles, uint64_t *emit_hash, int *n_emit,
+              double *emit_log, int max_log, uint64_t *work) {
+  int np = *n;
+  double t = ecm * ecm;              /* evolution starts at s */
+  double asmax = or_alpha_s(tcut);   /* alpha_s overestimate = alpha_s(t_C) */
+  int next_col = 1;
+  for (int i = 0; i < np; ++i) {
+    if (col[i] >= next_col) next_col = col[i] + 1;
+    if (acol[i] >= next_col) next_col = acol[i] + 1;
+  }
+  int status = OR_RUNNING;
+  uint32_t cycle = 0;
+  int nemit = 0;
+  uint64_t hash = 0xcbf29ce484222325ull;
+
+  while (status == OR_RUNNING) {
+    /* --- SelectWinnerEmission: every splitter, spectator, kernel ------- */
+    double winner_t = tcut;
+    int wi = -1, wk = -1, wK = -1;
+    double wq2 = 0.0, wzm = 0.0, wzp = 0.0;
+    for (int i = 0; i < np; ++i) {
+      for (int k = 0; k < np; ++k) {
+        if (i == k) continue;
+        if (!colour_connected(col[i], acol[i], col[k], acol[k])) continue;
+        if (work) work[1]++;
+        double q2 = 2.0 * mdot(&p[4 * i], &p[4 * k]);
+        if (!(q2 > 4.0 * tcut)) continue; /* no phase space above t_C */
+        if (work) work[2]++;
+        double zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * tcut / q2));
+        double zm = 1.0 - zp;
+        int kl[6];
+        int nk = or_kernel_list(pid[i], kl);
+        for (int j = 0; j < nk; ++j) {
+          int K = kl[j];
+          double c = asmax / (2.0 * OR_PI) * or_kernel_integral(K, zm, zp);
+          uint32_t w[4];
+          or_draw(seed, event, cycle, OR_P_TRIAL, trial_slot(i, k, j), w);
+          double u = (j & 1) ? or_uniform(w[2], w[3]) : or_uniform(w[0], w[1]);
+          double t_try = t * pow(u, 1.0 / c);
+          if (work) work[3]++;
+          if (t_try > winner_t) {
+            winner_t = t_try;
+            wi = i;
+            wk = k;
+            wK = K;
+            wq2 = q2;
+            wzm = zm;
+            wzp = zp;
+          }
+        }
+      }
+    }
+    uint32_t this_cycle = cycle++;
+    if (work) work[0]++;
+
+    /* --- cutoff ------------------------------------------------------ */
+    if (wi < 0) {
+      t = tcut;
+      status = OR_DONE;
+      break;
+    }
+    t = winner_t; /* the winner's scale bounds every later trial */
+
+    /* --- veto -------------------------------------------------------- */
+    uint32_t a[4];
+    or_draw(seed, event, this_cycle, OR_P_ACCEPT, 0, a);
+    double uz = or_uniform(a[0], a[1]);
+    double uv = or_uniform(a[2], a[3]);
+    double z = or_kernel_zgen(wK, wzm, wzp, uz);
+    double y = t / (wq2 * z * (1.0 - z));
+    int accept = 0;
+    if (y < 1.0) { /* inside the true phase space at this t */
+      if (work) work[5]++;
+      double prob = or_alpha_s(t) / asmax * or_kernel_value(wK, z, y) * (1.0 - y) /
+                    or_kernel_over(wK, z);
+      accept = uv < prob;
+    }
+    if (!accept) continue;
+
+    /* --- splitting --------------------------------------------------- */
+    if (np == cap) {
+      status = OR_OVERFLOW;
+      break;
+    }
+    uint32_t sdraw[4];
+    or_draw(seed, event, this_cycle, OR_P_SPLIT, 0, sdraw);
+    double phi = 2.0 * OR_PI * or_uniform(sdraw[0], sdraw[1]);
+    double ni[4], nj[4], nk4[4];
+    or_split_kinematics(&p[4 * wi], &p[4 * wk], t, z, phi, ni, nj, nk4);
+    for (int m = 0; m < 4; ++m) {
+      p[4 * wi + m] = ni[m];
+      p[4 * wk + m] = nk4[m];
+      p[4 * np + m] = nj[m];
+    }
+    /* colours and flavours; the colour side takes precedence */
+    int via_colour = (col[wi] != 0 && col[wi] == acol[wk]);
+    int jpid, jcol, jacol;
+    if (wK <= 10) { /* gluon emission: j sits between i and k */
+      int m = next_col++;
+      jpid = 21;
+      if (via_colour) {
+        jcol = col[wi];
+        jacol = m;
+        col[wi] = m;
+      } else {
+        jcol = m;
+        jacol = acol[wi];
+        acol[wi] = m;
+      }
+    } else { /* g -> f fbar: j is the parton colour-adjacent to k */
+      int f = wK - 10;
+      if (via_colour) {
+        jpid = f;
+        jcol = col[wi];
+        jacol = 0;
+        pid[wi] = -f;
+        col[wi] = 0;
+      } else {
+        jpid = -f;
+        jcol = 0;
+        jacol = acol[wi];
+        pid[wi] = f;
+        acol[wi] = 0;
+      }
+    }
+    pid[np] = jpid;
+    col[np] = jcol;
+    acol[np] = jacol;
+    if (emit_log && nemit < max_log) {
+      double *e = &emit_log[OR_NLOG * nemit];
+      e[0] = t;
+      e[1] = z;
+      e[2] = y;
+      e[3] = (double)wK;
+      e[4] = (double)wi;
+      e[5] = (double)wk;
+      e[6] = phi;
+    }
+    hash = fnv_step(hash, (uint32_t)wK);
+    hash = fnv_step(hash, (uint32_t)wi);
+    hash = fnv_step(hash, (uint32_t)wk);
+    ++np;
+    ++nemit;
+    if (work) work[4]++;
+    if (max_emit >= 0 && nemit >= max_emit) status = OR_STOPPED;
+  }
+  *n = np;
+  if (cycles) *cycles = (int)cycle;
+  if (emit_hash) *emit_hash = hash;
+  if (n_emit) *n_emit = nemit;
+  return status;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Observables (Section 3.1)                                               */
+/* ---------------------------------------------------------------------- */
+static double norm3(const double *v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+/* Exact thrust T = max_n sum|p.n| / sum|p|.  The optimal hemisphere split is
+   a plane through the origin; turning it until it touches two momenta
+   shows that it is one of the planes spanned by a pair (i, j), with i and j
+   themselves on either side: N(N-1)/2 planes x N dot products, plus the
+   four sign choices of i and j.  First maximum wins. */
+double or_thrust(int n, const double *p, double axis[3]) {
+  double sum = 0.0;
+  for (int a = 0; a < n; ++a) sum += norm3(&p[4 * a + 1]);
+  double best = -1.0, bv[3] = {0.0, 0.0, 1.0};
+  if (n < 3) {
+    /* all 2^n sign vectors directly */
+    for (int mask = 0; mask < (1 << n); ++mask) {
+      double v[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < n; ++a) {
+        double sg = (mask >> a & 1) ? -1.0 : 1.0;
+        for (int m = 0; m < 3; ++m) v[m] += sg * p[4 * a + 1 + m];
+      }
+      double m2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+      if (m2 > best) {
+        best = m2;
+        bv[0] = v[0];
+        bv[1] = v[1];
+        bv[2] = v[2];
+      }
+    }
+  } else {
+    static const double sgn[4][2] = {{1.0, 1.0}, {1.0, -1.0}, {-1.0, 1.0}, {-1.0, -1.0}};
+    for (int i = 0; i < n; ++i) {
+      for (int j = i + 1; j < n; ++j) {
+        const double *pi = &p[4 * i + 1], *pj = &p[4 * j + 1];
+        double nrm[3] = {pi[1] * pj[2] - pi[2] * pj[1], pi[2] * pj[0] - pi[0] * pj[2],
+                         pi[0] * pj[1] - pi[1] * pj[0]};
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < n; ++k) {
+          if (k == i || k == j) continue;
+          const double *pk = &p[4 * k + 1];
+          double d = pk[0] * nrm[0] + pk[1] * nrm[1] + pk[2] * nrm[2];
+          double sg = d > 0.0 ? 1.0 : -1.0;
+          for (int m = 0; m < 3; ++m) v[m] += sg * pk[m];
+        }
+        for (int c = 0; c < 4; ++c) {
+          double w[3];
+          for (int m = 0; m < 3; ++m) w[m] = v[m] + sgn[c][0] * pi[m] + sgn[c][1] * pj[m];
+          double m2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+          if (m2 > best) {
+            best = m2;
+            bv[0] = w[0];
+            bv[1] = w[1];
+            bv[2] = w[2];
+          }
+        }
+      }
+    }
+  }
+  double len = sqrt(best);
+  if (axis) {
+    if (len > 0.0) {
+      for (int m = 0; m < 3; ++m) axis[m] = bv[m] / len;
+    } else {
+      axis[0] = 0.0;
+      axis[1] = 0.0;
+      axis[2] = 1.0;
+    }
+  }
+  return sum > 0.0 ? len / sum : 0.0;
+}
+
+/* Durham (k_T) clustering with E-scheme recombination:
+   y_ab = 2 min(E_a^2, E_b^2) (1 - cos theta_ab) / s, written with
+   1 - cos theta = |u_a - u_b|^2 / 2 for unit vectors u.  y_{n,n+1} is the
+   smallest y at the step from n+1 to n pseudo-jets (0 if the event never
+   had n+1 partons).  Ties go to the lowest (a, b). */
+void or_durham(int n, const double *p, double s, double *y23, double *y34) {
+  enum { MAXJ = 1024 };
+  static double jet[MAXJ][4];
+  int m = n < MAXJ ? n : MAXJ;
+  for (int a = 0; a < m; ++a)
+    for (int c = 0; c < 4; ++c) jet[a][c] = p[4 * a + c];
+  *y23 = 0.0;
+  *y34 = 0.0;
+  while (m > 2) {
+    double ymin = 0.0;
+    int ba = -1, bb = -1;
+    for (int a = 0; a < m; ++a) {
+      double la = norm3(&jet[a][1]);
+      for (int b = a + 1; b < m; ++b) {
+        double lb = norm3(&jet[b][1]);
+        double d2 = 0.0;
+        for (int c = 1; c < 4; ++c) {
+          double dc = jet[a][c] / la - jet[b][c] / lb;
+          d2 += dc * dc;
+        }
+        double emin = jet[a][0] < jet[b][0] ? jet[a][0] : jet[b][0];
+        double y = emin * emin * d2 / s;
+        if (ba < 0 || y < ymin) {
+          ymin = y;
+          ba = a;
+          bb = b;
+        }
+      }
+    }
+    if (m == 4) *y34 = ymin;
+    if (m == 3) *y23 = ymin;
+    for (int c = 0; c < 4; ++c) jet[ba][c] += jet[bb][c];
+    for (int a = bb; a + 1 < m; ++a)
+      for (int c = 0; c < 4; ++c) jet[a][c] = jet[a + 1][c];
+    --m;
+  }
+}
+
+/* C = 3 (l1 l2 + l2 l3 + l3 l1) of the linearised momentum tensor
+     = (3/2) [ (sum|p|)^2 - sum_{a,b} (p_a.p_b)^2 / (|p_a||p_b|) ] / (sum|p|)^2 */
+double or_cparameter(int n, const double *p) {
+  double sum = 0.0, dbl = 0.0;
+  for (int a = 0; a < n; ++a) sum += norm3(&p[4 * a + 1]);
+  for (int a = 0; a < n; ++a) {
+    double la = norm3(&p[4 * a + 1]);
+    for (int b = 0; b < n; ++b) {
+      double lb = norm3(&p[4 * b + 1]);
+      double d = p[4 * a + 1] * p[4 * b + 1] + p[4 * a + 2] * p[4 * b + 2] + p[4 * a + 3] * p[4 * b + 3];
+      dbl += d * d / (la * lb);
+    }
+  }
+  double c = 1.5 * (sum * sum - dbl) / (sum * sum);
+  return c > 0.0 ? c : 0.0;
+}
+
+/* hemispheres split by the plane normal to the thrust axis (p.n >= 0 is the
+   "+" side): heavy-jet mass rho_H = max(M+^2, M-^2)/s; broadenings
+   B_pm = sum_pm |p x n| / (2 sum|p|), B_T = B+ + B-, B_W = max. */
+void or_hemispheres(int n, const double *p, const double axis[3], double s,
+                    double *rho_h, double *b_t, double *b_w) {
+  double hp[4] = {0, 0, 0, 0}, hm[4] = {0, 0, 0, 0};
+  double bp = 0.0, bm = 0.0, sum = 0.0;
+  for (int a = 0; a < n; ++a) {
+    const double *q = &p[4 * a];
+    sum += norm3(&q[1]);
+    double d = q[1] * axis[0] + q[2] * axis[1] + q[3] * axis[2];
+    double cr[3] = {q[2] * axis[2] - q[3] * axis[1], q[3] * axis[0] - q[1] * axis[2],
+                    q[1] * axis[1] - q[2] * axis[0]};
+    double kt = norm3(cr);
+    if (d >= 0.0) {
+      for (int c = 0; c < 4; ++c) hp[c] += q[c];
+      bp += kt;
+    } else {
+      for (int c = 0; c < 4; ++c) hm[c] += q[c];
+      bm += kt;
+    }
+  }
+  double mp = mdot(hp, hp), mm = mdot(hm, hm);
+  double rho = (mp > mm ? mp : mm) / s;
+  *rho_h = rho > 0.0 ? rho : 0.0;
+  bp /= 2.0 * sum;
+  bm /= 2.0 * sum;
+  *b_t = bp + bm;
+  *b_w = bp > bm ? bp : bm;
+}
+
+/* Validate: every component finite; total four-momentum equal to
+   (ecm, 0, 0, 0) within 1e-10 ecm per component; every parton massless
+   within 1e-10 s. */
+int or_validate(int n, const double *p, double ecm) {
+  double tot[4] = {0, 0, 0, 0};
+  for (int a = 0; a < 4 * n; ++a)
+    if (!isfinite(p[a])) return OR_NONFINITE;
+  for (int a = 0; a < n; ++a)
+    for (int c = 0; c < 4; ++c) tot[c] += p[4 * a + c];
+  double tol = 1e-10 * ecm;
+  if (fabs(tot[0] - ecm) > tol || fabs(tot[1]) > tol || fabs(tot[2]) > tol || fabs(tot[3]) > tol)
+    return OR_CONSERVATION;
+  for (int a = 0; a < n; ++a)
+    if (fabs(mdot(&p[4 * a], &p[4 * a])) > 1e-10 * ecm * ecm) return OR_CONSERVATION;
+  return OR_DONE;
+}
+
+/* obs = {y23, y34, tau = 1 - T, C, rho_H, B_T, B_W} */
+void or_observables(int n, const double *p, double ecm, double obs[7]) {
+  double s = ecm * ecm;
+  double axis[3];
+  double thrust = or_thrust(n, p, axis);
+  or_durham(n, p, s, &obs[0], &obs[1]);
+  double tau = 1.0 - thrust;
+  obs[2] = tau > 0.0 ? tau : 0.0;
+  obs[3] = or_cparameter(n, p);
+  or_hemispheres(n, p, axis, s, &obs[4], &obs[5], &obs[6]);
+}
+
+/* histogram ranges: log10 y23, log10 y34, tau, C, rho_H, B_T, B_W, cos(theta) */
+void or_hist_ranges(double lo[OR_NOBS], double hi[OR_NOBS]) {
+  static const double L[OR_NOBS] = {-4.3, -4.3, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0};
+  static const double H[OR_NOBS] = {-0.3, -0.3, 0.5, 1.0, 0.5, 0.5, 0.35, 1.0};
+  for (int h = 0; h < OR_NOBS; ++h) {
+    lo[h] = L[h];
+    hi[h] = H[h];
+  }
+}
+
+static void hist_fill(double *hist, int h, double x, double w, const double *lo, const double *hi) {
+  int b;
+  if (x != x) {
+    b = OR_NBINS + 1;
+  } else if (x < lo[h]) {
+    b = 0;
+  } else if (x >= hi[h]) {
+    b = OR_NBINS + 1;
+  } else {
+    b = 1 + (int)((x - lo[h]) / (hi[h] - lo[h]) * OR_NBINS);
+    if (b > OR_NBINS) b = OR_NBINS;
+  }
+  double *cell = &hist[3 * (OR_NHCOL * h + b)];
+  cell[0] += w;
+  cell[1] += w * w;
+  cell[2] += 1.0;
+}
+
+int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
+                const double *ecm, double ecm0, const double *tcut,
+                double tcut0, int cap, double *sum_d, int32_t *sum_i,
+                uint64_t *sum_hash, double *hist, int32_t *rec_n,
+                double *rec_p, int32_t *rec_pid, int32_t *rec_col,
+                int32_t *rec_acol, uint64_t *work) {
+  enum { MAXCAP = 1024 };
+  if (cap < 2 || cap > MAXCAP) return -1;
+  static double p[4 * MAXCAP];
+  static int pid[MAXCAP], col[MAXCAP], acol[MAXCAP];
+  double lo[OR_NOBS], hi[OR_NOBS];
+  or_hist_ranges(lo, hi);
+  for (uint64_t e = 0; e < n_events; ++e) {
+    uint64_t ev = first + e;
+    double E = ecm ? ecm[e] : ecm0;
+    double tc = tcut ? tcut[e] : tcut0;
+    int flavour;
+    double cth, phi, w;
+    or_me_event(seed, ev, E, &flavour, &cth, &phi, &w, p);
+    pid[0] = flavour;
+    col[0] = 1;
+    acol[0] = 0;
+    pid[1] = -flavour;
+    col[1] = 0;
+    acol[1] = 1;
+    int n = 2, cycles = 0, nemit = 0;
+    uint64_t hash = 0;
+    int status = or_shower(seed, ev, E, tc, cap, -1, &n, p, pid, col, acol, &cycles,
+                           &hash, &nemit, NULL, 0, work);
+    double obs[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (status == OR_DONE) status = or_validate(n, p, E);
+    if (status == OR_DONE) {
+      or_observables(n, p, E, obs);
+      if (hist) {
+        hist_fill(hist, 0, obs[0] > 0.0 ? log10(obs[0]) : -INFINITY, w, lo, hi);
+        hist_fill(hist, 1, obs[1] > 0.0 ? log10(obs[1]) : -INFINITY, w, lo, hi);
+        for (int h = 2; h < 7; ++h) hist_fill(hist, h, obs[h], w, lo, hi);
+        hist_fill(hist, 7, cth, w, lo, hi);
+      }
+    }
+    if (sum_d) {
+      double *d = &sum_d[OR_NSUM_D * e];
+      d[0] = w;
+      d[1] = cth;
+      for (int h = 0; h < 7; ++h) d[2 + h] = obs[h];
+      d[9] = phi;
+    }
+    if (sum_i) {
+      int32_t *si = &sum_i[OR_NSUM_I * e];
+      si[0] = n;
+      si[1] = status;
+      si[2] = cycles;
+      si[3] = nemit;
+      si[4] = flavour;
+    }
+    if (sum_hash) sum_hash[e] = hash;
+    if (rec_n) rec_n[e] = n;
+    if (rec_p) {
+      for (int a = 0; a < 4 * n; ++a) rec_p[(size_t)4 * cap * e + a] = p[a];
+    }
+    for (int a = 0; a < n; ++a) {
+      if (rec_pid) rec_pid[(size_t)cap * e + a] = pid[a];
+      if (rec_col) rec_col[(size_t)cap * e + a] = col[a];
+      if (rec_acol) rec_acol[(size_t)cap * e + a] = acol[a];
+    }
+  }
+  return 0;
+}
