@@ -1,0 +1,206 @@
+/*
+ * vsh.h -- C ABI of libvsh, an MI355X (gfx950) engine for the parallel
+ * Sudakov-veto parton shower of Seymour & Sule, "An Algorithm to Parallelise
+ * Parton Showers on a GPU" (arXiv:2403.08692).
+ *
+ * What one call computes (Section 3 and Appendices A-C of the paper):
+ * generate N events e+e- -> q qbar at sqrt(s) from the LO matrix element
+ * (App. B), shower each to the cutoff t_C with the veto algorithm run for all
+ * events at once (Sec. 2; App. A and C), then compute Durham jet rates and
+ * event shapes (Sec. 3.1) into histograms, returning per-event summaries and,
+ * on request, the event records.
+ *
+ * Conventions
+ *  - Every call returns vsh_status: VSH_OK (0) or a negative error code.
+ *    No C++ exception crosses this interface.  After an error,
+ *    vsh_last_error(ctx) describes it (valid until the next call on ctx).
+ *  - Units: GeV for energies and momenta, GeV^2 for t and t_C, pb for
+ *    weights.  Momenta are (E, px, py, pz).
+ *  - An event is a pure function of (seed, event id, sqrt(s), t_C, cap):
+ *    every random number is Philox4x32-10 keyed by (seed, event id) with a
+ *    counter naming the draw, so results do not depend on batching, launch
+ *    form, lane mapping or on which other requests share the device.
+ *  - Per-event problems (record overflow, non-finite momenta, violated
+ *    momentum conservation) are not call errors: they set the event's status
+ *    and are counted in the result; such events are left out of histograms.
+ *  - Threading: one context per device.  A context is internally locked:
+ *    calls from several host threads are serialised.
+ */
+#ifndef VSH_H
+#define VSH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VSH_VERSION_MAJOR 1
+#define VSH_VERSION_MINOR 0
+
+typedef enum {
+  VSH_OK = 0,
+  VSH_E_INVALID = -1,   /* bad argument (message names it)                     */
+  VSH_E_NOMEM = -2,     /* the request can never fit the context's memory budget */
+  VSH_E_DEVICE = -3,    /* no usable gfx950 device, or a HIP runtime error      */
+  VSH_E_BUSY = -4,      /* not finished yet (vsh_poll) / serving loop owns it   */
+  VSH_E_NOTFOUND = -5,  /* unknown ticket                                       */
+  VSH_E_CANCELLED = -6, /* the request was cancelled                            */
+  VSH_E_INTERNAL = -7
+} vsh_status;
+
+/* event status codes, per event */
+enum {
+  VSH_EV_RUNNING = 0,
+  VSH_EV_DONE = 1,         /* showered to the cutoff, validated                  */
+  VSH_EV_OVERFLOW = 2,     /* an accepted emission found the record full         */
+  VSH_EV_NONFINITE = 3,    /* a momentum component is not finite                 */
+  VSH_EV_CONSERVATION = 4, /* |sum p - (sqrt s, 0)| > 1e-10 sqrt s, or |p_i^2| > 1e-10 s */
+  VSH_EV_CYCLE_LIMIT = 5   /* stopped after 2^20 veto cycles (a guard; not reached in practice) */
+};
+
+/* observables / histograms: 50 uniform bins [lo, hi) plus underflow (bin 0)
+   and overflow (bin 51); each cell holds (sum w, sum w^2, entries).
+     0 log10 y23 (Durham)  [-4.3, -0.3]      4 rho_H (heavy-jet mass^2 / s) [0, 0.5]
+     1 log10 y34 (Durham)  [-4.3, -0.3]      5 B_T (total broadening)     [0, 0.5]
+     2 tau = 1 - T (thrust) [0, 0.5]          6 B_W (wide broadening)      [0, 0.35]
+     3 C-parameter          [0, 1]            7 cos(theta) of the quark    [-1, 1]
+   log10 y is filled only for y > 0; y = 0 (fewer than 3 or 4 partons) goes
+   to the underflow bin. */
+#define VSH_NOBS 8
+#define VSH_NBINS 50
+#define VSH_NHCOL (VSH_NBINS + 2)
+#define VSH_HIST_DOUBLES (VSH_NOBS * VSH_NHCOL * 3)
+
+/* per-event summary, structure of arrays [field][n_events]
+   double fields: 0 w (pb), 1 cos(theta), 2 y23, 3 y34, 4 tau, 5 C, 6 rho_H,
+                  7 B_T, 8 B_W, 9 phi (of the quark)
+   int32 fields : 0 partons n, 1 status, 2 veto cycles (SelectWinner calls,
+                  the last empty one included), 3 accepted emissions,
+                  4 flavour (1..5 = d,u,s,c,b), 5 trial emissions generated
+   hash         : FNV-1a over the sequence of accepted (kernel, splitter,
+                  spectator) triples, 32-bit words, offset basis
+                  0xcbf29ce484222325, prime 0x100000001b3 */
+#define VSH_NSUM_D 10
+#define VSH_NSUM_I 6
+
+/* request flags */
+#define VSH_SUMMARY 0x1u           /* return per-event summaries                       */
+#define VSH_RECORDS 0x2u           /* return the final partons of every event (CSR)     */
+#define VSH_FORM_PLAIN 0x0u        /* thread per event, one launch to the cutoff        */
+#define VSH_FORM_PERSISTENT 0x4u   /* persistent waves with ballot compaction + refill  */
+#define VSH_INPUTS_ON_DEVICE 0x8u  /* ecm_per_event / tcut_per_event are device pointers
+                                      (vsh_generate_into only)                          */
+
+typedef struct vsh_ctx vsh_ctx; /* device arena, stream, kernel cache, serving state */
+
+typedef struct {
+  int device;                /* HIP device ordinal                                      */
+  uint64_t mem_budget_bytes; /* device memory the context may hold; 0 = 80% of free      */
+  uint32_t flags;            /* reserved, 0                                              */
+} vsh_ctx_opts;
+
+/* Create a context on opts->device (opts may be NULL: device 0, default
+   budget).  Fails with VSH_E_DEVICE when the device is not gfx950 or HIP
+   reports an error.  *out is owned by the caller; release with vsh_destroy. */
+vsh_status vsh_create(const vsh_ctx_opts *opts, vsh_ctx **out);
+void vsh_destroy(vsh_ctx *ctx);
+/* Last error message of ctx (or of the last failed vsh_create if ctx is
+   NULL); never NULL. */
+const char *vsh_last_error(const vsh_ctx *ctx);
+
+typedef struct {
+  uint64_t n_events;     /* >= 1                                                    */
+  uint64_t seed;         /* Philox key                                              */
+  uint64_t first_event;  /* event ids are first_event .. first_event + n_events - 1 */
+  double ecm;            /* sqrt(s) in GeV, > 0; used when ecm_per_event is NULL      */
+  double t_cut;          /* t_C in GeV^2, > 0.01; used when tcut_per_event is NULL    */
+  const double *ecm_per_event;  /* optional [n_events]; host memory, read during the call
+                                   (copied by vsh_submit)                              */
+  const double *tcut_per_event; /* optional [n_events]; likewise                       */
+  uint32_t max_partons;  /* record capacity per event, 2..1024 (64, 128, 256 typical)  */
+  uint32_t flags;        /* VSH_SUMMARY | VSH_RECORDS | VSH_FORM_*                     */
+} vsh_request;
+
+/* Result of one request.  Library-owned host memory; release with
+   vsh_result_free.  Optional arrays are NULL unless their flag was set. */
+typedef struct {
+  uint64_t n_events, n_done, n_overflow, n_nonfinite, n_conservation;
+  double sum_w, sum_w2;       /* over all events: sigma estimate = sum_w / n_events */
+  uint32_t n_obs, n_bins;     /* VSH_NOBS, VSH_NBINS                               */
+  const double *hist_lo, *hist_hi; /* [VSH_NOBS]                                    */
+  const double *hist;         /* [VSH_NOBS][VSH_NHCOL][3]                           */
+  const double *sum_d;        /* [VSH_NSUM_D][n_events]                             */
+  const int32_t *sum_i;       /* [VSH_NSUM_I][n_events]                             */
+  const uint64_t *sum_hash;   /* [n_events]                                         */
+  const uint64_t *rec_offsets;/* [n_events + 1]; event e owns partons
+                                 rec_offsets[e] .. rec_offsets[e+1]-1               */
+  const double *rec_p;        /* [total][4]                                         */
+  const int8_t *rec_pid;      /* [total]: 1..5 quarks, -1..-5 antiquarks, 21 gluon   */
+  const uint16_t *rec_col, *rec_acol; /* [total]: colour / anticolour line, 0 = none */
+  uint64_t total_cycles;      /* sum over events of veto cycles                     */
+  uint64_t total_trials;      /* sum over events of trial emissions                  */
+  uint32_t max_cycles;        /* longest event, in veto cycles                       */
+  double t_me_ms, t_shower_ms, t_obs_ms, t_total_ms; /* device time per stage; total is
+                                                        host wall clock of the call  */
+} vsh_result;
+
+/* Blocking generation (Sec. 3 problem statement; App. C for the shower).
+   Allocates from the context arena (grow-only, reused across calls), runs
+   matrix element, shower and observables on the context's stream, copies the
+   results to pinned host memory.  Requests larger than the budget allows at
+   once are processed in event-id chunks (identical results).
+   Errors: VSH_E_INVALID (n_events = 0, ecm <= 0, t_cut <= 0.01, max_partons
+   outside 2..1024, unknown flags), VSH_E_NOMEM (not even one chunk fits),
+   VSH_E_DEVICE. */
+vsh_status vsh_generate(vsh_ctx *ctx, const vsh_request *req, vsh_result **out);
+void vsh_result_free(vsh_result *res);
+
+/* Shower caller-supplied initial states instead of LO events (a q g qbar
+   start, say).  offsets [n_events+1] index into p [total][4], pid, col,
+   acol [total] (host memory, read during the call); the event's sqrt(s) is
+   taken from the sum of its momenta' energies, t_cut from req; req->ecm and
+   the per-event arrays are ignored.  Weights are 1.  The evolution starts at
+   t = s of each event.  Same errors as vsh_generate, plus VSH_E_INVALID for an
+   event with more partons than max_partons or an inconsistent colour flow. */
+vsh_status vsh_shower_records(vsh_ctx *ctx, const vsh_request *req, const uint64_t *offsets,
+                              const double *p, const int8_t *pid, const uint16_t *col,
+                              const uint16_t *acol, vsh_result **out);
+
+/* Device-side generation into caller-owned device memory, on the caller's
+   HIP stream, with no allocation and no host synchronisation: the launch
+   sequence of vsh_generate without its copies.
+     stream      hipStream_t of the caller (NULL = the null stream)
+     workspace   device buffer of at least vsh_workspace_size() bytes
+     dev_hist    [VSH_HIST_DOUBLES] device doubles, accumulated into (clear first)
+     dev_sum_d   optional [VSH_NSUM_D][n_events] device doubles
+     dev_sum_i   optional [VSH_NSUM_I][n_events] device int32
+     dev_hash    optional [n_events] device uint64
+   With VSH_INPUTS_ON_DEVICE, ecm_per_event / tcut_per_event are device
+   pointers.  The call returns once the kernels are enqueued. */
+vsh_status vsh_generate_into(vsh_ctx *ctx, const vsh_request *req, void *stream, void *workspace,
+                             uint64_t workspace_bytes, double *dev_hist, double *dev_sum_d,
+                             int32_t *dev_sum_i, uint64_t *dev_hash);
+/* Workspace bytes vsh_generate_into needs for req (0 on invalid input). */
+uint64_t vsh_workspace_size(const vsh_request *req);
+
+/* Serving (continuous batching).  vsh_submit copies the request (and its
+   per-event arrays) and returns at once with a ticket; the context's serving
+   loop admits requests by event-record memory, runs their events together in
+   persistent launches as slots free up, and keeps one histogram set per
+   request.  Per-request results equal those of vsh_generate on the same
+   request up to the summation order of the histograms.
+   vsh_poll: *done = 1 once finished.  vsh_wait blocks until finished and
+   hands over the result (once; the ticket is then forgotten).
+   vsh_cancel: stops admitting the request's events; vsh_wait then returns
+   VSH_E_CANCELLED.  Errors: VSH_E_NOTFOUND for unknown tickets, and those of
+   vsh_generate at submission. */
+vsh_status vsh_submit(vsh_ctx *ctx, const vsh_request *req, uint64_t *ticket);
+vsh_status vsh_poll(vsh_ctx *ctx, uint64_t ticket, int *done);
+vsh_status vsh_wait(vsh_ctx *ctx, uint64_t ticket, vsh_result **out);
+vsh_status vsh_cancel(vsh_ctx *ctx, uint64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VSH_H */

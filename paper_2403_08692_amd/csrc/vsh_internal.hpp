@@ -1,0 +1,96 @@
+// vsh_internal.hpp -- host-side internals shared by the C-ABI translation
+// units: the context, the device arena, the plain-form layout and results.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <condition_variable>
+#include <cstddef>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/vsh.h"
+#include "vsh_kernels.hpp"
+
+namespace vsh {
+
+constexpr uint32_t kMaxCap = 1024;
+constexpr double kMinTcut = 0.01;  // GeV^2; the one-loop Landau pole is at 0.0077 GeV^2
+
+inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+struct Arena {
+  void* ptr = nullptr;
+  uint64_t size = 0;
+  vsh_status reserve(vsh_ctx* ctx, uint64_t bytes);
+  void release();
+};
+
+struct PlainLayout {
+  Records rec;
+  Scratch sc;
+  Summary sum;
+  double *ecm, *tcut, *hist;
+  char* end;
+};
+
+// launch parameters picked by the autotuner (defaults until it has run)
+struct Tuned {
+  uint32_t plain_block = 256;
+  uint32_t pers_block = 256;
+  uint32_t pers_waves_per_cu = 8;
+  uint32_t refill_period = 1;  // cycles between compaction / refill passes
+};
+
+struct ServeState;
+
+}  // namespace vsh
+
+struct vsh_ctx {
+  int device = 0;
+  int n_cu = 0;
+  uint64_t budget = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  vsh::Arena arena, arena2;
+  vsh::Tuned tuned;
+  std::mutex mu;
+  std::string error;
+  vsh::ServeState* serve = nullptr;  // owned; torn down by serve_shutdown
+};
+
+namespace vsh {
+
+struct ResultBox {
+  vsh_result pub;
+  std::vector<double> hist, lo, hi, sum_d;
+  std::vector<int32_t> sum_i;
+  std::vector<uint64_t> hash, rec_offsets;
+  std::vector<double> rec_p;
+  std::vector<int8_t> rec_pid;
+  std::vector<uint16_t> rec_col, rec_acol;
+};
+
+void set_error(vsh_ctx* ctx, const char* fmt, ...);
+vsh_status hip_fail(vsh_ctx* ctx, hipError_t err, const char* what);
+vsh_status validate_request(vsh_ctx* ctx, const vsh_request* req, bool need_energy);
+ResultBox* new_result(uint64_t n_events, bool summary);
+void finish_result(ResultBox* b);
+void tally_chunk(ResultBox* b, const int32_t* si, const double* sd, uint64_t stride, uint64_t count);
+uint64_t plain_layout_bytes(uint64_t stride, uint32_t cap);
+PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap);
+
+// persistent form (vsh_persistent.hip)
+vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result** out);
+uint64_t persistent_workspace_bytes(const vsh_request* req);
+vsh_status persistent_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void* ws,
+                           double* dev_hist, double* dev_sum_d, int32_t* dev_sum_i,
+                           uint64_t* dev_hash);
+
+// serving (vsh_serve.hip)
+void serve_shutdown(vsh_ctx* ctx);
+
+}  // namespace vsh
