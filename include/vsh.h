@@ -77,12 +77,13 @@ enum {
                   7 B_T, 8 B_W, 9 phi (of the quark)
    int32 fields : 0 partons n, 1 status, 2 veto cycles (SelectWinner calls,
                   the last empty one included), 3 accepted emissions,
-                  4 flavour (1..5 = d,u,s,c,b), 5 trial emissions generated
+                  4 flavour (1..5 = d,u,s,c,b), 5 trial emissions generated,
+                  6 dipole ends with phase space above t_C, summed over cycles
    hash         : FNV-1a over the sequence of accepted (kernel, splitter,
                   spectator) triples, 32-bit words, offset basis
                   0xcbf29ce484222325, prime 0x100000001b3 */
 #define VSH_NSUM_D 10
-#define VSH_NSUM_I 6
+#define VSH_NSUM_I 7
 
 /* request flags */
 #define VSH_SUMMARY 0x1u           /* return per-event summaries                       */
@@ -140,6 +141,8 @@ typedef struct {
   const uint16_t *rec_col, *rec_acol; /* [total]: colour / anticolour line, 0 = none */
   uint64_t total_cycles;      /* sum over events of veto cycles                     */
   uint64_t total_trials;      /* sum over events of trial emissions                  */
+  uint64_t total_ends;        /* sum over events and cycles of active dipole ends    */
+  uint64_t total_emissions;   /* sum over events of accepted emissions               */
   uint32_t max_cycles;        /* longest event, in veto cycles                       */
   double t_me_ms, t_shower_ms, t_obs_ms, t_total_ms; /* device time per stage; total is
                                                         host wall clock of the call  */
@@ -183,6 +186,17 @@ vsh_status vsh_generate_into(vsh_ctx *ctx, const vsh_request *req, void *stream,
                              int32_t *dev_sum_i, uint64_t *dev_hash);
 /* Workspace bytes vsh_generate_into needs for req (0 on invalid input). */
 uint64_t vsh_workspace_size(const vsh_request *req);
+
+/* Stage timing of vsh_generate_into.  After vsh_timing_start, each
+   vsh_generate_into call (at most VSH_TIMING_MAX_CALLS) records HIP events on
+   its own stream before and after each of its three stages: matrix element,
+   shower, observables + histograms.  vsh_timing_read waits for those events
+   and writes ms[3 * c + stage] for calls c = 0 .. *n_calls - 1 (at most
+   max_calls), then stops recording.  Errors: VSH_E_INVALID when timing was
+   not started. */
+#define VSH_TIMING_MAX_CALLS 1024
+vsh_status vsh_timing_start(vsh_ctx *ctx);
+vsh_status vsh_timing_read(vsh_ctx *ctx, float *ms, uint32_t max_calls, uint32_t *n_calls);
 
 /* Serving (continuous batching).  vsh_submit copies the request (and its
    per-event arrays) and returns at once with a ticket; the context's serving

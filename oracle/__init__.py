@@ -14,13 +14,16 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvsh_oracle.so")
+# VSH_ORACLE_LIB points at another build of the same source (an -O3
+# -march=native build for timing, or a deliberately broken copy in a test
+# that checks the pins catch it).
+LIB_PATH = os.environ.get("VSH_ORACLE_LIB") or os.path.join(HERE, "libvsh_oracle.so")
 
 NOBS = 8
 NBINS = 50
 NHCOL = NBINS + 2
 NSUM_D = 10
-NSUM_I = 5
+NSUM_I = 7
 NLOG = 7
 NWORK = 6
 
@@ -44,7 +47,8 @@ def lib():
     if _lib is not None:
         return _lib
     src = os.path.join(HERE, "vsh_oracle.c")
-    if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+    if not os.environ.get("VSH_ORACLE_LIB") and (
+            not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src)):
         from . import build as _build
 
         _build.build()
@@ -241,8 +245,8 @@ def generate(seed, first, n_events, ecm=91.2, tcut=1.0, cap=64, records=False, e
     """Run ME + shower + observables + histograms for events first..first+n-1.
 
     Returns a dict with per-event summaries (``sum_d`` [n, 10]: w, cos_theta,
-    y23, y34, tau, C, rho_H, B_T, B_W, phi; ``sum_i`` [n, 5]: n, status,
-    cycles, n_emit, flavour; ``hash`` [n]), histograms [8, 52, 3] and the
+    y23, y34, tau, C, rho_H, B_T, B_W, phi; ``sum_i`` [n, 7]: n, status,
+    cycles, n_emit, flavour, trials, active dipole ends; ``hash`` [n]), histograms [8, 52, 3] and the
     work counters; with ``records`` also the final partons.
     """
     n_events = int(n_events)

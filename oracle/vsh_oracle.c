@@ -726,8 +726,11 @@ int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
     acol[1] = 1;
     int n = 2, cycles = 0, nemit = 0;
     uint64_t hash = 0;
+    uint64_t ew[OR_NWORK] = {0, 0, 0, 0, 0, 0};
     int status = or_shower(seed, ev, E, tc, cap, -1, &n, p, pid, col, acol, &cycles,
-                           &hash, &nemit, NULL, 0, work);
+                           &hash, &nemit, NULL, 0, ew);
+    if (work)
+      for (int k = 0; k < OR_NWORK; ++k) work[k] += ew[k];
     double obs[7] = {0, 0, 0, 0, 0, 0, 0};
     if (status == OR_DONE) status = or_validate(n, p, E);
     if (status == OR_DONE) {
@@ -753,6 +756,8 @@ int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
       si[2] = cycles;
       si[3] = nemit;
       si[4] = flavour;
+      si[5] = (int32_t)ew[3]; /* trial emissions */
+      si[6] = (int32_t)ew[2]; /* dipole ends with phase space above t_C */
     }
     if (sum_hash) sum_hash[e] = hash;
     if (rec_n) rec_n[e] = n;

@@ -35,7 +35,7 @@ enum {
 };
 
 enum { OR_NOBS = 8, OR_NBINS = 50, OR_NHCOL = OR_NBINS + 2 };
-enum { OR_NSUM_D = 10, OR_NSUM_I = 5 };
+enum { OR_NSUM_D = 10, OR_NSUM_I = 7 };
 enum { OR_NLOG = 7 };
 enum { OR_NWORK = 6 };
 

@@ -25,7 +25,7 @@ VSH_INPUTS_ON_DEVICE = 0x8
 NOBS, NBINS = 8, 50
 NHCOL = NBINS + 2
 HIST_DOUBLES = NOBS * NHCOL * 3
-NSUM_D, NSUM_I = 10, 6
+NSUM_D, NSUM_I = 10, 7
 EV_DONE, EV_OVERFLOW, EV_NONFINITE, EV_CONSERVATION = 1, 2, 3, 4
 
 
@@ -52,7 +52,8 @@ class vsh_result(C.Structure):
                 ("rec_offsets", C.POINTER(C.c_uint64)), ("rec_p", C.POINTER(C.c_double)),
                 ("rec_pid", C.POINTER(C.c_int8)), ("rec_col", C.POINTER(C.c_uint16)),
                 ("rec_acol", C.POINTER(C.c_uint16)),
-                ("total_cycles", C.c_uint64), ("total_trials", C.c_uint64), ("max_cycles", C.c_uint32),
+                ("total_cycles", C.c_uint64), ("total_trials", C.c_uint64), ("total_ends", C.c_uint64),
+                ("total_emissions", C.c_uint64), ("max_cycles", C.c_uint32),
                 ("t_me_ms", C.c_double), ("t_shower_ms", C.c_double), ("t_obs_ms", C.c_double),
                 ("t_total_ms", C.c_double)]
 
@@ -93,13 +94,17 @@ def load():
     L.vsh_wait.restype = C.c_int
     L.vsh_cancel.argtypes = [P, C.c_uint64]
     L.vsh_cancel.restype = C.c_int
+    L.vsh_timing_start.argtypes = [P]
+    L.vsh_timing_start.restype = C.c_int
+    L.vsh_timing_read.argtypes = [P, C.POINTER(C.c_float), C.c_uint32, C.POINTER(C.c_uint32)]
+    L.vsh_timing_read.restype = C.c_int
     _lib = L
     return L
 
 
 EXPORTS = ["vsh_create", "vsh_destroy", "vsh_last_error", "vsh_generate", "vsh_result_free",
            "vsh_shower_records", "vsh_generate_into", "vsh_workspace_size", "vsh_submit", "vsh_poll",
-           "vsh_wait", "vsh_cancel"]
+           "vsh_wait", "vsh_cancel", "vsh_timing_start", "vsh_timing_read"]
 
 
 class VshError(RuntimeError):
@@ -124,7 +129,8 @@ def result_to_dict(res: vsh_result) -> dict:
     n = res.n_events
     out = dict(n_events=n, n_done=res.n_done, n_overflow=res.n_overflow, n_nonfinite=res.n_nonfinite,
                n_conservation=res.n_conservation, sum_w=res.sum_w, sum_w2=res.sum_w2,
-               total_cycles=res.total_cycles, total_trials=res.total_trials, max_cycles=res.max_cycles,
+               total_cycles=res.total_cycles, total_trials=res.total_trials, total_ends=res.total_ends,
+               total_emissions=res.total_emissions, max_cycles=res.max_cycles,
                t_me_ms=res.t_me_ms, t_shower_ms=res.t_shower_ms, t_obs_ms=res.t_obs_ms,
                t_total_ms=res.t_total_ms)
     out["hist"] = _arr(res.hist, HIST_DOUBLES, np.float64).reshape(NOBS, NHCOL, 3)
@@ -237,6 +243,16 @@ class Context:
         """All buffer arguments are integer device addresses; stream a hipStream_t address."""
         _check(load().vsh_generate_into(self._ptr, C.byref(req), stream, workspace, int(workspace_bytes),
                                         dev_hist, dev_sum_d, dev_sum_i, dev_hash), self._ptr)
+
+    def timing_start(self):
+        _check(load().vsh_timing_start(self._ptr), self._ptr)
+
+    def timing_read(self, max_calls=1024):
+        """Per-call stage times [n_calls, 3] in ms (ME, shower, observables)."""
+        buf = (C.c_float * (3 * max_calls))()
+        n = C.c_uint32()
+        _check(load().vsh_timing_read(self._ptr, buf, max_calls, C.byref(n)), self._ptr)
+        return np.array(buf[:3 * n.value], np.float64).reshape(n.value, 3)
 
     def submit(self, n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=128, summary=False,
                ecm_per_event=None, tcut_per_event=None):

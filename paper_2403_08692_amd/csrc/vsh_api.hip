@@ -216,6 +216,8 @@ void tally_chunk(ResultBox* b, const int32_t* si, const double* sd, uint64_t str
     r.total_cycles += cyc;
     r.max_cycles = std::max(r.max_cycles, cyc);
     r.total_trials += (uint32_t)si[kSiTrials * stride + e];
+    r.total_ends += (uint32_t)si[kSiEnds * stride + e];
+    r.total_emissions += (uint32_t)si[kSiEmit * stride + e];
   }
 }
 
@@ -447,6 +449,18 @@ vsh_status generate_plain(vsh_ctx* ctx, const vsh_request* req, const uint64_t* 
   return VSH_OK;
 }
 
+// events of the next timed vsh_generate_into call, or null when not timing
+hipEvent_t* timing_slot(vsh_ctx* ctx) {
+  if (!ctx->timing || ctx->timing_calls >= VSH_TIMING_MAX_CALLS) return nullptr;
+  const size_t need = 4 * (size_t)(ctx->timing_calls + 1);
+  while (ctx->timing_ev.size() < need) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->timing_ev.push_back(e);
+  }
+  return &ctx->timing_ev[4 * (size_t)ctx->timing_calls++];
+}
+
 }  // namespace vsh
 
 using namespace vsh;
@@ -517,6 +531,7 @@ void vsh_destroy(vsh_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   ctx->arena.release();
   ctx->arena2.release();
+  for (auto& e : ctx->timing_ev) (void)hipEventDestroy(e);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -647,9 +662,14 @@ vsh_status vsh_generate_into(vsh_ctx* ctx, const vsh_request* req, void* stream,
   in.ecm = req->ecm_per_event;
   in.tcut = req->tcut_per_event;
   Summary sum = L.sum;
+  hipEvent_t* tev = timing_slot(ctx);
+  if (tev) (void)hipEventRecord(tev[0], st);
   launch_me(L.rec, sum, in, (uint32_t)n, st);
+  if (tev) (void)hipEventRecord(tev[1], st);
   launch_shower_plain(L.rec, sum, in, (uint32_t)n, ctx->tuned.plain_block, st);
+  if (tev) (void)hipEventRecord(tev[2], st);
   launch_obs(L.rec, sum, in, L.sc, (uint32_t)n, dev_hist, st);
+  if (tev) (void)hipEventRecord(tev[3], st);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return hip_fail(ctx, err, "kernel launch");
   // summaries out, in the caller's [field][n_events] layout
@@ -665,6 +685,39 @@ vsh_status vsh_generate_into(vsh_ctx* ctx, const vsh_request* req, void* stream,
     err = hipMemcpyAsync(dev_hash, sum.hash, n * 8, hipMemcpyDeviceToDevice, st);
     if (err != hipSuccess) return hip_fail(ctx, err, "summary copy");
   }
+  return VSH_OK;
+}
+
+vsh_status vsh_timing_start(vsh_ctx* ctx) {
+  if (!ctx) return VSH_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->timing = true;
+  ctx->timing_calls = 0;
+  return VSH_OK;
+}
+
+vsh_status vsh_timing_read(vsh_ctx* ctx, float* ms, uint32_t max_calls, uint32_t* n_calls) {
+  if (!ctx) return VSH_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!ctx->timing) {
+    set_error(ctx, "vsh_timing_read without vsh_timing_start");
+    return VSH_E_INVALID;
+  }
+  const uint32_t n = std::min(ctx->timing_calls, max_calls);
+  for (uint32_t c = 0; c < n; ++c) {
+    hipEvent_t* e = &ctx->timing_ev[4 * (size_t)c];
+    hipError_t err = hipEventSynchronize(e[3]);
+    if (err != hipSuccess) return hip_fail(ctx, err, "hipEventSynchronize");
+    for (int k = 0; k < 3; ++k) {
+      float v = 0.0f;
+      err = hipEventElapsedTime(&v, e[k], e[k + 1]);
+      if (err != hipSuccess) return hip_fail(ctx, err, "hipEventElapsedTime");
+      if (ms) ms[3 * c + k] = v;
+    }
+  }
+  if (n_calls) *n_calls = n;
+  ctx->timing = false;
+  ctx->timing_calls = 0;
   return VSH_OK;
 }
 

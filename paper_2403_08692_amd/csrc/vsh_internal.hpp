@@ -60,6 +60,10 @@ struct vsh_ctx {
   std::mutex mu;
   std::string error;
   vsh::ServeState* serve = nullptr;  // owned; torn down by serve_shutdown
+  // stage timing of vsh_generate_into: 4 events per call
+  bool timing = false;
+  uint32_t timing_calls = 0;
+  std::vector<hipEvent_t> timing_ev;
 };
 
 namespace vsh {
@@ -86,6 +90,7 @@ PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap);
 // persistent form (vsh_persistent.hip)
 vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result** out);
 uint64_t persistent_workspace_bytes(const vsh_request* req);
+hipEvent_t* timing_slot(vsh_ctx* ctx);
 vsh_status persistent_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void* ws,
                            double* dev_hist, double* dev_sum_d, int32_t* dev_sum_i,
                            uint64_t* dev_hash);

@@ -79,7 +79,7 @@ struct EvState {
   double lt;     // ln t, the current upper scale
   double tcut, ltc, asmax, cfac;
   uint64_t hash;
-  uint32_t cycle, trials;
+  uint32_t cycle, trials, ends;
   int n, next_col, n_emit, status;
 };
 
@@ -99,6 +99,7 @@ __device__ __forceinline__ void end_trials(EvState& s, int i, int k, int pid_i, 
   const double zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * s.tcut / q2));
   const double zm = 1.0 - zp;
   const double L = log((1.0 - zm) / (1.0 - zp));
+  s.ends += 1;
   if (pid_i != kGluon) {
     const double c = s.cfac * ((2.0 * kCF) * L);
     const U4 d = s.key.draw(s.cycle, kPurposeTrial, trial_slot(i, k, 0));
@@ -251,6 +252,7 @@ __device__ __forceinline__ void init_state(EvState& s, const Records& r, const S
   s.hash = kFnvOffset;
   s.cycle = 0;
   s.trials = 0;
+  s.ends = 0;
   s.n = sm.i[kSiN * sm.stride + e];
   s.n_emit = 0;
   s.status = kRunning;
@@ -269,6 +271,7 @@ __device__ __forceinline__ void write_state(const EvState& s, const Summary& sm,
   sm.i[kSiCycles * sm.stride + e] = (int32_t)s.cycle;
   sm.i[kSiEmit * sm.stride + e] = s.n_emit;
   sm.i[kSiTrials * sm.stride + e] = (int32_t)s.trials;
+  sm.i[kSiEnds * sm.stride + e] = (int32_t)s.ends;
   sm.hash[e] = s.hash;
 }
 

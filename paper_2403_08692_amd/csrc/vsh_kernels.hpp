@@ -20,7 +20,7 @@
 namespace vsh {
 
 constexpr int kNSumD = 10;
-constexpr int kNSumI = 6;
+constexpr int kNSumI = 7;
 constexpr int kNObs = 8;
 constexpr int kNBins = 50;
 constexpr int kNHCol = kNBins + 2;
@@ -29,7 +29,7 @@ constexpr int kHistDoubles = kNObs * kNHCol * 3;
 // summary field indices
 enum { kSdW = 0, kSdCos = 1, kSdY23 = 2, kSdY34 = 3, kSdTau = 4, kSdC = 5, kSdRho = 6, kSdBT = 7,
        kSdBW = 8, kSdPhi = 9 };
-enum { kSiN = 0, kSiStatus = 1, kSiCycles = 2, kSiEmit = 3, kSiFlavour = 4, kSiTrials = 5 };
+enum { kSiN = 0, kSiStatus = 1, kSiCycles = 2, kSiEmit = 3, kSiFlavour = 4, kSiTrials = 5, kSiEnds = 6 };
 
 struct Records {
   double *E, *x, *y, *z;

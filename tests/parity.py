@@ -39,9 +39,9 @@ def oracle_records(orc, n):
 def compare(gpu: dict, orc: dict, ecm, n: int, records: bool = True):
     """Returns a report dict; raises AssertionError when a bar is missed."""
     gi = gpu["sum_i"]          # [6][n]
-    oi = orc["sum_i"].T        # [5][n]
+    oi = orc["sum_i"].T        # [7][n]
     same = np.ones(n, bool)
-    for f in range(5):
+    for f in range(7):
         same &= gi[f] == oi[f]
     same &= gpu["hash"] == orc["hash"]
     ecm = np.broadcast_to(np.asarray(ecm, np.float64), (n,))
