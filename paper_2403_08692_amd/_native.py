@@ -68,6 +68,14 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libvsh.so is not built ({LIB_PATH}); run __graft_entry__.build() first")
+    # PyTorch ships its own HIP runtime under the same soname; whichever is
+    # loaded first serves the whole process.  Load PyTorch's first when it is
+    # installed, so that device buffers and streams from PyTorch and the
+    # library's launches share one runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     L.vsh_create.argtypes = [C.POINTER(vsh_ctx_opts), C.POINTER(P)]

@@ -89,11 +89,12 @@ vsh_status validate_request(vsh_ctx* ctx, const vsh_request* req, bool need_ener
 // records, Durham scratch, summaries, per-event inputs, histogram.
 // ---------------------------------------------------------------------------
 uint64_t plain_bytes_per_event(uint32_t cap) {
-  return (uint64_t)cap * (4 * 8 + 1 + 4 * 2 + 4 * 8) + kNSumD * 8 + kNSumI * 4 + 8 + 2 * 8;
+  return (uint64_t)cap * (4 * 8 + 1 + 4 * 2) + kNSumD * 8 + kNSumI * 4 + 8 + 2 * 8;
 }
 
 uint64_t plain_layout_bytes(uint64_t stride, uint32_t cap) {
-  return align_up(plain_bytes_per_event(cap) * stride + 16 * 256 + kHistDoubles * 8, 256);
+  return align_up(plain_bytes_per_event(cap) * stride + obs_threads(stride) * cap * 32 + 20 * 256 +
+                      kHistDoubles * 8, 256);
 }
 
 PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap) {
@@ -116,11 +117,12 @@ PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap) {
   L.rec.apart = (uint16_t*)take(slots * 2);
   L.rec.stride = stride;
   L.rec.cap = cap;
-  L.sc.jE = (double*)take(slots * 8);
-  L.sc.jx = (double*)take(slots * 8);
-  L.sc.jy = (double*)take(slots * 8);
-  L.sc.jz = (double*)take(slots * 8);
-  L.sc.stride = stride;
+  const uint64_t ot = obs_threads(stride);
+  L.sc.jE = (double*)take(ot * cap * 8);
+  L.sc.jx = (double*)take(ot * cap * 8);
+  L.sc.jy = (double*)take(ot * cap * 8);
+  L.sc.jz = (double*)take(ot * cap * 8);
+  L.sc.stride = ot;
   L.sum.d = (double*)take(kNSumD * stride * 8);
   L.sum.i = (int32_t*)take(kNSumI * stride * 4);
   L.sum.hash = (uint64_t*)take(stride * 8);
@@ -239,6 +241,53 @@ __global__ void k_gather_records(Records r, const int32_t* __restrict__ n_of, co
     col[o + a] = r.col[s];
     acol[o + a] = r.acol[s];
   }
+}
+
+// Append the final partons of `count` events held slot-major in r (parton
+// counts n_dev on the device, n_host on the host) to box's CSR records.
+vsh_status gather_records(vsh_ctx* ctx, const Records& r, const int32_t* n_dev, const int32_t* n_host,
+                          uint64_t count, ResultBox* box) {
+  hipStream_t st = ctx->stream;
+  std::vector<uint64_t> off(count + 1, 0);
+  for (uint64_t e = 0; e < count; ++e) off[e + 1] = off[e] + (uint64_t)n_host[e];
+  const uint64_t total = off[count];
+  const uint64_t need = align_up((count + 1) * 8, 256) + align_up(total * 32, 256) + align_up(total, 256) +
+                        2 * align_up(total * 2, 256) + 256;
+  vsh_status rc = ctx->arena2.reserve(ctx, need);
+  if (rc) return rc;
+  char* q = (char*)ctx->arena2.ptr;
+  uint64_t* d_off = (uint64_t*)q;
+  q += align_up((count + 1) * 8, 256);
+  double* d_p = (double*)q;
+  q += align_up(total * 32, 256);
+  int8_t* d_pid = (int8_t*)q;
+  q += align_up(total, 256);
+  uint16_t* d_col = (uint16_t*)q;
+  q += align_up(total * 2, 256);
+  uint16_t* d_acol = (uint16_t*)q;
+  hipError_t err = hipMemcpyAsync(d_off, off.data(), (count + 1) * 8, hipMemcpyHostToDevice, st);
+  if (err != hipSuccess) return hip_fail(ctx, err, "offset copy");
+  hipLaunchKernelGGL(k_gather_records, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, st, r, n_dev,
+                     (const uint64_t*)d_off, (uint32_t)count, d_p, d_pid, d_col, d_acol);
+  err = hipGetLastError();
+  if (err != hipSuccess) return hip_fail(ctx, err, "k_gather_records");
+  const uint64_t base = box->rec_offsets.empty() ? 0 : box->rec_offsets.back();
+  if (box->rec_offsets.empty()) box->rec_offsets.push_back(0);
+  for (uint64_t e = 0; e < count; ++e) box->rec_offsets.push_back(base + off[e + 1]);
+  box->rec_p.resize((base + total) * 4);
+  box->rec_pid.resize(base + total);
+  box->rec_col.resize(base + total);
+  box->rec_acol.resize(base + total);
+  if (total) {
+    err = hipMemcpyAsync(&box->rec_p[base * 4], d_p, total * 32, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipMemcpyAsync(&box->rec_pid[base], d_pid, total, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipMemcpyAsync(&box->rec_col[base], d_col, total * 2, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipMemcpyAsync(&box->rec_acol[base], d_acol, total * 2, hipMemcpyDeviceToHost, st);
+    if (err != hipSuccess) return hip_fail(ctx, err, "record copy");
+  }
+  err = hipStreamSynchronize(st);
+  if (err != hipSuccess) return hip_fail(ctx, err, "hipStreamSynchronize");
+  return VSH_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -362,43 +411,8 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
     std::memcpy(&box->hash[first_idx], hs.data(), count * 8);
   }
   if (req->flags & VSH_RECORDS) {
-    // CSR offsets from the parton counts, then a device gather and one copy
-    std::vector<uint64_t> off(count + 1, 0);
-    for (uint64_t e = 0; e < count; ++e) off[e + 1] = off[e] + (uint64_t)si[kSiN * stride + e];
-    const uint64_t total = off[count];
-    const uint64_t need = align_up((count + 1) * 8, 256) + align_up(total * 32, 256) +
-                          align_up(total, 256) + 2 * align_up(total * 2, 256);
-    rc = ctx->arena2.reserve(ctx, need);
+    rc = gather_records(ctx, L.rec, L.sum.i + kSiN * stride, si.data() + kSiN * stride, count, box);
     if (rc) return rc;
-    char* q = (char*)ctx->arena2.ptr;
-    uint64_t* d_off = (uint64_t*)q;
-    q += align_up((count + 1) * 8, 256);
-    double* d_p = (double*)q;
-    q += align_up(total * 32, 256);
-    int8_t* d_pid = (int8_t*)q;
-    q += align_up(total, 256);
-    uint16_t* d_col = (uint16_t*)q;
-    q += align_up(total * 2, 256);
-    uint16_t* d_acol = (uint16_t*)q;
-    HIPCHK(hipMemcpyAsync(d_off, off.data(), (count + 1) * 8, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_gather_records, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, st, L.rec,
-                       (const int32_t*)(L.sum.i + kSiN * stride), (const uint64_t*)d_off, (uint32_t)count,
-                       d_p, d_pid, d_col, d_acol);
-    HIPCHK(hipGetLastError());
-    const uint64_t base = box->rec_offsets.empty() ? 0 : box->rec_offsets.back();
-    if (box->rec_offsets.empty()) box->rec_offsets.push_back(0);
-    for (uint64_t e = 0; e < count; ++e) box->rec_offsets.push_back(base + off[e + 1]);
-    box->rec_p.resize((base + total) * 4);
-    box->rec_pid.resize(base + total);
-    box->rec_col.resize(base + total);
-    box->rec_acol.resize(base + total);
-    if (total) {
-      HIPCHK(hipMemcpyAsync(&box->rec_p[base * 4], d_p, total * 32, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(&box->rec_pid[base], d_pid, total, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(&box->rec_col[base], d_col, total * 2, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(&box->rec_acol[base], d_acol, total * 2, hipMemcpyDeviceToHost, st));
-    }
-    HIPCHK(hipStreamSynchronize(st));
   }
 #undef HIPCHK
   return VSH_OK;
@@ -513,6 +527,13 @@ vsh_status vsh_create(const vsh_ctx_opts* opts, vsh_ctx** out) {
     delete ctx;
     return hip_fail(nullptr, err, "hipStreamCreate");
   }
+  for (auto& e : ctx->idle_ev) {
+    err = hipEventCreate(&e);
+    if (err != hipSuccess) {
+      delete ctx;
+      return hip_fail(nullptr, err, "hipEventCreate");
+    }
+  }
   for (auto& e : ctx->ev) {
     err = hipEventCreate(&e);
     if (err != hipSuccess) {
@@ -532,6 +553,9 @@ void vsh_destroy(vsh_ctx* ctx) {
   ctx->arena.release();
   ctx->arena2.release();
   for (auto& e : ctx->timing_ev) (void)hipEventDestroy(e);
+  destroy_graph(ctx->graph);
+  for (auto& e : ctx->idle_ev)
+    if (e) (void)hipEventDestroy(e);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);

@@ -14,6 +14,7 @@
 
 #include "../../include/vsh.h"
 #include "vsh_kernels.hpp"
+#include "vsh_persistent.hpp"
 
 namespace vsh {
 
@@ -42,7 +43,8 @@ struct Tuned {
   uint32_t plain_block = 256;
   uint32_t pers_block = 256;
   uint32_t pers_waves_per_cu = 8;
-  uint32_t refill_period = 1;  // cycles between compaction / refill passes
+  uint32_t refill_period = 1;     // veto cycles between compaction / refill passes
+  uint32_t refill_threshold = 1;  // idle lanes needed before a wave refills
 };
 
 struct ServeState;
@@ -55,6 +57,8 @@ struct vsh_ctx {
   uint64_t budget = 0;
   hipStream_t stream = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t idle_ev[4] = {nullptr, nullptr, nullptr, nullptr};  // graph event nodes when not timing
+  vsh::BatchGraph graph;
   vsh::Arena arena, arena2;
   vsh::Tuned tuned;
   std::mutex mu;
@@ -87,7 +91,11 @@ void tally_chunk(ResultBox* b, const int32_t* si, const double* sd, uint64_t str
 uint64_t plain_layout_bytes(uint64_t stride, uint32_t cap);
 PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap);
 
+vsh_status gather_records(vsh_ctx* ctx, const Records& r, const int32_t* n_dev, const int32_t* n_host,
+                          uint64_t count, ResultBox* box);
+
 // persistent form (vsh_persistent.hip)
+uint32_t persistent_lanes(const vsh_ctx* ctx);
 vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result** out);
 uint64_t persistent_workspace_bytes(const vsh_request* req);
 hipEvent_t* timing_slot(vsh_ctx* ctx);

@@ -81,6 +81,12 @@ struct Scratch {
 
 // host-side launchers (vsh_kernels.hip)
 namespace vsh {
+// k_obs runs a grid-stride loop over at most kObsBlocks x 256 threads; each
+// thread owns one Durham scratch slot, so the scratch holds obs_threads(n)
+// slots of cap partons.
+constexpr uint32_t kObsBlocks = 2048;
+uint64_t obs_threads(uint64_t n);
+__global__ void k_obs(Records r, Summary sm, EventInputs in, Scratch sc, uint32_t n, double* __restrict__ hist);
 void launch_me(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
                hipStream_t st);
 void launch_shower_plain(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,

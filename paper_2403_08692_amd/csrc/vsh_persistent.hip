@@ -1,20 +1,535 @@
-// vsh_persistent.hip -- persistent-wave form of the shower (placeholder until
-// the persistent kernel lands).
+// vsh_persistent.hip -- the batched form: persistent waves that keep every
+// lane busy with a fresh event until the work runs out.
+//
+// The paper's parallel veto algorithm (Sec. 2) runs one step for all events
+// in lockstep and leaves finished events idle until the last one reaches the
+// cutoff (Fig. 3; Fig. 7 shows the long tail).  Here each lane of a resident
+// wave owns one event slot.  After every `period` veto cycles the wave takes a
+// ballot of its idle lanes; if at least `threshold` are idle (or all are), one
+// lane claims that many event indices from a global work counter with a
+// single atomic, and the idle lanes take consecutive indices in lane order
+// (prefix count of the ballot below the lane).  A lane whose event finishes
+// copies the final partons and summary to the event's own output position.
+// A wave exits when the counter is exhausted and none of its lanes is busy.
+//
+// The work space is a list of segments (request, event range), so events of
+// several requests share one launch (serving); observables and histograms are
+// computed afterwards per request by k_obs over its output records.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
 #include "vsh_internal.hpp"
+#include "vsh_observables.hpp"
+#include "vsh_persistent.hpp"
+#include "vsh_shower.hpp"
 
 namespace vsh {
 
-vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request*, vsh_result**) {
-  set_error(ctx, "persistent form not available");
-  return VSH_E_INVALID;
+__device__ __forceinline__ uint32_t find_segment(const Segment* segs, uint32_t n, uint64_t w) {
+  uint32_t lo = 0, hi = n;  // segs[k].start ascending; find last k with start <= w
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (segs[mid].start <= w) lo = mid;
+    else hi = mid;
+  }
+  return lo;
 }
 
-uint64_t persistent_workspace_bytes(const vsh_request*) { return 0; }
+__global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
+  const uint64_t L = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;  // this lane's slot
+  const uint32_t lane = __lane_id();
+  const uint64_t wave_mask = __ballot(1);
+  const uint32_t wave_lanes = __popcll(wave_mask);
+  EvState s;
+  s.status = kDone;
+  bool busy = false;
+  bool drained = false;
+  uint32_t req = 0;
+  uint64_t ev = 0;  // event index within its request
+  uint32_t since = 0;
+  while (true) {
+    const uint64_t idle = __ballot(!busy);
+    const uint32_t n_idle = __popcll(idle);
+    if (!drained && n_idle > 0 &&
+        (n_idle == wave_lanes || (since >= A.period && n_idle >= A.threshold))) {
+      since = 0;
+      const uint32_t leader = __ffsll((unsigned long long)idle) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(A.next, (unsigned long long)n_idle);
+      base = __shfl(base, leader);
+      if (base + n_idle >= A.total) drained = true;
+      if (!busy) {
+        const uint64_t w = base + __popcll(idle & ((1ull << lane) - 1));
+        if (w < A.total) {
+          const uint32_t sg = find_segment(A.segs, A.n_segs, w);
+          req = A.segs[sg].req;
+          ev = A.segs[sg].lo + (w - A.segs[sg].start);
+          const ReqDev& R = A.reqs[req];
+          const double ecm = R.ecm ? R.ecm[ev] : R.ecm0;
+          const double tcut = R.tcut ? R.tcut[ev] : R.tcut0;
+          const Keyed key = make_keyed(R.seed, R.first + ev);
+          const MEOut m = me_event(A.slots, L, key, ecm);
+          const Summary& sm = R.sum;
+          sm.d[kSdW * sm.stride + ev] = m.w;
+          sm.d[kSdCos * sm.stride + ev] = m.c;
+          sm.d[kSdPhi * sm.stride + ev] = m.phi;
+          sm.i[kSiFlavour * sm.stride + ev] = m.f;
+          init_state(s, A.slots, L, key, ecm, tcut, 2);
+          busy = true;
+        }
+      }
+    }
+    if (!__any(busy)) break;  // counter exhausted and nothing left in this wave
+    if (busy) {
+      veto_cycle(s, A.slots, L);
+      if (s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
+      if (s.status != kRunning) {
+        const ReqDev& R = A.reqs[req];
+        const Records& o = R.out;
+        for (int a = 0; a < s.n; ++a) {
+          const uint64_t from = (uint64_t)a * A.slots.stride + L;
+          const uint64_t to = (uint64_t)a * o.stride + ev;
+          o.E[to] = A.slots.E[from];
+          o.x[to] = A.slots.x[from];
+          o.y[to] = A.slots.y[from];
+          o.z[to] = A.slots.z[from];
+          o.pid[to] = A.slots.pid[from];
+          o.col[to] = A.slots.col[from];
+          o.acol[to] = A.slots.acol[from];
+        }
+        write_state(s, R.sum, ev);
+        busy = false;
+      }
+    }
+    ++since;
+  }
+}
 
-vsh_status persistent_into(vsh_ctx* ctx, const vsh_request*, hipStream_t, void*, double*, double*,
-                           int32_t*, uint64_t*) {
-  set_error(ctx, "persistent form not available");
-  return VSH_E_INVALID;
+// Writes a batch's request and segment descriptors (passed by value, so the
+// launch carries them) and zeroes the work counter.
+__global__ void k_setup(ReqDev* rd, ReqDev d, Segment* sd, Segment s, unsigned long long* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *rd = d;
+    *sd = s;
+    *counter = 0ull;
+  }
+}
+
+__global__ void k_zero(double* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+uint32_t persistent_lanes(const vsh_ctx* ctx) {
+  const uint32_t waves = std::max<uint32_t>(1, ctx->tuned.pers_waves_per_cu) * (uint32_t)ctx->n_cu;
+  return waves * 64;
+}
+
+static uint32_t lanes_for_budget(uint32_t n_cu, uint32_t waves_per_cu) {
+  return std::max<uint32_t>(1, waves_per_cu) * n_cu * 64;
+}
+
+uint64_t slots_bytes(uint64_t lanes, uint32_t cap) { return lanes * cap * (4 * 8 + 1 + 4 * 2) + 9 * 256; }
+
+uint64_t request_out_bytes(uint64_t n, uint32_t cap) {
+  return n * cap * (4 * 8 + 1 + 2 * 2) + n * (kNSumD * 8 + kNSumI * 4 + 8) + 2 * n * 8 + 16 * 256 +
+         kHistDoubles * 8;
+}
+
+uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap) { return obs_threads(n) * cap * 32 + 4 * 256; }
+
+Carver::Carver(void* base) : p(static_cast<char*>(base)) {}
+char* Carver::take(uint64_t bytes) {
+  char* q = p;
+  p += align_up(bytes, 256);
+  return q;
+}
+
+Records carve_slots(Carver& c, uint64_t lanes, uint32_t cap) {
+  Records r;
+  const uint64_t n = lanes * cap;
+  r.E = (double*)c.take(n * 8);
+  r.x = (double*)c.take(n * 8);
+  r.y = (double*)c.take(n * 8);
+  r.z = (double*)c.take(n * 8);
+  r.pid = (int8_t*)c.take(n);
+  r.col = (uint16_t*)c.take(n * 2);
+  r.acol = (uint16_t*)c.take(n * 2);
+  r.cpart = (uint16_t*)c.take(n * 2);
+  r.apart = (uint16_t*)c.take(n * 2);
+  r.stride = lanes;
+  r.cap = cap;
+  return r;
+}
+
+ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap) {
+  ReqBuffers b;
+  const uint64_t m = n * cap;
+  b.out.E = (double*)c.take(m * 8);
+  b.out.x = (double*)c.take(m * 8);
+  b.out.y = (double*)c.take(m * 8);
+  b.out.z = (double*)c.take(m * 8);
+  b.out.pid = (int8_t*)c.take(m);
+  b.out.col = (uint16_t*)c.take(m * 2);
+  b.out.acol = (uint16_t*)c.take(m * 2);
+  b.out.cpart = nullptr;
+  b.out.apart = nullptr;
+  b.out.stride = n;
+  b.out.cap = cap;
+  b.sum.d = (double*)c.take(kNSumD * n * 8);
+  b.sum.i = (int32_t*)c.take(kNSumI * n * 4);
+  b.sum.hash = (uint64_t*)c.take(n * 8);
+  b.sum.stride = n;
+  b.ecm = (double*)c.take(n * 8);
+  b.tcut = (double*)c.take(n * 8);
+  b.hist = (double*)c.take(kHistDoubles * 8);
+  return b;
+}
+
+Scratch carve_scratch(Carver& c, uint64_t n, uint32_t cap) {
+  Scratch s;
+  const uint64_t t = obs_threads(n);
+  s.jE = (double*)c.take(t * cap * 8);
+  s.jx = (double*)c.take(t * cap * 8);
+  s.jy = (double*)c.take(t * cap * 8);
+  s.jz = (double*)c.take(t * cap * 8);
+  s.stride = t;
+  return s;
+}
+
+uint64_t batch_bytes(uint64_t lanes, uint64_t n, uint32_t cap) {
+  return slots_bytes(lanes, cap) + request_out_bytes(n, cap) + obs_scratch_bytes(n, cap) + 4096 +
+         sizeof(ReqDev) + sizeof(Segment) + 1024;
+}
+
+BatchLayout carve_batch(void* base, uint64_t lanes, uint64_t n, uint32_t cap) {
+  Carver c(base);
+  BatchLayout L;
+  L.slots = carve_slots(c, lanes, cap);
+  L.buf = carve_request(c, n, cap);
+  L.sc = carve_scratch(c, n, cap);
+  L.counter = (unsigned long long*)c.take(256);
+  L.reqs = (ReqDev*)c.take(sizeof(ReqDev));
+  L.segs = (Segment*)c.take(sizeof(Segment));
+  L.end = c.p;
+  return L;
+}
+
+void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, hipStream_t st) {
+  hipLaunchKernelGGL(k_shower_persistent, dim3((uint32_t)(lanes / block)), dim3(block), 0, st, A);
+}
+
+void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, unsigned long long* counter,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, rd, d, sd, s, counter);
+}
+
+void launch_zero(double* p, uint32_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+}
+
+// Host-side graph of one batch: [ev0] reset [ev1] persistent [ev2] obs [ev3].
+// The event nodes are pointed at the call's timing events (or at the
+// context's idle set) before each launch.
+static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistArgs& A, const ReqDev& d,
+                                    const Segment& sg, uint64_t lanes, uint32_t block, const BatchLayout& L,
+                                    const EventInputs& in, uint64_t n, double* hist) {
+  hipError_t err;
+#define GCHK(x)                                          \
+  do {                                                   \
+    err = (x);                                           \
+    if (err != hipSuccess) return hip_fail(ctx, err, #x); \
+  } while (0)
+  GCHK(hipGraphCreate(&g.graph, 0));
+  hipGraphNode_t prev = nullptr;
+  auto add_event = [&](int k) -> hipError_t {
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddEventRecordNode(&node, g.graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                              ctx->idle_ev[k]);
+    if (e == hipSuccess) {
+      g.ev_nodes[k] = node;
+      prev = node;
+    }
+    return e;
+  };
+  auto add_kernel = [&](const void* fn, dim3 grid, dim3 blk, void** args) -> hipError_t {
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(fn);
+    p.gridDim = grid;
+    p.blockDim = blk;
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddKernelNode(&node, g.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+    if (e == hipSuccess) prev = node;
+    return e;
+  };
+  g.args = A;
+  g.d = d;
+  g.s = sg;
+  g.rd = L.reqs;
+  g.sd = L.segs;
+  g.counter = L.counter;
+  g.rec = L.buf.out;
+  g.sum = L.buf.sum;
+  g.in = in;
+  g.sc = L.sc;
+  g.n = (uint32_t)n;
+  g.hist = hist;
+  GCHK(add_event(0));
+  void* a_setup[] = {&g.rd, &g.d, &g.sd, &g.s, &g.counter};
+  GCHK(add_kernel((const void*)k_setup, dim3(1), dim3(64), a_setup));
+  GCHK(add_event(1));
+  void* a_pers[] = {&g.args};
+  GCHK(add_kernel((const void*)k_shower_persistent, dim3((uint32_t)(lanes / block)), dim3(block), a_pers));
+  GCHK(add_event(2));
+  void* a_obs[] = {&g.rec, &g.sum, &g.in, &g.sc, &g.n, &g.hist};
+  GCHK(add_kernel((const void*)k_obs, dim3((uint32_t)(obs_threads(n) / 256)), dim3(256), a_obs));
+  GCHK(add_event(3));
+  GCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+#undef GCHK
+  return VSH_OK;
+}
+
+void destroy_graph(BatchGraph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g = BatchGraph{};
+}
+
+static void fill_request_desc(ReqDev& d, const ReqBuffers& b, const vsh_request* req, uint64_t first_idx,
+                              const double* ecm_dev, const double* tcut_dev) {
+  d.out = b.out;
+  d.sum = b.sum;
+  d.ecm = ecm_dev;
+  d.tcut = tcut_dev;
+  d.ecm0 = req->ecm;
+  d.tcut0 = req->t_cut;
+  d.seed = req->seed;
+  d.first = req->first_event + first_idx;
+  d.count = b.sum.stride;
+}
+
+// One batch of `n` events of req (starting at request index first_idx)
+// through the persistent form on stream st, with the batch's buffers in the
+// workspace at `base`.  Inputs: per-event arrays already on the device (or
+// null).  Writes the histogram into hist (accumulates).
+static vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, uint64_t n,
+                            hipStream_t st, void* base, const double* ecm_dev, const double* tcut_dev,
+                            double* hist, bool use_graph, BatchLayout* out_layout) {
+  const uint32_t cap = req->max_partons;
+  const uint64_t lanes = persistent_lanes(ctx);
+  const uint32_t block = ctx->tuned.pers_block;
+  BatchLayout L = carve_batch(base, lanes, n, cap);
+  if (out_layout) *out_layout = L;
+  ReqDev d;
+  fill_request_desc(d, L.buf, req, first_idx, ecm_dev, tcut_dev);
+  Segment sg{0, 0, 0, n, 0};
+  hipError_t err;
+  PersistArgs A;
+  A.slots = L.slots;
+  A.reqs = L.reqs;
+  A.segs = L.segs;
+  A.n_segs = 1;
+  A.total = n;
+  A.next = L.counter;
+  A.threshold = ctx->tuned.refill_threshold;
+  A.period = ctx->tuned.refill_period;
+  EventInputs in{};
+  in.ecm = ecm_dev;
+  in.tcut = tcut_dev;
+  in.ecm0 = req->ecm;
+  in.tcut0 = req->t_cut;
+  in.seed = req->seed;
+  in.first = req->first_event + first_idx;
+  hipEvent_t* tev = timing_slot(ctx);
+  if (use_graph) {
+    BatchGraph& g = ctx->graph;
+    const bool same = g.exec && std::memcmp(&g.args, &A, sizeof A) == 0 && g.hist == hist && g.n == n &&
+                      std::memcmp(&g.in, &in, sizeof in) == 0 && std::memcmp(&g.d, &d, sizeof d) == 0 &&
+                      std::memcmp(&g.s, &sg, sizeof sg) == 0 && g.lanes == lanes && g.block == block;
+    if (!same) {
+      destroy_graph(g);
+      vsh_status rc = build_batch_graph(ctx, g, A, d, sg, lanes, block, L, in, n, hist);
+      if (rc) {
+        destroy_graph(g);
+        return rc;
+      }
+      g.lanes = lanes;
+      g.block = block;
+    }
+    for (int k = 0; k < 4; ++k) {
+      err = hipGraphExecEventRecordNodeSetEvent(g.exec, g.ev_nodes[k], tev ? tev[k] : ctx->idle_ev[k]);
+      if (err != hipSuccess) return hip_fail(ctx, err, "hipGraphExecEventRecordNodeSetEvent");
+    }
+    err = hipGraphLaunch(g.exec, st);
+    if (err != hipSuccess) return hip_fail(ctx, err, "hipGraphLaunch");
+  } else {
+    if (tev) (void)hipEventRecord(tev[0], st);
+    launch_setup(L.reqs, d, L.segs, sg, L.counter, st);
+    if (tev) (void)hipEventRecord(tev[1], st);
+    launch_persistent(A, lanes, block, st);
+    if (tev) (void)hipEventRecord(tev[2], st);
+    launch_obs(L.buf.out, L.buf.sum, in, L.sc, (uint32_t)n, hist, st);
+    if (tev) (void)hipEventRecord(tev[3], st);
+    err = hipGetLastError();
+    if (err != hipSuccess) return hip_fail(ctx, err, "kernel launch");
+  }
+  return VSH_OK;
+}
+
+uint64_t persistent_workspace_bytes_ctx(const vsh_ctx* ctx, const vsh_request* req) {
+  return batch_bytes(persistent_lanes(ctx), req->n_events, req->max_partons);
+}
+
+uint64_t persistent_workspace_bytes(const vsh_request* req) {
+  // independent of the context: sized for the largest tuned grid (16 waves per CU on 256 CUs)
+  return batch_bytes(lanes_for_budget(256, 16), req->n_events, req->max_partons);
+}
+
+vsh_status persistent_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void* ws, double* dev_hist,
+                           double* dev_sum_d, int32_t* dev_sum_i, uint64_t* dev_hash) {
+  const uint64_t n = req->n_events;
+  if (persistent_lanes(ctx) > lanes_for_budget(256, 16)) {
+    set_error(ctx, "persistent grid larger than the workspace allows");
+    return VSH_E_INTERNAL;
+  }
+  BatchLayout L;
+  vsh_status rc = run_batch(ctx, req, 0, n, st, ws, req->ecm_per_event, req->tcut_per_event, dev_hist, true, &L);
+  if (rc) return rc;
+  hipError_t err;
+  if (dev_sum_d) {
+    err = hipMemcpyAsync(dev_sum_d, L.buf.sum.d, kNSumD * n * 8, hipMemcpyDeviceToDevice, st);
+    if (err != hipSuccess) return hip_fail(ctx, err, "summary copy");
+  }
+  if (dev_sum_i) {
+    err = hipMemcpyAsync(dev_sum_i, L.buf.sum.i, kNSumI * n * 4, hipMemcpyDeviceToDevice, st);
+    if (err != hipSuccess) return hip_fail(ctx, err, "summary copy");
+  }
+  if (dev_hash) {
+    err = hipMemcpyAsync(dev_hash, L.buf.sum.hash, n * 8, hipMemcpyDeviceToDevice, st);
+    if (err != hipSuccess) return hip_fail(ctx, err, "summary copy");
+  }
+  return VSH_OK;
+}
+
+vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result** out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const uint32_t cap = req->max_partons;
+  const uint64_t lanes = persistent_lanes(ctx);
+  // chunk so that a batch fits the budget (half of it when records are returned)
+  uint64_t budget = ctx->budget;
+  if (req->flags & VSH_RECORDS) budget /= 2;
+  const uint64_t fixed = slots_bytes(lanes, cap) + 64 * 1024;
+  if (budget <= fixed + request_out_bytes(64, cap) + obs_scratch_bytes(64, cap)) {
+    set_error(ctx, "memory budget too small for the persistent form at %u partons", cap);
+    return VSH_E_NOMEM;
+  }
+  const uint64_t per_event = request_out_bytes(1, cap) + 64 + (uint64_t)cap * 32;
+  uint64_t chunk = std::min<uint64_t>(req->n_events, (budget - fixed) / per_event);
+  chunk = std::min<uint64_t>(chunk, 1ull << 27);
+  ResultBox* box = new_result(req->n_events, req->flags & VSH_SUMMARY);
+  if (!box) {
+    set_error(ctx, "host allocation failed");
+    return VSH_E_NOMEM;
+  }
+  hipStream_t st = ctx->stream;
+  float t_me = 0, t_sh = 0, t_obs = 0;
+  for (uint64_t a = 0; a < req->n_events; a += chunk) {
+    const uint64_t n = std::min(chunk, req->n_events - a);
+    vsh_status rc = ctx->arena.reserve(ctx, batch_bytes(lanes, n, cap));
+    if (rc) {
+      delete box;
+      return rc;
+    }
+    BatchLayout L = carve_batch(ctx->arena.ptr, lanes, n, cap);
+    hipError_t err;
+    const double* ecm_dev = nullptr;
+    const double* tcut_dev = nullptr;
+    if (req->ecm_per_event) {
+      err = hipMemcpyAsync(L.buf.ecm, req->ecm_per_event + a, n * 8, hipMemcpyHostToDevice, st);
+      if (err != hipSuccess) { delete box; return hip_fail(ctx, err, "input copy"); }
+      ecm_dev = L.buf.ecm;
+    }
+    if (req->tcut_per_event) {
+      err = hipMemcpyAsync(L.buf.tcut, req->tcut_per_event + a, n * 8, hipMemcpyHostToDevice, st);
+      if (err != hipSuccess) { delete box; return hip_fail(ctx, err, "input copy"); }
+      tcut_dev = L.buf.tcut;
+    }
+    launch_zero(L.buf.hist, kHistDoubles, st);
+    (void)hipEventRecord(ctx->ev[0], st);
+    PersistArgs A;
+    ReqDev d;
+    fill_request_desc(d, L.buf, req, a, ecm_dev, tcut_dev);
+    const Segment sg{0, 0, 0, n, 0};
+    launch_setup(L.reqs, d, L.segs, sg, L.counter, st);
+    A.slots = L.slots;
+    A.reqs = L.reqs;
+    A.segs = L.segs;
+    A.n_segs = 1;
+    A.total = n;
+    A.next = L.counter;
+    A.threshold = ctx->tuned.refill_threshold;
+    A.period = ctx->tuned.refill_period;
+    (void)hipEventRecord(ctx->ev[1], st);
+    launch_persistent(A, lanes, ctx->tuned.pers_block, st);
+    (void)hipEventRecord(ctx->ev[2], st);
+    EventInputs in{};
+    in.ecm = ecm_dev;
+    in.tcut = tcut_dev;
+    in.ecm0 = req->ecm;
+    in.tcut0 = req->t_cut;
+    in.seed = req->seed;
+    in.first = req->first_event + a;
+    launch_obs(L.buf.out, L.buf.sum, in, L.sc, (uint32_t)n, L.buf.hist, st);
+    (void)hipEventRecord(ctx->ev[3], st);
+    err = hipGetLastError();
+    if (err != hipSuccess) { delete box; return hip_fail(ctx, err, "kernel launch"); }
+    std::vector<double> hh(kHistDoubles), sd((size_t)kNSumD * n);
+    std::vector<int32_t> si((size_t)kNSumI * n);
+    std::vector<uint64_t> hs(n);
+    err = hipMemcpyAsync(hh.data(), L.buf.hist, kHistDoubles * 8, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipMemcpyAsync(sd.data(), L.buf.sum.d, sd.size() * 8, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipMemcpyAsync(si.data(), L.buf.sum.i, si.size() * 4, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipMemcpyAsync(hs.data(), L.buf.sum.hash, n * 8, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    if (err != hipSuccess) { delete box; return hip_fail(ctx, err, "result copy"); }
+    float ms;
+    if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) t_me += ms;
+    if (hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]) == hipSuccess) t_sh += ms;
+    if (hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]) == hipSuccess) t_obs += ms;
+    for (int k = 0; k < kHistDoubles; ++k) box->hist[k] += hh[k];
+    tally_chunk(box, si.data(), sd.data(), n, n);
+    if (!box->sum_d.empty()) {
+      const uint64_t N = box->pub.n_events;
+      for (int f = 0; f < kNSumD; ++f) std::memcpy(&box->sum_d[f * N + a], &sd[f * n], n * 8);
+      for (int f = 0; f < kNSumI; ++f) std::memcpy(&box->sum_i[f * N + a], &si[f * n], n * 4);
+      std::memcpy(&box->hash[a], hs.data(), n * 8);
+    }
+    if (req->flags & VSH_RECORDS) {
+      vsh_status rc2 = gather_records(ctx, L.buf.out, L.buf.sum.i + kSiN * n, si.data() + kSiN * n, n, box);
+      if (rc2) {
+        delete box;
+        return rc2;
+      }
+    }
+  }
+  box->pub.t_me_ms = t_me;
+  box->pub.t_shower_ms = t_sh;
+  box->pub.t_obs_ms = t_obs;
+  box->pub.t_total_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  finish_result(box);
+  *out = &box->pub;
+  return VSH_OK;
 }
 
 }  // namespace vsh

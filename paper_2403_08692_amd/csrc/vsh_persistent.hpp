@@ -1,0 +1,98 @@
+// vsh_persistent.hpp -- device-visible descriptors of the persistent form and
+// the host-side layout helpers shared with the serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "vsh_kernels.hpp"
+
+namespace vsh {
+
+// one request as the persistent kernel sees it: where its events' outputs
+// go and how to name its events
+struct ReqDev {
+  Records out;          // final partons [cap][count] (partner links unused)
+  Summary sum;          // [field][count]
+  const double* ecm;    // per-event sqrt(s) [count] or null -> ecm0
+  const double* tcut;   // per-event t_C [count] or null -> tcut0
+  double ecm0, tcut0;
+  uint64_t seed, first;  // event ids first .. first + count - 1
+  uint64_t count;
+};
+
+// a contiguous range of one request's events inside a launch's work space
+struct Segment {
+  uint32_t req, pad;
+  uint64_t lo, hi;   // request event indices [lo, hi)
+  uint64_t start;    // first work index of this segment
+};
+
+struct PersistArgs {
+  Records slots;                  // working records, one slot per lane [cap][lanes]
+  const ReqDev* reqs;
+  const Segment* segs;
+  uint32_t n_segs;
+  uint32_t threshold;             // refill when at least this many lanes idle (or all)
+  uint64_t total;                 // work indices 0 .. total-1
+  unsigned long long* next;       // work counter, zeroed before the launch
+  uint32_t period;                // veto cycles between refill checks
+  uint32_t pad;
+};
+
+struct ReqBuffers {
+  Records out;
+  Summary sum;
+  double *ecm, *tcut, *hist;
+};
+
+struct Carver {
+  char* p;
+  explicit Carver(void* base);
+  char* take(uint64_t bytes);
+};
+
+struct BatchLayout {
+  Records slots;
+  ReqBuffers buf;
+  Scratch sc;
+  unsigned long long* counter;
+  ReqDev* reqs;
+  Segment* segs;
+  char* end;
+};
+
+// the launch sequence of one batch as an instantiated hipGraph; the kernel
+// arguments live here so the graph's parameter pointers stay valid
+struct BatchGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t ev_nodes[4] = {nullptr, nullptr, nullptr, nullptr};
+  ReqDev* rd = nullptr;
+  ReqDev d{};
+  Segment* sd = nullptr;
+  Segment s{};
+  unsigned long long* counter = nullptr;
+  PersistArgs args{};
+  Records rec{};
+  Summary sum{};
+  EventInputs in{};
+  Scratch sc{};
+  uint32_t n = 0;
+  double* hist = nullptr;
+  uint64_t lanes = 0;
+  uint32_t block = 0;
+};
+
+uint64_t slots_bytes(uint64_t lanes, uint32_t cap);
+uint64_t request_out_bytes(uint64_t n, uint32_t cap);
+uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap);
+Records carve_slots(Carver& c, uint64_t lanes, uint32_t cap);
+ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap);
+Scratch carve_scratch(Carver& c, uint64_t n, uint32_t cap);
+void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, hipStream_t st);
+void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, unsigned long long* counter,
+                  hipStream_t st);
+void launch_zero(double* p, uint32_t n, hipStream_t st);
+void destroy_graph(BatchGraph& g);
+
+}  // namespace vsh

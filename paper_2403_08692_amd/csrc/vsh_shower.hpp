@@ -1,0 +1,251 @@
+// vsh_shower.hpp -- one event's shower state and one cycle of the veto
+// algorithm (App. A SelectWinnerEmission + GenerateEmission; App. C
+// SelectWinner / CheckCutoff / alpha_s / AcceptOrVeto / GenerateEmission),
+// shared by the plain and the persistent forms; and the LO matrix element
+// that starts an event (App. B).
+#pragma once
+
+#include "vsh_kernels.hpp"
+
+namespace vsh {
+
+// LO event into slot `e` of r: flavour uniform over d,u,s,c,b by a 64-bit
+// multiply-shift of one 32-bit word, cos(theta), phi uniform; weight
+// 5 |M|^2 / (16 pi s) in pb.  Quark in slot 0 (colour line 1), antiquark in
+// slot 1, back to back.
+struct MEOut {
+  double w, c, phi;
+  int f;
+};
+
+__device__ __forceinline__ MEOut me_event(const Records& r, uint64_t e, const Keyed& key, double ecm) {
+  const U4 a = key.draw(0, kPurposeME, 0);
+  const int f = 1 + (int)(((uint64_t)a.x * 5u) >> 32);
+  const double c = 2.0 * unit(a.z, a.w) - 1.0;
+  const U4 b = key.draw(0, kPurposeME, 1);
+  const double phi = 2.0 * kPi * unit(b.x, b.y);
+  const double sh = ecm * ecm;
+  const double w = 5.0 * me2(f, sh, c) / (16.0 * kPi * sh) * kGeV2ToPb;
+  const double st = sqrt((1.0 - c) * (1.0 + c));
+  const double en = 0.5 * ecm;
+  const double px = en * st * cos(phi), py = en * st * sin(phi), pz = en * c;
+  r.store(0, e, P4{en, px, py, pz});
+  r.store(1, e, P4{en, -px, -py, -pz});
+  r.pid[e] = (int8_t)f;
+  r.pid[r.stride + e] = (int8_t)(-f);
+  r.col[e] = 1;
+  r.acol[e] = 0;
+  r.col[r.stride + e] = 0;
+  r.acol[r.stride + e] = 1;
+  r.cpart[e] = 1;
+  r.apart[e] = kNoPartner;
+  r.cpart[r.stride + e] = kNoPartner;
+  r.apart[r.stride + e] = 0;
+  return MEOut{w, c, phi, f};
+}
+
+// ---------------------------------------------------------------------------
+// Shower state of one event held in registers while it evolves.
+// ---------------------------------------------------------------------------
+struct EvState {
+  Keyed key;
+  double lt;     // ln t, the current upper scale
+  double tcut, ltc, asmax, cfac;
+  uint64_t hash;
+  uint32_t cycle, trials, ends;
+  int n, next_col, n_emit, status;
+};
+
+struct Winner {
+  double q2, zm, zp;
+  int i, k, K;
+};
+
+// All trials of the dipole end (i, k): one per kernel of the splitter,
+// t_try = t R^(1/c) compared as ln t + ln(R)/c (App. A, trial-scale
+// equation); strict maximum above the running best.  A gluon end's five
+// g -> f fbar kernels share c, so only their largest uniform needs a log.
+__device__ __forceinline__ void end_trials(EvState& s, int i, int k, int pid_i, const P4& pi,
+                                           const P4& pk, double& best, Winner& w) {
+  const double q2 = 2.0 * mdot(pi, pk);
+  if (!(q2 > 4.0 * s.tcut)) return;
+  const double zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * s.tcut / q2));
+  const double zm = 1.0 - zp;
+  const double L = log((1.0 - zm) / (1.0 - zp));
+  s.ends += 1;
+  if (pid_i != kGluon) {
+    const double c = s.cfac * ((2.0 * kCF) * L);
+    const U4 d = s.key.draw(s.cycle, kPurposeTrial, trial_slot(i, k, 0));
+    const double lt_try = s.lt + log(unit(d.x, d.y)) / c;
+    s.trials += 1;
+    if (lt_try > best) {
+      best = lt_try;
+      w = Winner{q2, zm, zp, i, k, pid_i > 0 ? pid_i - 1 : 4 - pid_i};
+    }
+  } else {
+    const double cgg = s.cfac * (kCA * L);
+    const double cqq = s.cfac * ((0.5 * kTR) * (zp - zm));
+    const U4 d0 = s.key.draw(s.cycle, kPurposeTrial, trial_slot(i, k, 0));
+    const U4 d1 = s.key.draw(s.cycle, kPurposeTrial, trial_slot(i, k, 1));
+    const U4 d2 = s.key.draw(s.cycle, kPurposeTrial, trial_slot(i, k, 2));
+    s.trials += 6;
+    const double lgg = s.lt + log(unit(d0.x, d0.y)) / cgg;
+    double um = unit(d0.z, d0.w);
+    int fm = 1;
+    double u = unit(d1.x, d1.y);
+    if (u > um) { um = u; fm = 2; }
+    u = unit(d1.z, d1.w);
+    if (u > um) { um = u; fm = 3; }
+    u = unit(d2.x, d2.y);
+    if (u > um) { um = u; fm = 4; }
+    u = unit(d2.z, d2.w);
+    if (u > um) { um = u; fm = 5; }
+    const double lqq = s.lt + log(um) / cqq;
+    if (lgg > best) {
+      best = lgg;
+      w = Winner{q2, zm, zp, i, k, 10};
+    }
+    if (lqq > best) {
+      best = lqq;
+      w = Winner{q2, zm, zp, i, k, 10 + fm};
+    }
+  }
+}
+
+// One cycle of the veto algorithm for one event: SelectWinnerEmission over
+// every colour-connected (splitter, spectator) in lexicographic order,
+// CheckCutoff, alpha_s, AcceptOrVeto, GenerateEmission.
+__device__ __forceinline__ void veto_cycle(EvState& s, const Records& r, uint64_t e) {
+  double best = s.ltc;
+  Winner w{0.0, 0.0, 0.0, -1, 0, 0};
+  for (int i = 0; i < s.n; ++i) {
+    const uint64_t oi = (uint64_t)i * r.stride + e;
+    const int pid_i = r.pid[oi];
+    int k1 = r.cpart[oi], k2 = r.apart[oi];
+    if (k2 == k1) k2 = kNoPartner;  // closed two-parton loop: one dipole
+    if (k1 > k2) {
+      const int t = k1;
+      k1 = k2;
+      k2 = t;
+    }
+    const P4 pi = r.load(i, e);
+    if (k1 != kNoPartner) end_trials(s, i, k1, pid_i, pi, r.load(k1, e), best, w);
+    if (k2 != kNoPartner) end_trials(s, i, k2, pid_i, pi, r.load(k2, e), best, w);
+  }
+  const uint32_t this_cycle = s.cycle++;
+  if (w.i < 0) {  // no trial above the cutoff
+    s.status = kDone;
+    return;
+  }
+  s.lt = best;  // the winner's scale bounds every later trial
+  const double t = exp(best);
+  const U4 a = s.key.draw(this_cycle, kPurposeAccept, 0);
+  const double z = kernel_zgen(w.K, w.zm, w.zp, unit(a.x, a.y));
+  const double y = t / (w.q2 * z * (1.0 - z));
+  if (!(y < 1.0)) return;
+  const double prob = alpha_s(t) / s.asmax * kernel_value(w.K, z, y) * (1.0 - y) / kernel_over(w.K, z);
+  if (!(unit(a.z, a.w) < prob)) return;
+  if (s.n == (int)r.cap) {
+    s.status = kOverflow;
+    return;
+  }
+  // --- splitting: kinematics, colours, flavours, append parton j at slot n
+  const U4 sd = s.key.draw(this_cycle, kPurposeSplit, 0);
+  const double phi = 2.0 * kPi * unit(sd.x, sd.y);
+  double sphi, cphi;
+  sincos(phi, &sphi, &cphi);
+  const int i = w.i, k = w.k, j = s.n;
+  P4 ni, nj, nk;
+  split_kinematics(r.load(i, e), r.load(k, e), t, z, cphi, sphi, ni, nj, nk);
+  r.store(i, e, ni);
+  r.store(k, e, nk);
+  r.store(j, e, nj);
+  const uint64_t oi = (uint64_t)i * r.stride + e;
+  const uint64_t ok = (uint64_t)k * r.stride + e;
+  const uint64_t oj = (uint64_t)j * r.stride + e;
+  const bool via_colour = r.cpart[oi] == k;
+  if (w.K <= 10) {  // gluon emitted between i and k on their colour line
+    const uint16_t m = (uint16_t)s.next_col++;
+    r.pid[oj] = (int8_t)kGluon;
+    if (via_colour) {
+      r.col[oj] = r.col[oi];
+      r.acol[oj] = m;
+      r.col[oi] = m;
+      r.cpart[oj] = (uint16_t)k;
+      r.apart[ok] = (uint16_t)j;
+      r.apart[oj] = (uint16_t)i;
+      r.cpart[oi] = (uint16_t)j;
+    } else {
+      r.col[oj] = m;
+      r.acol[oj] = r.acol[oi];
+      r.acol[oi] = m;
+      r.apart[oj] = (uint16_t)k;
+      r.cpart[ok] = (uint16_t)j;
+      r.cpart[oj] = (uint16_t)i;
+      r.apart[oi] = (uint16_t)j;
+    }
+  } else {  // g -> f fbar: j is the parton colour-adjacent to k
+    const int f = w.K - 10;
+    if (via_colour) {
+      r.pid[oj] = (int8_t)f;
+      r.col[oj] = r.col[oi];
+      r.acol[oj] = 0;
+      r.pid[oi] = (int8_t)(-f);
+      r.col[oi] = 0;
+      r.cpart[oj] = (uint16_t)k;
+      r.apart[ok] = (uint16_t)j;
+      r.apart[oj] = kNoPartner;
+      r.cpart[oi] = kNoPartner;
+    } else {
+      r.pid[oj] = (int8_t)(-f);
+      r.col[oj] = 0;
+      r.acol[oj] = r.acol[oi];
+      r.pid[oi] = (int8_t)f;
+      r.acol[oi] = 0;
+      r.apart[oj] = (uint16_t)k;
+      r.cpart[ok] = (uint16_t)j;
+      r.cpart[oj] = kNoPartner;
+      r.apart[oi] = kNoPartner;
+    }
+  }
+  s.hash = fnv_step(fnv_step(fnv_step(s.hash, (uint32_t)w.K), (uint32_t)i), (uint32_t)k);
+  s.n += 1;
+  s.n_emit += 1;
+}
+
+// Fresh state for an event whose n initial partons sit in slot e of r.
+__device__ __forceinline__ void init_state(EvState& s, const Records& r, uint64_t e, const Keyed& key,
+                                           double ecm, double tcut, int n) {
+  s.key = key;
+  s.tcut = tcut;
+  s.ltc = log(tcut);
+  s.asmax = alpha_s(tcut);
+  s.cfac = s.asmax / (2.0 * kPi);
+  s.lt = log(ecm * ecm);  // evolution starts at s
+  s.hash = kFnvOffset;
+  s.cycle = 0;
+  s.trials = 0;
+  s.ends = 0;
+  s.n = n;
+  s.n_emit = 0;
+  s.status = kRunning;
+  int mc = 0;
+  for (int a = 0; a < n; ++a) {
+    const int c = r.col[(uint64_t)a * r.stride + e], ac = r.acol[(uint64_t)a * r.stride + e];
+    mc = c > mc ? c : mc;
+    mc = ac > mc ? ac : mc;
+  }
+  s.next_col = mc + 1;
+}
+
+__device__ __forceinline__ void write_state(const EvState& s, const Summary& sm, uint64_t e) {
+  sm.i[kSiN * sm.stride + e] = s.n;
+  sm.i[kSiStatus * sm.stride + e] = s.status;
+  sm.i[kSiCycles * sm.stride + e] = (int32_t)s.cycle;
+  sm.i[kSiEmit * sm.stride + e] = s.n_emit;
+  sm.i[kSiTrials * sm.stride + e] = (int32_t)s.trials;
+  sm.i[kSiEnds * sm.stride + e] = (int32_t)s.ends;
+  sm.hash[e] = s.hash;
+}
+
+}  // namespace vsh

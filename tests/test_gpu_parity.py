@@ -83,3 +83,102 @@ def test_lep_slice_of_1e6_sampled(ctx, oracle):
     sig = oracle.sigma_lo(91.2 ** 2)
     w = g["sum_d"][0]
     assert abs(w.mean() - sig) < 4 * w.std() / np.sqrt(n)
+
+
+# ---------------------------------------------------------------------------
+# persistent (batched) form
+# ---------------------------------------------------------------------------
+def test_persistent_lep_small(ctx, oracle):
+    g, o, rep = _run(ctx, oracle, 1000, 1, 91.2, 1.0, 64, persistent=True)
+    parity.assert_parity(rep)
+    assert rep["frac"] == 1.0
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 4097])
+def test_persistent_ragged(ctx, oracle, n):
+    g, o, rep = _run(ctx, oracle, n, 5, 91.2, 1.0, 64, first=11, persistent=True)
+    parity.assert_parity(rep)
+
+
+def test_persistent_mixed_and_stress(ctx, oracle):
+    from paper_2403_08692_amd.workloads import mixed_energies
+
+    e, t = mixed_energies(1, 3000)
+    g, o, rep = _run(ctx, oracle, 3000, 1, 91.2, 1.0, 128, ecm_arr=e, tcut_arr=t, persistent=True)
+    parity.assert_parity(rep)
+    g, o, rep = _run(ctx, oracle, 500, 4, 500.0, 0.25, 256, persistent=True)
+    parity.assert_parity(rep)
+
+
+def test_persistent_equals_plain(ctx):
+    from paper_2403_08692_amd.workloads import mixed_energies
+
+    n = 200_000
+    e, t = mixed_energies(7, n)
+    a = ctx.generate(n, seed=7, max_partons=128, summary=True, ecm_per_event=e, tcut_per_event=t)
+    b = ctx.generate(n, seed=7, max_partons=128, summary=True, ecm_per_event=e, tcut_per_event=t, persistent=True)
+    np.testing.assert_array_equal(a["sum_i"], b["sum_i"])
+    np.testing.assert_array_equal(a["hash"], b["hash"])
+    np.testing.assert_allclose(a["sum_d"], b["sum_d"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(a["hist"], b["hist"], rtol=1e-11, atol=1e-9)
+    print("plain shower ms", a["t_shower_ms"], "persistent", b["t_shower_ms"], flush=True)
+
+
+def test_persistent_graph_replays_match_eager(ctx):
+    """vsh_generate_into (persistent form, replayed hipGraph) on PyTorch
+    buffers, several replays with host work between them, each checked
+    against the eager vsh_generate result."""
+    import torch
+
+    import paper_2403_08692_amd as P
+    from paper_2403_08692_amd._native import make_request
+
+    n = 50_000
+    ref = ctx.generate(n, seed=3, ecm=200.0, t_cut=0.5, max_partons=128, summary=True, persistent=True)
+    req, keep = make_request(n, 3, 0, 200.0, 0.5, 128, P.VSH_FORM_PERSISTENT)
+    ws_bytes = ctx.workspace_size(req)
+    dev = torch.device("cuda:0")
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    hist = torch.zeros(P.HIST_DOUBLES, dtype=torch.float64, device=dev)
+    sd = torch.empty((P.NSUM_D, n), dtype=torch.float64, device=dev)
+    si = torch.empty((P.NSUM_I, n), dtype=torch.int32, device=dev)
+    hs = torch.empty(n, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    for rep in range(4):
+        hist.zero_()
+        si.fill_(-1)
+        ctx.generate_into(req, stream.cuda_stream, ws.data_ptr(), ws_bytes, hist.data_ptr(), sd.data_ptr(),
+                          si.data_ptr(), hs.data_ptr())
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(si.cpu().numpy(), ref["sum_i"])
+        np.testing.assert_array_equal(hs.cpu().numpy().view(np.uint64), ref["hash"])
+        np.testing.assert_allclose(sd.cpu().numpy(), ref["sum_d"], rtol=1e-13, atol=0)
+        np.testing.assert_allclose(hist.cpu().numpy().reshape(P.NOBS, P.NHCOL, 3), ref["hist"], rtol=1e-11,
+                                   atol=1e-9)
+        _ = ctx.generate(100, seed=rep, summary=False)  # unrelated eager work between replays
+
+
+def test_plain_generate_into_matches_generate(ctx):
+    import torch
+
+    import paper_2403_08692_amd as P
+    from paper_2403_08692_amd._native import make_request
+
+    n = 20_000
+    ref = ctx.generate(n, seed=2, summary=True)
+    req, keep = make_request(n, 2, 0, 91.2, 1.0, 64, P.VSH_FORM_PLAIN)
+    ws_bytes = ctx.workspace_size(req)
+    dev = torch.device("cuda:0")
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    hist = torch.zeros(P.HIST_DOUBLES, dtype=torch.float64, device=dev)
+    si = torch.empty((P.NSUM_I, n), dtype=torch.int32, device=dev)
+    ctx.timing_start()
+    for _ in range(2):
+        hist.zero_()
+        ctx.generate_into(req, torch.cuda.current_stream(dev).cuda_stream, ws.data_ptr(), ws_bytes,
+                          hist.data_ptr(), None, si.data_ptr(), None)
+    torch.cuda.synchronize()
+    t = ctx.timing_read()
+    assert t.shape == (2, 3) and (t > 0).all()
+    np.testing.assert_array_equal(si.cpu().numpy(), ref["sum_i"])
+    np.testing.assert_allclose(hist.cpu().numpy().reshape(P.NOBS, P.NHCOL, 3), ref["hist"], rtol=1e-11, atol=1e-9)
