@@ -198,6 +198,28 @@ uint64_t vsh_workspace_size(const vsh_request *req);
 vsh_status vsh_timing_start(vsh_ctx *ctx);
 vsh_status vsh_timing_read(vsh_ctx *ctx, float *ms, uint32_t max_calls, uint32_t *n_calls);
 
+/* Launch parameters of the two forms.  vsh_autotune picks them by timing
+   candidates on a sample request; vsh_set_tuning sets them directly (values
+   are clamped to the ranges below).  They change speed only: every event
+   is the same for any setting. */
+typedef struct {
+  uint32_t plain_block;      /* threads per block, plain form: 64, 128 or 256          */
+  uint32_t mapping;          /* persistent form: 0 = one lane per event,
+                                1 = each cycle's trials spread over the wave's lanes   */
+  uint32_t waves_per_cu;     /* resident persistent waves per compute unit, 1..16      */
+  uint32_t block;            /* threads per block of mapping 0: 64, 128 or 256          */
+  uint32_t refill_threshold; /* idle lanes a wave waits for before refilling, 1..64     */
+  uint32_t refill_period;    /* veto cycles between refill checks, 1..64               */
+} vsh_tuning;
+vsh_status vsh_get_tuning(vsh_ctx *ctx, vsh_tuning *out);
+vsh_status vsh_set_tuning(vsh_ctx *ctx, const vsh_tuning *t);
+/* Time the candidate settings of the persistent form (or, with
+   VSH_FORM_PLAIN in sample->flags, the plain block size) on `sample`
+   (its first min(n_events, 2^18) events) and keep the fastest in ctx;
+   *chosen (optional) receives it.  Candidates whose summaries differ from
+   the first candidate's are rejected (VSH_E_INTERNAL). */
+vsh_status vsh_autotune(vsh_ctx *ctx, const vsh_request *sample, vsh_tuning *chosen);
+
 /* Serving (continuous batching).  vsh_submit copies the request (and its
    per-event arrays) and returns at once with a ticket; the context's serving
    loop admits requests by event-record memory, runs their events together in

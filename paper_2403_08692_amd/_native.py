@@ -40,6 +40,14 @@ class vsh_request(C.Structure):
                 ("max_partons", C.c_uint32), ("flags", C.c_uint32)]
 
 
+class vsh_tuning(C.Structure):
+    _fields_ = [("plain_block", C.c_uint32), ("mapping", C.c_uint32), ("waves_per_cu", C.c_uint32),
+                ("block", C.c_uint32), ("refill_threshold", C.c_uint32), ("refill_period", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class vsh_result(C.Structure):
     _fields_ = [("n_events", C.c_uint64), ("n_done", C.c_uint64), ("n_overflow", C.c_uint64),
                 ("n_nonfinite", C.c_uint64), ("n_conservation", C.c_uint64),
@@ -106,13 +114,20 @@ def load():
     L.vsh_timing_start.restype = C.c_int
     L.vsh_timing_read.argtypes = [P, C.POINTER(C.c_float), C.c_uint32, C.POINTER(C.c_uint32)]
     L.vsh_timing_read.restype = C.c_int
+    L.vsh_get_tuning.argtypes = [P, C.POINTER(vsh_tuning)]
+    L.vsh_get_tuning.restype = C.c_int
+    L.vsh_set_tuning.argtypes = [P, C.POINTER(vsh_tuning)]
+    L.vsh_set_tuning.restype = C.c_int
+    L.vsh_autotune.argtypes = [P, C.POINTER(vsh_request), C.POINTER(vsh_tuning)]
+    L.vsh_autotune.restype = C.c_int
     _lib = L
     return L
 
 
 EXPORTS = ["vsh_create", "vsh_destroy", "vsh_last_error", "vsh_generate", "vsh_result_free",
            "vsh_shower_records", "vsh_generate_into", "vsh_workspace_size", "vsh_submit", "vsh_poll",
-           "vsh_wait", "vsh_cancel", "vsh_timing_start", "vsh_timing_read"]
+           "vsh_wait", "vsh_cancel", "vsh_timing_start", "vsh_timing_read", "vsh_get_tuning", "vsh_set_tuning",
+           "vsh_autotune"]
 
 
 class VshError(RuntimeError):
@@ -251,6 +266,27 @@ class Context:
         """All buffer arguments are integer device addresses; stream a hipStream_t address."""
         _check(load().vsh_generate_into(self._ptr, C.byref(req), stream, workspace, int(workspace_bytes),
                                         dev_hist, dev_sum_d, dev_sum_i, dev_hash), self._ptr)
+
+    def get_tuning(self):
+        t = vsh_tuning()
+        _check(load().vsh_get_tuning(self._ptr, C.byref(t)), self._ptr)
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = vsh_tuning()
+        _check(load().vsh_get_tuning(self._ptr, C.byref(t)), self._ptr)
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(load().vsh_set_tuning(self._ptr, C.byref(t)), self._ptr)
+        return self.get_tuning()
+
+    def autotune(self, n_events=1 << 18, seed=1, ecm=91.2, t_cut=1.0, max_partons=64, persistent=True,
+                 ecm_per_event=None, tcut_per_event=None):
+        flags = VSH_FORM_PERSISTENT if persistent else VSH_FORM_PLAIN
+        req, keep = make_request(n_events, seed, 0, ecm, t_cut, max_partons, flags, ecm_per_event, tcut_per_event)
+        t = vsh_tuning()
+        _check(load().vsh_autotune(self._ptr, C.byref(req), C.byref(t)), self._ptr)
+        return t.as_dict()
 
     def timing_start(self):
         _check(load().vsh_timing_start(self._ptr), self._ptr)

@@ -45,6 +45,7 @@ struct Tuned {
   uint32_t pers_waves_per_cu = 8;
   uint32_t refill_period = 1;     // veto cycles between compaction / refill passes
   uint32_t refill_threshold = 1;  // idle lanes needed before a wave refills
+  uint32_t mapping = 1;           // persistent mapping: 0 lane per event, 1 flattened trials
 };
 
 struct ServeState;
@@ -61,6 +62,7 @@ struct vsh_ctx {
   vsh::BatchGraph graph;
   vsh::Arena arena, arena2;
   vsh::Tuned tuned;
+  float tuned_ms = 0.0f;  // shower-kernel time of the autotuner's choice on its sample
   std::mutex mu;
   std::string error;
   vsh::ServeState* serve = nullptr;  // owned; torn down by serve_shutdown
@@ -94,8 +96,16 @@ PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap);
 vsh_status gather_records(vsh_ctx* ctx, const Records& r, const int32_t* n_dev, const int32_t* n_host,
                           uint64_t count, ResultBox* box);
 
+vsh_status generate_plain(vsh_ctx* ctx, const vsh_request* req, const uint64_t* offsets, const double* p,
+                          const int8_t* pid, const uint16_t* col, const uint16_t* acol, vsh_result** out);
+
 // persistent form (vsh_persistent.hip)
 uint32_t persistent_lanes(const vsh_ctx* ctx);
+uint64_t batch_bytes(uint64_t lanes, uint64_t n, uint32_t cap);
+BatchLayout carve_batch(void* base, uint64_t lanes, uint64_t n, uint32_t cap);
+vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, uint64_t n, hipStream_t st,
+                     void* base, const double* ecm_dev, const double* tcut_dev, double* hist, bool use_graph,
+                     BatchLayout* out_layout);
 vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result** out);
 uint64_t persistent_workspace_bytes(const vsh_request* req);
 hipEvent_t* timing_slot(vsh_ctx* ctx);

@@ -109,6 +109,184 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Flattened mapping.  Same refill as above, but each veto cycle's trials of a
+// wave's 64 events are spread over its 64 lanes: the work items are the
+// partons of all busy events (event-major, parton order), taken 64 per
+// round; item (owner o, parton i) runs that parton's dipole ends.  Within a
+// round a segmented max over consecutive lanes of the same owner (earlier
+// lane wins ties, i.e. the lexicographically first trial as in the paper's
+// loop nest) leaves each owner's round best on its last lane, which folds it
+// into the owner's running best in LDS (earlier rounds win ties).  Each owner
+// then finishes its cycle in its own lane.
+// ---------------------------------------------------------------------------
+struct FlatShared {
+  double lt[64], tcut[64], ltc[64], cfac[64];
+  uint32_t key[4][64];
+  uint32_t cycle[64];
+  uint32_t start[65];
+  double best_v[64];
+  uint32_t best_idx[64];
+  uint32_t trials[64], ends[64];
+};
+
+__device__ __forceinline__ uint32_t owner_of(const uint32_t* start, uint32_t j) {
+  uint32_t lo = 0, hi = 64;  // last o with start[o] <= j (owners with no items have start[o] == start[o+1])
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (start[mid] <= j) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
+  __shared__ FlatShared sh;
+  const uint32_t lane = threadIdx.x;
+  const uint64_t wave_base = (uint64_t)blockIdx.x * 64;
+  const uint64_t L = wave_base + lane;
+  EvState s;
+  s.status = kDone;
+  bool busy = false;
+  bool drained = false;
+  uint32_t req = 0;
+  uint64_t ev = 0;
+  uint32_t since = 0;
+  while (true) {
+    const uint64_t idle = __ballot(!busy);
+    const uint32_t n_idle = __popcll(idle);
+    if (!drained && n_idle > 0 && (n_idle == 64 || (since >= A.period && n_idle >= A.threshold))) {
+      since = 0;
+      const uint32_t leader = __ffsll((unsigned long long)idle) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(A.next, (unsigned long long)n_idle);
+      base = __shfl(base, leader);
+      if (base + n_idle >= A.total) drained = true;
+      if (!busy) {
+        const uint64_t w = base + __popcll(idle & ((1ull << lane) - 1));
+        if (w < A.total) {
+          const uint32_t sg = find_segment(A.segs, A.n_segs, w);
+          req = A.segs[sg].req;
+          ev = A.segs[sg].lo + (w - A.segs[sg].start);
+          const ReqDev& R = A.reqs[req];
+          const double ecm = R.ecm ? R.ecm[ev] : R.ecm0;
+          const double tcut = R.tcut ? R.tcut[ev] : R.tcut0;
+          const Keyed key = make_keyed(R.seed, R.first + ev);
+          const MEOut m = me_event(A.slots, L, key, ecm);
+          const Summary& sm = R.sum;
+          sm.d[kSdW * sm.stride + ev] = m.w;
+          sm.d[kSdCos * sm.stride + ev] = m.c;
+          sm.d[kSdPhi * sm.stride + ev] = m.phi;
+          sm.i[kSiFlavour * sm.stride + ev] = m.f;
+          init_state(s, A.slots, L, key, ecm, tcut, 2);
+          busy = true;
+        }
+      }
+    }
+    if (!__any(busy)) break;
+    // --- publish the busy events and the item ranges
+    const uint32_t mine = busy ? (uint32_t)s.n : 0u;
+    uint32_t incl = mine;
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+      const uint32_t t = __shfl_up(incl, d);
+      if (lane >= d) incl += t;
+    }
+    const uint32_t total = __shfl(incl, 63);
+    sh.start[lane] = incl - mine;
+    if (lane == 63) sh.start[64] = total;
+    sh.lt[lane] = s.lt;
+    sh.tcut[lane] = s.tcut;
+    sh.ltc[lane] = s.ltc;
+    sh.cfac[lane] = s.cfac;
+    sh.key[0][lane] = s.key.ev_lo;
+    sh.key[1][lane] = s.key.ev_hi;
+    sh.key[2][lane] = s.key.k0;
+    sh.key[3][lane] = s.key.k1;
+    sh.cycle[lane] = s.cycle;
+    sh.best_v[lane] = -INFINITY;
+    sh.best_idx[lane] = kNoTrial;
+    sh.trials[lane] = 0;
+    sh.ends[lane] = 0;
+    __syncthreads();
+    // --- trials, 64 items per round
+    for (uint32_t r0 = 0; r0 < total; r0 += 64) {
+      const uint32_t j = r0 + lane;
+      const bool active = j < total;
+      double v = -INFINITY;
+      uint32_t idx = kNoTrial;
+      uint32_t o = 63, seg0 = 64, last = 0;
+      if (active) {
+        o = owner_of(sh.start, j);
+        const uint32_t i = j - sh.start[o];
+        seg0 = (sh.start[o] > r0 ? sh.start[o] : r0) - r0;
+        last = (j + 1 == sh.start[o + 1]) || lane == 63;
+        const TrialCtx c{Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]}, sh.lt[o], sh.tcut[o],
+                         sh.ltc[o], sh.cfac[o], sh.cycle[o]};
+        double best = c.ltc;
+        Winner w{0.0, 0.0, 0.0, -1, 0, 0};
+        uint32_t nt = 0, ne = 0;
+        parton_trials(c, A.slots, wave_base + o, (int)i, best, w, nt, ne);
+        if (w.i >= 0) {
+          v = best;
+          idx = pack_trial(w.i, w.k, w.K);
+        }
+        atomicAdd(&sh.trials[o], nt);
+        atomicAdd(&sh.ends[o], ne);
+      }
+      for (uint32_t d = 1; d < 64; d <<= 1) {
+        const double vn = __shfl_up(v, d);
+        const uint32_t in = __shfl_up(idx, d);
+        if (active && lane >= d && lane - d >= seg0 && in != kNoTrial && (vn >= v || idx == kNoTrial)) {
+          v = vn;
+          idx = in;
+        }
+      }
+      if (active && last && idx != kNoTrial && (idx < kNoTrial) &&
+          (sh.best_idx[o] == kNoTrial || v > sh.best_v[o])) {
+        sh.best_v[o] = v;
+        sh.best_idx[o] = idx;
+      }
+      __syncthreads();
+    }
+    // --- each owner finishes its cycle
+    if (busy) {
+      s.trials += sh.trials[lane];
+      s.ends += sh.ends[lane];
+      const uint32_t bi = sh.best_idx[lane];
+      Winner w{0.0, 0.0, 0.0, -1, 0, 0};
+      double best = s.ltc;
+      if (bi != kNoTrial) {
+        w.i = (int)(bi >> 14);
+        w.k = (int)((bi >> 4) & 1023u);
+        w.K = (int)(bi & 15u);
+        best = sh.best_v[lane];
+        end_limits(A.slots.load(w.i, L), A.slots.load(w.k, L), s.tcut, w.q2, w.zm, w.zp);
+      }
+      veto_finish(s, A.slots, L, best, w);
+      if (s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
+      if (s.status != kRunning) {
+        const ReqDev& R = A.reqs[req];
+        const Records& o = R.out;
+        for (int a = 0; a < s.n; ++a) {
+          const uint64_t from = (uint64_t)a * A.slots.stride + L;
+          const uint64_t to = (uint64_t)a * o.stride + ev;
+          o.E[to] = A.slots.E[from];
+          o.x[to] = A.slots.x[from];
+          o.y[to] = A.slots.y[from];
+          o.z[to] = A.slots.z[from];
+          o.pid[to] = A.slots.pid[from];
+          o.col[to] = A.slots.col[from];
+          o.acol[to] = A.slots.acol[from];
+        }
+        write_state(s, R.sum, ev);
+        busy = false;
+      }
+    }
+    __syncthreads();
+    ++since;
+  }
+}
+
 // Writes a batch's request and segment descriptors (passed by value, so the
 // launch carries them) and zeroes the work counter.
 __global__ void k_setup(ReqDev* rd, ReqDev d, Segment* sd, Segment s, unsigned long long* counter) {
@@ -222,8 +400,18 @@ BatchLayout carve_batch(void* base, uint64_t lanes, uint64_t n, uint32_t cap) {
   return L;
 }
 
-void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, hipStream_t st) {
-  hipLaunchKernelGGL(k_shower_persistent, dim3((uint32_t)(lanes / block)), dim3(block), 0, st, A);
+const void* persistent_kernel(uint32_t mapping) {
+  return mapping == kMapFlat ? (const void*)k_shower_flat : (const void*)k_shower_persistent;
+}
+
+uint32_t persistent_block(uint32_t mapping, uint32_t block) { return mapping == kMapFlat ? 64u : block; }
+
+void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uint32_t mapping, hipStream_t st) {
+  block = persistent_block(mapping, block);
+  if (mapping == kMapFlat)
+    hipLaunchKernelGGL(k_shower_flat, dim3((uint32_t)(lanes / block)), dim3(block), 0, st, A);
+  else
+    hipLaunchKernelGGL(k_shower_persistent, dim3((uint32_t)(lanes / block)), dim3(block), 0, st, A);
 }
 
 void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, unsigned long long* counter,
@@ -289,7 +477,7 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   GCHK(add_kernel((const void*)k_setup, dim3(1), dim3(64), a_setup));
   GCHK(add_event(1));
   void* a_pers[] = {&g.args};
-  GCHK(add_kernel((const void*)k_shower_persistent, dim3((uint32_t)(lanes / block)), dim3(block), a_pers));
+  GCHK(add_kernel(persistent_kernel(g.mapping), dim3((uint32_t)(lanes / block)), dim3(block), a_pers));
   GCHK(add_event(2));
   void* a_obs[] = {&g.rec, &g.sum, &g.in, &g.sc, &g.n, &g.hist};
   GCHK(add_kernel((const void*)k_obs, dim3((uint32_t)(obs_threads(n) / 256)), dim3(256), a_obs));
@@ -322,12 +510,13 @@ static void fill_request_desc(ReqDev& d, const ReqBuffers& b, const vsh_request*
 // through the persistent form on stream st, with the batch's buffers in the
 // workspace at `base`.  Inputs: per-event arrays already on the device (or
 // null).  Writes the histogram into hist (accumulates).
-static vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, uint64_t n,
+vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, uint64_t n,
                             hipStream_t st, void* base, const double* ecm_dev, const double* tcut_dev,
                             double* hist, bool use_graph, BatchLayout* out_layout) {
   const uint32_t cap = req->max_partons;
   const uint64_t lanes = persistent_lanes(ctx);
-  const uint32_t block = ctx->tuned.pers_block;
+  const uint32_t mapping = ctx->tuned.mapping;
+  const uint32_t block = persistent_block(mapping, ctx->tuned.pers_block);
   BatchLayout L = carve_batch(base, lanes, n, cap);
   if (out_layout) *out_layout = L;
   ReqDev d;
@@ -355,9 +544,11 @@ static vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first
     BatchGraph& g = ctx->graph;
     const bool same = g.exec && std::memcmp(&g.args, &A, sizeof A) == 0 && g.hist == hist && g.n == n &&
                       std::memcmp(&g.in, &in, sizeof in) == 0 && std::memcmp(&g.d, &d, sizeof d) == 0 &&
-                      std::memcmp(&g.s, &sg, sizeof sg) == 0 && g.lanes == lanes && g.block == block;
+                      std::memcmp(&g.s, &sg, sizeof sg) == 0 && g.lanes == lanes && g.block == block &&
+                      g.mapping == mapping;
     if (!same) {
       destroy_graph(g);
+      g.mapping = mapping;
       vsh_status rc = build_batch_graph(ctx, g, A, d, sg, lanes, block, L, in, n, hist);
       if (rc) {
         destroy_graph(g);
@@ -376,7 +567,7 @@ static vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first
     if (tev) (void)hipEventRecord(tev[0], st);
     launch_setup(L.reqs, d, L.segs, sg, L.counter, st);
     if (tev) (void)hipEventRecord(tev[1], st);
-    launch_persistent(A, lanes, block, st);
+    launch_persistent(A, lanes, block, mapping, st);
     if (tev) (void)hipEventRecord(tev[2], st);
     launch_obs(L.buf.out, L.buf.sum, in, L.sc, (uint32_t)n, hist, st);
     if (tev) (void)hipEventRecord(tev[3], st);
@@ -480,7 +671,7 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     A.threshold = ctx->tuned.refill_threshold;
     A.period = ctx->tuned.refill_period;
     (void)hipEventRecord(ctx->ev[1], st);
-    launch_persistent(A, lanes, ctx->tuned.pers_block, st);
+    launch_persistent(A, lanes, ctx->tuned.pers_block, ctx->tuned.mapping, st);
     (void)hipEventRecord(ctx->ev[2], st);
     EventInputs in{};
     in.ecm = ecm_dev;

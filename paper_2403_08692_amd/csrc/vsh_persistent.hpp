@@ -81,6 +81,7 @@ struct BatchGraph {
   double* hist = nullptr;
   uint64_t lanes = 0;
   uint32_t block = 0;
+  uint32_t mapping = 0;
 };
 
 uint64_t slots_bytes(uint64_t lanes, uint32_t cap);
@@ -89,7 +90,8 @@ uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap);
 Records carve_slots(Carver& c, uint64_t lanes, uint32_t cap);
 ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap);
 Scratch carve_scratch(Carver& c, uint64_t n, uint32_t cap);
-void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, hipStream_t st);
+enum : uint32_t { kMapLane = 0, kMapFlat = 1 };
+void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uint32_t mapping, hipStream_t st);
 void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, unsigned long long* counter,
                   hipStream_t st);
 void launch_zero(double* p, uint32_t n, hipStream_t st);

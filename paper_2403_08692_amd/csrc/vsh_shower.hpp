@@ -49,47 +49,74 @@ __device__ __forceinline__ MEOut me_event(const Records& r, uint64_t e, const Ke
 // ---------------------------------------------------------------------------
 struct EvState {
   Keyed key;
-  double lt;     // ln t, the current upper scale
+  double lt;  // ln t, the current upper scale
   double tcut, ltc, asmax, cfac;
   uint64_t hash;
   uint32_t cycle, trials, ends;
   int n, next_col, n_emit, status;
 };
 
+// what a trial needs to know about its event
+struct TrialCtx {
+  Keyed key;
+  double lt, tcut, ltc, cfac;
+  uint32_t cycle;
+};
+
+__device__ __forceinline__ TrialCtx trial_ctx(const EvState& s) {
+  return TrialCtx{s.key, s.lt, s.tcut, s.ltc, s.cfac, s.cycle};
+}
+
 struct Winner {
   double q2, zm, zp;
   int i, k, K;
 };
 
+// (splitter, spectator, kernel) in one word whose numeric order is the
+// lexicographic order of the paper's loop nest
+__device__ __forceinline__ uint32_t pack_trial(int i, int k, int K) {
+  return ((uint32_t)i << 14) | ((uint32_t)k << 4) | (uint32_t)K;
+}
+constexpr uint32_t kNoTrial = 0xFFFFFFFFu;
+
+// Dipole mass and the z range of the overestimate for the end (i, k).
+__device__ __forceinline__ bool end_limits(const P4& pi, const P4& pk, double tcut, double& q2, double& zm,
+                                           double& zp) {
+  q2 = 2.0 * mdot(pi, pk);
+  if (!(q2 > 4.0 * tcut)) return false;  // no phase space above the cutoff
+  zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * tcut / q2));
+  zm = 1.0 - zp;
+  return true;
+}
+
 // All trials of the dipole end (i, k): one per kernel of the splitter,
 // t_try = t R^(1/c) compared as ln t + ln(R)/c (App. A, trial-scale
 // equation); strict maximum above the running best.  A gluon end's five
 // g -> f fbar kernels share c, so only their largest uniform needs a log.
-__device__ __forceinline__ void end_trials(EvState& s, int i, int k, int pid_i, const P4& pi,
-                                           const P4& pk, double& best, Winner& w) {
-  const double q2 = 2.0 * mdot(pi, pk);
-  if (!(q2 > 4.0 * s.tcut)) return;
-  const double zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * s.tcut / q2));
-  const double zm = 1.0 - zp;
+__device__ __forceinline__ void end_trials(const TrialCtx& c, int i, int k, int pid_i, const P4& pi,
+                                           const P4& pk, double& best, Winner& w, uint32_t& trials,
+                                           uint32_t& ends) {
+  double q2, zm, zp;
+  if (!end_limits(pi, pk, c.tcut, q2, zm, zp)) return;
   const double L = log((1.0 - zm) / (1.0 - zp));
-  s.ends += 1;
+  ends += 1;
   if (pid_i != kGluon) {
-    const double c = s.cfac * ((2.0 * kCF) * L);
-    const U4 d = s.key.draw(s.cycle, kPurposeTrial, trial_slot(i, k, 0));
-    const double lt_try = s.lt + log(unit(d.x, d.y)) / c;
-    s.trials += 1;
+    const double cq = c.cfac * ((2.0 * kCF) * L);
+    const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
+    const double lt_try = c.lt + log(unit(d.x, d.y)) / cq;
+    trials += 1;
     if (lt_try > best) {
       best = lt_try;
       w = Winner{q2, zm, zp, i, k, pid_i > 0 ? pid_i - 1 : 4 - pid_i};
     }
   } else {
-    const double cgg = s.cfac * (kCA * L);
-    const double cqq = s.cfac * ((0.5 * kTR) * (zp - zm));
-    const U4 d0 = s.key.draw(s.cycle, kPurposeTrial, trial_slot(i, k, 0));
-    const U4 d1 = s.key.draw(s.cycle, kPurposeTrial, trial_slot(i, k, 1));
-    const U4 d2 = s.key.draw(s.cycle, kPurposeTrial, trial_slot(i, k, 2));
-    s.trials += 6;
-    const double lgg = s.lt + log(unit(d0.x, d0.y)) / cgg;
+    const double cgg = c.cfac * (kCA * L);
+    const double cqq = c.cfac * ((0.5 * kTR) * (zp - zm));
+    const U4 d0 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
+    const U4 d1 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 1));
+    const U4 d2 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 2));
+    trials += 6;
+    const double lgg = c.lt + log(unit(d0.x, d0.y)) / cgg;
     double um = unit(d0.z, d0.w);
     int fm = 1;
     double u = unit(d1.x, d1.y);
@@ -100,7 +127,7 @@ __device__ __forceinline__ void end_trials(EvState& s, int i, int k, int pid_i, 
     if (u > um) { um = u; fm = 4; }
     u = unit(d2.z, d2.w);
     if (u > um) { um = u; fm = 5; }
-    const double lqq = s.lt + log(um) / cqq;
+    const double lqq = c.lt + log(um) / cqq;
     if (lgg > best) {
       best = lgg;
       w = Winner{q2, zm, zp, i, k, 10};
@@ -112,26 +139,28 @@ __device__ __forceinline__ void end_trials(EvState& s, int i, int k, int pid_i, 
   }
 }
 
-// One cycle of the veto algorithm for one event: SelectWinnerEmission over
-// every colour-connected (splitter, spectator) in lexicographic order,
-// CheckCutoff, alpha_s, AcceptOrVeto, GenerateEmission.
-__device__ __forceinline__ void veto_cycle(EvState& s, const Records& r, uint64_t e) {
-  double best = s.ltc;
-  Winner w{0.0, 0.0, 0.0, -1, 0, 0};
-  for (int i = 0; i < s.n; ++i) {
-    const uint64_t oi = (uint64_t)i * r.stride + e;
-    const int pid_i = r.pid[oi];
-    int k1 = r.cpart[oi], k2 = r.apart[oi];
-    if (k2 == k1) k2 = kNoPartner;  // closed two-parton loop: one dipole
-    if (k1 > k2) {
-      const int t = k1;
-      k1 = k2;
-      k2 = t;
-    }
-    const P4 pi = r.load(i, e);
-    if (k1 != kNoPartner) end_trials(s, i, k1, pid_i, pi, r.load(k1, e), best, w);
-    if (k2 != kNoPartner) end_trials(s, i, k2, pid_i, pi, r.load(k2, e), best, w);
+// Trials of parton i of the event in slot e: its dipole ends in ascending
+// spectator order (a closed two-parton colour loop is one dipole).
+__device__ __forceinline__ void parton_trials(const TrialCtx& c, const Records& r, uint64_t e, int i,
+                                              double& best, Winner& w, uint32_t& trials, uint32_t& ends) {
+  const uint64_t oi = (uint64_t)i * r.stride + e;
+  const int pid_i = r.pid[oi];
+  int k1 = r.cpart[oi], k2 = r.apart[oi];
+  if (k2 == k1) k2 = kNoPartner;
+  if (k1 > k2) {
+    const int t = k1;
+    k1 = k2;
+    k2 = t;
   }
+  const P4 pi = r.load(i, e);
+  if (k1 != kNoPartner) end_trials(c, i, k1, pid_i, pi, r.load(k1, e), best, w, trials, ends);
+  if (k2 != kNoPartner) end_trials(c, i, k2, pid_i, pi, r.load(k2, e), best, w, trials, ends);
+}
+
+// The rest of one cycle once the winner is known: CheckCutoff, alpha_s,
+// AcceptOrVeto, GenerateEmission (App. C).  `best` is the winner's ln t.
+__device__ __forceinline__ void veto_finish(EvState& s, const Records& r, uint64_t e, double best,
+                                            const Winner& w) {
   const uint32_t this_cycle = s.cycle++;
   if (w.i < 0) {  // no trial above the cutoff
     s.status = kDone;
@@ -211,6 +240,17 @@ __device__ __forceinline__ void veto_cycle(EvState& s, const Records& r, uint64_
   s.hash = fnv_step(fnv_step(fnv_step(s.hash, (uint32_t)w.K), (uint32_t)i), (uint32_t)k);
   s.n += 1;
   s.n_emit += 1;
+}
+
+// One cycle of the veto algorithm for one event, all in this lane:
+// SelectWinnerEmission over every colour-connected (splitter, spectator) in
+// lexicographic order, then the veto and the splitting.
+__device__ __forceinline__ void veto_cycle(EvState& s, const Records& r, uint64_t e) {
+  double best = s.ltc;
+  Winner w{0.0, 0.0, 0.0, -1, 0, 0};
+  const TrialCtx c = trial_ctx(s);
+  for (int i = 0; i < s.n; ++i) parton_trials(c, r, e, i, best, w, s.trials, s.ends);
+  veto_finish(s, r, e, best, w);
 }
 
 // Fresh state for an event whose n initial partons sit in slot e of r.

@@ -1,0 +1,223 @@
+// vsh_tune.hip -- launch-parameter tuning of the two forms.
+//
+// The autotuner times candidate settings on a sample of the caller's
+// workload with HIP events around the shower kernel, checks that every
+// candidate produces the same per-event summaries as the first (the events
+// do not depend on the launch shape), and keeps the fastest.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "vsh_internal.hpp"
+
+namespace vsh {
+
+static uint32_t clampu(uint32_t v, uint32_t lo, uint32_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+static uint32_t block_choice(uint32_t b) { return b <= 64 ? 64 : (b <= 128 ? 128 : 256); }
+
+static vsh_tuning to_pub(const Tuned& t) {
+  vsh_tuning p;
+  p.plain_block = t.plain_block;
+  p.mapping = t.mapping;
+  p.waves_per_cu = t.pers_waves_per_cu;
+  p.block = t.pers_block;
+  p.refill_threshold = t.refill_threshold;
+  p.refill_period = t.refill_period;
+  return p;
+}
+
+static Tuned from_pub(const vsh_tuning& p) {
+  Tuned t;
+  t.plain_block = block_choice(p.plain_block);
+  t.mapping = p.mapping ? kMapFlat : kMapLane;
+  t.pers_waves_per_cu = clampu(p.waves_per_cu, 1, 16);
+  t.pers_block = block_choice(p.block);
+  t.refill_threshold = clampu(p.refill_threshold, 1, 64);
+  t.refill_period = clampu(p.refill_period, 1, 64);
+  return t;
+}
+
+// Time the persistent kernel of one batch (sample events [0, m)) under the
+// settings in ctx->tuned; return its milliseconds and the summaries.
+static vsh_status time_persistent(vsh_ctx* ctx, const vsh_request* req, uint64_t m, const double* ecm_dev,
+                                  const double* tcut_dev, void* base, double* hist, float* ms,
+                                  std::vector<int32_t>* si, std::vector<uint64_t>* hs) {
+  const bool was = ctx->timing;
+  const uint32_t was_calls = ctx->timing_calls;
+  ctx->timing = true;
+  ctx->timing_calls = 0;
+  BatchLayout L;
+  vsh_status rc = run_batch(ctx, req, 0, m, ctx->stream, base, ecm_dev, tcut_dev, hist, false, &L);
+  hipError_t err = hipSuccess;
+  if (!rc) err = hipStreamSynchronize(ctx->stream);
+  if (!rc && err == hipSuccess) err = hipEventElapsedTime(ms, ctx->timing_ev[1], ctx->timing_ev[2]);
+  ctx->timing = was;
+  ctx->timing_calls = was_calls;
+  if (rc) return rc;
+  if (err != hipSuccess) return hip_fail(ctx, err, "autotune timing");
+  if (si) {
+    si->resize((size_t)kNSumI * m);
+    hs->resize(m);
+    err = hipMemcpy(si->data(), L.buf.sum.i, si->size() * 4, hipMemcpyDeviceToHost);
+    if (err == hipSuccess) err = hipMemcpy(hs->data(), L.buf.sum.hash, m * 8, hipMemcpyDeviceToHost);
+    if (err != hipSuccess) return hip_fail(ctx, err, "autotune copy");
+  }
+  return VSH_OK;
+}
+
+static vsh_status autotune_persistent(vsh_ctx* ctx, const vsh_request* req) {
+  const uint64_t m = std::min<uint64_t>(req->n_events, 1ull << 18);
+  const uint32_t cap = req->max_partons;
+  const Tuned keep = ctx->tuned;
+  Tuned big = keep;
+  big.pers_waves_per_cu = 16;
+  ctx->tuned = big;
+  const uint64_t need = batch_bytes(persistent_lanes(ctx), m, cap);
+  ctx->tuned = keep;
+  vsh_status rc = ctx->arena.reserve(ctx, need);
+  if (rc) return rc;
+  void* base = ctx->arena.ptr;
+  BatchLayout L = carve_batch(base, (uint64_t)16 * ctx->n_cu * 64, m, cap);
+  hipError_t err;
+  const double* ecm_dev = nullptr;
+  const double* tcut_dev = nullptr;
+  // the per-event inputs live outside the batch layout of any candidate
+  rc = ctx->arena2.reserve(ctx, 2 * m * 8 + 2 * kHistDoubles * 8 + 512);
+  if (rc) return rc;
+  double* in_buf = (double*)ctx->arena2.ptr;
+  double* hist = in_buf + 2 * m;
+  (void)L;
+  if (req->ecm_per_event) {
+    err = hipMemcpy(in_buf, req->ecm_per_event, m * 8, hipMemcpyHostToDevice);
+    if (err != hipSuccess) return hip_fail(ctx, err, "autotune input");
+    ecm_dev = in_buf;
+  }
+  if (req->tcut_per_event) {
+    err = hipMemcpy(in_buf + m, req->tcut_per_event, m * 8, hipMemcpyHostToDevice);
+    if (err != hipSuccess) return hip_fail(ctx, err, "autotune input");
+    tcut_dev = in_buf + m;
+  }
+  std::vector<Tuned> cands;
+  for (uint32_t mapping : {kMapFlat, kMapLane})
+    for (uint32_t waves : {4u, 8u, 16u})
+      for (uint32_t thr : {1u, 16u})
+        for (uint32_t per : {1u, 4u}) {
+          Tuned t = keep;
+          t.mapping = mapping;
+          t.pers_waves_per_cu = waves;
+          t.pers_block = 256;
+          t.refill_threshold = thr;
+          t.refill_period = per;
+          cands.push_back(t);
+        }
+  std::vector<int32_t> ref_si, si;
+  std::vector<uint64_t> ref_hs, hs;
+  float best_ms = 1e30f;
+  Tuned best = keep;
+  for (size_t c = 0; c < cands.size(); ++c) {
+    ctx->tuned = cands[c];
+    float ms1 = 0, ms2 = 0;
+    rc = time_persistent(ctx, req, m, ecm_dev, tcut_dev, base, hist, &ms1, c == 0 ? &ref_si : &si,
+                         c == 0 ? &ref_hs : &hs);
+    if (!rc) rc = time_persistent(ctx, req, m, ecm_dev, tcut_dev, base, hist, &ms2, nullptr, nullptr);
+    if (rc) {
+      ctx->tuned = keep;
+      return rc;
+    }
+    if (c > 0 && (si != ref_si || hs != ref_hs)) {
+      ctx->tuned = keep;
+      set_error(ctx, "autotune: candidate %zu changed the events (internal error)", c);
+      return VSH_E_INTERNAL;
+    }
+    const float ms = std::min(ms1, ms2);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cands[c];
+    }
+  }
+  ctx->tuned = best;
+  ctx->tuned_ms = best_ms;
+  destroy_graph(ctx->graph);
+  return VSH_OK;
+}
+
+static vsh_status autotune_plain(vsh_ctx* ctx, const vsh_request* req) {
+  vsh_request r = *req;
+  r.n_events = std::min<uint64_t>(req->n_events, 1ull << 18);
+  r.flags = VSH_SUMMARY;
+  const Tuned keep = ctx->tuned;
+  float best_ms = 1e30f;
+  uint32_t best = keep.plain_block;
+  std::vector<int32_t> ref;
+  for (uint32_t b : {256u, 128u, 64u}) {
+    ctx->tuned.plain_block = b;
+    float ms = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      vsh_result* out = nullptr;
+      vsh_status rc = generate_plain(ctx, &r, nullptr, nullptr, nullptr, nullptr, nullptr, &out);
+      if (rc) {
+        ctx->tuned = keep;
+        return rc;
+      }
+      ms = std::min<float>(ms, (float)out->t_shower_ms);
+      std::vector<int32_t> si(out->sum_i, out->sum_i + (size_t)kNSumI * r.n_events);
+      vsh_result_free(out);
+      if (ref.empty()) ref = si;
+      else if (si != ref) {
+        ctx->tuned = keep;
+        set_error(ctx, "autotune: plain block %u changed the events (internal error)", b);
+        return VSH_E_INTERNAL;
+      }
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = b;
+    }
+  }
+  ctx->tuned = keep;
+  ctx->tuned.plain_block = best;
+  return VSH_OK;
+}
+
+}  // namespace vsh
+
+using namespace vsh;
+
+extern "C" {
+
+vsh_status vsh_get_tuning(vsh_ctx* ctx, vsh_tuning* out) {
+  if (!ctx || !out) return VSH_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  *out = to_pub(ctx->tuned);
+  return VSH_OK;
+}
+
+vsh_status vsh_set_tuning(vsh_ctx* ctx, const vsh_tuning* t) {
+  if (!ctx || !t) return VSH_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->tuned = from_pub(*t);
+  destroy_graph(ctx->graph);
+  return VSH_OK;
+}
+
+vsh_status vsh_autotune(vsh_ctx* ctx, const vsh_request* sample, vsh_tuning* chosen) {
+  if (!ctx) return VSH_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  vsh_status rc = validate_request(ctx, sample, true);
+  if (rc) return rc;
+  if (sample->flags & VSH_INPUTS_ON_DEVICE) {
+    set_error(ctx, "vsh_autotune takes host inputs");
+    return VSH_E_INVALID;
+  }
+  (void)hipSetDevice(ctx->device);
+  rc = (sample->flags & VSH_FORM_PERSISTENT) ? autotune_persistent(ctx, sample) : autotune_plain(ctx, sample);
+  if (rc) return rc;
+  if (chosen) *chosen = to_pub(ctx->tuned);
+  return VSH_OK;
+}
+
+}  // extern "C"

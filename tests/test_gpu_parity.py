@@ -182,3 +182,34 @@ def test_plain_generate_into_matches_generate(ctx):
     assert t.shape == (2, 3) and (t > 0).all()
     np.testing.assert_array_equal(si.cpu().numpy(), ref["sum_i"])
     np.testing.assert_allclose(hist.cpu().numpy().reshape(P.NOBS, P.NHCOL, 3), ref["hist"], rtol=1e-11, atol=1e-9)
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(mapping=1, waves_per_cu=8, refill_threshold=1, refill_period=1),
+    dict(mapping=1, waves_per_cu=4, refill_threshold=16, refill_period=4),
+    dict(mapping=0, waves_per_cu=8, block=256, refill_threshold=1, refill_period=1),
+    dict(mapping=0, waves_per_cu=16, block=64, refill_threshold=32, refill_period=3),
+])
+def test_persistent_settings_do_not_change_events(ctx, oracle, tuning):
+    old = ctx.get_tuning()
+    try:
+        ctx.set_tuning(**tuning)
+        g, o, rep = _run(ctx, oracle, 2500, 12, 200.0, 0.5, 128, persistent=True)
+        parity.assert_parity(rep)
+        assert rep["frac"] == 1.0
+    finally:
+        ctx.set_tuning(**old)
+
+
+def test_autotune_keeps_events(ctx):
+    from paper_2403_08692_amd.workloads import mixed_energies
+
+    e, t = mixed_energies(3, 100_000)
+    before = ctx.generate(100_000, seed=3, max_partons=128, ecm_per_event=e, tcut_per_event=t, persistent=True)
+    chosen = ctx.autotune(100_000, seed=3, max_partons=128, ecm_per_event=e, tcut_per_event=t)
+    print("autotune chose", chosen, flush=True)
+    after = ctx.generate(100_000, seed=3, max_partons=128, ecm_per_event=e, tcut_per_event=t, persistent=True)
+    np.testing.assert_array_equal(before["sum_i"], after["sum_i"])
+    np.testing.assert_array_equal(before["hash"], after["hash"])
+    plain = ctx.autotune(100_000, seed=3, max_partons=128, ecm_per_event=e, tcut_per_event=t, persistent=False)
+    assert plain["plain_block"] in (64, 128, 256)
