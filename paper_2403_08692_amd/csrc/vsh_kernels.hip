@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(256) k_shower_plain(Records r, Summary sm, Eve
   if (e >= n) return;
   EvState s;
   init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e),
-             sm.i[kSiN * sm.stride + e]);
+             sm.i[kSiN * sm.stride + e], (int)r.cap);
   while (s.status == kRunning) {
     veto_cycle(s, r, e);
     if (s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;

@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
   const uint32_t lane = __lane_id();
   const uint64_t wave_mask = __ballot(1);
   const uint32_t wave_lanes = __popcll(wave_mask);
-  EvState s;
+  EvState s = {};
   s.status = kDone;
   bool busy = false;
   bool drained = false;
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
           sm.d[kSdCos * sm.stride + ev] = m.c;
           sm.d[kSdPhi * sm.stride + ev] = m.phi;
           sm.i[kSiFlavour * sm.stride + ev] = m.f;
-          init_state(s, A.slots, L, key, ecm, tcut, 2);
+          init_state(s, A.slots, L, key, ecm, tcut, 2, (int)R.out.cap);
           busy = true;
         }
       }
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
   const uint32_t lane = threadIdx.x;
   const uint64_t wave_base = (uint64_t)blockIdx.x * 64;
   const uint64_t L = wave_base + lane;
-  EvState s;
+  EvState s = {};
   s.status = kDone;
   bool busy = false;
   bool drained = false;
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
           sm.d[kSdCos * sm.stride + ev] = m.c;
           sm.d[kSdPhi * sm.stride + ev] = m.phi;
           sm.i[kSiFlavour * sm.stride + ev] = m.f;
-          init_state(s, A.slots, L, key, ecm, tcut, 2);
+          init_state(s, A.slots, L, key, ecm, tcut, 2, (int)R.out.cap);
           busy = true;
         }
       }

@@ -1,16 +1,554 @@
-// vsh_serve.hip -- serving loop (placeholder until continuous batching lands).
+// vsh_serve.hip -- serving: continuous batching of event-generation requests.
+//
+// vsh_submit copies a request and returns a ticket.  A serving thread per
+// context
+//   * admits queued requests in arrival order while their event-record
+//     memory (every event's final record at its request's capacity, the
+//     summaries and the histogram) fits a device pool; a request that does
+//     not fit yet waits, one that can never fit is rejected at submission;
+//   * launches bounded epochs of the persistent shower kernel whose work list
+//     holds segments of every admitted request with events left, oldest
+//     first, so requests that arrive while others run join the next epoch;
+//     two epochs may be in flight on two streams, the second filling compute
+//     units the first's tail frees;
+//   * when all events of a request are finished, computes its observables and
+//     histogram on a drain stream, copies the result to the host and completes
+//     the ticket, returning its memory to the pool.
+// Every event is a pure function of (request seed, event id), so a request's
+// events are the same alone or in any mix; only the summation order of its
+// FP64 histogram can differ.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "vsh_internal.hpp"
 
 namespace vsh {
-void serve_shutdown(vsh_ctx*) {}
+
+using Clock = std::chrono::steady_clock;
+
+// first-fit sub-allocator over one device region (256-byte granules)
+struct Pool {
+  char* base = nullptr;
+  uint64_t size = 0;
+  std::map<uint64_t, uint64_t> free_;  // offset -> length
+
+  hipError_t init(uint64_t bytes) {
+    size = align_up(bytes, 256);
+    hipError_t err = hipMalloc(&base, size);
+    if (err != hipSuccess) {
+      base = nullptr;
+      size = 0;
+      return err;
+    }
+    free_.clear();
+    free_[0] = size;
+    return hipSuccess;
+  }
+  bool alloc(uint64_t bytes, uint64_t* off) {
+    bytes = align_up(bytes, 256);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const uint64_t rest = it->second - bytes;
+        const uint64_t at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t bytes) {
+    bytes = align_up(bytes, 256);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  void destroy() {
+    if (base) (void)hipFree(base);
+    base = nullptr;
+    size = 0;
+    free_.clear();
+  }
+};
+
+enum ReqState { kQueued, kAdmitted, kDraining, kFinished, kCancelledState };
+
+struct ServeReq {
+  uint64_t ticket = 0;
+  vsh_request req{};
+  std::vector<double> ecm, tcut;
+  Clock::time_point t_arrival;
+  int state = kQueued;
+  bool cancel = false;
+  uint64_t pool_off = 0, pool_bytes = 0;
+  ReqBuffers buf{};
+  uint64_t scheduled = 0, finished = 0;
+  int inflight = 0;
+  hipEvent_t drained = nullptr;
+  std::vector<double> hist, sd;
+  std::vector<int32_t> si;
+  std::vector<uint64_t> hs;
+  ResultBox* box = nullptr;
+};
+
+constexpr uint32_t kMaxEpochReqs = 512;
+
+struct Epoch {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<std::pair<uint64_t, uint64_t>> parts;  // (ticket, events)
+  ReqDev* reqs_host = nullptr;                       // pinned
+  Segment* segs_host = nullptr;                      // pinned
+  char* dev = nullptr;                               // descriptors, counter, slots
+  uint64_t dev_bytes = 0;
+};
+
+struct ServeState {
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  std::thread th;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::deque<uint64_t> pending;
+  std::vector<uint64_t> active;  // admitted, in admission order
+  std::unordered_map<uint64_t, std::unique_ptr<ServeReq>> reqs;
+  Pool pool;
+  Epoch ep[2];
+  hipStream_t drain = nullptr;
+  char* scratch = nullptr;
+  uint64_t scratch_bytes = 0;
+};
+
+static uint64_t request_bytes(const vsh_request& r) { return request_out_bytes(r.n_events, r.max_partons); }
+
+static void finish_request(ServeState& S, ServeReq& r, int state) {
+  if (r.pool_bytes) {
+    S.pool.release(r.pool_off, r.pool_bytes);
+    r.pool_bytes = 0;
+  }
+  if (r.drained) {
+    (void)hipEventDestroy(r.drained);
+    r.drained = nullptr;
+  }
+  r.state = state;
+  S.active.erase(std::remove(S.active.begin(), S.active.end(), r.ticket), S.active.end());
+  S.done_cv.notify_all();
+}
+
+static bool admit(vsh_ctx* ctx, ServeState& S) {
+  bool progress = false;
+  while (!S.pending.empty()) {
+    ServeReq& r = *S.reqs[S.pending.front()];
+    if (r.cancel) {
+      S.pending.pop_front();
+      finish_request(S, r, kCancelledState);
+      progress = true;
+      continue;
+    }
+    const uint64_t bytes = request_bytes(r.req);
+    uint64_t off = 0;
+    if (!S.pool.alloc(bytes, &off)) break;  // oldest first: wait for memory
+    S.pending.pop_front();
+    r.pool_off = off;
+    r.pool_bytes = bytes;
+    Carver c(S.pool.base + off);
+    r.buf = carve_request(c, r.req.n_events, r.req.max_partons);
+    const uint64_t n = r.req.n_events;
+    if (!r.ecm.empty()) (void)hipMemcpyAsync(r.buf.ecm, r.ecm.data(), n * 8, hipMemcpyHostToDevice, S.drain);
+    if (!r.tcut.empty()) (void)hipMemcpyAsync(r.buf.tcut, r.tcut.data(), n * 8, hipMemcpyHostToDevice, S.drain);
+    launch_zero(r.buf.hist, kHistDoubles, S.drain);
+    (void)hipStreamSynchronize(S.drain);  // inputs on the device before any epoch reads them
+    r.state = kAdmitted;
+    S.active.push_back(r.ticket);
+    progress = true;
+  }
+  (void)ctx;
+  return progress;
+}
+
+static bool ensure_epoch_memory(vsh_ctx* ctx, Epoch& E, uint64_t lanes, uint32_t cap) {
+  const uint64_t need = align_up(kMaxEpochReqs * sizeof(ReqDev), 256) +
+                        align_up(kMaxEpochReqs * sizeof(Segment), 256) + 256 + slots_bytes(lanes, cap);
+  if (need <= E.dev_bytes) return true;
+  if (E.dev) (void)hipFree(E.dev);
+  E.dev = nullptr;
+  E.dev_bytes = 0;
+  if (hipMalloc(&E.dev, need) != hipSuccess) {
+    (void)hipGetLastError();
+    E.dev = nullptr;
+    return false;
+  }
+  E.dev_bytes = need;
+  (void)ctx;
+  return true;
+}
+
+static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
+  Epoch* E = nullptr;
+  for (auto& e : S.ep)
+    if (!e.busy) {
+      E = &e;
+      break;
+    }
+  if (!E) return false;
+  const Tuned tn = ctx->tuned;
+  const uint64_t lanes = persistent_lanes(ctx);
+  const uint64_t limit = std::max<uint64_t>(2 * lanes, 1 << 16);
+  E->parts.clear();
+  uint64_t total = 0;
+  uint32_t nreq = 0, nseg = 0, cap = 2;
+  for (uint64_t t : S.active) {
+    ServeReq& r = *S.reqs[t];
+    if (r.cancel || r.state != kAdmitted || r.scheduled >= r.req.n_events) continue;
+    if (nreq >= kMaxEpochReqs || total >= limit) break;
+    const uint64_t take = std::min(r.req.n_events - r.scheduled, limit - total);
+    ReqDev& d = E->reqs_host[nreq];
+    d.out = r.buf.out;
+    d.sum = r.buf.sum;
+    d.ecm = r.ecm.empty() ? nullptr : r.buf.ecm;
+    d.tcut = r.tcut.empty() ? nullptr : r.buf.tcut;
+    d.ecm0 = r.req.ecm;
+    d.tcut0 = r.req.t_cut;
+    d.seed = r.req.seed;
+    d.first = r.req.first_event;
+    d.count = r.req.n_events;
+    Segment& sg = E->segs_host[nseg];
+    sg.req = nreq;
+    sg.pad = 0;
+    sg.lo = r.scheduled;
+    sg.hi = r.scheduled + take;
+    sg.start = total;
+    r.scheduled += take;
+    r.inflight += 1;
+    total += take;
+    cap = std::max(cap, r.req.max_partons);
+    E->parts.emplace_back(t, take);
+    ++nreq;
+    ++nseg;
+  }
+  if (total == 0) return false;
+  if (!ensure_epoch_memory(ctx, *E, lanes, cap)) {
+    // give the events back; retry when memory frees up
+    for (auto& p : E->parts) {
+      ServeReq& r = *S.reqs[p.first];
+      r.scheduled -= p.second;
+      r.inflight -= 1;
+    }
+    E->parts.clear();
+    return false;
+  }
+  Carver c(E->dev);
+  ReqDev* rd = (ReqDev*)c.take(kMaxEpochReqs * sizeof(ReqDev));
+  Segment* sd = (Segment*)c.take(kMaxEpochReqs * sizeof(Segment));
+  unsigned long long* counter = (unsigned long long*)c.take(256);
+  Records slots = carve_slots(c, lanes, cap);
+  (void)hipMemcpyAsync(rd, E->reqs_host, nreq * sizeof(ReqDev), hipMemcpyHostToDevice, E->stream);
+  (void)hipMemcpyAsync(sd, E->segs_host, nseg * sizeof(Segment), hipMemcpyHostToDevice, E->stream);
+  (void)hipMemsetAsync(counter, 0, 8, E->stream);
+  PersistArgs A;
+  A.slots = slots;
+  A.reqs = rd;
+  A.segs = sd;
+  A.n_segs = nseg;
+  A.threshold = tn.refill_threshold;
+  A.total = total;
+  A.next = counter;
+  A.period = tn.refill_period;
+  A.pad = 0;
+  launch_persistent(A, lanes, tn.pers_block, tn.mapping, E->stream);
+  (void)hipEventRecord(E->done, E->stream);
+  E->busy = true;
+  return true;
+}
+
+static void start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
+  const uint64_t n = r.req.n_events;
+  const uint32_t cap = r.req.max_partons;
+  const uint64_t need = obs_threads(n) * cap * 32 + 4 * 256;
+  if (need > S.scratch_bytes) {
+    (void)hipStreamSynchronize(S.drain);
+    if (S.scratch) (void)hipFree(S.scratch);
+    S.scratch = nullptr;
+    S.scratch_bytes = 0;
+    if (hipMalloc(&S.scratch, need) == hipSuccess) S.scratch_bytes = need;
+    else (void)hipGetLastError();
+  }
+  if (!S.scratch) {
+    r.cancel = true;  // cannot compute its observables: fail the request
+    finish_request(S, r, kCancelledState);
+    return;
+  }
+  Carver c(S.scratch);
+  Scratch sc = carve_scratch(c, n, cap);
+  EventInputs in{};
+  in.ecm = r.ecm.empty() ? nullptr : r.buf.ecm;
+  in.tcut = r.tcut.empty() ? nullptr : r.buf.tcut;
+  in.ecm0 = r.req.ecm;
+  in.tcut0 = r.req.t_cut;
+  in.seed = r.req.seed;
+  in.first = r.req.first_event;
+  launch_obs(r.buf.out, r.buf.sum, in, sc, (uint32_t)n, r.buf.hist, S.drain);
+  r.hist.resize(kHistDoubles);
+  r.sd.resize((size_t)kNSumD * n);
+  r.si.resize((size_t)kNSumI * n);
+  r.hs.resize(n);
+  (void)hipMemcpyAsync(r.hist.data(), r.buf.hist, kHistDoubles * 8, hipMemcpyDeviceToHost, S.drain);
+  (void)hipMemcpyAsync(r.sd.data(), r.buf.sum.d, r.sd.size() * 8, hipMemcpyDeviceToHost, S.drain);
+  (void)hipMemcpyAsync(r.si.data(), r.buf.sum.i, r.si.size() * 4, hipMemcpyDeviceToHost, S.drain);
+  (void)hipMemcpyAsync(r.hs.data(), r.buf.sum.hash, n * 8, hipMemcpyDeviceToHost, S.drain);
+  (void)hipEventCreateWithFlags(&r.drained, hipEventDisableTiming);
+  (void)hipEventRecord(r.drained, S.drain);
+  r.state = kDraining;
+  (void)ctx;
+}
+
+static bool retire_epochs(vsh_ctx* ctx, ServeState& S) {
+  bool progress = false;
+  for (auto& E : S.ep) {
+    if (!E.busy || hipEventQuery(E.done) != hipSuccess) continue;
+    for (auto& p : E.parts) {
+      auto it = S.reqs.find(p.first);
+      if (it == S.reqs.end()) continue;
+      ServeReq& r = *it->second;
+      r.finished += p.second;
+      r.inflight -= 1;
+      if (r.cancel) {
+        if (r.inflight == 0 && r.state == kAdmitted) finish_request(S, r, kCancelledState);
+      } else if (r.finished == r.req.n_events) {
+        start_drain(ctx, S, r);
+      }
+    }
+    E.parts.clear();
+    E.busy = false;
+    progress = true;
+  }
+  return progress;
+}
+
+static bool poll_drains(ServeState& S) {
+  bool progress = false;
+  std::vector<uint64_t> done;
+  for (uint64_t t : S.active) {
+    ServeReq& r = *S.reqs[t];
+    if (r.state == kDraining && hipEventQuery(r.drained) == hipSuccess) done.push_back(t);
+  }
+  for (uint64_t t : done) {
+    ServeReq& r = *S.reqs[t];
+    const uint64_t n = r.req.n_events;
+    ResultBox* box = new_result(n, r.req.flags & VSH_SUMMARY);
+    if (box) {
+      box->hist = r.hist;
+      tally_chunk(box, r.si.data(), r.sd.data(), n, n);
+      if (!box->sum_d.empty()) {
+        box->sum_d = r.sd;
+        box->sum_i = r.si;
+        box->hash = r.hs;
+      }
+      box->pub.t_total_ms = std::chrono::duration<double, std::milli>(Clock::now() - r.t_arrival).count();
+      finish_result(box);
+    }
+    r.box = box;
+    std::vector<double>().swap(r.sd);
+    std::vector<int32_t>().swap(r.si);
+    std::vector<uint64_t>().swap(r.hs);
+    finish_request(S, r, kFinished);
+    progress = true;
+  }
+  return progress;
+}
+
+static void serve_loop(vsh_ctx* ctx) {
+  (void)hipSetDevice(ctx->device);
+  ServeState& S = *ctx->serve;
+  std::unique_lock<std::mutex> lk(S.mu);
+  while (!S.stop) {
+    bool progress = false;
+    progress |= admit(ctx, S);
+    progress |= retire_epochs(ctx, S);
+    progress |= poll_drains(S);
+    while (launch_epoch(ctx, S)) progress = true;
+    if (!progress) S.cv.wait_for(lk, std::chrono::microseconds(100));
+  }
+}
+
+static vsh_status serve_start(vsh_ctx* ctx) {
+  if (ctx->serve) return VSH_OK;
+  auto S = std::make_unique<ServeState>();
+  const uint64_t pool_bytes = std::min<uint64_t>(ctx->budget / 2, 32ull << 30);
+  hipError_t err = S->pool.init(pool_bytes);
+  if (err != hipSuccess) return hip_fail(ctx, err, "serving pool");
+  err = hipStreamCreateWithFlags(&S->drain, hipStreamNonBlocking);
+  if (err != hipSuccess) return hip_fail(ctx, err, "hipStreamCreate");
+  for (auto& E : S->ep) {
+    err = hipStreamCreateWithFlags(&E.stream, hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&E.done, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipHostMalloc((void**)&E.reqs_host, kMaxEpochReqs * sizeof(ReqDev), 0);
+    if (err == hipSuccess) err = hipHostMalloc((void**)&E.segs_host, kMaxEpochReqs * sizeof(Segment), 0);
+    if (err != hipSuccess) return hip_fail(ctx, err, "serving setup");
+  }
+  ctx->serve = S.release();
+  ctx->serve->th = std::thread(serve_loop, ctx);
+  return VSH_OK;
+}
+
+void serve_shutdown(vsh_ctx* ctx) {
+  ServeState* S = ctx->serve;
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  if (S->th.joinable()) S->th.join();
+  for (auto& E : S->ep) {
+    if (E.stream) (void)hipStreamSynchronize(E.stream);
+  }
+  if (S->drain) (void)hipStreamSynchronize(S->drain);
+  for (auto& kv : S->reqs) {
+    ServeReq& r = *kv.second;
+    if (r.drained) (void)hipEventDestroy(r.drained);
+    if (r.box) vsh_result_free(&r.box->pub);
+  }
+  for (auto& E : S->ep) {
+    if (E.dev) (void)hipFree(E.dev);
+    if (E.reqs_host) (void)hipHostFree(E.reqs_host);
+    if (E.segs_host) (void)hipHostFree(E.segs_host);
+    if (E.done) (void)hipEventDestroy(E.done);
+    if (E.stream) (void)hipStreamDestroy(E.stream);
+  }
+  if (S->scratch) (void)hipFree(S->scratch);
+  if (S->drain) (void)hipStreamDestroy(S->drain);
+  S->pool.destroy();
+  delete S;
+  ctx->serve = nullptr;
+}
+
 }  // namespace vsh
 
+using namespace vsh;
+
 extern "C" {
-vsh_status vsh_submit(vsh_ctx* ctx, const vsh_request*, uint64_t*) {
-  vsh::set_error(ctx, "serving not available");
-  return VSH_E_INVALID;
+
+vsh_status vsh_submit(vsh_ctx* ctx, const vsh_request* req, uint64_t* ticket) {
+  if (!ctx || !ticket) return VSH_E_INVALID;
+  std::lock_guard<std::mutex> api(ctx->mu);
+  vsh_status rc = validate_request(ctx, req, true);
+  if (rc) return rc;
+  if (req->flags & (VSH_RECORDS | VSH_INPUTS_ON_DEVICE)) {
+    set_error(ctx, "served requests return summaries and histograms from host inputs");
+    return VSH_E_INVALID;
+  }
+  (void)hipSetDevice(ctx->device);
+  rc = serve_start(ctx);
+  if (rc) return rc;
+  ServeState& S = *ctx->serve;
+  if (request_bytes(*req) > S.pool.size) {
+    set_error(ctx, "request needs %llu bytes of event records; the serving pool holds %llu",
+              (unsigned long long)request_bytes(*req), (unsigned long long)S.pool.size);
+    return VSH_E_NOMEM;
+  }
+  auto r = std::make_unique<ServeReq>();
+  r->req = *req;
+  r->req.ecm_per_event = nullptr;
+  r->req.tcut_per_event = nullptr;
+  if (req->ecm_per_event) r->ecm.assign(req->ecm_per_event, req->ecm_per_event + req->n_events);
+  if (req->tcut_per_event) r->tcut.assign(req->tcut_per_event, req->tcut_per_event + req->n_events);
+  r->t_arrival = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    r->ticket = S.next_ticket++;
+    *ticket = r->ticket;
+    S.pending.push_back(r->ticket);
+    S.reqs.emplace(r->ticket, std::move(r));
+  }
+  S.cv.notify_all();
+  return VSH_OK;
 }
-vsh_status vsh_poll(vsh_ctx*, uint64_t, int*) { return VSH_E_NOTFOUND; }
-vsh_status vsh_wait(vsh_ctx*, uint64_t, vsh_result**) { return VSH_E_NOTFOUND; }
-vsh_status vsh_cancel(vsh_ctx*, uint64_t) { return VSH_E_NOTFOUND; }
+
+vsh_status vsh_poll(vsh_ctx* ctx, uint64_t ticket, int* done) {
+  if (!ctx || !done) return VSH_E_INVALID;
+  ServeState* S = ctx->serve;
+  if (!S) return VSH_E_NOTFOUND;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) {
+    set_error(ctx, "unknown ticket %llu", (unsigned long long)ticket);
+    return VSH_E_NOTFOUND;
+  }
+  const int st = it->second->state;
+  *done = (st == kFinished || st == kCancelledState) ? 1 : 0;
+  return VSH_OK;
 }
+
+vsh_status vsh_wait(vsh_ctx* ctx, uint64_t ticket, vsh_result** out) {
+  if (!ctx || !out) return VSH_E_INVALID;
+  *out = nullptr;
+  ServeState* S = ctx->serve;
+  if (!S) return VSH_E_NOTFOUND;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) {
+    set_error(ctx, "unknown ticket %llu", (unsigned long long)ticket);
+    return VSH_E_NOTFOUND;
+  }
+  ServeReq* r = it->second.get();
+  S->done_cv.wait(lk, [&] { return r->state == kFinished || r->state == kCancelledState; });
+  vsh_status rc = VSH_OK;
+  if (r->state == kCancelledState) {
+    set_error(ctx, "ticket %llu was cancelled", (unsigned long long)ticket);
+    rc = VSH_E_CANCELLED;
+  } else if (!r->box) {
+    set_error(ctx, "host allocation failed for ticket %llu", (unsigned long long)ticket);
+    rc = VSH_E_NOMEM;
+  } else {
+    *out = &r->box->pub;
+    r->box = nullptr;
+  }
+  S->reqs.erase(it);
+  return rc;
+}
+
+vsh_status vsh_cancel(vsh_ctx* ctx, uint64_t ticket) {
+  if (!ctx) return VSH_E_INVALID;
+  ServeState* S = ctx->serve;
+  if (!S) return VSH_E_NOTFOUND;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+      set_error(ctx, "unknown ticket %llu", (unsigned long long)ticket);
+      return VSH_E_NOTFOUND;
+    }
+    ServeReq& r = *it->second;
+    if (r.state == kFinished || r.state == kCancelledState) return VSH_OK;
+    r.cancel = true;
+    if (r.state == kAdmitted && r.inflight == 0) finish_request(*S, r, kCancelledState);
+  }
+  S->cv.notify_all();
+  return VSH_OK;
+}
+
+}  // extern "C"

@@ -54,6 +54,7 @@ struct EvState {
   uint64_t hash;
   uint32_t cycle, trials, ends;
   int n, next_col, n_emit, status;
+  int cap;  // record capacity of this event (its request's)
 };
 
 // what a trial needs to know about its event
@@ -174,7 +175,7 @@ __device__ __forceinline__ void veto_finish(EvState& s, const Records& r, uint64
   if (!(y < 1.0)) return;
   const double prob = alpha_s(t) / s.asmax * kernel_value(w.K, z, y) * (1.0 - y) / kernel_over(w.K, z);
   if (!(unit(a.z, a.w) < prob)) return;
-  if (s.n == (int)r.cap) {
+  if (s.n == s.cap) {
     s.status = kOverflow;
     return;
   }
@@ -255,7 +256,8 @@ __device__ __forceinline__ void veto_cycle(EvState& s, const Records& r, uint64_
 
 // Fresh state for an event whose n initial partons sit in slot e of r.
 __device__ __forceinline__ void init_state(EvState& s, const Records& r, uint64_t e, const Keyed& key,
-                                           double ecm, double tcut, int n) {
+                                           double ecm, double tcut, int n, int cap) {
+  s.cap = cap;
   s.key = key;
   s.tcut = tcut;
   s.ltc = log(tcut);

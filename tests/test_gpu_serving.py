@@ -1,0 +1,109 @@
+"""Serving (continuous batching) through the C ABI: every request's result is
+the same served alone, served in a mix, and generated in one blocking call;
+cancellation and error paths."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2403_08692_amd as P
+
+    c = P.Context()
+    yield c
+    c.close()
+
+
+def _same(a, b, tag):
+    np.testing.assert_array_equal(a["sum_i"], b["sum_i"], err_msg=tag)
+    np.testing.assert_array_equal(a["hash"], b["hash"], err_msg=tag)
+    np.testing.assert_allclose(a["sum_d"], b["sum_d"], rtol=1e-12, atol=1e-15, err_msg=tag)
+    # FP64 histogram sums may differ in summation order only
+    np.testing.assert_allclose(a["hist"], b["hist"], rtol=1e-11, atol=1e-9, err_msg=tag)
+    for k in ("n_done", "n_overflow", "n_nonfinite", "n_conservation", "total_cycles", "total_trials"):
+        assert a[k] == b[k], (tag, k)
+
+
+def test_served_alone_equals_generate(ctx):
+    kw = dict(seed=1001, ecm=91.2, t_cut=1.0, max_partons=128)
+    ref = ctx.generate(5000, summary=True, persistent=True, **kw)
+    t = ctx.submit(5000, summary=True, **kw)
+    got = ctx.wait(t)
+    _same(got, ref, "alone")
+    assert got["t_total_ms"] > 0
+
+
+def test_mix_equals_alone(ctx):
+    from paper_2403_08692_amd.workloads import serving_trace
+
+    trace = serving_trace(40, min_log10_n=2.0, max_log10_n=4.3)
+    alone = {}
+    for r in trace.requests[:12]:
+        t = ctx.submit(r.n_events, seed=r.seed, ecm=r.ecm, t_cut=r.tcut, max_partons=r.cap, summary=True)
+        alone[r.index] = ctx.wait(t)
+    tickets = [(r, ctx.submit(r.n_events, seed=r.seed, ecm=r.ecm, t_cut=r.tcut, max_partons=r.cap, summary=True))
+               for r in trace.requests]
+    for r, t in tickets:
+        res = ctx.wait(t)
+        if r.index in alone:
+            _same(res, alone[r.index], f"request {r.index}")
+        else:
+            assert res["n_events"] == r.n_events and res["n_done"] + res["n_overflow"] == r.n_events
+    # a served request equals the blocking plain form too
+    r = trace.requests[3]
+    ref = ctx.generate(r.n_events, seed=r.seed, ecm=r.ecm, t_cut=r.tcut, max_partons=r.cap, summary=True)
+    _same(alone[3], ref, "plain")
+
+
+def test_mix_with_per_event_energies(ctx):
+    from paper_2403_08692_amd.workloads import mixed_energies
+
+    e, tc = mixed_energies(5, 3000)
+    ref = ctx.generate(3000, seed=5, max_partons=128, summary=True, ecm_per_event=e, tcut_per_event=tc)
+    ts = [ctx.submit(3000, seed=5, max_partons=128, summary=True, ecm_per_event=e, tcut_per_event=tc)
+          for _ in range(3)]
+    others = [ctx.submit(2000, seed=77 + k, ecm=500.0, t_cut=0.5, max_partons=256) for k in range(3)]
+    for t in ts:
+        _same(ctx.wait(t), ref, "per-event energies")
+    for t in others:
+        assert ctx.wait(t)["n_events"] == 2000
+
+
+def test_cancel_and_errors(ctx):
+    import paper_2403_08692_amd as P
+
+    big = ctx.submit(100_000, seed=9, ecm=500.0, t_cut=0.25, max_partons=256)
+    ctx.cancel(big)
+    try:
+        ctx.wait(big)
+        cancelled = False
+    except P.VshError as e:
+        assert e.code == -6
+        cancelled = True
+    # the request either was cancelled or had already finished; either way its ticket is gone
+    with pytest.raises(P.VshError) as ei:
+        ctx.poll(big)
+    assert ei.value.code == -5
+    with pytest.raises(P.VshError) as ei:
+        ctx.wait(123456789)
+    assert ei.value.code == -5
+    with pytest.raises(P.VshError) as ei:
+        ctx.submit(10, t_cut=0.001)
+    assert ei.value.code == -1
+    # the service keeps working after a cancel
+    t = ctx.submit(1000, seed=3)
+    assert ctx.wait(t)["n_done"] == 1000
+    print("cancelled:", cancelled)
+
+
+def test_poll_reports_completion(ctx):
+    import time
+
+    t = ctx.submit(20_000, seed=11)
+    t0 = time.time()
+    while not ctx.poll(t):
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    assert ctx.wait(t)["n_done"] == 20_000
