@@ -146,6 +146,101 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def time_form(ctx, P, torch, w, n, form, steps, ecm_arr=None, tcut_arr=None):
+    """ms per step (ME + shower + observables + histograms) and the shower
+    kernel's mean ms for a workload through vsh_generate_into."""
+    import numpy as np
+
+    from paper_2403_08692_amd._native import make_request
+
+    dev = torch.device("cuda:0")
+    flags = P.VSH_FORM_PERSISTENT if form == "persistent" else P.VSH_FORM_PLAIN
+    e_dev = t_dev = None
+    if ecm_arr is not None:
+        e_dev = torch.from_numpy(ecm_arr).to(dev)
+        t_dev = torch.from_numpy(tcut_arr).to(dev)
+        flags |= P.VSH_INPUTS_ON_DEVICE
+    req, keep = make_request(n, w.seed, w.first_event, w.ecm, w.tcut, w.cap, flags,
+                             None if e_dev is None else e_dev.data_ptr(), None if t_dev is None else t_dev.data_ptr())
+    ws_bytes = ctx.workspace_size(req)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    hist = torch.zeros(P.HIST_DOUBLES, dtype=torch.float64, device=dev)
+    si = torch.empty((P.NSUM_I, n), dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream(dev)
+
+    def step():
+        hist.zero_()
+        ctx.generate_into(req, st.cuda_stream, ws.data_ptr(), ws_bytes, hist.data_ptr(), None, si.data_ptr(), None)
+
+    step()
+    torch.cuda.synchronize()
+    ctx.timing_start()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    stages = ctx.timing_read(steps)
+    s = si.cpu().numpy()
+    out = {"ms_per_step": dt * 1e3, "events_per_s": n / dt, "shower_ms": float(np.mean(stages[:, 1])),
+           "observables_ms": float(np.mean(stages[:, 2])), "n_done": int((s[1] == 1).sum()),
+           "n_overflow": int((s[1] == 2).sum()), "max_cycles": int(s[2].max()),
+           "cycles_per_event": float(s[2].mean())}
+    del ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving_bench(ctx, n_requests, rate_hz):
+    """Replay a Poisson request trace against vsh_submit / vsh_wait; latency
+    is the library's submit -> result-ready time of each request."""
+    import queue
+    import threading
+
+    import numpy as np
+
+    from paper_2403_08692_amd import workloads
+
+    trace = workloads.serving_trace(n_requests, rate_hz)
+    warm = ctx.submit(1000, seed=1)
+    ctx.wait(warm)
+    q = queue.Queue()
+    lag = []
+    t0 = time.perf_counter()
+
+    def submitter():
+        for r in trace.requests:
+            delay = t0 + r.arrival_s - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            lag.append(time.perf_counter() - t0 - r.arrival_s)
+            q.put((r, ctx.submit(r.n_events, seed=r.seed, ecm=r.ecm, t_cut=r.tcut, max_partons=r.cap)))
+        q.put(None)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, done_events, last = [], 0, t0
+    while True:
+        item = q.get()
+        if item is None:
+            break
+        r, t = item
+        res = ctx.wait(t)
+        lat.append(res["t_total_ms"])
+        done_events += res["n_done"] + res["n_overflow"]
+        last = time.perf_counter()
+    th.join()
+    lat = np.array(lat)
+    span = last - t0
+    return {"requests": n_requests, "rate_hz": rate_hz, "events": int(trace.total_events),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "events_per_s": trace.total_events / span,
+            "offered_events_per_s": trace.total_events / trace.requests[-1].arrival_s,
+            "submit_lag_p99_ms": float(np.percentile(lag, 99) * 1e3), "makespan_s": span,
+            "trace": "Poisson 200/s, N = 10^U (U in [2,5]), sqrt(s) in {10,35,91.2,200,500}, "
+                     "t_C in {0.5,1,2}, cap 128, seed 1000+index"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +249,8 @@ def main():
     ap.add_argument("--form", choices=["plain", "persistent"], default="plain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--events", type=int, default=0, help="override the batch size (testing only)")
+    ap.add_argument("--quick", action="store_true", help="main LEP line only (no batched/stress/serving legs)")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the shower shards by event-id "
@@ -246,6 +343,33 @@ def main():
     }
     if cpu:
         line["gpu_over_serial_oracle"] = value / cpu["serial_value"]
+    if not args.quick:
+        extra = {}
+        # LEP through the batched (persistent) form, autotuned on a sample
+        tuned = ctx.autotune(1 << 18, seed=w.seed, ecm=w.ecm, t_cut=w.tcut, max_partons=w.cap)
+        extra["lep_persistent"] = dict(time_form(ctx, P, torch, w, n, "persistent", 10), tuning=tuned)
+        # mixed energies and cutoffs, 10^7 events in one persistent launch (and the plain form)
+        m = workloads.MIXED
+        e_arr, t_arr = m.per_event()
+        tuned = ctx.autotune(1 << 18, seed=m.seed, max_partons=m.cap, ecm_per_event=e_arr[:1 << 18],
+                             tcut_per_event=t_arr[:1 << 18])
+        extra["mixed_1e7"] = {"workload": m.name,
+                              "persistent": dict(time_form(ctx, P, torch, m, m.n_events, "persistent", 3, e_arr, t_arr),
+                                                 tuning=tuned),
+                              "plain": time_form(ctx, P, torch, m, m.n_events, "plain", 2, e_arr, t_arr)}
+        del e_arr, t_arr
+        # long showers at 500 GeV, 256-parton records, both forms
+        st_w = workloads.STRESS
+        tuned = ctx.autotune(1 << 18, seed=st_w.seed, ecm=st_w.ecm, t_cut=st_w.tcut, max_partons=st_w.cap)
+        extra["stress_1e6"] = {"workload": st_w.name,
+                               "persistent": dict(time_form(ctx, P, torch, st_w, st_w.n_events, "persistent", 3),
+                                                  tuning=tuned),
+                               "plain": time_form(ctx, P, torch, st_w, st_w.n_events, "plain", 3)}
+        tuned = ctx.autotune(1 << 18, seed=1, max_partons=128, ecm=91.2, t_cut=1.0)
+        extra["serving"] = serving_bench(ctx, args.serving_requests, 200.0)
+        line["extra"] = extra
+        line["serving_p50_ms"] = extra["serving"]["p50_ms"]
+        line["serving_p99_ms"] = extra["serving"]["p99_ms"]
     print(json.dumps(line))
     ctx.close()
 
