@@ -93,7 +93,7 @@ uint64_t plain_bytes_per_event(uint32_t cap) {
 }
 
 uint64_t plain_layout_bytes(uint64_t stride, uint32_t cap) {
-  return align_up(plain_bytes_per_event(cap) * stride + obs_threads(stride) * cap * 32 + 20 * 256 +
+  return align_up(plain_bytes_per_event(cap) * stride + obs_scratch_bytes(stride, cap) + 20 * 256 +
                       kHistDoubles * 8, 256);
 }
 
@@ -117,12 +117,11 @@ PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap) {
   L.rec.apart = (uint16_t*)take(slots * 2);
   L.rec.stride = stride;
   L.rec.cap = cap;
-  const uint64_t ot = obs_threads(stride);
-  L.sc.jE = (double*)take(ot * cap * 8);
-  L.sc.jx = (double*)take(ot * cap * 8);
-  L.sc.jy = (double*)take(ot * cap * 8);
-  L.sc.jz = (double*)take(ot * cap * 8);
-  L.sc.stride = ot;
+  {
+    char* q = p;
+    L.sc = carve_obs_scratch(q, stride, cap);
+    p = q;
+  }
   L.sum.d = (double*)take(kNSumD * stride * 8);
   L.sum.i = (int32_t*)take(kNSumI * stride * 4);
   L.sum.hash = (uint64_t*)take(stride * 8);

@@ -8,6 +8,8 @@
 //   k_obs            validation, Durham y23/y34, thrust, C, rho_H, B_T/B_W
 //                    (Sec. 3.1) and histograms reduced in LDS before the
 //                    global atomics
+#include <algorithm>
+
 #include "vsh_observables.hpp"
 #include "vsh_shower.hpp"
 
@@ -59,19 +61,103 @@ __global__ void __launch_bounds__(256) k_shower_plain(Records r, Summary sm, Eve
   write_state(s, sm, e);
 }
 
-// Observables and histograms of events [0, n) held in r (slot-major, stride
-// r.stride).  Grid-stride loop: thread t uses Durham scratch slot t.
-__global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs in, Scratch sc,
-                                             uint32_t n, double* __restrict__ hist) {
+// ---------------------------------------------------------------------------
+// Observables pass.  Events are sorted by parton count (largest first) with a
+// counting sort, so the lanes of a wave work on events of the same size;
+// each thread copies its event into its scratch column (coalesced in every
+// later pass), computes the observables and fills an LDS histogram that is
+// added to the global one once per block.
+// ---------------------------------------------------------------------------
+__global__ void k_zero_u32(uint32_t* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Per-block counts in LDS, one global atomic per non-empty count per block.
+__global__ void __launch_bounds__(256) k_obs_count(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt) {
+  __shared__ uint32_t lc[kMaxCount + 1];
+  const uint32_t nb = cap + 1;
+  for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) lc[k] = 0u;
+  __syncthreads();
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) {
+    const uint32_t np = (uint32_t)sm.i[kSiN * sm.stride + e];
+    atomicAdd(&lc[cap - (np < cap ? np : cap)], 1u);
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x)
+    if (lc[k]) atomicAdd(&cnt[k], lc[k]);
+}
+
+// exclusive prefix sum of nb counters, in place (one block)
+__global__ void __launch_bounds__(256) k_obs_scan(uint32_t* cnt, uint32_t nb) {
+  __shared__ uint32_t part[256];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (nb + 255) / 256;
+  uint32_t sum = 0;
+  for (uint32_t k = t * per; k < nb && k < (t + 1) * per; ++k) sum += cnt[k];
+  part[t] = sum;
+  __syncthreads();
+  if (t == 0) {
+    uint32_t run = 0;
+    for (uint32_t k = 0; k < 256; ++k) {
+      const uint32_t v = part[k];
+      part[k] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  uint32_t run = part[t];
+  for (uint32_t k = t * per; k < nb && k < (t + 1) * per; ++k) {
+    const uint32_t v = cnt[k];
+    cnt[k] = run;
+    run += v;
+  }
+}
+
+// Each block reserves one range per parton count with a single global
+// atomic and places its events by their LDS rank inside the range.
+__global__ void __launch_bounds__(256) k_obs_scatter(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt,
+                                                     uint32_t* perm) {
+  __shared__ uint32_t lc[kMaxCount + 1];
+  const uint32_t nb = cap + 1;
+  for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) lc[k] = 0u;
+  __syncthreads();
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t bin = 0, rank = 0;
+  if (e < n) {
+    const uint32_t np = (uint32_t)sm.i[kSiN * sm.stride + e];
+    bin = cap - (np < cap ? np : cap);
+    rank = atomicAdd(&lc[bin], 1u);
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x)
+    if (lc[k]) lc[k] = atomicAdd(&cnt[k], lc[k]);
+  __syncthreads();
+  if (e < n) perm[lc[bin] + rank] = e;
+}
+
+__global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs in, Scratch sc, uint32_t n,
+                                             double* __restrict__ hist) {
   __shared__ double lh[kHistDoubles];
   for (int a = threadIdx.x; a < kHistDoubles; a += blockDim.x) lh[a] = 0.0;
   __syncthreads();
-  const uint64_t slot = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t e = slot; e < n; e += step) {
+  const uint32_t cap = r.cap;
+  const uint64_t n_big = sc.threshold <= cap ? sc.cnt[cap - sc.threshold] : 0u;  // done by k_obs_wave
+  for (uint64_t q = n_big + t; q < n; q += step) {
+    const uint64_t e = sc.perm[q];
     const int status = sm.i[kSiStatus * sm.stride + e];
     const int np = sm.i[kSiN * sm.stride + e];
-    const ObsOut o = event_observables(r, sc, e, slot, np, in.ecm_of(e), status);
+    for (int a = 0; a < np; ++a) {
+      const uint64_t from = (uint64_t)a * r.stride + e, to = (uint64_t)a * sc.stride + t;
+      sc.E[to] = r.E[from];
+      sc.x[to] = r.x[from];
+      sc.y[to] = r.y[from];
+      sc.z[to] = r.z[from];
+    }
+    const ObsOut o = scratch_observables(sc, t, np, in.ecm_of(e), status);
     if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
     for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
     sm.i[kSiStatus * sm.stride + e] = o.status;
@@ -80,6 +166,266 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
   for (int a = threadIdx.x; a < kHistDoubles; a += blockDim.x) {
     const double v = lh[a];
     if (v != 0.0) unsafeAtomicAdd(&hist[a], v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Large events: one wave per event, partons in LDS.  Thrust's candidate
+// planes (i < j, four sign choices) and each Durham step's pair scan are
+// spread over the lanes; ties go to the smallest index in the serial scan
+// order (first maximum for thrust, first minimum for Durham, as in the
+// one-thread-per-event path).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+// (value, index) -> largest value, smallest index among equal values
+__device__ __forceinline__ void wave_argmax(double& v, uint32_t& idx) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const double ov = __shfl_xor(v, d);
+    const uint32_t oi = __shfl_xor(idx, d);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_argmin(double& v, uint32_t& idx) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const double ov = __shfl_xor(v, d);
+    const uint32_t oi = __shfl_xor(idx, d);
+    if (ov < v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+}
+
+// Walk over the pairs (i < j < n) in row-major order: start at linear
+// index p, then advance by `by` indices at a time.
+struct PairWalk {
+  uint32_t i, r, n;  // row i, offset r within the row (j = i + 1 + r)
+  __device__ __forceinline__ PairWalk(uint32_t p, uint32_t n_) : i(0), r(p), n(n_) { settle(); }
+  __device__ __forceinline__ void settle() {
+    while (i + 1 < n && r >= n - 1 - i) {
+      r -= n - 1 - i;
+      ++i;
+    }
+  }
+  __device__ __forceinline__ void advance(uint32_t by) {
+    r += by;
+    settle();
+  }
+  __device__ __forceinline__ uint32_t j() const { return i + 1 + r; }
+};
+
+__global__ void __launch_bounds__(64) k_obs_wave(Records r, Summary sm, EventInputs in, const uint32_t* perm,
+                                                 const uint32_t* cnt, uint32_t cap, uint32_t threshold,
+                                                 double* __restrict__ hist) {
+  extern __shared__ double lds[];
+  double* lh = lds;                         // [kHistDoubles]
+  double* pE = lh + kHistDoubles;           // [cap] each
+  double* px = pE + cap;
+  double* py = px + cap;
+  double* pz = py + cap;
+  double* ux = pz + cap;
+  double* uy = ux + cap;
+  double* uz = uy + cap;
+  uint16_t* list = (uint16_t*)(uz + cap);   // current Durham jets, in order
+  const uint32_t lane = threadIdx.x;
+  for (int a = lane; a < kHistDoubles; a += 64) lh[a] = 0.0;
+  const uint32_t n_big = threshold <= cap ? cnt[cap - threshold] : 0u;
+  __syncthreads();
+  for (uint32_t q = blockIdx.x; q < n_big; q += gridDim.x) {
+    const uint64_t e = perm[q];
+    int status = sm.i[kSiStatus * sm.stride + e];
+    const int np = sm.i[kSiN * sm.stride + e];
+    const double ecm = in.ecm_of(e), sh = ecm * ecm;
+    double tE = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, bad = 0.0, sum = 0.0;
+    double mxx = 0.0, myy = 0.0, mzz = 0.0, mxy = 0.0, mxz = 0.0, myz = 0.0;
+    for (int a = lane; a < np; a += 64) {
+      const uint64_t o = (uint64_t)a * r.stride + e;
+      const P4 p{r.E[o], r.x[o], r.y[o], r.z[o]};
+      pE[a] = p.e;
+      px[a] = p.x;
+      py[a] = p.y;
+      pz[a] = p.z;
+      if (!(isfinite(p.e) && isfinite(p.x) && isfinite(p.y) && isfinite(p.z))) bad += 2.0;
+      else if (!(fabs(mdot(p, p)) <= 1e-10 * sh)) bad += 1.0;
+      tE += p.e;
+      tx += p.x;
+      ty += p.y;
+      tz += p.z;
+      const double l = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+      sum += l;
+      const double il = 1.0 / l;
+      mxx += p.x * p.x * il;
+      myy += p.y * p.y * il;
+      mzz += p.z * p.z * il;
+      mxy += p.x * p.y * il;
+      mxz += p.x * p.z * il;
+      myz += p.y * p.z * il;
+    }
+    tE = wave_sum(tE);
+    tx = wave_sum(tx);
+    ty = wave_sum(ty);
+    tz = wave_sum(tz);
+    bad = wave_sum(bad);
+    __syncthreads();
+    if (status == kDone) {
+      const double tol = 1e-10 * ecm;
+      if (bad >= 2.0) status = kNonFinite;
+      else if (fabs(tE - ecm) > tol || fabs(tx) > tol || fabs(ty) > tol || fabs(tz) > tol || bad > 0.0)
+        status = kConservation;
+    }
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (status == kDone) {
+      sum = wave_sum(sum);
+      mxx = wave_sum(mxx);
+      myy = wave_sum(myy);
+      mzz = wave_sum(mzz);
+      mxy = wave_sum(mxy);
+      mxz = wave_sum(mxz);
+      myz = wave_sum(myz);
+      // thrust over the candidate planes
+      const uint32_t npairs = (uint32_t)np * (np - 1) / 2;
+      double best = -1.0;
+      uint32_t bidx = 0xFFFFFFFFu;
+      double bx = 0.0, by = 0.0, bz = 1.0;
+      PairWalk pw(lane, (uint32_t)np);
+      for (uint32_t pidx = lane; pidx < npairs; pidx += 64, pw.advance(64)) {
+        const uint32_t i = pw.i, j = pw.j();
+        const double xi = px[i], yi = py[i], zi = pz[i], xj = px[j], yj = py[j], zj = pz[j];
+        const double nx = yi * zj - zi * yj, ny = zi * xj - xi * zj, nz = xi * yj - yi * xj;
+        double vx = 0.0, vy = 0.0, vz = 0.0;
+        for (int k = 0; k < np; ++k) {
+          if (k == (int)i || k == (int)j) continue;
+          const double xk = px[k], yk = py[k], zk = pz[k];
+          const double d = xk * nx + yk * ny + zk * nz;
+          if (d > 0.0) { vx += xk; vy += yk; vz += zk; }
+          else { vx -= xk; vy -= yk; vz -= zk; }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double si = (c < 2) ? 1.0 : -1.0, sj = (c & 1) ? -1.0 : 1.0;
+          const double wx = vx + si * xi + sj * xj, wy = vy + si * yi + sj * yj, wz = vz + si * zi + sj * zj;
+          const double m2 = wx * wx + wy * wy + wz * wz;
+          if (m2 > best) { best = m2; bidx = 4 * pidx + c; bx = wx; by = wy; bz = wz; }
+        }
+      }
+      double wbest = best;
+      uint32_t widx = bidx;
+      wave_argmax(wbest, widx);
+      // the winning lane broadcasts its vector
+      const uint64_t who = __ballot(bidx == widx && best == wbest);
+      const int src = __ffsll((unsigned long long)who) - 1;
+      bx = __shfl(bx, src);
+      by = __shfl(by, src);
+      bz = __shfl(bz, src);
+      const double lb = sqrt(wbest);
+      double ax = 0.0, ay = 0.0, az = 1.0;
+      if (lb > 0.0) { ax = bx / lb; ay = by / lb; az = bz / lb; }
+      const double T = sum > 0.0 ? lb / sum : 0.0;
+      const double tau = 1.0 - T;
+      v[2] = tau > 0.0 ? tau : 0.0;
+      const double m2s = mxx * mxx + myy * myy + mzz * mzz + 2.0 * (mxy * mxy + mxz * mxz + myz * myz);
+      const double cpar = 1.5 * (sum * sum - m2s) / (sum * sum);
+      v[3] = cpar > 0.0 ? cpar : 0.0;
+      // hemispheres
+      double hpE = 0, hpx = 0, hpy = 0, hpz = 0, hmE = 0, hmx = 0, hmy = 0, hmz = 0, bp = 0, bm = 0;
+      for (int a = lane; a < np; a += 64) {
+        const double x = px[a], y = py[a], z = pz[a], en = pE[a];
+        const double d = x * ax + y * ay + z * az;
+        const double cx = y * az - z * ay, cy = z * ax - x * az, cz = x * ay - y * ax;
+        const double kt = sqrt(cx * cx + cy * cy + cz * cz);
+        if (d >= 0.0) { hpE += en; hpx += x; hpy += y; hpz += z; bp += kt; }
+        else { hmE += en; hmx += x; hmy += y; hmz += z; bm += kt; }
+      }
+      hpE = wave_sum(hpE); hpx = wave_sum(hpx); hpy = wave_sum(hpy); hpz = wave_sum(hpz);
+      hmE = wave_sum(hmE); hmx = wave_sum(hmx); hmy = wave_sum(hmy); hmz = wave_sum(hmz);
+      bp = wave_sum(bp); bm = wave_sum(bm);
+      const double mp = hpE * hpE - hpx * hpx - hpy * hpy - hpz * hpz;
+      const double mm = hmE * hmE - hmx * hmx - hmy * hmy - hmz * hmz;
+      const double rho = (mp > mm ? mp : mm) / sh;
+      v[4] = rho > 0.0 ? rho : 0.0;
+      bp /= 2.0 * sum;
+      bm /= 2.0 * sum;
+      v[5] = bp + bm;
+      v[6] = bp > bm ? bp : bm;
+      // Durham: pair scan over the current jets each step
+      const double inv_s = 1.0 / sh;
+      for (int a = lane; a < np; a += 64) {
+        list[a] = (uint16_t)a;
+        const double l = sqrt(px[a] * px[a] + py[a] * py[a] + pz[a] * pz[a]);
+        ux[a] = px[a] / l;
+        uy[a] = py[a] / l;
+        uz[a] = pz[a] / l;
+      }
+      __syncthreads();
+      int m = np;
+      while (m > 2) {
+        const uint32_t mp2 = (uint32_t)m * (m - 1) / 2;
+        double ymin = INFINITY;
+        uint32_t yidx = 0xFFFFFFFFu;
+        PairWalk dw(lane, (uint32_t)m);
+        for (uint32_t pidx = lane; pidx < mp2; pidx += 64, dw.advance(64)) {
+          const int ja = list[dw.i], jb = list[dw.j()];
+          const double dx = ux[ja] - ux[jb], dy = uy[ja] - uy[jb], dz = uz[ja] - uz[jb];
+          const double d2 = (dx * dx + dy * dy) + dz * dz;
+          const double em = pE[ja] < pE[jb] ? pE[ja] : pE[jb];
+          const double y = em * em * d2 * inv_s;
+          if (y < ymin) { ymin = y; yidx = pidx; }
+        }
+        wave_argmin(ymin, yidx);
+        const PairWalk win(yidx, (uint32_t)m);
+        const uint32_t ia = win.i, ib = win.j();
+        if (m == 4) v[1] = ymin;
+        if (m == 3) v[0] = ymin;
+        const int ja = list[ia], jb = list[ib];
+        __syncthreads();
+        if (lane == 0) {
+          pE[ja] += pE[jb];
+          px[ja] += px[jb];
+          py[ja] += py[jb];
+          pz[ja] += pz[jb];
+          const double l = sqrt(px[ja] * px[ja] + py[ja] * py[ja] + pz[ja] * pz[ja]);
+          ux[ja] = px[ja] / l;
+          uy[ja] = py[ja] / l;
+          uz[ja] = pz[ja] / l;
+        }
+        // drop jet ib from the list (at most kObsWaveMaxCap entries: 8 per lane)
+        uint16_t mv[kObsWaveMaxCap / 64];
+#pragma unroll
+        for (uint32_t k = 0; k < kObsWaveMaxCap / 64; ++k) {
+          const uint32_t a = ib + 1 + lane + 64 * k;
+          mv[k] = a < (uint32_t)m ? list[a] : (uint16_t)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < kObsWaveMaxCap / 64; ++k) {
+          const uint32_t a = ib + 1 + lane + 64 * k;
+          if (a < (uint32_t)m) list[a - 1] = mv[k];
+        }
+        --m;
+        __syncthreads();
+      }
+      if (lane == 0) hist_fill_lds(lh, ObsOut{{v[0], v[1], v[2], v[3], v[4], v[5], v[6]}, status},
+                                   sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
+    }
+    if (lane < 7) sm.d[(kSdY23 + lane) * sm.stride + e] = v[lane];
+    if (lane == 0) sm.i[kSiStatus * sm.stride + e] = status;
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int a = lane; a < kHistDoubles; a += 64) {
+    const double val = lh[a];
+    if (val != 0.0) unsafeAtomicAdd(&hist[a], val);
   }
 }
 
@@ -108,17 +454,65 @@ void launch_shower_plain(const Records& r, const Summary& s, const EventInputs& 
   hipLaunchKernelGGL(k_shower_plain, dim3(blocks_for(n, block)), dim3(block), 0, st, r, s, in, n);
 }
 
-uint64_t obs_threads(uint64_t n) {
-  const uint64_t most = (uint64_t)kObsBlocks * 256;
+// at most 2^24 parton slots of scratch (1.1 GB) and 2^18 threads (about
+// the resident threads of the pass), at most n
+uint64_t obs_threads(uint64_t n, uint32_t cap) {
+  const uint64_t most = std::max<uint64_t>(256, std::min<uint64_t>(1ull << 18, ((1ull << 24) / cap) / 256 * 256));
   const uint64_t t = ((n + 255) / 256) * 256;
   return t < most ? t : most;
+}
+
+static inline uint64_t al256(uint64_t v) { return (v + 255) / 256 * 256; }
+
+uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap) {
+  const uint64_t m = obs_threads(n, cap) * cap;
+  return 8 * al256(m * 8) + al256(m * 2) + al256(m) + al256(n * 4) + al256((cap + 2) * 4) + 256;
+}
+
+Scratch carve_obs_scratch(char*& p, uint64_t n, uint32_t cap) {
+  Scratch s;
+  s.stride = obs_threads(n, cap);
+  const uint64_t m = s.stride * cap;
+  auto take = [&](uint64_t bytes) {
+    char* q = p;
+    p += al256(bytes);
+    return q;
+  };
+  s.E = (double*)take(m * 8);
+  s.x = (double*)take(m * 8);
+  s.y = (double*)take(m * 8);
+  s.z = (double*)take(m * 8);
+  s.ux = (double*)take(m * 8);
+  s.uy = (double*)take(m * 8);
+  s.uz = (double*)take(m * 8);
+  s.dn = (double*)take(m * 8);
+  s.nn = (uint16_t*)take(m * 2);
+  s.dead = (uint8_t*)take(m);
+  s.perm = (uint32_t*)take(n * 4);
+  s.cnt = (uint32_t*)take((cap + 2) * 4);
+  // events with at least `threshold` partons go to one wave each (LDS holds
+  // up to kObsWaveMaxCap partons); smaller ones to one thread each
+  s.threshold = cap <= kObsWaveMaxCap ? kObsWaveThreshold : 0xFFFFFFFFu;
+  return s;
 }
 
 void launch_obs(const Records& r, const Summary& s, const EventInputs& in, const Scratch& sc,
                 uint32_t n, double* hist, hipStream_t st) {
   if (!n) return;
-  const uint32_t blocks = (uint32_t)(obs_threads(n) / 256);
+  const uint32_t nb = r.cap + 1;
+  hipLaunchKernelGGL(k_zero_u32, dim3((nb + 255) / 256), dim3(256), 0, st, sc.cnt, nb);
+  hipLaunchKernelGGL(k_obs_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, n, r.cap, sc.cnt);
+  hipLaunchKernelGGL(k_obs_scan, dim3(1), dim3(256), 0, st, sc.cnt, nb);
+  hipLaunchKernelGGL(k_obs_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, n, r.cap, sc.cnt, sc.perm);
+  const uint32_t blocks = (uint32_t)(std::min<uint64_t>(sc.stride, ((uint64_t)n + 255) / 256 * 256) / 256);
   hipLaunchKernelGGL(k_obs, dim3(blocks), dim3(256), 0, st, r, s, in, sc, n, hist);
+  if (sc.threshold <= r.cap) {
+    const uint32_t wb = (uint32_t)std::min<uint64_t>(n, kObsWaveBlocks);
+    hipLaunchKernelGGL(k_obs_wave, dim3(wb), dim3(64), obs_wave_lds(r.cap), st, r, s, in, (const uint32_t*)sc.perm,
+                       (const uint32_t*)sc.cnt, r.cap, sc.threshold, hist);
+  }
 }
+
+size_t obs_wave_lds(uint32_t cap) { return (size_t)kHistDoubles * 8 + (size_t)cap * (7 * 8 + 2) + 64; }
 
 }  // namespace vsh

@@ -25,6 +25,7 @@ constexpr int kNObs = 8;
 constexpr int kNBins = 50;
 constexpr int kNHCol = kNBins + 2;
 constexpr int kHistDoubles = kNObs * kNHCol * 3;
+constexpr uint32_t kMaxCount = 1024;  // largest record capacity
 
 // summary field indices
 enum { kSdW = 0, kSdCos = 1, kSdY23 = 2, kSdY34 = 3, kSdTau = 4, kSdC = 5, kSdRho = 6, kSdBT = 7,
@@ -71,22 +72,43 @@ struct HistRanges {
   double lo[kNObs], hi[kNObs];
 };
 
-// jets scratch of the Durham clustering: [4][cap][stride] doubles
+// Scratch of the observables pass: thread slot t keeps its current event's
+// partons (and Durham's jets) at element [a][t]; the events are visited in
+// order of decreasing parton count (perm), so a wave's lanes hold events of
+// the same size.
 struct Scratch {
-  double *jE, *jx, *jy, *jz;
-  uint64_t stride;
+  double *E, *x, *y, *z;    // momenta; Durham merges jets in place
+  double *ux, *uy, *uz;     // unit three-vectors of the current jets
+  double *dn;               // forward nearest-neighbour y
+  uint16_t *nn;             // forward nearest neighbour, 0xFFFF none
+  uint8_t *dead;            // merged-away jets
+  uint64_t stride;          // thread slots
+  uint32_t *perm;           // event indices by decreasing parton count [n]
+  uint32_t *cnt;            // per-count offsets [cap + 2]
+  uint32_t threshold;       // events with at least this many partons: one wave each
 };
+
+constexpr uint32_t kObsWaveThreshold = 12;
+constexpr uint32_t kObsWaveMaxCap = 512;
+constexpr uint32_t kObsWaveBlocks = 8192;
+size_t obs_wave_lds(uint32_t cap);
 
 }  // namespace vsh
 
 // host-side launchers (vsh_kernels.hip)
 namespace vsh {
-// k_obs runs a grid-stride loop over at most kObsBlocks x 256 threads; each
-// thread owns one Durham scratch slot, so the scratch holds obs_threads(n)
-// slots of cap partons.
-constexpr uint32_t kObsBlocks = 2048;
-uint64_t obs_threads(uint64_t n);
+// The observables pass runs a grid-stride loop over obs_threads(n, cap)
+// threads (at most 2^25 parton slots of scratch in all).
+uint64_t obs_threads(uint64_t n, uint32_t cap);
+uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap);
+Scratch carve_obs_scratch(char*& p, uint64_t n, uint32_t cap);
 __global__ void k_obs(Records r, Summary sm, EventInputs in, Scratch sc, uint32_t n, double* __restrict__ hist);
+__global__ void k_obs_count(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt);
+__global__ void k_obs_scan(uint32_t* cnt, uint32_t nb);
+__global__ void k_obs_scatter(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt, uint32_t* perm);
+__global__ void k_zero_u32(uint32_t* p, uint32_t n);
+__global__ void k_obs_wave(Records r, Summary sm, EventInputs in, const uint32_t* perm, const uint32_t* cnt,
+                           uint32_t cap, uint32_t threshold, double* __restrict__ hist);
 void launch_me(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
                hipStream_t st);
 void launch_shower_plain(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,

@@ -14,109 +14,6 @@ __device__ __forceinline__ double len3(double x, double y, double z) {
   return sqrt(x * x + y * y + z * z);
 }
 
-// exact thrust by the plane enumeration: pairs (i<j) span candidate planes,
-// every other momentum sits on one side; i and j take all four sign choices
-__device__ __forceinline__ double thrust_of(const Records& r, uint64_t e, int n, double sum, double& ax,
-                            double& ay, double& az) {
-  double best = -1.0, bx = 0.0, by = 0.0, bz = 1.0;
-  if (n < 3) {
-    for (int m = 0; m < (1 << n); ++m) {
-      double vx = 0.0, vy = 0.0, vz = 0.0;
-      for (int a = 0; a < n; ++a) {
-        const double sg = (m >> a & 1) ? -1.0 : 1.0;
-        const uint64_t o = (uint64_t)a * r.stride + e;
-        vx += sg * r.x[o];
-        vy += sg * r.y[o];
-        vz += sg * r.z[o];
-      }
-      const double m2 = vx * vx + vy * vy + vz * vz;
-      if (m2 > best) { best = m2; bx = vx; by = vy; bz = vz; }
-    }
-  } else {
-    for (int i = 0; i < n; ++i) {
-      const uint64_t oi = (uint64_t)i * r.stride + e;
-      const double xi = r.x[oi], yi = r.y[oi], zi = r.z[oi];
-      for (int j = i + 1; j < n; ++j) {
-        const uint64_t oj = (uint64_t)j * r.stride + e;
-        const double xj = r.x[oj], yj = r.y[oj], zj = r.z[oj];
-        const double nx = yi * zj - zi * yj, ny = zi * xj - xi * zj, nz = xi * yj - yi * xj;
-        double vx = 0.0, vy = 0.0, vz = 0.0;
-        for (int k = 0; k < n; ++k) {
-          if (k == i || k == j) continue;
-          const uint64_t ok = (uint64_t)k * r.stride + e;
-          const double xk = r.x[ok], yk = r.y[ok], zk = r.z[ok];
-          const double d = xk * nx + yk * ny + zk * nz;
-          if (d > 0.0) { vx += xk; vy += yk; vz += zk; }
-          else { vx -= xk; vy -= yk; vz -= zk; }
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double si = (c < 2) ? 1.0 : -1.0, sj = (c & 1) ? -1.0 : 1.0;
-          const double wx = vx + si * xi + sj * xj, wy = vy + si * yi + sj * yj,
-                       wz = vz + si * zi + sj * zj;
-          const double m2 = wx * wx + wy * wy + wz * wz;
-          if (m2 > best) { best = m2; bx = wx; by = wy; bz = wz; }
-        }
-      }
-    }
-  }
-  const double l = sqrt(best);
-  if (l > 0.0) { ax = bx / l; ay = by / l; az = bz / l; }
-  else { ax = 0.0; ay = 0.0; az = 1.0; }
-  return sum > 0.0 ? l / sum : 0.0;
-}
-
-// Durham clustering, E-scheme; y_ab = min(E_a,E_b)^2 |u_a - u_b|^2 / s
-__device__ __forceinline__ void durham_of(const Records& r, const Scratch& sc, uint64_t e, uint64_t slot, int n, double sh,
-                          double& y23, double& y34) {
-  for (int a = 0; a < n; ++a) {
-    const uint64_t o = (uint64_t)a * r.stride + e;
-    const uint64_t q = (uint64_t)a * sc.stride + slot;
-    sc.jE[q] = r.E[o];
-    sc.jx[q] = r.x[o];
-    sc.jy[q] = r.y[o];
-    sc.jz[q] = r.z[o];
-  }
-  y23 = 0.0;
-  y34 = 0.0;
-  int m = n;
-  while (m > 2) {
-    double ymin = 0.0;
-    int ba = -1, bb = -1;
-    for (int a = 0; a < m; ++a) {
-      const uint64_t qa = (uint64_t)a * sc.stride + slot;
-      const double ea = sc.jE[qa], xa = sc.jx[qa], ya = sc.jy[qa], za = sc.jz[qa];
-      const double la = len3(xa, ya, za);
-      for (int b = a + 1; b < m; ++b) {
-        const uint64_t qb = (uint64_t)b * sc.stride + slot;
-        const double eb = sc.jE[qb], xb = sc.jx[qb], yb = sc.jy[qb], zb = sc.jz[qb];
-        const double lb = len3(xb, yb, zb);
-        const double dx = xa / la - xb / lb, dy = ya / la - yb / lb, dz = za / la - zb / lb;
-        const double d2 = (dx * dx + dy * dy) + dz * dz;
-        const double em = ea < eb ? ea : eb;
-        const double yv = em * em * d2 / sh;
-        if (ba < 0 || yv < ymin) { ymin = yv; ba = a; bb = b; }
-      }
-    }
-    if (m == 4) y34 = ymin;
-    if (m == 3) y23 = ymin;
-    const uint64_t qa = (uint64_t)ba * sc.stride + slot;
-    const uint64_t qb = (uint64_t)bb * sc.stride + slot;
-    sc.jE[qa] += sc.jE[qb];
-    sc.jx[qa] += sc.jx[qb];
-    sc.jy[qa] += sc.jy[qb];
-    sc.jz[qa] += sc.jz[qb];
-    for (int a = bb; a + 1 < m; ++a) {
-      const uint64_t q0 = (uint64_t)a * sc.stride + slot, q1 = q0 + sc.stride;
-      sc.jE[q0] = sc.jE[q1];
-      sc.jx[q0] = sc.jx[q1];
-      sc.jy[q0] = sc.jy[q1];
-      sc.jz[q0] = sc.jz[q1];
-    }
-    --m;
-  }
-}
-
 __device__ __forceinline__ int bin_of(double x, double lo, double hi) {
   if (x != x) return kNBins + 1;
   if (x < lo) return 0;
@@ -130,11 +27,109 @@ struct ObsOut {
   int status;
 };
 
-// Validate the event (finite; four-momentum conserved to 1e-10 sqrt(s) per
-// component; every parton massless to 1e-10 s) and, if it passes, compute
-// its observables.
-__device__ __forceinline__ ObsOut event_observables(const Records& r, const Scratch& sc, uint64_t e,
-                                                    uint64_t slot, int np, double ecm, int status) {
+// ---------------------------------------------------------------------------
+// Scratch-based observables.  The event's partons are first copied to a
+// per-thread scratch laid out [slot][thread] (lanes of a wave hold events of
+// equal size after the sort by parton count, so every pass below reads
+// consecutive addresses), then:
+//   validation, thrust (plane enumeration, first maximum), hemispheres,
+//   C from the momentum tensor M_ab = sum_i p_i^a p_i^b / |p_i|:
+//     sum_ij (p_i.p_j)^2/(|p_i||p_j|) = sum_ab M_ab^2,
+//   and Durham with forward nearest neighbours: for each jet a the smallest
+//   y(a, b) over later jets b (first b on ties); the global minimum over a
+//   (first a on ties) is then the first minimum of the pair scan in (a, b)
+//   order.  After a merge of (i, j), i < j, only jets whose neighbour was i
+//   or j need a rescan; earlier jets compare against the new i.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double durham_y(const Scratch& w, uint64_t qa, uint64_t qb, double inv_s) {
+  const double dx = w.ux[qa] - w.ux[qb], dy = w.uy[qa] - w.uy[qb], dz = w.uz[qa] - w.uz[qb];
+  const double d2 = (dx * dx + dy * dy) + dz * dz;
+  const double ea = w.E[qa], eb = w.E[qb];
+  const double em = ea < eb ? ea : eb;
+  return em * em * d2 * inv_s;
+}
+
+__device__ __forceinline__ void set_unit(const Scratch& w, uint64_t q) {
+  const double l = len3(w.x[q], w.y[q], w.z[q]);
+  w.ux[q] = w.x[q] / l;
+  w.uy[q] = w.y[q] / l;
+  w.uz[q] = w.z[q] / l;
+}
+
+// forward nearest neighbour of alive jet a among alive jets b > a
+__device__ __forceinline__ void forward_nn(const Scratch& w, uint64_t t, int a, int n, double inv_s) {
+  const uint64_t qa = (uint64_t)a * w.stride + t;
+  double best = 0.0;
+  int bb = -1;
+  for (int b = a + 1; b < n; ++b) {
+    if (w.dead[(uint64_t)b * w.stride + t]) continue;
+    const double y = durham_y(w, qa, (uint64_t)b * w.stride + t, inv_s);
+    if (bb < 0 || y < best) {
+      best = y;
+      bb = b;
+    }
+  }
+  w.nn[qa] = bb < 0 ? (uint16_t)0xFFFF : (uint16_t)bb;
+  w.dn[qa] = best;
+}
+
+__device__ void durham_nn(const Scratch& w, uint64_t t, int n, double sh, double& y23, double& y34) {
+  const double inv_s = 1.0 / sh;
+  y23 = 0.0;
+  y34 = 0.0;
+  if (n < 3) return;
+  for (int a = 0; a < n; ++a) {
+    w.dead[(uint64_t)a * w.stride + t] = 0;
+    set_unit(w, (uint64_t)a * w.stride + t);
+  }
+  for (int a = 0; a < n; ++a) forward_nn(w, t, a, n, inv_s);
+  int m = n;
+  while (m > 2) {
+    int ia = -1;
+    double ymin = 0.0;
+    for (int a = 0; a < n; ++a) {
+      const uint64_t qa = (uint64_t)a * w.stride + t;
+      if (w.dead[qa] || w.nn[qa] == 0xFFFF) continue;
+      const double d = w.dn[qa];
+      if (ia < 0 || d < ymin) {
+        ymin = d;
+        ia = a;
+      }
+    }
+    const int i = ia, j = w.nn[(uint64_t)ia * w.stride + t];
+    if (m == 4) y34 = ymin;
+    if (m == 3) y23 = ymin;
+    const uint64_t qi = (uint64_t)i * w.stride + t, qj = (uint64_t)j * w.stride + t;
+    w.E[qi] += w.E[qj];
+    w.x[qi] += w.x[qj];
+    w.y[qi] += w.y[qj];
+    w.z[qi] += w.z[qj];
+    set_unit(w, qi);
+    w.dead[qj] = 1;
+    --m;
+    if (m <= 2) break;
+    forward_nn(w, t, i, n, inv_s);
+    for (int a = 0; a < n; ++a) {
+      const uint64_t qa = (uint64_t)a * w.stride + t;
+      if (w.dead[qa] || a == i) continue;
+      const int na = w.nn[qa];
+      if (na == i || na == j) {
+        forward_nn(w, t, a, n, inv_s);
+      } else if (a < i) {
+        const double y = durham_y(w, qa, qi, inv_s);
+        if (na == 0xFFFF || y < w.dn[qa] || (y == w.dn[qa] && i < na)) {
+          w.nn[qa] = (uint16_t)i;
+          w.dn[qa] = y;
+        }
+      }
+    }
+  }
+}
+
+// Observables of one event whose n partons are in scratch column t.
+__device__ __forceinline__ ObsOut scratch_observables(const Scratch& w, uint64_t t, int np, double ecm,
+                                                      int status) {
   ObsOut o;
   for (int h = 0; h < 7; ++h) o.v[h] = 0.0;
   const double sh = ecm * ecm;
@@ -142,7 +137,8 @@ __device__ __forceinline__ ObsOut event_observables(const Records& r, const Scra
     double tE = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
     bool finite = true, massless = true;
     for (int a = 0; a < np; ++a) {
-      const P4 p = r.load(a, e);
+      const uint64_t q = (uint64_t)a * w.stride + t;
+      const P4 p{w.E[q], w.x[q], w.y[q], w.z[q]};
       finite = finite && isfinite(p.e) && isfinite(p.x) && isfinite(p.y) && isfinite(p.z);
       tE += p.e;
       tx += p.x;
@@ -157,40 +153,81 @@ __device__ __forceinline__ ObsOut event_observables(const Records& r, const Scra
   }
   o.status = status;
   if (status != kDone) return o;
-  double sum = 0.0;
+  // sum |p| and the momentum tensor
+  double sum = 0.0, mxx = 0.0, myy = 0.0, mzz = 0.0, mxy = 0.0, mxz = 0.0, myz = 0.0;
   for (int a = 0; a < np; ++a) {
-    const uint64_t q = (uint64_t)a * r.stride + e;
-    sum += len3(r.x[q], r.y[q], r.z[q]);
+    const uint64_t q = (uint64_t)a * w.stride + t;
+    const double x = w.x[q], y = w.y[q], z = w.z[q];
+    const double l = len3(x, y, z);
+    sum += l;
+    const double il = 1.0 / l;
+    mxx += x * x * il;
+    myy += y * y * il;
+    mzz += z * z * il;
+    mxy += x * y * il;
+    mxz += x * z * il;
+    myz += y * z * il;
   }
-  double ax, ay, az;
-  const double T = thrust_of(r, e, np, sum, ax, ay, az);
-  durham_of(r, sc, e, slot, np, sh, o.v[0], o.v[1]);
-  const double tau = 1.0 - T;
-  o.v[2] = tau > 0.0 ? tau : 0.0;
-  double dbl = 0.0;
-  for (int a = 0; a < np; ++a) {
-    const uint64_t qa = (uint64_t)a * r.stride + e;
-    const double xa = r.x[qa], ya = r.y[qa], za = r.z[qa], la = len3(xa, ya, za);
-    for (int b = 0; b < np; ++b) {
-      const uint64_t qb = (uint64_t)b * r.stride + e;
-      const double xb = r.x[qb], yb = r.y[qb], zb = r.z[qb], lb = len3(xb, yb, zb);
-      const double d = xa * xb + ya * yb + za * zb;
-      dbl += d * d / (la * lb);
+  // thrust
+  double best = -1.0, bx = 0.0, by = 0.0, bz = 1.0;
+  if (np < 3) {
+    for (int mk = 0; mk < (1 << np); ++mk) {
+      double vx = 0.0, vy = 0.0, vz = 0.0;
+      for (int a = 0; a < np; ++a) {
+        const double sg = (mk >> a & 1) ? -1.0 : 1.0;
+        const uint64_t q = (uint64_t)a * w.stride + t;
+        vx += sg * w.x[q];
+        vy += sg * w.y[q];
+        vz += sg * w.z[q];
+      }
+      const double m2 = vx * vx + vy * vy + vz * vz;
+      if (m2 > best) { best = m2; bx = vx; by = vy; bz = vz; }
+    }
+  } else {
+    for (int i = 0; i < np; ++i) {
+      const uint64_t qi = (uint64_t)i * w.stride + t;
+      const double xi = w.x[qi], yi = w.y[qi], zi = w.z[qi];
+      for (int j = i + 1; j < np; ++j) {
+        const uint64_t qj = (uint64_t)j * w.stride + t;
+        const double xj = w.x[qj], yj = w.y[qj], zj = w.z[qj];
+        const double nx = yi * zj - zi * yj, ny = zi * xj - xi * zj, nz = xi * yj - yi * xj;
+        double vx = 0.0, vy = 0.0, vz = 0.0;
+        for (int k = 0; k < np; ++k) {
+          if (k == i || k == j) continue;
+          const uint64_t qk = (uint64_t)k * w.stride + t;
+          const double xk = w.x[qk], yk = w.y[qk], zk = w.z[qk];
+          const double d = xk * nx + yk * ny + zk * nz;
+          if (d > 0.0) { vx += xk; vy += yk; vz += zk; }
+          else { vx -= xk; vy -= yk; vz -= zk; }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double si = (c < 2) ? 1.0 : -1.0, sj = (c & 1) ? -1.0 : 1.0;
+          const double wx = vx + si * xi + sj * xj, wy = vy + si * yi + sj * yj, wz = vz + si * zi + sj * zj;
+          const double m2 = wx * wx + wy * wy + wz * wz;
+          if (m2 > best) { best = m2; bx = wx; by = wy; bz = wz; }
+        }
+      }
     }
   }
-  const double cpar = 1.5 * (sum * sum - dbl) / (sum * sum);
+  const double lb = sqrt(best);
+  double ax = 0.0, ay = 0.0, az = 1.0;
+  if (lb > 0.0) { ax = bx / lb; ay = by / lb; az = bz / lb; }
+  const double T = sum > 0.0 ? lb / sum : 0.0;
+  const double tau = 1.0 - T;
+  o.v[2] = tau > 0.0 ? tau : 0.0;
+  const double m2s = mxx * mxx + myy * myy + mzz * mzz + 2.0 * (mxy * mxy + mxz * mxz + myz * myz);
+  const double cpar = 1.5 * (sum * sum - m2s) / (sum * sum);
   o.v[3] = cpar > 0.0 ? cpar : 0.0;
   P4 hp{0, 0, 0, 0}, hm{0, 0, 0, 0};
   double bp = 0.0, bm = 0.0;
   for (int a = 0; a < np; ++a) {
-    const P4 q = r.load(a, e);
-    const double d = q.x * ax + q.y * ay + q.z * az;
-    const double kt = len3(q.y * az - q.z * ay, q.z * ax - q.x * az, q.x * ay - q.y * ax);
-    if (d >= 0.0) {
-      hp.e += q.e; hp.x += q.x; hp.y += q.y; hp.z += q.z; bp += kt;
-    } else {
-      hm.e += q.e; hm.x += q.x; hm.y += q.y; hm.z += q.z; bm += kt;
-    }
+    const uint64_t q = (uint64_t)a * w.stride + t;
+    const P4 p{w.E[q], w.x[q], w.y[q], w.z[q]};
+    const double d = p.x * ax + p.y * ay + p.z * az;
+    const double kt = len3(p.y * az - p.z * ay, p.z * ax - p.x * az, p.x * ay - p.y * ax);
+    if (d >= 0.0) { hp.e += p.e; hp.x += p.x; hp.y += p.y; hp.z += p.z; bp += kt; }
+    else { hm.e += p.e; hm.x += p.x; hm.y += p.y; hm.z += p.z; bm += kt; }
   }
   const double mp = mdot(hp, hp), mm = mdot(hm, hm);
   const double rho = (mp > mm ? mp : mm) / sh;
@@ -199,6 +236,7 @@ __device__ __forceinline__ ObsOut event_observables(const Records& r, const Scra
   bm /= 2.0 * sum;
   o.v[5] = bp + bm;
   o.v[6] = bp > bm ? bp : bm;
+  durham_nn(w, t, np, sh, o.v[0], o.v[1]);  // last: merges jets in the scratch
   return o;
 }
 

@@ -321,7 +321,6 @@ uint64_t request_out_bytes(uint64_t n, uint32_t cap) {
          kHistDoubles * 8;
 }
 
-uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap) { return obs_threads(n) * cap * 32 + 4 * 256; }
 
 Carver::Carver(void* base) : p(static_cast<char*>(base)) {}
 char* Carver::take(uint64_t bytes) {
@@ -371,16 +370,7 @@ ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap) {
   return b;
 }
 
-Scratch carve_scratch(Carver& c, uint64_t n, uint32_t cap) {
-  Scratch s;
-  const uint64_t t = obs_threads(n);
-  s.jE = (double*)c.take(t * cap * 8);
-  s.jx = (double*)c.take(t * cap * 8);
-  s.jy = (double*)c.take(t * cap * 8);
-  s.jz = (double*)c.take(t * cap * 8);
-  s.stride = t;
-  return s;
-}
+Scratch carve_scratch(Carver& c, uint64_t n, uint32_t cap) { return carve_obs_scratch(c.p, n, cap); }
 
 uint64_t batch_bytes(uint64_t lanes, uint64_t n, uint32_t cap) {
   return slots_bytes(lanes, cap) + request_out_bytes(n, cap) + obs_scratch_bytes(n, cap) + 4096 +
@@ -447,12 +437,12 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
     }
     return e;
   };
-  auto add_kernel = [&](const void* fn, dim3 grid, dim3 blk, void** args) -> hipError_t {
+  auto add_kernel = [&](const void* fn, dim3 grid, dim3 blk, void** args, unsigned lds = 0) -> hipError_t {
     hipKernelNodeParams p{};
     p.func = const_cast<void*>(fn);
     p.gridDim = grid;
     p.blockDim = blk;
-    p.sharedMemBytes = 0;
+    p.sharedMemBytes = lds;
     p.kernelParams = args;
     p.extra = nullptr;
     hipGraphNode_t node;
@@ -479,8 +469,28 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   void* a_pers[] = {&g.args};
   GCHK(add_kernel(persistent_kernel(g.mapping), dim3((uint32_t)(lanes / block)), dim3(block), a_pers));
   GCHK(add_event(2));
+  g.nb = L.buf.out.cap + 1;
+  g.cap = L.buf.out.cap;
+  void* a_zero[] = {&g.sc.cnt, &g.nb};
+  GCHK(add_kernel((const void*)k_zero_u32, dim3((g.nb + 255) / 256), dim3(256), a_zero));
+  const uint32_t eb = (uint32_t)((n + 255) / 256);
+  void* a_count[] = {&g.sum, &g.n, &g.cap, &g.sc.cnt};
+  GCHK(add_kernel((const void*)k_obs_count, dim3(eb), dim3(256), a_count));
+  void* a_scan[] = {&g.sc.cnt, &g.nb};
+  GCHK(add_kernel((const void*)k_obs_scan, dim3(1), dim3(256), a_scan));
+  void* a_scatter[] = {&g.sum, &g.n, &g.cap, &g.sc.cnt, &g.sc.perm};
+  GCHK(add_kernel((const void*)k_obs_scatter, dim3(eb), dim3(256), a_scatter));
   void* a_obs[] = {&g.rec, &g.sum, &g.in, &g.sc, &g.n, &g.hist};
-  GCHK(add_kernel((const void*)k_obs, dim3((uint32_t)(obs_threads(n) / 256)), dim3(256), a_obs));
+  const uint32_t ob = (uint32_t)(std::min<uint64_t>(g.sc.stride, (n + 255) / 256 * 256) / 256);
+  GCHK(add_kernel((const void*)k_obs, dim3(ob), dim3(256), a_obs));
+  if (g.sc.threshold <= g.cap) {
+    g.perm_c = g.sc.perm;
+    g.cnt_c = g.sc.cnt;
+    g.thr = g.sc.threshold;
+    void* a_wave[] = {&g.rec, &g.sum, &g.in, &g.perm_c, &g.cnt_c, &g.cap, &g.thr, &g.hist};
+    const uint32_t wb = (uint32_t)std::min<uint64_t>(n, kObsWaveBlocks);
+    GCHK(add_kernel((const void*)k_obs_wave, dim3(wb), dim3(64), a_wave, (unsigned)obs_wave_lds(g.cap)));
+  }
   GCHK(add_event(3));
   GCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
 #undef GCHK

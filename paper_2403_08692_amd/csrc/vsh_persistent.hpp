@@ -77,7 +77,9 @@ struct BatchGraph {
   Summary sum{};
   EventInputs in{};
   Scratch sc{};
-  uint32_t n = 0;
+  uint32_t n = 0, nb = 0, cap = 0, thr = 0;
+  const uint32_t* perm_c = nullptr;
+  const uint32_t* cnt_c = nullptr;
   double* hist = nullptr;
   uint64_t lanes = 0;
   uint32_t block = 0;

@@ -287,7 +287,7 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
 static void start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
   const uint64_t n = r.req.n_events;
   const uint32_t cap = r.req.max_partons;
-  const uint64_t need = obs_threads(n) * cap * 32 + 4 * 256;
+  const uint64_t need = obs_scratch_bytes(n, cap);
   if (need > S.scratch_bytes) {
     (void)hipStreamSynchronize(S.drain);
     if (S.scratch) (void)hipFree(S.scratch);
