@@ -272,6 +272,9 @@ def main():
 
     dev = torch.device("cuda:0")
     ctx = P.Context(0)
+    # launch settings of the timed form, picked by the library's autotuner on a sample of the workload
+    tuning = ctx.autotune(1 << 18, seed=w.seed, ecm=w.ecm, t_cut=w.tcut, max_partons=w.cap,
+                          persistent=args.form == "persistent")
     flags = P.VSH_FORM_PERSISTENT if args.form == "persistent" else P.VSH_FORM_PLAIN
     req, keep = make_request(n, w.seed, w.first_event, w.ecm, w.tcut, w.cap, flags)
     ws_bytes = ctx.workspace_size(req)
@@ -325,7 +328,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n_events": n, "sqrt_s_GeV": w.ecm, "t_cut_GeV2": w.tcut,
-                   "max_partons": w.cap, "seed": w.seed, "form": args.form,
+                   "max_partons": w.cap, "seed": w.seed, "form": args.form, "tuning": tuning,
                    "step": "ME + shower + observables + histograms (vsh_generate_into)"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,

@@ -210,6 +210,8 @@ typedef struct {
   uint32_t block;            /* threads per block of mapping 0: 64, 128 or 256          */
   uint32_t refill_threshold; /* idle lanes a wave waits for before refilling, 1..64     */
   uint32_t refill_period;    /* veto cycles between refill checks, 1..64               */
+  uint32_t plain_waves;      /* register budget of the plain kernel, as resident waves
+                                per SIMD: 2, 3 or 4 (more waves, fewer registers)     */
 } vsh_tuning;
 vsh_status vsh_get_tuning(vsh_ctx *ctx, vsh_tuning *out);
 vsh_status vsh_set_tuning(vsh_ctx *ctx, const vsh_tuning *t);

@@ -102,6 +102,13 @@ __device__ __forceinline__ double alpha_s(double t) {
   return kAlphaSMZ / (1.0 + kAlphaSMZ * b0 * log(t / (kMZ * kMZ)));
 }
 
+// the same from ln t
+__device__ __forceinline__ double alpha_s_of_log(double lt) {
+  constexpr double b0 = (33.0 - 2.0 * kNf) / (12.0 * kPi);
+  constexpr double ln_mz2 = 9.025837845847876;  // ln(91.1876^2)
+  return kAlphaSMZ / (1.0 + kAlphaSMZ * b0 * (lt - ln_mz2));
+}
+
 // ---------------------------------------------------------------------------
 // Splitting kernels (ids): 0-4 q->qg, 5-9 qbar->qbar g, 10 g->gg,
 // 11-15 g->f fbar.  CS final-final kernels, leading colour (a gluon's charge

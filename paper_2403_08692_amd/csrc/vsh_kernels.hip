@@ -47,8 +47,11 @@ __global__ void __launch_bounds__(256) k_init_records(Records r, Summary s, uint
 }
 
 // Plain form: each thread evolves its event to the cutoff in one launch.
-__global__ void __launch_bounds__(256) k_shower_plain(Records r, Summary sm, EventInputs in,
-                                                      uint32_t n) {
+// Compiled for 2, 3 and 4 resident waves per SIMD (register budgets 256,
+// 168 and 128); the autotuner picks by timing.
+template <int kWaves>
+__global__ void __launch_bounds__(256, kWaves) k_shower_plain(Records r, Summary sm, EventInputs in,
+                                                              uint32_t n) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   EvState s;
@@ -448,10 +451,13 @@ void launch_shower_init_records(const Records& r, const Summary& s, const EventI
 }
 
 void launch_shower_plain(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
-                         uint32_t block, hipStream_t st) {
+                         uint32_t block, uint32_t waves, hipStream_t st) {
   if (!n) return;
   if (block == 0 || block > 256) block = 256;
-  hipLaunchKernelGGL(k_shower_plain, dim3(blocks_for(n, block)), dim3(block), 0, st, r, s, in, n);
+  const dim3 g(blocks_for(n, block)), b(block);
+  if (waves >= 4) hipLaunchKernelGGL(k_shower_plain<4>, g, b, 0, st, r, s, in, n);
+  else if (waves == 3) hipLaunchKernelGGL(k_shower_plain<3>, g, b, 0, st, r, s, in, n);
+  else hipLaunchKernelGGL(k_shower_plain<2>, g, b, 0, st, r, s, in, n);
 }
 
 // at most 2^24 parton slots of scratch (1.1 GB) and 2^18 threads (about

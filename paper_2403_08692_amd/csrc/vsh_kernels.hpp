@@ -112,7 +112,7 @@ __global__ void k_obs_wave(Records r, Summary sm, EventInputs in, const uint32_t
 void launch_me(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
                hipStream_t st);
 void launch_shower_plain(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
-                         uint32_t block, hipStream_t st);
+                         uint32_t block, uint32_t waves, hipStream_t st);
 void launch_obs(const Records& r, const Summary& s, const EventInputs& in, const Scratch& sc,
                 uint32_t n, double* hist, hipStream_t st);
 void launch_shower_init_records(const Records& r, const Summary& s, const EventInputs& in,

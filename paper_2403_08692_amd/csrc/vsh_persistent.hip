@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
         const TrialCtx c{Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]}, sh.lt[o], sh.tcut[o],
                          sh.ltc[o], sh.cfac[o], sh.cycle[o]};
         double best = c.ltc;
-        Winner w{0.0, 0.0, 0.0, -1, 0, 0};
+        Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
         uint32_t nt = 0, ne = 0;
         parton_trials(c, A.slots, wave_base + o, (int)i, best, w, nt, ne);
         if (w.i >= 0) {
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
       s.trials += sh.trials[lane];
       s.ends += sh.ends[lane];
       const uint32_t bi = sh.best_idx[lane];
-      Winner w{0.0, 0.0, 0.0, -1, 0, 0};
+      Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
       double best = s.ltc;
       if (bi != kNoTrial) {
         w.i = (int)(bi >> 14);
@@ -261,6 +261,7 @@ __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
         w.K = (int)(bi & 15u);
         best = sh.best_v[lane];
         end_limits(A.slots.load(w.i, L), A.slots.load(w.k, L), s.tcut, w.q2, w.zm, w.zp);
+        w.L = log_fast((1.0 - w.zm) / (1.0 - w.zp));
       }
       veto_finish(s, A.slots, L, best, w);
       if (s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;

@@ -6,6 +6,7 @@
 #pragma once
 
 #include "vsh_kernels.hpp"
+#include "vsh_math.hpp"
 
 namespace vsh {
 
@@ -69,7 +70,7 @@ __device__ __forceinline__ TrialCtx trial_ctx(const EvState& s) {
 }
 
 struct Winner {
-  double q2, zm, zp;
+  double q2, zm, zp, L;  // L = ln((1 - zm)/(1 - zp)), the log of the z range
   int i, k, K;
 };
 
@@ -99,43 +100,48 @@ __device__ __forceinline__ void end_trials(const TrialCtx& c, int i, int k, int 
                                            uint32_t& ends) {
   double q2, zm, zp;
   if (!end_limits(pi, pk, c.tcut, q2, zm, zp)) return;
-  const double L = log((1.0 - zm) / (1.0 - zp));
+  const double L = log_fast((1.0 - zm) / (1.0 - zp));
   ends += 1;
   if (pid_i != kGluon) {
     const double cq = c.cfac * ((2.0 * kCF) * L);
     const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
-    const double lt_try = c.lt + log(unit(d.x, d.y)) / cq;
+    const double lt_try = c.lt + log_fast(unit(d.x, d.y)) / cq;
     trials += 1;
     if (lt_try > best) {
       best = lt_try;
-      w = Winner{q2, zm, zp, i, k, pid_i > 0 ? pid_i - 1 : 4 - pid_i};
+      w = Winner{q2, zm, zp, L, i, k, pid_i > 0 ? pid_i - 1 : 4 - pid_i};
     }
   } else {
     const double cgg = c.cfac * (kCA * L);
     const double cqq = c.cfac * ((0.5 * kTR) * (zp - zm));
-    const U4 d0 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
-    const U4 d1 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 1));
-    const U4 d2 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 2));
+    // kernel list g->gg, g->d dbar, ..., g->b bbar: block g holds kernels 2g, 2g+1
     trials += 6;
-    const double lgg = c.lt + log(unit(d0.x, d0.y)) / cgg;
-    double um = unit(d0.z, d0.w);
-    int fm = 1;
-    double u = unit(d1.x, d1.y);
-    if (u > um) { um = u; fm = 2; }
-    u = unit(d1.z, d1.w);
-    if (u > um) { um = u; fm = 3; }
-    u = unit(d2.x, d2.y);
-    if (u > um) { um = u; fm = 4; }
-    u = unit(d2.z, d2.w);
-    if (u > um) { um = u; fm = 5; }
-    const double lqq = c.lt + log(um) / cqq;
+    double ugg = 0.0, um = 0.0;
+    int fm = 0;
+#pragma unroll 1
+    for (uint32_t g = 0; g < 3; ++g) {
+      const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, g));
+      const double u0 = unit(d.x, d.y), u1 = unit(d.z, d.w);
+      if (g == 0) {
+        ugg = u0;
+      } else if (u0 > um) {
+        um = u0;
+        fm = 2 * g;
+      }
+      if (u1 > um) {  // first flavour wins ties, as in the kernel loop
+        um = u1;
+        fm = 2 * g + 1;
+      }
+    }
+    const double lgg = c.lt + log_fast(ugg) / cgg;
+    const double lqq = c.lt + log_fast(um) / cqq;
     if (lgg > best) {
       best = lgg;
-      w = Winner{q2, zm, zp, i, k, 10};
+      w = Winner{q2, zm, zp, L, i, k, 10};
     }
     if (lqq > best) {
       best = lqq;
-      w = Winner{q2, zm, zp, i, k, 10 + fm};
+      w = Winner{q2, zm, zp, L, i, k, 10 + fm};
     }
   }
 }
@@ -170,10 +176,14 @@ __device__ __forceinline__ void veto_finish(EvState& s, const Records& r, uint64
   s.lt = best;  // the winner's scale bounds every later trial
   const double t = exp(best);
   const U4 a = s.key.draw(this_cycle, kPurposeAccept, 0);
-  const double z = kernel_zgen(w.K, w.zm, w.zp, unit(a.x, a.y));
+  // z from the overestimate's inverse integral: for the 1/(1-z) kernels
+  // 1 - z = (1 - zm) ((1 - zp)/(1 - zm))^u = (1 - zm) exp(-u L)
+  const double uz = unit(a.x, a.y);
+  const double z = w.K <= 10 ? 1.0 - (1.0 - w.zm) * exp(-uz * w.L) : w.zm + (w.zp - w.zm) * uz;
   const double y = t / (w.q2 * z * (1.0 - z));
   if (!(y < 1.0)) return;
-  const double prob = alpha_s(t) / s.asmax * kernel_value(w.K, z, y) * (1.0 - y) / kernel_over(w.K, z);
+  const double prob =
+      alpha_s_of_log(best) / s.asmax * kernel_value(w.K, z, y) * (1.0 - y) / kernel_over(w.K, z);
   if (!(unit(a.z, a.w) < prob)) return;
   if (s.n == s.cap) {
     s.status = kOverflow;
@@ -248,7 +258,7 @@ __device__ __forceinline__ void veto_finish(EvState& s, const Records& r, uint64
 // lexicographic order, then the veto and the splitting.
 __device__ __forceinline__ void veto_cycle(EvState& s, const Records& r, uint64_t e) {
   double best = s.ltc;
-  Winner w{0.0, 0.0, 0.0, -1, 0, 0};
+  Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
   const TrialCtx c = trial_ctx(s);
   for (int i = 0; i < s.n; ++i) parton_trials(c, r, e, i, best, w, s.trials, s.ends);
   veto_finish(s, r, e, best, w);

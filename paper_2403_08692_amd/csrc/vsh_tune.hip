@@ -22,6 +22,7 @@ static uint32_t block_choice(uint32_t b) { return b <= 64 ? 64 : (b <= 128 ? 128
 static vsh_tuning to_pub(const Tuned& t) {
   vsh_tuning p;
   p.plain_block = t.plain_block;
+  p.plain_waves = t.plain_waves;
   p.mapping = t.mapping;
   p.waves_per_cu = t.pers_waves_per_cu;
   p.block = t.pers_block;
@@ -33,6 +34,7 @@ static vsh_tuning to_pub(const Tuned& t) {
 static Tuned from_pub(const vsh_tuning& p) {
   Tuned t;
   t.plain_block = block_choice(p.plain_block);
+  t.plain_waves = clampu(p.plain_waves, 2, 4);
   t.mapping = p.mapping ? kMapFlat : kMapLane;
   t.pers_waves_per_cu = clampu(p.waves_per_cu, 1, 16);
   t.pers_block = block_choice(p.block);
@@ -151,10 +153,14 @@ static vsh_status autotune_plain(vsh_ctx* ctx, const vsh_request* req) {
   r.flags = VSH_SUMMARY;
   const Tuned keep = ctx->tuned;
   float best_ms = 1e30f;
-  uint32_t best = keep.plain_block;
+  Tuned best = keep;
   std::vector<int32_t> ref;
-  for (uint32_t b : {256u, 128u, 64u}) {
+  std::vector<std::pair<uint32_t, uint32_t>> cands;
+  for (uint32_t w : {2u, 3u, 4u})
+    for (uint32_t b : {256u, 64u}) cands.emplace_back(b, w);
+  for (auto [b, wv] : cands) {
     ctx->tuned.plain_block = b;
+    ctx->tuned.plain_waves = wv;
     float ms = 1e30f;
     for (int rep = 0; rep < 2; ++rep) {
       vsh_result* out = nullptr;
@@ -170,16 +176,18 @@ static vsh_status autotune_plain(vsh_ctx* ctx, const vsh_request* req) {
       else if (si != ref) {
         ctx->tuned = keep;
         set_error(ctx, "autotune: plain block %u changed the events (internal error)", b);
+        (void)wv;
         return VSH_E_INTERNAL;
       }
     }
     if (ms < best_ms) {
       best_ms = ms;
-      best = b;
+      best = ctx->tuned;
     }
   }
   ctx->tuned = keep;
-  ctx->tuned.plain_block = best;
+  ctx->tuned.plain_block = best.plain_block;
+  ctx->tuned.plain_waves = best.plain_waves;
   return VSH_OK;
 }
 
