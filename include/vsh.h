@@ -212,6 +212,8 @@ typedef struct {
   uint32_t refill_period;    /* veto cycles between refill checks, 1..64               */
   uint32_t plain_waves;      /* register budget of the plain kernel, as resident waves
                                 per SIMD: 2, 3 or 4 (more waves, fewer registers)     */
+  uint32_t plain_mapping;    /* plain form: 0 = one lane per event, 1 = each wave's 64
+                                events with their cycle's trials spread over its lanes */
 } vsh_tuning;
 vsh_status vsh_get_tuning(vsh_ctx *ctx, vsh_tuning *out);
 vsh_status vsh_set_tuning(vsh_ctx *ctx, const vsh_tuning *t);

@@ -43,7 +43,7 @@ class vsh_request(C.Structure):
 class vsh_tuning(C.Structure):
     _fields_ = [("plain_block", C.c_uint32), ("mapping", C.c_uint32), ("waves_per_cu", C.c_uint32),
                 ("block", C.c_uint32), ("refill_threshold", C.c_uint32), ("refill_period", C.c_uint32),
-                ("plain_waves", C.c_uint32)]
+                ("plain_waves", C.c_uint32), ("plain_mapping", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

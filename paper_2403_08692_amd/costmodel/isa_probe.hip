@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../csrc/vsh_device.hpp"
+#include "../csrc/vsh_math.hpp"
 
 using namespace vsh;
 
@@ -20,6 +21,7 @@ using namespace vsh;
 PROBE_D(base, x)
 PROBE_D(add, x + y)
 PROBE_D(log, log(x))
+PROBE_D(log_fast, log_series(x))
 PROBE_D(exp, exp(x))
 PROBE_D(pow, pow(x, y))
 PROBE_D(sqrt, sqrt(x))

@@ -41,7 +41,8 @@ struct PlainLayout {
 // launch parameters picked by the autotuner (defaults until it has run)
 struct Tuned {
   uint32_t plain_block = 64;
-  uint32_t plain_waves = 3;       // register budget of the plain kernel: resident waves per SIMD
+  uint32_t plain_waves = 3;
+  uint32_t plain_mapping = 1;     // plain form: 0 lane per event, 1 flattened trials       // register budget of the plain kernel: resident waves per SIMD
   uint32_t pers_block = 256;
   uint32_t pers_waves_per_cu = 8;
   uint32_t refill_period = 1;     // veto cycles between compaction / refill passes

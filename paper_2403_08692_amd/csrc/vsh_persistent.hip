@@ -140,6 +140,126 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* start, uint32_t j) 
   return lo;
 }
 
+// One veto cycle of every busy event of this wave, the trials spread over the
+// lanes; each owner lane then finishes its own event's cycle.  Owner o's event
+// sits in slot wave_base + o of `slots`.
+__device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy, const Records& slots,
+                                           uint64_t wave_base, uint32_t lane) {
+  const uint64_t L = wave_base + lane;
+  // --- publish the busy events and the item ranges
+  const uint32_t mine = busy ? (uint32_t)s.n : 0u;
+  uint32_t incl = mine;
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d);
+    if (lane >= d) incl += t;
+  }
+  const uint32_t total = __shfl(incl, 63);
+  sh.start[lane] = incl - mine;
+  if (lane == 63) sh.start[64] = total;
+  sh.lt[lane] = s.lt;
+  sh.tcut[lane] = s.tcut;
+  sh.ltc[lane] = s.ltc;
+  sh.cfac[lane] = s.cfac;
+  sh.key[0][lane] = s.key.ev_lo;
+  sh.key[1][lane] = s.key.ev_hi;
+  sh.key[2][lane] = s.key.k0;
+  sh.key[3][lane] = s.key.k1;
+  sh.cycle[lane] = s.cycle;
+  sh.best_v[lane] = -INFINITY;
+  sh.best_idx[lane] = kNoTrial;
+  sh.trials[lane] = 0;
+  sh.ends[lane] = 0;
+  __syncthreads();
+  // --- trials, 64 items per round
+  for (uint32_t r0 = 0; r0 < total; r0 += 64) {
+    const uint32_t j = r0 + lane;
+    const bool active = j < total;
+    double v = -INFINITY;
+    uint32_t idx = kNoTrial;
+    uint32_t o = 63, seg0 = 64, last = 0;
+    if (active) {
+      o = owner_of(sh.start, j);
+      const uint32_t i = j - sh.start[o];
+      seg0 = (sh.start[o] > r0 ? sh.start[o] : r0) - r0;
+      last = (j + 1 == sh.start[o + 1]) || lane == 63;
+      const TrialCtx c{Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]}, sh.lt[o], sh.tcut[o],
+                       sh.ltc[o], sh.cfac[o], sh.cycle[o]};
+      double best = c.ltc;
+      Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
+      uint32_t nt = 0, ne = 0;
+      parton_trials(c, slots, wave_base + o, (int)i, best, w, nt, ne);
+      if (w.i >= 0) {
+        v = best;
+        idx = pack_trial(w.i, w.k, w.K);
+      }
+      atomicAdd(&sh.trials[o], nt);
+      atomicAdd(&sh.ends[o], ne);
+    }
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+      const double vn = __shfl_up(v, d);
+      const uint32_t in = __shfl_up(idx, d);
+      if (active && lane >= d && lane - d >= seg0 && in != kNoTrial && (vn >= v || idx == kNoTrial)) {
+        v = vn;
+        idx = in;
+      }
+    }
+    if (active && last && idx != kNoTrial && (idx < kNoTrial) &&
+        (sh.best_idx[o] == kNoTrial || v > sh.best_v[o])) {
+      sh.best_v[o] = v;
+      sh.best_idx[o] = idx;
+    }
+    __syncthreads();
+  }
+  // --- each owner finishes its cycle
+  if (busy) {
+    s.trials += sh.trials[lane];
+    s.ends += sh.ends[lane];
+    const uint32_t bi = sh.best_idx[lane];
+    Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
+    double best = s.ltc;
+    if (bi != kNoTrial) {
+      w.i = (int)(bi >> 14);
+      w.k = (int)((bi >> 4) & 1023u);
+      w.K = (int)(bi & 15u);
+      best = sh.best_v[lane];
+      end_limits(slots.load(w.i, L), slots.load(w.k, L), s.tcut, w.q2, w.zm, w.zp);
+      w.L = log_fast((1.0 - w.zm) / (1.0 - w.zp));
+    }
+    veto_finish(s, slots, L, best, w);
+    if (s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
+  }
+}
+
+// Plain one-launch form with the flattened mapping: wave w owns events
+// 64w .. 64w+63 of the batch (already started by k_me) from start to cutoff,
+// with no refill; finished lanes only stop contributing trial work.
+__global__ void __launch_bounds__(64) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n) {
+  __shared__ FlatShared sh;
+  const uint32_t lane = threadIdx.x;
+  const uint64_t wave_base = (uint64_t)blockIdx.x * 64;
+  const uint64_t e = wave_base + lane;
+  EvState s = {};
+  s.status = kDone;
+  bool busy = e < n;
+  if (busy)
+    init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e),
+               sm.i[kSiN * sm.stride + e], (int)r.cap);
+  while (__any(busy)) {
+    flat_cycle(sh, s, busy, r, wave_base, lane);
+    if (busy && s.status != kRunning) {
+      write_state(s, sm, e);
+      busy = false;
+    }
+    __syncthreads();
+  }
+}
+
+void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
+                              hipStream_t st) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_shower_plain_flat, dim3((n + 63) / 64), dim3(64), 0, st, r, s, in, n);
+}
+
 __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
@@ -184,87 +304,8 @@ __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
       }
     }
     if (!__any(busy)) break;
-    // --- publish the busy events and the item ranges
-    const uint32_t mine = busy ? (uint32_t)s.n : 0u;
-    uint32_t incl = mine;
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-      const uint32_t t = __shfl_up(incl, d);
-      if (lane >= d) incl += t;
-    }
-    const uint32_t total = __shfl(incl, 63);
-    sh.start[lane] = incl - mine;
-    if (lane == 63) sh.start[64] = total;
-    sh.lt[lane] = s.lt;
-    sh.tcut[lane] = s.tcut;
-    sh.ltc[lane] = s.ltc;
-    sh.cfac[lane] = s.cfac;
-    sh.key[0][lane] = s.key.ev_lo;
-    sh.key[1][lane] = s.key.ev_hi;
-    sh.key[2][lane] = s.key.k0;
-    sh.key[3][lane] = s.key.k1;
-    sh.cycle[lane] = s.cycle;
-    sh.best_v[lane] = -INFINITY;
-    sh.best_idx[lane] = kNoTrial;
-    sh.trials[lane] = 0;
-    sh.ends[lane] = 0;
-    __syncthreads();
-    // --- trials, 64 items per round
-    for (uint32_t r0 = 0; r0 < total; r0 += 64) {
-      const uint32_t j = r0 + lane;
-      const bool active = j < total;
-      double v = -INFINITY;
-      uint32_t idx = kNoTrial;
-      uint32_t o = 63, seg0 = 64, last = 0;
-      if (active) {
-        o = owner_of(sh.start, j);
-        const uint32_t i = j - sh.start[o];
-        seg0 = (sh.start[o] > r0 ? sh.start[o] : r0) - r0;
-        last = (j + 1 == sh.start[o + 1]) || lane == 63;
-        const TrialCtx c{Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]}, sh.lt[o], sh.tcut[o],
-                         sh.ltc[o], sh.cfac[o], sh.cycle[o]};
-        double best = c.ltc;
-        Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
-        uint32_t nt = 0, ne = 0;
-        parton_trials(c, A.slots, wave_base + o, (int)i, best, w, nt, ne);
-        if (w.i >= 0) {
-          v = best;
-          idx = pack_trial(w.i, w.k, w.K);
-        }
-        atomicAdd(&sh.trials[o], nt);
-        atomicAdd(&sh.ends[o], ne);
-      }
-      for (uint32_t d = 1; d < 64; d <<= 1) {
-        const double vn = __shfl_up(v, d);
-        const uint32_t in = __shfl_up(idx, d);
-        if (active && lane >= d && lane - d >= seg0 && in != kNoTrial && (vn >= v || idx == kNoTrial)) {
-          v = vn;
-          idx = in;
-        }
-      }
-      if (active && last && idx != kNoTrial && (idx < kNoTrial) &&
-          (sh.best_idx[o] == kNoTrial || v > sh.best_v[o])) {
-        sh.best_v[o] = v;
-        sh.best_idx[o] = idx;
-      }
-      __syncthreads();
-    }
-    // --- each owner finishes its cycle
+    flat_cycle(sh, s, busy, A.slots, wave_base, lane);
     if (busy) {
-      s.trials += sh.trials[lane];
-      s.ends += sh.ends[lane];
-      const uint32_t bi = sh.best_idx[lane];
-      Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
-      double best = s.ltc;
-      if (bi != kNoTrial) {
-        w.i = (int)(bi >> 14);
-        w.k = (int)((bi >> 4) & 1023u);
-        w.K = (int)(bi & 15u);
-        best = sh.best_v[lane];
-        end_limits(A.slots.load(w.i, L), A.slots.load(w.k, L), s.tcut, w.q2, w.zm, w.zp);
-        w.L = log_fast((1.0 - w.zm) / (1.0 - w.zp));
-      }
-      veto_finish(s, A.slots, L, best, w);
-      if (s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
       if (s.status != kRunning) {
         const ReqDev& R = A.reqs[req];
         const Records& o = R.out;

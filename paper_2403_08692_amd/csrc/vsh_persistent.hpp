@@ -97,6 +97,8 @@ void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uin
 void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, unsigned long long* counter,
                   hipStream_t st);
 void launch_zero(double* p, uint32_t n, hipStream_t st);
+void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
+                              hipStream_t st);
 void destroy_graph(BatchGraph& g);
 
 }  // namespace vsh

@@ -23,6 +23,7 @@ static vsh_tuning to_pub(const Tuned& t) {
   vsh_tuning p;
   p.plain_block = t.plain_block;
   p.plain_waves = t.plain_waves;
+  p.plain_mapping = t.plain_mapping;
   p.mapping = t.mapping;
   p.waves_per_cu = t.pers_waves_per_cu;
   p.block = t.pers_block;
@@ -35,6 +36,7 @@ static Tuned from_pub(const vsh_tuning& p) {
   Tuned t;
   t.plain_block = block_choice(p.plain_block);
   t.plain_waves = clampu(p.plain_waves, 2, 4);
+  t.plain_mapping = p.plain_mapping ? kMapFlat : kMapLane;
   t.mapping = p.mapping ? kMapFlat : kMapLane;
   t.pers_waves_per_cu = clampu(p.waves_per_cu, 1, 16);
   t.pers_block = block_choice(p.block);
@@ -155,12 +157,17 @@ static vsh_status autotune_plain(vsh_ctx* ctx, const vsh_request* req) {
   float best_ms = 1e30f;
   Tuned best = keep;
   std::vector<int32_t> ref;
-  std::vector<std::pair<uint32_t, uint32_t>> cands;
+  struct Cand {
+    uint32_t block, waves, mapping;
+  };
+  std::vector<Cand> cands{{64, 2, kMapFlat}};
   for (uint32_t w : {2u, 3u, 4u})
-    for (uint32_t b : {256u, 64u}) cands.emplace_back(b, w);
-  for (auto [b, wv] : cands) {
+    for (uint32_t b : {256u, 64u}) cands.push_back({b, w, kMapLane});
+  for (const Cand& cd : cands) {
+    const uint32_t b = cd.block, wv = cd.waves;
     ctx->tuned.plain_block = b;
     ctx->tuned.plain_waves = wv;
+    ctx->tuned.plain_mapping = cd.mapping;
     float ms = 1e30f;
     for (int rep = 0; rep < 2; ++rep) {
       vsh_result* out = nullptr;
@@ -188,6 +195,7 @@ static vsh_status autotune_plain(vsh_ctx* ctx, const vsh_request* req) {
   ctx->tuned = keep;
   ctx->tuned.plain_block = best.plain_block;
   ctx->tuned.plain_waves = best.plain_waves;
+  ctx->tuned.plain_mapping = best.plain_mapping;
   return VSH_OK;
 }
 

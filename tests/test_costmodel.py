@@ -1,0 +1,26 @@
+"""The benchmark's ALU cost table equals what the ISA probe measures on the
+library's own gfx950 build (hipcc cross-compiles here; no GPU needed)."""
+import shutil
+
+import pytest
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None and not __import__("os").path.exists("/opt/rocm/bin/hipcc"),
+                    reason="hipcc not available")
+def test_cost_table_matches_isa_probe():
+    import bench
+    from paper_2403_08692_amd.costmodel import isa_costs
+
+    measured = isa_costs.measure()
+    for k, v in bench.COST.items():
+        assert measured[k] == v, (k, measured[k], v)
+
+
+def test_algorithmic_ops_scale():
+    import bench
+
+    # one LEP-like event: 123 active ends (63 quark, 60 gluon), 31 cycles, 3 emissions
+    ops = bench.algorithmic_ops(1, 123, 63 + 6 * 60, 31, 3)
+    assert 5e4 < ops < 1.5e5
+    # work is additive over events
+    assert bench.algorithmic_ops(2, 246, 2 * 423, 62, 6) == pytest.approx(2 * ops)

@@ -213,3 +213,21 @@ def test_autotune_keeps_events(ctx):
     np.testing.assert_array_equal(before["hash"], after["hash"])
     plain = ctx.autotune(100_000, seed=3, max_partons=128, ecm_per_event=e, tcut_per_event=t, persistent=False)
     assert plain["plain_block"] in (64, 128, 256)
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(plain_mapping=1),
+    dict(plain_mapping=0, plain_block=256, plain_waves=2),
+    dict(plain_mapping=0, plain_block=64, plain_waves=4),
+])
+def test_plain_settings_do_not_change_events(ctx, oracle, tuning):
+    old = ctx.get_tuning()
+    try:
+        ctx.set_tuning(**tuning)
+        g, o, rep = _run(ctx, oracle, 1500, 21, 200.0, 0.5, 128)
+        parity.assert_parity(rep)
+        assert rep["frac"] == 1.0
+        g, o, rep = _run(ctx, oracle, 300, 22, 500.0, 0.25, 256)
+        parity.assert_parity(rep)
+    finally:
+        ctx.set_tuning(**old)
