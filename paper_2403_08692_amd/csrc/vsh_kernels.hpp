@@ -107,6 +107,7 @@ __global__ void k_obs_count(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt)
 __global__ void k_obs_scan(uint32_t* cnt, uint32_t nb);
 __global__ void k_obs_scatter(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt, uint32_t* perm);
 __global__ void k_zero_u32(uint32_t* p, uint32_t n);
+__global__ void k_me(Records r, Summary s, EventInputs in, uint32_t n);
 __global__ void k_obs_wave(Records r, Summary sm, EventInputs in, const uint32_t* perm, const uint32_t* cnt,
                            uint32_t cap, uint32_t threshold, double* __restrict__ hist);
 void launch_me(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,

@@ -71,14 +71,8 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
           const ReqDev& R = A.reqs[req];
           const double ecm = R.ecm ? R.ecm[ev] : R.ecm0;
           const double tcut = R.tcut ? R.tcut[ev] : R.tcut0;
-          const Keyed key = make_keyed(R.seed, R.first + ev);
-          const MEOut m = me_event(A.slots, L, key, ecm);
-          const Summary& sm = R.sum;
-          sm.d[kSdW * sm.stride + ev] = m.w;
-          sm.d[kSdCos * sm.stride + ev] = m.c;
-          sm.d[kSdPhi * sm.stride + ev] = m.phi;
-          sm.i[kSiFlavour * sm.stride + ev] = m.f;
-          init_state(s, A.slots, L, key, ecm, tcut, 2, (int)R.out.cap);
+          start_from_record(s, R.out, ev, A.slots, L, make_keyed(R.seed, R.first + ev), ecm, tcut,
+                            (int)R.out.cap);
           busy = true;
         }
       }
@@ -291,14 +285,8 @@ __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
           const ReqDev& R = A.reqs[req];
           const double ecm = R.ecm ? R.ecm[ev] : R.ecm0;
           const double tcut = R.tcut ? R.tcut[ev] : R.tcut0;
-          const Keyed key = make_keyed(R.seed, R.first + ev);
-          const MEOut m = me_event(A.slots, L, key, ecm);
-          const Summary& sm = R.sum;
-          sm.d[kSdW * sm.stride + ev] = m.w;
-          sm.d[kSdCos * sm.stride + ev] = m.c;
-          sm.d[kSdPhi * sm.stride + ev] = m.phi;
-          sm.i[kSiFlavour * sm.stride + ev] = m.f;
-          init_state(s, A.slots, L, key, ecm, tcut, 2, (int)R.out.cap);
+          start_from_record(s, R.out, ev, A.slots, L, make_keyed(R.seed, R.first + ev), ecm, tcut,
+                            (int)R.out.cap);
           busy = true;
         }
       }
@@ -507,6 +495,8 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   GCHK(add_event(0));
   void* a_setup[] = {&g.rd, &g.d, &g.sd, &g.s, &g.counter};
   GCHK(add_kernel((const void*)k_setup, dim3(1), dim3(64), a_setup));
+  void* a_me[] = {&g.rec, &g.sum, &g.in, &g.n};
+  GCHK(add_kernel((const void*)k_me, dim3((uint32_t)((n + 255) / 256)), dim3(256), a_me));
   GCHK(add_event(1));
   void* a_pers[] = {&g.args};
   GCHK(add_kernel(persistent_kernel(g.mapping), dim3((uint32_t)(lanes / block)), dim3(block), a_pers));
@@ -618,6 +608,7 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
   } else {
     if (tev) (void)hipEventRecord(tev[0], st);
     launch_setup(L.reqs, d, L.segs, sg, L.counter, st);
+    launch_me(L.buf.out, L.buf.sum, in, (uint32_t)n, st);
     if (tev) (void)hipEventRecord(tev[1], st);
     launch_persistent(A, lanes, block, mapping, st);
     if (tev) (void)hipEventRecord(tev[2], st);
@@ -714,6 +705,14 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     fill_request_desc(d, L.buf, req, a, ecm_dev, tcut_dev);
     const Segment sg{0, 0, 0, n, 0};
     launch_setup(L.reqs, d, L.segs, sg, L.counter, st);
+    EventInputs in{};
+    in.ecm = ecm_dev;
+    in.tcut = tcut_dev;
+    in.ecm0 = req->ecm;
+    in.tcut0 = req->t_cut;
+    in.seed = req->seed;
+    in.first = req->first_event + a;
+    launch_me(L.buf.out, L.buf.sum, in, (uint32_t)n, st);
     A.slots = L.slots;
     A.reqs = L.reqs;
     A.segs = L.segs;
@@ -725,13 +724,6 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     (void)hipEventRecord(ctx->ev[1], st);
     launch_persistent(A, lanes, ctx->tuned.pers_block, ctx->tuned.mapping, st);
     (void)hipEventRecord(ctx->ev[2], st);
-    EventInputs in{};
-    in.ecm = ecm_dev;
-    in.tcut = tcut_dev;
-    in.ecm0 = req->ecm;
-    in.tcut0 = req->t_cut;
-    in.seed = req->seed;
-    in.first = req->first_event + a;
     launch_obs(L.buf.out, L.buf.sum, in, L.sc, (uint32_t)n, L.buf.hist, st);
     (void)hipEventRecord(ctx->ev[3], st);
     err = hipGetLastError();

@@ -180,7 +180,15 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     if (!r.ecm.empty()) (void)hipMemcpyAsync(r.buf.ecm, r.ecm.data(), n * 8, hipMemcpyHostToDevice, S.drain);
     if (!r.tcut.empty()) (void)hipMemcpyAsync(r.buf.tcut, r.tcut.data(), n * 8, hipMemcpyHostToDevice, S.drain);
     launch_zero(r.buf.hist, kHistDoubles, S.drain);
-    (void)hipStreamSynchronize(S.drain);  // inputs on the device before any epoch reads them
+    EventInputs in{};
+    in.ecm = r.ecm.empty() ? nullptr : r.buf.ecm;
+    in.tcut = r.tcut.empty() ? nullptr : r.buf.tcut;
+    in.ecm0 = r.req.ecm;
+    in.tcut0 = r.req.t_cut;
+    in.seed = r.req.seed;
+    in.first = r.req.first_event;
+    launch_me(r.buf.out, r.buf.sum, in, (uint32_t)n, S.drain);  // LO partons of every event
+    (void)hipStreamSynchronize(S.drain);  // inputs and LO events on the device before any epoch reads them
     r.state = kAdmitted;
     S.active.push_back(r.ticket);
     progress = true;

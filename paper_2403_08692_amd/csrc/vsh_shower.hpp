@@ -38,10 +38,12 @@ __device__ __forceinline__ MEOut me_event(const Records& r, uint64_t e, const Ke
   r.acol[e] = 0;
   r.col[r.stride + e] = 0;
   r.acol[r.stride + e] = 1;
-  r.cpart[e] = 1;
-  r.apart[e] = kNoPartner;
-  r.cpart[r.stride + e] = kNoPartner;
-  r.apart[r.stride + e] = 0;
+  if (r.cpart) {  // output records carry no partner links
+    r.cpart[e] = 1;
+    r.apart[e] = kNoPartner;
+    r.cpart[r.stride + e] = kNoPartner;
+    r.apart[r.stride + e] = 0;
+  }
   return MEOut{w, c, phi, f};
 }
 
@@ -270,10 +272,10 @@ __device__ __forceinline__ void init_state(EvState& s, const Records& r, uint64_
   s.cap = cap;
   s.key = key;
   s.tcut = tcut;
-  s.ltc = log(tcut);
-  s.asmax = alpha_s(tcut);
+  s.ltc = log_fast(tcut);
+  s.asmax = alpha_s_of_log(s.ltc);  // the overestimate alpha_s(t_C)
   s.cfac = s.asmax / (2.0 * kPi);
-  s.lt = log(ecm * ecm);  // evolution starts at s
+  s.lt = log_fast(ecm * ecm);  // evolution starts at s
   s.hash = kFnvOffset;
   s.cycle = 0;
   s.trials = 0;
@@ -288,6 +290,41 @@ __device__ __forceinline__ void init_state(EvState& s, const Records& r, uint64_
     mc = ac > mc ? ac : mc;
   }
   s.next_col = mc + 1;
+}
+
+// Start the event whose LO partons the matrix-element pass left in slots 0
+// and 1 of `from` (column `ev`) in working slot e of r.
+__device__ __forceinline__ void start_from_record(EvState& s, const Records& from, uint64_t ev, const Records& r,
+                                                  uint64_t e, const Keyed& key, double ecm, double tcut, int cap) {
+  for (uint32_t a = 0; a < 2; ++a) {
+    const uint64_t f = (uint64_t)a * from.stride + ev, t = (uint64_t)a * r.stride + e;
+    r.E[t] = from.E[f];
+    r.x[t] = from.x[f];
+    r.y[t] = from.y[f];
+    r.z[t] = from.z[f];
+    r.pid[t] = from.pid[f];
+    r.col[t] = from.col[f];
+    r.acol[t] = from.acol[f];
+  }
+  r.cpart[e] = 1;
+  r.apart[e] = kNoPartner;
+  r.cpart[r.stride + e] = kNoPartner;
+  r.apart[r.stride + e] = 0;
+  s.key = key;
+  s.tcut = tcut;
+  s.ltc = log_fast(tcut);
+  s.asmax = alpha_s_of_log(s.ltc);
+  s.cfac = s.asmax / (2.0 * kPi);
+  s.lt = log_fast(ecm * ecm);
+  s.hash = kFnvOffset;
+  s.cycle = 0;
+  s.trials = 0;
+  s.ends = 0;
+  s.n = 2;
+  s.n_emit = 0;
+  s.status = kRunning;
+  s.next_col = 2;
+  s.cap = cap;
 }
 
 __device__ __forceinline__ void write_state(const EvState& s, const Summary& sm, uint64_t e) {
