@@ -206,9 +206,13 @@ typedef struct {
   uint32_t plain_block;      /* threads per block, plain form: 64, 128 or 256          */
   uint32_t mapping;          /* persistent form: 0 = one lane per event,
                                 1 = each cycle's trials spread over the wave's lanes   */
-  uint32_t waves_per_cu;     /* resident persistent waves per compute unit, 1..16      */
+  uint32_t waves_per_cu;     /* persistent waves launched per compute unit, 1..16 (the
+                                flattened kernel keeps 8 resident per CU; later waves
+                                start as earlier ones exit)                           */
   uint32_t block;            /* threads per block of mapping 0: 64, 128 or 256          */
-  uint32_t refill_threshold; /* idle lanes a wave waits for before refilling, 1..64     */
+  uint32_t refill_threshold; /* idle lanes a wave waits for before refilling, 1..64;
+                                batches evolve in their output records and claim whole
+                                multiples of 16 events, so there it is at least 16    */
   uint32_t refill_period;    /* veto cycles between refill checks, 1..64               */
   uint32_t plain_waves;      /* register budget of the plain kernel, as resident waves
                                 per SIMD: 2, 3 or 4 (more waves, fewer registers)     */

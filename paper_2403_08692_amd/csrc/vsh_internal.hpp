@@ -41,12 +41,12 @@ struct PlainLayout {
 // launch parameters picked by the autotuner (defaults until it has run)
 struct Tuned {
   uint32_t plain_block = 64;
-  uint32_t plain_waves = 3;
-  uint32_t plain_mapping = 1;     // plain form: 0 lane per event, 1 flattened trials       // register budget of the plain kernel: resident waves per SIMD
+  uint32_t plain_waves = 3;       // register budget of the plain lane kernel: resident waves per SIMD
+  uint32_t plain_mapping = 1;     // plain form: 0 lane per event, 1 flattened trials
   uint32_t pers_block = 256;
-  uint32_t pers_waves_per_cu = 8;
-  uint32_t refill_period = 1;     // veto cycles between compaction / refill passes
-  uint32_t refill_threshold = 1;  // idle lanes needed before a wave refills
+  uint32_t pers_waves_per_cu = 16;
+  uint32_t refill_period = 1;      // veto cycles between compaction / refill passes
+  uint32_t refill_threshold = 16;  // idle lanes needed before a wave refills
   uint32_t mapping = 1;           // persistent mapping: 0 lane per event, 1 flattened trials
 };
 
@@ -103,8 +103,8 @@ vsh_status generate_plain(vsh_ctx* ctx, const vsh_request* req, const uint64_t* 
 
 // persistent form (vsh_persistent.hip)
 uint32_t persistent_lanes(const vsh_ctx* ctx);
-uint64_t batch_bytes(uint64_t lanes, uint64_t n, uint32_t cap);
-BatchLayout carve_batch(void* base, uint64_t lanes, uint64_t n, uint32_t cap);
+uint64_t batch_bytes(uint64_t n, uint32_t cap);
+BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap);
 vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, uint64_t n, hipStream_t st,
                      void* base, const double* ecm_dev, const double* tcut_dev, double* hist, bool use_graph,
                      BatchLayout* out_layout);

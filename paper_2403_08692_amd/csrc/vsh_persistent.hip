@@ -39,63 +39,97 @@ __device__ __forceinline__ uint32_t find_segment(const Segment* segs, uint32_t n
   return lo;
 }
 
+// Claim work for the idle lanes of this wave (see the file comment).  Returns
+// true for a lane that took an event; sets req/ev and, once the counter is
+// exhausted, drained.  Claims are whole multiples of kGranule events, so with
+// kGranule = 16 every claim starts on a 16-event boundary and each 128-byte
+// line of a record column (16 doubles of consecutive events) belongs to one
+// wave: needed when the events evolve in place, where neighbouring events of
+// one line would otherwise be written by waves on different XCDs.
+template <uint32_t kGranule>
+__device__ __forceinline__ bool refill(const PersistArgs& A, bool busy, uint32_t wave_lanes, uint32_t lane,
+                                      uint32_t& since, bool& drained, uint32_t& req, uint64_t& ev) {
+  const uint64_t idle = __ballot(!busy);
+  const uint32_t n_idle = __popcll(idle);
+  const uint32_t take = n_idle / kGranule * kGranule;
+  if (drained || take == 0 || (n_idle != wave_lanes && (since < A.period || n_idle < A.threshold)))
+    return false;
+  since = 0;
+  const uint32_t leader = __ffsll((unsigned long long)idle) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(A.next, (unsigned long long)take);
+  base = __shfl(base, leader);
+  if (base + take >= A.total) drained = true;
+  if (busy) return false;
+  const uint32_t rank = __popcll(idle & ((1ull << lane) - 1));
+  const uint64_t w = base + rank;
+  if (rank >= take || w >= A.total) return false;
+  const uint32_t sg = find_segment(A.segs, A.n_segs, w);
+  req = A.segs[sg].req;
+  ev = A.segs[sg].lo + (w - A.segs[sg].start);
+  return true;
+}
+
+// Start event ev of request R in working slot `slot`.  In place, the slots
+// are R's own output records, where the matrix-element pass has already
+// left the LO partons and their partner links.
+template <bool kInPlace>
+__device__ __forceinline__ void start_event(EvState& s, const PersistArgs& A, const ReqDev& R, uint64_t ev,
+                                            uint64_t slot) {
+  const double ecm = R.ecm ? R.ecm[ev] : R.ecm0;
+  const double tcut = R.tcut ? R.tcut[ev] : R.tcut0;
+  const Keyed key = make_keyed(R.seed, R.first + ev);
+  if (kInPlace) lo_state(s, key, ecm, tcut, (int)R.out.cap);
+  else start_from_record(s, R.out, ev, A.slots, slot, key, ecm, tcut, (int)R.out.cap);
+}
+
+// Record a finished event: its summary, and (unless in place) its partons
+// copied from the working slot to the request's output.
+template <bool kInPlace>
+__device__ __forceinline__ void finish_event(const EvState& s, const PersistArgs& A, const ReqDev& R, uint64_t ev,
+                                             uint64_t slot) {
+  if (!kInPlace) {
+    const Records& o = R.out;
+    for (int a = 0; a < s.n; ++a) {
+      const uint64_t from = (uint64_t)a * A.slots.stride + slot;
+      const uint64_t to = (uint64_t)a * o.stride + ev;
+      o.E[to] = A.slots.E[from];
+      o.x[to] = A.slots.x[from];
+      o.y[to] = A.slots.y[from];
+      o.z[to] = A.slots.z[from];
+      o.pid[to] = A.slots.pid[from];
+      o.col[to] = A.slots.col[from];
+      o.acol[to] = A.slots.acol[from];
+    }
+  }
+  write_state(s, R.sum, ev);
+}
+
+template <bool kInPlace>
 __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
-  const uint64_t L = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;  // this lane's slot
+  const uint64_t L = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;  // this lane's working slot
   const uint32_t lane = __lane_id();
-  const uint64_t wave_mask = __ballot(1);
-  const uint32_t wave_lanes = __popcll(wave_mask);
+  const uint32_t wave_lanes = __popcll(__ballot(1));
   EvState s = {};
   s.status = kDone;
   bool busy = false;
   bool drained = false;
   uint32_t req = 0;
   uint64_t ev = 0;  // event index within its request
+  uint64_t slot = L;
   uint32_t since = 0;
   while (true) {
-    const uint64_t idle = __ballot(!busy);
-    const uint32_t n_idle = __popcll(idle);
-    if (!drained && n_idle > 0 &&
-        (n_idle == wave_lanes || (since >= A.period && n_idle >= A.threshold))) {
-      since = 0;
-      const uint32_t leader = __ffsll((unsigned long long)idle) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(A.next, (unsigned long long)n_idle);
-      base = __shfl(base, leader);
-      if (base + n_idle >= A.total) drained = true;
-      if (!busy) {
-        const uint64_t w = base + __popcll(idle & ((1ull << lane) - 1));
-        if (w < A.total) {
-          const uint32_t sg = find_segment(A.segs, A.n_segs, w);
-          req = A.segs[sg].req;
-          ev = A.segs[sg].lo + (w - A.segs[sg].start);
-          const ReqDev& R = A.reqs[req];
-          const double ecm = R.ecm ? R.ecm[ev] : R.ecm0;
-          const double tcut = R.tcut ? R.tcut[ev] : R.tcut0;
-          start_from_record(s, R.out, ev, A.slots, L, make_keyed(R.seed, R.first + ev), ecm, tcut,
-                            (int)R.out.cap);
-          busy = true;
-        }
-      }
+    if (refill<(kInPlace ? 16u : 1u)>(A, busy, wave_lanes, lane, since, drained, req, ev)) {
+      slot = kInPlace ? ev : L;
+      start_event<kInPlace>(s, A, A.reqs[req], ev, slot);
+      busy = true;
     }
     if (!__any(busy)) break;  // counter exhausted and nothing left in this wave
     if (busy) {
-      veto_cycle(s, A.slots, L);
+      veto_cycle(s, A.slots, slot);
       if (s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
       if (s.status != kRunning) {
-        const ReqDev& R = A.reqs[req];
-        const Records& o = R.out;
-        for (int a = 0; a < s.n; ++a) {
-          const uint64_t from = (uint64_t)a * A.slots.stride + L;
-          const uint64_t to = (uint64_t)a * o.stride + ev;
-          o.E[to] = A.slots.E[from];
-          o.x[to] = A.slots.x[from];
-          o.y[to] = A.slots.y[from];
-          o.z[to] = A.slots.z[from];
-          o.pid[to] = A.slots.pid[from];
-          o.col[to] = A.slots.col[from];
-          o.acol[to] = A.slots.acol[from];
-        }
-        write_state(s, R.sum, ev);
+        finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
         busy = false;
       }
     }
@@ -116,6 +150,7 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
 // ---------------------------------------------------------------------------
 struct FlatShared {
   double lt[64], tcut[64], ltc[64], cfac[64];
+  uint64_t slot[64];
   uint32_t key[4][64];
   uint32_t cycle[64];
   uint32_t start[65];
@@ -135,11 +170,10 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* start, uint32_t j) 
 }
 
 // One veto cycle of every busy event of this wave, the trials spread over the
-// lanes; each owner lane then finishes its own event's cycle.  Owner o's event
-// sits in slot wave_base + o of `slots`.
+// lanes; each owner lane then finishes its own event's cycle.  The event of
+// the calling lane sits in column `slot` of `slots`.
 __device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy, const Records& slots,
-                                           uint64_t wave_base, uint32_t lane) {
-  const uint64_t L = wave_base + lane;
+                                           uint64_t slot, uint32_t lane) {
   // --- publish the busy events and the item ranges
   const uint32_t mine = busy ? (uint32_t)s.n : 0u;
   uint32_t incl = mine;
@@ -154,6 +188,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy
   sh.tcut[lane] = s.tcut;
   sh.ltc[lane] = s.ltc;
   sh.cfac[lane] = s.cfac;
+  sh.slot[lane] = slot;
   sh.key[0][lane] = s.key.ev_lo;
   sh.key[1][lane] = s.key.ev_hi;
   sh.key[2][lane] = s.key.k0;
@@ -181,7 +216,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy
       double best = c.ltc;
       Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
       uint32_t nt = 0, ne = 0;
-      parton_trials(c, slots, wave_base + o, (int)i, best, w, nt, ne);
+      parton_trials(c, slots, sh.slot[o], (int)i, best, w, nt, ne);
       if (w.i >= 0) {
         v = best;
         idx = pack_trial(w.i, w.k, w.K);
@@ -216,10 +251,10 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy
       w.k = (int)((bi >> 4) & 1023u);
       w.K = (int)(bi & 15u);
       best = sh.best_v[lane];
-      end_limits(slots.load(w.i, L), slots.load(w.k, L), s.tcut, w.q2, w.zm, w.zp);
+      end_limits(slots.load(w.i, slot), slots.load(w.k, slot), s.tcut, w.q2, w.zm, w.zp);
       w.L = log_fast((1.0 - w.zm) / (1.0 - w.zp));
     }
-    veto_finish(s, slots, L, best, w);
+    veto_finish(s, slots, slot, best, w);
     if (s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
   }
 }
@@ -230,8 +265,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy
 __global__ void __launch_bounds__(64) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
-  const uint64_t wave_base = (uint64_t)blockIdx.x * 64;
-  const uint64_t e = wave_base + lane;
+  const uint64_t e = (uint64_t)blockIdx.x * 64 + lane;
   EvState s = {};
   s.status = kDone;
   bool busy = e < n;
@@ -239,7 +273,7 @@ __global__ void __launch_bounds__(64) k_shower_plain_flat(Records r, Summary sm,
     init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e),
                sm.i[kSiN * sm.stride + e], (int)r.cap);
   while (__any(busy)) {
-    flat_cycle(sh, s, busy, r, wave_base, lane);
+    flat_cycle(sh, s, busy, r, e, lane);
     if (busy && s.status != kRunning) {
       write_state(s, sm, e);
       busy = false;
@@ -254,63 +288,30 @@ void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInp
   hipLaunchKernelGGL(k_shower_plain_flat, dim3((n + 63) / 64), dim3(64), 0, st, r, s, in, n);
 }
 
+template <bool kInPlace>
 __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
-  const uint64_t wave_base = (uint64_t)blockIdx.x * 64;
-  const uint64_t L = wave_base + lane;
+  const uint64_t L = (uint64_t)blockIdx.x * 64 + lane;
   EvState s = {};
   s.status = kDone;
   bool busy = false;
   bool drained = false;
   uint32_t req = 0;
   uint64_t ev = 0;
+  uint64_t slot = L;
   uint32_t since = 0;
   while (true) {
-    const uint64_t idle = __ballot(!busy);
-    const uint32_t n_idle = __popcll(idle);
-    if (!drained && n_idle > 0 && (n_idle == 64 || (since >= A.period && n_idle >= A.threshold))) {
-      since = 0;
-      const uint32_t leader = __ffsll((unsigned long long)idle) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(A.next, (unsigned long long)n_idle);
-      base = __shfl(base, leader);
-      if (base + n_idle >= A.total) drained = true;
-      if (!busy) {
-        const uint64_t w = base + __popcll(idle & ((1ull << lane) - 1));
-        if (w < A.total) {
-          const uint32_t sg = find_segment(A.segs, A.n_segs, w);
-          req = A.segs[sg].req;
-          ev = A.segs[sg].lo + (w - A.segs[sg].start);
-          const ReqDev& R = A.reqs[req];
-          const double ecm = R.ecm ? R.ecm[ev] : R.ecm0;
-          const double tcut = R.tcut ? R.tcut[ev] : R.tcut0;
-          start_from_record(s, R.out, ev, A.slots, L, make_keyed(R.seed, R.first + ev), ecm, tcut,
-                            (int)R.out.cap);
-          busy = true;
-        }
-      }
+    if (refill<(kInPlace ? 16u : 1u)>(A, busy, 64, lane, since, drained, req, ev)) {
+      slot = kInPlace ? ev : L;
+      start_event<kInPlace>(s, A, A.reqs[req], ev, slot);
+      busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle(sh, s, busy, A.slots, wave_base, lane);
-    if (busy) {
-      if (s.status != kRunning) {
-        const ReqDev& R = A.reqs[req];
-        const Records& o = R.out;
-        for (int a = 0; a < s.n; ++a) {
-          const uint64_t from = (uint64_t)a * A.slots.stride + L;
-          const uint64_t to = (uint64_t)a * o.stride + ev;
-          o.E[to] = A.slots.E[from];
-          o.x[to] = A.slots.x[from];
-          o.y[to] = A.slots.y[from];
-          o.z[to] = A.slots.z[from];
-          o.pid[to] = A.slots.pid[from];
-          o.col[to] = A.slots.col[from];
-          o.acol[to] = A.slots.acol[from];
-        }
-        write_state(s, R.sum, ev);
-        busy = false;
-      }
+    flat_cycle(sh, s, busy, A.slots, slot, lane);
+    if (busy && s.status != kRunning) {
+      finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
+      busy = false;
     }
     __syncthreads();
     ++since;
@@ -340,14 +341,10 @@ uint32_t persistent_lanes(const vsh_ctx* ctx) {
   return waves * 64;
 }
 
-static uint32_t lanes_for_budget(uint32_t n_cu, uint32_t waves_per_cu) {
-  return std::max<uint32_t>(1, waves_per_cu) * n_cu * 64;
-}
-
 uint64_t slots_bytes(uint64_t lanes, uint32_t cap) { return lanes * cap * (4 * 8 + 1 + 4 * 2) + 9 * 256; }
 
-uint64_t request_out_bytes(uint64_t n, uint32_t cap) {
-  return n * cap * (4 * 8 + 1 + 2 * 2) + n * (kNSumD * 8 + kNSumI * 4 + 8) + 2 * n * 8 + 16 * 256 +
+uint64_t request_out_bytes(uint64_t n, uint32_t cap, bool partners) {
+  return n * cap * (4 * 8 + 1 + 2 * 2 + (partners ? 2 * 2 : 0)) + n * (kNSumD * 8 + kNSumI * 4 + 8) + 2 * n * 8 + 16 * 256 +
          kHistDoubles * 8;
 }
 
@@ -376,7 +373,7 @@ Records carve_slots(Carver& c, uint64_t lanes, uint32_t cap) {
   return r;
 }
 
-ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap) {
+ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap, bool partners) {
   ReqBuffers b;
   const uint64_t m = n * cap;
   b.out.E = (double*)c.take(m * 8);
@@ -386,8 +383,8 @@ ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap) {
   b.out.pid = (int8_t*)c.take(m);
   b.out.col = (uint16_t*)c.take(m * 2);
   b.out.acol = (uint16_t*)c.take(m * 2);
-  b.out.cpart = nullptr;
-  b.out.apart = nullptr;
+  b.out.cpart = partners ? (uint16_t*)c.take(m * 2) : nullptr;
+  b.out.apart = partners ? (uint16_t*)c.take(m * 2) : nullptr;
   b.out.stride = n;
   b.out.cap = cap;
   b.sum.d = (double*)c.take(kNSumD * n * 8);
@@ -402,16 +399,16 @@ ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap) {
 
 Scratch carve_scratch(Carver& c, uint64_t n, uint32_t cap) { return carve_obs_scratch(c.p, n, cap); }
 
-uint64_t batch_bytes(uint64_t lanes, uint64_t n, uint32_t cap) {
-  return slots_bytes(lanes, cap) + request_out_bytes(n, cap) + obs_scratch_bytes(n, cap) + 4096 +
+// A batch is one request, showered in place in its output records.
+uint64_t batch_bytes(uint64_t n, uint32_t cap) {
+  return request_out_bytes(n, cap, true) + obs_scratch_bytes(n, cap) + 4096 +
          sizeof(ReqDev) + sizeof(Segment) + 1024;
 }
 
-BatchLayout carve_batch(void* base, uint64_t lanes, uint64_t n, uint32_t cap) {
+BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap) {
   Carver c(base);
   BatchLayout L;
-  L.slots = carve_slots(c, lanes, cap);
-  L.buf = carve_request(c, n, cap);
+  L.buf = carve_request(c, n, cap, true);
   L.sc = carve_scratch(c, n, cap);
   L.counter = (unsigned long long*)c.take(256);
   L.reqs = (ReqDev*)c.take(sizeof(ReqDev));
@@ -420,18 +417,24 @@ BatchLayout carve_batch(void* base, uint64_t lanes, uint64_t n, uint32_t cap) {
   return L;
 }
 
-const void* persistent_kernel(uint32_t mapping) {
-  return mapping == kMapFlat ? (const void*)k_shower_flat : (const void*)k_shower_persistent;
+const void* persistent_kernel(uint32_t mapping, bool in_place) {
+  if (mapping == kMapFlat) return in_place ? (const void*)k_shower_flat<true> : (const void*)k_shower_flat<false>;
+  return in_place ? (const void*)k_shower_persistent<true> : (const void*)k_shower_persistent<false>;
 }
 
 uint32_t persistent_block(uint32_t mapping, uint32_t block) { return mapping == kMapFlat ? 64u : block; }
 
-void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uint32_t mapping, hipStream_t st) {
+void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uint32_t mapping, bool in_place,
+                       hipStream_t st) {
   block = persistent_block(mapping, block);
-  if (mapping == kMapFlat)
-    hipLaunchKernelGGL(k_shower_flat, dim3((uint32_t)(lanes / block)), dim3(block), 0, st, A);
-  else
-    hipLaunchKernelGGL(k_shower_persistent, dim3((uint32_t)(lanes / block)), dim3(block), 0, st, A);
+  const dim3 grid((uint32_t)(lanes / block));
+  if (mapping == kMapFlat) {
+    if (in_place) hipLaunchKernelGGL(k_shower_flat<true>, grid, dim3(block), 0, st, A);
+    else hipLaunchKernelGGL(k_shower_flat<false>, grid, dim3(block), 0, st, A);
+  } else {
+    if (in_place) hipLaunchKernelGGL(k_shower_persistent<true>, grid, dim3(block), 0, st, A);
+    else hipLaunchKernelGGL(k_shower_persistent<false>, grid, dim3(block), 0, st, A);
+  }
 }
 
 void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, unsigned long long* counter,
@@ -499,7 +502,7 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   GCHK(add_kernel((const void*)k_me, dim3((uint32_t)((n + 255) / 256)), dim3(256), a_me));
   GCHK(add_event(1));
   void* a_pers[] = {&g.args};
-  GCHK(add_kernel(persistent_kernel(g.mapping), dim3((uint32_t)(lanes / block)), dim3(block), a_pers));
+  GCHK(add_kernel(persistent_kernel(g.mapping, true), dim3((uint32_t)(lanes / block)), dim3(block), a_pers));
   GCHK(add_event(2));
   g.nb = L.buf.out.cap + 1;
   g.cap = L.buf.out.cap;
@@ -559,14 +562,14 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
   const uint64_t lanes = persistent_lanes(ctx);
   const uint32_t mapping = ctx->tuned.mapping;
   const uint32_t block = persistent_block(mapping, ctx->tuned.pers_block);
-  BatchLayout L = carve_batch(base, lanes, n, cap);
+  BatchLayout L = carve_batch(base, n, cap);
   if (out_layout) *out_layout = L;
   ReqDev d;
   fill_request_desc(d, L.buf, req, first_idx, ecm_dev, tcut_dev);
   Segment sg{0, 0, 0, n, 0};
   hipError_t err;
   PersistArgs A;
-  A.slots = L.slots;
+  A.slots = L.buf.out;  // in place
   A.reqs = L.reqs;
   A.segs = L.segs;
   A.n_segs = 1;
@@ -610,7 +613,7 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
     launch_setup(L.reqs, d, L.segs, sg, L.counter, st);
     launch_me(L.buf.out, L.buf.sum, in, (uint32_t)n, st);
     if (tev) (void)hipEventRecord(tev[1], st);
-    launch_persistent(A, lanes, block, mapping, st);
+    launch_persistent(A, lanes, block, mapping, true, st);
     if (tev) (void)hipEventRecord(tev[2], st);
     launch_obs(L.buf.out, L.buf.sum, in, L.sc, (uint32_t)n, hist, st);
     if (tev) (void)hipEventRecord(tev[3], st);
@@ -621,21 +624,16 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
 }
 
 uint64_t persistent_workspace_bytes_ctx(const vsh_ctx* ctx, const vsh_request* req) {
-  return batch_bytes(persistent_lanes(ctx), req->n_events, req->max_partons);
+  return batch_bytes(req->n_events, req->max_partons);
 }
 
 uint64_t persistent_workspace_bytes(const vsh_request* req) {
-  // independent of the context: sized for the largest tuned grid (16 waves per CU on 256 CUs)
-  return batch_bytes(lanes_for_budget(256, 16), req->n_events, req->max_partons);
+  return batch_bytes(req->n_events, req->max_partons);
 }
 
 vsh_status persistent_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void* ws, double* dev_hist,
                            double* dev_sum_d, int32_t* dev_sum_i, uint64_t* dev_hash) {
   const uint64_t n = req->n_events;
-  if (persistent_lanes(ctx) > lanes_for_budget(256, 16)) {
-    set_error(ctx, "persistent grid larger than the workspace allows");
-    return VSH_E_INTERNAL;
-  }
   BatchLayout L;
   vsh_status rc = run_batch(ctx, req, 0, n, st, ws, req->ecm_per_event, req->tcut_per_event, dev_hist, true, &L);
   if (rc) return rc;
@@ -662,12 +660,12 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
   // chunk so that a batch fits the budget (half of it when records are returned)
   uint64_t budget = ctx->budget;
   if (req->flags & VSH_RECORDS) budget /= 2;
-  const uint64_t fixed = slots_bytes(lanes, cap) + 64 * 1024;
-  if (budget <= fixed + request_out_bytes(64, cap) + obs_scratch_bytes(64, cap)) {
+  const uint64_t fixed = 64 * 1024;
+  if (budget <= fixed + request_out_bytes(64, cap, true) + obs_scratch_bytes(64, cap)) {
     set_error(ctx, "memory budget too small for the persistent form at %u partons", cap);
     return VSH_E_NOMEM;
   }
-  const uint64_t per_event = request_out_bytes(1, cap) + 64 + (uint64_t)cap * 32;
+  const uint64_t per_event = request_out_bytes(1, cap, true) + 64 + (uint64_t)cap * 32;
   uint64_t chunk = std::min<uint64_t>(req->n_events, (budget - fixed) / per_event);
   chunk = std::min<uint64_t>(chunk, 1ull << 27);
   ResultBox* box = new_result(req->n_events, req->flags & VSH_SUMMARY);
@@ -679,12 +677,12 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
   float t_me = 0, t_sh = 0, t_obs = 0;
   for (uint64_t a = 0; a < req->n_events; a += chunk) {
     const uint64_t n = std::min(chunk, req->n_events - a);
-    vsh_status rc = ctx->arena.reserve(ctx, batch_bytes(lanes, n, cap));
+    vsh_status rc = ctx->arena.reserve(ctx, batch_bytes(n, cap));
     if (rc) {
       delete box;
       return rc;
     }
-    BatchLayout L = carve_batch(ctx->arena.ptr, lanes, n, cap);
+    BatchLayout L = carve_batch(ctx->arena.ptr, n, cap);
     hipError_t err;
     const double* ecm_dev = nullptr;
     const double* tcut_dev = nullptr;
@@ -713,7 +711,7 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     in.seed = req->seed;
     in.first = req->first_event + a;
     launch_me(L.buf.out, L.buf.sum, in, (uint32_t)n, st);
-    A.slots = L.slots;
+    A.slots = L.buf.out;  // in place
     A.reqs = L.reqs;
     A.segs = L.segs;
     A.n_segs = 1;
@@ -722,7 +720,7 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     A.threshold = ctx->tuned.refill_threshold;
     A.period = ctx->tuned.refill_period;
     (void)hipEventRecord(ctx->ev[1], st);
-    launch_persistent(A, lanes, ctx->tuned.pers_block, ctx->tuned.mapping, st);
+    launch_persistent(A, lanes, ctx->tuned.pers_block, ctx->tuned.mapping, true, st);
     (void)hipEventRecord(ctx->ev[2], st);
     launch_obs(L.buf.out, L.buf.sum, in, L.sc, (uint32_t)n, L.buf.hist, st);
     (void)hipEventRecord(ctx->ev[3], st);

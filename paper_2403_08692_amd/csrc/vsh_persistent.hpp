@@ -11,7 +11,7 @@ namespace vsh {
 // one request as the persistent kernel sees it: where its events' outputs
 // go and how to name its events
 struct ReqDev {
-  Records out;          // final partons [cap][count] (partner links unused)
+  Records out;          // final partons [cap][count]; partner links only when showered in place
   Summary sum;          // [field][count]
   const double* ecm;    // per-event sqrt(s) [count] or null -> ecm0
   const double* tcut;   // per-event t_C [count] or null -> tcut0
@@ -28,7 +28,8 @@ struct Segment {
 };
 
 struct PersistArgs {
-  Records slots;                  // working records, one slot per lane [cap][lanes]
+  Records slots;                  // working records: one slot per lane [cap][lanes], or the
+                                  // single request's output records when showered in place
   const ReqDev* reqs;
   const Segment* segs;
   uint32_t n_segs;
@@ -52,7 +53,6 @@ struct Carver {
 };
 
 struct BatchLayout {
-  Records slots;
   ReqBuffers buf;
   Scratch sc;
   unsigned long long* counter;
@@ -87,13 +87,14 @@ struct BatchGraph {
 };
 
 uint64_t slots_bytes(uint64_t lanes, uint32_t cap);
-uint64_t request_out_bytes(uint64_t n, uint32_t cap);
+uint64_t request_out_bytes(uint64_t n, uint32_t cap, bool partners);
 uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap);
 Records carve_slots(Carver& c, uint64_t lanes, uint32_t cap);
-ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap);
+ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap, bool partners);
 Scratch carve_scratch(Carver& c, uint64_t n, uint32_t cap);
 enum : uint32_t { kMapLane = 0, kMapFlat = 1 };
-void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uint32_t mapping, hipStream_t st);
+void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uint32_t mapping, bool in_place,
+                       hipStream_t st);
 void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, unsigned long long* counter,
                   hipStream_t st);
 void launch_zero(double* p, uint32_t n, hipStream_t st);

@@ -142,7 +142,7 @@ struct ServeState {
   uint64_t scratch_bytes = 0;
 };
 
-static uint64_t request_bytes(const vsh_request& r) { return request_out_bytes(r.n_events, r.max_partons); }
+static uint64_t request_bytes(const vsh_request& r) { return request_out_bytes(r.n_events, r.max_partons, false); }
 
 static void finish_request(ServeState& S, ServeReq& r, int state) {
   if (r.pool_bytes) {
@@ -175,7 +175,7 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     r.pool_off = off;
     r.pool_bytes = bytes;
     Carver c(S.pool.base + off);
-    r.buf = carve_request(c, r.req.n_events, r.req.max_partons);
+    r.buf = carve_request(c, r.req.n_events, r.req.max_partons, false);
     const uint64_t n = r.req.n_events;
     if (!r.ecm.empty()) (void)hipMemcpyAsync(r.buf.ecm, r.ecm.data(), n * 8, hipMemcpyHostToDevice, S.drain);
     if (!r.tcut.empty()) (void)hipMemcpyAsync(r.buf.tcut, r.tcut.data(), n * 8, hipMemcpyHostToDevice, S.drain);
@@ -286,7 +286,7 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
   A.next = counter;
   A.period = tn.refill_period;
   A.pad = 0;
-  launch_persistent(A, lanes, tn.pers_block, tn.mapping, E->stream);
+  launch_persistent(A, lanes, tn.pers_block, tn.mapping, false, E->stream);
   (void)hipEventRecord(E->done, E->stream);
   E->busy = true;
   return true;

@@ -292,8 +292,27 @@ __device__ __forceinline__ void init_state(EvState& s, const Records& r, uint64_
   s.next_col = mc + 1;
 }
 
+// State of an event that starts from its two LO partons (colour line 1).
+__device__ __forceinline__ void lo_state(EvState& s, const Keyed& key, double ecm, double tcut, int cap) {
+  s.key = key;
+  s.tcut = tcut;
+  s.ltc = log_fast(tcut);
+  s.asmax = alpha_s_of_log(s.ltc);
+  s.cfac = s.asmax / (2.0 * kPi);
+  s.lt = log_fast(ecm * ecm);
+  s.hash = kFnvOffset;
+  s.cycle = 0;
+  s.trials = 0;
+  s.ends = 0;
+  s.n = 2;
+  s.n_emit = 0;
+  s.status = kRunning;
+  s.next_col = 2;
+  s.cap = cap;
+}
+
 // Start the event whose LO partons the matrix-element pass left in slots 0
-// and 1 of `from` (column `ev`) in working slot e of r.
+// and 1 of `from` (column `ev`, no partner links there) in working slot e of r.
 __device__ __forceinline__ void start_from_record(EvState& s, const Records& from, uint64_t ev, const Records& r,
                                                   uint64_t e, const Keyed& key, double ecm, double tcut, int cap) {
   for (uint32_t a = 0; a < 2; ++a) {
@@ -310,21 +329,7 @@ __device__ __forceinline__ void start_from_record(EvState& s, const Records& fro
   r.apart[e] = kNoPartner;
   r.cpart[r.stride + e] = kNoPartner;
   r.apart[r.stride + e] = 0;
-  s.key = key;
-  s.tcut = tcut;
-  s.ltc = log_fast(tcut);
-  s.asmax = alpha_s_of_log(s.ltc);
-  s.cfac = s.asmax / (2.0 * kPi);
-  s.lt = log_fast(ecm * ecm);
-  s.hash = kFnvOffset;
-  s.cycle = 0;
-  s.trials = 0;
-  s.ends = 0;
-  s.n = 2;
-  s.n_emit = 0;
-  s.status = kRunning;
-  s.next_col = 2;
-  s.cap = cap;
+  lo_state(s, key, ecm, tcut, cap);
 }
 
 __device__ __forceinline__ void write_state(const EvState& s, const Summary& sm, uint64_t e) {

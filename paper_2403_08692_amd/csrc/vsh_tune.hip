@@ -77,15 +77,11 @@ static vsh_status autotune_persistent(vsh_ctx* ctx, const vsh_request* req) {
   const uint64_t m = std::min<uint64_t>(req->n_events, 1ull << 18);
   const uint32_t cap = req->max_partons;
   const Tuned keep = ctx->tuned;
-  Tuned big = keep;
-  big.pers_waves_per_cu = 16;
-  ctx->tuned = big;
-  const uint64_t need = batch_bytes(persistent_lanes(ctx), m, cap);
-  ctx->tuned = keep;
+  const uint64_t need = batch_bytes(m, cap);
   vsh_status rc = ctx->arena.reserve(ctx, need);
   if (rc) return rc;
   void* base = ctx->arena.ptr;
-  BatchLayout L = carve_batch(base, (uint64_t)16 * ctx->n_cu * 64, m, cap);
+  BatchLayout L = carve_batch(base, m, cap);
   hipError_t err;
   const double* ecm_dev = nullptr;
   const double* tcut_dev = nullptr;
@@ -108,7 +104,7 @@ static vsh_status autotune_persistent(vsh_ctx* ctx, const vsh_request* req) {
   std::vector<Tuned> cands;
   for (uint32_t mapping : {kMapFlat, kMapLane})
     for (uint32_t waves : {4u, 8u, 16u})
-      for (uint32_t thr : {1u, 16u})
+      for (uint32_t thr : {16u, 32u})
         for (uint32_t per : {1u, 4u}) {
           Tuned t = keep;
           t.mapping = mapping;
