@@ -125,10 +125,10 @@ def cpu_baseline(w, serial_events=160_000, per_proc=40_000):
             "merged_histograms_equal_serial": same, "host_cpu": model or platform.processor()}
 
 
-def traffic_from_profile(kernel_src_hash):
+def traffic_from_profile(kernel, kernel_src_hash):
     """HBM bytes per launch of the shower kernel from the committed counter
     summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_shower_plain_lep.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_lep.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
@@ -139,12 +139,24 @@ def traffic_from_profile(kernel_src_hash):
 
 
 def kernel_source_hash():
+    """sha256 over every HIP source of the library: a committed counter
+    summary counts only while the kernels are the ones it measured."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("vsh_device.hpp", "vsh_kernels.hpp", "vsh_kernels.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2403_08692_amd", "csrc", f), "rb").read())
+    d = os.path.join(ROOT, "paper_2403_08692_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()
+
+
+def shower_kernel_name(form, tuning):
+    """Name of the shower kernel that the tuned form launches."""
+    if form == "persistent":
+        return "k_shower_flat" if tuning["mapping"] == 1 else "k_shower_persistent"
+    return "k_shower_plain_flat" if tuning["plain_mapping"] == 1 else "k_shower_plain"
 
 
 def time_form(ctx, P, torch, w, n, form, steps, ecm_arr=None, tcut_arr=None):
@@ -247,7 +259,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", choices=["plain", "persistent"], default="plain")
+    ap.add_argument("--form", choices=["plain", "persistent"], default="persistent",
+                    help="persistent = the batched form (refill, in-place evolution); plain = one lane or "
+                         "one wave's lanes per event from start to cutoff")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--events", type=int, default=0, help="override the batch size (testing only)")
     ap.add_argument("--quick", action="store_true", help="main LEP line only (no batched/stress/serving legs)")
@@ -313,7 +327,8 @@ def main():
     shower_ms = float(np.mean(stages[:, 1]))
     achieved = ops / (shower_ms * 1e-3) / 1e12
     h = hist.cpu().numpy().reshape(P.NOBS, P.NHCOL, 3)
-    traffic = traffic_from_profile(kernel_source_hash())
+    kernel = shower_kernel_name(args.form, tuning)
+    traffic = traffic_from_profile(kernel, kernel_source_hash())
 
     line = {
         "metric": METRIC,
@@ -333,7 +348,7 @@ def main():
                    "step": "ME + shower + observables + histograms (vsh_generate_into)"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-                     "kernel": "k_shower_plain" if args.form == "plain" else "k_shower_persistent",
+                     "kernel": kernel,
                      "kernel_ms": shower_ms, "ops_per_launch": ops,
                      "ops_per_event": ops / n},
         "stages_ms": {"me": float(np.mean(stages[:, 0])), "shower": shower_ms,
@@ -349,9 +364,11 @@ def main():
         line["gpu_over_serial_oracle"] = value / cpu["serial_value"]
     if not args.quick:
         extra = {}
-        # LEP through the batched (persistent) form, autotuned on a sample
-        tuned = ctx.autotune(1 << 18, seed=w.seed, ecm=w.ecm, t_cut=w.tcut, max_partons=w.cap)
-        extra["lep_persistent"] = dict(time_form(ctx, P, torch, w, n, "persistent", 10), tuning=tuned)
+        # LEP through the other form, autotuned on a sample
+        other = "plain" if args.form == "persistent" else "persistent"
+        tuned = ctx.autotune(1 << 18, seed=w.seed, ecm=w.ecm, t_cut=w.tcut, max_partons=w.cap,
+                             persistent=other == "persistent")
+        extra[f"lep_{other}"] = dict(time_form(ctx, P, torch, w, n, other, 10), tuning=tuned)
         # mixed energies and cutoffs, 10^7 events in one persistent launch (and the plain form)
         m = workloads.MIXED
         e_arr, t_arr = m.per_event()

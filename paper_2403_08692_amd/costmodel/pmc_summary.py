@@ -1,10 +1,13 @@
 """Summarise rocprofv3 output for one kernel: the kernel-trace statistics
 (calls, average duration) and, from counter-collection runs, the per-dispatch
 average of each counter.  Writes a short text summary (and optionally the
-HBM-traffic JSON the benchmark reads).
+HBM-traffic JSON the benchmark reads).  With --last N only the last N
+dispatches of the kernel count (a benchmark's timed steps, after the
+autotuner's trial launches on a smaller sample).
 
-  python -m paper_2403_08692_amd.costmodel.pmc_summary --kernel k_shower_plain \
-      --stats DIR/..._kernel_stats.csv --pmc DIR1/..._counter_collection.csv ...
+  python -m paper_2403_08692_amd.costmodel.pmc_summary --kernel k_shower_flat \
+      --stats DIR/..._kernel_stats.csv --trace DIR/..._kernel_trace.csv --last 10 \
+      --pmc DIR1/..._counter_collection.csv ...
 """
 import argparse
 import csv
@@ -30,8 +33,19 @@ def kernel_stats(path, kernel):
     return out
 
 
-def counters(path, kernel):
-    """{counter: [value per dispatch]} for dispatches of kernels matching `kernel`."""
+def trace_durations(path, kernel):
+    """[(dispatch id, ns)] of the dispatches of kernels matching `kernel`, in dispatch order."""
+    out = []
+    for row in read_csv(path):
+        name = row.get("Kernel_Name") or row.get("Kernel-Name") or ""
+        if kernel in name:
+            out.append((int(row["Dispatch_Id"]), int(row["End_Timestamp"]) - int(row["Start_Timestamp"])))
+    return sorted(out)
+
+
+def counters(path, kernel, last=0):
+    """{counter: [value per dispatch]} for dispatches of kernels matching `kernel`
+    (the last `last` of them if last > 0)."""
     per = {}
     for row in read_csv(path):
         name = row.get("Kernel_Name") or row.get("Kernel-Name") or ""
@@ -42,13 +56,21 @@ def counters(path, kernel):
         disp = row.get("Dispatch_Id") or row.get("Correlation_Id")
         per.setdefault(c, {}).setdefault(disp, 0.0)
         per[c][disp] += v
-    return {c: list(d.values()) for c, d in per.items()}
+    out = {}
+    for c, d in per.items():
+        keys = sorted(d, key=lambda k: int(k))
+        if last > 0:
+            keys = keys[-last:]
+        out[c] = [d[k] for k in keys]
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--kernel", required=True)
     ap.add_argument("--stats", nargs="*", default=[])
+    ap.add_argument("--trace", nargs="*", default=[], help="kernel_trace CSVs (per-dispatch durations)")
+    ap.add_argument("--last", type=int, default=0, help="count only the last N dispatches of the kernel")
     ap.add_argument("--pmc", nargs="*", default=[])
     ap.add_argument("--calib", nargs="*", default=[], help="counter CSVs of the copy calibration")
     ap.add_argument("--calib-bytes", type=float, default=float(2 << 30))
@@ -61,10 +83,18 @@ def main():
             for k in kernel_stats(p, args.kernel):
                 lines.append(f"kernel-trace {os.path.basename(p)}: {k['name'][:60]} calls={k['calls']} "
                              f"avg={k['avg_ns'] / 1e6:.4f} ms total={k['total_ns'] / 1e6:.3f} ms ({k['pct']:.1f}%)")
+    for s in args.trace:
+        for p in glob.glob(s):
+            d = trace_durations(p, args.kernel)
+            sel = d[-args.last:] if args.last > 0 else d
+            if sel:
+                ms = [ns / 1e6 for _, ns in sel]
+                lines.append(f"kernel-trace {os.path.basename(p)}: last {len(sel)} of {len(d)} dispatches "
+                             f"avg={sum(ms) / len(ms):.4f} ms min={min(ms):.4f} max={max(ms):.4f}")
     avg = {}
     for s in args.pmc:
         for p in glob.glob(s):
-            for c, vals in counters(p, args.kernel).items():
+            for c, vals in counters(p, args.kernel, args.last).items():
                 avg[c] = sum(vals) / len(vals)
                 lines.append(f"pmc {c}: {avg[c]:.6g} per dispatch ({len(vals)} dispatches)")
     scale = {}
