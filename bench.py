@@ -60,7 +60,7 @@ def algorithmic_ops(n_events, ends, trials, cycles, emissions):
     per_g_end = per_end_setup + 3 * c["philox"] + 6 * c["unit"] + 2 * c["log_fast"] + 2 * c["div"] + 12
     per_winner = 2 * c["exp"] + c["philox"] + 2 * c["unit"] + 6 * c["div"] + 25
     per_emission = c["philox"] + c["unit"] + c["sincos"] + 3 * c["sqrt"] + 8 * c["div"] + 140
-    per_event = 2 * c["philox"] + 3 * c["unit"] + c["sincos"] + c["sqrt"] + 2 * c["div"] + 60 + 3 * c["log"]
+    per_event = 2 * c["philox"] + 3 * c["unit"] + c["sincos"] + c["sqrt"] + 3 * c["div"] + 60 + 2 * c["log_fast"]
     return (q_ends * per_q_end + g_ends * per_g_end + winners * per_winner +
             emissions * per_emission + n_events * per_event)
 

@@ -15,6 +15,20 @@
  * Section 3.1.  Compiled with -ffp-contract=off and no fast-math.
  *
  * Momenta are stored as (E, px, py, pz) in GeV; scales t in GeV^2.
+ *
+ * Pins (tests/test_oracle_*.py check each function against something other
+ * than itself): Philox against the published known-answer vectors; alpha_s
+ * against closed-form values and the one-loop running; the kernels against
+ * the DGLAP collinear limits, their overestimates, integrals and z inverses
+ * by quadrature; the matrix element against sigma_LO, the R ratio and the
+ * angular shape; the dipole map against its invariants; the first emission
+ * and the no-emission probability against the Sudakov factor by quadrature;
+ * thrust against brute force over every hemisphere split; C against the
+ * eigenvalues of the momentum tensor; Durham against three-parton closed
+ * forms and four-parton brute force; hemisphere masses against brute force.
+ * Whole showered events beyond the first emission have no external
+ * reference: parity unpinned there (colour, flavour and momentum
+ * conservation are checked, the distributions are not).
  */
 #ifndef VSH_ORACLE_H
 #define VSH_ORACLE_H

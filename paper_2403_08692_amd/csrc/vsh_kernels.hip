@@ -460,10 +460,18 @@ void launch_shower_plain(const Records& r, const Summary& s, const EventInputs& 
   else hipLaunchKernelGGL(k_shower_plain<2>, g, b, 0, st, r, s, in, n);
 }
 
+// Parton slots of Durham scratch per thread of the one-thread-per-event
+// pass: it only sees events below the wave threshold when the wave pass
+// runs, else every event up to cap.
+static uint32_t thread_slots(uint32_t cap) {
+  return (cap <= kObsWaveMaxCap && kObsWaveThreshold <= cap) ? kObsWaveThreshold - 1 : cap;
+}
+
 // at most 2^24 parton slots of scratch (1.1 GB) and 2^18 threads (about
 // the resident threads of the pass), at most n
 uint64_t obs_threads(uint64_t n, uint32_t cap) {
-  const uint64_t most = std::max<uint64_t>(256, std::min<uint64_t>(1ull << 18, ((1ull << 24) / cap) / 256 * 256));
+  const uint64_t most =
+      std::max<uint64_t>(256, std::min<uint64_t>(1ull << 18, ((1ull << 24) / thread_slots(cap)) / 256 * 256));
   const uint64_t t = ((n + 255) / 256) * 256;
   return t < most ? t : most;
 }
@@ -471,14 +479,14 @@ uint64_t obs_threads(uint64_t n, uint32_t cap) {
 static inline uint64_t al256(uint64_t v) { return (v + 255) / 256 * 256; }
 
 uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap) {
-  const uint64_t m = obs_threads(n, cap) * cap;
+  const uint64_t m = obs_threads(n, cap) * thread_slots(cap);
   return 8 * al256(m * 8) + al256(m * 2) + al256(m) + al256(n * 4) + al256((cap + 2) * 4) + 256;
 }
 
 Scratch carve_obs_scratch(char*& p, uint64_t n, uint32_t cap) {
   Scratch s;
   s.stride = obs_threads(n, cap);
-  const uint64_t m = s.stride * cap;
+  const uint64_t m = s.stride * thread_slots(cap);
   auto take = [&](uint64_t bytes) {
     char* q = p;
     p += al256(bytes);

@@ -47,6 +47,24 @@ def test_energies_and_caps(ctx, oracle, ecm, tcut, cap):
     parity.assert_parity(rep)
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_large_events_both_observable_passes(ctx, oracle, persistent):
+    # 500 GeV with t_C = 0.03: sizes from about 10 to 80 partons, so both
+    # observable passes (thread per event, wave per event) and their split
+    # of the sorted events are exercised
+    g, o, rep = _run(ctx, oracle, 500, 5, 500.0, 0.03, 256, persistent=persistent)
+    parity.assert_parity(rep)
+    n = o["sum_i"][:, 0]
+    assert (n < 12).any() and (n >= 32).any()
+
+
+def test_overflow_wave_pass(ctx, oracle):
+    # cap 40: overflowing events stop at 40 partons, on the wave pass
+    g, o, rep = _run(ctx, oracle, 300, 6, 500.0, 0.03, 40)
+    parity.assert_parity(rep)
+    assert g["n_overflow"] > 0
+
+
 def test_overflow_small_cap(ctx, oracle):
     g, o, rep = _run(ctx, oracle, 800, 2, 91.2, 1.0, 4)
     assert rep["frac"] == 1.0

@@ -170,3 +170,54 @@ def test_split_ranges_reproduce_the_serial_run(oracle):
     np.testing.assert_array_equal(np.concatenate([p["sum_d"] for p in parts]), whole["sum_d"])
     np.testing.assert_array_equal(np.concatenate([p["hash"] for p in parts]), whole["hash"])
     np.testing.assert_allclose(sum(p["hist"] for p in parts), whole["hist"], rtol=1e-13)
+
+
+def rambo(rng, n, ecm):
+    """n massless momenta with total (ecm, 0, 0, 0), flat in phase space
+    (Kleiss, Stirling and Ellis, the RAMBO construction)."""
+    c = rng.uniform(-1, 1, n)
+    phi = rng.uniform(0, 2 * np.pi, n)
+    q0 = -np.log(rng.uniform(0, 1, n) * rng.uniform(0, 1, n))
+    s = np.sqrt(1 - c * c)
+    q = np.stack([q0, q0 * s * np.cos(phi), q0 * s * np.sin(phi), q0 * c], axis=1)
+    Q = q.sum(axis=0)
+    M = np.sqrt(Q[0] ** 2 - Q[1:] @ Q[1:])
+    b = -Q[1:] / M
+    x = ecm / M
+    gam = Q[0] / M
+    a = 1 / (1 + gam)
+    bq = q[:, 1:] @ b
+    p = np.empty_like(q)
+    p[:, 0] = x * (gam * q[:, 0] + bq)
+    p[:, 1:] = x * (q[:, 1:] + b[None, :] * q[:, :1] + a * bq[:, None] * b[None, :])
+    return p
+
+
+def durham_y(pa, pb, s):
+    """2 min(E_a, E_b)^2 (1 - cos theta_ab) / s, the Durham measure."""
+    ua, ub = pa[1:], pb[1:]
+    cos = ua @ ub / np.sqrt((ua @ ua) * (ub @ ub))
+    return 2 * min(pa[0], pb[0]) ** 2 * (1 - cos) / s
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_durham_four_partons_brute_force(oracle, seed):
+    # four partons: y34 is the smallest pair measure; merging that pair by
+    # adding four-momenta (E-scheme) leaves three jets whose smallest pair
+    # measure is y23
+    rng = np.random.default_rng(seed)
+    ecm = 91.2
+    s = ecm * ecm
+    for _ in range(100):
+        p = rambo(rng, 4, ecm)
+        assert abs(p[:, 0].sum() - ecm) < 1e-9 and np.abs(p[:, 1:].sum(axis=0)).max() < 1e-9
+        pairs = list(itertools.combinations(range(4), 2))
+        ys = [durham_y(p[a], p[b], s) for a, b in pairs]
+        k = int(np.argmin(ys))
+        a, b = pairs[k]
+        rest = [p[c] for c in range(4) if c not in (a, b)]
+        jets = [p[a] + p[b]] + rest
+        y23 = min(durham_y(jets[u], jets[v], s) for u, v in itertools.combinations(range(3), 2))
+        g23, g34 = oracle.durham(p, s)
+        assert g34 == pytest.approx(ys[k], rel=1e-11)
+        assert g23 == pytest.approx(y23, rel=1e-11)
