@@ -169,13 +169,21 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* start, uint32_t j) 
   return lo;
 }
 
-// One veto cycle of every busy event of this wave, the trials spread over the
-// lanes; each owner lane then finishes its own event's cycle.  The event of
-// the calling lane sits in column `slot` of `slots`.
-__device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy, const Records& slots,
-                                           uint64_t slot, uint32_t lane) {
-  // --- publish the busy events and the item ranges
-  const uint32_t mine = busy ? (uint32_t)s.n : 0u;
+// One veto cycle of every busy event of this wave whose last accepted
+// emission has been built, the trials spread over the lanes; each owner lane
+// then decides its own event's cycle.  An accepted emission stays pending
+// (the event makes no trials meanwhile) until at least a quarter of the busy
+// events have one, or all of them do; then the wave builds them together.
+// Deferring an emission changes nothing in the event: its random numbers are
+// keyed by the event's own cycle.  The event of the calling lane sits in
+// column `slot` of `slots`.
+constexpr uint32_t kEmitDiv = 4;
+
+__device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy, bool& pend, Pending& pd,
+                                           const Records& slots, uint64_t slot, uint32_t lane) {
+  const bool trial = busy && !pend;
+  // --- publish the events that make trials and the item ranges
+  const uint32_t mine = trial ? (uint32_t)s.n : 0u;
   uint32_t incl = mine;
   for (uint32_t d = 1; d < 64; d <<= 1) {
     const uint32_t t = __shfl_up(incl, d);
@@ -239,8 +247,8 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy
     }
     __syncthreads();
   }
-  // --- each owner finishes its cycle
-  if (busy) {
+  // --- each owner that made trials decides its cycle
+  if (trial) {
     s.trials += sh.trials[lane];
     s.ends += sh.ends[lane];
     const uint32_t bi = sh.best_idx[lane];
@@ -254,9 +262,16 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy
       end_limits(slots.load(w.i, slot), slots.load(w.k, slot), s.tcut, w.q2, w.zm, w.zp);
       w.L = log_fast((1.0 - w.zm) / (1.0 - w.zp));
     }
-    veto_finish(s, slots, slot, best, w);
-    if (s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
+    pend = veto_decide(s, best, w, pd);
   }
+  // --- pending emissions, built together
+  const uint32_t n_pend = __popcll(__ballot(pend));
+  const uint32_t n_busy = __popcll(__ballot(busy));
+  if (n_pend > 0 && kEmitDiv * n_pend >= n_busy && pend) {
+    emit(s, slots, slot, pd);
+    pend = false;
+  }
+  if (busy && !pend && s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
 }
 
 // Plain one-launch form with the flattened mapping: wave w owns events
@@ -269,11 +284,13 @@ __global__ void __launch_bounds__(64) k_shower_plain_flat(Records r, Summary sm,
   EvState s = {};
   s.status = kDone;
   bool busy = e < n;
+  bool pend = false;
+  Pending pd{};
   if (busy)
     init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e),
                sm.i[kSiN * sm.stride + e], (int)r.cap);
   while (__any(busy)) {
-    flat_cycle(sh, s, busy, r, e, lane);
+    flat_cycle(sh, s, busy, pend, pd, r, e, lane);
     if (busy && s.status != kRunning) {
       write_state(s, sm, e);
       busy = false;
@@ -297,6 +314,8 @@ __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
   s.status = kDone;
   bool busy = false;
   bool drained = false;
+  bool pend = false;
+  Pending pd{};
   uint32_t req = 0;
   uint64_t ev = 0;
   uint64_t slot = L;
@@ -308,7 +327,7 @@ __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
       busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle(sh, s, busy, A.slots, slot, lane);
+    flat_cycle(sh, s, busy, pend, pd, A.slots, slot, lane);
     if (busy && s.status != kRunning) {
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
       busy = false;
@@ -577,6 +596,7 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
   A.next = L.counter;
   A.threshold = ctx->tuned.refill_threshold;
   A.period = ctx->tuned.refill_period;
+  A.pad = 0;
   EventInputs in{};
   in.ecm = ecm_dev;
   in.tcut = tcut_dev;
@@ -719,6 +739,7 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     A.next = L.counter;
     A.threshold = ctx->tuned.refill_threshold;
     A.period = ctx->tuned.refill_period;
+    A.pad = 0;
     (void)hipEventRecord(ctx->ev[1], st);
     launch_persistent(A, lanes, ctx->tuned.pers_block, ctx->tuned.mapping, true, st);
     (void)hipEventRecord(ctx->ev[2], st);

@@ -282,10 +282,10 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
   A.segs = sd;
   A.n_segs = nseg;
   A.threshold = tn.refill_threshold;
+  A.pad = 0;
   A.total = total;
   A.next = counter;
   A.period = tn.refill_period;
-  A.pad = 0;
   launch_persistent(A, lanes, tn.pers_block, tn.mapping, false, E->stream);
   (void)hipEventRecord(E->done, E->stream);
   E->busy = true;

@@ -166,14 +166,22 @@ __device__ __forceinline__ void parton_trials(const TrialCtx& c, const Records& 
   if (k2 != kNoPartner) end_trials(c, i, k2, pid_i, pi, r.load(k2, e), best, w, trials, ends);
 }
 
-// The rest of one cycle once the winner is known: CheckCutoff, alpha_s,
-// AcceptOrVeto, GenerateEmission (App. C).  `best` is the winner's ln t.
-__device__ __forceinline__ void veto_finish(EvState& s, const Records& r, uint64_t e, double best,
-                                            const Winner& w) {
+// An accepted emission that has not been built yet: the winner's (i, k, K),
+// its t and z, and the cycle that drew it (keys the azimuth).
+struct Pending {
+  double t, z;
+  int i, k, K;
+  uint32_t cycle;
+};
+
+// The decision part of one cycle once the winner is known: CheckCutoff,
+// alpha_s, AcceptOrVeto (App. C).  `best` is the winner's ln t.  Returns true
+// for an accepted emission that fits the record, described in p.
+__device__ __forceinline__ bool veto_decide(EvState& s, double best, const Winner& w, Pending& p) {
   const uint32_t this_cycle = s.cycle++;
   if (w.i < 0) {  // no trial above the cutoff
     s.status = kDone;
-    return;
+    return false;
   }
   s.lt = best;  // the winner's scale bounds every later trial
   const double t = exp(best);
@@ -183,15 +191,24 @@ __device__ __forceinline__ void veto_finish(EvState& s, const Records& r, uint64
   const double uz = unit(a.x, a.y);
   const double z = w.K <= 10 ? 1.0 - (1.0 - w.zm) * exp(-uz * w.L) : w.zm + (w.zp - w.zm) * uz;
   const double y = t / (w.q2 * z * (1.0 - z));
-  if (!(y < 1.0)) return;
+  if (!(y < 1.0)) return false;
   const double prob =
       alpha_s_of_log(best) / s.asmax * kernel_value(w.K, z, y) * (1.0 - y) / kernel_over(w.K, z);
-  if (!(unit(a.z, a.w) < prob)) return;
+  if (!(unit(a.z, a.w) < prob)) return false;
   if (s.n == s.cap) {
     s.status = kOverflow;
-    return;
+    return false;
   }
-  // --- splitting: kinematics, colours, flavours, append parton j at slot n
+  p = Pending{t, z, w.i, w.k, w.K, this_cycle};
+  return true;
+}
+
+// GenerateEmission (App. C): kinematics, colours, flavours, and parton j
+// appended at slot n.
+__device__ __forceinline__ void emit(EvState& s, const Records& r, uint64_t e, const Pending& pe) {
+  const double t = pe.t, z = pe.z;
+  const uint32_t this_cycle = pe.cycle;
+  const Winner w{0.0, 0.0, 0.0, 0.0, pe.i, pe.k, pe.K};
   const U4 sd = s.key.draw(this_cycle, kPurposeSplit, 0);
   const double phi = 2.0 * kPi * unit(sd.x, sd.y);
   double sphi, cphi;
@@ -253,6 +270,14 @@ __device__ __forceinline__ void veto_finish(EvState& s, const Records& r, uint64
   s.hash = fnv_step(fnv_step(fnv_step(s.hash, (uint32_t)w.K), (uint32_t)i), (uint32_t)k);
   s.n += 1;
   s.n_emit += 1;
+}
+
+// The rest of one cycle once the winner is known: decision, then the
+// emission if accepted.
+__device__ __forceinline__ void veto_finish(EvState& s, const Records& r, uint64_t e, double best,
+                                            const Winner& w) {
+  Pending p;
+  if (veto_decide(s, best, w, p)) emit(s, r, e, p);
 }
 
 // One cycle of the veto algorithm for one event, all in this lane:
