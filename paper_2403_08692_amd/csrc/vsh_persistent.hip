@@ -140,24 +140,34 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
 // ---------------------------------------------------------------------------
 // Flattened mapping.  Same refill as above, but each veto cycle's trials of a
 // wave's 64 events are spread over its 64 lanes: the work items are the
-// partons of all busy events (event-major, parton order), taken 64 per
-// round; item (owner o, parton i) runs that parton's dipole ends.  Within a
-// round a segmented max over consecutive lanes of the same owner (earlier
-// lane wins ties, i.e. the lexicographically first trial as in the paper's
-// loop nest) leaves each owner's round best on its last lane, which folds it
-// into the owner's running best in LDS (earlier rounds win ties).  Each owner
-// then finishes its cycle in its own lane.
+// partons of all busy events, taken 64 per round; item (owner o, parton i)
+// runs that parton's dipole ends.  A gluon item (two ends, three Philox
+// blocks and two logs per end) costs about four quark items (one end, one
+// block, one log), so gluon and quark partons get rounds of their own: first
+// the gluons of every event (event-major), padded to a whole round, then the
+// quarks.  Each event keeps a bit mask of its gluon slots in LDS, so item r of
+// an owner is its r-th set (or clear) bit.  Within a round a segmented max
+// over consecutive lanes of the same owner leaves the owner's round best on
+// its last lane, which folds it into the owner's running best in LDS.  Both
+// compare (larger ln t, then smaller packed (i, k, K)): the paper's loop
+// order keeps the first of equal trials, and this rule picks that one in
+// whatever order the items come.  Each owner then decides its own cycle.
 // ---------------------------------------------------------------------------
 struct FlatShared {
   double lt[64], tcut[64], ltc[64], cfac[64];
   uint64_t slot[64];
   uint32_t key[4][64];
   uint32_t cycle[64];
-  uint32_t start[65];
+  uint32_t gstart[65], qstart[65];  // per-owner item offsets in the gluon and quark sections
   double best_v[64];
   uint32_t best_idx[64];
   uint32_t trials[64], ends[64];
 };
+
+// per-owner gluon masks, ceil(cap / 64) words each, in dynamic LDS
+extern __shared__ uint64_t flat_gmask[];
+
+__device__ __forceinline__ uint32_t mask_words(uint32_t cap) { return (cap + 63) / 64; }
 
 __device__ __forceinline__ uint32_t owner_of(const uint32_t* start, uint32_t j) {
   uint32_t lo = 0, hi = 64;  // last o with start[o] <= j (owners with no items have start[o] == start[o+1])
@@ -169,6 +179,44 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* start, uint32_t j) 
   return lo;
 }
 
+// position of the r-th (from 0) set bit of x; x has more than r set bits
+__device__ __forceinline__ uint32_t select64(uint64_t x, uint32_t r) {
+  uint32_t pos = 0;
+#pragma unroll
+  for (uint32_t w = 32; w >= 1; w >>= 1) {
+    const uint32_t c = __popcll(x & ((1ull << w) - 1));
+    if (r >= c) {
+      r -= c;
+      x >>= w;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+// slot of the r-th gluon (gluon = true) or r-th quark of an event's mask
+__device__ __forceinline__ uint32_t select_slot(const uint64_t* m, uint32_t words, uint32_t r, bool gluon) {
+  for (uint32_t w = 0; w < words; ++w) {
+    const uint64_t x = gluon ? m[w] : ~m[w];
+    const uint32_t c = __popcll(x);
+    if (r < c) return 64 * w + select64(x, r);
+    r -= c;
+  }
+  return 0;  // not reached for r below the owner's count
+}
+
+// The gluon mask of the event in column `slot`, from its partons' ids.
+__device__ __forceinline__ void mask_init(uint64_t* m, uint32_t words, const Records& r, uint64_t slot, int n) {
+  for (uint32_t w = 0; w < words; ++w) m[w] = 0ull;
+  for (int a = 0; a < n; ++a)
+    if (r.pid[(uint64_t)a * r.stride + slot] == kGluon) m[a >> 6] |= 1ull << (a & 63);
+}
+
+// (v, idx) beats (w, jdx): larger ln t, or equal and earlier in loop order
+__device__ __forceinline__ bool beats(double v, uint32_t idx, double w, uint32_t jdx) {
+  return idx != kNoTrial && (jdx == kNoTrial || v > w || (v == w && idx < jdx));
+}
+
 // One veto cycle of every busy event of this wave whose last accepted
 // emission has been built, the trials spread over the lanes; each owner lane
 // then decides its own event's cycle.  An accepted emission stays pending
@@ -176,22 +224,34 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* start, uint32_t j) 
 // events have one, or all of them do; then the wave builds them together.
 // Deferring an emission changes nothing in the event: its random numbers are
 // keyed by the event's own cycle.  The event of the calling lane sits in
-// column `slot` of `slots`.
+// column `slot` of `slots`; its gluon mask at gm + lane * words.
 constexpr uint32_t kEmitDiv = 4;
 
-__device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy, bool& pend, Pending& pd,
-                                           const Records& slots, uint64_t slot, uint32_t lane) {
+__device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_t words, EvState& s, bool busy,
+                                           bool& pend, Pending& pd, const Records& slots, uint64_t slot,
+                                           uint32_t lane) {
   const bool trial = busy && !pend;
-  // --- publish the events that make trials and the item ranges
-  const uint32_t mine = trial ? (uint32_t)s.n : 0u;
-  uint32_t incl = mine;
+  uint64_t* mym = gm + (uint64_t)lane * words;
+  // --- publish the events that make trials and the item ranges of both sections
+  uint32_t ng = 0;
+  if (trial)
+    for (uint32_t w = 0; w < words; ++w) ng += __popcll(mym[w]);
+  const uint64_t mine = trial ? (((uint64_t)((uint32_t)s.n - ng) << 32) | ng) : 0ull;
+  uint64_t incl = mine;
   for (uint32_t d = 1; d < 64; d <<= 1) {
-    const uint32_t t = __shfl_up(incl, d);
+    const uint64_t t = __shfl_up(incl, d);
     if (lane >= d) incl += t;
   }
-  const uint32_t total = __shfl(incl, 63);
-  sh.start[lane] = incl - mine;
-  if (lane == 63) sh.start[64] = total;
+  const uint64_t excl = incl - mine;
+  sh.gstart[lane] = (uint32_t)excl;
+  sh.qstart[lane] = (uint32_t)(excl >> 32);
+  if (lane == 63) {
+    sh.gstart[64] = (uint32_t)incl;
+    sh.qstart[64] = (uint32_t)(incl >> 32);
+  }
+  const uint64_t tot = __shfl(incl, 63);
+  const uint32_t n_g = (uint32_t)tot, n_q = (uint32_t)(tot >> 32);
+  const uint32_t g_pad = (n_g + 63) & ~63u;
   sh.lt[lane] = s.lt;
   sh.tcut[lane] = s.tcut;
   sh.ltc[lane] = s.ltc;
@@ -207,18 +267,21 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy
   sh.trials[lane] = 0;
   sh.ends[lane] = 0;
   __syncthreads();
-  // --- trials, 64 items per round
-  for (uint32_t r0 = 0; r0 < total; r0 += 64) {
-    const uint32_t j = r0 + lane;
-    const bool active = j < total;
+  // --- trials, 64 items per round: the gluon section, then the quark section
+  for (uint32_t r0 = 0; r0 < g_pad + n_q; r0 += 64) {
+    const bool gsec = r0 < g_pad;
+    const uint32_t* st = gsec ? sh.gstart : sh.qstart;
+    const uint32_t b0 = gsec ? r0 : r0 - g_pad;  // first section index of this round
+    const uint32_t j = b0 + lane;
+    const bool active = j < (gsec ? n_g : n_q);
     double v = -INFINITY;
     uint32_t idx = kNoTrial;
     uint32_t o = 63, seg0 = 64, last = 0;
     if (active) {
-      o = owner_of(sh.start, j);
-      const uint32_t i = j - sh.start[o];
-      seg0 = (sh.start[o] > r0 ? sh.start[o] : r0) - r0;
-      last = (j + 1 == sh.start[o + 1]) || lane == 63;
+      o = owner_of(st, j);
+      const uint32_t i = select_slot(gm + (uint64_t)o * words, words, j - st[o], gsec);
+      seg0 = (st[o] > b0 ? st[o] : b0) - b0;
+      last = (j + 1 == st[o + 1]) || lane == 63;
       const TrialCtx c{Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]}, sh.lt[o], sh.tcut[o],
                        sh.ltc[o], sh.cfac[o], sh.cycle[o]};
       double best = c.ltc;
@@ -235,13 +298,12 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy
     for (uint32_t d = 1; d < 64; d <<= 1) {
       const double vn = __shfl_up(v, d);
       const uint32_t in = __shfl_up(idx, d);
-      if (active && lane >= d && lane - d >= seg0 && in != kNoTrial && (vn >= v || idx == kNoTrial)) {
+      if (active && lane >= d && lane - d >= seg0 && beats(vn, in, v, idx)) {
         v = vn;
         idx = in;
       }
     }
-    if (active && last && idx != kNoTrial && (idx < kNoTrial) &&
-        (sh.best_idx[o] == kNoTrial || v > sh.best_v[o])) {
+    if (active && last && beats(v, idx, sh.best_v[o], sh.best_idx[o])) {
       sh.best_v[o] = v;
       sh.best_idx[o] = idx;
     }
@@ -264,11 +326,14 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy
     }
     pend = veto_decide(s, best, w, pd);
   }
-  // --- pending emissions, built together
+  // --- pending emissions, built together; the new parton's type goes into the mask
   const uint32_t n_pend = __popcll(__ballot(pend));
   const uint32_t n_busy = __popcll(__ballot(busy));
   if (n_pend > 0 && kEmitDiv * n_pend >= n_busy && pend) {
+    const int j = s.n;
     emit(s, slots, slot, pd);
+    if (pd.K <= 10) mym[j >> 6] |= 1ull << (j & 63);               // gluon emitted
+    else mym[pd.i >> 6] &= ~(1ull << (pd.i & 63));                 // g -> f fbar: i is now a quark
     pend = false;
   }
   if (busy && !pend && s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
@@ -277,20 +342,23 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, EvState& s, bool busy
 // Plain one-launch form with the flattened mapping: wave w owns events
 // 64w .. 64w+63 of the batch (already started by k_me) from start to cutoff,
 // with no refill; finished lanes only stop contributing trial work.
-__global__ void __launch_bounds__(64) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n) {
+__global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
+  const uint32_t words = mask_words(r.cap);
   const uint64_t e = (uint64_t)blockIdx.x * 64 + lane;
   EvState s = {};
   s.status = kDone;
   bool busy = e < n;
   bool pend = false;
   Pending pd{};
-  if (busy)
+  if (busy) {
     init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e),
                sm.i[kSiN * sm.stride + e], (int)r.cap);
+    mask_init(flat_gmask + (uint64_t)lane * words, words, r, e, s.n);
+  }
   while (__any(busy)) {
-    flat_cycle(sh, s, busy, pend, pd, r, e, lane);
+    flat_cycle(sh, flat_gmask, words, s, busy, pend, pd, r, e, lane);
     if (busy && s.status != kRunning) {
       write_state(s, sm, e);
       busy = false;
@@ -299,16 +367,19 @@ __global__ void __launch_bounds__(64) k_shower_plain_flat(Records r, Summary sm,
   }
 }
 
+size_t flat_lds_bytes(uint32_t cap) { return (size_t)64 * ((cap + 63) / 64) * 8; }
+
 void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
                               hipStream_t st) {
   if (!n) return;
-  hipLaunchKernelGGL(k_shower_plain_flat, dim3((n + 63) / 64), dim3(64), 0, st, r, s, in, n);
+  hipLaunchKernelGGL(k_shower_plain_flat, dim3((n + 63) / 64), dim3(64), flat_lds_bytes(r.cap), st, r, s, in, n);
 }
 
 template <bool kInPlace>
-__global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
+__global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
+  const uint32_t words = mask_words(A.slots.cap);
   const uint64_t L = (uint64_t)blockIdx.x * 64 + lane;
   EvState s = {};
   s.status = kDone;
@@ -324,10 +395,11 @@ __global__ void __launch_bounds__(64) k_shower_flat(PersistArgs A) {
     if (refill<(kInPlace ? 16u : 1u)>(A, busy, 64, lane, since, drained, req, ev)) {
       slot = kInPlace ? ev : L;
       start_event<kInPlace>(s, A, A.reqs[req], ev, slot);
+      mask_init(flat_gmask + (uint64_t)lane * words, words, A.slots, slot, s.n);
       busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle(sh, s, busy, pend, pd, A.slots, slot, lane);
+    flat_cycle(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, lane);
     if (busy && s.status != kRunning) {
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
       busy = false;
@@ -448,8 +520,9 @@ void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uin
   block = persistent_block(mapping, block);
   const dim3 grid((uint32_t)(lanes / block));
   if (mapping == kMapFlat) {
-    if (in_place) hipLaunchKernelGGL(k_shower_flat<true>, grid, dim3(block), 0, st, A);
-    else hipLaunchKernelGGL(k_shower_flat<false>, grid, dim3(block), 0, st, A);
+    const size_t lds = flat_lds_bytes(A.slots.cap);
+    if (in_place) hipLaunchKernelGGL(k_shower_flat<true>, grid, dim3(block), lds, st, A);
+    else hipLaunchKernelGGL(k_shower_flat<false>, grid, dim3(block), lds, st, A);
   } else {
     if (in_place) hipLaunchKernelGGL(k_shower_persistent<true>, grid, dim3(block), 0, st, A);
     else hipLaunchKernelGGL(k_shower_persistent<false>, grid, dim3(block), 0, st, A);
@@ -521,7 +594,8 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   GCHK(add_kernel((const void*)k_me, dim3((uint32_t)((n + 255) / 256)), dim3(256), a_me));
   GCHK(add_event(1));
   void* a_pers[] = {&g.args};
-  GCHK(add_kernel(persistent_kernel(g.mapping, true), dim3((uint32_t)(lanes / block)), dim3(block), a_pers));
+  GCHK(add_kernel(persistent_kernel(g.mapping, true), dim3((uint32_t)(lanes / block)), dim3(block), a_pers,
+                  g.mapping == kMapFlat ? (unsigned)flat_lds_bytes(A.slots.cap) : 0u));
   GCHK(add_event(2));
   g.nb = L.buf.out.cap + 1;
   g.cap = L.buf.out.cap;
