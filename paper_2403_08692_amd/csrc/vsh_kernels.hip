@@ -153,14 +153,19 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
     const uint64_t e = sc.perm[q];
     const int status = sm.i[kSiStatus * sm.stride + e];
     const int np = sm.i[kSiN * sm.stride + e];
-    for (int a = 0; a < np; ++a) {
-      const uint64_t from = (uint64_t)a * r.stride + e, to = (uint64_t)a * sc.stride + t;
-      sc.E[to] = r.E[from];
-      sc.x[to] = r.x[from];
-      sc.y[to] = r.y[from];
-      sc.z[to] = r.z[from];
+    ObsOut o;
+    if (np <= kObsRegSlots) {
+      o = reg_observables<kObsRegSlots>(r, e, np, in.ecm_of(e), status);
+    } else {
+      for (int a = 0; a < np; ++a) {
+        const uint64_t from = (uint64_t)a * r.stride + e, to = (uint64_t)a * sc.stride + t;
+        sc.E[to] = r.E[from];
+        sc.x[to] = r.x[from];
+        sc.y[to] = r.y[from];
+        sc.z[to] = r.z[from];
+      }
+      o = scratch_observables(sc, t, np, in.ecm_of(e), status);
     }
-    const ObsOut o = scratch_observables(sc, t, np, in.ecm_of(e), status);
     if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
     for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
     sm.i[kSiStatus * sm.stride + e] = o.status;

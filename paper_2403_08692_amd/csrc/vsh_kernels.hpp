@@ -89,6 +89,7 @@ struct Scratch {
 };
 
 constexpr uint32_t kObsWaveThreshold = 12;
+constexpr int kObsRegSlots = 8;  // events of at most this many partons: observables in registers
 constexpr uint32_t kObsWaveMaxCap = 512;
 constexpr uint32_t kObsWaveBlocks = 8192;
 size_t obs_wave_lds(uint32_t cap);

@@ -240,6 +240,206 @@ __device__ __forceinline__ ObsOut scratch_observables(const Scratch& w, uint64_t
   return o;
 }
 
+// ---------------------------------------------------------------------------
+// Register observables for events of at most M partons: the same quantities
+// in the same scan orders, with the partons held in registers (loops fully
+// unrolled over M slots, guarded by the parton count, which is uniform over
+// most waves after the sort).  Durham scans every alive pair (a < b) in order
+// and keeps the first minimum, the same merge the nearest-neighbour version
+// picks; a merge adds jet b into jet a.
+// ---------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, int np, double ecm, int status) {
+  ObsOut o;
+#pragma unroll
+  for (int h = 0; h < 7; ++h) o.v[h] = 0.0;
+  double E[M], X[M], Y[M], Z[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    E[a] = X[a] = Y[a] = Z[a] = 0.0;
+    if (a < np) {
+      const P4 p = r.load(a, e);
+      E[a] = p.e;
+      X[a] = p.x;
+      Y[a] = p.y;
+      Z[a] = p.z;
+    }
+  }
+  const double sh = ecm * ecm;
+  if (status == kDone) {
+    double tE = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
+    bool finite = true, massless = true;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      if (a < np) {
+        const P4 p{E[a], X[a], Y[a], Z[a]};
+        finite = finite && isfinite(p.e) && isfinite(p.x) && isfinite(p.y) && isfinite(p.z);
+        tE += p.e;
+        tx += p.x;
+        ty += p.y;
+        tz += p.z;
+        massless = massless && fabs(mdot(p, p)) <= 1e-10 * sh;
+      }
+    }
+    const double tol = 1e-10 * ecm;
+    if (!finite) status = kNonFinite;
+    else if (fabs(tE - ecm) > tol || fabs(tx) > tol || fabs(ty) > tol || fabs(tz) > tol || !massless)
+      status = kConservation;
+  }
+  o.status = status;
+  if (status != kDone) return o;
+  // sum |p| and the momentum tensor
+  double sum = 0.0, mxx = 0.0, myy = 0.0, mzz = 0.0, mxy = 0.0, mxz = 0.0, myz = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    if (a < np) {
+      const double x = X[a], y = Y[a], z = Z[a];
+      const double l = len3(x, y, z);
+      sum += l;
+      const double il = 1.0 / l;
+      mxx += x * x * il;
+      myy += y * y * il;
+      mzz += z * z * il;
+      mxy += x * y * il;
+      mxz += x * z * il;
+      myz += y * z * il;
+    }
+  }
+  // thrust
+  double best = -1.0, bx = 0.0, by = 0.0, bz = 1.0;
+  if (np < 3) {
+    for (int mk = 0; mk < (1 << np); ++mk) {
+      double vx = 0.0, vy = 0.0, vz = 0.0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        if (a < np) {
+          const double sg = (mk >> a & 1) ? -1.0 : 1.0;
+          vx += sg * X[a];
+          vy += sg * Y[a];
+          vz += sg * Z[a];
+        }
+      }
+      const double m2 = vx * vx + vy * vy + vz * vz;
+      if (m2 > best) { best = m2; bx = vx; by = vy; bz = vz; }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+#pragma unroll
+      for (int j = i + 1; j < M; ++j) {
+        if (j < np) {
+          const double nx = Y[i] * Z[j] - Z[i] * Y[j], ny = Z[i] * X[j] - X[i] * Z[j],
+                       nz = X[i] * Y[j] - Y[i] * X[j];
+          double vx = 0.0, vy = 0.0, vz = 0.0;
+#pragma unroll
+          for (int k = 0; k < M; ++k) {
+            if (k != i && k != j && k < np) {
+              const double d = X[k] * nx + Y[k] * ny + Z[k] * nz;
+              if (d > 0.0) { vx += X[k]; vy += Y[k]; vz += Z[k]; }
+              else { vx -= X[k]; vy -= Y[k]; vz -= Z[k]; }
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double si = (c < 2) ? 1.0 : -1.0, sj = (c & 1) ? -1.0 : 1.0;
+            const double wx = vx + si * X[i] + sj * X[j], wy = vy + si * Y[i] + sj * Y[j],
+                         wz = vz + si * Z[i] + sj * Z[j];
+            const double m2 = wx * wx + wy * wy + wz * wz;
+            if (m2 > best) { best = m2; bx = wx; by = wy; bz = wz; }
+          }
+        }
+      }
+    }
+  }
+  const double lb = sqrt(best);
+  double ax = 0.0, ay = 0.0, az = 1.0;
+  if (lb > 0.0) { ax = bx / lb; ay = by / lb; az = bz / lb; }
+  const double T = sum > 0.0 ? lb / sum : 0.0;
+  const double tau = 1.0 - T;
+  o.v[2] = tau > 0.0 ? tau : 0.0;
+  const double m2s = mxx * mxx + myy * myy + mzz * mzz + 2.0 * (mxy * mxy + mxz * mxz + myz * myz);
+  const double cpar = 1.5 * (sum * sum - m2s) / (sum * sum);
+  o.v[3] = cpar > 0.0 ? cpar : 0.0;
+  P4 hp{0, 0, 0, 0}, hm{0, 0, 0, 0};
+  double bp = 0.0, bm = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    if (a < np) {
+      const P4 p{E[a], X[a], Y[a], Z[a]};
+      const double d = p.x * ax + p.y * ay + p.z * az;
+      const double kt = len3(p.y * az - p.z * ay, p.z * ax - p.x * az, p.x * ay - p.y * ax);
+      if (d >= 0.0) { hp.e += p.e; hp.x += p.x; hp.y += p.y; hp.z += p.z; bp += kt; }
+      else { hm.e += p.e; hm.x += p.x; hm.y += p.y; hm.z += p.z; bm += kt; }
+    }
+  }
+  const double mp = mdot(hp, hp), mm = mdot(hm, hm);
+  const double rho = (mp > mm ? mp : mm) / sh;
+  o.v[4] = rho > 0.0 ? rho : 0.0;
+  bp /= 2.0 * sum;
+  bm /= 2.0 * sum;
+  o.v[5] = bp + bm;
+  o.v[6] = bp > bm ? bp : bm;
+  // Durham, E-scheme
+  if (np >= 3) {
+    const double inv_s = 1.0 / sh;
+    double UX[M], UY[M], UZ[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      UX[a] = UY[a] = UZ[a] = 0.0;
+      if (a < np) {
+        const double l = len3(X[a], Y[a], Z[a]);
+        UX[a] = X[a] / l;
+        UY[a] = Y[a] / l;
+        UZ[a] = Z[a] / l;
+      }
+    }
+    uint32_t alive = (1u << np) - 1u;
+    for (int m = np; m > 2; --m) {
+      double ymin = 0.0;
+      int ia = -1, ib = -1;
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+#pragma unroll
+        for (int b = a + 1; b < M; ++b) {
+          if ((alive >> a & 1u) && (alive >> b & 1u)) {
+            const double dx = UX[a] - UX[b], dy = UY[a] - UY[b], dz = UZ[a] - UZ[b];
+            const double d2 = (dx * dx + dy * dy) + dz * dz;
+            const double em = E[a] < E[b] ? E[a] : E[b];
+            const double y = em * em * d2 * inv_s;
+            if (ia < 0 || y < ymin) {
+              ymin = y;
+              ia = a;
+              ib = b;
+            }
+          }
+        }
+      }
+      if (m == 4) o.v[1] = ymin;
+      if (m == 3) o.v[0] = ymin;
+      if (m == 3) break;
+      double eb = 0.0, xb = 0.0, yb = 0.0, zb = 0.0;
+#pragma unroll
+      for (int b = 0; b < M; ++b)
+        if (b == ib) { eb = E[b]; xb = X[b]; yb = Y[b]; zb = Z[b]; }
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        if (a == ia) {
+          E[a] += eb;
+          X[a] += xb;
+          Y[a] += yb;
+          Z[a] += zb;
+          const double l = len3(X[a], Y[a], Z[a]);
+          UX[a] = X[a] / l;
+          UY[a] = Y[a] / l;
+          UZ[a] = Z[a] / l;
+        }
+      }
+      alive &= ~(1u << ib);
+    }
+  }
+  return o;
+}
+
 __device__ __forceinline__ double hist_lo(int h) {
   return h < 2 ? -4.3 : (h == 7 ? -1.0 : 0.0);
 }
