@@ -203,6 +203,20 @@ def test_no_emission_fraction_is_sudakov(oracle):
     assert np.all(d[:, 2:9] < 1e-12)
 
 
+@pytest.mark.parametrize("ecm,tc", [(10.0, 4.0), (6.0, 4.0)])
+def test_emission_probability_near_the_kinematic_limit(oracle, ecm, tc):
+    # t_C close to s/4: most of the phase space lies near the cutoff, where
+    # the z range of the overestimate meets the physical limit
+    # z(1 - z) = t_C / Q^2.  With room for no third parton, the first
+    # accepted emission overflows the record, so the overflow fraction is
+    # 1 - Delta(t_C, s) of the q qbar start.
+    n = 1_000_000
+    r = oracle.generate(29, 0, n, ecm, tc, 2)
+    frac = (r["sum_i"][:, 1] == 2).mean()
+    ref = 1.0 - _sudakov_qqbar(tc, ecm * ecm)
+    assert abs(frac - ref) < 4.5 * np.sqrt(ref * (1 - ref) / n), (frac, ref)
+
+
 def _qgq_start():
     # a fixed q g qbar configuration at sqrt(s) = 91.2 GeV: x_q = 0.8, x_qbar = 0.7
     ecm = 91.2
