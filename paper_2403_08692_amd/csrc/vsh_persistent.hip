@@ -159,12 +159,14 @@ struct FlatShared {
   uint32_t key[4][64];
   uint32_t cycle[64];
   uint32_t gstart[65], qstart[65];  // per-owner item offsets in the gluon and quark sections
+  uint16_t item[2048];              // the cycle's items, owner << 10 | parton: gluons, then quarks
   double best_v[64];
   uint32_t best_idx[64];
   uint32_t trials[64], ends[64];
 };
 
-// per-owner gluon masks, ceil(cap / 64) words each, in dynamic LDS
+// per-owner gluon masks, then per-owner stale masks (partons whose cached end
+// coefficients must be recomputed), ceil(cap / 64) words each, in dynamic LDS
 extern __shared__ uint64_t flat_gmask[];
 
 __device__ __forceinline__ uint32_t mask_words(uint32_t cap) { return (cap + 63) / 64; }
@@ -205,11 +207,65 @@ __device__ __forceinline__ uint32_t select_slot(const uint64_t* m, uint32_t word
   return 0;  // not reached for r below the owner's count
 }
 
-// The gluon mask of the event in column `slot`, from its partons' ids.
-__device__ __forceinline__ void mask_init(uint64_t* m, uint32_t words, const Records& r, uint64_t slot, int n) {
-  for (uint32_t w = 0; w < words; ++w) m[w] = 0ull;
+// The gluon mask of the event in column `slot`, from its partons' ids, and
+// its stale mask with every parton set.
+__device__ __forceinline__ void mask_init(uint64_t* m, uint64_t* st, uint32_t words, const Records& r,
+                                          uint64_t slot, int n) {
+  for (uint32_t w = 0; w < words; ++w) {
+    m[w] = 0ull;
+    const int lo = 64 * (int)w;
+    st[w] = n >= lo + 64 ? ~0ull : (n > lo ? (1ull << (n - lo)) - 1ull : 0ull);
+  }
   for (int a = 0; a < n; ++a)
     if (r.pid[(uint64_t)a * r.stride + slot] == kGluon) m[a >> 6] |= 1ull << (a & 63);
+}
+
+__device__ __forceinline__ void set_bit(uint64_t* m, int a) {
+  if (a >= 0 && a != kNoPartner) m[a >> 6] |= 1ull << (a & 63);
+}
+
+// Trials of parton i of the event in column `slot`, with the coefficients of
+// its dipole ends taken from the cache column `col` unless the parton is
+// stale (then computed from the momenta and stored).  The coefficients only
+// change when the momenta or colour partners of an end change, i.e. after an
+// emission next to it; the cached values are the ones a recomputation would
+// give.  Same trials, same order, same winner as parton_trials.
+__device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Records& r, uint64_t slot, int i,
+                                                     const EndCache& ec, uint64_t col, bool stale, double& best,
+                                                     uint32_t& widx, uint32_t& trials, uint32_t& ends) {
+  const uint64_t oi = (uint64_t)i * r.stride + slot;
+  const int pid_i = r.pid[oi];
+  int k1 = r.cpart[oi], k2 = r.apart[oi];
+  if (k2 == k1) k2 = kNoPartner;
+  if (k1 > k2) {
+    const int t = k1;
+    k1 = k2;
+    k2 = t;
+  }
+  P4 pi{0.0, 0.0, 0.0, 0.0};
+  if (stale) pi = r.load(i, slot);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int k = e == 0 ? k1 : k2;
+    if (k == kNoPartner) continue;
+    const uint64_t q = (uint64_t)(2 * i + e) * ec.stride + col;
+    double ca = 0.0, cb = 0.0;
+    if (stale) {
+      double q2, zm, zp, L;
+      if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, r.load(k, slot), q2, zm, zp, L, ca, cb)) ca = cb = 0.0;
+      if (ec.c0) {
+        ec.c0[q] = ca;
+        ec.c1[q] = cb;
+      }
+    } else {
+      ca = ec.c0[q];
+      if (pid_i == kGluon) cb = ec.c1[q];
+    }
+    if (ca == 0.0) continue;  // no phase space above the cutoff
+    ends += 1;
+    const int K = end_draws(c, i, k, pid_i, ca, cb, best, trials);
+    if (K >= 0) widx = pack_trial(i, k, K);
+  }
 }
 
 // (v, idx) beats (w, jdx): larger ln t, or equal and earlier in loop order
@@ -229,9 +285,11 @@ constexpr uint32_t kEmitDiv = 4;
 
 __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_t words, EvState& s, bool busy,
                                            bool& pend, Pending& pd, const Records& slots, uint64_t slot,
-                                           uint32_t lane) {
+                                           const EndCache& ec, uint64_t wave_col, uint32_t lane) {
   const bool trial = busy && !pend;
   uint64_t* mym = gm + (uint64_t)lane * words;
+  uint64_t* sm = gm + (uint64_t)64 * words;  // stale masks
+  uint64_t* mys = sm + (uint64_t)lane * words;
   // --- publish the events that make trials and the item ranges of both sections
   uint32_t ng = 0;
   if (trial)
@@ -252,6 +310,16 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   const uint64_t tot = __shfl(incl, 63);
   const uint32_t n_g = (uint32_t)tot, n_q = (uint32_t)(tot >> 32);
   const uint32_t g_pad = (n_g + 63) & ~63u;
+  constexpr uint32_t kItems = sizeof(sh.item) / sizeof(sh.item[0]);
+  if (trial) {  // list this event's items (beyond the list's length rounds search the offsets instead)
+    uint32_t gpos = (uint32_t)excl, qpos = n_g + (uint32_t)(excl >> 32);
+    uint64_t mw = 0;
+    for (int a = 0; a < s.n; ++a) {
+      if ((a & 63) == 0) mw = mym[a >> 6];
+      const uint32_t pos = ((mw >> (a & 63)) & 1ull) ? gpos++ : qpos++;
+      if (pos < kItems) sh.item[pos] = (uint16_t)((lane << 10) | (uint32_t)a);
+    }
+  }
   sh.lt[lane] = s.lt;
   sh.tcut[lane] = s.tcut;
   sh.ltc[lane] = s.ltc;
@@ -278,19 +346,30 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     uint32_t idx = kNoTrial;
     uint32_t o = 63, seg0 = 64, last = 0;
     if (active) {
-      o = owner_of(st, j);
-      const uint32_t i = select_slot(gm + (uint64_t)o * words, words, j - st[o], gsec);
+      const uint32_t at = gsec ? j : n_g + j;  // position in the item list
+      uint32_t i;
+      if (at < kItems) {
+        const uint32_t it = sh.item[at];
+        o = it >> 10;
+        i = it & 1023u;
+      } else {
+        o = owner_of(st, j);
+        i = select_slot(gm + (uint64_t)o * words, words, j - st[o], gsec);
+      }
       seg0 = (st[o] > b0 ? st[o] : b0) - b0;
       last = (j + 1 == st[o + 1]) || lane == 63;
       const TrialCtx c{Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]}, sh.lt[o], sh.tcut[o],
                        sh.ltc[o], sh.cfac[o], sh.cycle[o]};
       double best = c.ltc;
-      Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
+      uint32_t widx = kNoTrial;
       uint32_t nt = 0, ne = 0;
-      parton_trials(c, slots, sh.slot[o], (int)i, best, w, nt, ne);
-      if (w.i >= 0) {
+      const uint64_t sw = sm[(uint64_t)o * words + (i >> 6)];
+      const bool stale = !ec.c0 || ((sw >> (i & 63)) & 1ull);
+      parton_trials_cached(c, slots, sh.slot[o], (int)i, ec, wave_col + o, stale, best, widx, nt, ne);
+      if (stale && ec.c0) atomicAnd((unsigned long long*)&sm[(uint64_t)o * words + (i >> 6)], ~(1ull << (i & 63)));
+      if (widx != kNoTrial) {
         v = best;
-        idx = pack_trial(w.i, w.k, w.K);
+        idx = widx;
       }
       atomicAdd(&sh.trials[o], nt);
       atomicAdd(&sh.ends[o], ne);
@@ -334,6 +413,16 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     emit(s, slots, slot, pd);
     if (pd.K <= 10) mym[j >> 6] |= 1ull << (j & 63);               // gluon emitted
     else mym[pd.i >> 6] &= ~(1ull << (pd.i & 63));                 // g -> f fbar: i is now a quark
+    // ends whose momenta or partners changed: those of i, j, k and of the
+    // other colour partners of i and k (partner links are symmetric)
+    const uint64_t oi = (uint64_t)pd.i * slots.stride + slot, ok = (uint64_t)pd.k * slots.stride + slot;
+    set_bit(mys, pd.i);
+    set_bit(mys, j);
+    set_bit(mys, pd.k);
+    set_bit(mys, slots.cpart[oi]);
+    set_bit(mys, slots.apart[oi]);
+    set_bit(mys, slots.cpart[ok]);
+    set_bit(mys, slots.apart[ok]);
     pend = false;
   }
   if (busy && !pend && s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
@@ -355,10 +444,11 @@ __global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary 
   if (busy) {
     init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e),
                sm.i[kSiN * sm.stride + e], (int)r.cap);
-    mask_init(flat_gmask + (uint64_t)lane * words, words, r, e, s.n);
+    mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
+  const EndCache none{nullptr, nullptr, 0};
   while (__any(busy)) {
-    flat_cycle(sh, flat_gmask, words, s, busy, pend, pd, r, e, lane);
+    flat_cycle(sh, flat_gmask, words, s, busy, pend, pd, r, e, none, 0, lane);
     if (busy && s.status != kRunning) {
       write_state(s, sm, e);
       busy = false;
@@ -367,7 +457,7 @@ __global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary 
   }
 }
 
-size_t flat_lds_bytes(uint32_t cap) { return (size_t)64 * ((cap + 63) / 64) * 8; }
+size_t flat_lds_bytes(uint32_t cap) { return (size_t)2 * 64 * ((cap + 63) / 64) * 8; }
 
 void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
                               hipStream_t st) {
@@ -395,11 +485,12 @@ __global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
     if (refill<(kInPlace ? 16u : 1u)>(A, busy, 64, lane, since, drained, req, ev)) {
       slot = kInPlace ? ev : L;
       start_event<kInPlace>(s, A, A.reqs[req], ev, slot);
-      mask_init(flat_gmask + (uint64_t)lane * words, words, A.slots, slot, s.n);
+      mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, A.slots,
+                slot, s.n);
       busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, lane);
+    flat_cycle(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane);
     if (busy && s.status != kRunning) {
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
       busy = false;
@@ -490,9 +581,15 @@ ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap, bool partners) {
 
 Scratch carve_scratch(Carver& c, uint64_t n, uint32_t cap) { return carve_obs_scratch(c.p, n, cap); }
 
+// Lanes of the largest persistent grid (16 waves on each of 256 CUs): the
+// stride of a batch's end-coefficient cache, whatever the tuning.
+constexpr uint64_t kCacheLanes = 16ull * 256 * 64;
+
+uint64_t cache_bytes(uint32_t cap) { return 2 * align_up(kCacheLanes * 2 * cap * 8, 256); }
+
 // A batch is one request, showered in place in its output records.
 uint64_t batch_bytes(uint64_t n, uint32_t cap) {
-  return request_out_bytes(n, cap, true) + obs_scratch_bytes(n, cap) + 4096 +
+  return request_out_bytes(n, cap, true) + cache_bytes(cap) + obs_scratch_bytes(n, cap) + 4096 +
          sizeof(ReqDev) + sizeof(Segment) + 1024;
 }
 
@@ -500,6 +597,9 @@ BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap) {
   Carver c(base);
   BatchLayout L;
   L.buf = carve_request(c, n, cap, true);
+  L.cache.c0 = (double*)c.take(kCacheLanes * 2 * cap * 8);
+  L.cache.c1 = (double*)c.take(kCacheLanes * 2 * cap * 8);
+  L.cache.stride = kCacheLanes;
   L.sc = carve_scratch(c, n, cap);
   L.counter = (unsigned long long*)c.take(256);
   L.reqs = (ReqDev*)c.take(sizeof(ReqDev));
@@ -655,6 +755,11 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
   const uint64_t lanes = persistent_lanes(ctx);
   const uint32_t mapping = ctx->tuned.mapping;
   const uint32_t block = persistent_block(mapping, ctx->tuned.pers_block);
+  if (lanes > kCacheLanes) {
+    set_error(ctx, "persistent grid of %llu lanes exceeds the %llu the batch layout holds",
+              (unsigned long long)lanes, (unsigned long long)kCacheLanes);
+    return VSH_E_INTERNAL;
+  }
   BatchLayout L = carve_batch(base, n, cap);
   if (out_layout) *out_layout = L;
   ReqDev d;
@@ -671,6 +776,7 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
   A.threshold = ctx->tuned.refill_threshold;
   A.period = ctx->tuned.refill_period;
   A.pad = 0;
+  A.cache = L.cache;
   EventInputs in{};
   in.ecm = ecm_dev;
   in.tcut = tcut_dev;
@@ -754,7 +860,12 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
   // chunk so that a batch fits the budget (half of it when records are returned)
   uint64_t budget = ctx->budget;
   if (req->flags & VSH_RECORDS) budget /= 2;
-  const uint64_t fixed = 64 * 1024;
+  if (lanes > kCacheLanes) {
+    set_error(ctx, "persistent grid of %llu lanes exceeds the %llu the batch layout holds",
+              (unsigned long long)lanes, (unsigned long long)kCacheLanes);
+    return VSH_E_INTERNAL;
+  }
+  const uint64_t fixed = 64 * 1024 + cache_bytes(cap);
   if (budget <= fixed + request_out_bytes(64, cap, true) + obs_scratch_bytes(64, cap)) {
     set_error(ctx, "memory budget too small for the persistent form at %u partons", cap);
     return VSH_E_NOMEM;
@@ -814,6 +925,7 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     A.threshold = ctx->tuned.refill_threshold;
     A.period = ctx->tuned.refill_period;
     A.pad = 0;
+    A.cache = L.cache;
     (void)hipEventRecord(ctx->ev[1], st);
     launch_persistent(A, lanes, ctx->tuned.pers_block, ctx->tuned.mapping, true, st);
     (void)hipEventRecord(ctx->ev[2], st);

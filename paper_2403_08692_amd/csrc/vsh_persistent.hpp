@@ -27,6 +27,15 @@ struct Segment {
   uint64_t start;    // first work index of this segment
 };
 
+// Cached trial coefficients of the dipole ends of each lane's event
+// (flattened mapping): element [(2 a + e) * stride + lane] is end e (by
+// ascending spectator) of parton a; c0 = the quark kernel's or g -> g g's,
+// c1 = g -> f fbar's, 0 = no phase space.  Null pointers: no cache.
+struct EndCache {
+  double *c0, *c1;
+  uint64_t stride;
+};
+
 struct PersistArgs {
   Records slots;                  // working records: one slot per lane [cap][lanes], or the
                                   // single request's output records when showered in place
@@ -38,6 +47,7 @@ struct PersistArgs {
   unsigned long long* next;       // work counter, zeroed before the launch
   uint32_t period;                // veto cycles between refill checks
   uint32_t pad;
+  EndCache cache;                 // flattened mapping: per-lane end coefficients, or none
 };
 
 struct ReqBuffers {
@@ -54,6 +64,7 @@ struct Carver {
 
 struct BatchLayout {
   ReqBuffers buf;
+  EndCache cache;
   Scratch sc;
   unsigned long long* counter;
   ReqDev* reqs;

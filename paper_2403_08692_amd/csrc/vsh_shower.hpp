@@ -93,29 +93,42 @@ __device__ __forceinline__ bool end_limits(const P4& pi, const P4& pk, double tc
   return true;
 }
 
-// All trials of the dipole end (i, k): one per kernel of the splitter,
-// t_try = t R^(1/c) compared as ln t + ln(R)/c (App. A, trial-scale
-// equation); strict maximum above the running best.  A gluon end's five
-// g -> f fbar kernels share c, so only their largest uniform needs a log.
-__device__ __forceinline__ void end_trials(const TrialCtx& c, int i, int k, int pid_i, const P4& pi,
-                                           const P4& pk, double& best, Winner& w, uint32_t& trials,
-                                           uint32_t& ends) {
-  double q2, zm, zp;
-  if (!end_limits(pi, pk, c.tcut, q2, zm, zp)) return;
-  const double L = log_fast((1.0 - zm) / (1.0 - zp));
-  ends += 1;
+// Trial coefficients c = alpha_s^over/(2 pi) * I of the dipole end (i, k):
+// for a quark end ca = its one kernel's; for a gluon end ca = g -> g g's and
+// cb = the common one of the five g -> f fbar kernels.  False (and no
+// coefficients) for an end without phase space above the cutoff.
+__device__ __forceinline__ bool end_coeffs(double cfac, double tcut, int pid_i, const P4& pi, const P4& pk,
+                                           double& q2, double& zm, double& zp, double& L, double& ca,
+                                           double& cb) {
+  if (!end_limits(pi, pk, tcut, q2, zm, zp)) return false;
+  L = log_fast((1.0 - zm) / (1.0 - zp));
   if (pid_i != kGluon) {
-    const double cq = c.cfac * ((2.0 * kCF) * L);
+    ca = cfac * ((2.0 * kCF) * L);
+    cb = 0.0;
+  } else {
+    ca = cfac * (kCA * L);
+    cb = cfac * ((0.5 * kTR) * (zp - zm));
+  }
+  return true;
+}
+
+// The trials of an end with coefficients (ca, cb): t_try = t R^(1/c)
+// compared as ln t + ln(R)/c (App. A, trial-scale equation), strict maximum
+// above the running best.  A gluon end's five g -> f fbar kernels share c, so
+// only their largest uniform needs a log.  Returns the winning kernel (or -1
+// if none beat `best`).
+__device__ __forceinline__ int end_draws(const TrialCtx& c, int i, int k, int pid_i, double ca, double cb,
+                                         double& best, uint32_t& trials) {
+  int K = -1;
+  if (pid_i != kGluon) {
     const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
-    const double lt_try = c.lt + log_fast(unit(d.x, d.y)) / cq;
+    const double lt_try = c.lt + log_fast(unit(d.x, d.y)) / ca;
     trials += 1;
     if (lt_try > best) {
       best = lt_try;
-      w = Winner{q2, zm, zp, L, i, k, pid_i > 0 ? pid_i - 1 : 4 - pid_i};
+      K = pid_i > 0 ? pid_i - 1 : 4 - pid_i;
     }
   } else {
-    const double cgg = c.cfac * (kCA * L);
-    const double cqq = c.cfac * ((0.5 * kTR) * (zp - zm));
     // kernel list g->gg, g->d dbar, ..., g->b bbar: block g holds kernels 2g, 2g+1
     trials += 6;
     double ugg = 0.0, um = 0.0;
@@ -135,17 +148,29 @@ __device__ __forceinline__ void end_trials(const TrialCtx& c, int i, int k, int 
         fm = 2 * g + 1;
       }
     }
-    const double lgg = c.lt + log_fast(ugg) / cgg;
-    const double lqq = c.lt + log_fast(um) / cqq;
+    const double lgg = c.lt + log_fast(ugg) / ca;
+    const double lqq = c.lt + log_fast(um) / cb;
     if (lgg > best) {
       best = lgg;
-      w = Winner{q2, zm, zp, L, i, k, 10};
+      K = 10;
     }
     if (lqq > best) {
       best = lqq;
-      w = Winner{q2, zm, zp, L, i, k, 10 + fm};
+      K = 10 + fm;
     }
   }
+  return K;
+}
+
+// All trials of the dipole end (i, k): one per kernel of the splitter.
+__device__ __forceinline__ void end_trials(const TrialCtx& c, int i, int k, int pid_i, const P4& pi,
+                                           const P4& pk, double& best, Winner& w, uint32_t& trials,
+                                           uint32_t& ends) {
+  double q2, zm, zp, L, ca, cb;
+  if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, pk, q2, zm, zp, L, ca, cb)) return;
+  ends += 1;
+  const int K = end_draws(c, i, k, pid_i, ca, cb, best, trials);
+  if (K >= 0) w = Winner{q2, zm, zp, L, i, k, K};
 }
 
 // Trials of parton i of the event in slot e: its dipole ends in ascending
