@@ -234,6 +234,16 @@ __device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Re
                                                      const EndCache& ec, uint64_t col, bool stale, double& best,
                                                      uint32_t& widx, uint32_t& trials, uint32_t& ends) {
   const uint64_t oi = (uint64_t)i * r.stride + slot;
+  const uint64_t q0 = (uint64_t)(2 * i) * ec.stride + col;
+  // a fresh parton's cached coefficients are loaded together with its id and
+  // links (rows of an absent second end are read and ignored)
+  double cc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!stale) {
+    cc[0] = ec.c0[q0];
+    cc[1] = ec.c1[q0];
+    cc[2] = ec.c0[q0 + ec.stride];
+    cc[3] = ec.c1[q0 + ec.stride];
+  }
   const int pid_i = r.pid[oi];
   int k1 = r.cpart[oi], k2 = r.apart[oi];
   if (k2 == k1) k2 = kNoPartner;
@@ -248,8 +258,8 @@ __device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Re
   for (int e = 0; e < 2; ++e) {
     const int k = e == 0 ? k1 : k2;
     if (k == kNoPartner) continue;
-    const uint64_t q = (uint64_t)(2 * i + e) * ec.stride + col;
-    double ca = 0.0, cb = 0.0;
+    const uint64_t q = q0 + (uint64_t)e * ec.stride;
+    double ca = cc[2 * e], cb = cc[2 * e + 1];
     if (stale) {
       double q2, zm, zp, L;
       if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, r.load(k, slot), q2, zm, zp, L, ca, cb)) ca = cb = 0.0;
@@ -257,9 +267,6 @@ __device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Re
         ec.c0[q] = ca;
         ec.c1[q] = cb;
       }
-    } else {
-      ca = ec.c0[q];
-      if (pid_i == kGluon) cb = ec.c1[q];
     }
     if (ca == 0.0) continue;  // no phase space above the cutoff
     ends += 1;
