@@ -316,6 +316,14 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   }
   const uint64_t tot = __shfl(incl, 63);
   const uint32_t n_g = (uint32_t)tot, n_q = (uint32_t)(tot >> 32);
+  // longest per-event run of items in either section: a round's segmented
+  // max needs only the shuffle steps below it
+  uint32_t gmax = (uint32_t)mine, qmax = (uint32_t)(mine >> 32);
+  for (uint32_t d = 32; d >= 1; d >>= 1) {
+    const uint32_t a = __shfl_xor(gmax, d), b = __shfl_xor(qmax, d);
+    gmax = a > gmax ? a : gmax;
+    qmax = b > qmax ? b : qmax;
+  }
   const uint32_t g_pad = (n_g + 63) & ~63u;
   constexpr uint32_t kItems = sizeof(sh.item) / sizeof(sh.item[0]);
   if (trial) {  // list this event's items (beyond the list's length rounds search the offsets instead)
@@ -381,7 +389,8 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       atomicAdd(&sh.trials[o], nt);
       atomicAdd(&sh.ends[o], ne);
     }
-    for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t run = gsec ? gmax : qmax;
+    for (uint32_t d = 1; d < 64 && d < run; d <<= 1) {
       const double vn = __shfl_up(v, d);
       const uint32_t in = __shfl_up(idx, d);
       if (active && lane >= d && lane - d >= seg0 && beats(vn, in, v, idx)) {
