@@ -224,54 +224,71 @@ __device__ __forceinline__ void set_bit(uint64_t* m, int a) {
   if (a >= 0 && a != kNoPartner) m[a >> 6] |= 1ull << (a & 63);
 }
 
-// Trials of parton i of the event in column `slot`, with the coefficients of
-// its dipole ends taken from the cache column `col` unless the parton is
-// stale (then computed from the momenta and stored).  The coefficients only
-// change when the momenta or colour partners of an end change, i.e. after an
-// emission next to it; the cached values are the ones a recomputation would
-// give.  Same trials, same order, same winner as parton_trials.
+// Trials of parton i of the event in column `slot`.  Each lane's event keeps,
+// per parton, one cache entry of kCacheWords words at
+// rec[((col * cap) + i) * kCacheWords]: its id and its spectators in
+// ascending order (packed in word 0), then per end the trial coefficients
+// (quark kernel or g -> g g, and g -> f fbar; 0 = no phase space).  An entry
+// changes only when an emission touches the parton or its partners, which
+// marks it stale: then it is rebuilt from the records (the values a
+// recomputation gives).  A fresh parton needs nothing but its entry.  Same
+// trials, same order, same winner as parton_trials.
+__device__ __forceinline__ uint64_t pack_meta(int pid, int k1, int k2) {
+  return (uint64_t)(uint8_t)(int8_t)pid | ((uint64_t)(uint16_t)k1 << 8) | ((uint64_t)(uint16_t)k2 << 24);
+}
+
 __device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Records& r, uint64_t slot, int i,
                                                      const EndCache& ec, uint64_t col, bool stale, double& best,
                                                      uint32_t& widx, uint32_t& trials, uint32_t& ends) {
-  const uint64_t oi = (uint64_t)i * r.stride + slot;
-  const uint64_t q0 = (uint64_t)(2 * i) * ec.stride + col;
-  // a fresh parton's cached coefficients are loaded together with its id and
-  // links (rows of an absent second end are read and ignored)
-  double cc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (!stale) {
-    cc[0] = ec.c0[q0];
-    cc[1] = ec.c1[q0];
-    cc[2] = ec.c0[q0 + ec.stride];
-    cc[3] = ec.c1[q0 + ec.stride];
-  }
-  const int pid_i = r.pid[oi];
-  int k1 = r.cpart[oi], k2 = r.apart[oi];
-  if (k2 == k1) k2 = kNoPartner;
-  if (k1 > k2) {
-    const int t = k1;
-    k1 = k2;
-    k2 = t;
-  }
+  uint64_t* ent = ec.rec ? ec.rec + ((col * ec.cap) + (uint64_t)i) * kCacheWords : nullptr;
+  uint64_t w[kCacheWords];
+  int pid_i, k1, k2;
   P4 pi{0.0, 0.0, 0.0, 0.0};
-  if (stale) pi = r.load(i, slot);
+  if (!stale) {
+#pragma unroll
+    for (int q = 0; q < kCacheWords; ++q) w[q] = ent[q];
+    pid_i = (int)(int8_t)(uint8_t)(w[0] & 0xFFu);
+    k1 = (int)((w[0] >> 8) & 0xFFFFu);
+    k2 = (int)((w[0] >> 24) & 0xFFFFu);
+  } else {
+    const uint64_t oi = (uint64_t)i * r.stride + slot;
+    pid_i = r.pid[oi];
+    k1 = r.cpart[oi];
+    k2 = r.apart[oi];
+    if (k2 == k1) k2 = kNoPartner;
+    if (k1 > k2) {
+      const int t = k1;
+      k1 = k2;
+      k2 = t;
+    }
+    pi = r.load(i, slot);
+    w[0] = pack_meta(pid_i, k1, k2);
+  }
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int k = e == 0 ? k1 : k2;
-    if (k == kNoPartner) continue;
-    const uint64_t q = q0 + (uint64_t)e * ec.stride;
-    double ca = cc[2 * e], cb = cc[2 * e + 1];
-    if (stale) {
-      double q2, zm, zp, L;
-      if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, r.load(k, slot), q2, zm, zp, L, ca, cb)) ca = cb = 0.0;
-      if (ec.c0) {
-        ec.c0[q] = ca;
-        ec.c1[q] = cb;
+    double ca = 0.0, cb = 0.0;
+    if (k != kNoPartner) {
+      if (stale) {
+        double q2, zm, zp, L;
+        if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, r.load(k, slot), q2, zm, zp, L, ca, cb)) ca = cb = 0.0;
+        w[1 + 2 * e] = (uint64_t)__double_as_longlong(ca);
+        w[2 + 2 * e] = (uint64_t)__double_as_longlong(cb);
+      } else {
+        ca = __longlong_as_double((long long)w[1 + 2 * e]);
+        cb = __longlong_as_double((long long)w[2 + 2 * e]);
       }
     }
-    if (ca == 0.0) continue;  // no phase space above the cutoff
+    if (ca == 0.0) continue;  // no partner, or no phase space above the cutoff
     ends += 1;
     const int K = end_draws(c, i, k, pid_i, ca, cb, best, trials);
     if (K >= 0) widx = pack_trial(i, k, K);
+  }
+  if (stale && ent) {
+    if (k1 == kNoPartner) w[1] = w[2] = 0ull;
+    if (k2 == kNoPartner) w[3] = w[4] = 0ull;
+#pragma unroll
+    for (int q = 0; q < kCacheWords; ++q) ent[q] = w[q];
   }
 }
 
@@ -379,9 +396,9 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       uint32_t widx = kNoTrial;
       uint32_t nt = 0, ne = 0;
       const uint64_t sw = sm[(uint64_t)o * words + (i >> 6)];
-      const bool stale = !ec.c0 || ((sw >> (i & 63)) & 1ull);
+      const bool stale = !ec.rec || ((sw >> (i & 63)) & 1ull);
       parton_trials_cached(c, slots, sh.slot[o], (int)i, ec, wave_col + o, stale, best, widx, nt, ne);
-      if (stale && ec.c0) atomicAnd((unsigned long long*)&sm[(uint64_t)o * words + (i >> 6)], ~(1ull << (i & 63)));
+      if (stale && ec.rec) atomicAnd((unsigned long long*)&sm[(uint64_t)o * words + (i >> 6)], ~(1ull << (i & 63)));
       if (widx != kNoTrial) {
         v = best;
         idx = widx;
@@ -462,7 +479,7 @@ __global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary 
                sm.i[kSiN * sm.stride + e], (int)r.cap);
     mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
-  const EndCache none{nullptr, nullptr, 0};
+  const EndCache none{nullptr, 0};
   while (__any(busy)) {
     flat_cycle(sh, flat_gmask, words, s, busy, pend, pd, r, e, none, 0, lane);
     if (busy && s.status != kRunning) {
@@ -601,7 +618,7 @@ Scratch carve_scratch(Carver& c, uint64_t n, uint32_t cap) { return carve_obs_sc
 // stride of a batch's end-coefficient cache, whatever the tuning.
 constexpr uint64_t kCacheLanes = 16ull * 256 * 64;
 
-uint64_t cache_bytes(uint32_t cap) { return 2 * align_up(kCacheLanes * 2 * cap * 8, 256); }
+uint64_t cache_bytes(uint32_t cap) { return align_up(kCacheLanes * cap * kCacheWords * 8, 256); }
 
 // A batch is one request, showered in place in its output records.
 uint64_t batch_bytes(uint64_t n, uint32_t cap) {
@@ -613,9 +630,8 @@ BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap) {
   Carver c(base);
   BatchLayout L;
   L.buf = carve_request(c, n, cap, true);
-  L.cache.c0 = (double*)c.take(kCacheLanes * 2 * cap * 8);
-  L.cache.c1 = (double*)c.take(kCacheLanes * 2 * cap * 8);
-  L.cache.stride = kCacheLanes;
+  L.cache.rec = (uint64_t*)c.take(kCacheLanes * cap * kCacheWords * 8);
+  L.cache.cap = cap;
   L.sc = carve_scratch(c, n, cap);
   L.counter = (unsigned long long*)c.take(256);
   L.reqs = (ReqDev*)c.take(sizeof(ReqDev));

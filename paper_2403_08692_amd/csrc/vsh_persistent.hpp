@@ -27,13 +27,13 @@ struct Segment {
   uint64_t start;    // first work index of this segment
 };
 
-// Cached trial coefficients of the dipole ends of each lane's event
-// (flattened mapping): element [(2 a + e) * stride + lane] is end e (by
-// ascending spectator) of parton a; c0 = the quark kernel's or g -> g g's,
-// c1 = g -> f fbar's, 0 = no phase space.  Null pointers: no cache.
+// Per-lane cache of each parton's dipole ends (flattened mapping): entry
+// [(lane * cap) + a] of kCacheWords words holds parton a's id and ordered
+// spectators, then per end its trial coefficients.  Null: no cache.
+constexpr int kCacheWords = 5;
 struct EndCache {
-  double *c0, *c1;
-  uint64_t stride;
+  uint64_t* rec;
+  uint32_t cap;
 };
 
 struct PersistArgs {

@@ -283,7 +283,7 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
   A.n_segs = nseg;
   A.threshold = tn.refill_threshold;
   A.pad = 0;
-  A.cache = EndCache{nullptr, nullptr, 0};
+  A.cache = EndCache{nullptr, 0};
   A.total = total;
   A.next = counter;
   A.period = tn.refill_period;
