@@ -42,26 +42,31 @@ COST = {"philox": 119, "unit": 9, "log": 97, "log_fast": 54, "exp": 41, "sqrt": 
 def algorithmic_ops(n_events, ends, trials, cycles, emissions):
     """VALU lane-operations the veto algorithm needs for a batch, under the
     random-number contract (one Philox block per two kernel trials of a
-    dipole end).  Per active dipole end and cycle: the dipole mass and z
-    limits (dot product, divide, square root), the overestimate integral's
-    log and the trial coefficients; then per kernel trial its uniform, and a
-    log and a divide per trial scale (a gluon end's five g -> f fbar trials
-    share one coefficient, so only the largest of their uniforms needs the
-    log).  Per cycle with a winner: the accept block, t = exp(ln t), z from
-    the overestimate (one exp), y, alpha_s from ln t, kernel over
-    overestimate.  Per accepted emission: the azimuth block, sincos and the
-    dipole map.  Per event: the matrix element and the shower's start-up."""
+    dipole end).  Per active dipole end and cycle: per kernel trial its
+    uniform, and a log and a divide per trial scale (a gluon end's five
+    g -> f fbar trials share one coefficient, so only the largest of their
+    uniforms needs the log).  An end's dipole mass, z limits, overestimate
+    integral and coefficients (a divide, a square root and a log) change only
+    when an emission touches the end: they are charged for the two ends of
+    the initial dipole and for at most eight ends per emission (the new
+    parton's two, the emitter's and the spectator's towards it, and those of
+    their other colour partners).  Per cycle with a winner: the accept block,
+    t = exp(ln t), z from the overestimate (one exp), y, alpha_s from ln t,
+    kernel over overestimate.  Per accepted emission: the azimuth block,
+    sincos and the dipole map.  Per event: the matrix element and the
+    shower's start-up."""
     g_ends = (trials - ends) / 5.0      # gluon ends make 6 trials, quark ends 1
     q_ends = ends - g_ends
     winners = cycles - n_events         # every finished event ends on one empty cycle
     c = COST
-    per_end_setup = 8 + c["div"] + c["sqrt"] + c["log_fast"] + c["div"] + 6
-    per_q_end = per_end_setup + c["philox"] + c["unit"] + c["log_fast"] + c["div"] + 3
-    per_g_end = per_end_setup + 3 * c["philox"] + 6 * c["unit"] + 2 * c["log_fast"] + 2 * c["div"] + 12
+    end_setup = 8 + c["div"] + c["sqrt"] + c["log_fast"] + c["div"] + 6
+    setups = 2 * n_events + 8 * emissions
+    per_q_end = c["philox"] + c["unit"] + c["log_fast"] + c["div"] + 3
+    per_g_end = 3 * c["philox"] + 6 * c["unit"] + 2 * c["log_fast"] + 2 * c["div"] + 12
     per_winner = 2 * c["exp"] + c["philox"] + 2 * c["unit"] + 6 * c["div"] + 25
     per_emission = c["philox"] + c["unit"] + c["sincos"] + 3 * c["sqrt"] + 8 * c["div"] + 140
     per_event = 2 * c["philox"] + 3 * c["unit"] + c["sincos"] + c["sqrt"] + 3 * c["div"] + 60 + 2 * c["log_fast"]
-    return (q_ends * per_q_end + g_ends * per_g_end + winners * per_winner +
+    return (q_ends * per_q_end + g_ends * per_g_end + setups * end_setup + winners * per_winner +
             emissions * per_emission + n_events * per_event)
 
 
