@@ -148,24 +148,34 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
   const uint32_t cap = r.cap;
+  // After k_obs_scatter, cnt[b] is the end of bin b (bin = cap - parton
+  // count), so cnt[cap - m] counts the events with at least m partons; they
+  // sit at the front of perm, largest first.
   const uint64_t n_big = sc.threshold <= cap ? sc.cnt[cap - sc.threshold] : 0u;  // done by k_obs_wave
-  for (uint64_t q = n_big + t; q < n; q += step) {
+  const uint64_t n_mid = (uint32_t)kObsRegSlots < cap ? sc.cnt[cap - (kObsRegSlots + 1)] : n_big;
+  // events of at most kObsRegSlots partons, in event order (coalesced records and summaries)
+  for (uint64_t e = t; e < n; e += step) {
+    const int np = sm.i[kSiN * sm.stride + e];
+    if (np > kObsRegSlots) continue;
+    const int status = sm.i[kSiStatus * sm.stride + e];
+    const ObsOut o = reg_observables<kObsRegSlots>(r, e, np, in.ecm_of(e), status);
+    if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
+    for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
+    sm.i[kSiStatus * sm.stride + e] = o.status;
+  }
+  // the rest below the wave threshold, sorted by size, through the scratch
+  for (uint64_t q = n_big + t; q < n_mid; q += step) {
     const uint64_t e = sc.perm[q];
     const int status = sm.i[kSiStatus * sm.stride + e];
     const int np = sm.i[kSiN * sm.stride + e];
-    ObsOut o;
-    if (np <= kObsRegSlots) {
-      o = reg_observables<kObsRegSlots>(r, e, np, in.ecm_of(e), status);
-    } else {
-      for (int a = 0; a < np; ++a) {
-        const uint64_t from = (uint64_t)a * r.stride + e, to = (uint64_t)a * sc.stride + t;
-        sc.E[to] = r.E[from];
-        sc.x[to] = r.x[from];
-        sc.y[to] = r.y[from];
-        sc.z[to] = r.z[from];
-      }
-      o = scratch_observables(sc, t, np, in.ecm_of(e), status);
+    for (int a = 0; a < np; ++a) {
+      const uint64_t from = (uint64_t)a * r.stride + e, to = (uint64_t)a * sc.stride + t;
+      sc.E[to] = r.E[from];
+      sc.x[to] = r.x[from];
+      sc.y[to] = r.y[from];
+      sc.z[to] = r.z[from];
     }
+    const ObsOut o = scratch_observables(sc, t, np, in.ecm_of(e), status);
     if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
     for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
     sm.i[kSiStatus * sm.stride + e] = o.status;
@@ -248,6 +258,7 @@ __global__ void __launch_bounds__(64) k_obs_wave(Records r, Summary sm, EventInp
   uint16_t* list = (uint16_t*)(uz + cap);   // current Durham jets, in order
   const uint32_t lane = threadIdx.x;
   for (int a = lane; a < kHistDoubles; a += 64) lh[a] = 0.0;
+  // cnt[cap - m] = events with at least m partons (see k_obs)
   const uint32_t n_big = threshold <= cap ? cnt[cap - threshold] : 0u;
   __syncthreads();
   for (uint32_t q = blockIdx.x; q < n_big; q += gridDim.x) {

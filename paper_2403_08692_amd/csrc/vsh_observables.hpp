@@ -323,13 +323,18 @@ __device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, 
       if (m2 > best) { best = m2; bx = vx; by = vy; bz = vz; }
     }
   } else {
+    // the outer index runs as a loop (its momentum picked out of the
+    // registers), the inner ones unrolled over the M slots
+#pragma unroll 1
+    for (int i = 0; i + 1 < np; ++i) {
+      double xi = 0.0, yi = 0.0, zi = 0.0;
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
+      for (int a = 0; a < M; ++a)
+        if (a == i) { xi = X[a]; yi = Y[a]; zi = Z[a]; }
 #pragma unroll
-      for (int j = i + 1; j < M; ++j) {
-        if (j < np) {
-          const double nx = Y[i] * Z[j] - Z[i] * Y[j], ny = Z[i] * X[j] - X[i] * Z[j],
-                       nz = X[i] * Y[j] - Y[i] * X[j];
+      for (int j = 1; j < M; ++j) {
+        if (j > i && j < np) {
+          const double nx = yi * Z[j] - zi * Y[j], ny = zi * X[j] - xi * Z[j], nz = xi * Y[j] - yi * X[j];
           double vx = 0.0, vy = 0.0, vz = 0.0;
 #pragma unroll
           for (int k = 0; k < M; ++k) {
@@ -342,8 +347,7 @@ __device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, 
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const double si = (c < 2) ? 1.0 : -1.0, sj = (c & 1) ? -1.0 : 1.0;
-            const double wx = vx + si * X[i] + sj * X[j], wy = vy + si * Y[i] + sj * Y[j],
-                         wz = vz + si * Z[i] + sj * Z[j];
+            const double wx = vx + si * xi + sj * X[j], wy = vy + si * yi + sj * Y[j], wz = vz + si * zi + sj * Z[j];
             const double m2 = wx * wx + wy * wy + wz * wz;
             if (m2 > best) { best = m2; bx = wx; by = wy; bz = wz; }
           }
@@ -397,14 +401,19 @@ __device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, 
     for (int m = np; m > 2; --m) {
       double ymin = 0.0;
       int ia = -1, ib = -1;
+#pragma unroll 1
+      for (int a = 0; a + 1 < np; ++a) {
+        if (!(alive >> a & 1u)) continue;
+        double ea = 0.0, uxa = 0.0, uya = 0.0, uza = 0.0;
 #pragma unroll
-      for (int a = 0; a < M; ++a) {
+        for (int q = 0; q < M; ++q)
+          if (q == a) { ea = E[q]; uxa = UX[q]; uya = UY[q]; uza = UZ[q]; }
 #pragma unroll
-        for (int b = a + 1; b < M; ++b) {
-          if ((alive >> a & 1u) && (alive >> b & 1u)) {
-            const double dx = UX[a] - UX[b], dy = UY[a] - UY[b], dz = UZ[a] - UZ[b];
+        for (int b = 1; b < M; ++b) {
+          if (b > a && (alive >> b & 1u)) {
+            const double dx = uxa - UX[b], dy = uya - UY[b], dz = uza - UZ[b];
             const double d2 = (dx * dx + dy * dy) + dz * dz;
-            const double em = E[a] < E[b] ? E[a] : E[b];
+            const double em = ea < E[b] ? ea : E[b];
             const double y = em * em * d2 * inv_s;
             if (ia < 0 || y < ymin) {
               ymin = y;
