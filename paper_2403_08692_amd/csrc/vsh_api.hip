@@ -89,7 +89,7 @@ vsh_status validate_request(vsh_ctx* ctx, const vsh_request* req, bool need_ener
 // records, Durham scratch, summaries, per-event inputs, histogram.
 // ---------------------------------------------------------------------------
 uint64_t plain_bytes_per_event(uint32_t cap) {
-  return (uint64_t)cap * (4 * 8 + 1 + 4 * 2) + kNSumD * 8 + kNSumI * 4 + 8 + 2 * 8;
+  return (uint64_t)cap * (4 * 8 + 1 + 4 * 2 + kCacheWords * 8) + kNSumD * 8 + kNSumI * 4 + 8 + 2 * 8;
 }
 
 uint64_t plain_layout_bytes(uint64_t stride, uint32_t cap) {
@@ -117,6 +117,7 @@ PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap) {
   L.rec.apart = (uint16_t*)take(slots * 2);
   L.rec.stride = stride;
   L.rec.cap = cap;
+  L.cache = (uint64_t*)take(slots * kCacheWords * 8);
   {
     char* q = p;
     L.sc = carve_obs_scratch(q, stride, cap);
@@ -376,7 +377,7 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(ctx->ev[1], st));
-  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, L.sum, in, (uint32_t)count, st);
+  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, L.sum, in, (uint32_t)count, L.cache, st);
   else launch_shower_plain(L.rec, L.sum, in, (uint32_t)count, ctx->tuned.plain_block, ctx->tuned.plain_waves, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(ctx->ev[2], st));
@@ -690,7 +691,7 @@ vsh_status vsh_generate_into(vsh_ctx* ctx, const vsh_request* req, void* stream,
   if (tev) (void)hipEventRecord(tev[0], st);
   launch_me(L.rec, sum, in, (uint32_t)n, st);
   if (tev) (void)hipEventRecord(tev[1], st);
-  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, sum, in, (uint32_t)n, st);
+  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, sum, in, (uint32_t)n, L.cache, st);
   else launch_shower_plain(L.rec, sum, in, (uint32_t)n, ctx->tuned.plain_block, ctx->tuned.plain_waves, st);
   if (tev) (void)hipEventRecord(tev[2], st);
   launch_obs(L.rec, sum, in, L.sc, (uint32_t)n, dev_hist, st);

@@ -32,6 +32,7 @@ struct Arena {
 
 struct PlainLayout {
   Records rec;
+  uint64_t* cache;  // end cache of the flattened kernel, [event][cap] entries of kCacheWords words
   Scratch sc;
   Summary sum;
   double *ecm, *tcut, *hist;

@@ -464,7 +464,8 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
 // Plain one-launch form with the flattened mapping: wave w owns events
 // 64w .. 64w+63 of the batch (already started by k_me) from start to cutoff,
 // with no refill; finished lanes only stop contributing trial work.
-__global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n) {
+__global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n,
+                                                             EndCache ec) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
   const uint32_t words = mask_words(r.cap);
@@ -479,9 +480,8 @@ __global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary 
                sm.i[kSiN * sm.stride + e], (int)r.cap);
     mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
-  const EndCache none{nullptr, 0};
   while (__any(busy)) {
-    flat_cycle(sh, flat_gmask, words, s, busy, pend, pd, r, e, none, 0, lane);
+    flat_cycle(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane);
     if (busy && s.status != kRunning) {
       write_state(s, sm, e);
       busy = false;
@@ -492,10 +492,13 @@ __global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary 
 
 size_t flat_lds_bytes(uint32_t cap) { return (size_t)2 * 64 * ((cap + 63) / 64) * 8; }
 
+// cache: [event][cap] entries of kCacheWords words (column = event), or null
 void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
-                              hipStream_t st) {
+                              uint64_t* cache, hipStream_t st) {
   if (!n) return;
-  hipLaunchKernelGGL(k_shower_plain_flat, dim3((n + 63) / 64), dim3(64), flat_lds_bytes(r.cap), st, r, s, in, n);
+  const EndCache ec{cache, r.cap};
+  hipLaunchKernelGGL(k_shower_plain_flat, dim3((n + 63) / 64), dim3(64), flat_lds_bytes(r.cap), st, r, s, in, n,
+                     ec);
 }
 
 template <bool kInPlace>
