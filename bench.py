@@ -130,10 +130,10 @@ def cpu_baseline(w, serial_events=160_000, per_proc=40_000):
             "merged_histograms_equal_serial": same, "host_cpu": model or platform.processor()}
 
 
-def traffic_from_profile(kernel, kernel_src_hash):
+def traffic_from_profile(kernel, workload, kernel_src_hash):
     """HBM bytes per launch of the shower kernel from the committed counter
     summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_lep.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
@@ -267,6 +267,9 @@ def main():
     ap.add_argument("--form", choices=["plain", "persistent"], default="plain",
                     help="plain = the one-launch form the metric is quoted on (each wave keeps its events "
                          "from start to cutoff); persistent = the batched form (refill, in-place evolution)")
+    ap.add_argument("--workload", choices=["lep", "mixed", "stress"], default="lep",
+                    help="lep = the metric's configuration (default); mixed and stress time one other "
+                         "configuration alone (for profiling), without the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--events", type=int, default=0, help="override the batch size (testing only)")
     ap.add_argument("--quick", action="store_true", help="main LEP line only (no batched/stress/serving legs)")
@@ -280,9 +283,9 @@ def main():
 
     from paper_2403_08692_amd import workloads
 
-    w = workloads.LEP
+    w = {"lep": workloads.LEP, "mixed": workloads.MIXED, "stress": workloads.STRESS}[args.workload]
     n = args.events or w.n_events
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+    cpu = None if (args.no_cpu_baseline or args.workload != "lep") else cpu_baseline(w)
 
     import numpy as np
     import torch
@@ -292,11 +295,21 @@ def main():
 
     dev = torch.device("cuda:0")
     ctx = P.Context(0)
+    e_arr, t_arr = w.per_event(0, n)
+    m = min(n, 1 << 18)
     # launch settings of the timed form, picked by the library's autotuner on a sample of the workload
-    tuning = ctx.autotune(1 << 18, seed=w.seed, ecm=w.ecm, t_cut=w.tcut, max_partons=w.cap,
-                          persistent=args.form == "persistent")
+    tuning = ctx.autotune(m, seed=w.seed, ecm=w.ecm, t_cut=w.tcut, max_partons=w.cap,
+                          persistent=args.form == "persistent",
+                          ecm_per_event=None if e_arr is None else e_arr[:m],
+                          tcut_per_event=None if t_arr is None else t_arr[:m])
     flags = P.VSH_FORM_PERSISTENT if args.form == "persistent" else P.VSH_FORM_PLAIN
-    req, keep = make_request(n, w.seed, w.first_event, w.ecm, w.tcut, w.cap, flags)
+    e_dev = t_dev = None
+    if e_arr is not None:
+        e_dev = torch.from_numpy(e_arr).to(dev)
+        t_dev = torch.from_numpy(t_arr).to(dev)
+        flags |= P.VSH_INPUTS_ON_DEVICE
+    req, keep = make_request(n, w.seed, w.first_event, w.ecm, w.tcut, w.cap, flags,
+                             None if e_dev is None else e_dev.data_ptr(), None if t_dev is None else t_dev.data_ptr())
     ws_bytes = ctx.workspace_size(req)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     hist = torch.zeros(P.HIST_DOUBLES, dtype=torch.float64, device=dev)
@@ -333,7 +346,7 @@ def main():
     achieved = ops / (shower_ms * 1e-3) / 1e12
     h = hist.cpu().numpy().reshape(P.NOBS, P.NHCOL, 3)
     kernel = shower_kernel_name(args.form, tuning)
-    traffic = traffic_from_profile(kernel, kernel_source_hash())
+    traffic = traffic_from_profile(kernel, args.workload, kernel_source_hash())
 
     line = {
         "metric": METRIC,
@@ -348,7 +361,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_events": n, "sqrt_s_GeV": w.ecm, "t_cut_GeV2": w.tcut,
+        "config": {"workload": w.name, "n_events": n,
+                   "sqrt_s_GeV": w.ecm if e_arr is None else "per event", "t_cut_GeV2": w.tcut if t_arr is None else "per event",
                    "max_partons": w.cap, "seed": w.seed, "form": args.form, "tuning": tuning,
                    "step": "ME + shower + observables + histograms (vsh_generate_into)"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
@@ -368,7 +382,7 @@ def main():
     }
     if cpu:
         line["gpu_over_serial_oracle"] = value / cpu["serial_value"]
-    if not args.quick:
+    if not args.quick and args.workload == "lep":
         extra = {}
         # LEP through the other form, autotuned on a sample
         other = "plain" if args.form == "persistent" else "persistent"
