@@ -88,8 +88,11 @@ enum {
 /* request flags */
 #define VSH_SUMMARY 0x1u           /* return per-event summaries                       */
 #define VSH_RECORDS 0x2u           /* return the final partons of every event (CSR)     */
-#define VSH_FORM_PLAIN 0x0u        /* thread per event, one launch to the cutoff        */
-#define VSH_FORM_PERSISTENT 0x4u   /* persistent waves with ballot compaction + refill  */
+#define VSH_FORM_PLAIN 0x0u        /* one launch; each wave keeps its events (one lane
+                                      each, or 64 with their trials spread over the
+                                      lanes) from start to the cutoff                   */
+#define VSH_FORM_PERSISTENT 0x4u   /* persistent waves with ballot compaction + refill,
+                                      events evolving in their output records           */
 #define VSH_INPUTS_ON_DEVICE 0x8u  /* ecm_per_event / tcut_per_event are device pointers
                                       (vsh_generate_into only)                          */
 
@@ -222,7 +225,8 @@ typedef struct {
 vsh_status vsh_get_tuning(vsh_ctx *ctx, vsh_tuning *out);
 vsh_status vsh_set_tuning(vsh_ctx *ctx, const vsh_tuning *t);
 /* Time the candidate settings of the persistent form (or, with
-   VSH_FORM_PLAIN in sample->flags, the plain block size) on `sample`
+   VSH_FORM_PLAIN in sample->flags, the plain mapping, block size and register
+   budget) on `sample`
    (its first min(n_events, 2^18) events) and keep the fastest in ctx;
    *chosen (optional) receives it.  Candidates whose summaries differ from
    the first candidate's are rejected (VSH_E_INTERNAL). */

@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
   // After k_obs_scatter, cnt[b] is the end of bin b (bin = cap - parton
   // count), so cnt[cap - m] counts the events with at least m partons; they
   // sit at the front of perm, largest first.
-  const uint64_t n_big = sc.threshold <= cap ? sc.cnt[cap - sc.threshold] : 0u;  // done by k_obs_wave
+  const uint64_t n_big = sc.threshold <= cap ? sc.cnt[cap - sc.threshold] : 0u;  // done by k_obs_group
   const uint64_t n_mid = (uint32_t)kObsRegSlots < cap ? sc.cnt[cap - (kObsRegSlots + 1)] : n_big;
   // events of at most kObsRegSlots partons, in event order (coalesced records and summaries)
   for (uint64_t e = t; e < n; e += step) {
@@ -188,24 +188,29 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
 }
 
 // ---------------------------------------------------------------------------
-// Large events: one wave per event, partons in LDS.  Thrust's candidate
-// planes (i < j, four sign choices) and each Durham step's pair scan are
-// spread over the lanes; ties go to the smallest index in the serial scan
-// order (first maximum for thrust, first minimum for Durham, as in the
-// one-thread-per-event path).
+// Events of 12 partons and more: a group of G lanes per event (G = 16 for up
+// to 31 partons, four events per wave; G = 64 beyond), the group's partons
+// in LDS.  Thrust's candidate planes (i < j, four sign choices) and each
+// Durham step's pair scan are spread over the group's lanes; ties go to the
+// smallest index in the serial scan order (first maximum for thrust, first
+// minimum for Durham, as in the one-thread-per-event path).  A block is one
+// wave, whose LDS operations take effect in program order, so the groups
+// (which may run different numbers of steps) need no barrier between them.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  for (int d = G / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, G);
   return v;
 }
 
 // (value, index) -> largest value, smallest index among equal values
-__device__ __forceinline__ void wave_argmax(double& v, uint32_t& idx) {
+template <int G>
+__device__ __forceinline__ void group_argmax(double& v, uint32_t& idx) {
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const double ov = __shfl_xor(v, d);
-    const uint32_t oi = __shfl_xor(idx, d);
+  for (int d = G / 2; d >= 1; d >>= 1) {
+    const double ov = __shfl_xor(v, d, G);
+    const uint32_t oi = __shfl_xor(idx, d, G);
     if (ov > v || (ov == v && oi < idx)) {
       v = ov;
       idx = oi;
@@ -213,11 +218,12 @@ __device__ __forceinline__ void wave_argmax(double& v, uint32_t& idx) {
   }
 }
 
-__device__ __forceinline__ void wave_argmin(double& v, uint32_t& idx) {
+template <int G>
+__device__ __forceinline__ void group_argmin(double& v, uint32_t& idx) {
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const double ov = __shfl_xor(v, d);
-    const uint32_t oi = __shfl_xor(idx, d);
+  for (int d = G / 2; d >= 1; d >>= 1) {
+    const double ov = __shfl_xor(v, d, G);
+    const uint32_t oi = __shfl_xor(idx, d, G);
     if (ov < v || (ov == v && oi < idx)) {
       v = ov;
       idx = oi;
@@ -243,32 +249,38 @@ struct PairWalk {
   __device__ __forceinline__ uint32_t j() const { return i + 1 + r; }
 };
 
-__global__ void __launch_bounds__(64) k_obs_wave(Records r, Summary sm, EventInputs in, const uint32_t* perm,
-                                                 const uint32_t* cnt, uint32_t cap, uint32_t threshold,
-                                                 double* __restrict__ hist) {
+// events with lo_n <= partons < hi_n; `slots` (at most G * MV) LDS parton
+// slots per group
+template <int G, int MV>
+__global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventInputs in, const uint32_t* perm,
+                                                  const uint32_t* cnt, uint32_t cap, uint32_t lo_n, uint32_t hi_n,
+                                                  uint32_t slots, double* __restrict__ hist) {
+  constexpr uint32_t kGroups = 64 / G;
+  constexpr uint64_t kGroupBits = G == 64 ? ~0ull : ((1ull << (G % 64)) - 1ull);
   extern __shared__ double lds[];
-  double* lh = lds;                         // [kHistDoubles]
-  double* pE = lh + kHistDoubles;           // [cap] each
-  double* px = pE + cap;
-  double* py = px + cap;
-  double* pz = py + cap;
-  double* ux = pz + cap;
-  double* uy = ux + cap;
-  double* uz = uy + cap;
-  uint16_t* list = (uint16_t*)(uz + cap);   // current Durham jets, in order
-  const uint32_t lane = threadIdx.x;
-  for (int a = lane; a < kHistDoubles; a += 64) lh[a] = 0.0;
-  // cnt[cap - m] = events with at least m partons (see k_obs)
-  const uint32_t n_big = threshold <= cap ? cnt[cap - threshold] : 0u;
+  double* lh = lds;  // [kHistDoubles]
+  const uint32_t lane = threadIdx.x % G, grp = threadIdx.x / G;
+  double* pE = lh + kHistDoubles + (size_t)grp * 7 * slots;  // [slots] each
+  double* px = pE + slots;
+  double* py = px + slots;
+  double* pz = py + slots;
+  double* ux = pz + slots;
+  double* uy = ux + slots;
+  double* uz = uy + slots;
+  uint16_t* list = (uint16_t*)(lh + kHistDoubles + (size_t)kGroups * 7 * slots) + (size_t)grp * slots;
+  for (int a = threadIdx.x; a < kHistDoubles; a += 64) lh[a] = 0.0;
+  // cnt[cap - m] counts the events with at least m partons (see k_obs)
+  const uint32_t q_lo = hi_n <= cap ? cnt[cap - hi_n] : 0u;
+  const uint32_t q_hi = lo_n <= cap ? cnt[cap - lo_n] : 0u;
   __syncthreads();
-  for (uint32_t q = blockIdx.x; q < n_big; q += gridDim.x) {
+  for (uint32_t q = q_lo + blockIdx.x * kGroups + grp; q < q_hi; q += gridDim.x * kGroups) {
     const uint64_t e = perm[q];
     int status = sm.i[kSiStatus * sm.stride + e];
     const int np = sm.i[kSiN * sm.stride + e];
     const double ecm = in.ecm_of(e), sh = ecm * ecm;
     double tE = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, bad = 0.0, sum = 0.0;
     double mxx = 0.0, myy = 0.0, mzz = 0.0, mxy = 0.0, mxz = 0.0, myz = 0.0;
-    for (int a = lane; a < np; a += 64) {
+    for (int a = lane; a < np; a += G) {
       const uint64_t o = (uint64_t)a * r.stride + e;
       const P4 p{r.E[o], r.x[o], r.y[o], r.z[o]};
       pE[a] = p.e;
@@ -291,12 +303,11 @@ __global__ void __launch_bounds__(64) k_obs_wave(Records r, Summary sm, EventInp
       mxz += p.x * p.z * il;
       myz += p.y * p.z * il;
     }
-    tE = wave_sum(tE);
-    tx = wave_sum(tx);
-    ty = wave_sum(ty);
-    tz = wave_sum(tz);
-    bad = wave_sum(bad);
-    __syncthreads();
+    tE = group_sum<G>(tE);
+    tx = group_sum<G>(tx);
+    ty = group_sum<G>(ty);
+    tz = group_sum<G>(tz);
+    bad = group_sum<G>(bad);
     if (status == kDone) {
       const double tol = 1e-10 * ecm;
       if (bad >= 2.0) status = kNonFinite;
@@ -305,20 +316,20 @@ __global__ void __launch_bounds__(64) k_obs_wave(Records r, Summary sm, EventInp
     }
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     if (status == kDone) {
-      sum = wave_sum(sum);
-      mxx = wave_sum(mxx);
-      myy = wave_sum(myy);
-      mzz = wave_sum(mzz);
-      mxy = wave_sum(mxy);
-      mxz = wave_sum(mxz);
-      myz = wave_sum(myz);
+      sum = group_sum<G>(sum);
+      mxx = group_sum<G>(mxx);
+      myy = group_sum<G>(myy);
+      mzz = group_sum<G>(mzz);
+      mxy = group_sum<G>(mxy);
+      mxz = group_sum<G>(mxz);
+      myz = group_sum<G>(myz);
       // thrust over the candidate planes
       const uint32_t npairs = (uint32_t)np * (np - 1) / 2;
       double best = -1.0;
       uint32_t bidx = 0xFFFFFFFFu;
       double bx = 0.0, by = 0.0, bz = 1.0;
       PairWalk pw(lane, (uint32_t)np);
-      for (uint32_t pidx = lane; pidx < npairs; pidx += 64, pw.advance(64)) {
+      for (uint32_t pidx = lane; pidx < npairs; pidx += G, pw.advance(G)) {
         const uint32_t i = pw.i, j = pw.j();
         const double xi = px[i], yi = py[i], zi = pz[i], xj = px[j], yj = py[j], zj = pz[j];
         const double nx = yi * zj - zi * yj, ny = zi * xj - xi * zj, nz = xi * yj - yi * xj;
@@ -340,13 +351,13 @@ __global__ void __launch_bounds__(64) k_obs_wave(Records r, Summary sm, EventInp
       }
       double wbest = best;
       uint32_t widx = bidx;
-      wave_argmax(wbest, widx);
-      // the winning lane broadcasts its vector
+      group_argmax<G>(wbest, widx);
+      // the winning lane of the group broadcasts its vector
       const uint64_t who = __ballot(bidx == widx && best == wbest);
-      const int src = __ffsll((unsigned long long)who) - 1;
-      bx = __shfl(bx, src);
-      by = __shfl(by, src);
-      bz = __shfl(bz, src);
+      const uint32_t src = (uint32_t)__ffsll((unsigned long long)((who >> (grp * G)) & kGroupBits)) - 1;
+      bx = __shfl(bx, (int)src, G);
+      by = __shfl(by, (int)src, G);
+      bz = __shfl(bz, (int)src, G);
       const double lb = sqrt(wbest);
       double ax = 0.0, ay = 0.0, az = 1.0;
       if (lb > 0.0) { ax = bx / lb; ay = by / lb; az = bz / lb; }
@@ -358,7 +369,7 @@ __global__ void __launch_bounds__(64) k_obs_wave(Records r, Summary sm, EventInp
       v[3] = cpar > 0.0 ? cpar : 0.0;
       // hemispheres
       double hpE = 0, hpx = 0, hpy = 0, hpz = 0, hmE = 0, hmx = 0, hmy = 0, hmz = 0, bp = 0, bm = 0;
-      for (int a = lane; a < np; a += 64) {
+      for (int a = lane; a < np; a += G) {
         const double x = px[a], y = py[a], z = pz[a], en = pE[a];
         const double d = x * ax + y * ay + z * az;
         const double cx = y * az - z * ay, cy = z * ax - x * az, cz = x * ay - y * ax;
@@ -366,9 +377,9 @@ __global__ void __launch_bounds__(64) k_obs_wave(Records r, Summary sm, EventInp
         if (d >= 0.0) { hpE += en; hpx += x; hpy += y; hpz += z; bp += kt; }
         else { hmE += en; hmx += x; hmy += y; hmz += z; bm += kt; }
       }
-      hpE = wave_sum(hpE); hpx = wave_sum(hpx); hpy = wave_sum(hpy); hpz = wave_sum(hpz);
-      hmE = wave_sum(hmE); hmx = wave_sum(hmx); hmy = wave_sum(hmy); hmz = wave_sum(hmz);
-      bp = wave_sum(bp); bm = wave_sum(bm);
+      hpE = group_sum<G>(hpE); hpx = group_sum<G>(hpx); hpy = group_sum<G>(hpy); hpz = group_sum<G>(hpz);
+      hmE = group_sum<G>(hmE); hmx = group_sum<G>(hmx); hmy = group_sum<G>(hmy); hmz = group_sum<G>(hmz);
+      bp = group_sum<G>(bp); bm = group_sum<G>(bm);
       const double mp = hpE * hpE - hpx * hpx - hpy * hpy - hpz * hpz;
       const double mm = hmE * hmE - hmx * hmx - hmy * hmy - hmz * hmz;
       const double rho = (mp > mm ? mp : mm) / sh;
@@ -379,21 +390,20 @@ __global__ void __launch_bounds__(64) k_obs_wave(Records r, Summary sm, EventInp
       v[6] = bp > bm ? bp : bm;
       // Durham: pair scan over the current jets each step
       const double inv_s = 1.0 / sh;
-      for (int a = lane; a < np; a += 64) {
+      for (int a = lane; a < np; a += G) {
         list[a] = (uint16_t)a;
         const double l = sqrt(px[a] * px[a] + py[a] * py[a] + pz[a] * pz[a]);
         ux[a] = px[a] / l;
         uy[a] = py[a] / l;
         uz[a] = pz[a] / l;
       }
-      __syncthreads();
       int m = np;
       while (m > 2) {
         const uint32_t mp2 = (uint32_t)m * (m - 1) / 2;
         double ymin = INFINITY;
         uint32_t yidx = 0xFFFFFFFFu;
         PairWalk dw(lane, (uint32_t)m);
-        for (uint32_t pidx = lane; pidx < mp2; pidx += 64, dw.advance(64)) {
+        for (uint32_t pidx = lane; pidx < mp2; pidx += G, dw.advance(G)) {
           const int ja = list[dw.i], jb = list[dw.j()];
           const double dx = ux[ja] - ux[jb], dy = uy[ja] - uy[jb], dz = uz[ja] - uz[jb];
           const double d2 = (dx * dx + dy * dy) + dz * dz;
@@ -401,13 +411,12 @@ __global__ void __launch_bounds__(64) k_obs_wave(Records r, Summary sm, EventInp
           const double y = em * em * d2 * inv_s;
           if (y < ymin) { ymin = y; yidx = pidx; }
         }
-        wave_argmin(ymin, yidx);
+        group_argmin<G>(ymin, yidx);
         const PairWalk win(yidx, (uint32_t)m);
         const uint32_t ia = win.i, ib = win.j();
         if (m == 4) v[1] = ymin;
         if (m == 3) v[0] = ymin;
         const int ja = list[ia], jb = list[ib];
-        __syncthreads();
         if (lane == 0) {
           pE[ja] += pE[jb];
           px[ja] += px[jb];
@@ -418,34 +427,52 @@ __global__ void __launch_bounds__(64) k_obs_wave(Records r, Summary sm, EventInp
           uy[ja] = py[ja] / l;
           uz[ja] = pz[ja] / l;
         }
-        // drop jet ib from the list (at most kObsWaveMaxCap entries: 8 per lane)
-        uint16_t mv[kObsWaveMaxCap / 64];
+        // drop jet ib from the list: read the entries after it, then write them back one place down
+        uint16_t mv[MV];
 #pragma unroll
-        for (uint32_t k = 0; k < kObsWaveMaxCap / 64; ++k) {
-          const uint32_t a = ib + 1 + lane + 64 * k;
+        for (uint32_t k = 0; k < MV; ++k) {
+          const uint32_t a = ib + 1 + lane + G * k;
           mv[k] = a < (uint32_t)m ? list[a] : (uint16_t)0;
         }
-        __syncthreads();
 #pragma unroll
-        for (uint32_t k = 0; k < kObsWaveMaxCap / 64; ++k) {
-          const uint32_t a = ib + 1 + lane + 64 * k;
+        for (uint32_t k = 0; k < MV; ++k) {
+          const uint32_t a = ib + 1 + lane + G * k;
           if (a < (uint32_t)m) list[a - 1] = mv[k];
         }
         --m;
-        __syncthreads();
       }
       if (lane == 0) hist_fill_lds(lh, ObsOut{{v[0], v[1], v[2], v[3], v[4], v[5], v[6]}, status},
                                    sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
     }
     if (lane < 7) sm.d[(kSdY23 + lane) * sm.stride + e] = v[lane];
     if (lane == 0) sm.i[kSiStatus * sm.stride + e] = status;
-    __syncthreads();
   }
   __syncthreads();
-  for (int a = lane; a < kHistDoubles; a += 64) {
+  for (int a = threadIdx.x; a < kHistDoubles; a += 64) {
     const double val = lh[a];
     if (val != 0.0) unsafeAtomicAdd(&hist[a], val);
   }
+}
+
+// The group launches for records of capacity cap: 16 lanes for 12..31
+// partons, 64 lanes from 32 (events below 12 go to k_obs).
+uint32_t obs_group_launches(uint32_t cap, ObsGroupLaunch out[2]) {
+  uint32_t k = 0;
+  if (cap > kObsWaveMaxCap || kObsWaveThreshold > cap) return 0;
+  const uint32_t mid = 32;
+  {
+    const uint32_t slots = std::min<uint32_t>(mid - 1, cap);
+    out[k++] = ObsGroupLaunch{(const void*)k_obs_group<16, 2>, kObsWaveThreshold, mid, slots,
+                              (uint32_t)obs_group_lds(16, slots)};
+  }
+  if (cap >= mid)
+    out[k++] = ObsGroupLaunch{(const void*)k_obs_group<64, kObsWaveMaxCap / 64>, mid, cap + 1, cap,
+                              (uint32_t)obs_group_lds(64, cap)};
+  return k;
+}
+
+size_t obs_group_lds(uint32_t g, uint32_t slots) {
+  return (size_t)kHistDoubles * 8 + (size_t)(64 / g) * slots * (7 * 8 + 2) + 64;
 }
 
 // ---------------------------------------------------------------------------
@@ -536,13 +563,21 @@ void launch_obs(const Records& r, const Summary& s, const EventInputs& in, const
   hipLaunchKernelGGL(k_obs_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, n, r.cap, sc.cnt, sc.perm);
   const uint32_t blocks = (uint32_t)(std::min<uint64_t>(sc.stride, ((uint64_t)n + 255) / 256 * 256) / 256);
   hipLaunchKernelGGL(k_obs, dim3(blocks), dim3(256), 0, st, r, s, in, sc, n, hist);
-  if (sc.threshold <= r.cap) {
+  ObsGroupLaunch gl[2];
+  const uint32_t ng = obs_group_launches(r.cap, gl);
+  for (uint32_t k = 0; k < ng; ++k) {
     const uint32_t wb = (uint32_t)std::min<uint64_t>(n, kObsWaveBlocks);
-    hipLaunchKernelGGL(k_obs_wave, dim3(wb), dim3(64), obs_wave_lds(r.cap), st, r, s, in, (const uint32_t*)sc.perm,
-                       (const uint32_t*)sc.cnt, r.cap, sc.threshold, hist);
+    const uint32_t* perm = sc.perm;
+    const uint32_t* cnt = sc.cnt;
+    uint32_t cap = r.cap, lo = gl[k].lo, hi = gl[k].hi, slots = gl[k].slots;
+    Records rr = r;
+    Summary ss = s;
+    EventInputs ii = in;
+    double* hh = hist;
+    void* args[] = {&rr, &ss, &ii, &perm, &cnt, &cap, &lo, &hi, &slots, &hh};
+    (void)hipLaunchKernel(gl[k].fn, dim3(wb), dim3(64), args, gl[k].lds, st);
   }
 }
 
-size_t obs_wave_lds(uint32_t cap) { return (size_t)kHistDoubles * 8 + (size_t)cap * (7 * 8 + 2) + 64; }
 
 }  // namespace vsh

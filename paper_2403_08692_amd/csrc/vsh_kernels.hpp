@@ -92,7 +92,6 @@ constexpr uint32_t kObsWaveThreshold = 12;
 constexpr int kObsRegSlots = 8;  // events of at most this many partons: observables in registers
 constexpr uint32_t kObsWaveMaxCap = 512;
 constexpr uint32_t kObsWaveBlocks = 8192;
-size_t obs_wave_lds(uint32_t cap);
 
 }  // namespace vsh
 
@@ -109,8 +108,14 @@ __global__ void k_obs_scan(uint32_t* cnt, uint32_t nb);
 __global__ void k_obs_scatter(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt, uint32_t* perm);
 __global__ void k_zero_u32(uint32_t* p, uint32_t n);
 __global__ void k_me(Records r, Summary s, EventInputs in, uint32_t n);
-__global__ void k_obs_wave(Records r, Summary sm, EventInputs in, const uint32_t* perm, const uint32_t* cnt,
-                           uint32_t cap, uint32_t threshold, double* __restrict__ hist);
+// one launch of the group observables kernel: function, parton-count range
+// [lo, hi), LDS parton slots per group, dynamic LDS bytes
+struct ObsGroupLaunch {
+  const void* fn;
+  uint32_t lo, hi, slots, lds;
+};
+uint32_t obs_group_launches(uint32_t cap, ObsGroupLaunch out[2]);
+size_t obs_group_lds(uint32_t g, uint32_t slots);
 void launch_me(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
                hipStream_t st);
 void launch_shower_plain(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,

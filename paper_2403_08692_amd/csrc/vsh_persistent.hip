@@ -746,13 +746,17 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   void* a_obs[] = {&g.rec, &g.sum, &g.in, &g.sc, &g.n, &g.hist};
   const uint32_t ob = (uint32_t)(std::min<uint64_t>(g.sc.stride, (n + 255) / 256 * 256) / 256);
   GCHK(add_kernel((const void*)k_obs, dim3(ob), dim3(256), a_obs));
-  if (g.sc.threshold <= g.cap) {
-    g.perm_c = g.sc.perm;
-    g.cnt_c = g.sc.cnt;
-    g.thr = g.sc.threshold;
-    void* a_wave[] = {&g.rec, &g.sum, &g.in, &g.perm_c, &g.cnt_c, &g.cap, &g.thr, &g.hist};
+  g.perm_c = g.sc.perm;
+  g.cnt_c = g.sc.cnt;
+  ObsGroupLaunch gl[2];
+  const uint32_t ng = obs_group_launches(g.cap, gl);
+  for (uint32_t k = 0; k < ng; ++k) {
+    g.glo[k] = gl[k].lo;
+    g.ghi[k] = gl[k].hi;
+    g.gslots[k] = gl[k].slots;
+    void* a_grp[] = {&g.rec, &g.sum, &g.in, &g.perm_c, &g.cnt_c, &g.cap, &g.glo[k], &g.ghi[k], &g.gslots[k], &g.hist};
     const uint32_t wb = (uint32_t)std::min<uint64_t>(n, kObsWaveBlocks);
-    GCHK(add_kernel((const void*)k_obs_wave, dim3(wb), dim3(64), a_wave, (unsigned)obs_wave_lds(g.cap)));
+    GCHK(add_kernel(gl[k].fn, dim3(wb), dim3(64), a_grp, gl[k].lds));
   }
   GCHK(add_event(3));
   GCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
