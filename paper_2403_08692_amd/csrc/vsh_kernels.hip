@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
 }
 
 // ---------------------------------------------------------------------------
-// Events of 12 partons and more: a group of G lanes per event (G = 16 for up
+// Events of 9 partons and more: a group of G lanes per event (G = 16 for up
 // to 31 partons, four events per wave; G = 64 beyond), the group's partons
 // in LDS.  Thrust's candidate planes (i < j, four sign choices) and each
 // Durham step's pair scan are spread over the group's lanes; ties go to the
@@ -454,8 +454,9 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
   }
 }
 
-// The group launches for records of capacity cap: 16 lanes for 12..31
-// partons, 64 lanes from 32 (events below 12 go to k_obs).
+// The group launches for records of capacity cap: 16 lanes from
+// kObsWaveThreshold to 31 partons, 64 lanes from 32 (smaller events go to
+// k_obs).
 uint32_t obs_group_launches(uint32_t cap, ObsGroupLaunch out[2]) {
   uint32_t k = 0;
   if (cap > kObsWaveMaxCap || kObsWaveThreshold > cap) return 0;

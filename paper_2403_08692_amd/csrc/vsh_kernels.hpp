@@ -88,7 +88,7 @@ struct Scratch {
   uint32_t threshold;       // events with at least this many partons: one wave each
 };
 
-constexpr uint32_t kObsWaveThreshold = 12;
+constexpr uint32_t kObsWaveThreshold = 9;
 constexpr int kObsRegSlots = 8;  // events of at most this many partons: observables in registers
 constexpr uint32_t kObsWaveMaxCap = 512;
 constexpr uint32_t kObsWaveBlocks = 8192;
