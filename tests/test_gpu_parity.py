@@ -50,16 +50,16 @@ def test_energies_and_caps(ctx, oracle, ecm, tcut, cap):
 @pytest.mark.parametrize("persistent", [False, True])
 def test_large_events_both_observable_passes(ctx, oracle, persistent):
     # 500 GeV with t_C = 0.03: sizes from about 10 to 80 partons, so both
-    # observable passes (thread per event, wave per event) and their split
-    # of the sorted events are exercised
+    # lane-group widths of the observables (16 lanes up to 31 partons, a
+    # wave from 32) and their split of the sorted events are exercised
     g, o, rep = _run(ctx, oracle, 500, 5, 500.0, 0.03, 256, persistent=persistent)
     parity.assert_parity(rep)
     n = o["sum_i"][:, 0]
-    assert (n < 12).any() and (n >= 32).any()
+    assert (n < 32).any() and (n >= 32).any()
 
 
 def test_overflow_wave_pass(ctx, oracle):
-    # cap 40: overflowing events stop at 40 partons, on the wave pass
+    # cap 40: overflowing events stop at 40 partons, on the 64-lane groups
     g, o, rep = _run(ctx, oracle, 300, 6, 500.0, 0.03, 40)
     parity.assert_parity(rep)
     assert g["n_overflow"] > 0
