@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
   // events of at most kObsRegSlots partons, in event order (coalesced records and summaries)
   for (uint64_t e = t; e < n; e += step) {
     const int np = sm.i[kSiN * sm.stride + e];
-    if (np > kObsRegSlots) continue;
+    if (np > kObsRegSlots || (uint32_t)np >= sc.threshold) continue;  // the lane groups take those
     const int status = sm.i[kSiStatus * sm.stride + e];
     const ObsOut o = reg_observables<kObsRegSlots>(r, e, np, in.ecm_of(e), status);
     if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
@@ -444,7 +444,9 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
       if (lane == 0) hist_fill_lds(lh, ObsOut{{v[0], v[1], v[2], v[3], v[4], v[5], v[6]}, status},
                                    sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
     }
-    if (lane < 7) sm.d[(kSdY23 + lane) * sm.stride + e] = v[lane];
+#pragma unroll
+    for (uint32_t h = 0; h < 7; ++h)  // the group's lanes share the seven stores
+      if (h % G == lane) sm.d[(kSdY23 + h) * sm.stride + e] = v[h];
     if (lane == 0) sm.i[kSiStatus * sm.stride + e] = status;
   }
   __syncthreads();
@@ -457,18 +459,18 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
 // The group launches for records of capacity cap: 16 lanes from
 // kObsWaveThreshold to 31 partons, 64 lanes from 32 (smaller events go to
 // k_obs).
-uint32_t obs_group_launches(uint32_t cap, ObsGroupLaunch out[2]) {
+uint32_t obs_group_launches(uint32_t cap, ObsGroupLaunch out[3]) {
   uint32_t k = 0;
   if (cap > kObsWaveMaxCap || kObsWaveThreshold > cap) return 0;
-  const uint32_t mid = 32;
-  {
-    const uint32_t slots = std::min<uint32_t>(mid - 1, cap);
-    out[k++] = ObsGroupLaunch{(const void*)k_obs_group<16, 2>, kObsWaveThreshold, mid, slots,
+  const uint32_t t = kObsWaveThreshold;
+  {  // 16 lanes up to 31 partons
+    const uint32_t slots = std::min<uint32_t>(31, cap);
+    out[k++] = ObsGroupLaunch{(const void*)k_obs_group<16, 2>, std::max<uint32_t>(t, 9), 32, slots,
                               (uint32_t)obs_group_lds(16, slots)};
   }
-  if (cap >= mid)
-    out[k++] = ObsGroupLaunch{(const void*)k_obs_group<64, kObsWaveMaxCap / 64>, mid, cap + 1, cap,
-                              (uint32_t)obs_group_lds(64, cap)};
+  if (cap >= 32)  // a wave from 32
+    out[k++] = ObsGroupLaunch{(const void*)k_obs_group<64, kObsWaveMaxCap / 64>, std::max<uint32_t>(t, 32), cap + 1,
+                              cap, (uint32_t)obs_group_lds(64, cap)};
   return k;
 }
 
@@ -564,7 +566,7 @@ void launch_obs(const Records& r, const Summary& s, const EventInputs& in, const
   hipLaunchKernelGGL(k_obs_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, n, r.cap, sc.cnt, sc.perm);
   const uint32_t blocks = (uint32_t)(std::min<uint64_t>(sc.stride, ((uint64_t)n + 255) / 256 * 256) / 256);
   hipLaunchKernelGGL(k_obs, dim3(blocks), dim3(256), 0, st, r, s, in, sc, n, hist);
-  ObsGroupLaunch gl[2];
+  ObsGroupLaunch gl[3];
   const uint32_t ng = obs_group_launches(r.cap, gl);
   for (uint32_t k = 0; k < ng; ++k) {
     const uint32_t wb = (uint32_t)std::min<uint64_t>(n, kObsWaveBlocks);

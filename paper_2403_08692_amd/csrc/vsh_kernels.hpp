@@ -114,7 +114,7 @@ struct ObsGroupLaunch {
   const void* fn;
   uint32_t lo, hi, slots, lds;
 };
-uint32_t obs_group_launches(uint32_t cap, ObsGroupLaunch out[2]);
+uint32_t obs_group_launches(uint32_t cap, ObsGroupLaunch out[3]);
 size_t obs_group_lds(uint32_t g, uint32_t slots);
 void launch_me(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
                hipStream_t st);

@@ -748,7 +748,7 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   GCHK(add_kernel((const void*)k_obs, dim3(ob), dim3(256), a_obs));
   g.perm_c = g.sc.perm;
   g.cnt_c = g.sc.cnt;
-  ObsGroupLaunch gl[2];
+  ObsGroupLaunch gl[3];
   const uint32_t ng = obs_group_launches(g.cap, gl);
   for (uint32_t k = 0; k < ng; ++k) {
     g.glo[k] = gl[k].lo;

@@ -89,7 +89,7 @@ struct BatchGraph {
   EventInputs in{};
   Scratch sc{};
   uint32_t n = 0, nb = 0, cap = 0, thr = 0;
-  uint32_t glo[2] = {0, 0}, ghi[2] = {0, 0}, gslots[2] = {0, 0};
+  uint32_t glo[3] = {0, 0, 0}, ghi[3] = {0, 0, 0}, gslots[3] = {0, 0, 0};
   const uint32_t* perm_c = nullptr;
   const uint32_t* cnt_c = nullptr;
   double* hist = nullptr;
