@@ -341,7 +341,6 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     gmax = a > gmax ? a : gmax;
     qmax = b > qmax ? b : qmax;
   }
-  const uint32_t g_pad = (n_g + 63) & ~63u;
   constexpr uint32_t kItems = sizeof(sh.item) / sizeof(sh.item[0]);
   if (trial) {  // list this event's items (beyond the list's length rounds search the offsets instead)
     uint32_t gpos = (uint32_t)excl, qpos = n_g + (uint32_t)(excl >> 32);
@@ -367,18 +366,21 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   sh.trials[lane] = 0;
   sh.ends[lane] = 0;
   __syncthreads();
-  // --- trials, 64 items per round: the gluon section, then the quark section
-  for (uint32_t r0 = 0; r0 < g_pad + n_q; r0 += 64) {
-    const bool gsec = r0 < g_pad;
+  // --- trials, 64 items per round: the gluon items, then the quark items
+  // (a round may hold the end of one and the start of the other: its quark
+  // lanes finish early, in time the round takes for its gluons anyway)
+  const uint32_t run = gmax > qmax ? gmax : qmax;
+  for (uint32_t r0 = 0; r0 < n_g + n_q; r0 += 64) {
+    const uint32_t at = r0 + lane;  // position in the item list
+    const bool gsec = at < n_g;
     const uint32_t* st = gsec ? sh.gstart : sh.qstart;
-    const uint32_t b0 = gsec ? r0 : r0 - g_pad;  // first section index of this round
-    const uint32_t j = b0 + lane;
-    const bool active = j < (gsec ? n_g : n_q);
+    const uint32_t base = gsec ? 0u : n_g;  // list position of the section
+    const uint32_t j = at - base;           // index within the section
+    const bool active = at < n_g + n_q;
     double v = -INFINITY;
     uint32_t idx = kNoTrial;
     uint32_t o = 63, seg0 = 64, last = 0;
     if (active) {
-      const uint32_t at = gsec ? j : n_g + j;  // position in the item list
       uint32_t i;
       if (at < kItems) {
         const uint32_t it = sh.item[at];
@@ -388,7 +390,8 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
         o = owner_of(st, j);
         i = select_slot(gm + (uint64_t)o * words, words, j - st[o], gsec);
       }
-      seg0 = (st[o] > b0 ? st[o] : b0) - b0;
+      const uint32_t first = base + st[o];  // list position of the owner's first item in this section
+      seg0 = (first > r0 ? first : r0) - r0;
       last = (j + 1 == st[o + 1]) || lane == 63;
       const TrialCtx c{Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]}, sh.lt[o], sh.tcut[o],
                        sh.ltc[o], sh.cfac[o], sh.cycle[o]};
@@ -406,7 +409,6 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       atomicAdd(&sh.trials[o], nt);
       atomicAdd(&sh.ends[o], ne);
     }
-    const uint32_t run = gsec ? gmax : qmax;
     for (uint32_t d = 1; d < 64 && d < run; d <<= 1) {
       const double vn = __shfl_up(v, d);
       const uint32_t in = __shfl_up(idx, d);
@@ -415,7 +417,13 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
         idx = in;
       }
     }
-    if (active && last && beats(v, idx, sh.best_v[o], sh.best_idx[o])) {
+    // fold each run's best into its owner's: gluon runs first, then quark
+    // runs (one owner may end a run of each kind in the same round)
+    if (active && last && gsec && beats(v, idx, sh.best_v[o], sh.best_idx[o])) {
+      sh.best_v[o] = v;
+      sh.best_idx[o] = idx;
+    }
+    if (active && last && !gsec && beats(v, idx, sh.best_v[o], sh.best_idx[o])) {
       sh.best_v[o] = v;
       sh.best_idx[o] = idx;
     }
