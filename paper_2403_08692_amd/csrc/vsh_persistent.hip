@@ -159,7 +159,9 @@ struct FlatShared {
   uint32_t key[4][64];
   uint32_t cycle[64];
   uint32_t gstart[65], qstart[65];  // per-owner item offsets in the gluon and quark sections
+  uint32_t sstart[65];              // per-owner offsets in the list of stale partons
   uint16_t item[2048];              // the cycle's items, owner << 10 | parton: gluons, then quarks
+  uint16_t sitem[512];              // the cycle's stale partons, owner << 10 | parton
   double best_v[64];
   uint32_t best_idx[64];
   uint32_t trials[64], ends[64];
@@ -237,6 +239,38 @@ __device__ __forceinline__ uint64_t pack_meta(int pid, int k1, int k2) {
   return (uint64_t)(uint8_t)(int8_t)pid | ((uint64_t)(uint16_t)k1 << 8) | ((uint64_t)(uint16_t)k2 << 24);
 }
 
+// Rebuild the cache entry of parton i of the event in column `slot` from the
+// records (the stale rounds of a cycle).
+__device__ __forceinline__ void entry_build(double cfac, double tcut, const Records& r, uint64_t slot, int i,
+                                            const EndCache& ec, uint64_t col) {
+  uint64_t* ent = ec.rec + ((col * ec.cap) + (uint64_t)i) * kCacheWords;
+  const uint64_t oi = (uint64_t)i * r.stride + slot;
+  const int pid_i = r.pid[oi];
+  int k1 = r.cpart[oi], k2 = r.apart[oi];
+  if (k2 == k1) k2 = kNoPartner;
+  if (k1 > k2) {
+    const int t = k1;
+    k1 = k2;
+    k2 = t;
+  }
+  const P4 pi = r.load(i, slot);
+  uint64_t w[kCacheWords];
+  w[0] = pack_meta(pid_i, k1, k2);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int k = e == 0 ? k1 : k2;
+    double ca = 0.0, cb = 0.0;
+    if (k != kNoPartner) {
+      double q2, zm, zp, L;
+      if (!end_coeffs(cfac, tcut, pid_i, pi, r.load(k, slot), q2, zm, zp, L, ca, cb)) ca = cb = 0.0;
+    }
+    w[1 + 2 * e] = (uint64_t)__double_as_longlong(ca);
+    w[2 + 2 * e] = (uint64_t)__double_as_longlong(cb);
+  }
+#pragma unroll
+  for (int q = 0; q < kCacheWords; ++q) ent[q] = w[q];
+}
+
 __device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Records& r, uint64_t slot, int i,
                                                      const EndCache& ec, uint64_t col, bool stale, double& best,
                                                      uint32_t& widx, uint32_t& trials, uint32_t& ends) {
@@ -307,6 +341,11 @@ __device__ __forceinline__ bool beats(double v, uint32_t idx, double w, uint32_t
 // column `slot` of `slots`; its gluon mask at gm + lane * words.
 constexpr uint32_t kEmitDiv = 4;
 
+// kCached: the kernel has an end cache (ec); the cycle then starts with
+// rounds that rebuild the entries of stale partons, so that every trial
+// round reads fresh entries only.  Without it, each item computes its
+// parton's coefficients itself.
+template <bool kCached>
 __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_t words, EvState& s, bool busy,
                                            bool& pend, Pending& pd, const Records& slots, uint64_t slot,
                                            const EndCache& ec, uint64_t wave_col, uint32_t lane) {
@@ -314,41 +353,58 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   uint64_t* mym = gm + (uint64_t)lane * words;
   uint64_t* sm = gm + (uint64_t)64 * words;  // stale masks
   uint64_t* mys = sm + (uint64_t)lane * words;
-  // --- publish the events that make trials and the item ranges of both sections
-  uint32_t ng = 0;
+  // --- publish the events that make trials, the item ranges of both
+  // sections and of the stale partons (counts in 21-bit fields: at most 64
+  // events of 1024 partons)
+  constexpr uint64_t kF = (1ull << 21) - 1;
+  uint32_t ng = 0, ns = 0;
   if (trial)
-    for (uint32_t w = 0; w < words; ++w) ng += __popcll(mym[w]);
-  const uint64_t mine = trial ? (((uint64_t)((uint32_t)s.n - ng) << 32) | ng) : 0ull;
+    for (uint32_t w = 0; w < words; ++w) {
+      ng += __popcll(mym[w]);
+      if (kCached) ns += __popcll(mys[w]);
+    }
+  const uint64_t mine = trial ? ((uint64_t)ng | ((uint64_t)((uint32_t)s.n - ng) << 21) | ((uint64_t)ns << 42)) : 0ull;
   uint64_t incl = mine;
   for (uint32_t d = 1; d < 64; d <<= 1) {
     const uint64_t t = __shfl_up(incl, d);
     if (lane >= d) incl += t;
   }
   const uint64_t excl = incl - mine;
-  sh.gstart[lane] = (uint32_t)excl;
-  sh.qstart[lane] = (uint32_t)(excl >> 32);
+  sh.gstart[lane] = (uint32_t)(excl & kF);
+  sh.qstart[lane] = (uint32_t)((excl >> 21) & kF);
+  sh.sstart[lane] = (uint32_t)(excl >> 42);
   if (lane == 63) {
-    sh.gstart[64] = (uint32_t)incl;
-    sh.qstart[64] = (uint32_t)(incl >> 32);
+    sh.gstart[64] = (uint32_t)(incl & kF);
+    sh.qstart[64] = (uint32_t)((incl >> 21) & kF);
+    sh.sstart[64] = (uint32_t)(incl >> 42);
   }
   const uint64_t tot = __shfl(incl, 63);
-  const uint32_t n_g = (uint32_t)tot, n_q = (uint32_t)(tot >> 32);
+  const uint32_t n_g = (uint32_t)(tot & kF), n_q = (uint32_t)((tot >> 21) & kF), n_s = (uint32_t)(tot >> 42);
   // longest per-event run of items in either section: a round's segmented
   // max needs only the shuffle steps below it
-  uint32_t gmax = (uint32_t)mine, qmax = (uint32_t)(mine >> 32);
+  uint32_t gmax = (uint32_t)(mine & kF), qmax = (uint32_t)((mine >> 21) & kF);
   for (uint32_t d = 32; d >= 1; d >>= 1) {
     const uint32_t a = __shfl_xor(gmax, d), b = __shfl_xor(qmax, d);
     gmax = a > gmax ? a : gmax;
     qmax = b > qmax ? b : qmax;
   }
   constexpr uint32_t kItems = sizeof(sh.item) / sizeof(sh.item[0]);
-  if (trial) {  // list this event's items (beyond the list's length rounds search the offsets instead)
-    uint32_t gpos = (uint32_t)excl, qpos = n_g + (uint32_t)(excl >> 32);
-    uint64_t mw = 0;
+  constexpr uint32_t kSItems = sizeof(sh.sitem) / sizeof(sh.sitem[0]);
+  if (trial) {  // list this event's items (beyond the lists' lengths rounds search the offsets instead)
+    uint32_t gpos = (uint32_t)(excl & kF), qpos = n_g + (uint32_t)((excl >> 21) & kF), spos = (uint32_t)(excl >> 42);
+    uint64_t mw = 0, sw = 0;
     for (int a = 0; a < s.n; ++a) {
-      if ((a & 63) == 0) mw = mym[a >> 6];
+      if ((a & 63) == 0) {
+        mw = mym[a >> 6];
+        if (kCached) sw = mys[a >> 6];
+      }
+      const uint32_t item = (lane << 10) | (uint32_t)a;
       const uint32_t pos = ((mw >> (a & 63)) & 1ull) ? gpos++ : qpos++;
-      if (pos < kItems) sh.item[pos] = (uint16_t)((lane << 10) | (uint32_t)a);
+      if (pos < kItems) sh.item[pos] = (uint16_t)item;
+      if (kCached && ((sw >> (a & 63)) & 1ull)) {
+        if (spos < kSItems) sh.sitem[spos] = (uint16_t)item;
+        ++spos;
+      }
     }
   }
   sh.lt[lane] = s.lt;
@@ -366,6 +422,28 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   sh.trials[lane] = 0;
   sh.ends[lane] = 0;
   __syncthreads();
+  // --- rebuild the cache entries of the stale partons, 64 per round
+  if (kCached && n_s > 0) {
+    for (uint32_t r0 = 0; r0 < n_s; r0 += 64) {
+      const uint32_t at = r0 + lane;
+      if (at < n_s) {
+        uint32_t o, i;
+        if (at < kSItems) {
+          const uint32_t it = sh.sitem[at];
+          o = it >> 10;
+          i = it & 1023u;
+        } else {
+          o = owner_of(sh.sstart, at);
+          i = select_slot(sm + (uint64_t)o * words, words, at - sh.sstart[o], true);
+        }
+        entry_build(sh.cfac[o], sh.tcut[o], slots, sh.slot[o], (int)i, ec, wave_col + o);
+      }
+    }
+    __threadfence_block();  // the rebuilt entries are stored before any trial round reads them
+    __syncthreads();
+    if (trial)
+      for (uint32_t w = 0; w < words; ++w) mys[w] = 0ull;
+  }
   // --- trials, 64 items per round: the gluon items, then the quark items
   // (a round may hold the end of one and the start of the other: its quark
   // lanes finish early, in time the round takes for its gluons anyway)
@@ -398,10 +476,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       double best = c.ltc;
       uint32_t widx = kNoTrial;
       uint32_t nt = 0, ne = 0;
-      const uint64_t sw = sm[(uint64_t)o * words + (i >> 6)];
-      const bool stale = !ec.rec || ((sw >> (i & 63)) & 1ull);
-      parton_trials_cached(c, slots, sh.slot[o], (int)i, ec, wave_col + o, stale, best, widx, nt, ne);
-      if (stale && ec.rec) atomicAnd((unsigned long long*)&sm[(uint64_t)o * words + (i >> 6)], ~(1ull << (i & 63)));
+      parton_trials_cached(c, slots, sh.slot[o], (int)i, ec, wave_col + o, !kCached, best, widx, nt, ne);
       if (widx != kNoTrial) {
         v = best;
         idx = widx;
@@ -489,7 +564,7 @@ __global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary 
     mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
   while (__any(busy)) {
-    flat_cycle(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane);
+    flat_cycle<true>(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane);
     if (busy && s.status != kRunning) {
       write_state(s, sm, e);
       busy = false;
@@ -534,7 +609,7 @@ __global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
       busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane);
+    flat_cycle<kInPlace>(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane);
     if (busy && s.status != kRunning) {
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
       busy = false;
