@@ -357,6 +357,9 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   // sections and of the stale partons (counts in 21-bit fields: at most 64
   // events of 1024 partons)
   constexpr uint64_t kF = (1ull << 21) - 1;
+  // the cycle's accept block depends on the event and cycle only: drawn here,
+  // where its arithmetic overlaps the waits of the publishing
+  const U4 acc = trial ? accept_draw(s) : U4{0u, 0u, 0u, 0u};
   uint32_t ng = 0, ns = 0;
   if (trial)
     for (uint32_t w = 0; w < words; ++w) {
@@ -519,7 +522,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       end_limits(slots.load(w.i, slot), slots.load(w.k, slot), s.tcut, w.q2, w.zm, w.zp);
       w.L = log_fast((1.0 - w.zm) / (1.0 - w.zp));
     }
-    pend = veto_decide(s, best, w, pd);
+    pend = veto_decide_drawn(s, best, w, acc, pd);
   }
   // --- pending emissions, built together; the new parton's type goes into the mask
   const uint32_t n_pend = __popcll(__ballot(pend));

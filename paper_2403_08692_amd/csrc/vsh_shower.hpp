@@ -200,9 +200,11 @@ struct Pending {
 };
 
 // The decision part of one cycle once the winner is known: CheckCutoff,
-// alpha_s, AcceptOrVeto (App. C).  `best` is the winner's ln t.  Returns true
-// for an accepted emission that fits the record, described in p.
-__device__ __forceinline__ bool veto_decide(EvState& s, double best, const Winner& w, Pending& p) {
+// alpha_s, AcceptOrVeto (App. C).  `best` is the winner's ln t, `a` the
+// cycle's accept block (drawn ahead by the caller).  Returns true for an
+// accepted emission that fits the record, described in p.
+__device__ __forceinline__ bool veto_decide_drawn(EvState& s, double best, const Winner& w, const U4& a,
+                                                  Pending& p) {
   const uint32_t this_cycle = s.cycle++;
   if (w.i < 0) {  // no trial above the cutoff
     s.status = kDone;
@@ -210,7 +212,6 @@ __device__ __forceinline__ bool veto_decide(EvState& s, double best, const Winne
   }
   s.lt = best;  // the winner's scale bounds every later trial
   const double t = exp(best);
-  const U4 a = s.key.draw(this_cycle, kPurposeAccept, 0);
   // z from the overestimate's inverse integral: for the 1/(1-z) kernels
   // 1 - z = (1 - zm) ((1 - zp)/(1 - zm))^u = (1 - zm) exp(-u L)
   const double uz = unit(a.x, a.y);
@@ -226,6 +227,12 @@ __device__ __forceinline__ bool veto_decide(EvState& s, double best, const Winne
   }
   p = Pending{t, z, w.i, w.k, w.K, this_cycle};
   return true;
+}
+
+__device__ __forceinline__ U4 accept_draw(const EvState& s) { return s.key.draw(s.cycle, kPurposeAccept, 0); }
+
+__device__ __forceinline__ bool veto_decide(EvState& s, double best, const Winner& w, Pending& p) {
+  return veto_decide_drawn(s, best, w, accept_draw(s), p);
 }
 
 // GenerateEmission (App. C): kinematics, colours, flavours, and parton j
