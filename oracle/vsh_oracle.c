@@ -325,7 +325,7 @@ static uint64_t fnv_step(uint64_t h, uint32_t v) {
 }
 
 int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
-              int max_emit, int *n, double *p, int *pid, int *col, int *acol,
+              int max_cycles, int max_emit, int *n, double *p, int *pid, int *col, int *acol,
               int *cycles, uint64_t *emit_hash, int *n_emit,
               double *emit_log, int max_log, uint64_t *work) {
   int np = *n;
@@ -342,6 +342,12 @@ int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
   uint64_t hash = 0xcbf29ce484222325ull;
 
   while (status == OR_RUNNING) {
+    /* --- tail cut: an event still above the cutoff after max_cycles veto
+       cycles is given up and vetoed ----------------------------------- */
+    if (max_cycles > 0 && cycle >= (uint32_t)max_cycles) {
+      status = OR_TRUNCATED;
+      break;
+    }
     /* --- SelectWinnerEmission: every splitter, spectator, kernel ------- */
     double winner_t = tcut;
     int wi = -1, wk = -1, wK = -1;
@@ -701,12 +707,12 @@ static void hist_fill(double *hist, int h, double x, double w, const double *lo,
 
 int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
                 const double *ecm, double ecm0, const double *tcut,
-                double tcut0, int cap, double *sum_d, int32_t *sum_i,
+                double tcut0, int cap, int max_cycles, double *sum_d, int32_t *sum_i,
                 uint64_t *sum_hash, double *hist, int32_t *rec_n,
                 double *rec_p, int32_t *rec_pid, int32_t *rec_col,
                 int32_t *rec_acol, uint64_t *work) {
   enum { MAXCAP = 1024 };
-  if (cap < 2 || cap > MAXCAP) return -1;
+  if (cap < 2 || cap > MAXCAP || max_cycles < 0) return -1;
   static double p[4 * MAXCAP];
   static int pid[MAXCAP], col[MAXCAP], acol[MAXCAP];
   double lo[OR_NOBS], hi[OR_NOBS];
@@ -727,7 +733,7 @@ int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
     int n = 2, cycles = 0, nemit = 0;
     uint64_t hash = 0;
     uint64_t ew[OR_NWORK] = {0, 0, 0, 0, 0, 0};
-    int status = or_shower(seed, ev, E, tc, cap, -1, &n, p, pid, col, acol, &cycles,
+    int status = or_shower(seed, ev, E, tc, cap, max_cycles, -1, &n, p, pid, col, acol, &cycles,
                            &hash, &nemit, NULL, 0, ew);
     if (work)
       for (int k = 0; k < OR_NWORK; ++k) work[k] += ew[k];

@@ -25,7 +25,8 @@
  * and the no-emission probability against the Sudakov factor by quadrature;
  * thrust against brute force over every hemisphere split; C against the
  * eigenvalues of the momentum tensor; Durham against three-parton closed
- * forms and four-parton brute force; hemisphere masses against brute force.
+ * forms and four-parton brute force; hemisphere masses against brute force;
+ * the tail cut (max_cycles) against the first cycles of the uncut shower.
  * Whole showered events beyond the first emission have no external
  * reference: parity unpinned there (colour, flavour and momentum
  * conservation are checked, the distributions are not).
@@ -45,7 +46,10 @@ enum {
   OR_OVERFLOW = 2,    /* an accepted emission found the record full        */
   OR_NONFINITE = 3,   /* a non-finite momentum component                   */
   OR_CONSERVATION = 4,/* momentum conservation or masslessness violated    */
-  OR_STOPPED = 5      /* stopped after max_emit emissions (test runs only) */
+  OR_TRUNCATED = 5,   /* still above the cutoff after max_cycles veto cycles:
+                         the event is vetoed (the tail cut that the caption
+                         of Fig. 7 suggests studying)                      */
+  OR_STOPPED = 6      /* stopped after max_emit emissions (test runs only) */
 };
 
 enum { OR_NOBS = 8, OR_NBINS = 50, OR_NHCOL = OR_NBINS + 2 };
@@ -84,9 +88,12 @@ void or_split_kinematics(const double pi[4], const double pk[4], double t,
                          double out_j[4], double out_k[4]);
 
 /* Shower one event from the n0 partons given in p/pid/col/acol (arrays of
-   length cap, updated in place).  Returns the final status. */
+   length cap, updated in place).  Returns the final status.  max_cycles > 0
+   stops an event that has used that many veto cycles without reaching the
+   cutoff (status OR_TRUNCATED); 0 means no limit.  max_emit >= 0 stops after
+   that many emissions (test runs). */
 int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
-              int max_emit, int *n, double *p, int *pid, int *col, int *acol,
+              int max_cycles, int max_emit, int *n, double *p, int *pid, int *col, int *acol,
               int *cycles, uint64_t *emit_hash, int *n_emit,
               double *emit_log, int max_log, uint64_t *work);
 
@@ -103,10 +110,12 @@ void   or_hist_ranges(double lo[OR_NOBS], double hi[OR_NOBS]);
 /* Whole pipeline over events first .. first+n_events-1.  Per-event
    ecm/tcut arrays may be NULL (then ecm0/tcut0 are used).  Any output
    pointer may be NULL.  hist is [OR_NOBS][OR_NHCOL][3] (sum w, sum w^2,
-   entries), accumulated (not cleared).  Returns 0, or -1 on bad arguments. */
+   entries), accumulated (not cleared); only events that reach the cutoff
+   and validate fill it.  max_cycles as for or_shower.  Returns 0, or -1 on
+   bad arguments. */
 int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
                 const double *ecm, double ecm0, const double *tcut,
-                double tcut0, int cap, double *sum_d, int32_t *sum_i,
+                double tcut0, int cap, int max_cycles, double *sum_d, int32_t *sum_i,
                 uint64_t *sum_hash, double *hist, int32_t *rec_n,
                 double *rec_p, int32_t *rec_pid, int32_t *rec_col,
                 int32_t *rec_acol, uint64_t *work);

@@ -69,6 +69,8 @@ MUTANTS = [
     ("C-parameter prefactor", "double c = 1.5 * (sum * sum - dbl) / (sum * sum);",
      "double c = 1.0 * (sum * sum - dbl) / (sum * sum);"),
     ("wide broadening as the minimum", "*b_w = bp > bm ? bp : bm;", "*b_w = bp < bm ? bp : bm;"),
+    ("tail cut one cycle late", "if (max_cycles > 0 && cycle >= (uint32_t)max_cycles) {",
+     "if (max_cycles > 0 && cycle > (uint32_t)max_cycles) {"),
     ("heavy-jet mass as the lighter hemisphere", "double rho = (mp > mm ? mp : mm) / s;",
      "double rho = (mp < mm ? mp : mm) / s;"),
 ]

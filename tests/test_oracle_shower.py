@@ -118,6 +118,75 @@ def test_overflow_status_at_small_cap(oracle):
 
 
 # ---------------------------------------------------------------------------
+# Tail cut (the study that the caption of Fig. 7 suggests): an event still
+# above the cutoff after C veto cycles is given up and vetoed.  With the same
+# random numbers the cut run is the first C cycles of the full run.
+# ---------------------------------------------------------------------------
+def test_tail_cut_is_a_prefix_of_the_full_shower(oracle):
+    truncated = 0
+    for e in range(150):
+        f, _, _, _, p = oracle.me_event(2, e, 91.2)
+        args = (2, e, 91.2, 1.0, p, [f, -f], [1, 0], [0, 1])
+        full = oracle.shower(*args)
+        assert full["status"] == 1
+        for C in (1, 3, full["cycles"] // 2, full["cycles"] - 1, full["cycles"], full["cycles"] + 5):
+            if C < 1:
+                continue
+            cut = oracle.shower(*args, max_cycles=C)
+            if C >= full["cycles"]:  # the event reaches the cutoff in time: nothing changes
+                for k in ("status", "n", "cycles", "hash", "n_emit"):
+                    assert cut[k] == full[k], (e, C, k)
+                np.testing.assert_array_equal(cut["p"], full["p"])
+                continue
+            truncated += 1
+            assert cut["status"] == 5 and cut["cycles"] == C, (e, C)
+            m = cut["n_emit"]
+            assert m <= full["n_emit"] and cut["n"] == 2 + m
+            # its emissions are the first m of the full shower ...
+            np.testing.assert_array_equal(cut["log"], full["log"][:m])
+            # ... and its partons those after the m-th emission of the full shower
+            ref = oracle.shower(*args, max_emit=m) if m > 0 else dict(p=p, pid=[f, -f], col=[1, 0], acol=[0, 1])
+            np.testing.assert_array_equal(cut["p"], ref["p"])
+            for k in ("pid", "col", "acol"):
+                np.testing.assert_array_equal(cut[k], ref[k])
+    assert truncated > 300
+
+
+def _fill(h, x, w, lo, hi):
+    if not x >= lo:
+        b = 0
+    elif x >= hi:
+        b = 51
+    else:
+        b = min(1 + int((x - lo) / (hi - lo) * 50), 50)
+    h[b] += (w, w * w, 1.0)
+
+
+def test_tail_cut_vetoes_exactly_the_long_events(oracle):
+    n, C = 1500, 35
+    full = oracle.generate(9, 0, n, 91.2, 1.0, 64)
+    cut = oracle.generate(9, 0, n, 91.2, 1.0, 64, max_cycles=C)
+    long = full["sum_i"][:, 2] > C
+    assert 0.05 < long.mean() < 0.5
+    # events that end within C cycles are untouched
+    np.testing.assert_array_equal(cut["sum_i"][~long], full["sum_i"][~long])
+    np.testing.assert_array_equal(cut["sum_d"][~long], full["sum_d"][~long])
+    np.testing.assert_array_equal(cut["hash"][~long], full["hash"][~long])
+    # the others are given up after exactly C cycles, with no observables
+    assert (cut["sum_i"][long, 1] == 5).all() and (cut["sum_i"][long, 2] == C).all()
+    assert (cut["sum_d"][long, 2:9] == 0).all()
+    # the histograms hold the kept events only, filled as in the full run
+    lo, hi = oracle.hist_ranges()
+    ref = np.zeros_like(cut["hist"])
+    for e in np.flatnonzero(~long):
+        d = full["sum_d"][e]
+        xs = [np.log10(d[2]) if d[2] > 0 else -np.inf, np.log10(d[3]) if d[3] > 0 else -np.inf, *d[4:9], d[1]]
+        for h, x in enumerate(xs):
+            _fill(ref[h], x, d[0], lo[h], hi[h])
+    np.testing.assert_allclose(cut["hist"], ref, rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------------------
 # Veto algorithm against the Sudakov factor
 # ---------------------------------------------------------------------------
 def _alpha_s(t):
