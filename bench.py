@@ -164,9 +164,10 @@ def shower_kernel_name(form, tuning):
     return "k_shower_plain_flat" if tuning["plain_mapping"] == 1 else "k_shower_plain"
 
 
-def time_form(ctx, P, torch, w, n, form, steps, ecm_arr=None, tcut_arr=None):
+def time_form(ctx, P, torch, w, n, form, steps, ecm_arr=None, tcut_arr=None, cycle_limit=0, keep=False):
     """ms per step (ME + shower + observables + histograms) and the shower
-    kernel's mean ms for a workload through vsh_generate_into."""
+    kernel's mean ms for a workload through vsh_generate_into; with keep, also
+    the last step's histograms and per-event veto-cycle counts and statuses."""
     import numpy as np
 
     from paper_2403_08692_amd._native import make_request
@@ -178,8 +179,9 @@ def time_form(ctx, P, torch, w, n, form, steps, ecm_arr=None, tcut_arr=None):
         e_dev = torch.from_numpy(ecm_arr).to(dev)
         t_dev = torch.from_numpy(tcut_arr).to(dev)
         flags |= P.VSH_INPUTS_ON_DEVICE
-    req, keep = make_request(n, w.seed, w.first_event, w.ecm, w.tcut, w.cap, flags,
-                             None if e_dev is None else e_dev.data_ptr(), None if t_dev is None else t_dev.data_ptr())
+    req, _ = make_request(n, w.seed, w.first_event, w.ecm, w.tcut, w.cap, flags,
+                          None if e_dev is None else e_dev.data_ptr(), None if t_dev is None else t_dev.data_ptr(),
+                          cycle_limit)
     ws_bytes = ctx.workspace_size(req)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     hist = torch.zeros(P.HIST_DOUBLES, dtype=torch.float64, device=dev)
@@ -204,9 +206,60 @@ def time_form(ctx, P, torch, w, n, form, steps, ecm_arr=None, tcut_arr=None):
            "observables_ms": float(np.mean(stages[:, 2])), "n_done": int((s[1] == 1).sum()),
            "n_overflow": int((s[1] == 2).sum()), "max_cycles": int(s[2].max()),
            "cycles_per_event": float(s[2].mean())}
+    if keep:
+        out["hist"] = hist.cpu().numpy().reshape(P.NOBS, P.NHCOL, 3)
+        out["cycles"] = s[2].copy()
+        out["status"] = s[1].copy()
     del ws
     torch.cuda.empty_cache()
     return out
+
+
+def shape_chi2(h_a, h_b):
+    """chi^2/ndf between the normalised entry counts of two independent
+    samples (bins with entries in either): about 1 when they share one
+    distribution, the histogram bar of the GPU-oracle parity tests."""
+    import numpy as np
+
+    na, nb = h_a.sum(), h_b.sum()
+    pa, pb = h_a / na, h_b / nb
+    ok = (h_a + h_b) > 0
+    var = pa[ok] * (1 - pa[ok]) / na + pb[ok] * (1 - pb[ok]) / nb
+    return float(((pa[ok] - pb[ok]) ** 2 / np.maximum(var, 1e-300)).sum() / max(ok.sum() - 1, 1))
+
+
+def tail_cut_study(ctx, P, torch, w, n, refill_shower_ms):
+    """The study suggested with Fig. 7: cut the batch tail after C veto cycles
+    (C the cycle count by which a fraction q of the events has finished),
+    vetoing the events still above the cutoff.  Reports, per C, the plain
+    form's shower time saved and the bias of the kept events' distributions
+    against an independent uncut sample (another seed; the uncut GPU events
+    match the oracle's event by event)."""
+    import dataclasses
+
+    import numpy as np
+
+    full = time_form(ctx, P, torch, w, n, "plain", 5, keep=True)
+    ref = time_form(ctx, P, torch, dataclasses.replace(w, seed=w.seed + 1), n, "plain", 2, keep=True)
+    cyc = np.sort(full["cycles"])
+    names = ["log10_y23", "log10_y34", "tau", "C", "rho_H", "B_T", "B_W", "cos_theta"]
+
+    def chi2(h):
+        return {names[k]: round(shape_chi2(h[k, :, 2], ref["hist"][k, :, 2]), 2) for k in range(P.NOBS)}
+
+    rows = []
+    for q in (0.5, 0.9, 0.99, 0.999):
+        C = int(cyc[int(np.ceil(q * n)) - 1])
+        r = time_form(ctx, P, torch, w, n, "plain", 5, cycle_limit=C, keep=True)
+        kept = int((r["status"] == 1).sum())
+        rows.append({"finished_fraction": q, "cycle_limit": C, "vetoed_fraction": 1 - kept / n,
+                     "shower_ms": r["shower_ms"], "time_saved": 1 - r["shower_ms"] / full["shower_ms"],
+                     "sigma_shift": r["hist"][7, :, 0].sum() / full["hist"][7, :, 0].sum() - 1,
+                     "chi2_ndf": chi2(r["hist"])})
+    return {"workload": w.name, "uncut_plain_shower_ms": full["shower_ms"], "max_cycles": int(cyc[-1]),
+            "refill_shower_ms": refill_shower_ms,
+            "bias_measure": "chi^2/ndf of normalised entry counts against an uncut sample of the next seed",
+            "uncut_chi2_ndf": chi2(full["hist"]), "cuts": rows}
 
 
 def serving_bench(ctx, n_requests, rate_hz):
@@ -389,6 +442,10 @@ def main():
         tuned = ctx.autotune(1 << 18, seed=w.seed, ecm=w.ecm, t_cut=w.tcut, max_partons=w.cap,
                              persistent=other == "persistent")
         extra[f"lep_{other}"] = dict(time_form(ctx, P, torch, w, n, other, 10), tuning=tuned)
+        # the batch-tail cut of Fig. 7's caption against refill, on the plain form
+        refill_ms = extra["lep_persistent"]["shower_ms"] if other == "persistent" else line["stages_ms"]["shower"]
+        ctx.autotune(1 << 18, seed=w.seed, ecm=w.ecm, t_cut=w.tcut, max_partons=w.cap, persistent=False)
+        extra["tail_cut"] = tail_cut_study(ctx, P, torch, w, n, refill_ms)
         # mixed energies and cutoffs, 10^7 events in one persistent launch (and the plain form)
         m = workloads.MIXED
         e_arr, t_arr = m.per_event()

@@ -56,7 +56,9 @@ enum {
   VSH_EV_OVERFLOW = 2,     /* an accepted emission found the record full         */
   VSH_EV_NONFINITE = 3,    /* a momentum component is not finite                 */
   VSH_EV_CONSERVATION = 4, /* |sum p - (sqrt s, 0)| > 1e-10 sqrt s, or |p_i^2| > 1e-10 s */
-  VSH_EV_CYCLE_LIMIT = 5   /* stopped after 2^20 veto cycles (a guard; not reached in practice) */
+  VSH_EV_CYCLE_LIMIT = 5   /* still above the cutoff after the request's cycle_limit veto cycles
+                              (2^20 when 0: a guard, not reached in practice); vetoed: no
+                              observables, left out of the histograms                */
 };
 
 /* observables / histograms: 50 uniform bins [lo, hi) plus underflow (bin 0)
@@ -124,6 +126,11 @@ typedef struct {
   const double *tcut_per_event; /* optional [n_events]; likewise                       */
   uint32_t max_partons;  /* record capacity per event, 2..1024 (64, 128, 256 typical)  */
   uint32_t flags;        /* VSH_SUMMARY | VSH_RECORDS | VSH_FORM_*                     */
+  uint32_t cycle_limit;  /* tail cut (the study suggested with Fig. 7): an event still
+                            above the cutoff after this many veto cycles stops with
+                            VSH_EV_CYCLE_LIMIT and is vetoed.  0 = no cut (2^20 guard);
+                            values above 2^20 act as 2^20.  Events that end within the
+                            limit are exactly those of the uncut run.                */
 } vsh_request;
 
 /* Result of one request.  Library-owned host memory; release with
@@ -149,6 +156,7 @@ typedef struct {
   uint32_t max_cycles;        /* longest event, in veto cycles                       */
   double t_me_ms, t_shower_ms, t_obs_ms, t_total_ms; /* device time per stage; total is
                                                         host wall clock of the call  */
+  uint64_t n_cycle_limit;     /* events stopped by the request's cycle_limit        */
 } vsh_result;
 
 /* Blocking generation (Sec. 3 problem statement; App. C for the shower).

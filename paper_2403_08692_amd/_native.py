@@ -37,7 +37,7 @@ class vsh_request(C.Structure):
     _fields_ = [("n_events", C.c_uint64), ("seed", C.c_uint64), ("first_event", C.c_uint64),
                 ("ecm", C.c_double), ("t_cut", C.c_double),
                 ("ecm_per_event", C.c_void_p), ("tcut_per_event", C.c_void_p),
-                ("max_partons", C.c_uint32), ("flags", C.c_uint32)]
+                ("max_partons", C.c_uint32), ("flags", C.c_uint32), ("cycle_limit", C.c_uint32)]
 
 
 class vsh_tuning(C.Structure):
@@ -64,7 +64,7 @@ class vsh_result(C.Structure):
                 ("total_cycles", C.c_uint64), ("total_trials", C.c_uint64), ("total_ends", C.c_uint64),
                 ("total_emissions", C.c_uint64), ("max_cycles", C.c_uint32),
                 ("t_me_ms", C.c_double), ("t_shower_ms", C.c_double), ("t_obs_ms", C.c_double),
-                ("t_total_ms", C.c_double)]
+                ("t_total_ms", C.c_double), ("n_cycle_limit", C.c_uint64)]
 
 
 _lib = None
@@ -152,7 +152,7 @@ def _arr(ptr, count, dtype):
 def result_to_dict(res: vsh_result) -> dict:
     n = res.n_events
     out = dict(n_events=n, n_done=res.n_done, n_overflow=res.n_overflow, n_nonfinite=res.n_nonfinite,
-               n_conservation=res.n_conservation, sum_w=res.sum_w, sum_w2=res.sum_w2,
+               n_conservation=res.n_conservation, n_cycle_limit=res.n_cycle_limit, sum_w=res.sum_w, sum_w2=res.sum_w2,
                total_cycles=res.total_cycles, total_trials=res.total_trials, total_ends=res.total_ends,
                total_emissions=res.total_emissions, max_cycles=res.max_cycles,
                t_me_ms=res.t_me_ms, t_shower_ms=res.t_shower_ms, t_obs_ms=res.t_obs_ms,
@@ -176,9 +176,11 @@ def result_to_dict(res: vsh_result) -> dict:
 
 
 def make_request(n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=64, flags=0,
-                 ecm_per_event=None, tcut_per_event=None):
+                 ecm_per_event=None, tcut_per_event=None, cycle_limit=0):
     """Build a vsh_request; per-event arrays are numpy float64 (host) or
-    integer device addresses (with VSH_INPUTS_ON_DEVICE).  Returns (req, keepalive)."""
+    integer device addresses (with VSH_INPUTS_ON_DEVICE).  cycle_limit > 0
+    vetoes events still above the cutoff after that many veto cycles.
+    Returns (req, keepalive)."""
     keep = []
 
     def addr(a):
@@ -191,7 +193,7 @@ def make_request(n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_parto
         return a.ctypes.data
 
     req = vsh_request(int(n_events), int(seed), int(first_event), float(ecm), float(t_cut),
-                      addr(ecm_per_event), addr(tcut_per_event), int(max_partons), int(flags))
+                      addr(ecm_per_event), addr(tcut_per_event), int(max_partons), int(flags), int(cycle_limit))
     return req, keep
 
 
@@ -229,11 +231,12 @@ class Context:
         return load().vsh_last_error(self._ptr).decode()
 
     def generate(self, n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=64,
-                 summary=True, records=False, persistent=False, ecm_per_event=None, tcut_per_event=None):
+                 summary=True, records=False, persistent=False, ecm_per_event=None, tcut_per_event=None,
+                 cycle_limit=0):
         flags = (VSH_SUMMARY if summary else 0) | (VSH_RECORDS if records else 0) | \
                 (VSH_FORM_PERSISTENT if persistent else 0)
         req, keep = make_request(n_events, seed, first_event, ecm, t_cut, max_partons, flags,
-                                 ecm_per_event, tcut_per_event)
+                                 ecm_per_event, tcut_per_event, cycle_limit)
         res = C.POINTER(vsh_result)()
         _check(load().vsh_generate(self._ptr, C.byref(req), C.byref(res)), self._ptr)
         try:
@@ -300,10 +303,10 @@ class Context:
         return np.array(buf[:3 * n.value], np.float64).reshape(n.value, 3)
 
     def submit(self, n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=128, summary=False,
-               ecm_per_event=None, tcut_per_event=None):
+               ecm_per_event=None, tcut_per_event=None, cycle_limit=0):
         flags = VSH_SUMMARY if summary else 0
         req, keep = make_request(n_events, seed, first_event, ecm, t_cut, max_partons, flags,
-                                 ecm_per_event, tcut_per_event)
+                                 ecm_per_event, tcut_per_event, cycle_limit)
         t = C.c_uint64()
         _check(load().vsh_submit(self._ptr, C.byref(req), C.byref(t)), self._ptr)
         return t.value

@@ -211,6 +211,7 @@ void tally_chunk(ResultBox* b, const int32_t* si, const double* sd, uint64_t str
     r.n_overflow += st == kOverflow;
     r.n_nonfinite += st == kNonFinite;
     r.n_conservation += st == kConservation;
+    r.n_cycle_limit += st == kCycleLimitHit;
     const double w = sd[kSdW * stride + e];
     r.sum_w += w;
     r.sum_w2 += w * w;
@@ -317,6 +318,7 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
   EventInputs in{};
   in.seed = req->seed;
   in.first = req->first_event + first_idx;
+  in.cycle_limit = effective_cycle_limit(req->cycle_limit);
   in.ecm0 = req->ecm;
   in.tcut0 = req->t_cut;
   const bool from_records = caller_offsets != nullptr;
@@ -682,6 +684,7 @@ vsh_status vsh_generate_into(vsh_ctx* ctx, const vsh_request* req, void* stream,
   EventInputs in{};
   in.seed = req->seed;
   in.first = req->first_event;
+  in.cycle_limit = effective_cycle_limit(req->cycle_limit);
   in.ecm0 = req->ecm;
   in.tcut0 = req->t_cut;
   in.ecm = req->ecm_per_event;

@@ -36,6 +36,10 @@ enum : uint8_t { kRunning = 0, kDone = 1, kOverflow = 2, kNonFinite = 3, kConser
 // after a few hundred cycles; this bound only guarantees that every lane of
 // a launch exits whatever its inputs.
 constexpr uint32_t kCycleLimit = 1u << 20;
+// A request's tail cut (0 = none) as the cycle count the kernels compare with.
+constexpr uint32_t effective_cycle_limit(uint32_t requested) {
+  return requested == 0 || requested > kCycleLimit ? kCycleLimit : requested;
+}
 
 // draw purposes of the random-number contract
 enum : uint32_t { kPurposeME = 1, kPurposeTrial = 2, kPurposeAccept = 3, kPurposeSplit = 4 };

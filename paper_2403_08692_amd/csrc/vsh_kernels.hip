@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256, kWaves) k_shower_plain(Records r, Summary
              sm.i[kSiN * sm.stride + e], (int)r.cap);
   while (s.status == kRunning) {
     veto_cycle(s, r, e);
-    if (s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
+    if (s.cycle >= in.cycle_limit && s.status == kRunning) s.status = kCycleLimitHit;
   }
   write_state(s, sm, e);
 }

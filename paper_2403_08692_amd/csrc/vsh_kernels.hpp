@@ -64,6 +64,7 @@ struct EventInputs {
   const double *tcut;  // [n] or null -> tcut0
   double ecm0, tcut0;
   uint64_t seed, first;
+  uint32_t cycle_limit;  // veto cycles after which a running event is given up (>= 1)
   __device__ __forceinline__ double ecm_of(uint64_t e) const { return ecm ? ecm[e] : ecm0; }
   __device__ __forceinline__ double tcut_of(uint64_t e) const { return tcut ? tcut[e] : tcut0; }
 };

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
     if (!__any(busy)) break;  // counter exhausted and nothing left in this wave
     if (busy) {
       veto_cycle(s, A.slots, slot);
-      if (s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
+      if (s.status == kRunning && s.cycle >= A.reqs[req].cycle_limit) s.status = kCycleLimitHit;
       if (s.status != kRunning) {
         finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
         busy = false;
@@ -165,6 +165,7 @@ struct FlatShared {
   double best_v[64];
   uint32_t best_idx[64];
   uint32_t trials[64], ends[64];
+  uint32_t climit[64];  // each event's cycle limit
 };
 
 // per-owner gluon masks, then per-owner stale masks (partons whose cached end
@@ -544,7 +545,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     set_bit(mys, slots.apart[ok]);
     pend = false;
   }
-  if (busy && !pend && s.cycle >= kCycleLimit && s.status == kRunning) s.status = kCycleLimitHit;
+  if (busy && !pend && s.status == kRunning && s.cycle >= sh.climit[lane]) s.status = kCycleLimitHit;
 }
 
 // Plain one-launch form with the flattened mapping: wave w owns events
@@ -564,6 +565,7 @@ __global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary 
   if (busy) {
     init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e),
                sm.i[kSiN * sm.stride + e], (int)r.cap);
+    sh.climit[lane] = in.cycle_limit;
     mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
   while (__any(busy)) {
@@ -607,6 +609,7 @@ __global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
     if (refill<(kInPlace ? 16u : 1u)>(A, busy, 64, lane, since, drained, req, ev)) {
       slot = kInPlace ? ev : L;
       start_event<kInPlace>(s, A, A.reqs[req], ev, slot);
+      sh.climit[lane] = A.reqs[req].cycle_limit;
       mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, A.slots,
                 slot, s.n);
       busy = true;
@@ -867,6 +870,7 @@ static void fill_request_desc(ReqDev& d, const ReqBuffers& b, const vsh_request*
   d.seed = req->seed;
   d.first = req->first_event + first_idx;
   d.count = b.sum.stride;
+  d.cycle_limit = effective_cycle_limit(req->cycle_limit);
 }
 
 // One batch of `n` events of req (starting at request index first_idx)
@@ -909,6 +913,7 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
   in.tcut0 = req->t_cut;
   in.seed = req->seed;
   in.first = req->first_event + first_idx;
+  in.cycle_limit = effective_cycle_limit(req->cycle_limit);
   hipEvent_t* tev = timing_slot(ctx);
   if (use_graph) {
     BatchGraph& g = ctx->graph;
@@ -1040,6 +1045,7 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     in.tcut0 = req->t_cut;
     in.seed = req->seed;
     in.first = req->first_event + a;
+    in.cycle_limit = effective_cycle_limit(req->cycle_limit);
     launch_me(L.buf.out, L.buf.sum, in, (uint32_t)n, st);
     A.slots = L.buf.out;  // in place
     A.reqs = L.reqs;

@@ -18,6 +18,7 @@ struct ReqDev {
   double ecm0, tcut0;
   uint64_t seed, first;  // event ids first .. first + count - 1
   uint64_t count;
+  uint32_t cycle_limit;  // veto cycles after which a running event is given up (>= 1)
 };
 
 // a contiguous range of one request's events inside a launch's work space

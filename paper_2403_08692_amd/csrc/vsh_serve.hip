@@ -187,6 +187,7 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     in.tcut0 = r.req.t_cut;
     in.seed = r.req.seed;
     in.first = r.req.first_event;
+    in.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
     launch_me(r.buf.out, r.buf.sum, in, (uint32_t)n, S.drain);  // LO partons of every event
     (void)hipStreamSynchronize(S.drain);  // inputs and LO events on the device before any epoch reads them
     r.state = kAdmitted;
@@ -243,6 +244,7 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
     d.seed = r.req.seed;
     d.first = r.req.first_event;
     d.count = r.req.n_events;
+    d.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
     Segment& sg = E->segs_host[nseg];
     sg.req = nreq;
     sg.pad = 0;
@@ -319,6 +321,7 @@ static void start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
   in.tcut0 = r.req.t_cut;
   in.seed = r.req.seed;
   in.first = r.req.first_event;
+  in.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
   launch_obs(r.buf.out, r.buf.sum, in, sc, (uint32_t)n, r.buf.hist, S.drain);
   r.hist.resize(kHistDoubles);
   r.sd.resize((size_t)kNSumD * n);

@@ -24,3 +24,18 @@ def test_algorithmic_ops_scale():
     assert 5e4 < ops < 1.5e5
     # work is additive over events
     assert bench.algorithmic_ops(2, 246, 2 * 423, 62, 6) == pytest.approx(2 * ops)
+
+
+def test_shape_chi2_detects_a_biased_cut():
+    import numpy as np
+
+    import bench
+
+    rng = np.random.default_rng(3)
+    a, b = rng.normal(size=200_000), rng.normal(size=150_000)
+
+    def h(x):
+        return np.histogram(x, bins=50, range=(-3, 3))[0].astype(float)
+
+    assert 0.4 < bench.shape_chi2(h(a), h(b)) < 1.7  # same distribution (49 ndf: 1 +- 0.2)
+    assert bench.shape_chi2(h(a[np.abs(a) < 2.5]), h(b)) > 20  # tails cut away

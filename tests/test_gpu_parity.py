@@ -73,6 +73,32 @@ def test_overflow_small_cap(ctx, oracle):
     assert g["n_done"] + g["n_overflow"] == 800
 
 
+@pytest.mark.parametrize("form,mapping", [("plain", 1), ("plain", 0), ("persistent", 1), ("persistent", 0)])
+def test_tail_cut(ctx, oracle, form, mapping):
+    # events still above the cutoff after 30 veto cycles are vetoed (status 5,
+    # no observables, not histogrammed); the others are those of the uncut run
+    n, C = 3000, 30
+    persistent = form == "persistent"
+    key = "mapping" if persistent else "plain_mapping"
+    before = ctx.get_tuning()[key]
+    ctx.set_tuning(**{key: mapping})
+    try:
+        print(f"case tail cut n={n} C={C} form={form} mapping={mapping}", flush=True)
+        g = ctx.generate(n, seed=4, ecm=91.2, t_cut=1.0, max_partons=64, summary=True, records=True,
+                         persistent=persistent, cycle_limit=C)
+    finally:
+        ctx.set_tuning(**{key: before})
+    o = oracle.generate(4, 0, n, 91.2, 1.0, 64, records=True, max_cycles=C)
+    rep, same = parity.compare(g, o, 91.2, n)
+    print(rep, flush=True)
+    parity.assert_parity(rep)
+    cut = o["sum_i"][:, 1] == 5
+    assert 0.05 < cut.mean() < 0.6
+    assert g["n_cycle_limit"] == int(cut.sum()) and g["n_done"] == n - int(cut.sum())
+    assert (g["sum_i"][2][cut] == C).all()
+    assert g["hist"][7, :, 2].sum() == n - cut.sum()
+
+
 def test_mixed_energies_per_event(ctx, oracle):
     from paper_2403_08692_amd.workloads import mixed_energies
 

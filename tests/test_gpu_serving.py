@@ -22,7 +22,8 @@ def _same(a, b, tag):
     np.testing.assert_allclose(a["sum_d"], b["sum_d"], rtol=1e-12, atol=1e-15, err_msg=tag)
     # FP64 histogram sums may differ in summation order only
     np.testing.assert_allclose(a["hist"], b["hist"], rtol=1e-11, atol=1e-9, err_msg=tag)
-    for k in ("n_done", "n_overflow", "n_nonfinite", "n_conservation", "total_cycles", "total_trials"):
+    for k in ("n_done", "n_overflow", "n_nonfinite", "n_conservation", "n_cycle_limit", "total_cycles",
+              "total_trials"):
         assert a[k] == b[k], (tag, k)
 
 
@@ -33,6 +34,17 @@ def test_served_alone_equals_generate(ctx):
     got = ctx.wait(t)
     _same(got, ref, "alone")
     assert got["t_total_ms"] > 0
+
+
+def test_served_tail_cut_equals_generate(ctx):
+    # a request with a tail cut served beside uncut ones: each its own limit
+    kw = dict(seed=1002, ecm=91.2, t_cut=1.0, max_partons=64)
+    ref = ctx.generate(4000, summary=True, cycle_limit=25, **kw)
+    assert ref["n_cycle_limit"] > 0
+    full = ctx.submit(4000, summary=True, **kw)
+    cut = ctx.submit(4000, summary=True, cycle_limit=25, **kw)
+    _same(ctx.wait(cut), ref, "cut")
+    assert ctx.wait(full)["n_cycle_limit"] == 0
 
 
 def test_mix_equals_alone(ctx):
