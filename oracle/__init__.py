@@ -76,8 +76,8 @@ def lib():
     L.or_sigma_lo.restype = C.c_double
     L.or_me_event.argtypes = [C.c_uint64, C.c_uint64, C.c_double, _ip, _dp, _dp, _dp, _dp]
     L.or_split_kinematics.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
-    L.or_shower.argtypes = [C.c_uint64, C.c_uint64, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
-                            _ip, _dp, _ip, _ip, _ip, _ip, _u64p, _ip, _dp, C.c_int, _u64p]
+    L.or_shower.argtypes = [C.c_uint64, C.c_uint64, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
+                            C.c_int, _ip, _dp, _ip, _ip, _ip, _ip, _u64p, _ip, _dp, _dp, C.c_int, _u64p]
     L.or_shower.restype = C.c_int
     L.or_thrust.argtypes = [C.c_int, _dp, _dp]
     L.or_thrust.restype = C.c_double
@@ -90,7 +90,7 @@ def lib():
     L.or_observables.argtypes = [C.c_int, _dp, C.c_double, _dp]
     L.or_hist_ranges.argtypes = [_dp, _dp]
     L.or_generate.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, _dp, C.c_double, _dp, C.c_double,
-                              C.c_int, C.c_int, _dp, _i32p, _u64p, _dp, _i32p, _dp, _i32p, _i32p, _i32p, _u64p]
+                              C.c_int, C.c_int, C.c_double, _dp, _i32p, _u64p, _dp, _i32p, _dp, _i32p, _i32p, _i32p, _u64p]
     L.or_generate.restype = C.c_int
     _lib = L
     return L
@@ -168,10 +168,11 @@ def split_kinematics(pi, pk, t, z, phi):
     return oi, oj, ok
 
 
-def shower(seed, event, ecm, tcut, p, pid, col, acol, cap=64, max_emit=-1, max_log=64, max_cycles=0):
+def shower(seed, event, ecm, tcut, p, pid, col, acol, cap=64, max_emit=-1, max_log=64, max_cycles=0, t_over=0.0):
     """Shower one event from the given partons.  Returns a dict.  max_cycles > 0
     gives up (status TRUNCATED) an event still above the cutoff after that many
-    veto cycles."""
+    veto cycles; t_over > 0 takes alpha_s(t_over) for the trial density (the
+    weighted veto; the returned ``weight`` is the event's shower weight)."""
     n0 = len(pid)
     P = np.zeros((cap, 4))
     P[:n0] = np.asarray(p, np.float64).reshape(n0, 4)
@@ -184,12 +185,13 @@ def shower(seed, event, ecm, tcut, p, pid, col, acol, cap=64, max_emit=-1, max_l
     h = C.c_uint64()
     log = np.zeros((max_log, NLOG))
     work = np.zeros(NWORK, np.uint64)
-    st = lib().or_shower(seed, event, ecm, tcut, cap, int(max_cycles), max_emit, C.byref(n), _ptr(P, _dp), _ptr(PID, _ip),
-                         _ptr(COL, _ip), _ptr(ACOL, _ip), C.byref(cyc), C.byref(h), C.byref(nemit),
-                         _ptr(log, _dp), max_log, _ptr(work, _u64p))
+    wgt = C.c_double()
+    st = lib().or_shower(seed, event, ecm, tcut, cap, int(max_cycles), float(t_over), max_emit, C.byref(n),
+                         _ptr(P, _dp), _ptr(PID, _ip), _ptr(COL, _ip), _ptr(ACOL, _ip), C.byref(cyc), C.byref(h),
+                         C.byref(nemit), C.byref(wgt), _ptr(log, _dp), max_log, _ptr(work, _u64p))
     m = n.value
     return dict(status=st, n=m, p=P[:m].copy(), pid=PID[:m].copy(), col=COL[:m].copy(), acol=ACOL[:m].copy(),
-                cycles=cyc.value, hash=h.value, n_emit=nemit.value, log=log[:min(nemit.value, max_log)].copy(),
+                cycles=cyc.value, hash=h.value, n_emit=nemit.value, weight=wgt.value, log=log[:min(nemit.value, max_log)].copy(),
                 work=work)
 
 
@@ -244,7 +246,7 @@ def hist_ranges():
 
 
 def generate(seed, first, n_events, ecm=91.2, tcut=1.0, cap=64, records=False, ecm_arr=None, tcut_arr=None,
-             max_cycles=0):
+             max_cycles=0, t_over=0.0):
     """Run ME + shower + observables + histograms for events first..first+n-1.
 
     Returns a dict with per-event summaries (``sum_d`` [n, 10]: w, cos_theta,
@@ -252,7 +254,9 @@ def generate(seed, first, n_events, ecm=91.2, tcut=1.0, cap=64, records=False, e
     cycles, n_emit, flavour, trials, active dipole ends; ``hash`` [n]), histograms [8, 52, 3] and the
     work counters; with ``records`` also the final partons.  ``max_cycles`` > 0
     vetoes events still above the cutoff after that many veto cycles (status
-    TRUNCATED, left out of the histograms).
+    TRUNCATED, left out of the histograms); ``t_over`` > 0 runs the weighted
+    veto with alpha_s(t_over) in the trial density (event weights in ``sum_d``
+    field 0 and the histograms include the shower weight).
     """
     n_events = int(n_events)
     sum_d = np.zeros((n_events, NSUM_D))
@@ -268,7 +272,7 @@ def generate(seed, first, n_events, ecm=91.2, tcut=1.0, cap=64, records=False, e
     e_arr = None if ecm_arr is None else np.ascontiguousarray(ecm_arr, np.float64)
     t_arr = None if tcut_arr is None else np.ascontiguousarray(tcut_arr, np.float64)
     rc = lib().or_generate(seed, first, n_events, _ptr(e_arr, _dp), float(ecm), _ptr(t_arr, _dp), float(tcut),
-                           int(cap), int(max_cycles), _ptr(sum_d, _dp), _ptr(sum_i, _i32p), _ptr(hsh, _u64p), _ptr(hist, _dp),
+                           int(cap), int(max_cycles), float(t_over), _ptr(sum_d, _dp), _ptr(sum_i, _i32p), _ptr(hsh, _u64p), _ptr(hist, _dp),
                            _ptr(rec.get("n"), _i32p), _ptr(rec.get("p"), _dp), _ptr(rec.get("pid"), _i32p),
                            _ptr(rec.get("col"), _i32p), _ptr(rec.get("acol"), _i32p), _ptr(work, _u64p))
     if rc != 0:

@@ -325,12 +325,16 @@ static uint64_t fnv_step(uint64_t h, uint32_t v) {
 }
 
 int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
-              int max_cycles, int max_emit, int *n, double *p, int *pid, int *col, int *acol,
-              int *cycles, uint64_t *emit_hash, int *n_emit,
-              double *emit_log, int max_log, uint64_t *work) {
+              int max_cycles, double t_over, int max_emit, int *n, double *p, int *pid,
+              int *col, int *acol, int *cycles, uint64_t *emit_hash, int *n_emit,
+              double *weight, double *emit_log, int max_log, uint64_t *work) {
   int np = *n;
   double t = ecm * ecm;              /* evolution starts at s */
-  double asmax = or_alpha_s(tcut);   /* alpha_s overestimate = alpha_s(t_C) */
+  /* alpha_s of the trial density: alpha_s(t_C) bounds alpha_s(t) at every
+     t >= t_C.  A larger scale t_over makes the trial density fall below the
+     true one for t < t_over; the weighted veto below corrects for that. */
+  double asmax = or_alpha_s(t_over > 0.0 ? t_over : tcut);
+  double wgt = 1.0;
   int next_col = 1;
   for (int i = 0; i < np; ++i) {
     if (col[i] >= next_col) next_col = col[i] + 1;
@@ -407,7 +411,18 @@ int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
       if (work) work[5]++;
       double prob = or_alpha_s(t) / asmax * or_kernel_value(wK, z, y) * (1.0 - y) /
                     or_kernel_over(wK, z);
-      accept = uv < prob;
+      if (prob > 1.0) {
+        /* weighted veto where the true density exceeds the trial density:
+           accept with probability e, weight the event by prob / e if
+           accepted and (1 - prob) / (1 - e) if not; e = prob / (2 prob - 1)
+           minimises the variance of that factor, which is then
+           +-(2 prob - 1) */
+        double e = prob / (2.0 * prob - 1.0);
+        accept = uv < e;
+        wgt *= accept ? 2.0 * prob - 1.0 : -(2.0 * prob - 1.0);
+      } else {
+        accept = uv < prob;
+      }
     }
     if (!accept) continue;
 
@@ -482,6 +497,7 @@ int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
   if (cycles) *cycles = (int)cycle;
   if (emit_hash) *emit_hash = hash;
   if (n_emit) *n_emit = nemit;
+  if (weight) *weight = wgt;
   return status;
 }
 
@@ -707,12 +723,12 @@ static void hist_fill(double *hist, int h, double x, double w, const double *lo,
 
 int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
                 const double *ecm, double ecm0, const double *tcut,
-                double tcut0, int cap, int max_cycles, double *sum_d, int32_t *sum_i,
+                double tcut0, int cap, int max_cycles, double t_over, double *sum_d, int32_t *sum_i,
                 uint64_t *sum_hash, double *hist, int32_t *rec_n,
                 double *rec_p, int32_t *rec_pid, int32_t *rec_col,
                 int32_t *rec_acol, uint64_t *work) {
   enum { MAXCAP = 1024 };
-  if (cap < 2 || cap > MAXCAP || max_cycles < 0) return -1;
+  if (cap < 2 || cap > MAXCAP || max_cycles < 0 || t_over < 0.0) return -1;
   static double p[4 * MAXCAP];
   static int pid[MAXCAP], col[MAXCAP], acol[MAXCAP];
   double lo[OR_NOBS], hi[OR_NOBS];
@@ -733,8 +749,10 @@ int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
     int n = 2, cycles = 0, nemit = 0;
     uint64_t hash = 0;
     uint64_t ew[OR_NWORK] = {0, 0, 0, 0, 0, 0};
-    int status = or_shower(seed, ev, E, tc, cap, max_cycles, -1, &n, p, pid, col, acol, &cycles,
-                           &hash, &nemit, NULL, 0, ew);
+    double wsh = 1.0;
+    int status = or_shower(seed, ev, E, tc, cap, max_cycles, t_over, -1, &n, p, pid, col, acol,
+                           &cycles, &hash, &nemit, &wsh, NULL, 0, ew);
+    w *= wsh; /* the event weight: matrix element times weighted veto */
     if (work)
       for (int k = 0; k < OR_NWORK; ++k) work[k] += ew[k];
     double obs[7] = {0, 0, 0, 0, 0, 0, 0};

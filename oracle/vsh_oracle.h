@@ -90,12 +90,17 @@ void or_split_kinematics(const double pi[4], const double pk[4], double t,
 /* Shower one event from the n0 partons given in p/pid/col/acol (arrays of
    length cap, updated in place).  Returns the final status.  max_cycles > 0
    stops an event that has used that many veto cycles without reaching the
-   cutoff (status OR_TRUNCATED); 0 means no limit.  max_emit >= 0 stops after
-   that many emissions (test runs). */
+   cutoff (status OR_TRUNCATED); 0 means no limit.  t_over > 0 takes
+   alpha_s(t_over) for the trial density instead of alpha_s(t_C): below
+   t_over that is no overestimate, and the weighted veto (where the ratio r
+   exceeds 1: accept with probability r / (2r - 1), weight the event by
+   +-(2r - 1)) keeps every distribution exact on average; *weight returns
+   the product of those factors (1 with t_over = 0).
+   max_emit >= 0 stops after that many emissions (test runs). */
 int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
-              int max_cycles, int max_emit, int *n, double *p, int *pid, int *col, int *acol,
-              int *cycles, uint64_t *emit_hash, int *n_emit,
-              double *emit_log, int max_log, uint64_t *work);
+              int max_cycles, double t_over, int max_emit, int *n, double *p, int *pid,
+              int *col, int *acol, int *cycles, uint64_t *emit_hash, int *n_emit,
+              double *weight, double *emit_log, int max_log, uint64_t *work);
 
 /* observables */
 double or_thrust(int n, const double *p, double axis[3]);
@@ -111,11 +116,12 @@ void   or_hist_ranges(double lo[OR_NOBS], double hi[OR_NOBS]);
    ecm/tcut arrays may be NULL (then ecm0/tcut0 are used).  Any output
    pointer may be NULL.  hist is [OR_NOBS][OR_NHCOL][3] (sum w, sum w^2,
    entries), accumulated (not cleared); only events that reach the cutoff
-   and validate fill it.  max_cycles as for or_shower.  Returns 0, or -1 on
-   bad arguments. */
+   and validate fill it.  max_cycles and t_over as for or_shower; the event
+   weight (summary field 0, histograms) is the matrix-element weight times
+   the shower's.  Returns 0, or -1 on bad arguments. */
 int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
                 const double *ecm, double ecm0, const double *tcut,
-                double tcut0, int cap, int max_cycles, double *sum_d, int32_t *sum_i,
+                double tcut0, int cap, int max_cycles, double t_over, double *sum_d, int32_t *sum_i,
                 uint64_t *sum_hash, double *hist, int32_t *rec_n,
                 double *rec_p, int32_t *rec_pid, int32_t *rec_col,
                 int32_t *rec_acol, uint64_t *work);

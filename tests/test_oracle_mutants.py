@@ -71,6 +71,10 @@ MUTANTS = [
     ("wide broadening as the minimum", "*b_w = bp > bm ? bp : bm;", "*b_w = bp < bm ? bp : bm;"),
     ("tail cut one cycle late", "if (max_cycles > 0 && cycle >= (uint32_t)max_cycles) {",
      "if (max_cycles > 0 && cycle > (uint32_t)max_cycles) {"),
+    ("weighted veto: rejections keep a positive weight", "wgt *= accept ? 2.0 * prob - 1.0 : -(2.0 * prob - 1.0);",
+     "wgt *= accept ? 2.0 * prob - 1.0 : (2.0 * prob - 1.0);"),
+    ("weighted veto: always accept above the trial density", "accept = uv < e;", "accept = 1;"),
+    ("weighted veto: acceptance one half", "double e = prob / (2.0 * prob - 1.0);", "double e = 0.5;"),
     ("heavy-jet mass as the lighter hemisphere", "double rho = (mp > mm ? mp : mm) / s;",
      "double rho = (mp < mm ? mp : mm) / s;"),
 ]

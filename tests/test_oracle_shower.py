@@ -260,6 +260,46 @@ def test_first_emission_follows_sudakov(oracle, ecm, tc):
     assert ts.max() <= s / 4
 
 
+@pytest.mark.parametrize("t_over", [10.0, 300.0])
+def test_weighted_veto_follows_sudakov(oracle, t_over):
+    # alpha_s(t_over) in the trial density undershoots the true density below
+    # t_over; with the weighted veto the weighted first-emission distribution
+    # and the weighted no-emission probability are still the Sudakov ones
+    ecm, tc, n = 91.2, 1.0, 40_000
+    s = ecm * ecm
+    ts, ws = np.zeros(n), np.zeros(n)
+    for e in range(n):
+        f, c, ph, w, p = oracle.me_event(23, e, ecm)
+        r = oracle.shower(23, e, ecm, tc, p, [f, -f], [1, 0], [0, 1], cap=4, max_emit=1, max_log=1, t_over=t_over)
+        ts[e] = r["log"][0, 0] if r["n_emit"] else 0.0
+        ws[e] = r["weight"]
+    assert (ws < 0).any() and (ws > 1).any()  # the weights are in play
+    edges = np.exp(np.linspace(np.log(tc), np.log(s / 4), 16))
+    cdf = np.array([_sudakov_qqbar(x, s) for x in edges])
+    exp = np.concatenate([[cdf[0]], np.diff(cdf)]) * n
+    idx = np.where(ts > 0, np.searchsorted(edges, ts) , 0)  # 0 = no emission, b = bin b
+    W = np.bincount(idx, weights=ws, minlength=len(edges))
+    V = np.bincount(idx, weights=ws * ws, minlength=len(edges))
+    chi2 = ((W - exp) ** 2 / V).sum()
+    ndf = len(edges)
+    assert chi2 < ndf + 5 * np.sqrt(2 * ndf), chi2
+    # the same events unweighted fail that bar: the weights carry the correction
+    cnt = np.bincount(idx, minlength=len(edges))
+    assert ((cnt - exp) ** 2 / np.maximum(cnt, 1)).sum() > ndf + 5 * np.sqrt(2 * ndf)
+
+
+def test_weighted_veto_is_inert_when_the_trial_density_bounds(oracle):
+    # t_over at or below t_C keeps an overestimate: weights stay 1 and the
+    # events are those of the plain veto (t_over below t_C only wastes trials)
+    base = oracle.generate(31, 0, 300, 91.2, 1.0, 64)
+    same = oracle.generate(31, 0, 300, 91.2, 1.0, 64, t_over=1.0)
+    np.testing.assert_array_equal(same["sum_i"], base["sum_i"])
+    np.testing.assert_array_equal(same["sum_d"], base["sum_d"])
+    loose = oracle.generate(31, 0, 300, 91.2, 1.0, 64, t_over=0.5)
+    np.testing.assert_array_equal(loose["sum_d"][:, 0], base["sum_d"][:, 0])
+    assert (loose["sum_i"][:, 2] >= base["sum_i"][:, 2]).mean() > 0.5
+
+
 def test_no_emission_fraction_is_sudakov(oracle):
     n = 100_000
     r = oracle.generate(17, 0, n, 91.2, 1.0, 64)
