@@ -164,7 +164,8 @@ def shower_kernel_name(form, tuning):
     return "k_shower_plain_flat" if tuning["plain_mapping"] == 1 else "k_shower_plain"
 
 
-def time_form(ctx, P, torch, w, n, form, steps, ecm_arr=None, tcut_arr=None, cycle_limit=0, keep=False):
+def time_form(ctx, P, torch, w, n, form, steps, ecm_arr=None, tcut_arr=None, cycle_limit=0, keep=False,
+              t_over=0.0):
     """ms per step (ME + shower + observables + histograms) and the shower
     kernel's mean ms for a workload through vsh_generate_into; with keep, also
     the last step's histograms and per-event veto-cycle counts and statuses."""
@@ -181,7 +182,7 @@ def time_form(ctx, P, torch, w, n, form, steps, ecm_arr=None, tcut_arr=None, cyc
         flags |= P.VSH_INPUTS_ON_DEVICE
     req, _ = make_request(n, w.seed, w.first_event, w.ecm, w.tcut, w.cap, flags,
                           None if e_dev is None else e_dev.data_ptr(), None if t_dev is None else t_dev.data_ptr(),
-                          cycle_limit)
+                          cycle_limit, t_over)
     ws_bytes = ctx.workspace_size(req)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     hist = torch.zeros(P.HIST_DOUBLES, dtype=torch.float64, device=dev)
@@ -260,6 +261,46 @@ def tail_cut_study(ctx, P, torch, w, n, refill_shower_ms):
             "refill_shower_ms": refill_shower_ms,
             "bias_measure": "chi^2/ndf of normalised entry counts against an uncut sample of the next seed",
             "uncut_chi2_ndf": chi2(full["hist"]), "cuts": rows}
+
+
+def weighted_chi2(h_a, h_b):
+    """chi^2/ndf of two independent weighted histograms of the same
+    normalisation (sum w per bin, errors from sum w^2)."""
+    import numpy as np
+
+    v = h_a[:, 1] + h_b[:, 1]
+    ok = v > 0
+    return float(((h_a[ok, 0] - h_b[ok, 0]) ** 2 / v[ok]).sum() / max(ok.sum(), 1))
+
+
+def weighted_veto_study(ctx, P, torch, w, n):
+    """The extension of the veto algorithm to a trial density that is not an
+    overestimate (App. A footnote): alpha_s(t_over) in the trial density.
+    Reports, per t_over, the plain form's shower time and cycles, the weight
+    spread (effective sample size relative to the unweighted run), and the
+    weighted histograms against an unweighted sample of the next seed."""
+    import dataclasses
+
+    ref = time_form(ctx, P, torch, dataclasses.replace(w, seed=w.seed + 1), n, "plain", 2, keep=True)
+    names = ["log10_y23", "log10_y34", "tau", "C", "rho_H", "B_T", "B_W", "cos_theta"]
+
+    def neff(h):  # (sum w)^2 / sum w^2 over all histogrammed events, from the cos(theta) row
+        return h[7, :, 0].sum() ** 2 / h[7, :, 1].sum()
+
+    rows = []
+    base = None
+    for t_over in (0.0, 10.0, 100.0, 1000.0):
+        r = time_form(ctx, P, torch, w, n, "plain", 5, keep=True, t_over=t_over)
+        if base is None:
+            base = r
+        rel = neff(r["hist"]) / neff(base["hist"])
+        rows.append({"t_over": t_over, "shower_ms": r["shower_ms"], "cycles_per_event": r["cycles_per_event"],
+                     "ms_per_step": r["ms_per_step"], "neff_fraction": rel,
+                     "effective_events_per_s": r["events_per_s"] * rel,
+                     "sigma_ratio": r["hist"][7, :, 0].sum() / ref["hist"][7, :, 0].sum(),
+                     "chi2_ndf": {names[k]: round(weighted_chi2(r["hist"][k], ref["hist"][k]), 2)
+                                  for k in range(P.NOBS)}})
+    return {"workload": w.name, "reference": "unweighted run of the next seed", "rows": rows}
 
 
 def serving_bench(ctx, n_requests, rate_hz):
@@ -446,6 +487,7 @@ def main():
         refill_ms = extra["lep_persistent"]["shower_ms"] if other == "persistent" else line["stages_ms"]["shower"]
         ctx.autotune(1 << 18, seed=w.seed, ecm=w.ecm, t_cut=w.tcut, max_partons=w.cap, persistent=False)
         extra["tail_cut"] = tail_cut_study(ctx, P, torch, w, n, refill_ms)
+        extra["weighted_veto"] = weighted_veto_study(ctx, P, torch, w, n)
         # mixed energies and cutoffs, 10^7 events in one persistent launch (and the plain form)
         m = workloads.MIXED
         e_arr, t_arr = m.per_event()

@@ -131,6 +131,16 @@ typedef struct {
                             VSH_EV_CYCLE_LIMIT and is vetoed.  0 = no cut (2^20 guard);
                             values above 2^20 act as 2^20.  Events that end within the
                             limit are exactly those of the uncut run.                */
+  double t_over;         /* scale (GeV^2) of alpha_s in the trial density: 0 = t_cut, an
+                            overestimate (App. A), every shower weight 1.  A larger value
+                            makes fewer trials; below t_over the trial density undershoots,
+                            and the weighted veto (the extension for bounded ratios that
+                            App. A notes) keeps every distribution exact on average: where
+                            the ratio r of true to trial density exceeds 1 the emission is
+                            accepted with probability r/(2r - 1) and the event weight
+                            multiplied by +(2r - 1), or by -(2r - 1) on rejection.  Event
+                            weights (summary field 0, histograms, sum_w) include it.
+                            0 or > 0.01                                               */
 } vsh_request;
 
 /* Result of one request.  Library-owned host memory; release with

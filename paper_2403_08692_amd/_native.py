@@ -37,7 +37,8 @@ class vsh_request(C.Structure):
     _fields_ = [("n_events", C.c_uint64), ("seed", C.c_uint64), ("first_event", C.c_uint64),
                 ("ecm", C.c_double), ("t_cut", C.c_double),
                 ("ecm_per_event", C.c_void_p), ("tcut_per_event", C.c_void_p),
-                ("max_partons", C.c_uint32), ("flags", C.c_uint32), ("cycle_limit", C.c_uint32)]
+                ("max_partons", C.c_uint32), ("flags", C.c_uint32), ("cycle_limit", C.c_uint32),
+                ("t_over", C.c_double)]
 
 
 class vsh_tuning(C.Structure):
@@ -176,10 +177,11 @@ def result_to_dict(res: vsh_result) -> dict:
 
 
 def make_request(n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=64, flags=0,
-                 ecm_per_event=None, tcut_per_event=None, cycle_limit=0):
+                 ecm_per_event=None, tcut_per_event=None, cycle_limit=0, t_over=0.0):
     """Build a vsh_request; per-event arrays are numpy float64 (host) or
     integer device addresses (with VSH_INPUTS_ON_DEVICE).  cycle_limit > 0
-    vetoes events still above the cutoff after that many veto cycles.
+    vetoes events still above the cutoff after that many veto cycles; t_over
+    > 0 is the alpha_s scale of the trial density (weighted veto).
     Returns (req, keepalive)."""
     keep = []
 
@@ -193,7 +195,8 @@ def make_request(n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_parto
         return a.ctypes.data
 
     req = vsh_request(int(n_events), int(seed), int(first_event), float(ecm), float(t_cut),
-                      addr(ecm_per_event), addr(tcut_per_event), int(max_partons), int(flags), int(cycle_limit))
+                      addr(ecm_per_event), addr(tcut_per_event), int(max_partons), int(flags), int(cycle_limit),
+                      float(t_over))
     return req, keep
 
 
@@ -232,11 +235,11 @@ class Context:
 
     def generate(self, n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=64,
                  summary=True, records=False, persistent=False, ecm_per_event=None, tcut_per_event=None,
-                 cycle_limit=0):
+                 cycle_limit=0, t_over=0.0):
         flags = (VSH_SUMMARY if summary else 0) | (VSH_RECORDS if records else 0) | \
                 (VSH_FORM_PERSISTENT if persistent else 0)
         req, keep = make_request(n_events, seed, first_event, ecm, t_cut, max_partons, flags,
-                                 ecm_per_event, tcut_per_event, cycle_limit)
+                                 ecm_per_event, tcut_per_event, cycle_limit, t_over)
         res = C.POINTER(vsh_result)()
         _check(load().vsh_generate(self._ptr, C.byref(req), C.byref(res)), self._ptr)
         try:
@@ -303,10 +306,10 @@ class Context:
         return np.array(buf[:3 * n.value], np.float64).reshape(n.value, 3)
 
     def submit(self, n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=128, summary=False,
-               ecm_per_event=None, tcut_per_event=None, cycle_limit=0):
+               ecm_per_event=None, tcut_per_event=None, cycle_limit=0, t_over=0.0):
         flags = VSH_SUMMARY if summary else 0
         req, keep = make_request(n_events, seed, first_event, ecm, t_cut, max_partons, flags,
-                                 ecm_per_event, tcut_per_event, cycle_limit)
+                                 ecm_per_event, tcut_per_event, cycle_limit, t_over)
         t = C.c_uint64()
         _check(load().vsh_submit(self._ptr, C.byref(req), C.byref(t)), self._ptr)
         return t.value

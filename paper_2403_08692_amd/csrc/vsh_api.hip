@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -65,6 +66,10 @@ vsh_status validate_request(vsh_ctx* ctx, const vsh_request* req, bool need_ener
   }
   if (!req->tcut_per_event && !(req->t_cut > kMinTcut)) {
     set_error(ctx, "t_cut must be > %g GeV^2 (got %g)", kMinTcut, req->t_cut);
+    return VSH_E_INVALID;
+  }
+  if (!(req->t_over == 0.0 || (req->t_over > kMinTcut && std::isfinite(req->t_over)))) {
+    set_error(ctx, "t_over must be 0 or a finite value > %g GeV^2 (got %g)", kMinTcut, req->t_over);
     return VSH_E_INVALID;
   }
   if (!dev) {
@@ -319,6 +324,7 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
   in.seed = req->seed;
   in.first = req->first_event + first_idx;
   in.cycle_limit = effective_cycle_limit(req->cycle_limit);
+  in.t_over = req->t_over;
   in.ecm0 = req->ecm;
   in.tcut0 = req->t_cut;
   const bool from_records = caller_offsets != nullptr;
@@ -685,6 +691,7 @@ vsh_status vsh_generate_into(vsh_ctx* ctx, const vsh_request* req, void* stream,
   in.seed = req->seed;
   in.first = req->first_event;
   in.cycle_limit = effective_cycle_limit(req->cycle_limit);
+  in.t_over = req->t_over;
   in.ecm0 = req->ecm;
   in.tcut0 = req->t_cut;
   in.ecm = req->ecm_per_event;

@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(256, kWaves) k_shower_plain(Records r, Summary
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   EvState s;
-  init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e),
+  init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e), in.t_over,
              sm.i[kSiN * sm.stride + e], (int)r.cap);
   while (s.status == kRunning) {
     veto_cycle(s, r, e);

@@ -65,6 +65,7 @@ struct EventInputs {
   double ecm0, tcut0;
   uint64_t seed, first;
   uint32_t cycle_limit;  // veto cycles after which a running event is given up (>= 1)
+  double t_over;         // scale of alpha_s in the trial density, 0 = the event's t_C
   __device__ __forceinline__ double ecm_of(uint64_t e) const { return ecm ? ecm[e] : ecm0; }
   __device__ __forceinline__ double tcut_of(uint64_t e) const { return tcut ? tcut[e] : tcut0; }
 };

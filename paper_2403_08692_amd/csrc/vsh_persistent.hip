@@ -79,8 +79,8 @@ __device__ __forceinline__ void start_event(EvState& s, const PersistArgs& A, co
   const double ecm = R.ecm ? R.ecm[ev] : R.ecm0;
   const double tcut = R.tcut ? R.tcut[ev] : R.tcut0;
   const Keyed key = make_keyed(R.seed, R.first + ev);
-  if (kInPlace) lo_state(s, key, ecm, tcut, (int)R.out.cap);
-  else start_from_record(s, R.out, ev, A.slots, slot, key, ecm, tcut, (int)R.out.cap);
+  if (kInPlace) lo_state(s, key, ecm, tcut, R.t_over, (int)R.out.cap);
+  else start_from_record(s, R.out, ev, A.slots, slot, key, ecm, tcut, R.t_over, (int)R.out.cap);
 }
 
 // Record a finished event: its summary, and (unless in place) its partons
@@ -166,6 +166,7 @@ struct FlatShared {
   uint32_t best_idx[64];
   uint32_t trials[64], ends[64];
   uint32_t climit[64];  // each event's cycle limit
+  double wsh[64];       // each event's shower weight (weighted veto)
 };
 
 // per-owner gluon masks, then per-owner stale masks (partons whose cached end
@@ -523,7 +524,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       end_limits(slots.load(w.i, slot), slots.load(w.k, slot), s.tcut, w.q2, w.zm, w.zp);
       w.L = log_fast((1.0 - w.zm) / (1.0 - w.zp));
     }
-    pend = veto_decide_drawn(s, best, w, acc, pd);
+    pend = veto_decide_drawn(s, best, w, acc, pd, sh.wsh[lane]);
   }
   // --- pending emissions, built together; the new parton's type goes into the mask
   const uint32_t n_pend = __popcll(__ballot(pend));
@@ -563,14 +564,16 @@ __global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary 
   bool pend = false;
   Pending pd{};
   if (busy) {
-    init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e),
+    init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e), in.t_over,
                sm.i[kSiN * sm.stride + e], (int)r.cap);
     sh.climit[lane] = in.cycle_limit;
+    sh.wsh[lane] = 1.0;
     mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
   while (__any(busy)) {
     flat_cycle<true>(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane);
     if (busy && s.status != kRunning) {
+      s.wsh = sh.wsh[lane];
       write_state(s, sm, e);
       busy = false;
     }
@@ -610,6 +613,7 @@ __global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
       slot = kInPlace ? ev : L;
       start_event<kInPlace>(s, A, A.reqs[req], ev, slot);
       sh.climit[lane] = A.reqs[req].cycle_limit;
+      sh.wsh[lane] = 1.0;
       mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, A.slots,
                 slot, s.n);
       busy = true;
@@ -617,6 +621,7 @@ __global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
     if (!__any(busy)) break;
     flat_cycle<kInPlace>(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane);
     if (busy && s.status != kRunning) {
+      s.wsh = sh.wsh[lane];
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
       busy = false;
     }
@@ -871,6 +876,7 @@ static void fill_request_desc(ReqDev& d, const ReqBuffers& b, const vsh_request*
   d.first = req->first_event + first_idx;
   d.count = b.sum.stride;
   d.cycle_limit = effective_cycle_limit(req->cycle_limit);
+  d.t_over = req->t_over;
 }
 
 // One batch of `n` events of req (starting at request index first_idx)
@@ -914,6 +920,7 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
   in.seed = req->seed;
   in.first = req->first_event + first_idx;
   in.cycle_limit = effective_cycle_limit(req->cycle_limit);
+  in.t_over = req->t_over;
   hipEvent_t* tev = timing_slot(ctx);
   if (use_graph) {
     BatchGraph& g = ctx->graph;
@@ -1046,6 +1053,7 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     in.seed = req->seed;
     in.first = req->first_event + a;
     in.cycle_limit = effective_cycle_limit(req->cycle_limit);
+    in.t_over = req->t_over;
     launch_me(L.buf.out, L.buf.sum, in, (uint32_t)n, st);
     A.slots = L.buf.out;  // in place
     A.reqs = L.reqs;

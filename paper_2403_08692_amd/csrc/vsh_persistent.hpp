@@ -19,6 +19,7 @@ struct ReqDev {
   uint64_t seed, first;  // event ids first .. first + count - 1
   uint64_t count;
   uint32_t cycle_limit;  // veto cycles after which a running event is given up (>= 1)
+  double t_over;         // scale of alpha_s in the trial density, 0 = the event's t_C
 };
 
 // a contiguous range of one request's events inside a launch's work space

@@ -188,6 +188,7 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     in.seed = r.req.seed;
     in.first = r.req.first_event;
     in.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
+    in.t_over = r.req.t_over;
     launch_me(r.buf.out, r.buf.sum, in, (uint32_t)n, S.drain);  // LO partons of every event
     (void)hipStreamSynchronize(S.drain);  // inputs and LO events on the device before any epoch reads them
     r.state = kAdmitted;
@@ -245,6 +246,7 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
     d.first = r.req.first_event;
     d.count = r.req.n_events;
     d.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
+    d.t_over = r.req.t_over;
     Segment& sg = E->segs_host[nseg];
     sg.req = nreq;
     sg.pad = 0;
@@ -322,6 +324,7 @@ static void start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
   in.seed = r.req.seed;
   in.first = r.req.first_event;
   in.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
+  in.t_over = r.req.t_over;
   launch_obs(r.buf.out, r.buf.sum, in, sc, (uint32_t)n, r.buf.hist, S.drain);
   r.hist.resize(kHistDoubles);
   r.sd.resize((size_t)kNSumD * n);

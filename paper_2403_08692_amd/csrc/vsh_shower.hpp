@@ -58,6 +58,7 @@ struct EvState {
   uint32_t cycle, trials, ends;
   int n, next_col, n_emit, status;
   int cap;  // record capacity of this event (its request's)
+  double wsh;  // shower weight of the weighted veto (1 while the trial density bounds)
 };
 
 // what a trial needs to know about its event
@@ -204,7 +205,7 @@ struct Pending {
 // cycle's accept block (drawn ahead by the caller).  Returns true for an
 // accepted emission that fits the record, described in p.
 __device__ __forceinline__ bool veto_decide_drawn(EvState& s, double best, const Winner& w, const U4& a,
-                                                  Pending& p) {
+                                                  Pending& p, double& wsh) {
   const uint32_t this_cycle = s.cycle++;
   if (w.i < 0) {  // no trial above the cutoff
     s.status = kDone;
@@ -220,7 +221,17 @@ __device__ __forceinline__ bool veto_decide_drawn(EvState& s, double best, const
   if (!(y < 1.0)) return false;
   const double prob =
       alpha_s_of_log(best) / s.asmax * kernel_value(w.K, z, y) * (1.0 - y) / kernel_over(w.K, z);
-  if (!(unit(a.z, a.w) < prob)) return false;
+  if (prob > 1.0) {
+    // the trial density undershoots here (alpha_s of the trial density taken
+    // above t_C): weighted veto, accept with probability r / (2r - 1) and
+    // weight the event by +-(2r - 1), the least-variance choice
+    const double g = 2.0 * prob - 1.0;
+    const bool acc = unit(a.z, a.w) < prob / g;
+    wsh *= acc ? g : -g;
+    if (!acc) return false;
+  } else if (!(unit(a.z, a.w) < prob)) {
+    return false;
+  }
   if (s.n == s.cap) {
     s.status = kOverflow;
     return false;
@@ -232,7 +243,7 @@ __device__ __forceinline__ bool veto_decide_drawn(EvState& s, double best, const
 __device__ __forceinline__ U4 accept_draw(const EvState& s) { return s.key.draw(s.cycle, kPurposeAccept, 0); }
 
 __device__ __forceinline__ bool veto_decide(EvState& s, double best, const Winner& w, Pending& p) {
-  return veto_decide_drawn(s, best, w, accept_draw(s), p);
+  return veto_decide_drawn(s, best, w, accept_draw(s), p, s.wsh);
 }
 
 // GenerateEmission (App. C): kinematics, colours, flavours, and parton j
@@ -324,14 +335,21 @@ __device__ __forceinline__ void veto_cycle(EvState& s, const Records& r, uint64_
 }
 
 // Fresh state for an event whose n initial partons sit in slot e of r.
+// alpha_s of the trial density: alpha_s(t_C), an overestimate at every
+// t >= t_C, unless a scale t_over > 0 is given (then the weighted veto)
+__device__ __forceinline__ double trial_alpha_s(double ltc, double t_over) {
+  return alpha_s_of_log(t_over > 0.0 ? log_fast(t_over) : ltc);
+}
+
 __device__ __forceinline__ void init_state(EvState& s, const Records& r, uint64_t e, const Keyed& key,
-                                           double ecm, double tcut, int n, int cap) {
+                                           double ecm, double tcut, double t_over, int n, int cap) {
   s.cap = cap;
   s.key = key;
   s.tcut = tcut;
   s.ltc = log_fast(tcut);
-  s.asmax = alpha_s_of_log(s.ltc);  // the overestimate alpha_s(t_C)
+  s.asmax = trial_alpha_s(s.ltc, t_over);
   s.cfac = s.asmax / (2.0 * kPi);
+  s.wsh = 1.0;
   s.lt = log_fast(ecm * ecm);  // evolution starts at s
   s.hash = kFnvOffset;
   s.cycle = 0;
@@ -350,12 +368,14 @@ __device__ __forceinline__ void init_state(EvState& s, const Records& r, uint64_
 }
 
 // State of an event that starts from its two LO partons (colour line 1).
-__device__ __forceinline__ void lo_state(EvState& s, const Keyed& key, double ecm, double tcut, int cap) {
+__device__ __forceinline__ void lo_state(EvState& s, const Keyed& key, double ecm, double tcut, double t_over,
+                                         int cap) {
   s.key = key;
   s.tcut = tcut;
   s.ltc = log_fast(tcut);
-  s.asmax = alpha_s_of_log(s.ltc);
+  s.asmax = trial_alpha_s(s.ltc, t_over);
   s.cfac = s.asmax / (2.0 * kPi);
+  s.wsh = 1.0;
   s.lt = log_fast(ecm * ecm);
   s.hash = kFnvOffset;
   s.cycle = 0;
@@ -371,7 +391,8 @@ __device__ __forceinline__ void lo_state(EvState& s, const Keyed& key, double ec
 // Start the event whose LO partons the matrix-element pass left in slots 0
 // and 1 of `from` (column `ev`, no partner links there) in working slot e of r.
 __device__ __forceinline__ void start_from_record(EvState& s, const Records& from, uint64_t ev, const Records& r,
-                                                  uint64_t e, const Keyed& key, double ecm, double tcut, int cap) {
+                                                  uint64_t e, const Keyed& key, double ecm, double tcut,
+                                                  double t_over, int cap) {
   for (uint32_t a = 0; a < 2; ++a) {
     const uint64_t f = (uint64_t)a * from.stride + ev, t = (uint64_t)a * r.stride + e;
     r.E[t] = from.E[f];
@@ -386,7 +407,7 @@ __device__ __forceinline__ void start_from_record(EvState& s, const Records& fro
   r.apart[e] = kNoPartner;
   r.cpart[r.stride + e] = kNoPartner;
   r.apart[r.stride + e] = 0;
-  lo_state(s, key, ecm, tcut, cap);
+  lo_state(s, key, ecm, tcut, t_over, cap);
 }
 
 __device__ __forceinline__ void write_state(const EvState& s, const Summary& sm, uint64_t e) {
@@ -397,6 +418,7 @@ __device__ __forceinline__ void write_state(const EvState& s, const Summary& sm,
   sm.i[kSiTrials * sm.stride + e] = (int32_t)s.trials;
   sm.i[kSiEnds * sm.stride + e] = (int32_t)s.ends;
   sm.hash[e] = s.hash;
+  if (s.wsh != 1.0) sm.d[kSdW * sm.stride + e] *= s.wsh;  // event weight = matrix element x shower
 }
 
 }  // namespace vsh

@@ -6,7 +6,7 @@ Bars (written here, used by every GPU parity test):
     lines -- are compared exactly ("identical events");
   * at least 99.9% of events must be identical;
   * on identical events every momentum component agrees to 1e-9 sqrt(s);
-  * weights to 1e-12 relative; observables to 1e-9 relative or 1e-12
+  * weights (on identical events) to 1e-12 relative; observables to 1e-9 relative or 1e-12
     absolute (they are computed from momenta that agree to ~1e-15);
   * histograms: chi^2/ndf < 1.5 over filled bins, with the entry counts
     per bin allowed to differ only by events that differ.
@@ -62,7 +62,8 @@ def compare(gpu: dict, orc: dict, ecm, n: int, records: bool = True):
     frac = same.mean()
     gd = gpu["sum_d"]          # [10][n]
     od = orc["sum_d"].T        # [10][n]
-    w_err = np.max(np.abs(gd[0] - od[0]) / np.abs(od[0]))
+    # event weights (matrix element x weighted-veto factors) on identical events
+    w_err = float(np.max(np.abs(gd[0][same] - od[0][same]) / np.abs(od[0][same]))) if same.any() else 0.0
     obs_bad = 0
     for f in range(2, 9):
         g, o = gd[f][same], od[f][same]

@@ -99,6 +99,31 @@ def test_tail_cut(ctx, oracle, form, mapping):
     assert g["hist"][7, :, 2].sum() == n - cut.sum()
 
 
+@pytest.mark.parametrize("form,mapping", [("plain", 1), ("plain", 0), ("persistent", 1), ("persistent", 0)])
+def test_weighted_veto(ctx, oracle, form, mapping):
+    # alpha_s(10 GeV^2) in the trial density: fewer trials, and event weights
+    # +-(2r - 1) where the true density exceeds the trial density
+    n, t_over = 3000, 10.0
+    persistent = form == "persistent"
+    key = "mapping" if persistent else "plain_mapping"
+    before = ctx.get_tuning()[key]
+    ctx.set_tuning(**{key: mapping})
+    try:
+        print(f"case weighted veto n={n} t_over={t_over} form={form} mapping={mapping}", flush=True)
+        g = ctx.generate(n, seed=6, ecm=91.2, t_cut=1.0, max_partons=64, summary=True, records=True,
+                         persistent=persistent, t_over=t_over)
+    finally:
+        ctx.set_tuning(**{key: before})
+    o = oracle.generate(6, 0, n, 91.2, 1.0, 64, records=True, t_over=t_over)
+    rep, same = parity.compare(g, o, 91.2, n)
+    print(rep, flush=True)
+    parity.assert_parity(rep)
+    w = o["sum_d"][:, 0]
+    me = np.array([oracle.me_event(6, e, 91.2)[3] for e in range(n)])
+    assert (w < 0).any() and (np.abs(w / me - 1) > 1e-12).mean() > 0.1  # the weights are in play
+    assert g["sum_w"] == pytest.approx(w.sum(), rel=1e-12)
+
+
 def test_mixed_energies_per_event(ctx, oracle):
     from paper_2403_08692_amd.workloads import mixed_energies
 

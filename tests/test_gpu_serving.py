@@ -47,6 +47,16 @@ def test_served_tail_cut_equals_generate(ctx):
     assert ctx.wait(full)["n_cycle_limit"] == 0
 
 
+def test_served_weighted_veto_equals_generate(ctx):
+    kw = dict(seed=1003, ecm=200.0, t_cut=0.5, max_partons=128, t_over=20.0)
+    ref = ctx.generate(3000, summary=True, **kw)
+    plain = ctx.submit(3000, summary=True, **dict(kw, t_over=0.0))
+    t = ctx.submit(3000, summary=True, **kw)
+    _same(ctx.wait(t), ref, "weighted veto")
+    assert (ref["sum_d"][0] < 0).any()
+    assert ctx.wait(plain)["sum_d"][0].min() > 0
+
+
 def test_mix_equals_alone(ctx):
     from paper_2403_08692_amd.workloads import serving_trace
 
@@ -104,6 +114,10 @@ def test_cancel_and_errors(ctx):
     with pytest.raises(P.VshError) as ei:
         ctx.submit(10, t_cut=0.001)
     assert ei.value.code == -1
+    for bad in (-1.0, 0.005, float("nan"), float("inf")):  # t_over: 0 or a finite scale above 0.01
+        with pytest.raises(P.VshError) as ei:
+            ctx.submit(10, t_over=bad)
+        assert ei.value.code == -1 and "t_over" in str(ei.value)
     # the service keeps working after a cancel
     t = ctx.submit(1000, seed=3)
     assert ctx.wait(t)["n_done"] == 1000
