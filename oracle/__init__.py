@@ -77,7 +77,7 @@ def lib():
     L.or_me_event.argtypes = [C.c_uint64, C.c_uint64, C.c_double, _ip, _dp, _dp, _dp, _dp]
     L.or_split_kinematics.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
     L.or_shower.argtypes = [C.c_uint64, C.c_uint64, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
-                            C.c_int, _ip, _dp, _ip, _ip, _ip, _ip, _u64p, _ip, _dp, _dp, C.c_int, _u64p]
+                            _dp, C.c_int, _ip, _dp, _ip, _ip, _ip, _ip, _u64p, _ip, _dp, _dp, C.c_int, _u64p]
     L.or_shower.restype = C.c_int
     L.or_thrust.argtypes = [C.c_int, _dp, _dp]
     L.or_thrust.restype = C.c_double
@@ -89,8 +89,24 @@ def lib():
     L.or_validate.restype = C.c_int
     L.or_observables.argtypes = [C.c_int, _dp, C.c_double, _dp]
     L.or_hist_ranges.argtypes = [_dp, _dp]
+    L.or_me2_massive.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
+    L.or_me2_massive.restype = C.c_double
+    L.or_sigma_lo_massive.argtypes = [C.c_double, _dp]
+    L.or_sigma_lo_massive.restype = C.c_double
+    L.or_me_event_massive.argtypes = [C.c_uint64, C.c_uint64, C.c_double, _dp, _ip, _dp, _dp, _dp, _dp]
+    L.or_massive_limits.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp]
+    L.or_massive_limits.restype = C.c_int
+    L.or_massive_flux.argtypes = [C.c_double] * 5
+    L.or_massive_flux.restype = C.c_double
+    L.or_kernel_value_massive.argtypes = [C.c_int] + [C.c_double] * 5
+    L.or_kernel_value_massive.restype = C.c_double
+    L.or_massive_ratio.argtypes = [C.c_int] + [C.c_double] * 7
+    L.or_massive_ratio.restype = C.c_double
+    L.or_split_kinematics_massive.argtypes = [_dp, _dp] + [C.c_double] * 7 + [_dp, _dp, _dp]
+    L.or_validate_massive.argtypes = [C.c_int, _dp, _ip, C.c_double, _dp]
+    L.or_validate_massive.restype = C.c_int
     L.or_generate.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, _dp, C.c_double, _dp, C.c_double,
-                              C.c_int, C.c_int, C.c_double, _dp, _i32p, _u64p, _dp, _i32p, _dp, _i32p, _i32p, _i32p, _u64p]
+                              C.c_int, C.c_int, C.c_double, _dp, _dp, _i32p, _u64p, _dp, _i32p, _dp, _i32p, _i32p, _i32p, _u64p]
     L.or_generate.restype = C.c_int
     _lib = L
     return L
@@ -98,6 +114,60 @@ def lib():
 
 def _ptr(a, t):
     return None if a is None else a.ctypes.data_as(t)
+
+
+def _mass_table(mass):
+    """Six doubles indexed by flavour (0 unused, 1..5 = d, u, s, c, b), or None."""
+    if mass is None:
+        return None
+    m = np.ascontiguousarray(mass, np.float64)
+    assert m.shape == (6,)
+    return m
+
+
+def me2_massive(flavour, s, cos_theta, m):
+    return lib().or_me2_massive(int(flavour), float(s), float(cos_theta), float(m))
+
+
+def sigma_lo_massive(s, mass):
+    return lib().or_sigma_lo_massive(float(s), _ptr(_mass_table(mass), _dp))
+
+
+def me_event_massive(seed, event, ecm, mass):
+    f = C.c_int()
+    c, ph, w = C.c_double(), C.c_double(), C.c_double()
+    p = np.zeros(8)
+    lib().or_me_event_massive(seed, event, ecm, _ptr(_mass_table(mass), _dp), C.byref(f), C.byref(c), C.byref(ph),
+                              C.byref(w), _ptr(p, _dp))
+    return f.value, c.value, ph.value, w.value, p.reshape(2, 4)
+
+
+def massive_limits(Q2, mi, mj, mk, tcut):
+    zm, zp = C.c_double(), C.c_double()
+    ok = lib().or_massive_limits(float(Q2), float(mi), float(mj), float(mk), float(tcut), C.byref(zm), C.byref(zp))
+    return (zm.value, zp.value) if ok else None
+
+
+def massive_flux(Q2, mi, mj, mk, mij):
+    return lib().or_massive_flux(float(Q2), float(mi), float(mj), float(mk), float(mij))
+
+
+def kernel_value_massive(K, z, y, mi, qb2, sij):
+    return lib().or_kernel_value_massive(int(K), float(z), float(y), float(mi), float(qb2), float(sij))
+
+
+def massive_ratio(K, t, z, Q2, mi, mj, mk, fover):
+    return lib().or_massive_ratio(int(K), float(t), float(z), float(Q2), float(mi), float(mj), float(mk),
+                                  float(fover))
+
+
+def split_kinematics_massive(pij, pk, mi, mj, mk, mij, t, z, phi):
+    pij = np.ascontiguousarray(pij, np.float64)
+    pk = np.ascontiguousarray(pk, np.float64)
+    oi, oj, ok = np.zeros(4), np.zeros(4), np.zeros(4)
+    lib().or_split_kinematics_massive(_ptr(pij, _dp), _ptr(pk, _dp), mi, mj, mk, mij, t, z, phi, _ptr(oi, _dp),
+                                      _ptr(oj, _dp), _ptr(ok, _dp))
+    return oi, oj, ok
 
 
 def philox(ctr, key):
@@ -168,11 +238,13 @@ def split_kinematics(pi, pk, t, z, phi):
     return oi, oj, ok
 
 
-def shower(seed, event, ecm, tcut, p, pid, col, acol, cap=64, max_emit=-1, max_log=64, max_cycles=0, t_over=0.0):
+def shower(seed, event, ecm, tcut, p, pid, col, acol, cap=64, max_emit=-1, max_log=64, max_cycles=0, t_over=0.0,
+           mass=None):
     """Shower one event from the given partons.  Returns a dict.  max_cycles > 0
     gives up (status TRUNCATED) an event still above the cutoff after that many
     veto cycles; t_over > 0 takes alpha_s(t_over) for the trial density (the
-    weighted veto; the returned ``weight`` is the event's shower weight)."""
+    weighted veto; the returned ``weight`` is the event's shower weight); mass
+    is a table of six quark masses indexed by flavour (None: massless)."""
     n0 = len(pid)
     P = np.zeros((cap, 4))
     P[:n0] = np.asarray(p, np.float64).reshape(n0, 4)
@@ -186,7 +258,9 @@ def shower(seed, event, ecm, tcut, p, pid, col, acol, cap=64, max_emit=-1, max_l
     log = np.zeros((max_log, NLOG))
     work = np.zeros(NWORK, np.uint64)
     wgt = C.c_double()
-    st = lib().or_shower(seed, event, ecm, tcut, cap, int(max_cycles), float(t_over), max_emit, C.byref(n),
+    mt = _mass_table(mass)
+    st = lib().or_shower(seed, event, ecm, tcut, cap, int(max_cycles), float(t_over), _ptr(mt, _dp), max_emit,
+                         C.byref(n),
                          _ptr(P, _dp), _ptr(PID, _ip), _ptr(COL, _ip), _ptr(ACOL, _ip), C.byref(cyc), C.byref(h),
                          C.byref(nemit), C.byref(wgt), _ptr(log, _dp), max_log, _ptr(work, _u64p))
     m = n.value
@@ -246,7 +320,7 @@ def hist_ranges():
 
 
 def generate(seed, first, n_events, ecm=91.2, tcut=1.0, cap=64, records=False, ecm_arr=None, tcut_arr=None,
-             max_cycles=0, t_over=0.0):
+             max_cycles=0, t_over=0.0, mass=None):
     """Run ME + shower + observables + histograms for events first..first+n-1.
 
     Returns a dict with per-event summaries (``sum_d`` [n, 10]: w, cos_theta,
@@ -272,7 +346,7 @@ def generate(seed, first, n_events, ecm=91.2, tcut=1.0, cap=64, records=False, e
     e_arr = None if ecm_arr is None else np.ascontiguousarray(ecm_arr, np.float64)
     t_arr = None if tcut_arr is None else np.ascontiguousarray(tcut_arr, np.float64)
     rc = lib().or_generate(seed, first, n_events, _ptr(e_arr, _dp), float(ecm), _ptr(t_arr, _dp), float(tcut),
-                           int(cap), int(max_cycles), float(t_over), _ptr(sum_d, _dp), _ptr(sum_i, _i32p), _ptr(hsh, _u64p), _ptr(hist, _dp),
+                           int(cap), int(max_cycles), float(t_over), _ptr(_mass_table(mass), _dp), _ptr(sum_d, _dp), _ptr(sum_i, _i32p), _ptr(hsh, _u64p), _ptr(hist, _dp),
                            _ptr(rec.get("n"), _i32p), _ptr(rec.get("p"), _dp), _ptr(rec.get("pid"), _i32p),
                            _ptr(rec.get("col"), _i32p), _ptr(rec.get("acol"), _i32p), _ptr(work, _u64p))
     if rc != 0:

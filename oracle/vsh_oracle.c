@@ -210,6 +210,45 @@ double or_me2(int flavour, double s, double cos_theta) {
   return e2 * e2 * NC * (A * (1.0 + cos_theta * cos_theta) + B * cos_theta);
 }
 
+/* Quarks of mass m, velocity beta = sqrt(1 - 4 m^2 / s) in the CM frame.
+   The vector current gives 1 + beta^2 c^2 + (1 - beta^2) = 2 - beta^2 (1 - c^2),
+   the axial current beta^2 (1 + c^2), their interference beta c: the
+   c-even coefficient A splits into its vector part A_V (the v_f^2 and
+   photon terms) and axial part A_A (the a_f^2 term). */
+double or_me2_massive(int flavour, double s, double cos_theta, double m) {
+  if (m == 0.0) return or_me2(flavour, s, cos_theta);
+  double b2 = 1.0 - 4.0 * m * m / s;
+  if (!(b2 > 0.0)) return 0.0;
+  double beta = sqrt(b2);
+  double chi1, chi2, sw2;
+  ew_factors(s, &chi1, &chi2, &sw2);
+  double qe = -1.0, ae = -0.5, ve = -0.5 + 2.0 * sw2, qf, vf, af;
+  fermion_couplings(flavour, sw2, &qf, &vf, &af);
+  double av = qe * qe * qf * qf + 2.0 * qe * qf * ve * vf * chi1 + (ae * ae + ve * ve) * vf * vf * chi2;
+  double aa = (ae * ae + ve * ve) * af * af * chi2;
+  double B = 4.0 * qe * qf * ae * af * chi1 + 8.0 * ae * af * ve * vf * chi2;
+  double c = cos_theta;
+  double e2 = 4.0 * OR_PI * ALPHA_EM;
+  return e2 * e2 * NC * (av * (2.0 - b2 * (1.0 - c * c)) + aa * b2 * (1.0 + c * c) + B * beta * c);
+}
+
+/* sigma_LO over the flavours open at s (2 m_f < sqrt(s)), in pb */
+double or_sigma_lo_massive(double s, const double mass[6]) {
+  double total = 0.0;
+  for (int f = 1; f <= NF; ++f) {
+    double m = mass ? mass[f] : 0.0;
+    double b2 = 1.0 - 4.0 * m * m / s;
+    if (!(b2 > 0.0)) continue;
+    double beta = sqrt(b2);
+    /* beta times the integral over c of |M|^2 / (32 pi s); the c-even part
+       of |M|^2 is a + b c^2 with a = M(0) and b = (M(1) + M(-1))/2 - a */
+    double a0 = or_me2_massive(f, s, 0.0, m);
+    double b0 = 0.5 * (or_me2_massive(f, s, 1.0, m) + or_me2_massive(f, s, -1.0, m)) - a0;
+    total += beta * (2.0 * a0 + 2.0 * b0 / 3.0) / (32.0 * OR_PI * s);
+  }
+  return total * GEV2_TO_PB;
+}
+
 /* total LO cross-section over the five flavours, in pb: the integral of
    |M|^2 / (32 pi s) over cos(theta) in [-1, 1] */
 double or_sigma_lo(double s) {
@@ -227,17 +266,38 @@ double or_sigma_lo(double s) {
    5 |M|^2 / (16 pi s), in pb.  Outputs p[0..3] quark, p[4..7] antiquark. */
 void or_me_event(uint64_t seed, uint64_t event, double ecm, int *flavour,
                  double *cos_theta, double *phi, double *weight, double p[8]) {
+  or_me_event_massive(seed, event, ecm, NULL, flavour, cos_theta, phi, weight, p);
+}
+
+/* With quark masses: the flavour is uniform over the flavours open at
+   this sqrt(s) (2 m_f < sqrt(s); d, u, s always), in the order d, u, s, c,
+   b, with weight n_open; the two-body phase space brings a factor beta and
+   the quarks have |p| = beta sqrt(s) / 2. */
+void or_me_event_massive(uint64_t seed, uint64_t event, double ecm, const double mass[6],
+                         int *flavour, double *cos_theta, double *phi, double *weight,
+                         double p[8]) {
   uint32_t w[4];
+  double s = ecm * ecm;
+  int open[5], n_open = 0;
+  for (int f = 1; f <= NF; ++f)
+    if (!mass || 4.0 * mass[f] * mass[f] < s) open[n_open++] = f;
   or_draw(seed, event, 0, OR_P_ME, 0, w);
-  int f = 1 + (int)(((uint64_t)w[0] * 5u) >> 32);
+  int f = open[(int)(((uint64_t)w[0] * (uint64_t)n_open) >> 32)];
   double c = 2.0 * or_uniform(w[2], w[3]) - 1.0;
   or_draw(seed, event, 0, OR_P_ME, 1, w);
   double ph = 2.0 * OR_PI * or_uniform(w[0], w[1]);
-  double s = ecm * ecm;
-  double wt = 5.0 * or_me2(f, s, c) / (16.0 * OR_PI * s) * GEV2_TO_PB;
+  double m = mass ? mass[f] : 0.0;
+  double wt, beta = 1.0;
+  if (m == 0.0) {
+    wt = (double)n_open * or_me2(f, s, c) / (16.0 * OR_PI * s) * GEV2_TO_PB;
+  } else {
+    beta = sqrt(1.0 - 4.0 * m * m / s);
+    wt = (double)n_open * beta * or_me2_massive(f, s, c, m) / (16.0 * OR_PI * s) * GEV2_TO_PB;
+  }
   double st = sqrt((1.0 - c) * (1.0 + c));
   double e = 0.5 * ecm;
-  double px = e * st * cos(ph), py = e * st * sin(ph), pz = e * c;
+  double pm = e * beta;
+  double px = pm * st * cos(ph), py = pm * st * sin(ph), pz = pm * c;
   p[0] = e;
   p[1] = px;
   p[2] = py;
@@ -310,6 +370,169 @@ void or_split_kinematics(const double pi[4], const double pk[4], double t,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Massive quarks (the step the conclusions name: the veto algorithm stays */
+/* as it is, the splitting functions gain mass terms).  mass[f] is the     */
+/* mass of flavour f = 1..5 (d, u, s, c, b); a NULL table means massless.  */
+/* A kernel whose splitter, products and spectator are all massless uses   */
+/* the massless formulas above unchanged.                                  */
+/*                                                                          */
+/* Evolution variable: t = y Qb2 z (1-z) - (1-z)^2 mi^2 - z^2 mj^2 with      */
+/* Qb2 = Q^2 - mi^2 - mj^2 - mk^2 (the transverse momentum of i and j when  */
+/* the spectator is massless), y = p_i.p_j / (p_i.p_j + p_i.p_k + p_j.p_k)  */
+/* and z = p_i.p_k / (p_i.p_k + p_j.p_k); Q = p~ij + p~k.                   */
+/* ---------------------------------------------------------------------- */
+static double flavour_mass(const double *mass, int pid) {
+  if (!mass || pid == 21 || pid == 0) return 0.0;
+  return mass[pid > 0 ? pid : -pid];
+}
+
+/* masses of the products i and j of kernel K (i keeps the splitter's slot) */
+static void kernel_product_masses(int K, const double *mass, double *mi, double *mj) {
+  if (K < 10) {
+    *mi = flavour_mass(mass, K < 5 ? K + 1 : K - 4);
+    *mj = 0.0;
+  } else if (K == 10) {
+    *mi = 0.0;
+    *mj = 0.0;
+  } else {
+    *mi = flavour_mass(mass, K - 10);
+    *mj = *mi;
+  }
+}
+
+static double kallen(double a, double b, double c) {
+  return a * a + b * b + c * c - 2.0 * (a * b + a * c + b * c);
+}
+
+/* z range of the overestimate: t >= t_C with y <= 1 holds between the roots
+   of (mi^2 + mj^2 + Qb2) z^2 - (2 mi^2 + Qb2) z + mi^2 + t_C = 0.  Returns 0
+   when there is no phase space. */
+int or_massive_limits(double Q2, double mi, double mj, double mk, double tcut, double *zm,
+                      double *zp) {
+  double mi2 = mi * mi, mj2 = mj * mj;
+  double qb2 = Q2 - mi2 - mj2 - mk * mk;
+  if (!(qb2 > 0.0)) return 0;
+  double A = mi2 + mj2 + qb2, B = 2.0 * mi2 + qb2, C = mi2 + tcut;
+  double disc = B * B - 4.0 * A * C;
+  if (!(disc > 0.0)) return 0;
+  double r = sqrt(disc);
+  *zm = (B - r) / (2.0 * A);
+  *zp = (B + r) / (2.0 * A);
+  return 1;
+}
+
+/* Flux factor of the massive dipole phase space: the three-body phase
+   space over the two-body one is Qb2^2 (1 - y) dy dz / (16 pi^2
+   sqrt(lambda(Q^2, mij^2, mk^2))) and 2 p_i.p_j = y Qb2, so the emission
+   density is alpha_s/(2 pi) F (1 - y) (dy/y) dz V with
+   F = Qb2 / sqrt(lambda(Q^2, mij^2, mk^2)); F = 1 when everything is
+   massless, and F > 1 only for Q -> Q g with a massive spectator. */
+double or_massive_flux(double Q2, double mi, double mj, double mk, double mij) {
+  return (Q2 - mi * mi - mj * mj - mk * mk) / sqrt(kallen(Q2, mij * mij, mk * mk));
+}
+
+/* Mass terms of the quasi-collinear limit added to the massless kernels:
+     Q -> Q g:     C_F [2/(1 - z(1 - y)) - (1 + z) - m^2/(p_i.p_j)]
+     g -> Q Qbar:  (T_R/2) [1 - 2 z (1 - z) + 2 m^2 / s_ij]
+   with p_i.p_j = y Qb2 / 2 and s_ij = (p_i + p_j)^2 = 2 m^2 + y Qb2 for the
+   pair; g -> g g has none. */
+double or_kernel_value_massive(int K, double z, double y, double mi, double qb2, double sij) {
+  if (K < 10) return CF * (2.0 / (1.0 - z * (1.0 - y)) - (1.0 + z) - 2.0 * mi * mi / (y * qb2));
+  if (K == 10) return or_kernel_value(K, z, y);
+  return 0.5 * TR * (1.0 - 2.0 * z * (1.0 - z) + 2.0 * mi * mi / sij);
+}
+
+/* The emission at (t, z) in the massive map: Q = p~ij + p~k; the spectator
+   keeps its direction in the Q frame, rescaled so that (Q - p_k)^2 = s_ij,
+     p_k = sqrt(lambda(Q^2, s_ij, mk^2) / lambda(Q^2, mij^2, mk^2))
+             (p~k - (Q.p~k / Q^2) Q) + (Q^2 + mk^2 - s_ij) / (2 Q^2) Q,
+   and p_ij = Q - p_k.  Then p_i = a p_ij + b p_k + kT, kT orthogonal to
+   p_ij and p_k, from p_i^2 = mi^2, p_j^2 = mj^2 and p_i.p_k = z p_ij.p_k:
+     b = (mi^2 - mj^2 - (2z - 1) s_ij) P / (2 (P^2 - s_ij mk^2)),
+     a = z - b mk^2 / P,   -kT^2 = a^2 s_ij + b^2 mk^2 + 2 a b P - mi^2,
+   with P = p_ij.p_k = (Q^2 - s_ij - mk^2)/2 and P^2 - s_ij mk^2 =
+   lambda(Q^2, s_ij, mk^2)/4.  With all masses zero, a = z and
+   b = (1 - 2z) y / (1 - y): the massless map.  Returns 0 outside the phase
+   space (y >= 1, no room for p_k, or kT^2 < 0). */
+static int massive_vars(double Q2, double mi, double mj, double mk, double t, double z,
+                        double *y, double *sij, double *a, double *b, double *kt2) {
+  double mi2 = mi * mi, mj2 = mj * mj, mk2 = mk * mk;
+  double qb2 = Q2 - mi2 - mj2 - mk2;
+  double yy = (t + (1.0 - z) * (1.0 - z) * mi2 + z * z * mj2) / (qb2 * z * (1.0 - z));
+  if (!(yy < 1.0)) return 0;
+  double s = mi2 + mj2 + yy * qb2;
+  double lam = kallen(Q2, s, mk2);
+  if (!(lam > 0.0)) return 0;
+  double P = 0.5 * (Q2 - s - mk2);
+  double bb = (mi2 - mj2 - (2.0 * z - 1.0) * s) * P / (0.5 * lam);
+  double aa = z - bb * mk2 / P;
+  double k2 = aa * aa * s + bb * bb * mk2 + 2.0 * aa * bb * P - mi2;
+  if (!(k2 >= 0.0)) return 0;
+  *y = yy;
+  *sij = s;
+  *a = aa;
+  *b = bb;
+  *kt2 = k2;
+  return 1;
+}
+
+/* True over trial density of a massive kernel at (t, z), without the
+   alpha_s ratio: F (1 - y) t/(t + (1-z)^2 mi^2 + z^2 mj^2) V / (F_over O),
+   where t/(t + ...) turns dy/y into dt/t at fixed z and F_over = max(F, 1)
+   scales the overestimate; 0 where the kernel is not positive (inside the
+   dead cone); -1 outside the phase space. */
+double or_massive_ratio(int K, double t, double z, double Q2, double mi, double mj, double mk,
+                        double fover) {
+  double y, sij, a, b, k2;
+  if (!massive_vars(Q2, mi, mj, mk, t, z, &y, &sij, &a, &b, &k2)) return -1.0;
+  double qb2 = Q2 - mi * mi - mj * mj - mk * mk;
+  double v = or_kernel_value_massive(K, z, y, mi, qb2, sij);
+  if (!(v > 0.0)) return 0.0;
+  double f = or_massive_flux(Q2, mi, mj, mk, K < 10 ? mi : 0.0);
+  double cz = (1.0 - z) * (1.0 - z) * mi * mi + z * z * mj * mj;
+  return f * (1.0 - y) * (t / (t + cz)) * v / (fover * or_kernel_over(K, z));
+}
+
+/* transverse unit vectors orthogonal to two momenta, as in the massless map */
+static void transverse_basis(const double *pa, const double *pb, double n1[4], double n2[4]) {
+  double d[3];
+  for (int m = 0; m < 3; ++m) d[m] = pb[0] * pa[1 + m] - pa[0] * pb[1 + m];
+  int ax = 0;
+  if (fabs(d[1]) < fabs(d[ax])) ax = 1;
+  if (fabs(d[2]) < fabs(d[ax])) ax = 2;
+  double r[4] = {0.0, 0.0, 0.0, 0.0};
+  r[1 + ax] = 1.0;
+  eps4(pa, pb, r, n1);
+  double l1 = sqrt(-mdot(n1, n1));
+  for (int m = 0; m < 4; ++m) n1[m] /= l1;
+  eps4(pa, pb, n1, n2);
+  double l2 = sqrt(-mdot(n2, n2));
+  for (int m = 0; m < 4; ++m) n2[m] /= l2;
+}
+
+void or_split_kinematics_massive(const double pij[4], const double pk[4], double mi, double mj,
+                                 double mk, double mij, double t, double z, double phi,
+                                 double out_i[4], double out_j[4], double out_k[4]) {
+  double Q[4];
+  for (int m = 0; m < 4; ++m) Q[m] = pij[m] + pk[m];
+  double Q2 = mdot(Q, Q);
+  double y, s, a, b, k2;
+  massive_vars(Q2, mi, mj, mk, t, z, &y, &s, &a, &b, &k2);
+  double scale = sqrt(kallen(Q2, s, mk * mk) / kallen(Q2, mij * mij, mk * mk));
+  double along = mdot(Q, pk) / Q2, shift = (Q2 + mk * mk - s) / (2.0 * Q2);
+  double n1[4], n2[4];
+  transverse_basis(pij, pk, n1, n2);
+  double kt = sqrt(k2), c1 = cos(phi), s1 = sin(phi);
+  for (int m = 0; m < 4; ++m) {
+    double newk = scale * (pk[m] - along * Q[m]) + shift * Q[m];
+    double newij = Q[m] - newk;
+    out_k[m] = newk;
+    out_i[m] = a * newij + b * newk + kt * (c1 * n1[m] + s1 * n2[m]);
+    out_j[m] = newij - out_i[m];
+  }
+}
+
+/* ---------------------------------------------------------------------- */
 /* Shower (Appendix A)                                                     */
 /* ---------------------------------------------------------------------- */
 /* leading-colour connection: i's colour flows into k's anticolour, or i's
@@ -325,7 +548,8 @@ static uint64_t fnv_step(uint64_t h, uint32_t v) {
 }
 
 int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
-              int max_cycles, double t_over, int max_emit, int *n, double *p, int *pid,
+              int max_cycles, double t_over, const double *mass, int max_emit, int *n,
+              double *p, int *pid,
               int *col, int *acol, int *cycles, uint64_t *emit_hash, int *n_emit,
               double *weight, double *emit_log, int max_log, uint64_t *work) {
   int np = *n;
@@ -356,21 +580,38 @@ int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
     double winner_t = tcut;
     int wi = -1, wk = -1, wK = -1;
     double wq2 = 0.0, wzm = 0.0, wzp = 0.0;
+    /* the winner's (p~ij + p~k)^2, masses and overestimate factor, and
+       whether its kernel takes the massive formulas */
+    double wQ2 = 0.0, wmi = 0.0, wmj = 0.0, wmk = 0.0, wfo = 1.0;
+    int wmassive = 0;
     for (int i = 0; i < np; ++i) {
       for (int k = 0; k < np; ++k) {
         if (i == k) continue;
         if (!colour_connected(col[i], acol[i], col[k], acol[k])) continue;
         if (work) work[1]++;
         double q2 = 2.0 * mdot(&p[4 * i], &p[4 * k]);
-        if (!(q2 > 4.0 * tcut)) continue; /* no phase space above t_C */
-        if (work) work[2]++;
-        double zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * tcut / q2));
-        double zm = 1.0 - zp;
+        double msplit = flavour_mass(mass, pid[i]), mk = flavour_mass(mass, pid[k]);
+        double Q2 = q2 + msplit * msplit + mk * mk; /* (p~ij + p~k)^2 */
         int kl[6];
         int nk = or_kernel_list(pid[i], kl);
+        int active = 0;
         for (int j = 0; j < nk; ++j) {
           int K = kl[j];
+          double mi, mj, zm, zp, fo = 1.0;
+          kernel_product_masses(K, mass, &mi, &mj);
+          int massive = mi > 0.0 || mj > 0.0 || mk > 0.0;
+          if (!massive) {
+            if (!(q2 > 4.0 * tcut)) continue; /* no phase space above t_C */
+            zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * tcut / q2));
+            zm = 1.0 - zp;
+          } else {
+            if (!or_massive_limits(Q2, mi, mj, mk, tcut, &zm, &zp)) continue;
+            double f = or_massive_flux(Q2, mi, mj, mk, K < 10 ? mi : 0.0);
+            fo = f > 1.0 ? f : 1.0;
+          }
+          active = 1;
           double c = asmax / (2.0 * OR_PI) * or_kernel_integral(K, zm, zp);
+          if (massive) c *= fo;
           uint32_t w[4];
           or_draw(seed, event, cycle, OR_P_TRIAL, trial_slot(i, k, j), w);
           double u = (j & 1) ? or_uniform(w[2], w[3]) : or_uniform(w[0], w[1]);
@@ -384,8 +625,15 @@ int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
             wq2 = q2;
             wzm = zm;
             wzp = zp;
+            wQ2 = Q2;
+            wmi = mi;
+            wmj = mj;
+            wmk = mk;
+            wfo = fo;
+            wmassive = massive;
           }
         }
+        if (active && work) work[2]++; /* an end with phase space above t_C */
       }
     }
     uint32_t this_cycle = cycle++;
@@ -405,12 +653,24 @@ int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
     double uz = or_uniform(a[0], a[1]);
     double uv = or_uniform(a[2], a[3]);
     double z = or_kernel_zgen(wK, wzm, wzp, uz);
-    double y = t / (wq2 * z * (1.0 - z));
+    double y, prob = 0.0;
+    int inside; /* inside the true phase space at this t */
+    if (!wmassive) {
+      y = t / (wq2 * z * (1.0 - z));
+      inside = y < 1.0;
+      if (inside)
+        prob = or_alpha_s(t) / asmax * or_kernel_value(wK, z, y) * (1.0 - y) /
+               or_kernel_over(wK, z);
+    } else {
+      double qb2 = wQ2 - wmi * wmi - wmj * wmj - wmk * wmk;
+      y = (t + (1.0 - z) * (1.0 - z) * wmi * wmi + z * z * wmj * wmj) / (qb2 * z * (1.0 - z));
+      double r = or_massive_ratio(wK, t, z, wQ2, wmi, wmj, wmk, wfo);
+      inside = r >= 0.0;
+      prob = or_alpha_s(t) / asmax * r;
+    }
     int accept = 0;
-    if (y < 1.0) { /* inside the true phase space at this t */
+    if (inside) {
       if (work) work[5]++;
-      double prob = or_alpha_s(t) / asmax * or_kernel_value(wK, z, y) * (1.0 - y) /
-                    or_kernel_over(wK, z);
       if (prob > 1.0) {
         /* weighted veto where the true density exceeds the trial density:
            accept with probability e, weight the event by prob / e if
@@ -435,7 +695,11 @@ int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
     or_draw(seed, event, this_cycle, OR_P_SPLIT, 0, sdraw);
     double phi = 2.0 * OR_PI * or_uniform(sdraw[0], sdraw[1]);
     double ni[4], nj[4], nk4[4];
-    or_split_kinematics(&p[4 * wi], &p[4 * wk], t, z, phi, ni, nj, nk4);
+    if (wmassive)
+      or_split_kinematics_massive(&p[4 * wi], &p[4 * wk], wmi, wmj, wmk, wK < 10 ? wmi : 0.0, t, z,
+                                  phi, ni, nj, nk4);
+    else
+      or_split_kinematics(&p[4 * wi], &p[4 * wk], t, z, phi, ni, nj, nk4);
     for (int m = 0; m < 4; ++m) {
       p[4 * wi + m] = ni[m];
       p[4 * wk + m] = nk4[m];
@@ -665,8 +929,24 @@ void or_hemispheres(int n, const double *p, const double axis[3], double s,
 }
 
 /* Validate: every component finite; total four-momentum equal to
-   (ecm, 0, 0, 0) within 1e-10 ecm per component; every parton massless
-   within 1e-10 s. */
+   (ecm, 0, 0, 0) within 1e-10 ecm per component; every parton on its mass
+   shell (massless unless the table gives its flavour a mass) within 1e-10 s. */
+int or_validate_massive(int n, const double *p, const int *pid, double ecm, const double *mass) {
+  double tot[4] = {0, 0, 0, 0};
+  for (int a = 0; a < 4 * n; ++a)
+    if (!isfinite(p[a])) return OR_NONFINITE;
+  for (int a = 0; a < n; ++a)
+    for (int c = 0; c < 4; ++c) tot[c] += p[4 * a + c];
+  double tol = 1e-10 * ecm;
+  if (fabs(tot[0] - ecm) > tol || fabs(tot[1]) > tol || fabs(tot[2]) > tol || fabs(tot[3]) > tol)
+    return OR_CONSERVATION;
+  for (int a = 0; a < n; ++a) {
+    double m = flavour_mass(mass, pid[a]);
+    if (fabs(mdot(&p[4 * a], &p[4 * a]) - m * m) > 1e-10 * ecm * ecm) return OR_CONSERVATION;
+  }
+  return OR_DONE;
+}
+
 int or_validate(int n, const double *p, double ecm) {
   double tot[4] = {0, 0, 0, 0};
   for (int a = 0; a < 4 * n; ++a)
@@ -723,7 +1003,8 @@ static void hist_fill(double *hist, int h, double x, double w, const double *lo,
 
 int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
                 const double *ecm, double ecm0, const double *tcut,
-                double tcut0, int cap, int max_cycles, double t_over, double *sum_d, int32_t *sum_i,
+                double tcut0, int cap, int max_cycles, double t_over, const double *mass,
+                double *sum_d, int32_t *sum_i,
                 uint64_t *sum_hash, double *hist, int32_t *rec_n,
                 double *rec_p, int32_t *rec_pid, int32_t *rec_col,
                 int32_t *rec_acol, uint64_t *work) {
@@ -739,7 +1020,7 @@ int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
     double tc = tcut ? tcut[e] : tcut0;
     int flavour;
     double cth, phi, w;
-    or_me_event(seed, ev, E, &flavour, &cth, &phi, &w, p);
+    or_me_event_massive(seed, ev, E, mass, &flavour, &cth, &phi, &w, p);
     pid[0] = flavour;
     col[0] = 1;
     acol[0] = 0;
@@ -750,13 +1031,13 @@ int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
     uint64_t hash = 0;
     uint64_t ew[OR_NWORK] = {0, 0, 0, 0, 0, 0};
     double wsh = 1.0;
-    int status = or_shower(seed, ev, E, tc, cap, max_cycles, t_over, -1, &n, p, pid, col, acol,
+    int status = or_shower(seed, ev, E, tc, cap, max_cycles, t_over, mass, -1, &n, p, pid, col, acol,
                            &cycles, &hash, &nemit, &wsh, NULL, 0, ew);
     w *= wsh; /* the event weight: matrix element times weighted veto */
     if (work)
       for (int k = 0; k < OR_NWORK; ++k) work[k] += ew[k];
     double obs[7] = {0, 0, 0, 0, 0, 0, 0};
-    if (status == OR_DONE) status = or_validate(n, p, E);
+    if (status == OR_DONE) status = mass ? or_validate_massive(n, p, pid, E, mass) : or_validate(n, p, E);
     if (status == OR_DONE) {
       or_observables(n, p, E, obs);
       if (hist) {

@@ -26,7 +26,13 @@
  * thrust against brute force over every hemisphere split; C against the
  * eigenvalues of the momentum tensor; Durham against three-parton closed
  * forms and four-parton brute force; hemisphere masses against brute force;
- * the tail cut (max_cycles) against the first cycles of the uncut shower.
+ * the tail cut (max_cycles) against the first cycles of the uncut shower;
+ * the weighted veto against the Sudakov factor by quadrature; massive
+ * quarks against the vector-current threshold factor and a Dirac-trace spin
+ * sum (matrix element), the Dalitz-plot Jacobian and invariants (map), the
+ * massive eikonal factor (soft limit), the massless limit, and the first
+ * emission off a heavy pair against a Dalitz-plot quadrature.  The g -> Q
+ * Qbar mass term is pinned only by its bound and massless limit.
  * Whole showered events beyond the first emission have no external
  * reference: parity unpinned there (colour, flavour and momentum
  * conservation are checked, the distributions are not).
@@ -82,6 +88,24 @@ double or_sigma_lo(double s);
 void   or_me_event(uint64_t seed, uint64_t event, double ecm, int *flavour,
                    double *cos_theta, double *phi, double *weight, double p[8]);
 
+/* Massive quarks: mass[f] is the mass of flavour f = 1..5 (d, u, s, c, b;
+   mass[0] unused); NULL means five massless flavours. */
+double or_me2_massive(int flavour, double s, double cos_theta, double m);
+double or_sigma_lo_massive(double s, const double mass[6]);
+void   or_me_event_massive(uint64_t seed, uint64_t event, double ecm, const double mass[6],
+                           int *flavour, double *cos_theta, double *phi, double *weight,
+                           double p[8]);
+int    or_massive_limits(double Q2, double mi, double mj, double mk, double tcut, double *zm,
+                         double *zp);
+double or_massive_flux(double Q2, double mi, double mj, double mk, double mij);
+double or_kernel_value_massive(int K, double z, double y, double mi, double qb2, double sij);
+double or_massive_ratio(int K, double t, double z, double Q2, double mi, double mj, double mk,
+                        double fover);
+void   or_split_kinematics_massive(const double pij[4], const double pk[4], double mi, double mj,
+                                   double mk, double mij, double t, double z, double phi,
+                                   double out_i[4], double out_j[4], double out_k[4]);
+int    or_validate_massive(int n, const double *p, const int *pid, double ecm, const double *mass);
+
 /* Catani-Seymour final-final map */
 void or_split_kinematics(const double pi[4], const double pk[4], double t,
                          double z, double phi, double out_i[4],
@@ -95,10 +119,13 @@ void or_split_kinematics(const double pi[4], const double pk[4], double t,
    t_over that is no overestimate, and the weighted veto (where the ratio r
    exceeds 1: accept with probability r / (2r - 1), weight the event by
    +-(2r - 1)) keeps every distribution exact on average; *weight returns
-   the product of those factors (1 with t_over = 0).
+   the product of those factors (1 with t_over = 0).  mass (NULL = massless)
+   gives quark masses: kernels with a massive splitter, product or spectator
+   take the massive phase space, kernels and map.
    max_emit >= 0 stops after that many emissions (test runs). */
 int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
-              int max_cycles, double t_over, int max_emit, int *n, double *p, int *pid,
+              int max_cycles, double t_over, const double *mass, int max_emit, int *n,
+              double *p, int *pid,
               int *col, int *acol, int *cycles, uint64_t *emit_hash, int *n_emit,
               double *weight, double *emit_log, int max_log, uint64_t *work);
 
@@ -116,12 +143,13 @@ void   or_hist_ranges(double lo[OR_NOBS], double hi[OR_NOBS]);
    ecm/tcut arrays may be NULL (then ecm0/tcut0 are used).  Any output
    pointer may be NULL.  hist is [OR_NOBS][OR_NHCOL][3] (sum w, sum w^2,
    entries), accumulated (not cleared); only events that reach the cutoff
-   and validate fill it.  max_cycles and t_over as for or_shower; the event
+   and validate fill it.  max_cycles, t_over and mass as for or_shower; the event
    weight (summary field 0, histograms) is the matrix-element weight times
    the shower's.  Returns 0, or -1 on bad arguments. */
 int or_generate(uint64_t seed, uint64_t first, uint64_t n_events,
                 const double *ecm, double ecm0, const double *tcut,
-                double tcut0, int cap, int max_cycles, double t_over, double *sum_d, int32_t *sum_i,
+                double tcut0, int cap, int max_cycles, double t_over, const double *mass,
+                double *sum_d, int32_t *sum_i,
                 uint64_t *sum_hash, double *hist, int32_t *rec_n,
                 double *rec_p, int32_t *rec_pid, int32_t *rec_col,
                 int32_t *rec_acol, uint64_t *work);

@@ -6,12 +6,14 @@ a copy of the oracle's source, builds it on the CPU, and runs the pin suite
 (tests/test_oracle_*.py) against it through VSH_ORACLE_LIB.  Every mutant
 must fail at least one pin; the committed oracle itself passes them all.
 
-Known blind spot: the overestimate's z range narrowed inside the physical
+Known blind spots: the overestimate's z range narrowed inside the physical
 limits z(1 - z) = t_C / Q^2 (say by a factor 1.5 in t_C / Q^2) loses only a
 sliver where the (1 - y) factor already suppresses the density: 2.5% of the
 emission probability at sqrt(s) = 6 GeV, t_C = 4 GeV^2, about 3 standard
 deviations of the near-threshold pin.  A wider range only costs efficiency
-(the veto's y < 1 trims it to the true phase space).
+(the veto's y < 1 trims it to the true phase space).  For the same reason
+the massive z range taken without the spectator mass (a wider range) only
+costs efficiency.
 """
 import concurrent.futures as cf
 import os
@@ -24,7 +26,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "vsh_oracle.c")
 PINS = ["tests/test_oracle_rng.py", "tests/test_oracle_physics.py", "tests/test_oracle_shower.py",
-        "tests/test_oracle_observables.py"]
+        "tests/test_oracle_observables.py", "tests/test_oracle_massive.py"]
 
 # (name, text in vsh_oracle.c, replacement)
 MUTANTS = [
@@ -54,7 +56,8 @@ MUTANTS = [
     ("dipole-end threshold at the running scale", "if (!(q2 > 4.0 * tcut)) continue;",
      "if (!(q2 > 4.0 * t)) continue;"),
     ("veto without the (1-y) measure", "or_kernel_value(wK, z, y) * (1.0 - y) /", "or_kernel_value(wK, z, y) /"),
-    ("veto alpha_s at the cutoff", "double prob = or_alpha_s(t) / asmax", "double prob = or_alpha_s(tcut) / asmax"),
+    ("veto alpha_s at the cutoff", "prob = or_alpha_s(t) / asmax * or_kernel_value",
+     "prob = or_alpha_s(tcut) / asmax * or_kernel_value"),
     ("uniform for the veto from the z words", "double uv = or_uniform(a[2], a[3]);", "double uv = or_uniform(a[0], a[1]);"),
     ("colour line not moved to the emitter", "        jacol = m;\n        col[wi] = m;",
      "        jacol = m;\n        col[wi] = col[wi];"),
@@ -75,6 +78,22 @@ MUTANTS = [
      "wgt *= accept ? 2.0 * prob - 1.0 : (2.0 * prob - 1.0);"),
     ("weighted veto: always accept above the trial density", "accept = uv < e;", "accept = 1;"),
     ("weighted veto: acceptance one half", "double e = prob / (2.0 * prob - 1.0);", "double e = 0.5;"),
+    ("massive flux inverted", "return (Q2 - mi * mi - mj * mj - mk * mk) / sqrt(kallen(Q2, mij * mij, mk * mk));",
+     "return sqrt(kallen(Q2, mij * mij, mk * mk)) / (Q2 - mi * mi - mj * mj - mk * mk);"),
+    ("massive Q -> Q g mass term halved", "- 2.0 * mi * mi / (y * qb2));", "- mi * mi / (y * qb2));"),
+    ("massive Jacobian dy/y taken as dt/t", "(t / (t + cz))", "(1.0)"),
+    ("massive map without the spectator rescaling",
+     "double scale = sqrt(kallen(Q2, s, mk * mk) / kallen(Q2, mij * mij, mk * mk));", "double scale = 1.0;"),
+    ("massive map: sign of the p_k coefficient", "double bb = (mi2 - mj2 - (2.0 * z - 1.0) * s)",
+     "double bb = (mi2 - mj2 + (2.0 * z - 1.0) * s)"),
+    ("massive ME: axial current with the vector threshold", "aa * b2 * (1.0 + c * c)",
+     "aa * (2.0 - b2 * (1.0 - c * c))"),
+    ("massive ME: phase-space beta dropped", "wt = (double)n_open * beta * or_me2_massive(",
+     "wt = (double)n_open * or_me2_massive("),
+    ("closed flavours produced", "if (!mass || 4.0 * mass[f] * mass[f] < s) open[n_open++] = f;",
+     "open[n_open++] = f;"),
+    ("mass shells ignored in validation", "if (fabs(mdot(&p[4 * a], &p[4 * a]) - m * m) > 1e-10 * ecm * ecm)",
+     "if (fabs(mdot(&p[4 * a], &p[4 * a])) > 1e-10 * ecm * ecm)"),
     ("heavy-jet mass as the lighter hemisphere", "double rho = (mp > mm ? mp : mm) / s;",
      "double rho = (mp < mm ? mp : mm) / s;"),
 ]
