@@ -141,6 +141,15 @@ typedef struct {
                             multiplied by +(2r - 1), or by -(2r - 1) on rejection.  Event
                             weights (summary field 0, histograms, sum_w) include it.
                             0 or > 0.01                                               */
+  double mass_c, mass_b; /* charm and bottom quark masses in GeV (0 = massless, the
+                            default; d, u, s stay massless): the extension to massive
+                            final-state quarks that the conclusions name.  The matrix
+                            element then carries the quark velocity and draws only
+                            flavours open at sqrt(s); kernels with a massive parton
+                            take the massive dipole phase space, the quasi-collinear
+                            mass terms and the massive recoil map; events validate on
+                            their mass shells.  Such requests run the lane mapping's
+                            massive kernels.  0 <= mass, finite                      */
 } vsh_request;
 
 /* Result of one request.  Library-owned host memory; release with

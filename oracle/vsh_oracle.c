@@ -453,27 +453,25 @@ double or_kernel_value_massive(int K, double z, double y, double mi, double qb2,
    with P = p_ij.p_k = (Q^2 - s_ij - mk^2)/2 and P^2 - s_ij mk^2 =
    lambda(Q^2, s_ij, mk^2)/4.  With all masses zero, a = z and
    b = (1 - 2z) y / (1 - y): the massless map.  Returns 0 outside the phase
-   space (y >= 1, no room for p_k, or kT^2 < 0). */
+   space (y >= 1, no room for p_k, or kT^2 < 0); the outputs are set either
+   way. */
 static int massive_vars(double Q2, double mi, double mj, double mk, double t, double z,
                         double *y, double *sij, double *a, double *b, double *kt2) {
   double mi2 = mi * mi, mj2 = mj * mj, mk2 = mk * mk;
   double qb2 = Q2 - mi2 - mj2 - mk2;
   double yy = (t + (1.0 - z) * (1.0 - z) * mi2 + z * z * mj2) / (qb2 * z * (1.0 - z));
-  if (!(yy < 1.0)) return 0;
   double s = mi2 + mj2 + yy * qb2;
   double lam = kallen(Q2, s, mk2);
-  if (!(lam > 0.0)) return 0;
   double P = 0.5 * (Q2 - s - mk2);
   double bb = (mi2 - mj2 - (2.0 * z - 1.0) * s) * P / (0.5 * lam);
   double aa = z - bb * mk2 / P;
   double k2 = aa * aa * s + bb * bb * mk2 + 2.0 * aa * bb * P - mi2;
-  if (!(k2 >= 0.0)) return 0;
   *y = yy;
   *sij = s;
   *a = aa;
   *b = bb;
   *kt2 = k2;
-  return 1;
+  return yy < 1.0 && lam > 0.0 && k2 >= 0.0;
 }
 
 /* True over trial density of a massive kernel at (t, z), without the
@@ -518,11 +516,12 @@ void or_split_kinematics_massive(const double pij[4], const double pk[4], double
   double Q2 = mdot(Q, Q);
   double y, s, a, b, k2;
   massive_vars(Q2, mi, mj, mk, t, z, &y, &s, &a, &b, &k2);
-  double scale = sqrt(kallen(Q2, s, mk * mk) / kallen(Q2, mij * mij, mk * mk));
+  double lam = kallen(Q2, s, mk * mk);
+  double scale = sqrt((lam > 0.0 ? lam : 0.0) / kallen(Q2, mij * mij, mk * mk));
   double along = mdot(Q, pk) / Q2, shift = (Q2 + mk * mk - s) / (2.0 * Q2);
   double n1[4], n2[4];
   transverse_basis(pij, pk, n1, n2);
-  double kt = sqrt(k2), c1 = cos(phi), s1 = sin(phi);
+  double kt = sqrt(k2 > 0.0 ? k2 : 0.0), c1 = cos(phi), s1 = sin(phi);
   for (int m = 0; m < 4; ++m) {
     double newk = scale * (pk[m] - along * Q[m]) + shift * Q[m];
     double newij = Q[m] - newk;

@@ -38,7 +38,7 @@ class vsh_request(C.Structure):
                 ("ecm", C.c_double), ("t_cut", C.c_double),
                 ("ecm_per_event", C.c_void_p), ("tcut_per_event", C.c_void_p),
                 ("max_partons", C.c_uint32), ("flags", C.c_uint32), ("cycle_limit", C.c_uint32),
-                ("t_over", C.c_double)]
+                ("t_over", C.c_double), ("mass_c", C.c_double), ("mass_b", C.c_double)]
 
 
 class vsh_tuning(C.Structure):
@@ -177,11 +177,12 @@ def result_to_dict(res: vsh_result) -> dict:
 
 
 def make_request(n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=64, flags=0,
-                 ecm_per_event=None, tcut_per_event=None, cycle_limit=0, t_over=0.0):
+                 ecm_per_event=None, tcut_per_event=None, cycle_limit=0, t_over=0.0, mass_c=0.0, mass_b=0.0):
     """Build a vsh_request; per-event arrays are numpy float64 (host) or
     integer device addresses (with VSH_INPUTS_ON_DEVICE).  cycle_limit > 0
     vetoes events still above the cutoff after that many veto cycles; t_over
-    > 0 is the alpha_s scale of the trial density (weighted veto).
+    > 0 is the alpha_s scale of the trial density (weighted veto); mass_c,
+    mass_b > 0 make charm and bottom quarks massive.
     Returns (req, keepalive)."""
     keep = []
 
@@ -196,7 +197,7 @@ def make_request(n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_parto
 
     req = vsh_request(int(n_events), int(seed), int(first_event), float(ecm), float(t_cut),
                       addr(ecm_per_event), addr(tcut_per_event), int(max_partons), int(flags), int(cycle_limit),
-                      float(t_over))
+                      float(t_over), float(mass_c), float(mass_b))
     return req, keep
 
 
@@ -235,11 +236,11 @@ class Context:
 
     def generate(self, n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=64,
                  summary=True, records=False, persistent=False, ecm_per_event=None, tcut_per_event=None,
-                 cycle_limit=0, t_over=0.0):
+                 cycle_limit=0, t_over=0.0, mass_c=0.0, mass_b=0.0):
         flags = (VSH_SUMMARY if summary else 0) | (VSH_RECORDS if records else 0) | \
                 (VSH_FORM_PERSISTENT if persistent else 0)
         req, keep = make_request(n_events, seed, first_event, ecm, t_cut, max_partons, flags,
-                                 ecm_per_event, tcut_per_event, cycle_limit, t_over)
+                                 ecm_per_event, tcut_per_event, cycle_limit, t_over, mass_c, mass_b)
         res = C.POINTER(vsh_result)()
         _check(load().vsh_generate(self._ptr, C.byref(req), C.byref(res)), self._ptr)
         try:
@@ -248,14 +249,15 @@ class Context:
             load().vsh_result_free(res)
 
     def shower_records(self, offsets, p, pid, col, acol, seed=1, first_event=0, t_cut=1.0, max_partons=64,
-                       summary=True, records=True):
+                       summary=True, records=True, mass_c=0.0, mass_b=0.0):
         offsets = np.ascontiguousarray(offsets, np.uint64)
         p = np.ascontiguousarray(p, np.float64)
         pid = np.ascontiguousarray(pid, np.int8)
         col = np.ascontiguousarray(col, np.uint16)
         acol = np.ascontiguousarray(acol, np.uint16)
         flags = (VSH_SUMMARY if summary else 0) | (VSH_RECORDS if records else 0)
-        req, keep = make_request(len(offsets) - 1, seed, first_event, 0.0, t_cut, max_partons, flags)
+        req, keep = make_request(len(offsets) - 1, seed, first_event, 0.0, t_cut, max_partons, flags,
+                                 mass_c=mass_c, mass_b=mass_b)
         res = C.POINTER(vsh_result)()
         _check(load().vsh_shower_records(self._ptr, C.byref(req), offsets.ctypes.data, p.ctypes.data,
                                          pid.ctypes.data, col.ctypes.data, acol.ctypes.data, C.byref(res)),
@@ -306,10 +308,10 @@ class Context:
         return np.array(buf[:3 * n.value], np.float64).reshape(n.value, 3)
 
     def submit(self, n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=128, summary=False,
-               ecm_per_event=None, tcut_per_event=None, cycle_limit=0, t_over=0.0):
+               ecm_per_event=None, tcut_per_event=None, cycle_limit=0, t_over=0.0, mass_c=0.0, mass_b=0.0):
         flags = VSH_SUMMARY if summary else 0
         req, keep = make_request(n_events, seed, first_event, ecm, t_cut, max_partons, flags,
-                                 ecm_per_event, tcut_per_event, cycle_limit, t_over)
+                                 ecm_per_event, tcut_per_event, cycle_limit, t_over, mass_c, mass_b)
         t = C.c_uint64()
         _check(load().vsh_submit(self._ptr, C.byref(req), C.byref(t)), self._ptr)
         return t.value

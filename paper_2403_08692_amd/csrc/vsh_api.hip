@@ -68,6 +68,10 @@ vsh_status validate_request(vsh_ctx* ctx, const vsh_request* req, bool need_ener
     set_error(ctx, "t_cut must be > %g GeV^2 (got %g)", kMinTcut, req->t_cut);
     return VSH_E_INVALID;
   }
+  if (!(req->mass_c >= 0.0 && std::isfinite(req->mass_c) && req->mass_b >= 0.0 && std::isfinite(req->mass_b))) {
+    set_error(ctx, "quark masses must be finite and >= 0 (got c %g, b %g)", req->mass_c, req->mass_b);
+    return VSH_E_INVALID;
+  }
   if (!(req->t_over == 0.0 || (req->t_over > kMinTcut && std::isfinite(req->t_over)))) {
     set_error(ctx, "t_over must be 0 or a finite value > %g GeV^2 (got %g)", kMinTcut, req->t_over);
     return VSH_E_INVALID;
@@ -325,6 +329,8 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
   in.first = req->first_event + first_idx;
   in.cycle_limit = effective_cycle_limit(req->cycle_limit);
   in.t_over = req->t_over;
+  in.qm = request_masses(*req);
+  in.massive = request_massive(*req);
   in.ecm0 = req->ecm;
   in.tcut0 = req->t_cut;
   const bool from_records = caller_offsets != nullptr;
@@ -385,7 +391,7 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(ctx->ev[1], st));
-  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, L.sum, in, (uint32_t)count, L.cache, st);
+  if (ctx->tuned.plain_mapping == kMapFlat && !in.massive) launch_shower_plain_flat(L.rec, L.sum, in, (uint32_t)count, L.cache, st);
   else launch_shower_plain(L.rec, L.sum, in, (uint32_t)count, ctx->tuned.plain_block, ctx->tuned.plain_waves, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(ctx->ev[2], st));
@@ -692,6 +698,8 @@ vsh_status vsh_generate_into(vsh_ctx* ctx, const vsh_request* req, void* stream,
   in.first = req->first_event;
   in.cycle_limit = effective_cycle_limit(req->cycle_limit);
   in.t_over = req->t_over;
+  in.qm = request_masses(*req);
+  in.massive = request_massive(*req);
   in.ecm0 = req->ecm;
   in.tcut0 = req->t_cut;
   in.ecm = req->ecm_per_event;
@@ -701,7 +709,7 @@ vsh_status vsh_generate_into(vsh_ctx* ctx, const vsh_request* req, void* stream,
   if (tev) (void)hipEventRecord(tev[0], st);
   launch_me(L.rec, sum, in, (uint32_t)n, st);
   if (tev) (void)hipEventRecord(tev[1], st);
-  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, sum, in, (uint32_t)n, L.cache, st);
+  if (ctx->tuned.plain_mapping == kMapFlat && !in.massive) launch_shower_plain_flat(L.rec, sum, in, (uint32_t)n, L.cache, st);
   else launch_shower_plain(L.rec, sum, in, (uint32_t)n, ctx->tuned.plain_block, ctx->tuned.plain_waves, st);
   if (tev) (void)hipEventRecord(tev[2], st);
   launch_obs(L.rec, sum, in, L.sc, (uint32_t)n, dev_hist, st);

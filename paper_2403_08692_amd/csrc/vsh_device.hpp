@@ -41,6 +41,16 @@ constexpr uint32_t effective_cycle_limit(uint32_t requested) {
   return requested == 0 || requested > kCycleLimit ? kCycleLimit : requested;
 }
 
+// Quark masses by flavour (GeV), all zero for the massless shower.
+struct QuarkMasses {
+  double d, u, s, c, b;
+};
+
+__device__ __forceinline__ double quark_mass(const QuarkMasses& q, int pid) {
+  const int a = pid < 0 ? -pid : pid;
+  return a == 1 ? q.d : a == 2 ? q.u : a == 3 ? q.s : a == 4 ? q.c : a == 5 ? q.b : 0.0;
+}
+
 // draw purposes of the random-number contract
 enum : uint32_t { kPurposeME = 1, kPurposeTrial = 2, kPurposeAccept = 3, kPurposeSplit = 4 };
 

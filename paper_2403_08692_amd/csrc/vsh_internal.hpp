@@ -14,6 +14,12 @@
 
 #include "../../include/vsh.h"
 #include "vsh_kernels.hpp"
+
+namespace vsh {
+// a request's quark masses (d, u, s massless) and whether any is above zero
+inline QuarkMasses request_masses(const vsh_request& r) { return QuarkMasses{0.0, 0.0, 0.0, r.mass_c, r.mass_b}; }
+inline uint32_t request_massive(const vsh_request& r) { return r.mass_c > 0.0 || r.mass_b > 0.0 ? 1u : 0u; }
+}  // namespace vsh
 #include "vsh_persistent.hpp"
 
 namespace vsh {

@@ -18,7 +18,7 @@ namespace vsh {
 __global__ void __launch_bounds__(256) k_me(Records r, Summary s, EventInputs in, uint32_t n) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  const MEOut m = me_event(r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e));
+  const MEOut m = me_event(r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.qm, in.massive != 0);
   s.d[kSdW * s.stride + e] = m.w;
   s.d[kSdCos * s.stride + e] = m.c;
   s.d[kSdPhi * s.stride + e] = m.phi;
@@ -48,8 +48,9 @@ __global__ void __launch_bounds__(256) k_init_records(Records r, Summary s, uint
 
 // Plain form: each thread evolves its event to the cutoff in one launch.
 // Compiled for 2, 3 and 4 resident waves per SIMD (register budgets 256,
-// 168 and 128); the autotuner picks by timing.
-template <int kWaves>
+// 168 and 128); the autotuner picks by timing.  kMassive: each kernel with
+// its own massive phase space (requests with quark masses).
+template <int kWaves, bool kMassive = false>
 __global__ void __launch_bounds__(256, kWaves) k_shower_plain(Records r, Summary sm, EventInputs in,
                                                               uint32_t n) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -58,7 +59,8 @@ __global__ void __launch_bounds__(256, kWaves) k_shower_plain(Records r, Summary
   init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e), in.t_over,
              sm.i[kSiN * sm.stride + e], (int)r.cap);
   while (s.status == kRunning) {
-    veto_cycle(s, r, e);
+    if constexpr (kMassive) veto_cycle_massive(s, r, e, in.qm);
+    else veto_cycle(s, r, e);
     if (s.cycle >= in.cycle_limit && s.status == kRunning) s.status = kCycleLimitHit;
   }
   write_state(s, sm, e);
@@ -140,6 +142,7 @@ __global__ void __launch_bounds__(256) k_obs_scatter(Summary sm, uint32_t n, uin
   if (e < n) perm[lc[bin] + rank] = e;
 }
 
+template <bool kMassive>
 __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs in, Scratch sc, uint32_t n,
                                              double* __restrict__ hist) {
   __shared__ double lh[kHistDoubles];
@@ -158,7 +161,7 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
     const int np = sm.i[kSiN * sm.stride + e];
     if (np > kObsRegSlots || (uint32_t)np >= sc.threshold) continue;  // the lane groups take those
     const int status = sm.i[kSiStatus * sm.stride + e];
-    const ObsOut o = reg_observables<kObsRegSlots>(r, e, np, in.ecm_of(e), status);
+    const ObsOut o = reg_observables<kObsRegSlots, kMassive>(r, e, np, in.ecm_of(e), status, in);
     if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
     for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
     sm.i[kSiStatus * sm.stride + e] = o.status;
@@ -175,7 +178,7 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
       sc.y[to] = r.y[from];
       sc.z[to] = r.z[from];
     }
-    const ObsOut o = scratch_observables(sc, t, np, in.ecm_of(e), status);
+    const ObsOut o = scratch_observables<kMassive>(sc, t, np, in.ecm_of(e), status, in, r, e);
     if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
     for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
     sm.i[kSiStatus * sm.stride + e] = o.status;
@@ -251,7 +254,7 @@ struct PairWalk {
 
 // events with lo_n <= partons < hi_n; `slots` (at most G * MV) LDS parton
 // slots per group
-template <int G, int MV>
+template <int G, int MV, bool kMassive>
 __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventInputs in, const uint32_t* perm,
                                                   const uint32_t* cnt, uint32_t cap, uint32_t lo_n, uint32_t hi_n,
                                                   uint32_t slots, double* __restrict__ hist) {
@@ -288,7 +291,7 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
       py[a] = p.y;
       pz[a] = p.z;
       if (!(isfinite(p.e) && isfinite(p.x) && isfinite(p.y) && isfinite(p.z))) bad += 2.0;
-      else if (!(fabs(mdot(p, p)) <= 1e-10 * sh)) bad += 1.0;
+      else if (!(fabs(mdot(p, p) - shell2<kMassive>(in, r, a, e)) <= 1e-10 * sh)) bad += 1.0;
       tE += p.e;
       tx += p.x;
       ty += p.y;
@@ -459,18 +462,22 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
 // The group launches for records of capacity cap: 16 lanes from
 // kObsWaveThreshold to 31 partons, 64 lanes from 32 (smaller events go to
 // k_obs).
-uint32_t obs_group_launches(uint32_t cap, ObsGroupLaunch out[3]) {
+const void* obs_kernel(bool massive) { return massive ? (const void*)k_obs<true> : (const void*)k_obs<false>; }
+
+uint32_t obs_group_launches(uint32_t cap, bool massive, ObsGroupLaunch out[3]) {
   uint32_t k = 0;
   if (cap > kObsWaveMaxCap || kObsWaveThreshold > cap) return 0;
   const uint32_t t = kObsWaveThreshold;
   {  // 16 lanes up to 31 partons
     const uint32_t slots = std::min<uint32_t>(31, cap);
-    out[k++] = ObsGroupLaunch{(const void*)k_obs_group<16, 2>, std::max<uint32_t>(t, 9), 32, slots,
-                              (uint32_t)obs_group_lds(16, slots)};
+    const void* fn = massive ? (const void*)k_obs_group<16, 2, true> : (const void*)k_obs_group<16, 2, false>;
+    out[k++] = ObsGroupLaunch{fn, std::max<uint32_t>(t, 9), 32, slots, (uint32_t)obs_group_lds(16, slots)};
   }
-  if (cap >= 32)  // a wave from 32
-    out[k++] = ObsGroupLaunch{(const void*)k_obs_group<64, kObsWaveMaxCap / 64>, std::max<uint32_t>(t, 32), cap + 1,
-                              cap, (uint32_t)obs_group_lds(64, cap)};
+  if (cap >= 32) {  // a wave from 32
+    const void* fn = massive ? (const void*)k_obs_group<64, kObsWaveMaxCap / 64, true>
+                             : (const void*)k_obs_group<64, kObsWaveMaxCap / 64, false>;
+    out[k++] = ObsGroupLaunch{fn, std::max<uint32_t>(t, 32), cap + 1, cap, (uint32_t)obs_group_lds(64, cap)};
+  }
   return k;
 }
 
@@ -501,7 +508,8 @@ void launch_shower_plain(const Records& r, const Summary& s, const EventInputs& 
   if (!n) return;
   if (block == 0 || block > 256) block = 256;
   const dim3 g(blocks_for(n, block)), b(block);
-  if (waves >= 4) hipLaunchKernelGGL(k_shower_plain<4>, g, b, 0, st, r, s, in, n);
+  if (in.massive) hipLaunchKernelGGL((k_shower_plain<2, true>), g, b, 0, st, r, s, in, n);
+  else if (waves >= 4) hipLaunchKernelGGL(k_shower_plain<4>, g, b, 0, st, r, s, in, n);
   else if (waves == 3) hipLaunchKernelGGL(k_shower_plain<3>, g, b, 0, st, r, s, in, n);
   else hipLaunchKernelGGL(k_shower_plain<2>, g, b, 0, st, r, s, in, n);
 }
@@ -565,9 +573,10 @@ void launch_obs(const Records& r, const Summary& s, const EventInputs& in, const
   hipLaunchKernelGGL(k_obs_scan, dim3(1), dim3(256), 0, st, sc.cnt, nb);
   hipLaunchKernelGGL(k_obs_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, n, r.cap, sc.cnt, sc.perm);
   const uint32_t blocks = (uint32_t)(std::min<uint64_t>(sc.stride, ((uint64_t)n + 255) / 256 * 256) / 256);
-  hipLaunchKernelGGL(k_obs, dim3(blocks), dim3(256), 0, st, r, s, in, sc, n, hist);
+  if (in.massive) hipLaunchKernelGGL(k_obs<true>, dim3(blocks), dim3(256), 0, st, r, s, in, sc, n, hist);
+  else hipLaunchKernelGGL(k_obs<false>, dim3(blocks), dim3(256), 0, st, r, s, in, sc, n, hist);
   ObsGroupLaunch gl[3];
-  const uint32_t ng = obs_group_launches(r.cap, gl);
+  const uint32_t ng = obs_group_launches(r.cap, in.massive != 0, gl);
   for (uint32_t k = 0; k < ng; ++k) {
     const uint32_t wb = (uint32_t)std::min<uint64_t>(n, kObsWaveBlocks);
     const uint32_t* perm = sc.perm;

@@ -66,6 +66,8 @@ struct EventInputs {
   uint64_t seed, first;
   uint32_t cycle_limit;  // veto cycles after which a running event is given up (>= 1)
   double t_over;         // scale of alpha_s in the trial density, 0 = the event's t_C
+  QuarkMasses qm;        // quark masses (massive kernels only when `massive`)
+  uint32_t massive;      // any quark mass above zero
   __device__ __forceinline__ double ecm_of(uint64_t e) const { return ecm ? ecm[e] : ecm0; }
   __device__ __forceinline__ double tcut_of(uint64_t e) const { return tcut ? tcut[e] : tcut0; }
 };
@@ -104,7 +106,8 @@ namespace vsh {
 uint64_t obs_threads(uint64_t n, uint32_t cap);
 uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap);
 Scratch carve_obs_scratch(char*& p, uint64_t n, uint32_t cap);
-__global__ void k_obs(Records r, Summary sm, EventInputs in, Scratch sc, uint32_t n, double* __restrict__ hist);
+// k_obs for requests without (false) or with (true) quark masses
+const void* obs_kernel(bool massive);
 __global__ void k_obs_count(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt);
 __global__ void k_obs_scan(uint32_t* cnt, uint32_t nb);
 __global__ void k_obs_scatter(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt, uint32_t* perm);
@@ -116,7 +119,7 @@ struct ObsGroupLaunch {
   const void* fn;
   uint32_t lo, hi, slots, lds;
 };
-uint32_t obs_group_launches(uint32_t cap, ObsGroupLaunch out[3]);
+uint32_t obs_group_launches(uint32_t cap, bool massive, ObsGroupLaunch out[3]);
 size_t obs_group_lds(uint32_t g, uint32_t slots);
 void launch_me(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
                hipStream_t st);

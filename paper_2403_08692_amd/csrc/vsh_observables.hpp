@@ -127,15 +127,29 @@ __device__ void durham_nn(const Scratch& w, uint64_t t, int n, double sh, double
   }
 }
 
-// Observables of one event whose n partons are in scratch column t.
+// Squared mass shell of parton a of event e of r: zero unless the request
+// gives quark masses (the kMassive instantiations of the passes).
+template <bool kMassive>
+__device__ __forceinline__ double shell2(const EventInputs& in, const Records& r, int a, uint64_t e) {
+  if constexpr (!kMassive) {
+    return 0.0;
+  } else {
+    const double m = quark_mass(in.qm, r.pid[(uint64_t)a * r.stride + e]);
+    return m * m;
+  }
+}
+
+// Observables of one event (e of r) whose n partons are in scratch column t.
+template <bool kMassive>
 __device__ __forceinline__ ObsOut scratch_observables(const Scratch& w, uint64_t t, int np, double ecm,
-                                                      int status) {
+                                                      int status, const EventInputs& in, const Records& r,
+                                                      uint64_t e) {
   ObsOut o;
   for (int h = 0; h < 7; ++h) o.v[h] = 0.0;
   const double sh = ecm * ecm;
   if (status == kDone) {
     double tE = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
-    bool finite = true, massless = true;
+    bool finite = true, on_shell = true;
     for (int a = 0; a < np; ++a) {
       const uint64_t q = (uint64_t)a * w.stride + t;
       const P4 p{w.E[q], w.x[q], w.y[q], w.z[q]};
@@ -144,11 +158,11 @@ __device__ __forceinline__ ObsOut scratch_observables(const Scratch& w, uint64_t
       tx += p.x;
       ty += p.y;
       tz += p.z;
-      massless = massless && fabs(mdot(p, p)) <= 1e-10 * sh;
+      on_shell = on_shell && fabs(mdot(p, p) - shell2<kMassive>(in, r, a, e)) <= 1e-10 * sh;
     }
     const double tol = 1e-10 * ecm;
     if (!finite) status = kNonFinite;
-    else if (fabs(tE - ecm) > tol || fabs(tx) > tol || fabs(ty) > tol || fabs(tz) > tol || !massless)
+    else if (fabs(tE - ecm) > tol || fabs(tx) > tol || fabs(ty) > tol || fabs(tz) > tol || !on_shell)
       status = kConservation;
   }
   o.status = status;
@@ -248,8 +262,9 @@ __device__ __forceinline__ ObsOut scratch_observables(const Scratch& w, uint64_t
 // and keeps the first minimum, the same merge the nearest-neighbour version
 // picks; a merge adds jet b into jet a.
 // ---------------------------------------------------------------------------
-template <int M>
-__device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, int np, double ecm, int status) {
+template <int M, bool kMassive>
+__device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, int np, double ecm, int status,
+                                                  const EventInputs& in) {
   ObsOut o;
 #pragma unroll
   for (int h = 0; h < 7; ++h) o.v[h] = 0.0;
@@ -268,7 +283,7 @@ __device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, 
   const double sh = ecm * ecm;
   if (status == kDone) {
     double tE = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
-    bool finite = true, massless = true;
+    bool finite = true, on_shell = true;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
       if (a < np) {
@@ -278,12 +293,12 @@ __device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, 
         tx += p.x;
         ty += p.y;
         tz += p.z;
-        massless = massless && fabs(mdot(p, p)) <= 1e-10 * sh;
+        on_shell = on_shell && fabs(mdot(p, p) - shell2<kMassive>(in, r, a, e)) <= 1e-10 * sh;
       }
     }
     const double tol = 1e-10 * ecm;
     if (!finite) status = kNonFinite;
-    else if (fabs(tE - ecm) > tol || fabs(tx) > tol || fabs(ty) > tol || fabs(tz) > tol || !massless)
+    else if (fabs(tE - ecm) > tol || fabs(tx) > tol || fabs(ty) > tol || fabs(tz) > tol || !on_shell)
       status = kConservation;
   }
   o.status = status;

@@ -105,7 +105,7 @@ __device__ __forceinline__ void finish_event(const EvState& s, const PersistArgs
   write_state(s, R.sum, ev);
 }
 
-template <bool kInPlace>
+template <bool kInPlace, bool kMassive = false>
 __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
   const uint64_t L = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;  // this lane's working slot
   const uint32_t lane = __lane_id();
@@ -126,7 +126,8 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
     }
     if (!__any(busy)) break;  // counter exhausted and nothing left in this wave
     if (busy) {
-      veto_cycle(s, A.slots, slot);
+      if constexpr (kMassive) veto_cycle_massive(s, A.slots, slot, A.reqs[req].qm);
+      else veto_cycle(s, A.slots, slot);
       if (s.status == kRunning && s.cycle >= A.reqs[req].cycle_limit) s.status = kCycleLimitHit;
       if (s.status != kRunning) {
         finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
@@ -737,7 +738,10 @@ BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap) {
   return L;
 }
 
-const void* persistent_kernel(uint32_t mapping, bool in_place) {
+// Requests with quark masses run the lane mapping's massive kernel.
+const void* persistent_kernel(uint32_t mapping, bool in_place, bool massive) {
+  if (massive)
+    return in_place ? (const void*)k_shower_persistent<true, true> : (const void*)k_shower_persistent<false, true>;
   if (mapping == kMapFlat) return in_place ? (const void*)k_shower_flat<true> : (const void*)k_shower_flat<false>;
   return in_place ? (const void*)k_shower_persistent<true> : (const void*)k_shower_persistent<false>;
 }
@@ -745,10 +749,13 @@ const void* persistent_kernel(uint32_t mapping, bool in_place) {
 uint32_t persistent_block(uint32_t mapping, uint32_t block) { return mapping == kMapFlat ? 64u : block; }
 
 void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uint32_t mapping, bool in_place,
-                       hipStream_t st) {
+                       bool massive, hipStream_t st) {
   block = persistent_block(mapping, block);
   const dim3 grid((uint32_t)(lanes / block));
-  if (mapping == kMapFlat) {
+  if (massive) {
+    if (in_place) hipLaunchKernelGGL((k_shower_persistent<true, true>), grid, dim3(block), 0, st, A);
+    else hipLaunchKernelGGL((k_shower_persistent<false, true>), grid, dim3(block), 0, st, A);
+  } else if (mapping == kMapFlat) {
     const size_t lds = flat_lds_bytes(A.slots.cap);
     if (in_place) hipLaunchKernelGGL(k_shower_flat<true>, grid, dim3(block), lds, st, A);
     else hipLaunchKernelGGL(k_shower_flat<false>, grid, dim3(block), lds, st, A);
@@ -823,8 +830,9 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   GCHK(add_kernel((const void*)k_me, dim3((uint32_t)((n + 255) / 256)), dim3(256), a_me));
   GCHK(add_event(1));
   void* a_pers[] = {&g.args};
-  GCHK(add_kernel(persistent_kernel(g.mapping, true), dim3((uint32_t)(lanes / block)), dim3(block), a_pers,
-                  g.mapping == kMapFlat ? (unsigned)flat_lds_bytes(A.slots.cap) : 0u));
+  const bool massive = g.in.massive != 0;
+  GCHK(add_kernel(persistent_kernel(g.mapping, true, massive), dim3((uint32_t)(lanes / block)), dim3(block),
+                  a_pers, g.mapping == kMapFlat && !massive ? (unsigned)flat_lds_bytes(A.slots.cap) : 0u));
   GCHK(add_event(2));
   g.nb = L.buf.out.cap + 1;
   g.cap = L.buf.out.cap;
@@ -839,11 +847,11 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   GCHK(add_kernel((const void*)k_obs_scatter, dim3(eb), dim3(256), a_scatter));
   void* a_obs[] = {&g.rec, &g.sum, &g.in, &g.sc, &g.n, &g.hist};
   const uint32_t ob = (uint32_t)(std::min<uint64_t>(g.sc.stride, (n + 255) / 256 * 256) / 256);
-  GCHK(add_kernel((const void*)k_obs, dim3(ob), dim3(256), a_obs));
+  GCHK(add_kernel(obs_kernel(massive), dim3(ob), dim3(256), a_obs));
   g.perm_c = g.sc.perm;
   g.cnt_c = g.sc.cnt;
   ObsGroupLaunch gl[3];
-  const uint32_t ng = obs_group_launches(g.cap, gl);
+  const uint32_t ng = obs_group_launches(g.cap, massive, gl);
   for (uint32_t k = 0; k < ng; ++k) {
     g.glo[k] = gl[k].lo;
     g.ghi[k] = gl[k].hi;
@@ -877,6 +885,8 @@ static void fill_request_desc(ReqDev& d, const ReqBuffers& b, const vsh_request*
   d.count = b.sum.stride;
   d.cycle_limit = effective_cycle_limit(req->cycle_limit);
   d.t_over = req->t_over;
+  d.qm = request_masses(*req);
+  d.massive = request_massive(*req);
 }
 
 // One batch of `n` events of req (starting at request index first_idx)
@@ -921,6 +931,8 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
   in.first = req->first_event + first_idx;
   in.cycle_limit = effective_cycle_limit(req->cycle_limit);
   in.t_over = req->t_over;
+  in.qm = request_masses(*req);
+  in.massive = request_massive(*req);
   hipEvent_t* tev = timing_slot(ctx);
   if (use_graph) {
     BatchGraph& g = ctx->graph;
@@ -950,7 +962,7 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
     launch_setup(L.reqs, d, L.segs, sg, L.counter, st);
     launch_me(L.buf.out, L.buf.sum, in, (uint32_t)n, st);
     if (tev) (void)hipEventRecord(tev[1], st);
-    launch_persistent(A, lanes, block, mapping, true, st);
+    launch_persistent(A, lanes, block, mapping, true, in.massive != 0, st);
     if (tev) (void)hipEventRecord(tev[2], st);
     launch_obs(L.buf.out, L.buf.sum, in, L.sc, (uint32_t)n, hist, st);
     if (tev) (void)hipEventRecord(tev[3], st);
@@ -1054,6 +1066,8 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     in.first = req->first_event + a;
     in.cycle_limit = effective_cycle_limit(req->cycle_limit);
     in.t_over = req->t_over;
+    in.qm = request_masses(*req);
+    in.massive = request_massive(*req);
     launch_me(L.buf.out, L.buf.sum, in, (uint32_t)n, st);
     A.slots = L.buf.out;  // in place
     A.reqs = L.reqs;
@@ -1066,7 +1080,7 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     A.pad = 0;
     A.cache = L.cache;
     (void)hipEventRecord(ctx->ev[1], st);
-    launch_persistent(A, lanes, ctx->tuned.pers_block, ctx->tuned.mapping, true, st);
+    launch_persistent(A, lanes, ctx->tuned.pers_block, ctx->tuned.mapping, true, in.massive != 0, st);
     (void)hipEventRecord(ctx->ev[2], st);
     launch_obs(L.buf.out, L.buf.sum, in, L.sc, (uint32_t)n, L.buf.hist, st);
     (void)hipEventRecord(ctx->ev[3], st);

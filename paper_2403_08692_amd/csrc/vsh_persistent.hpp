@@ -20,6 +20,8 @@ struct ReqDev {
   uint64_t count;
   uint32_t cycle_limit;  // veto cycles after which a running event is given up (>= 1)
   double t_over;         // scale of alpha_s in the trial density, 0 = the event's t_C
+  QuarkMasses qm;        // quark masses
+  uint32_t massive;      // any quark mass above zero
 };
 
 // a contiguous range of one request's events inside a launch's work space
@@ -108,7 +110,7 @@ ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap, bool partners);
 Scratch carve_scratch(Carver& c, uint64_t n, uint32_t cap);
 enum : uint32_t { kMapLane = 0, kMapFlat = 1 };
 void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uint32_t mapping, bool in_place,
-                       hipStream_t st);
+                       bool massive, hipStream_t st);
 void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, unsigned long long* counter,
                   hipStream_t st);
 void launch_zero(double* p, uint32_t n, hipStream_t st);

@@ -189,6 +189,8 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     in.first = r.req.first_event;
     in.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
     in.t_over = r.req.t_over;
+    in.qm = request_masses(r.req);
+    in.massive = request_massive(r.req);
     launch_me(r.buf.out, r.buf.sum, in, (uint32_t)n, S.drain);  // LO partons of every event
     (void)hipStreamSynchronize(S.drain);  // inputs and LO events on the device before any epoch reads them
     r.state = kAdmitted;
@@ -230,6 +232,7 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
   E->parts.clear();
   uint64_t total = 0;
   uint32_t nreq = 0, nseg = 0, cap = 2;
+  bool massive = false;  // any request of the epoch with quark masses
   for (uint64_t t : S.active) {
     ServeReq& r = *S.reqs[t];
     if (r.cancel || r.state != kAdmitted || r.scheduled >= r.req.n_events) continue;
@@ -247,6 +250,9 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
     d.count = r.req.n_events;
     d.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
     d.t_over = r.req.t_over;
+    d.qm = request_masses(r.req);
+    d.massive = request_massive(r.req);
+    massive |= d.massive != 0;
     Segment& sg = E->segs_host[nseg];
     sg.req = nreq;
     sg.pad = 0;
@@ -291,7 +297,7 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
   A.total = total;
   A.next = counter;
   A.period = tn.refill_period;
-  launch_persistent(A, lanes, tn.pers_block, tn.mapping, false, E->stream);
+  launch_persistent(A, lanes, tn.pers_block, tn.mapping, false, massive, E->stream);
   (void)hipEventRecord(E->done, E->stream);
   E->busy = true;
   return true;
@@ -325,6 +331,8 @@ static void start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
   in.first = r.req.first_event;
   in.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
   in.t_over = r.req.t_over;
+  in.qm = request_masses(r.req);
+  in.massive = request_massive(r.req);
   launch_obs(r.buf.out, r.buf.sum, in, sc, (uint32_t)n, r.buf.hist, S.drain);
   r.hist.resize(kHistDoubles);
   r.sd.resize((size_t)kNSumD * n);

@@ -6,6 +6,7 @@
 #pragma once
 
 #include "vsh_kernels.hpp"
+#include "vsh_massive.hpp"
 #include "vsh_math.hpp"
 
 namespace vsh {
@@ -13,23 +14,56 @@ namespace vsh {
 // LO event into slot `e` of r: flavour uniform over d,u,s,c,b by a 64-bit
 // multiply-shift of one 32-bit word, cos(theta), phi uniform; weight
 // 5 |M|^2 / (16 pi s) in pb.  Quark in slot 0 (colour line 1), antiquark in
-// slot 1, back to back.
+// slot 1, back to back.  With quark masses the flavour is uniform over those
+// open at this sqrt(s) (2 m_f < sqrt(s)), the weight n_open beta |M|^2 /
+// (16 pi s) and |p| = beta sqrt(s)/2.
 struct MEOut {
   double w, c, phi;
   int f;
 };
 
-__device__ __forceinline__ MEOut me_event(const Records& r, uint64_t e, const Keyed& key, double ecm) {
+__device__ __forceinline__ MEOut me_event(const Records& r, uint64_t e, const Keyed& key, double ecm,
+                                          const QuarkMasses& qm, bool massive) {
   const U4 a = key.draw(0, kPurposeME, 0);
-  const int f = 1 + (int)(((uint64_t)a.x * 5u) >> 32);
+  const double sh = ecm * ecm;
+  int f;
+  uint32_t n_open = 5;
+  if (!massive) {
+    f = 1 + (int)(((uint64_t)a.x * 5u) >> 32);
+  } else {
+    n_open = 0;
+    for (int g = 1; g <= 5; ++g) {
+      const double m = quark_mass(qm, g);
+      n_open += 4.0 * m * m < sh;
+    }
+    const uint32_t idx = (uint32_t)(((uint64_t)a.x * (uint64_t)n_open) >> 32);
+    f = 0;
+    uint32_t seen = 0;
+    for (int g = 1; g <= 5; ++g) {
+      const double m = quark_mass(qm, g);
+      if (4.0 * m * m < sh) {
+        if (seen == idx) f = g;
+        ++seen;
+      }
+    }
+  }
   const double c = 2.0 * unit(a.z, a.w) - 1.0;
   const U4 b = key.draw(0, kPurposeME, 1);
   const double phi = 2.0 * kPi * unit(b.x, b.y);
-  const double sh = ecm * ecm;
-  const double w = 5.0 * me2(f, sh, c) / (16.0 * kPi * sh) * kGeV2ToPb;
+  double w, beta = 1.0;
+  const double mq = massive ? quark_mass(qm, f) : 0.0;
+  if (!massive) {
+    w = 5.0 * me2(f, sh, c) / (16.0 * kPi * sh) * kGeV2ToPb;
+  } else if (mq == 0.0) {
+    w = (double)n_open * me2(f, sh, c) / (16.0 * kPi * sh) * kGeV2ToPb;
+  } else {
+    beta = sqrt(1.0 - 4.0 * mq * mq / sh);
+    w = (double)n_open * beta * me2_massive(f, sh, c, mq) / (16.0 * kPi * sh) * kGeV2ToPb;
+  }
   const double st = sqrt((1.0 - c) * (1.0 + c));
   const double en = 0.5 * ecm;
-  const double px = en * st * cos(phi), py = en * st * sin(phi), pz = en * c;
+  const double pm = en * beta;
+  const double px = pm * st * cos(phi), py = pm * st * sin(phi), pz = pm * c;
   r.store(0, e, P4{en, px, py, pz});
   r.store(1, e, P4{en, -px, -py, -pz});
   r.pid[e] = (int8_t)f;
@@ -200,6 +234,20 @@ struct Pending {
   uint32_t cycle;
 };
 
+// AcceptOrVeto's test with the accept block's words (2, 3).  Where the
+// trial density undershoots (alpha_s of the trial density taken above t_C,
+// ratio prob > 1): the weighted veto, accept with probability r / (2r - 1)
+// and weight the event by +-(2r - 1), the least-variance choice.
+__device__ __forceinline__ bool accept_test(double prob, const U4& a, double& wsh) {
+  if (prob > 1.0) {
+    const double g = 2.0 * prob - 1.0;
+    const bool acc = unit(a.z, a.w) < prob / g;
+    wsh *= acc ? g : -g;
+    return acc;
+  }
+  return unit(a.z, a.w) < prob;
+}
+
 // The decision part of one cycle once the winner is known: CheckCutoff,
 // alpha_s, AcceptOrVeto (App. C).  `best` is the winner's ln t, `a` the
 // cycle's accept block (drawn ahead by the caller).  Returns true for an
@@ -221,17 +269,7 @@ __device__ __forceinline__ bool veto_decide_drawn(EvState& s, double best, const
   if (!(y < 1.0)) return false;
   const double prob =
       alpha_s_of_log(best) / s.asmax * kernel_value(w.K, z, y) * (1.0 - y) / kernel_over(w.K, z);
-  if (prob > 1.0) {
-    // the trial density undershoots here (alpha_s of the trial density taken
-    // above t_C): weighted veto, accept with probability r / (2r - 1) and
-    // weight the event by +-(2r - 1), the least-variance choice
-    const double g = 2.0 * prob - 1.0;
-    const bool acc = unit(a.z, a.w) < prob / g;
-    wsh *= acc ? g : -g;
-    if (!acc) return false;
-  } else if (!(unit(a.z, a.w) < prob)) {
-    return false;
-  }
+  if (!accept_test(prob, a, wsh)) return false;
   if (s.n == s.cap) {
     s.status = kOverflow;
     return false;
@@ -246,22 +284,11 @@ __device__ __forceinline__ bool veto_decide(EvState& s, double best, const Winne
   return veto_decide_drawn(s, best, w, accept_draw(s), p, s.wsh);
 }
 
-// GenerateEmission (App. C): kinematics, colours, flavours, and parton j
-// appended at slot n.
-__device__ __forceinline__ void emit(EvState& s, const Records& r, uint64_t e, const Pending& pe) {
-  const double t = pe.t, z = pe.z;
-  const uint32_t this_cycle = pe.cycle;
-  const Winner w{0.0, 0.0, 0.0, 0.0, pe.i, pe.k, pe.K};
-  const U4 sd = s.key.draw(this_cycle, kPurposeSplit, 0);
-  const double phi = 2.0 * kPi * unit(sd.x, sd.y);
-  double sphi, cphi;
-  sincos(phi, &sphi, &cphi);
+// Colours, flavours, partner links and the hash of an emission whose
+// momenta are in place (GenerateEmission, App. C); parton j appended at
+// slot n.
+__device__ __forceinline__ void emit_colours(EvState& s, const Records& r, uint64_t e, const Winner& w) {
   const int i = w.i, k = w.k, j = s.n;
-  P4 ni, nj, nk;
-  split_kinematics(r.load(i, e), r.load(k, e), t, z, cphi, sphi, ni, nj, nk);
-  r.store(i, e, ni);
-  r.store(k, e, nk);
-  r.store(j, e, nj);
   const uint64_t oi = (uint64_t)i * r.stride + e;
   const uint64_t ok = (uint64_t)k * r.stride + e;
   const uint64_t oj = (uint64_t)j * r.stride + e;
@@ -315,6 +342,24 @@ __device__ __forceinline__ void emit(EvState& s, const Records& r, uint64_t e, c
   s.n_emit += 1;
 }
 
+// GenerateEmission (App. C): kinematics, then colours and flavours.
+__device__ __forceinline__ void emit(EvState& s, const Records& r, uint64_t e, const Pending& pe) {
+  const double t = pe.t, z = pe.z;
+  const uint32_t this_cycle = pe.cycle;
+  const Winner w{0.0, 0.0, 0.0, 0.0, pe.i, pe.k, pe.K};
+  const U4 sd = s.key.draw(this_cycle, kPurposeSplit, 0);
+  const double phi = 2.0 * kPi * unit(sd.x, sd.y);
+  double sphi, cphi;
+  sincos(phi, &sphi, &cphi);
+  const int i = w.i, k = w.k, j = s.n;
+  P4 ni, nj, nk;
+  split_kinematics(r.load(i, e), r.load(k, e), t, z, cphi, sphi, ni, nj, nk);
+  r.store(i, e, ni);
+  r.store(k, e, nk);
+  r.store(j, e, nj);
+  emit_colours(s, r, e, w);
+}
+
 // The rest of one cycle once the winner is known: decision, then the
 // emission if accepted.
 __device__ __forceinline__ void veto_finish(EvState& s, const Records& r, uint64_t e, double best,
@@ -332,6 +377,161 @@ __device__ __forceinline__ void veto_cycle(EvState& s, const Records& r, uint64_
   const TrialCtx c = trial_ctx(s);
   for (int i = 0; i < s.n; ++i) parton_trials(c, r, e, i, best, w, s.trials, s.ends);
   veto_finish(s, r, e, best, w);
+}
+
+// ---------------------------------------------------------------------------
+// Massive quarks (vsh_massive.hpp): one cycle with each kernel's own phase
+// space.  Kernels whose partons are all massless take exactly the massless
+// numbers above, so an event without heavy quarks is the massless event.
+// ---------------------------------------------------------------------------
+struct MWinner {
+  Winner w;
+  double Q2, mi, mj, mk, fo;  // (p~ij + p~k)^2, masses, overestimate factor max(F, 1)
+  bool massive;
+};
+
+// product masses of kernel K (i keeps the splitter's slot)
+__device__ __forceinline__ void product_masses(int K, const QuarkMasses& qm, double& mi, double& mj) {
+  if (K < 10) {
+    mi = quark_mass(qm, K < 5 ? K + 1 : K - 4);
+    mj = 0.0;
+  } else if (K == 10) {
+    mi = 0.0;
+    mj = 0.0;
+  } else {
+    mi = quark_mass(qm, K - 10);
+    mj = mi;
+  }
+}
+
+// Every kernel of the end (i, k), in kernel order, each with its own z range
+// and coefficient; strict maximum of ln t over the trials.
+__device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int k, int pid_i, int pid_k,
+                                                   const P4& pi, const P4& pk, const QuarkMasses& qm,
+                                                   double& best, MWinner& W, uint32_t& trials,
+                                                   uint32_t& ends) {
+  const double q2 = 2.0 * mdot(pi, pk);
+  const double msp = quark_mass(qm, pid_i), mk = quark_mass(qm, pid_k);
+  const double Q2 = q2 + msp * msp + mk * mk;
+  const bool gluon = pid_i == kGluon;
+  const int nk = gluon ? 6 : 1;
+  bool active = false;
+#pragma unroll 1
+  for (int j = 0; j < nk; ++j) {
+    const int K = gluon ? 10 + j : (pid_i > 0 ? pid_i - 1 : 4 - pid_i);
+    double mi, mj, zm, zp, fo = 1.0;
+    product_masses(K, qm, mi, mj);
+    const bool massive = mi > 0.0 || mj > 0.0 || mk > 0.0;
+    if (!massive) {
+      if (!(q2 > 4.0 * c.tcut)) continue;
+      zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * c.tcut / q2));
+      zm = 1.0 - zp;
+    } else {
+      if (!massive_limits(Q2, mi, mj, mk, c.tcut, zm, zp)) continue;
+      const double f = massive_flux(Q2, mi, mj, mk, K < 10 ? mi : 0.0);
+      fo = f > 1.0 ? f : 1.0;
+    }
+    active = true;
+    const double L = log_fast((1.0 - zm) / (1.0 - zp));
+    double cc = K < 10 ? c.cfac * ((2.0 * kCF) * L)
+                : K == 10 ? c.cfac * (kCA * L)
+                          : c.cfac * ((0.5 * kTR) * (zp - zm));
+    if (massive) cc *= fo;
+    const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, (uint32_t)j >> 1));
+    const double u = (j & 1) ? unit(d.z, d.w) : unit(d.x, d.y);
+    const double lt_try = c.lt + log_fast(u) / cc;
+    trials += 1;
+    if (lt_try > best) {
+      best = lt_try;
+      W = MWinner{Winner{q2, zm, zp, L, i, k, K}, Q2, mi, mj, mk, fo, massive};
+    }
+  }
+  if (active) ends += 1;
+}
+
+__device__ __forceinline__ void parton_trials_massive(const TrialCtx& c, const Records& r, uint64_t e, int i,
+                                                      const QuarkMasses& qm, double& best, MWinner& W,
+                                                      uint32_t& trials, uint32_t& ends) {
+  const uint64_t oi = (uint64_t)i * r.stride + e;
+  const int pid_i = r.pid[oi];
+  int k1 = r.cpart[oi], k2 = r.apart[oi];
+  if (k2 == k1) k2 = kNoPartner;
+  if (k1 > k2) {
+    const int t = k1;
+    k1 = k2;
+    k2 = t;
+  }
+  const P4 pi = r.load(i, e);
+  if (k1 != kNoPartner)
+    end_trials_massive(c, i, k1, pid_i, r.pid[(uint64_t)k1 * r.stride + e], pi, r.load(k1, e), qm, best, W,
+                       trials, ends);
+  if (k2 != kNoPartner)
+    end_trials_massive(c, i, k2, pid_i, r.pid[(uint64_t)k2 * r.stride + e], pi, r.load(k2, e), qm, best, W,
+                       trials, ends);
+}
+
+__device__ __forceinline__ bool veto_decide_massive(EvState& s, double best, const MWinner& W, const U4& a,
+                                                    Pending& p, double& wsh) {
+  const Winner& w = W.w;
+  const uint32_t this_cycle = s.cycle++;
+  if (w.i < 0) {
+    s.status = kDone;
+    return false;
+  }
+  s.lt = best;
+  const double t = exp(best);
+  const double uz = unit(a.x, a.y);
+  const double z = w.K <= 10 ? 1.0 - (1.0 - w.zm) * exp(-uz * w.L) : w.zm + (w.zp - w.zm) * uz;
+  double prob;
+  if (!W.massive) {
+    const double y = t / (w.q2 * z * (1.0 - z));
+    if (!(y < 1.0)) return false;
+    prob = alpha_s_of_log(best) / s.asmax * kernel_value(w.K, z, y) * (1.0 - y) / kernel_over(w.K, z);
+  } else {
+    const double ratio = massive_ratio(w.K, t, z, W.Q2, W.mi, W.mj, W.mk, W.fo);
+    if (ratio < 0.0) return false;  // outside the phase space
+    prob = alpha_s_of_log(best) / s.asmax * ratio;
+  }
+  if (!accept_test(prob, a, wsh)) return false;
+  if (s.n == s.cap) {
+    s.status = kOverflow;
+    return false;
+  }
+  p = Pending{t, z, w.i, w.k, w.K, this_cycle};
+  return true;
+}
+
+__device__ __forceinline__ void emit_massive(EvState& s, const Records& r, uint64_t e, const Pending& pe,
+                                             const QuarkMasses& qm) {
+  const Winner w{0.0, 0.0, 0.0, 0.0, pe.i, pe.k, pe.K};
+  const U4 sd = s.key.draw(pe.cycle, kPurposeSplit, 0);
+  const double phi = 2.0 * kPi * unit(sd.x, sd.y);
+  double sphi, cphi;
+  sincos(phi, &sphi, &cphi);
+  const int i = w.i, k = w.k, j = s.n;
+  double mi, mj;
+  product_masses(w.K, qm, mi, mj);
+  const double mk = quark_mass(qm, r.pid[(uint64_t)k * r.stride + e]);
+  P4 ni, nj, nk;
+  if (mi > 0.0 || mj > 0.0 || mk > 0.0)
+    split_massive(r.load(i, e), r.load(k, e), mi, mj, mk, w.K < 10 ? mi : 0.0, pe.t, pe.z, cphi, sphi, ni, nj,
+                  nk);
+  else
+    split_kinematics(r.load(i, e), r.load(k, e), pe.t, pe.z, cphi, sphi, ni, nj, nk);
+  r.store(i, e, ni);
+  r.store(k, e, nk);
+  r.store(j, e, nj);
+  emit_colours(s, r, e, w);
+}
+
+__device__ __forceinline__ void veto_cycle_massive(EvState& s, const Records& r, uint64_t e,
+                                                   const QuarkMasses& qm) {
+  double best = s.ltc;
+  MWinner W{Winner{0.0, 0.0, 0.0, 0.0, -1, 0, 0}, 0.0, 0.0, 0.0, 0.0, 1.0, false};
+  const TrialCtx c = trial_ctx(s);
+  for (int i = 0; i < s.n; ++i) parton_trials_massive(c, r, e, i, qm, best, W, s.trials, s.ends);
+  Pending p;
+  if (veto_decide_massive(s, best, W, accept_draw(s), p, s.wsh)) emit_massive(s, r, e, p, qm);
 }
 
 // Fresh state for an event whose n initial partons sit in slot e of r.

@@ -1,0 +1,64 @@
+"""GPU parity of massive charm and bottom quarks (the extension the
+conclusions name) against the oracle's massive shower, event by event, in
+both forms and through serving."""
+import numpy as np
+import pytest
+
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+MC, MB = 1.5, 4.8
+TABLE = [0.0, 0.0, 0.0, 0.0, MC, MB]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2403_08692_amd as P
+
+    c = P.Context()
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("ecm,tcut,cap,n", [(91.2, 1.0, 64, 2000), (12.0, 0.5, 64, 1500), (500.0, 0.25, 256, 400)])
+def test_massive_parity(ctx, oracle, persistent, ecm, tcut, cap, n):
+    print(f"case massive ecm={ecm} tcut={tcut} cap={cap} n={n} persistent={persistent}", flush=True)
+    g = ctx.generate(n, seed=21, ecm=ecm, t_cut=tcut, max_partons=cap, summary=True, records=True,
+                     persistent=persistent, mass_c=MC, mass_b=MB)
+    o = oracle.generate(21, 0, n, ecm, tcut, cap, records=True, mass=TABLE)
+    rep, same = parity.compare(g, o, ecm, n)
+    print(rep, flush=True)
+    parity.assert_parity(rep)
+    fl = o["sum_i"][:, 4]
+    assert (fl == 5).sum() > 0.1 * n and g["n_done"] == int((o["sum_i"][:, 1] == 1).sum())
+    # heavy quarks on their mass shells in the GPU records
+    off = g["rec_offsets"].astype(np.int64)
+    for e in np.flatnonzero(fl >= 4)[:50]:
+        p, pid = g["rec_p"][off[e]:off[e + 1]], g["rec_pid"][off[e]:off[e + 1]]
+        m2 = p[:, 0] ** 2 - (p[:, 1:] ** 2).sum(1)
+        want = np.array([0.0 if f == 21 else TABLE[abs(f)] ** 2 for f in pid])
+        np.testing.assert_allclose(m2, want, atol=1e-9 * ecm * ecm)
+
+
+def test_massive_and_massless_requests_served_together(ctx):
+    heavy = dict(seed=31, ecm=91.2, t_cut=1.0, max_partons=64, mass_c=MC, mass_b=MB)
+    light = dict(seed=32, ecm=91.2, t_cut=1.0, max_partons=64)
+    ref_h = ctx.generate(3000, summary=True, **heavy)
+    ref_l = ctx.generate(3000, summary=True, **light)
+    th, tl = ctx.submit(3000, summary=True, **heavy), ctx.submit(3000, summary=True, **light)
+    for t, ref in ((th, ref_h), (tl, ref_l)):
+        got = ctx.wait(t)
+        np.testing.assert_array_equal(got["sum_i"], ref["sum_i"])
+        np.testing.assert_array_equal(got["hash"], ref["hash"])
+        np.testing.assert_allclose(got["sum_d"], ref["sum_d"], rtol=1e-12, atol=1e-15)
+
+
+def test_invalid_masses_rejected(ctx):
+    import paper_2403_08692_amd as P
+
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(P.VshError) as ei:
+            ctx.generate(10, mass_b=bad)
+        assert ei.value.code == -1

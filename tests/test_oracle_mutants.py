@@ -83,7 +83,7 @@ MUTANTS = [
     ("massive Q -> Q g mass term halved", "- 2.0 * mi * mi / (y * qb2));", "- mi * mi / (y * qb2));"),
     ("massive Jacobian dy/y taken as dt/t", "(t / (t + cz))", "(1.0)"),
     ("massive map without the spectator rescaling",
-     "double scale = sqrt(kallen(Q2, s, mk * mk) / kallen(Q2, mij * mij, mk * mk));", "double scale = 1.0;"),
+     "double scale = sqrt((lam > 0.0 ? lam : 0.0) / kallen(Q2, mij * mij, mk * mk));", "double scale = 1.0;"),
     ("massive map: sign of the p_k coefficient", "double bb = (mi2 - mj2 - (2.0 * z - 1.0) * s)",
      "double bb = (mi2 - mj2 + (2.0 * z - 1.0) * s)"),
     ("massive ME: axial current with the vector threshold", "aa * b2 * (1.0 + c * c)",
