@@ -165,7 +165,7 @@ def shower_kernel_name(form, tuning):
 
 
 def time_form(ctx, P, torch, w, n, form, steps, ecm_arr=None, tcut_arr=None, cycle_limit=0, keep=False,
-              t_over=0.0):
+              t_over=0.0, mass_c=0.0, mass_b=0.0):
     """ms per step (ME + shower + observables + histograms) and the shower
     kernel's mean ms for a workload through vsh_generate_into; with keep, also
     the last step's histograms and per-event veto-cycle counts and statuses."""
@@ -182,7 +182,7 @@ def time_form(ctx, P, torch, w, n, form, steps, ecm_arr=None, tcut_arr=None, cyc
         flags |= P.VSH_INPUTS_ON_DEVICE
     req, _ = make_request(n, w.seed, w.first_event, w.ecm, w.tcut, w.cap, flags,
                           None if e_dev is None else e_dev.data_ptr(), None if t_dev is None else t_dev.data_ptr(),
-                          cycle_limit, t_over)
+                          cycle_limit, t_over, mass_c, mass_b)
     ws_bytes = ctx.workspace_size(req)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     hist = torch.zeros(P.HIST_DOUBLES, dtype=torch.float64, device=dev)
@@ -488,6 +488,11 @@ def main():
         ctx.autotune(1 << 18, seed=w.seed, ecm=w.ecm, t_cut=w.tcut, max_partons=w.cap, persistent=False)
         extra["tail_cut"] = tail_cut_study(ctx, P, torch, w, n, refill_ms)
         extra["weighted_veto"] = weighted_veto_study(ctx, P, torch, w, n)
+        # massive charm and bottom quarks (lane mapping's massive kernels), both forms
+        extra["massive_lep"] = {"workload": w.name, "mass_c": 1.5, "mass_b": 4.8,
+                                "plain": time_form(ctx, P, torch, w, n, "plain", 5, mass_c=1.5, mass_b=4.8),
+                                "persistent": time_form(ctx, P, torch, w, n, "persistent", 5, mass_c=1.5,
+                                                        mass_b=4.8)}
         # mixed energies and cutoffs, 10^7 events in one persistent launch (and the plain form)
         m = workloads.MIXED
         e_arr, t_arr = m.per_event()
