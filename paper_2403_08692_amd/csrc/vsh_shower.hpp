@@ -404,8 +404,12 @@ __device__ __forceinline__ void product_masses(int K, const QuarkMasses& qm, dou
   }
 }
 
-// Every kernel of the end (i, k), in kernel order, each with its own z range
-// and coefficient; strict maximum of ln t over the trials.
+// Every kernel of the end (i, k) in kernel order, strict maximum of ln t.
+// Kernels share what their masses let them share: g -> g g and the three
+// light g -> q qbar have the same z range (only the spectator's mass enters),
+// and the light flavours one coefficient, so only their largest uniform needs
+// a log; the c and b kernels have their own range and coefficient.  Each
+// Philox block (two kernels) is drawn once.
 __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int k, int pid_i, int pid_k,
                                                    const P4& pi, const P4& pk, const QuarkMasses& qm,
                                                    double& best, MWinner& W, uint32_t& trials,
@@ -413,37 +417,106 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
   const double q2 = 2.0 * mdot(pi, pk);
   const double msp = quark_mass(qm, pid_i), mk = quark_mass(qm, pid_k);
   const double Q2 = q2 + msp * msp + mk * mk;
-  const bool gluon = pid_i == kGluon;
-  const int nk = gluon ? 6 : 1;
   bool active = false;
-#pragma unroll 1
-  for (int j = 0; j < nk; ++j) {
-    const int K = gluon ? 10 + j : (pid_i > 0 ? pid_i - 1 : 4 - pid_i);
-    double mi, mj, zm, zp, fo = 1.0;
-    product_masses(K, qm, mi, mj);
-    const bool massive = mi > 0.0 || mj > 0.0 || mk > 0.0;
+  if (pid_i != kGluon) {
+    const int K = pid_i > 0 ? pid_i - 1 : 4 - pid_i;
+    const double mi = msp;
+    const bool massive = mi > 0.0 || mk > 0.0;
+    double zm, zp, fo = 1.0;
     if (!massive) {
-      if (!(q2 > 4.0 * c.tcut)) continue;
-      zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * c.tcut / q2));
-      zm = 1.0 - zp;
+      active = q2 > 4.0 * c.tcut;
+      if (active) {
+        zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * c.tcut / q2));
+        zm = 1.0 - zp;
+      }
     } else {
-      if (!massive_limits(Q2, mi, mj, mk, c.tcut, zm, zp)) continue;
-      const double f = massive_flux(Q2, mi, mj, mk, K < 10 ? mi : 0.0);
-      fo = f > 1.0 ? f : 1.0;
+      active = massive_limits(Q2, mi, 0.0, mk, c.tcut, zm, zp);
+      if (active) {
+        const double f = massive_flux(Q2, mi, 0.0, mk, mi);
+        fo = f > 1.0 ? f : 1.0;
+      }
     }
-    active = true;
-    const double L = log_fast((1.0 - zm) / (1.0 - zp));
-    double cc = K < 10 ? c.cfac * ((2.0 * kCF) * L)
-                : K == 10 ? c.cfac * (kCA * L)
-                          : c.cfac * ((0.5 * kTR) * (zp - zm));
-    if (massive) cc *= fo;
-    const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, (uint32_t)j >> 1));
-    const double u = (j & 1) ? unit(d.z, d.w) : unit(d.x, d.y);
-    const double lt_try = c.lt + log_fast(u) / cc;
-    trials += 1;
-    if (lt_try > best) {
-      best = lt_try;
-      W = MWinner{Winner{q2, zm, zp, L, i, k, K}, Q2, mi, mj, mk, fo, massive};
+    if (active) {
+      const double L = log_fast((1.0 - zm) / (1.0 - zp));
+      double cc = c.cfac * ((2.0 * kCF) * L);
+      if (massive) cc *= fo;
+      const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
+      const double lt_try = c.lt + log_fast(unit(d.x, d.y)) / cc;
+      trials += 1;
+      if (lt_try > best) {
+        best = lt_try;
+        W = MWinner{Winner{q2, zm, zp, L, i, k, K}, Q2, mi, 0.0, mk, fo, massive};
+      }
+    }
+  } else {
+    // blocks: 0 -> g g, d dbar; 1 -> u ubar, s sbar; 2 -> c cbar, b bbar
+    const U4 d0 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
+    const U4 d1 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 1));
+    const U4 d2 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 2));
+    const bool light_massive = mk > 0.0;  // g g and light q qbar: only the spectator's mass
+    double zm = 0.0, zp = 0.0, L = 0.0, cqq = 0.0, foa = 1.0;
+    bool ok = light_massive ? massive_limits(Q2, 0.0, 0.0, mk, c.tcut, zm, zp) : q2 > 4.0 * c.tcut;
+    if (ok) {
+      if (!light_massive) {
+        zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * c.tcut / q2));
+        zm = 1.0 - zp;
+      } else {
+        const double f = massive_flux(Q2, 0.0, 0.0, mk, 0.0);  // 1 up to rounding
+        foa = f > 1.0 ? f : 1.0;
+      }
+      active = true;
+      L = log_fast((1.0 - zm) / (1.0 - zp));
+      double cgg = c.cfac * (kCA * L);
+      cqq = c.cfac * ((0.5 * kTR) * (zp - zm));
+      if (light_massive) {
+        cgg *= foa;
+        cqq *= foa;
+      }
+      trials += 4;
+      const double lgg = c.lt + log_fast(unit(d0.x, d0.y)) / cgg;
+      if (lgg > best) {
+        best = lgg;
+        W = MWinner{Winner{q2, zm, zp, L, i, k, 10}, Q2, 0.0, 0.0, mk, foa, light_massive};
+      }
+      double um = unit(d0.z, d0.w);
+      int fm = 1;
+      const double uu = unit(d1.x, d1.y), us = unit(d1.z, d1.w);
+      if (uu > um) {  // the first flavour wins ties, as in the kernel loop
+        um = uu;
+        fm = 2;
+      }
+      if (us > um) {
+        um = us;
+        fm = 3;
+      }
+      const double lqq = c.lt + log_fast(um) / cqq;
+      if (lqq > best) {
+        best = lqq;
+        W = MWinner{Winner{q2, zm, zp, L, i, k, 10 + fm}, Q2, 0.0, 0.0, mk, foa, light_massive};
+      }
+    }
+#pragma unroll 1
+    for (int f = 4; f <= 5; ++f) {  // c cbar, b bbar
+      const double m = quark_mass(qm, f);
+      const bool massive = m > 0.0 || mk > 0.0;
+      double zmf = zm, zpf = zp, Lf = L, cf = cqq, fo = foa;
+      if (m > 0.0) {
+        if (!massive_limits(Q2, m, m, mk, c.tcut, zmf, zpf)) continue;
+        const double fl = massive_flux(Q2, m, m, mk, 0.0);
+        fo = fl > 1.0 ? fl : 1.0;
+        Lf = log_fast((1.0 - zmf) / (1.0 - zpf));
+        cf = c.cfac * ((0.5 * kTR) * (zpf - zmf)) * fo;
+      } else if (!ok) {
+        continue;  // a massless flavour shares the light flavours' range
+      }
+      active = true;
+      trials += 1;
+      const double u = f == 4 ? unit(d2.x, d2.y) : unit(d2.z, d2.w);
+      const double lt_try = c.lt + log_fast(u) / cf;
+      if (lt_try > best) {
+        best = lt_try;
+        W = MWinner{Winner{q2, zmf, zpf, Lf, i, k, 10 + f}, Q2, m, m, mk, fo, massive};
+      }
     }
   }
   if (active) ends += 1;

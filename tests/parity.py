@@ -6,7 +6,10 @@ Bars (written here, used by every GPU parity test):
     lines -- are compared exactly ("identical events");
   * at least 99.9% of events must be identical;
   * on identical events every momentum component agrees to 1e-9 sqrt(s);
-  * weights (on identical events) to 1e-12 relative; observables to 1e-9 relative or 1e-12
+  * weights (on identical events) to 1e-9 relative: with the weighted veto an
+    event weight carries one factor +-(2r - 1) per veto above the trial
+    density, each from the same kinematics as the momenta, so it gets the
+    momenta's bar; observables to 1e-9 relative or 1e-12
     absolute (they are computed from momenta that agree to ~1e-15);
   * histograms: chi^2/ndf < 1.5 over filled bins, with the entry counts
     per bin allowed to differ only by events that differ.
@@ -21,7 +24,7 @@ import numpy as np
 MOM_TOL = 1e-9
 OBS_RTOL = 1e-9
 OBS_ATOL = 1e-12
-W_RTOL = 1e-12
+W_RTOL = 1e-9
 MIN_IDENTICAL = 0.999
 
 

@@ -62,3 +62,21 @@ def test_invalid_masses_rejected(ctx):
         with pytest.raises(P.VshError) as ei:
             ctx.generate(10, mass_b=bad)
         assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("persistent,masses", [(False, True), (True, True), (False, False), (True, False)])
+def test_options_together(ctx, oracle, persistent, masses):
+    # tail cut, weighted veto and (optionally) quark masses in one request
+    n, C, t_over = 2000, 40, 20.0
+    mc, mb = (MC, MB) if masses else (0.0, 0.0)
+    print(f"case options n={n} C={C} t_over={t_over} masses={masses} persistent={persistent}", flush=True)
+    g = ctx.generate(n, seed=23, ecm=200.0, t_cut=0.5, max_partons=128, summary=True, records=True,
+                     persistent=persistent, cycle_limit=C, t_over=t_over, mass_c=mc, mass_b=mb)
+    o = oracle.generate(23, 0, n, 200.0, 0.5, 128, records=True, max_cycles=C, t_over=t_over,
+                        mass=TABLE if masses else None)
+    rep, same = parity.compare(g, o, 200.0, n)
+    print(rep, flush=True)
+    parity.assert_parity(rep)
+    st = o["sum_i"][:, 1]
+    assert (st == 5).any() and (o["sum_d"][:, 0] < 0).any()
+    assert g["n_cycle_limit"] == int((st == 5).sum())
