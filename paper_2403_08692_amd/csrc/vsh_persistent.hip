@@ -233,7 +233,9 @@ __device__ __forceinline__ void set_bit(uint64_t* m, int a) {
 // per parton, one cache entry of kCacheWords words at
 // rec[((col * cap) + i) * kCacheWords]: its id and its spectators in
 // ascending order (packed in word 0), then per end the trial coefficients
-// (quark kernel or g -> g g, and g -> f fbar; 0 = no phase space).  An entry
+// (quark kernel or g -> g g, and g -> f fbar; 0 = no phase space; a quark
+// end keeps the g -> f fbar form cfac T_R/2 (z+ - z-) too, from which the
+// decision recovers the end's range and mass).  An entry
 // changes only when an emission touches the parton or its partners, which
 // marks it stale: then it is rebuilt from the records (the values a
 // recomputation gives).  A fresh parton needs nothing but its entry.  Same
@@ -522,8 +524,20 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       w.k = (int)((bi >> 4) & 1023u);
       w.K = (int)(bi & 15u);
       best = sh.best_v[lane];
-      end_limits(slots.load(w.i, slot), slots.load(w.k, slot), s.tcut, w.q2, w.zm, w.zp);
-      w.L = log_fast((1.0 - w.zm) / (1.0 - w.zp));
+      // the winning end's coefficients: from its fresh cache entry, or
+      // recomputed from the records (the same numbers)
+      double ca, cb;
+      if (kCached) {
+        const uint64_t* ent = ec.rec + ((wave_col + lane) * ec.cap + (uint64_t)w.i) * kCacheWords;
+        const int e = (int)((ent[0] >> 8) & 0xFFFFu) == w.k ? 0 : 1;
+        ca = __longlong_as_double((long long)ent[1 + 2 * e]);
+        cb = __longlong_as_double((long long)ent[2 + 2 * e]);
+      } else {
+        double q2, zm, zp, L;
+        end_coeffs(s.cfac, s.tcut, slots.pid[(uint64_t)w.i * slots.stride + slot], slots.load(w.i, slot),
+                   slots.load(w.k, slot), q2, zm, zp, L, ca, cb);
+      }
+      end_from_coeffs(s.cfac, s.tcut, w.K, ca, cb, w);
     }
     pend = veto_decide_drawn(s, best, w, acc, pd, sh.wsh[lane]);
   }

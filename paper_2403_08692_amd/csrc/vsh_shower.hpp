@@ -129,22 +129,30 @@ __device__ __forceinline__ bool end_limits(const P4& pi, const P4& pk, double tc
 }
 
 // Trial coefficients c = alpha_s^over/(2 pi) * I of the dipole end (i, k):
-// for a quark end ca = its one kernel's; for a gluon end ca = g -> g g's and
-// cb = the common one of the five g -> f fbar kernels.  False (and no
+// for a quark end ca = its one kernel's; for a gluon end ca = g -> g g's; cb
+// = the common one of the five g -> f fbar kernels (kept for a quark end too:
+// the decision recovers the end's range from it).  False (and no
 // coefficients) for an end without phase space above the cutoff.
 __device__ __forceinline__ bool end_coeffs(double cfac, double tcut, int pid_i, const P4& pi, const P4& pk,
                                            double& q2, double& zm, double& zp, double& L, double& ca,
                                            double& cb) {
   if (!end_limits(pi, pk, tcut, q2, zm, zp)) return false;
   L = log_fast((1.0 - zm) / (1.0 - zp));
-  if (pid_i != kGluon) {
-    ca = cfac * ((2.0 * kCF) * L);
-    cb = 0.0;
-  } else {
-    ca = cfac * (kCA * L);
-    cb = cfac * ((0.5 * kTR) * (zp - zm));
-  }
+  ca = pid_i != kGluon ? cfac * ((2.0 * kCF) * L) : cfac * (kCA * L);
+  cb = cfac * ((0.5 * kTR) * (zp - zm));
   return true;
+}
+
+// The winning end's z range, mass and log range as the decision takes them:
+// recovered from its trial coefficients (the numbers the flattened kernels
+// cache), so that every form decides from the same bits.  cb / (cfac T_R/2)
+// = z+ - z- = sqrt(1 - 4 t_C / Q^2), ca / (cfac C) = L with C = 2 C_F or C_A.
+__device__ __forceinline__ void end_from_coeffs(double cfac, double tcut, int K, double ca, double cb, Winner& w) {
+  const double dz = cb / (cfac * (0.5 * kTR));
+  w.zp = 0.5 * (1.0 + dz);
+  w.zm = 1.0 - w.zp;
+  w.q2 = 4.0 * tcut / ((1.0 - dz) * (1.0 + dz));
+  w.L = ca / (cfac * (K <= 9 ? 2.0 * kCF : kCA));
 }
 
 // The trials of an end with coefficients (ca, cb): t_try = t R^(1/c)
@@ -205,7 +213,12 @@ __device__ __forceinline__ void end_trials(const TrialCtx& c, int i, int k, int 
   if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, pk, q2, zm, zp, L, ca, cb)) return;
   ends += 1;
   const int K = end_draws(c, i, k, pid_i, ca, cb, best, trials);
-  if (K >= 0) w = Winner{q2, zm, zp, L, i, k, K};
+  if (K >= 0) {
+    w.i = i;
+    w.k = k;
+    w.K = K;
+    end_from_coeffs(c.cfac, c.tcut, K, ca, cb, w);
+  }
 }
 
 // Trials of parton i of the event in slot e: its dipole ends in ascending
@@ -445,7 +458,9 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
       trials += 1;
       if (lt_try > best) {
         best = lt_try;
-        W = MWinner{Winner{q2, zm, zp, L, i, k, K}, Q2, mi, 0.0, mk, fo, massive};
+        Winner wn{q2, zm, zp, L, i, k, K};
+        if (!massive) end_from_coeffs(c.cfac, c.tcut, K, cc, c.cfac * ((0.5 * kTR) * (zp - zm)), wn);
+        W = MWinner{wn, Q2, mi, 0.0, mk, fo, massive};
       }
     }
   } else {
@@ -454,7 +469,7 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
     const U4 d1 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 1));
     const U4 d2 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 2));
     const bool light_massive = mk > 0.0;  // g g and light q qbar: only the spectator's mass
-    double zm = 0.0, zp = 0.0, L = 0.0, cqq = 0.0, foa = 1.0;
+    double zm = 0.0, zp = 0.0, L = 0.0, cgg = 0.0, cqq = 0.0, foa = 1.0;
     bool ok = light_massive ? massive_limits(Q2, 0.0, 0.0, mk, c.tcut, zm, zp) : q2 > 4.0 * c.tcut;
     if (ok) {
       if (!light_massive) {
@@ -466,7 +481,7 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
       }
       active = true;
       L = log_fast((1.0 - zm) / (1.0 - zp));
-      double cgg = c.cfac * (kCA * L);
+      cgg = c.cfac * (kCA * L);
       cqq = c.cfac * ((0.5 * kTR) * (zp - zm));
       if (light_massive) {
         cgg *= foa;
@@ -474,9 +489,12 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
       }
       trials += 4;
       const double lgg = c.lt + log_fast(unit(d0.x, d0.y)) / cgg;
+      // a winner among these kernels: the range as the massless forms take it
+      Winner wn{q2, zm, zp, L, i, k, 10};
+      if (!light_massive) end_from_coeffs(c.cfac, c.tcut, 10, cgg, cqq, wn);
       if (lgg > best) {
         best = lgg;
-        W = MWinner{Winner{q2, zm, zp, L, i, k, 10}, Q2, 0.0, 0.0, mk, foa, light_massive};
+        W = MWinner{wn, Q2, 0.0, 0.0, mk, foa, light_massive};
       }
       double um = unit(d0.z, d0.w);
       int fm = 1;
@@ -492,7 +510,8 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
       const double lqq = c.lt + log_fast(um) / cqq;
       if (lqq > best) {
         best = lqq;
-        W = MWinner{Winner{q2, zm, zp, L, i, k, 10 + fm}, Q2, 0.0, 0.0, mk, foa, light_massive};
+        wn.K = 10 + fm;
+        W = MWinner{wn, Q2, 0.0, 0.0, mk, foa, light_massive};
       }
     }
 #pragma unroll 1
@@ -515,7 +534,9 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
       const double lt_try = c.lt + log_fast(u) / cf;
       if (lt_try > best) {
         best = lt_try;
-        W = MWinner{Winner{q2, zmf, zpf, Lf, i, k, 10 + f}, Q2, m, m, mk, fo, massive};
+        Winner wn{q2, zmf, zpf, Lf, i, k, 10 + f};
+        if (!massive) end_from_coeffs(c.cfac, c.tcut, 10 + f, cgg, cqq, wn);
+        W = MWinner{wn, Q2, m, m, mk, fo, massive};
       }
     }
   }
