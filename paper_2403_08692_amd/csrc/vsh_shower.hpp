@@ -107,7 +107,7 @@ __device__ __forceinline__ TrialCtx trial_ctx(const EvState& s) {
 }
 
 struct Winner {
-  double q2, zm, zp, L;  // L = ln((1 - zm)/(1 - zp)), the log of the z range
+  double rq2, zm, zp, L;  // rq2 = 1/Q^2; L = ln((1 - zm)/(1 - zp)), the log of the z range
   int i, k, K;
 };
 
@@ -147,12 +147,39 @@ __device__ __forceinline__ bool end_coeffs(double cfac, double tcut, int pid_i, 
 // recovered from its trial coefficients (the numbers the flattened kernels
 // cache), so that every form decides from the same bits.  cb / (cfac T_R/2)
 // = z+ - z- = sqrt(1 - 4 t_C / Q^2), ca / (cfac C) = L with C = 2 C_F or C_A.
+// The divisions by cfac and t_C do not wait for the coefficients.
 __device__ __forceinline__ void end_from_coeffs(double cfac, double tcut, int K, double ca, double cb, Winner& w) {
-  const double dz = cb / (cfac * (0.5 * kTR));
+  const double rcf = 1.0 / cfac, rt4 = 0.25 / tcut;
+  const double dz = cb * (rcf * (1.0 / (0.5 * kTR)));
   w.zp = 0.5 * (1.0 + dz);
   w.zm = 1.0 - w.zp;
-  w.q2 = 4.0 * tcut / ((1.0 - dz) * (1.0 + dz));
-  w.L = ca / (cfac * (K <= 9 ? 2.0 * kCF : kCA));
+  w.rq2 = ((1.0 - dz) * (1.0 + dz)) * rt4;
+  w.L = ca * (rcf * (K <= 9 ? 1.0 / (2.0 * kCF) : 1.0 / kCA));
+}
+
+// True over trial density of a massless kernel at scale t = e^lt (App. A:
+// alpha_s(t)/alpha_s^over x V (1-y) / O) in one division, with y = yn/yd,
+// yn = t/Q^2 and yd = z(1-z); the CS w = 1 - z(1-y) = wn/yd.  -1 for
+// y >= 1 (outside the phase space).
+__device__ __forceinline__ double massless_ratio(int K, double lt, double t, double z, double rq2,
+                                                 double asmax) {
+  const double omz = 1.0 - z;
+  const double yn = t * rq2, yd = z * omz;
+  if (!(yn < yd)) return -1.0;
+  constexpr double b0 = (33.0 - 2.0 * kNf) / (12.0 * kPi);
+  constexpr double ln_mz2 = 9.025837845847876;  // ln(91.1876^2), as in alpha_s_of_log
+  const double da = 1.0 + kAlphaSMZ * b0 * (lt - ln_mz2);
+  double num, den;
+  if (K <= 10) {
+    const double wn = omz * yd + z * yn;
+    const double a = K < 10 ? 1.0 + z : 2.0 - z * omz;  // q -> q g : g -> g g
+    num = omz * (yd - yn) * (2.0 * yd - a * wn);
+    den = 2.0 * yd * wn;
+  } else {
+    num = (1.0 - 2.0 * z * omz) * (yd - yn);
+    den = yd;
+  }
+  return kAlphaSMZ * num / (asmax * da * den);
 }
 
 // The trials of an end with coefficients (ca, cb): t_try = t R^(1/c)
@@ -278,10 +305,8 @@ __device__ __forceinline__ bool veto_decide_drawn(EvState& s, double best, const
   // 1 - z = (1 - zm) ((1 - zp)/(1 - zm))^u = (1 - zm) exp(-u L)
   const double uz = unit(a.x, a.y);
   const double z = w.K <= 10 ? 1.0 - (1.0 - w.zm) * exp(-uz * w.L) : w.zm + (w.zp - w.zm) * uz;
-  const double y = t / (w.q2 * z * (1.0 - z));
-  if (!(y < 1.0)) return false;
-  const double prob =
-      alpha_s_of_log(best) / s.asmax * kernel_value(w.K, z, y) * (1.0 - y) / kernel_over(w.K, z);
+  const double prob = massless_ratio(w.K, best, t, z, w.rq2, s.asmax);
+  if (prob < 0.0) return false;  // y >= 1
   if (!accept_test(prob, a, wsh)) return false;
   if (s.n == s.cap) {
     s.status = kOverflow;
@@ -458,7 +483,7 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
       trials += 1;
       if (lt_try > best) {
         best = lt_try;
-        Winner wn{q2, zm, zp, L, i, k, K};
+        Winner wn{0.0, zm, zp, L, i, k, K};
         if (!massive) end_from_coeffs(c.cfac, c.tcut, K, cc, c.cfac * ((0.5 * kTR) * (zp - zm)), wn);
         W = MWinner{wn, Q2, mi, 0.0, mk, fo, massive};
       }
@@ -490,7 +515,7 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
       trials += 4;
       const double lgg = c.lt + log_fast(unit(d0.x, d0.y)) / cgg;
       // a winner among these kernels: the range as the massless forms take it
-      Winner wn{q2, zm, zp, L, i, k, 10};
+      Winner wn{0.0, zm, zp, L, i, k, 10};
       if (!light_massive) end_from_coeffs(c.cfac, c.tcut, 10, cgg, cqq, wn);
       if (lgg > best) {
         best = lgg;
@@ -534,7 +559,7 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
       const double lt_try = c.lt + log_fast(u) / cf;
       if (lt_try > best) {
         best = lt_try;
-        Winner wn{q2, zmf, zpf, Lf, i, k, 10 + f};
+        Winner wn{0.0, zmf, zpf, Lf, i, k, 10 + f};
         if (!massive) end_from_coeffs(c.cfac, c.tcut, 10 + f, cgg, cqq, wn);
         W = MWinner{wn, Q2, m, m, mk, fo, massive};
       }
@@ -578,9 +603,8 @@ __device__ __forceinline__ bool veto_decide_massive(EvState& s, double best, con
   const double z = w.K <= 10 ? 1.0 - (1.0 - w.zm) * exp(-uz * w.L) : w.zm + (w.zp - w.zm) * uz;
   double prob;
   if (!W.massive) {
-    const double y = t / (w.q2 * z * (1.0 - z));
-    if (!(y < 1.0)) return false;
-    prob = alpha_s_of_log(best) / s.asmax * kernel_value(w.K, z, y) * (1.0 - y) / kernel_over(w.K, z);
+    prob = massless_ratio(w.K, best, t, z, w.rq2, s.asmax);
+    if (prob < 0.0) return false;  // y >= 1
   } else {
     const double ratio = massive_ratio(w.K, t, z, W.Q2, W.mi, W.mj, W.mk, W.fo);
     if (ratio < 0.0) return false;  // outside the phase space
