@@ -176,6 +176,18 @@ extern __shared__ uint64_t flat_gmask[];
 
 __device__ __forceinline__ uint32_t mask_words(uint32_t cap) { return (cap + 63) / 64; }
 
+// Wave-wide scan and reduction through the device library's cross-lane
+// (DPP) sequences; every lane of the wave must call them.
+extern "C" __device__ uint64_t __ockl_wfscan_add_u64(uint64_t, bool);
+extern "C" __device__ uint32_t __ockl_wfred_max_u32(uint32_t);
+__device__ __forceinline__ uint64_t wave_inclusive_sum(uint64_t x) { return __ockl_wfscan_add_u64(x, true); }
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) { return __ockl_wfred_max_u32(x); }
+__device__ __forceinline__ uint64_t lane63(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint32_t owner_of(const uint32_t* start, uint32_t j) {
   uint32_t lo = 0, hi = 64;  // last o with start[o] <= j (owners with no items have start[o] == start[o+1])
   while (hi - lo > 1) {
@@ -372,11 +384,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       if (kCached) ns += __popcll(mys[w]);
     }
   const uint64_t mine = trial ? ((uint64_t)ng | ((uint64_t)((uint32_t)s.n - ng) << 21) | ((uint64_t)ns << 42)) : 0ull;
-  uint64_t incl = mine;
-  for (uint32_t d = 1; d < 64; d <<= 1) {
-    const uint64_t t = __shfl_up(incl, d);
-    if (lane >= d) incl += t;
-  }
+  const uint64_t incl = wave_inclusive_sum(mine);  // every lane of the wave takes part
   const uint64_t excl = incl - mine;
   sh.gstart[lane] = (uint32_t)(excl & kF);
   sh.qstart[lane] = (uint32_t)((excl >> 21) & kF);
@@ -386,16 +394,11 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     sh.qstart[64] = (uint32_t)((incl >> 21) & kF);
     sh.sstart[64] = (uint32_t)(incl >> 42);
   }
-  const uint64_t tot = __shfl(incl, 63);
+  const uint64_t tot = lane63(incl);
   const uint32_t n_g = (uint32_t)(tot & kF), n_q = (uint32_t)((tot >> 21) & kF), n_s = (uint32_t)(tot >> 42);
   // longest per-event run of items in either section: a round's segmented
   // max needs only the shuffle steps below it
-  uint32_t gmax = (uint32_t)(mine & kF), qmax = (uint32_t)((mine >> 21) & kF);
-  for (uint32_t d = 32; d >= 1; d >>= 1) {
-    const uint32_t a = __shfl_xor(gmax, d), b = __shfl_xor(qmax, d);
-    gmax = a > gmax ? a : gmax;
-    qmax = b > qmax ? b : qmax;
-  }
+  const uint32_t gmax = wave_max((uint32_t)(mine & kF)), qmax = wave_max((uint32_t)((mine >> 21) & kF));
   constexpr uint32_t kItems = sizeof(sh.item) / sizeof(sh.item[0]);
   constexpr uint32_t kSItems = sizeof(sh.sitem) / sizeof(sh.sitem[0]);
   if (trial) {  // list this event's items (beyond the lists' lengths rounds search the offsets instead)
