@@ -165,7 +165,7 @@ struct FlatShared {
   uint16_t sitem[512];              // the cycle's stale partons, owner << 10 | parton
   double best_v[64];
   uint32_t best_idx[64];
-  uint32_t trials[64], ends[64];
+  uint32_t counts[64];  // the cycle's trials (low 16 bits) and active ends (high 16 bits) per owner
   uint32_t climit[64];  // each event's cycle limit
   double wsh[64];       // each event's shower weight (weighted veto)
 };
@@ -430,8 +430,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   sh.cycle[lane] = s.cycle;
   sh.best_v[lane] = -INFINITY;
   sh.best_idx[lane] = kNoTrial;
-  sh.trials[lane] = 0;
-  sh.ends[lane] = 0;
+  sh.counts[lane] = 0;
   __syncthreads();
   // --- rebuild the cache entries of the stale partons, 64 per round
   if (kCached && n_s > 0) {
@@ -492,8 +491,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
         v = best;
         idx = widx;
       }
-      atomicAdd(&sh.trials[o], nt);
-      atomicAdd(&sh.ends[o], ne);
+      atomicAdd(&sh.counts[o], nt | (ne << 16));  // at most 12 x 1024 trials and 2048 ends per cycle
     }
     for (uint32_t d = 1; d < 64 && d < run; d <<= 1) {
       const double vn = __shfl_up(v, d);
@@ -517,8 +515,8 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   }
   // --- each owner that made trials decides its cycle
   if (trial) {
-    s.trials += sh.trials[lane];
-    s.ends += sh.ends[lane];
+    s.trials += sh.counts[lane] & 0xFFFFu;
+    s.ends += sh.counts[lane] >> 16;
     const uint32_t bi = sh.best_idx[lane];
     Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
     double best = s.ltc;
