@@ -16,13 +16,15 @@
  *    vsh_last_error(ctx) describes it (valid until the next call on ctx).
  *  - Units: GeV for energies and momenta, GeV^2 for t and t_C, pb for
  *    weights.  Momenta are (E, px, py, pz).
- *  - An event is a pure function of (seed, event id, sqrt(s), t_C, cap):
+ *  - An event is a pure function of (seed, event id, sqrt(s), t_C, cap) and
+ *    the request's physics options (cycle_limit, t_over, quark masses):
  *    every random number is Philox4x32-10 keyed by (seed, event id) with a
  *    counter naming the draw, so results do not depend on batching, launch
  *    form, lane mapping or on which other requests share the device.
  *  - Per-event problems (record overflow, non-finite momenta, violated
- *    momentum conservation) are not call errors: they set the event's status
- *    and are counted in the result; such events are left out of histograms.
+ *    momentum conservation) and the tail cut (cycle_limit) are not call
+ *    errors: they set the event's status and are counted in the result;
+ *    such events are left out of histograms.
  *  - Threading: one context per device.  A context is internally locked:
  *    calls from several host threads are serialised.
  */
@@ -36,7 +38,7 @@ extern "C" {
 #endif
 
 #define VSH_VERSION_MAJOR 1
-#define VSH_VERSION_MINOR 0
+#define VSH_VERSION_MINOR 1
 
 typedef enum {
   VSH_OK = 0,
@@ -184,8 +186,9 @@ typedef struct {
    results to pinned host memory.  Requests larger than the budget allows at
    once are processed in event-id chunks (identical results).
    Errors: VSH_E_INVALID (n_events = 0, ecm <= 0, t_cut <= 0.01, max_partons
-   outside 2..1024, unknown flags), VSH_E_NOMEM (not even one chunk fits),
-   VSH_E_DEVICE. */
+   outside 2..1024, unknown flags, t_over neither 0 nor a finite value above
+   0.01, a negative or non-finite quark mass), VSH_E_NOMEM (not even one
+   chunk fits), VSH_E_DEVICE. */
 vsh_status vsh_generate(vsh_ctx *ctx, const vsh_request *req, vsh_result **out);
 void vsh_result_free(vsh_result *res);
 
