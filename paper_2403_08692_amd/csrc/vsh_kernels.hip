@@ -156,15 +156,37 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
   // sit at the front of perm, largest first.
   const uint64_t n_big = sc.threshold <= cap ? sc.cnt[cap - sc.threshold] : 0u;  // done by k_obs_group
   const uint64_t n_mid = (uint32_t)kObsRegSlots < cap ? sc.cnt[cap - (kObsRegSlots + 1)] : n_big;
-  // events of at most kObsRegSlots partons, in event order (coalesced records and summaries)
-  for (uint64_t e = t; e < n; e += step) {
-    const int np = sm.i[kSiN * sm.stride + e];
-    if (np > kObsRegSlots || (uint32_t)np >= sc.threshold) continue;  // the lane groups take those
-    const int status = sm.i[kSiStatus * sm.stride + e];
-    const ObsOut o = reg_observables<kObsRegSlots, kMassive>(r, e, np, in.ecm_of(e), status, in);
-    if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
-    for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
-    sm.i[kSiStatus * sm.stride + e] = o.status;
+  // events of at most kObsRegSlots partons, in windows of 256 consecutive
+  // events (coalesced counts; the records of a window share cache lines),
+  // each window ordered by parton count in LDS so that a wave's events have
+  // nearly the same size and its loops stop at the wave's largest
+  __shared__ uint16_t order[256];
+  __shared__ uint32_t bin_n[kObsRegSlots + 2];  // events per parton count, then the others
+  for (uint64_t w0 = (uint64_t)blockIdx.x * 256; w0 < n; w0 += (uint64_t)gridDim.x * 256) {
+    const uint64_t e_own = w0 + threadIdx.x;
+    const int np_own = e_own < n ? sm.i[kSiN * sm.stride + e_own] : kObsRegSlots + 1;
+    const bool mine = np_own <= kObsRegSlots && (uint32_t)np_own < sc.threshold;  // else the lane groups
+    const int bin = mine ? np_own : kObsRegSlots + 1;
+    if (threadIdx.x < kObsRegSlots + 2) bin_n[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t rank = atomicAdd(&bin_n[bin], 1u);
+    __syncthreads();
+    uint32_t start = 0;
+    for (int b = 0; b < bin; ++b) start += bin_n[b];
+    order[start + rank] = (uint16_t)threadIdx.x;
+    __syncthreads();
+    const uint64_t e = w0 + order[threadIdx.x];
+    const int np = e < n ? sm.i[kSiN * sm.stride + e] : kObsRegSlots + 1;
+    const bool ok = np <= kObsRegSlots && (uint32_t)np < sc.threshold;
+    const int wmax = (int)wave_max(ok ? (uint32_t)np : 0u);
+    if (ok) {
+      const int status = sm.i[kSiStatus * sm.stride + e];
+      const ObsOut o = reg_observables<kObsRegSlots, kMassive>(r, e, np, wmax, in.ecm_of(e), status, in);
+      if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
+      for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
+      sm.i[kSiStatus * sm.stride + e] = o.status;
+    }
+    __syncthreads();  // order and bin_n serve the next window
   }
   // the rest below the wave threshold, sorted by size, through the scratch
   for (uint64_t q = n_big + t; q < n_mid; q += step) {

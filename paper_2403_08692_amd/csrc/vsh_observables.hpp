@@ -263,8 +263,8 @@ __device__ __forceinline__ ObsOut scratch_observables(const Scratch& w, uint64_t
 // picks; a merge adds jet b into jet a.
 // ---------------------------------------------------------------------------
 template <int M, bool kMassive>
-__device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, int np, double ecm, int status,
-                                                  const EventInputs& in) {
+__device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, int np, int wmax, double ecm,
+                                                  int status, const EventInputs& in) {
   ObsOut o;
 #pragma unroll
   for (int h = 0; h < 7; ++h) o.v[h] = 0.0;
@@ -272,6 +272,7 @@ __device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, 
 #pragma unroll
   for (int a = 0; a < M; ++a) {
     E[a] = X[a] = Y[a] = Z[a] = 0.0;
+    if (a >= wmax) continue;  // wmax: the wave's largest parton count (uniform)
     if (a < np) {
       const P4 p = r.load(a, e);
       E[a] = p.e;
@@ -348,11 +349,13 @@ __device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, 
         if (a == i) { xi = X[a]; yi = Y[a]; zi = Z[a]; }
 #pragma unroll
       for (int j = 1; j < M; ++j) {
+        if (j >= wmax) break;
         if (j > i && j < np) {
           const double nx = yi * Z[j] - zi * Y[j], ny = zi * X[j] - xi * Z[j], nz = xi * Y[j] - yi * X[j];
           double vx = 0.0, vy = 0.0, vz = 0.0;
 #pragma unroll
           for (int k = 0; k < M; ++k) {
+            if (k >= wmax) break;
             if (k != i && k != j && k < np) {
               const double d = X[k] * nx + Y[k] * ny + Z[k] * nz;
               if (d > 0.0) { vx += X[k]; vy += Y[k]; vz += Z[k]; }
@@ -425,6 +428,7 @@ __device__ __forceinline__ ObsOut reg_observables(const Records& r, uint64_t e, 
           if (q == a) { ea = E[q]; uxa = UX[q]; uya = UY[q]; uza = UZ[q]; }
 #pragma unroll
         for (int b = 1; b < M; ++b) {
+          if (b >= wmax) break;
           if (b > a && (alive >> b & 1u)) {
             const double dx = uxa - UX[b], dy = uya - UY[b], dz = uza - UZ[b];
             const double d2 = (dx * dx + dy * dy) + dz * dz;

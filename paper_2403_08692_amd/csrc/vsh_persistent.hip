@@ -176,17 +176,6 @@ extern __shared__ uint64_t flat_gmask[];
 
 __device__ __forceinline__ uint32_t mask_words(uint32_t cap) { return (cap + 63) / 64; }
 
-// Wave-wide scan and reduction through the device library's cross-lane
-// (DPP) sequences; every lane of the wave must call them.
-extern "C" __device__ uint64_t __ockl_wfscan_add_u64(uint64_t, bool);
-extern "C" __device__ uint32_t __ockl_wfred_max_u32(uint32_t);
-__device__ __forceinline__ uint64_t wave_inclusive_sum(uint64_t x) { return __ockl_wfscan_add_u64(x, true); }
-__device__ __forceinline__ uint32_t wave_max(uint32_t x) { return __ockl_wfred_max_u32(x); }
-__device__ __forceinline__ uint64_t lane63(uint64_t x) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
-  return ((uint64_t)hi << 32) | lo;
-}
 
 __device__ __forceinline__ uint32_t owner_of(const uint32_t* start, uint32_t j) {
   uint32_t lo = 0, hi = 64;  // last o with start[o] <= j (owners with no items have start[o] == start[o+1])
