@@ -203,7 +203,7 @@ __device__ __forceinline__ int end_draws(const TrialCtx& c, int i, int k, int pi
     trials += 6;
     double ugg = 0.0, um = 0.0;
     int fm = 0;
-#pragma unroll 1
+#pragma unroll  // the three Philox blocks interleave
     for (uint32_t g = 0; g < 3; ++g) {
       const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, g));
       const double u0 = unit(d.x, d.y), u1 = unit(d.z, d.w);
