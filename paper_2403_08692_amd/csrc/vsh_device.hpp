@@ -121,14 +121,9 @@ __device__ __forceinline__ uint32_t trial_slot(uint32_t i, uint32_t k, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// One-loop alpha_s, n_f = 5, alpha_s(M_Z^2) = 0.118, at the emission's kT^2.
+// One-loop alpha_s, n_f = 5, alpha_s(M_Z^2) = 0.118, at the emission's kT^2,
+// from lt = ln kT^2.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double alpha_s(double t) {
-  constexpr double b0 = (33.0 - 2.0 * kNf) / (12.0 * kPi);
-  return kAlphaSMZ / (1.0 + kAlphaSMZ * b0 * log(t / (kMZ * kMZ)));
-}
-
-// the same from ln t
 __device__ __forceinline__ double alpha_s_of_log(double lt) {
   constexpr double b0 = (33.0 - 2.0 * kNf) / (12.0 * kPi);
   constexpr double ln_mz2 = 9.025837845847876;  // ln(91.1876^2)
