@@ -88,8 +88,9 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     }
     const uint64_t a = (uint64_t)0xD2511F53u * c0;
     const uint64_t b = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+    // three-input XOR in one gfx950 VALU op (truth table 0x96)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), c3, k1, 0x96);
     c1 = (uint32_t)b;
     c3 = (uint32_t)a;
     c0 = n0;
