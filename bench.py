@@ -488,11 +488,17 @@ def main():
         ctx.autotune(1 << 18, seed=w.seed, ecm=w.ecm, t_cut=w.tcut, max_partons=w.cap, persistent=False)
         extra["tail_cut"] = tail_cut_study(ctx, P, torch, w, n, refill_ms)
         extra["weighted_veto"] = weighted_veto_study(ctx, P, torch, w, n)
-        # massive charm and bottom quarks (lane mapping's massive kernels), both forms
+        # massive charm and bottom quarks, both forms in the tuned (flattened) mapping, and the
+        # plain form with one lane per event
         extra["massive_lep"] = {"workload": w.name, "mass_c": 1.5, "mass_b": 4.8,
+                                "mapping": ctx.get_tuning()["plain_mapping"],
                                 "plain": time_form(ctx, P, torch, w, n, "plain", 5, mass_c=1.5, mass_b=4.8),
                                 "persistent": time_form(ctx, P, torch, w, n, "persistent", 5, mass_c=1.5,
                                                         mass_b=4.8)}
+        pm = ctx.get_tuning()["plain_mapping"]
+        ctx.set_tuning(plain_mapping=0)
+        extra["massive_lep"]["plain_lane"] = time_form(ctx, P, torch, w, n, "plain", 3, mass_c=1.5, mass_b=4.8)
+        ctx.set_tuning(plain_mapping=pm)
         # mixed energies and cutoffs, 10^7 events in one persistent launch (and the plain form)
         m = workloads.MIXED
         e_arr, t_arr = m.per_event()

@@ -168,6 +168,7 @@ struct FlatShared {
   uint32_t counts[64];  // the cycle's trials (low 16 bits) and active ends (high 16 bits) per owner
   uint32_t climit[64];  // each event's cycle limit
   double wsh[64];       // each event's shower weight (weighted veto)
+  double mc[64], mb[64];  // each event's charm and bottom masses (massive requests)
 };
 
 // per-owner gluon masks, then per-owner stale masks (partons whose cached end
@@ -332,6 +333,17 @@ __device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Re
   }
 }
 
+// Trials of parton i of an event with quark masses in column `slot`: the
+// massive ends compute their ranges themselves each cycle (no end cache);
+// only the item's best (i, k, K) is kept.
+__device__ __forceinline__ void parton_trials_mflat(const TrialCtx& c, const Records& r, uint64_t slot, int i,
+                                                    const QuarkMasses& qm, double& best, uint32_t& widx,
+                                                    uint32_t& trials, uint32_t& ends) {
+  MWinner W{Winner{0.0, 0.0, 0.0, 0.0, -1, 0, 0}, 0.0, 0.0, 0.0, 0.0, 1.0, false};
+  parton_trials_massive(c, r, slot, i, qm, best, W, trials, ends);
+  if (W.w.i >= 0) widx = pack_trial(W.w.i, W.w.k, W.w.K);
+}
+
 // (v, idx) beats (w, jdx): larger ln t, or equal and earlier in loop order
 __device__ __forceinline__ bool beats(double v, uint32_t idx, double w, uint32_t jdx) {
   return idx != kNoTrial && (jdx == kNoTrial || v > w || (v == w && idx < jdx));
@@ -350,11 +362,15 @@ constexpr uint32_t kEmitDiv = 4;
 // kCached: the kernel has an end cache (ec); the cycle then starts with
 // rounds that rebuild the entries of stale partons, so that every trial
 // round reads fresh entries only.  Without it, each item computes its
-// parton's coefficients itself.
-template <bool kCached>
+// parton's coefficients itself.  kMassive: the events carry quark masses
+// (qm, the calling lane's event's); no end cache, the owner recomputes its
+// winner's range from the records.
+template <bool kCached, bool kMassive = false>
 __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_t words, EvState& s, bool busy,
                                            bool& pend, Pending& pd, const Records& slots, uint64_t slot,
-                                           const EndCache& ec, uint64_t wave_col, uint32_t lane) {
+                                           const EndCache& ec, uint64_t wave_col, uint32_t lane,
+                                           const QuarkMasses& qm = QuarkMasses{0.0, 0.0, 0.0, 0.0, 0.0}) {
+  static_assert(!(kCached && kMassive), "massive events take no end cache");
   const bool trial = busy && !pend;
   uint64_t* mym = gm + (uint64_t)lane * words;
   uint64_t* sm = gm + (uint64_t)64 * words;  // stale masks
@@ -420,6 +436,10 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   sh.best_v[lane] = -INFINITY;
   sh.best_idx[lane] = kNoTrial;
   sh.counts[lane] = 0;
+  if (kMassive) {
+    sh.mc[lane] = qm.c;
+    sh.mb[lane] = qm.b;
+  }
   __syncthreads();
   // --- rebuild the cache entries of the stale partons, 64 per round
   if (kCached && n_s > 0) {
@@ -475,7 +495,11 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       double best = c.ltc;
       uint32_t widx = kNoTrial;
       uint32_t nt = 0, ne = 0;
-      parton_trials_cached(c, slots, sh.slot[o], (int)i, ec, wave_col + o, !kCached, best, widx, nt, ne);
+      if constexpr (kMassive)
+        parton_trials_mflat(c, slots, sh.slot[o], (int)i, QuarkMasses{0.0, 0.0, 0.0, sh.mc[o], sh.mb[o]}, best,
+                            widx, nt, ne);
+      else
+        parton_trials_cached(c, slots, sh.slot[o], (int)i, ec, wave_col + o, !kCached, best, widx, nt, ne);
       if (widx != kNoTrial) {
         v = best;
         idx = widx;
@@ -503,7 +527,18 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     __syncthreads();
   }
   // --- each owner that made trials decides its cycle
-  if (trial) {
+  if (trial && kMassive) {
+    s.trials += sh.counts[lane] & 0xFFFFu;
+    s.ends += sh.counts[lane] >> 16;
+    const uint32_t bi = sh.best_idx[lane];
+    MWinner W{Winner{0.0, 0.0, 0.0, 0.0, -1, 0, 0}, 0.0, 0.0, 0.0, 0.0, 1.0, false};
+    double best = s.ltc;
+    if (bi != kNoTrial) {
+      best = sh.best_v[lane];
+      W = massive_winner(trial_ctx(s), slots, slot, (int)(bi >> 14), (int)((bi >> 4) & 1023u), (int)(bi & 15u), qm);
+    }
+    pend = veto_decide_massive(s, best, W, acc, pd, sh.wsh[lane]);
+  } else if (trial) {
     s.trials += sh.counts[lane] & 0xFFFFu;
     s.ends += sh.counts[lane] >> 16;
     const uint32_t bi = sh.best_idx[lane];
@@ -536,7 +571,8 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   const uint32_t n_busy = __popcll(__ballot(busy));
   if (n_pend > 0 && kEmitDiv * n_pend >= n_busy && pend) {
     const int j = s.n;
-    emit(s, slots, slot, pd);
+    if constexpr (kMassive) emit_massive(s, slots, slot, pd, qm);
+    else emit(s, slots, slot, pd);
     if (pd.K <= 10) mym[j >> 6] |= 1ull << (j & 63);               // gluon emitted
     else mym[pd.i >> 6] &= ~(1ull << (pd.i & 63));                 // g -> f fbar: i is now a quark
     // ends whose momenta or partners changed: those of i, j, k and of the
@@ -557,6 +593,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
 // Plain one-launch form with the flattened mapping: wave w owns events
 // 64w .. 64w+63 of the batch (already started by k_me) from start to cutoff,
 // with no refill; finished lanes only stop contributing trial work.
+template <bool kMassive>
 __global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n,
                                                              EndCache ec) {
   __shared__ FlatShared sh;
@@ -576,7 +613,7 @@ __global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary 
     mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
   while (__any(busy)) {
-    flat_cycle<true>(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane);
+    flat_cycle<!kMassive, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane, in.qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
       write_state(s, sm, e);
@@ -593,11 +630,15 @@ void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInp
                               uint64_t* cache, hipStream_t st) {
   if (!n) return;
   const EndCache ec{cache, r.cap};
-  hipLaunchKernelGGL(k_shower_plain_flat, dim3((n + 63) / 64), dim3(64), flat_lds_bytes(r.cap), st, r, s, in, n,
-                     ec);
+  if (in.massive)
+    hipLaunchKernelGGL(k_shower_plain_flat<true>, dim3((n + 63) / 64), dim3(64), flat_lds_bytes(r.cap), st, r, s,
+                       in, n, ec);
+  else
+    hipLaunchKernelGGL(k_shower_plain_flat<false>, dim3((n + 63) / 64), dim3(64), flat_lds_bytes(r.cap), st, r, s,
+                       in, n, ec);
 }
 
-template <bool kInPlace>
+template <bool kInPlace, bool kMassive>
 __global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
@@ -624,7 +665,8 @@ __global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
       busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle<kInPlace>(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane);
+    flat_cycle<kInPlace && !kMassive, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache,
+                                                L - lane, lane, A.reqs[req].qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
@@ -742,11 +784,15 @@ BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap) {
   return L;
 }
 
-// Requests with quark masses run the lane mapping's massive kernel.
+// The kernel of a mapping, in place or not, for requests with or without
+// quark masses.
 const void* persistent_kernel(uint32_t mapping, bool in_place, bool massive) {
+  if (mapping == kMapFlat) {
+    if (massive) return in_place ? (const void*)k_shower_flat<true, true> : (const void*)k_shower_flat<false, true>;
+    return in_place ? (const void*)k_shower_flat<true, false> : (const void*)k_shower_flat<false, false>;
+  }
   if (massive)
     return in_place ? (const void*)k_shower_persistent<true, true> : (const void*)k_shower_persistent<false, true>;
-  if (mapping == kMapFlat) return in_place ? (const void*)k_shower_flat<true> : (const void*)k_shower_flat<false>;
   return in_place ? (const void*)k_shower_persistent<true> : (const void*)k_shower_persistent<false>;
 }
 
@@ -756,17 +802,9 @@ void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uin
                        bool massive, hipStream_t st) {
   block = persistent_block(mapping, block);
   const dim3 grid((uint32_t)(lanes / block));
-  if (massive) {
-    if (in_place) hipLaunchKernelGGL((k_shower_persistent<true, true>), grid, dim3(block), 0, st, A);
-    else hipLaunchKernelGGL((k_shower_persistent<false, true>), grid, dim3(block), 0, st, A);
-  } else if (mapping == kMapFlat) {
-    const size_t lds = flat_lds_bytes(A.slots.cap);
-    if (in_place) hipLaunchKernelGGL(k_shower_flat<true>, grid, dim3(block), lds, st, A);
-    else hipLaunchKernelGGL(k_shower_flat<false>, grid, dim3(block), lds, st, A);
-  } else {
-    if (in_place) hipLaunchKernelGGL(k_shower_persistent<true>, grid, dim3(block), 0, st, A);
-    else hipLaunchKernelGGL(k_shower_persistent<false>, grid, dim3(block), 0, st, A);
-  }
+  const size_t lds = mapping == kMapFlat ? flat_lds_bytes(A.slots.cap) : 0;
+  void* args[] = {const_cast<PersistArgs*>(&A)};
+  (void)hipLaunchKernel(persistent_kernel(mapping, in_place, massive), grid, dim3(block), args, lds, st);
 }
 
 void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, unsigned long long* counter,
@@ -836,7 +874,7 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   void* a_pers[] = {&g.args};
   const bool massive = g.in.massive != 0;
   GCHK(add_kernel(persistent_kernel(g.mapping, true, massive), dim3((uint32_t)(lanes / block)), dim3(block),
-                  a_pers, g.mapping == kMapFlat && !massive ? (unsigned)flat_lds_bytes(A.slots.cap) : 0u));
+                  a_pers, g.mapping == kMapFlat ? (unsigned)flat_lds_bytes(A.slots.cap) : 0u));
   GCHK(add_event(2));
   g.nb = L.buf.out.cap + 1;
   g.cap = L.buf.out.cap;

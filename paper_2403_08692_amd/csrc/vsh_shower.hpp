@@ -442,6 +442,91 @@ __device__ __forceinline__ void product_masses(int K, const QuarkMasses& qm, dou
   }
 }
 
+// Range and trial coefficient of one kernel class of an end, as the trials
+// and the decision both take them: z limits, L = ln((1 - zm)/(1 - zp)), the
+// coefficient c and the overestimate factor fo = max(F, 1); `massive` for a
+// kernel that takes the massive formulas.
+struct MRange {
+  double zm, zp, L, c, fo;
+  bool massive;
+};
+
+// A quark end (q -> q g) with splitter mass mi and spectator mass mk.  False
+// without phase space above the cutoff.
+__device__ __forceinline__ bool mrange_quark(const TrialCtx& c, double q2, double Q2, double mi, double mk,
+                                             MRange& R) {
+  R.massive = mi > 0.0 || mk > 0.0;
+  R.fo = 1.0;
+  if (!R.massive) {
+    if (!(q2 > 4.0 * c.tcut)) return false;
+    R.zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * c.tcut / q2));
+    R.zm = 1.0 - R.zp;
+  } else {
+    if (!massive_limits(Q2, mi, 0.0, mk, c.tcut, R.zm, R.zp)) return false;
+    const double f = massive_flux(Q2, mi, 0.0, mk, mi);
+    R.fo = f > 1.0 ? f : 1.0;
+  }
+  R.L = log_fast((1.0 - R.zm) / (1.0 - R.zp));
+  R.c = c.cfac * ((2.0 * kCF) * R.L);
+  if (R.massive) R.c *= R.fo;
+  return true;
+}
+
+// g -> g g and the light g -> q qbar of a gluon end share one z range (only
+// the spectator's mass enters): R.c is g -> g g's coefficient, cqq the
+// common one of the light flavours.  Zero range and coefficients without
+// phase space above the cutoff.
+__device__ __forceinline__ bool mrange_light(const TrialCtx& c, double q2, double Q2, double mk, MRange& R,
+                                             double& cqq) {
+  R.massive = mk > 0.0;
+  R.zm = R.zp = R.L = R.c = cqq = 0.0;
+  R.fo = 1.0;
+  const bool ok = R.massive ? massive_limits(Q2, 0.0, 0.0, mk, c.tcut, R.zm, R.zp) : q2 > 4.0 * c.tcut;
+  if (!ok) return false;
+  if (!R.massive) {
+    R.zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * c.tcut / q2));
+    R.zm = 1.0 - R.zp;
+  } else {
+    const double f = massive_flux(Q2, 0.0, 0.0, mk, 0.0);  // 1 up to rounding
+    R.fo = f > 1.0 ? f : 1.0;
+  }
+  R.L = log_fast((1.0 - R.zm) / (1.0 - R.zp));
+  R.c = c.cfac * (kCA * R.L);
+  cqq = c.cfac * ((0.5 * kTR) * (R.zp - R.zm));
+  if (R.massive) {
+    R.c *= R.fo;
+    cqq *= R.fo;
+  }
+  return true;
+}
+
+// g -> Q Qbar of a flavour with mass m: its own range when massive, else the
+// light flavours' (G, cqq, light_ok from mrange_light).
+__device__ __forceinline__ bool mrange_heavy(const TrialCtx& c, double Q2, double m, double mk, bool light_ok,
+                                             const MRange& G, double cqq, MRange& R) {
+  R = MRange{G.zm, G.zp, G.L, cqq, G.fo, m > 0.0 || mk > 0.0};
+  if (m > 0.0) {
+    if (!massive_limits(Q2, m, m, mk, c.tcut, R.zm, R.zp)) return false;
+    const double fl = massive_flux(Q2, m, m, mk, 0.0);
+    R.fo = fl > 1.0 ? fl : 1.0;
+    R.L = log_fast((1.0 - R.zm) / (1.0 - R.zp));
+    R.c = c.cfac * ((0.5 * kTR) * (R.zp - R.zm)) * R.fo;
+    return true;
+  }
+  return light_ok;
+}
+
+// The winner record of kernel K of the end (i, k) with range R; cgg and cqq
+// are the end's g -> g g and light g -> q qbar coefficients (a massless
+// kernel's decision recovers its range from them, as the massless forms do).
+__device__ __forceinline__ MWinner mwinner_of(const TrialCtx& c, int i, int k, int K, const MRange& R, double cgg,
+                                              double cqq, double Q2, double mi, double mj, double mk) {
+  Winner wn{0.0, R.zm, R.zp, R.L, i, k, K};
+  if (!R.massive) end_from_coeffs(c.cfac, c.tcut, K < 10 ? K : 10, cgg, cqq, wn);
+  wn.K = K;
+  return MWinner{wn, Q2, mi, mj, mk, R.fo, R.massive};
+}
+
 // Every kernel of the end (i, k) in kernel order, strict maximum of ln t.
 // Kernels share what their masses let them share: g -> g g and the three
 // light g -> q qbar have the same z range (only the spectator's mass enters),
@@ -458,34 +543,15 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
   bool active = false;
   if (pid_i != kGluon) {
     const int K = pid_i > 0 ? pid_i - 1 : 4 - pid_i;
-    const double mi = msp;
-    const bool massive = mi > 0.0 || mk > 0.0;
-    double zm, zp, fo = 1.0;
-    if (!massive) {
-      active = q2 > 4.0 * c.tcut;
-      if (active) {
-        zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * c.tcut / q2));
-        zm = 1.0 - zp;
-      }
-    } else {
-      active = massive_limits(Q2, mi, 0.0, mk, c.tcut, zm, zp);
-      if (active) {
-        const double f = massive_flux(Q2, mi, 0.0, mk, mi);
-        fo = f > 1.0 ? f : 1.0;
-      }
-    }
-    if (active) {
-      const double L = log_fast((1.0 - zm) / (1.0 - zp));
-      double cc = c.cfac * ((2.0 * kCF) * L);
-      if (massive) cc *= fo;
+    MRange R;
+    if (mrange_quark(c, q2, Q2, msp, mk, R)) {
+      active = true;
       const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
-      const double lt_try = c.lt + log_fast(unit(d.x, d.y)) / cc;
+      const double lt_try = c.lt + log_fast(unit(d.x, d.y)) / R.c;
       trials += 1;
       if (lt_try > best) {
         best = lt_try;
-        Winner wn{0.0, zm, zp, L, i, k, K};
-        if (!massive) end_from_coeffs(c.cfac, c.tcut, K, cc, c.cfac * ((0.5 * kTR) * (zp - zm)), wn);
-        W = MWinner{wn, Q2, mi, 0.0, mk, fo, massive};
+        W = mwinner_of(c, i, k, K, R, R.c, c.cfac * ((0.5 * kTR) * (R.zp - R.zm)), Q2, msp, 0.0, mk);
       }
     }
   } else {
@@ -493,33 +559,16 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
     const U4 d0 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
     const U4 d1 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 1));
     const U4 d2 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 2));
-    const bool light_massive = mk > 0.0;  // g g and light q qbar: only the spectator's mass
-    double zm = 0.0, zp = 0.0, L = 0.0, cgg = 0.0, cqq = 0.0, foa = 1.0;
-    bool ok = light_massive ? massive_limits(Q2, 0.0, 0.0, mk, c.tcut, zm, zp) : q2 > 4.0 * c.tcut;
+    MRange G;
+    double cqq;
+    const bool ok = mrange_light(c, q2, Q2, mk, G, cqq);
     if (ok) {
-      if (!light_massive) {
-        zp = 0.5 * (1.0 + sqrt(1.0 - 4.0 * c.tcut / q2));
-        zm = 1.0 - zp;
-      } else {
-        const double f = massive_flux(Q2, 0.0, 0.0, mk, 0.0);  // 1 up to rounding
-        foa = f > 1.0 ? f : 1.0;
-      }
       active = true;
-      L = log_fast((1.0 - zm) / (1.0 - zp));
-      cgg = c.cfac * (kCA * L);
-      cqq = c.cfac * ((0.5 * kTR) * (zp - zm));
-      if (light_massive) {
-        cgg *= foa;
-        cqq *= foa;
-      }
       trials += 4;
-      const double lgg = c.lt + log_fast(unit(d0.x, d0.y)) / cgg;
-      // a winner among these kernels: the range as the massless forms take it
-      Winner wn{0.0, zm, zp, L, i, k, 10};
-      if (!light_massive) end_from_coeffs(c.cfac, c.tcut, 10, cgg, cqq, wn);
+      const double lgg = c.lt + log_fast(unit(d0.x, d0.y)) / G.c;
       if (lgg > best) {
         best = lgg;
-        W = MWinner{wn, Q2, 0.0, 0.0, mk, foa, light_massive};
+        W = mwinner_of(c, i, k, 10, G, G.c, cqq, Q2, 0.0, 0.0, mk);
       }
       double um = unit(d0.z, d0.w);
       int fm = 1;
@@ -535,37 +584,49 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
       const double lqq = c.lt + log_fast(um) / cqq;
       if (lqq > best) {
         best = lqq;
-        wn.K = 10 + fm;
-        W = MWinner{wn, Q2, 0.0, 0.0, mk, foa, light_massive};
+        W = mwinner_of(c, i, k, 10 + fm, G, G.c, cqq, Q2, 0.0, 0.0, mk);
       }
     }
 #pragma unroll 1
     for (int f = 4; f <= 5; ++f) {  // c cbar, b bbar
       const double m = quark_mass(qm, f);
-      const bool massive = m > 0.0 || mk > 0.0;
-      double zmf = zm, zpf = zp, Lf = L, cf = cqq, fo = foa;
-      if (m > 0.0) {
-        if (!massive_limits(Q2, m, m, mk, c.tcut, zmf, zpf)) continue;
-        const double fl = massive_flux(Q2, m, m, mk, 0.0);
-        fo = fl > 1.0 ? fl : 1.0;
-        Lf = log_fast((1.0 - zmf) / (1.0 - zpf));
-        cf = c.cfac * ((0.5 * kTR) * (zpf - zmf)) * fo;
-      } else if (!ok) {
-        continue;  // a massless flavour shares the light flavours' range
-      }
+      MRange H;
+      if (!mrange_heavy(c, Q2, m, mk, ok, G, cqq, H)) continue;
       active = true;
       trials += 1;
       const double u = f == 4 ? unit(d2.x, d2.y) : unit(d2.z, d2.w);
-      const double lt_try = c.lt + log_fast(u) / cf;
+      const double lt_try = c.lt + log_fast(u) / H.c;
       if (lt_try > best) {
         best = lt_try;
-        Winner wn{0.0, zmf, zpf, Lf, i, k, 10 + f};
-        if (!massive) end_from_coeffs(c.cfac, c.tcut, 10 + f, cgg, cqq, wn);
-        W = MWinner{wn, Q2, m, m, mk, fo, massive};
+        W = mwinner_of(c, i, k, 10 + f, H, G.c, cqq, Q2, m, m, mk);
       }
     }
   }
   if (active) ends += 1;
+}
+
+// The winner record of kernel K of the end (i, k) of the event in column e,
+// recomputed from the records with the arithmetic of the trials above (the
+// flattened forms, which keep only the winner's (i, k, K)).
+__device__ __forceinline__ MWinner massive_winner(const TrialCtx& c, const Records& r, uint64_t e, int i, int k,
+                                                  int K, const QuarkMasses& qm) {
+  const int pid_i = r.pid[(uint64_t)i * r.stride + e], pid_k = r.pid[(uint64_t)k * r.stride + e];
+  const P4 pi = r.load(i, e), pk = r.load(k, e);
+  const double q2 = 2.0 * mdot(pi, pk);
+  const double msp = quark_mass(qm, pid_i), mk = quark_mass(qm, pid_k);
+  const double Q2 = q2 + msp * msp + mk * mk;
+  MRange R;
+  if (K < 10) {
+    mrange_quark(c, q2, Q2, msp, mk, R);
+    return mwinner_of(c, i, k, K, R, R.c, c.cfac * ((0.5 * kTR) * (R.zp - R.zm)), Q2, msp, 0.0, mk);
+  }
+  MRange G;
+  double cqq;
+  const bool ok = mrange_light(c, q2, Q2, mk, G, cqq);
+  if (K <= 13) return mwinner_of(c, i, k, K, G, G.c, cqq, Q2, 0.0, 0.0, mk);
+  const double m = quark_mass(qm, K - 10);
+  mrange_heavy(c, Q2, m, mk, ok, G, cqq, R);
+  return mwinner_of(c, i, k, K, R, G.c, cqq, Q2, m, m, mk);
 }
 
 __device__ __forceinline__ void parton_trials_massive(const TrialCtx& c, const Records& r, uint64_t e, int i,

@@ -21,12 +21,21 @@ def ctx():
     c.close()
 
 
+@pytest.mark.parametrize("mapping", [1, 0])
 @pytest.mark.parametrize("persistent", [False, True])
 @pytest.mark.parametrize("ecm,tcut,cap,n", [(91.2, 1.0, 64, 2000), (12.0, 0.5, 64, 1500), (500.0, 0.25, 256, 400)])
-def test_massive_parity(ctx, oracle, persistent, ecm, tcut, cap, n):
-    print(f"case massive ecm={ecm} tcut={tcut} cap={cap} n={n} persistent={persistent}", flush=True)
-    g = ctx.generate(n, seed=21, ecm=ecm, t_cut=tcut, max_partons=cap, summary=True, records=True,
-                     persistent=persistent, mass_c=MC, mass_b=MB)
+def test_massive_parity(ctx, oracle, mapping, persistent, ecm, tcut, cap, n):
+    # mapping 1: the trials of a wave's events spread over its lanes; 0: one lane per event
+    key = "mapping" if persistent else "plain_mapping"
+    before = ctx.get_tuning()[key]
+    ctx.set_tuning(**{key: mapping})
+    try:
+        print(f"case massive ecm={ecm} tcut={tcut} cap={cap} n={n} persistent={persistent} mapping={mapping}",
+              flush=True)
+        g = ctx.generate(n, seed=21, ecm=ecm, t_cut=tcut, max_partons=cap, summary=True, records=True,
+                         persistent=persistent, mass_c=MC, mass_b=MB)
+    finally:
+        ctx.set_tuning(**{key: before})
     o = oracle.generate(21, 0, n, ecm, tcut, cap, records=True, mass=TABLE)
     rep, same = parity.compare(g, o, ecm, n)
     print(rep, flush=True)
@@ -42,17 +51,26 @@ def test_massive_parity(ctx, oracle, persistent, ecm, tcut, cap, n):
         np.testing.assert_allclose(m2, want, atol=1e-9 * ecm * ecm)
 
 
-def test_massive_and_massless_requests_served_together(ctx):
-    heavy = dict(seed=31, ecm=91.2, t_cut=1.0, max_partons=64, mass_c=MC, mass_b=MB)
-    light = dict(seed=32, ecm=91.2, t_cut=1.0, max_partons=64)
-    ref_h = ctx.generate(3000, summary=True, **heavy)
-    ref_l = ctx.generate(3000, summary=True, **light)
-    th, tl = ctx.submit(3000, summary=True, **heavy), ctx.submit(3000, summary=True, **light)
-    for t, ref in ((th, ref_h), (tl, ref_l)):
-        got = ctx.wait(t)
-        np.testing.assert_array_equal(got["sum_i"], ref["sum_i"])
-        np.testing.assert_array_equal(got["hash"], ref["hash"])
-        np.testing.assert_allclose(got["sum_d"], ref["sum_d"], rtol=1e-12, atol=1e-15)
+@pytest.mark.parametrize("mapping", [1, 0])
+def test_massive_and_massless_requests_served_together(ctx, mapping):
+    # an epoch with a massive request runs the massive kernel for every event
+    # of it; massless events must come out as they do alone
+    before = ctx.get_tuning()
+    ctx.set_tuning(plain_mapping=mapping, mapping=mapping)
+    try:
+        print(f"case served together mapping={mapping}", flush=True)
+        heavy = dict(seed=31, ecm=91.2, t_cut=1.0, max_partons=64, mass_c=MC, mass_b=MB)
+        light = dict(seed=32, ecm=91.2, t_cut=1.0, max_partons=64)
+        ref_h = ctx.generate(3000, summary=True, **heavy)
+        ref_l = ctx.generate(3000, summary=True, **light)
+        th, tl = ctx.submit(3000, summary=True, **heavy), ctx.submit(3000, summary=True, **light)
+        for t, ref in ((th, ref_h), (tl, ref_l)):
+            got = ctx.wait(t)
+            np.testing.assert_array_equal(got["sum_i"], ref["sum_i"])
+            np.testing.assert_array_equal(got["hash"], ref["hash"])
+            np.testing.assert_allclose(got["sum_d"], ref["sum_d"], rtol=1e-12, atol=1e-15)
+    finally:
+        ctx.set_tuning(plain_mapping=before["plain_mapping"], mapping=before["mapping"])
 
 
 def test_invalid_masses_rejected(ctx):
