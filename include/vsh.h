@@ -150,8 +150,8 @@ typedef struct {
                             flavours open at sqrt(s); kernels with a massive parton
                             take the massive dipole phase space, the quasi-collinear
                             mass terms and the massive recoil map; events validate on
-                            their mass shells.  Such requests run the lane mapping's
-                            massive kernels.  0 <= mass, finite                      */
+                            their mass shells.  Such requests run the massive kernels
+                            of the tuned mapping.  0 <= mass, finite                  */
 } vsh_request;
 
 /* Result of one request.  Library-owned host memory; release with
