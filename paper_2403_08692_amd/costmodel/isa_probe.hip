@@ -58,5 +58,5 @@ extern "C" __global__ void probe_unit(const uint32_t* __restrict__ a, double* __
 }
 
 extern "C" __global__ void probe_unit_base(const uint32_t* __restrict__ a, double* __restrict__ o) {
-  o[threadIdx.x] = (double)(a[threadIdx.x] ^ a[threadIdx.x + 64]);
+  o[threadIdx.x] = __hiloint2double((int)a[threadIdx.x], (int)a[threadIdx.x + 64]);  // the words' bits, stored
 }

@@ -110,10 +110,12 @@ __device__ __forceinline__ Keyed make_keyed(uint64_t seed, uint64_t event) {
   return Keyed{(uint32_t)event, (uint32_t)(event >> 32), (uint32_t)seed, (uint32_t)(seed >> 32)};
 }
 
-// 52 random bits -> (2m+1) 2^-53, exact and strictly inside (0,1)
+// 52 random bits m -> (2m+1) 2^-53, exact and strictly inside (0,1): the
+// bits give 1 + m 2^-52 in [1, 2), and subtracting 1 - 2^-53 is exact
+// (Sterbenz) and leaves m 2^-52 + 2^-53
 __device__ __forceinline__ double unit(uint32_t hi, uint32_t lo) {
-  const uint64_t m = ((uint64_t)(hi >> 12) << 32) | lo;
-  return (double)(2 * m + 1) * 0x1p-53;
+  const double one_m = __hiloint2double((int)(0x3FF00000u | (hi >> 12)), (int)lo);
+  return one_m - 0x1.fffffffffffffp-1;
 }
 
 // trial slot: splitter i, spectator k (both < 1024), block g of the kernel list
