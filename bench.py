@@ -36,7 +36,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.32 T lane-operations/s
 # VALU issue-slot costs per lane of the arithmetic building blocks, from the
 # gfx950 assembly of this library's own build (costmodel/isa_costs.py; a CPU
 # test keeps this table equal to what the probe measures).
-COST = {"philox": 99, "unit": 3, "log": 97, "log_fast": 54, "exp": 41, "sqrt": 21, "div": 11, "sincos": 162}
+COST = {"philox": 99, "unit": 3, "log": 97, "log_fast": 38, "exp": 41, "sqrt": 21, "div": 11, "sincos": 162}
 
 
 def algorithmic_ops(n_events, ends, trials, cycles, emissions):
