@@ -352,12 +352,13 @@ __device__ __forceinline__ bool beats(double v, uint32_t idx, double w, uint32_t
 // One veto cycle of every busy event of this wave whose last accepted
 // emission has been built, the trials spread over the lanes; each owner lane
 // then decides its own event's cycle.  An accepted emission stays pending
-// (the event makes no trials meanwhile) until at least a quarter of the busy
-// events have one, or all of them do; then the wave builds them together.
+// (the event makes no trials meanwhile) until at least half of the busy
+// events have one; then the wave builds them together (a quarter, three
+// quarters and all of them measured slower on LEP, mixed and stress events).
 // Deferring an emission changes nothing in the event: its random numbers are
 // keyed by the event's own cycle.  The event of the calling lane sits in
 // column `slot` of `slots`; its gluon mask at gm + lane * words.
-constexpr uint32_t kEmitDiv = 4;
+constexpr uint32_t kEmitDiv = 2;
 
 // kCached: the kernel has an end cache (ec); the cycle then starts with
 // rounds that rebuild the entries of stale partons, so that every trial
