@@ -73,6 +73,27 @@ def test_overflow_small_cap(ctx, oracle):
     assert g["n_done"] + g["n_overflow"] == 800
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_limits_and_degenerate_requests(ctx, oracle, persistent):
+    import paper_2403_08692_amd as P
+
+    # empty requests and record capacities outside 2..1024 are refused before any launch
+    for n, cap in ((0, 64), (10, 1), (10, 1025)):
+        print(f"case refused n={n} cap={cap} persistent={persistent}", flush=True)
+        with pytest.raises(P.VshError) as ei:
+            ctx.generate(n, seed=1, max_partons=cap, persistent=persistent)
+        assert ei.value.code == -1
+    # no phase space above the cutoff (4 t_C > s): every event ends on its
+    # first cycle with its two partons, thrust exactly 1
+    g, o, rep = _run(ctx, oracle, 300, 4, 10.0, 30.0, 64, persistent=persistent)
+    parity.assert_parity(rep)
+    assert rep["frac"] == 1.0 and (g["sum_i"][0] == 2).all() and (g["sum_i"][2] == 1).all()
+    assert (g["sum_d"][4] <= 1e-15).all()  # tau = 1 - T
+    # the largest record capacity, on a ragged batch
+    g, o, rep = _run(ctx, oracle, 70, 8, 500.0, 0.25, 1024, persistent=persistent)
+    parity.assert_parity(rep)
+
+
 @pytest.mark.parametrize("form,mapping", [("plain", 1), ("plain", 0), ("persistent", 1), ("persistent", 0)])
 def test_tail_cut(ctx, oracle, form, mapping):
     # events still above the cutoff after 30 veto cycles are vetoed (status 5,
