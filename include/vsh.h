@@ -271,12 +271,23 @@ vsh_status vsh_autotune(vsh_ctx *ctx, const vsh_request *sample, vsh_tuning *cho
    vsh_poll: *done = 1 once finished.  vsh_wait blocks until finished and
    hands over the result (once; the ticket is then forgotten).
    vsh_cancel: stops admitting the request's events; vsh_wait then returns
-   VSH_E_CANCELLED.  Errors: VSH_E_NOTFOUND for unknown tickets, and those of
-   vsh_generate at submission. */
+   VSH_E_CANCELLED.  A HIP error while a request is admitted, showered or
+   measured fails that request alone: it finishes (vsh_poll reports it done),
+   and vsh_wait returns VSH_E_DEVICE (VSH_E_NOMEM when the observables'
+   scratch cannot be allocated) with the HIP error in vsh_last_error.
+   Errors: VSH_E_NOTFOUND for unknown tickets, and those of vsh_generate at
+   submission. */
 vsh_status vsh_submit(vsh_ctx *ctx, const vsh_request *req, uint64_t *ticket);
 vsh_status vsh_poll(vsh_ctx *ctx, uint64_t ticket, int *done);
 vsh_status vsh_wait(vsh_ctx *ctx, uint64_t ticket, vsh_result **out);
 vsh_status vsh_cancel(vsh_ctx *ctx, uint64_t ticket);
+
+/* Testing hook for the serving error path (for test suites, not part of the
+   method): the next `count` serving launches of ctx report a HIP launch
+   failure to the loop instead of launching, so the requests they hold fail
+   as described above while the device stays healthy.  Starts the serving
+   loop if needed. */
+vsh_status vsh_test_fail_epochs(vsh_ctx *ctx, uint32_t count);
 
 #ifdef __cplusplus
 }

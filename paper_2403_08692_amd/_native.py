@@ -112,6 +112,8 @@ def load():
     L.vsh_wait.restype = C.c_int
     L.vsh_cancel.argtypes = [P, C.c_uint64]
     L.vsh_cancel.restype = C.c_int
+    L.vsh_test_fail_epochs.argtypes = [P, C.c_uint32]
+    L.vsh_test_fail_epochs.restype = C.c_int
     L.vsh_timing_start.argtypes = [P]
     L.vsh_timing_start.restype = C.c_int
     L.vsh_timing_read.argtypes = [P, C.POINTER(C.c_float), C.c_uint32, C.POINTER(C.c_uint32)]
@@ -129,7 +131,7 @@ def load():
 EXPORTS = ["vsh_create", "vsh_destroy", "vsh_last_error", "vsh_generate", "vsh_result_free",
            "vsh_shower_records", "vsh_generate_into", "vsh_workspace_size", "vsh_submit", "vsh_poll",
            "vsh_wait", "vsh_cancel", "vsh_timing_start", "vsh_timing_read", "vsh_get_tuning", "vsh_set_tuning",
-           "vsh_autotune"]
+           "vsh_autotune", "vsh_test_fail_epochs"]
 
 
 class VshError(RuntimeError):
@@ -331,3 +333,7 @@ class Context:
 
     def cancel(self, ticket):
         _check(load().vsh_cancel(self._ptr, ticket), self._ptr)
+
+    def test_fail_epochs(self, count):
+        """Testing hook: the next `count` serving launches report a HIP launch failure."""
+        _check(load().vsh_test_fail_epochs(self._ptr, int(count)), self._ptr)

@@ -27,6 +27,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -93,7 +94,7 @@ struct Pool {
   }
 };
 
-enum ReqState { kQueued, kAdmitted, kDraining, kFinished, kCancelledState };
+enum ReqState { kQueued, kAdmitted, kDraining, kFinished, kCancelledState, kFailed };
 
 struct ServeReq {
   uint64_t ticket = 0;
@@ -111,6 +112,8 @@ struct ServeReq {
   std::vector<int32_t> si;
   std::vector<uint64_t> hs;
   ResultBox* box = nullptr;
+  vsh_status fail_code = VSH_OK;  // set when the request failed (state kFailed once nothing is in flight)
+  std::string fail_msg;
 };
 
 constexpr uint32_t kMaxEpochReqs = 512;
@@ -140,6 +143,7 @@ struct ServeState {
   hipStream_t drain = nullptr;
   char* scratch = nullptr;
   uint64_t scratch_bytes = 0;
+  uint32_t fail_epochs = 0;  // testing: epochs still to report a device error without launching
 };
 
 static uint64_t request_bytes(const vsh_request& r) { return request_out_bytes(r.n_events, r.max_partons, false); }
@@ -156,6 +160,19 @@ static void finish_request(ServeState& S, ServeReq& r, int state) {
   r.state = state;
   S.active.erase(std::remove(S.active.begin(), S.active.end(), r.ticket), S.active.end());
   S.done_cv.notify_all();
+}
+
+// Mark a request failed: no further events of it are scheduled, and it
+// finishes (state kFailed) as soon as none of its events is in flight.
+static void fail_request(ServeState& S, ServeReq& r, vsh_status code, const char* what, hipError_t err) {
+  if (r.fail_code == VSH_OK) {
+    r.fail_code = code;
+    r.fail_msg = what;
+    if (err != hipSuccess) r.fail_msg += std::string(": ") + hipGetErrorString(err);
+  }
+  r.cancel = true;
+  if (r.inflight == 0 && r.state != kFinished && r.state != kCancelledState && r.state != kFailed)
+    finish_request(S, r, kFailed);
 }
 
 static bool admit(vsh_ctx* ctx, ServeState& S) {
@@ -177,8 +194,10 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     Carver c(S.pool.base + off);
     r.buf = carve_request(c, r.req.n_events, r.req.max_partons, false);
     const uint64_t n = r.req.n_events;
-    if (!r.ecm.empty()) (void)hipMemcpyAsync(r.buf.ecm, r.ecm.data(), n * 8, hipMemcpyHostToDevice, S.drain);
-    if (!r.tcut.empty()) (void)hipMemcpyAsync(r.buf.tcut, r.tcut.data(), n * 8, hipMemcpyHostToDevice, S.drain);
+    hipError_t err = hipSuccess;
+    if (!r.ecm.empty()) err = hipMemcpyAsync(r.buf.ecm, r.ecm.data(), n * 8, hipMemcpyHostToDevice, S.drain);
+    if (err == hipSuccess && !r.tcut.empty())
+      err = hipMemcpyAsync(r.buf.tcut, r.tcut.data(), n * 8, hipMemcpyHostToDevice, S.drain);
     launch_zero(r.buf.hist, kHistDoubles, S.drain);
     EventInputs in{};
     in.ecm = r.ecm.empty() ? nullptr : r.buf.ecm;
@@ -192,9 +211,14 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     in.qm = request_masses(r.req);
     in.massive = request_massive(r.req);
     launch_me(r.buf.out, r.buf.sum, in, (uint32_t)n, S.drain);  // LO partons of every event
-    (void)hipStreamSynchronize(S.drain);  // inputs and LO events on the device before any epoch reads them
+    const hipError_t lerr = hipGetLastError();
+    if (err == hipSuccess) err = lerr;
+    // inputs and LO events on the device before any epoch reads them
+    const hipError_t serr = hipStreamSynchronize(S.drain);
+    if (err == hipSuccess) err = serr;
     r.state = kAdmitted;
     S.active.push_back(r.ticket);
+    if (err != hipSuccess) fail_request(S, r, VSH_E_DEVICE, "admission", err);
     progress = true;
   }
   (void)ctx;
@@ -283,9 +307,9 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
   Segment* sd = (Segment*)c.take(kMaxEpochReqs * sizeof(Segment));
   unsigned long long* counter = (unsigned long long*)c.take(256);
   Records slots = carve_slots(c, lanes, cap);
-  (void)hipMemcpyAsync(rd, E->reqs_host, nreq * sizeof(ReqDev), hipMemcpyHostToDevice, E->stream);
-  (void)hipMemcpyAsync(sd, E->segs_host, nseg * sizeof(Segment), hipMemcpyHostToDevice, E->stream);
-  (void)hipMemsetAsync(counter, 0, 8, E->stream);
+  hipError_t err = hipMemcpyAsync(rd, E->reqs_host, nreq * sizeof(ReqDev), hipMemcpyHostToDevice, E->stream);
+  if (err == hipSuccess) err = hipMemcpyAsync(sd, E->segs_host, nseg * sizeof(Segment), hipMemcpyHostToDevice, E->stream);
+  if (err == hipSuccess) err = hipMemsetAsync(counter, 0, 8, E->stream);
   PersistArgs A;
   A.slots = slots;
   A.reqs = rd;
@@ -297,8 +321,26 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
   A.total = total;
   A.next = counter;
   A.period = tn.refill_period;
-  launch_persistent(A, lanes, tn.pers_block, tn.mapping, false, massive, E->stream);
-  (void)hipEventRecord(E->done, E->stream);
+  if (err == hipSuccess && S.fail_epochs > 0) {  // testing hook: report a device error, launch nothing
+    --S.fail_epochs;
+    err = hipErrorLaunchFailure;
+  }
+  if (err == hipSuccess) {
+    launch_persistent(A, lanes, tn.pers_block, tn.mapping, false, massive, E->stream);
+    err = hipGetLastError();
+  }
+  if (err == hipSuccess) err = hipEventRecord(E->done, E->stream);
+  if (err != hipSuccess) {
+    // nothing of this epoch runs: its requests fail (work already queued on
+    // the stream finishes before the stream is used again)
+    for (auto& p : E->parts) {
+      ServeReq& r = *S.reqs[p.first];
+      r.inflight -= 1;
+      fail_request(S, r, VSH_E_DEVICE, "epoch launch", err);
+    }
+    E->parts.clear();
+    return false;
+  }
   E->busy = true;
   return true;
 }
@@ -315,9 +357,8 @@ static void start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
     if (hipMalloc(&S.scratch, need) == hipSuccess) S.scratch_bytes = need;
     else (void)hipGetLastError();
   }
-  if (!S.scratch) {
-    r.cancel = true;  // cannot compute its observables: fail the request
-    finish_request(S, r, kCancelledState);
+  if (!S.scratch) {  // cannot compute its observables: fail the request
+    fail_request(S, r, VSH_E_NOMEM, "observables scratch", hipSuccess);
     return;
   }
   Carver c(S.scratch);
@@ -338,12 +379,20 @@ static void start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
   r.sd.resize((size_t)kNSumD * n);
   r.si.resize((size_t)kNSumI * n);
   r.hs.resize(n);
-  (void)hipMemcpyAsync(r.hist.data(), r.buf.hist, kHistDoubles * 8, hipMemcpyDeviceToHost, S.drain);
-  (void)hipMemcpyAsync(r.sd.data(), r.buf.sum.d, r.sd.size() * 8, hipMemcpyDeviceToHost, S.drain);
-  (void)hipMemcpyAsync(r.si.data(), r.buf.sum.i, r.si.size() * 4, hipMemcpyDeviceToHost, S.drain);
-  (void)hipMemcpyAsync(r.hs.data(), r.buf.sum.hash, n * 8, hipMemcpyDeviceToHost, S.drain);
-  (void)hipEventCreateWithFlags(&r.drained, hipEventDisableTiming);
-  (void)hipEventRecord(r.drained, S.drain);
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(r.hist.data(), r.buf.hist, kHistDoubles * 8, hipMemcpyDeviceToHost, S.drain);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(r.sd.data(), r.buf.sum.d, r.sd.size() * 8, hipMemcpyDeviceToHost, S.drain);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(r.si.data(), r.buf.sum.i, r.si.size() * 4, hipMemcpyDeviceToHost, S.drain);
+  if (err == hipSuccess) err = hipMemcpyAsync(r.hs.data(), r.buf.sum.hash, n * 8, hipMemcpyDeviceToHost, S.drain);
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&r.drained, hipEventDisableTiming);
+  if (err == hipSuccess) err = hipEventRecord(r.drained, S.drain);
+  if (err != hipSuccess) {
+    fail_request(S, r, VSH_E_DEVICE, "observables launch", err);
+    return;
+  }
   r.state = kDraining;
   (void)ctx;
 }
@@ -351,15 +400,20 @@ static void start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
 static bool retire_epochs(vsh_ctx* ctx, ServeState& S) {
   bool progress = false;
   for (auto& E : S.ep) {
-    if (!E.busy || hipEventQuery(E.done) != hipSuccess) continue;
+    if (!E.busy) continue;
+    const hipError_t q = hipEventQuery(E.done);
+    if (q == hipErrorNotReady) continue;
     for (auto& p : E.parts) {
       auto it = S.reqs.find(p.first);
       if (it == S.reqs.end()) continue;
       ServeReq& r = *it->second;
       r.finished += p.second;
       r.inflight -= 1;
-      if (r.cancel) {
-        if (r.inflight == 0 && r.state == kAdmitted) finish_request(S, r, kCancelledState);
+      if (q != hipSuccess) {
+        fail_request(S, r, VSH_E_DEVICE, "epoch", q);
+      } else if (r.cancel) {
+        if (r.inflight == 0 && r.state == kAdmitted)
+          finish_request(S, r, r.fail_code != VSH_OK ? kFailed : kCancelledState);
       } else if (r.finished == r.req.n_events) {
         start_drain(ctx, S, r);
       }
@@ -374,9 +428,17 @@ static bool retire_epochs(vsh_ctx* ctx, ServeState& S) {
 static bool poll_drains(ServeState& S) {
   bool progress = false;
   std::vector<uint64_t> done;
+  std::vector<std::pair<uint64_t, hipError_t>> failed;
   for (uint64_t t : S.active) {
     ServeReq& r = *S.reqs[t];
-    if (r.state == kDraining && hipEventQuery(r.drained) == hipSuccess) done.push_back(t);
+    if (r.state != kDraining) continue;
+    const hipError_t q = hipEventQuery(r.drained);
+    if (q == hipSuccess) done.push_back(t);
+    else if (q != hipErrorNotReady) failed.emplace_back(t, q);
+  }
+  for (auto& f : failed) {
+    fail_request(S, *S.reqs[f.first], VSH_E_DEVICE, "observables", f.second);
+    progress = true;
   }
   for (uint64_t t : done) {
     ServeReq& r = *S.reqs[t];
@@ -475,6 +537,17 @@ using namespace vsh;
 
 extern "C" {
 
+vsh_status vsh_test_fail_epochs(vsh_ctx* ctx, uint32_t count) {
+  if (!ctx) return VSH_E_INVALID;
+  std::lock_guard<std::mutex> api(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  const vsh_status rc = serve_start(ctx);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ctx->serve->mu);
+  ctx->serve->fail_epochs = count;
+  return VSH_OK;
+}
+
 vsh_status vsh_submit(vsh_ctx* ctx, const vsh_request* req, uint64_t* ticket) {
   if (!ctx || !ticket) return VSH_E_INVALID;
   std::lock_guard<std::mutex> api(ctx->mu);
@@ -522,7 +595,7 @@ vsh_status vsh_poll(vsh_ctx* ctx, uint64_t ticket, int* done) {
     return VSH_E_NOTFOUND;
   }
   const int st = it->second->state;
-  *done = (st == kFinished || st == kCancelledState) ? 1 : 0;
+  *done = (st == kFinished || st == kCancelledState || st == kFailed) ? 1 : 0;
   return VSH_OK;
 }
 
@@ -538,9 +611,12 @@ vsh_status vsh_wait(vsh_ctx* ctx, uint64_t ticket, vsh_result** out) {
     return VSH_E_NOTFOUND;
   }
   ServeReq* r = it->second.get();
-  S->done_cv.wait(lk, [&] { return r->state == kFinished || r->state == kCancelledState; });
+  S->done_cv.wait(lk, [&] { return r->state == kFinished || r->state == kCancelledState || r->state == kFailed; });
   vsh_status rc = VSH_OK;
-  if (r->state == kCancelledState) {
+  if (r->state == kFailed) {
+    set_error(ctx, "ticket %llu failed: %s", (unsigned long long)ticket, r->fail_msg.c_str());
+    rc = r->fail_code;
+  } else if (r->state == kCancelledState) {
     set_error(ctx, "ticket %llu was cancelled", (unsigned long long)ticket);
     rc = VSH_E_CANCELLED;
   } else if (!r->box) {
@@ -566,7 +642,7 @@ vsh_status vsh_cancel(vsh_ctx* ctx, uint64_t ticket) {
       return VSH_E_NOTFOUND;
     }
     ServeReq& r = *it->second;
-    if (r.state == kFinished || r.state == kCancelledState) return VSH_OK;
+    if (r.state == kFinished || r.state == kCancelledState || r.state == kFailed) return VSH_OK;
     r.cancel = true;
     if (r.state == kAdmitted && r.inflight == 0) finish_request(*S, r, kCancelledState);
   }

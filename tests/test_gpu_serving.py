@@ -124,6 +124,24 @@ def test_cancel_and_errors(ctx):
     print("cancelled:", cancelled)
 
 
+def test_device_error_fails_only_its_request(ctx):
+    # forced from the host: the next serving launch reports a HIP launch
+    # failure instead of launching, so the GPU itself stays healthy
+    import paper_2403_08692_amd as P
+
+    ref = ctx.generate(2000, seed=41, summary=True)
+    ctx.test_fail_epochs(1)
+    t = ctx.submit(2000, seed=41, summary=True)
+    with pytest.raises(P.VshError) as ei:
+        ctx.wait(t)
+    assert ei.value.code == -3 and "launch" in str(ei.value)
+    # the loop goes on: the same request again gives the events generate gives
+    t = ctx.submit(2000, seed=41, summary=True)
+    got = ctx.wait(t)
+    np.testing.assert_array_equal(got["sum_i"], ref["sum_i"])
+    np.testing.assert_array_equal(got["hash"], ref["hash"])
+
+
 def test_poll_reports_completion(ctx):
     import time
 
