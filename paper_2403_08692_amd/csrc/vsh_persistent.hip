@@ -164,7 +164,9 @@ struct FlatShared {
   uint16_t item[2048];              // the cycle's items, owner << 10 | parton: gluons, then quarks
   uint16_t sitem[512];              // the cycle's stale partons, owner << 10 | parton
   double best_v[64];
-  uint32_t best_idx[64];
+  uint32_t best_idx[64];  // packed (i, k, K) << 6 | the lane whose item made it
+  double coef[2][64];     // per item lane: its best end's trial coefficients (ca, cb)
+  double best_c[2][64];   // per owner: those of its running best
   uint32_t counts[64];  // the cycle's trials (low 16 bits) and active ends (high 16 bits) per owner
   uint32_t climit[64];  // each event's cycle limit
   double wsh[64];       // each event's shower weight (weighted veto)
@@ -280,7 +282,8 @@ __device__ __forceinline__ void entry_build(double cfac, double tcut, const Reco
 
 __device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Records& r, uint64_t slot, int i,
                                                      const EndCache& ec, uint64_t col, bool stale, double& best,
-                                                     uint32_t& widx, uint32_t& trials, uint32_t& ends) {
+                                                     uint32_t& widx, double& wca, double& wcb, uint32_t& trials,
+                                                     uint32_t& ends) {
   uint64_t* ent = ec.rec ? ec.rec + ((col * ec.cap) + (uint64_t)i) * kCacheWords : nullptr;
   uint64_t w[kCacheWords];
   int pid_i, k1, k2;
@@ -323,7 +326,11 @@ __device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Re
     if (ca == 0.0) continue;  // no partner, or no phase space above the cutoff
     ends += 1;
     const int K = end_draws(c, i, k, pid_i, ca, cb, best, trials);
-    if (K >= 0) widx = pack_trial(i, k, K);
+    if (K >= 0) {
+      widx = pack_trial(i, k, K);
+      wca = ca;
+      wcb = cb;
+    }
   }
   if (stale && ent) {
     if (k1 == kNoPartner) w[1] = w[2] = 0ull;
@@ -493,17 +500,20 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       last = (j + 1 == st[o + 1]) || lane == 63;
       const TrialCtx c{Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]}, sh.lt[o], sh.tcut[o],
                        sh.ltc[o], sh.cfac[o], sh.cycle[o]};
-      double best = c.ltc;
+      double best = c.ltc, wca = 0.0, wcb = 0.0;
       uint32_t widx = kNoTrial;
       uint32_t nt = 0, ne = 0;
       if constexpr (kMassive)
         parton_trials_mflat(c, slots, sh.slot[o], (int)i, QuarkMasses{0.0, 0.0, 0.0, sh.mc[o], sh.mb[o]}, best,
                             widx, nt, ne);
       else
-        parton_trials_cached(c, slots, sh.slot[o], (int)i, ec, wave_col + o, !kCached, best, widx, nt, ne);
+        parton_trials_cached(c, slots, sh.slot[o], (int)i, ec, wave_col + o, !kCached, best, widx, wca, wcb, nt,
+                             ne);
       if (widx != kNoTrial) {
         v = best;
-        idx = widx;
+        idx = (widx << 6) | lane;  // same order as widx: items of one owner differ in i
+        sh.coef[0][lane] = wca;
+        sh.coef[1][lane] = wcb;
       }
       atomicAdd(&sh.counts[o], nt | (ne << 16));  // at most 12 x 1024 trials and 2048 ends per cycle
     }
@@ -520,10 +530,14 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     if (active && last && gsec && beats(v, idx, sh.best_v[o], sh.best_idx[o])) {
       sh.best_v[o] = v;
       sh.best_idx[o] = idx;
+      sh.best_c[0][o] = sh.coef[0][idx & 63u];
+      sh.best_c[1][o] = sh.coef[1][idx & 63u];
     }
     if (active && last && !gsec && beats(v, idx, sh.best_v[o], sh.best_idx[o])) {
       sh.best_v[o] = v;
       sh.best_idx[o] = idx;
+      sh.best_c[0][o] = sh.coef[0][idx & 63u];
+      sh.best_c[1][o] = sh.coef[1][idx & 63u];
     }
     __syncthreads();
   }
@@ -535,8 +549,9 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     MWinner W{Winner{0.0, 0.0, 0.0, 0.0, -1, 0, 0}, 0.0, 0.0, 0.0, 0.0, 1.0, false};
     double best = s.ltc;
     if (bi != kNoTrial) {
+      const uint32_t wi = bi >> 6;
       best = sh.best_v[lane];
-      W = massive_winner(trial_ctx(s), slots, slot, (int)(bi >> 14), (int)((bi >> 4) & 1023u), (int)(bi & 15u), qm);
+      W = massive_winner(trial_ctx(s), slots, slot, (int)(wi >> 14), (int)((wi >> 4) & 1023u), (int)(wi & 15u), qm);
     }
     pend = veto_decide_massive(s, best, W, acc, pd, sh.wsh[lane]);
   } else if (trial) {
@@ -546,24 +561,15 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
     double best = s.ltc;
     if (bi != kNoTrial) {
-      w.i = (int)(bi >> 14);
-      w.k = (int)((bi >> 4) & 1023u);
-      w.K = (int)(bi & 15u);
+      const uint32_t wi = bi >> 6;
+      w.i = (int)(wi >> 14);
+      w.k = (int)((wi >> 4) & 1023u);
+      w.K = (int)(wi & 15u);
       best = sh.best_v[lane];
-      // the winning end's coefficients: from its fresh cache entry, or
-      // recomputed from the records (the same numbers)
-      double ca, cb;
-      if (kCached) {
-        const uint64_t* ent = ec.rec + ((wave_col + lane) * ec.cap + (uint64_t)w.i) * kCacheWords;
-        const int e = (int)((ent[0] >> 8) & 0xFFFFu) == w.k ? 0 : 1;
-        ca = __longlong_as_double((long long)ent[1 + 2 * e]);
-        cb = __longlong_as_double((long long)ent[2 + 2 * e]);
-      } else {
-        double q2, zm, zp, L;
-        end_coeffs(s.cfac, s.tcut, slots.pid[(uint64_t)w.i * slots.stride + slot], slots.load(w.i, slot),
-                   slots.load(w.k, slot), q2, zm, zp, L, ca, cb);
-      }
-      end_from_coeffs(s.cfac, s.tcut, w.K, ca, cb, w);
+      // the winning end's coefficients, passed on by the item that drew the
+      // winner: its cache entry's numbers (or, without a cache, what the item
+      // computed from the records, the same numbers)
+      end_from_coeffs(s.cfac, s.tcut, w.K, sh.best_c[0][lane], sh.best_c[1][lane], w);
     }
     pend = veto_decide_drawn(s, best, w, acc, pd, sh.wsh[lane]);
   }
