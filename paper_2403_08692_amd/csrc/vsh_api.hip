@@ -97,16 +97,16 @@ vsh_status validate_request(vsh_ctx* ctx, const vsh_request* req, bool need_ener
 // Plain-form device layout of a chunk of `stride` events with capacity cap:
 // records, Durham scratch, summaries, per-event inputs, histogram.
 // ---------------------------------------------------------------------------
-uint64_t plain_bytes_per_event(uint32_t cap) {
-  return (uint64_t)cap * (4 * 8 + 1 + 4 * 2 + kCacheWords * 8) + kNSumD * 8 + kNSumI * 4 + 8 + 2 * 8;
+uint64_t plain_bytes_per_event(uint32_t cap, bool massive) {
+  return (uint64_t)cap * (4 * 8 + 1 + 4 * 2 + cache_words(massive) * 8) + kNSumD * 8 + kNSumI * 4 + 8 + 2 * 8;
 }
 
-uint64_t plain_layout_bytes(uint64_t stride, uint32_t cap) {
-  return align_up(plain_bytes_per_event(cap) * stride + obs_scratch_bytes(stride, cap) + 20 * 256 +
+uint64_t plain_layout_bytes(uint64_t stride, uint32_t cap, bool massive) {
+  return align_up(plain_bytes_per_event(cap, massive) * stride + obs_scratch_bytes(stride, cap) + 20 * 256 +
                       kHistDoubles * 8, 256);
 }
 
-PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap) {
+PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap, bool massive) {
   PlainLayout L;
   char* p = static_cast<char*>(base);
   auto take = [&](uint64_t bytes) {
@@ -126,7 +126,7 @@ PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap) {
   L.rec.apart = (uint16_t*)take(slots * 2);
   L.rec.stride = stride;
   L.rec.cap = cap;
-  L.cache = (uint64_t*)take(slots * kCacheWords * 8);
+  L.cache = (uint64_t*)take(slots * cache_words(massive) * 8);
   {
     char* q = p;
     L.sc = carve_obs_scratch(q, stride, cap);
@@ -314,9 +314,10 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
   hipStream_t st = ctx->stream;
   const uint32_t cap = req->max_partons;
   const uint64_t stride = align_up(count, 64);
-  vsh_status rc = ctx->arena.reserve(ctx, plain_layout_bytes(stride, cap));
+  const bool massive = request_massive(*req) != 0;
+  vsh_status rc = ctx->arena.reserve(ctx, plain_layout_bytes(stride, cap, massive));
   if (rc) return rc;
-  PlainLayout L = carve_plain(ctx->arena.ptr, stride, cap);
+  PlainLayout L = carve_plain(ctx->arena.ptr, stride, cap, massive);
   hipError_t err;
 #define HIPCHK(x)                                 \
   do {                                            \
@@ -434,7 +435,7 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
 }
 
 uint64_t chunk_events(vsh_ctx* ctx, const vsh_request* req) {
-  const uint64_t per = plain_bytes_per_event(req->max_partons);
+  const uint64_t per = plain_bytes_per_event(req->max_partons, request_massive(*req) != 0);
   uint64_t budget = ctx->budget;
   // leave room for the record-gather buffer when records are returned
   if (req->flags & VSH_RECORDS) budget = budget / 2;
@@ -657,7 +658,7 @@ vsh_status vsh_shower_records(vsh_ctx* ctx, const vsh_request* req, const uint64
 uint64_t vsh_workspace_size(const vsh_request* req) {
   if (!req || req->n_events == 0 || req->max_partons < 2 || req->max_partons > kMaxCap) return 0;
   if (req->flags & VSH_FORM_PERSISTENT) return persistent_workspace_bytes(req);
-  return plain_layout_bytes(align_up(req->n_events, 64), req->max_partons);
+  return plain_layout_bytes(align_up(req->n_events, 64), req->max_partons, request_massive(*req) != 0);
 }
 
 vsh_status vsh_generate_into(vsh_ctx* ctx, const vsh_request* req, void* stream, void* workspace,
@@ -692,7 +693,7 @@ vsh_status vsh_generate_into(vsh_ctx* ctx, const vsh_request* req, void* stream,
     return persistent_into(ctx, req, st, workspace, dev_hist, dev_sum_d, dev_sum_i, dev_hash);
   const uint64_t n = req->n_events;
   const uint64_t stride = align_up(n, 64);
-  PlainLayout L = carve_plain(workspace, stride, req->max_partons);
+  PlainLayout L = carve_plain(workspace, stride, req->max_partons, request_massive(*req) != 0);
   EventInputs in{};
   in.seed = req->seed;
   in.first = req->first_event;

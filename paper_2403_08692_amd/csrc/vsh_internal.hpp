@@ -99,8 +99,8 @@ vsh_status validate_request(vsh_ctx* ctx, const vsh_request* req, bool need_ener
 ResultBox* new_result(uint64_t n_events, bool summary);
 void finish_result(ResultBox* b);
 void tally_chunk(ResultBox* b, const int32_t* si, const double* sd, uint64_t stride, uint64_t count);
-uint64_t plain_layout_bytes(uint64_t stride, uint32_t cap);
-PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap);
+uint64_t plain_layout_bytes(uint64_t stride, uint32_t cap, bool massive);
+PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap, bool massive);
 
 vsh_status gather_records(vsh_ctx* ctx, const Records& r, const int32_t* n_dev, const int32_t* n_host,
                           uint64_t count, ResultBox* box);
@@ -110,8 +110,8 @@ vsh_status generate_plain(vsh_ctx* ctx, const vsh_request* req, const uint64_t* 
 
 // persistent form (vsh_persistent.hip)
 uint32_t persistent_lanes(const vsh_ctx* ctx);
-uint64_t batch_bytes(uint64_t n, uint32_t cap);
-BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap);
+uint64_t batch_bytes(uint64_t n, uint32_t cap, bool massive);
+BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap, bool massive);
 vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, uint64_t n, hipStream_t st,
                      void* base, const double* ecm_dev, const double* tcut_dev, double* hist, bool use_graph,
                      BatchLayout* out_layout);

@@ -280,6 +280,59 @@ __device__ __forceinline__ void entry_build(double cfac, double tcut, const Reco
   for (int q = 0; q < kCacheWords; ++q) ent[q] = w[q];
 }
 
+// The same for an event with quark masses: per end the four class
+// coefficients of massive_end_coeffs.
+__device__ __forceinline__ void entry_build_massive(double cfac, double tcut, const Records& r, uint64_t slot, int i,
+                                                    const EndCache& ec, uint64_t col, const QuarkMasses& qm) {
+  uint64_t* ent = ec.rec + ((col * ec.cap) + (uint64_t)i) * kMCacheWords;
+  const uint64_t oi = (uint64_t)i * r.stride + slot;
+  const int pid_i = r.pid[oi];
+  int k1 = r.cpart[oi], k2 = r.apart[oi];
+  if (k2 == k1) k2 = kNoPartner;
+  if (k1 > k2) {
+    const int t = k1;
+    k1 = k2;
+    k2 = t;
+  }
+  const P4 pi = r.load(i, slot);
+  const TrialCtx c{Keyed{0u, 0u, 0u, 0u}, 0.0, tcut, 0.0, cfac, 0u};  // the ranges read t_C and cfac only
+  uint64_t w[kMCacheWords];
+  w[0] = pack_meta(pid_i, k1, k2);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int k = e == 0 ? k1 : k2;
+    double cc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (k != kNoPartner) massive_end_coeffs(c, pid_i, r.pid[(uint64_t)k * r.stride + slot], pi, r.load(k, slot), qm, cc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[1 + 4 * e + q] = (uint64_t)__double_as_longlong(cc[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < kMCacheWords; ++q) ent[q] = w[q];
+}
+
+// Trials of parton i of an event with quark masses from its fresh cache
+// entry (the stale rounds rebuilt it): the draws and counts of
+// parton_trials_massive; only the item's best (i, k, K) is kept.
+__device__ __forceinline__ void parton_trials_mcached(const TrialCtx& c, uint64_t col, int i, const EndCache& ec,
+                                                      double& best, uint32_t& widx, uint32_t& trials,
+                                                      uint32_t& ends) {
+  const uint64_t* ent = ec.rec + ((col * ec.cap) + (uint64_t)i) * kMCacheWords;
+  uint64_t w[kMCacheWords];
+#pragma unroll
+  for (int q = 0; q < kMCacheWords; ++q) w[q] = ent[q];
+  const int pid_i = (int)(int8_t)(uint8_t)(w[0] & 0xFFu);
+  const int ks[2] = {(int)((w[0] >> 8) & 0xFFFFu), (int)((w[0] >> 24) & 0xFFFFu)};
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    if (ks[e] == kNoPartner) continue;
+    double cc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cc[q] = __longlong_as_double((long long)w[1 + 4 * e + q]);
+    const int K = end_draws_massive(c, i, ks[e], pid_i, cc, best, trials, ends);
+    if (K >= 0) widx = pack_trial(i, ks[e], K);
+  }
+}
+
 __device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Records& r, uint64_t slot, int i,
                                                      const EndCache& ec, uint64_t col, bool stale, double& best,
                                                      uint32_t& widx, double& wca, double& wcb, uint32_t& trials,
@@ -378,7 +431,6 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
                                            bool& pend, Pending& pd, const Records& slots, uint64_t slot,
                                            const EndCache& ec, uint64_t wave_col, uint32_t lane,
                                            const QuarkMasses& qm = QuarkMasses{0.0, 0.0, 0.0, 0.0, 0.0}) {
-  static_assert(!(kCached && kMassive), "massive events take no end cache");
   const bool trial = busy && !pend;
   uint64_t* mym = gm + (uint64_t)lane * words;
   uint64_t* sm = gm + (uint64_t)64 * words;  // stale masks
@@ -463,7 +515,11 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
           o = owner_of(sh.sstart, at);
           i = select_slot(sm + (uint64_t)o * words, words, at - sh.sstart[o], true);
         }
-        entry_build(sh.cfac[o], sh.tcut[o], slots, sh.slot[o], (int)i, ec, wave_col + o);
+        if constexpr (kMassive)
+          entry_build_massive(sh.cfac[o], sh.tcut[o], slots, sh.slot[o], (int)i, ec, wave_col + o,
+                              QuarkMasses{0.0, 0.0, 0.0, sh.mc[o], sh.mb[o]});
+        else
+          entry_build(sh.cfac[o], sh.tcut[o], slots, sh.slot[o], (int)i, ec, wave_col + o);
       }
     }
     __threadfence_block();  // the rebuilt entries are stored before any trial round reads them
@@ -503,7 +559,9 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       double best = c.ltc, wca = 0.0, wcb = 0.0;
       uint32_t widx = kNoTrial;
       uint32_t nt = 0, ne = 0;
-      if constexpr (kMassive)
+      if constexpr (kMassive && kCached)
+        parton_trials_mcached(c, wave_col + o, (int)i, ec, best, widx, nt, ne);
+      else if constexpr (kMassive)
         parton_trials_mflat(c, slots, sh.slot[o], (int)i, QuarkMasses{0.0, 0.0, 0.0, sh.mc[o], sh.mb[o]}, best,
                             widx, nt, ne);
       else
@@ -620,7 +678,7 @@ __global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary 
     mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
   while (__any(busy)) {
-    flat_cycle<!kMassive, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane, in.qm);
+    flat_cycle<true, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane, in.qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
       write_state(s, sm, e);
@@ -672,8 +730,8 @@ __global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
       busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle<kInPlace && !kMassive, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache,
-                                                L - lane, lane, A.reqs[req].qm);
+    flat_cycle<kInPlace, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane,
+                                   A.reqs[req].qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
@@ -769,19 +827,21 @@ Scratch carve_scratch(Carver& c, uint64_t n, uint32_t cap) { return carve_obs_sc
 // stride of a batch's end-coefficient cache, whatever the tuning.
 constexpr uint64_t kCacheLanes = 16ull * 256 * 64;
 
-uint64_t cache_bytes(uint32_t cap) { return align_up(kCacheLanes * cap * kCacheWords * 8, 256); }
+uint64_t cache_bytes(uint32_t cap, bool massive) {
+  return align_up(kCacheLanes * cap * cache_words(massive) * 8, 256);
+}
 
 // A batch is one request, showered in place in its output records.
-uint64_t batch_bytes(uint64_t n, uint32_t cap) {
-  return request_out_bytes(n, cap, true) + cache_bytes(cap) + obs_scratch_bytes(n, cap) + 4096 +
+uint64_t batch_bytes(uint64_t n, uint32_t cap, bool massive) {
+  return request_out_bytes(n, cap, true) + cache_bytes(cap, massive) + obs_scratch_bytes(n, cap) + 4096 +
          sizeof(ReqDev) + sizeof(Segment) + 1024;
 }
 
-BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap) {
+BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap, bool massive) {
   Carver c(base);
   BatchLayout L;
   L.buf = carve_request(c, n, cap, true);
-  L.cache.rec = (uint64_t*)c.take(kCacheLanes * cap * kCacheWords * 8);
+  L.cache.rec = (uint64_t*)c.take(kCacheLanes * cap * cache_words(massive) * 8);
   L.cache.cap = cap;
   L.sc = carve_scratch(c, n, cap);
   L.counter = (unsigned long long*)c.take(256);
@@ -954,7 +1014,7 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
               (unsigned long long)lanes, (unsigned long long)kCacheLanes);
     return VSH_E_INTERNAL;
   }
-  BatchLayout L = carve_batch(base, n, cap);
+  BatchLayout L = carve_batch(base, n, cap, request_massive(*req) != 0);
   if (out_layout) *out_layout = L;
   ReqDev d;
   fill_request_desc(d, L.buf, req, first_idx, ecm_dev, tcut_dev);
@@ -1022,11 +1082,11 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
 }
 
 uint64_t persistent_workspace_bytes_ctx(const vsh_ctx* ctx, const vsh_request* req) {
-  return batch_bytes(req->n_events, req->max_partons);
+  return batch_bytes(req->n_events, req->max_partons, request_massive(*req) != 0);
 }
 
 uint64_t persistent_workspace_bytes(const vsh_request* req) {
-  return batch_bytes(req->n_events, req->max_partons);
+  return batch_bytes(req->n_events, req->max_partons, request_massive(*req) != 0);
 }
 
 vsh_status persistent_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void* ws, double* dev_hist,
@@ -1063,7 +1123,7 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
               (unsigned long long)lanes, (unsigned long long)kCacheLanes);
     return VSH_E_INTERNAL;
   }
-  const uint64_t fixed = 64 * 1024 + cache_bytes(cap);
+  const uint64_t fixed = 64 * 1024 + cache_bytes(cap, request_massive(*req) != 0);
   if (budget <= fixed + request_out_bytes(64, cap, true) + obs_scratch_bytes(64, cap)) {
     set_error(ctx, "memory budget too small for the persistent form at %u partons", cap);
     return VSH_E_NOMEM;
@@ -1080,12 +1140,12 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
   float t_me = 0, t_sh = 0, t_obs = 0;
   for (uint64_t a = 0; a < req->n_events; a += chunk) {
     const uint64_t n = std::min(chunk, req->n_events - a);
-    vsh_status rc = ctx->arena.reserve(ctx, batch_bytes(n, cap));
+    vsh_status rc = ctx->arena.reserve(ctx, batch_bytes(n, cap, request_massive(*req) != 0));
     if (rc) {
       delete box;
       return rc;
     }
-    BatchLayout L = carve_batch(ctx->arena.ptr, n, cap);
+    BatchLayout L = carve_batch(ctx->arena.ptr, n, cap, request_massive(*req) != 0);
     hipError_t err;
     const double* ecm_dev = nullptr;
     const double* tcut_dev = nullptr;

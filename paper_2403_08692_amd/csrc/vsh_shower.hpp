@@ -605,6 +605,102 @@ __device__ __forceinline__ void end_trials_massive(const TrialCtx& c, int i, int
   if (active) ends += 1;
 }
 
+// The trial coefficients of the end (i, k) by kernel class, with the
+// arithmetic of end_trials_massive: a quark end's in cc[0]; a gluon end's
+// g -> g g, light g -> q qbar, g -> c cbar and g -> b bbar in cc[0..3].  0 for a
+// class without phase space above the cutoff (an active class's coefficient
+// is positive).  The flattened kernels cache them between emissions.
+__device__ __forceinline__ void massive_end_coeffs(const TrialCtx& c, int pid_i, int pid_k, const P4& pi,
+                                                   const P4& pk, const QuarkMasses& qm, double cc[4]) {
+  cc[0] = cc[1] = cc[2] = cc[3] = 0.0;
+  const double q2 = 2.0 * mdot(pi, pk);
+  const double msp = quark_mass(qm, pid_i), mk = quark_mass(qm, pid_k);
+  const double Q2 = q2 + msp * msp + mk * mk;
+  if (pid_i != kGluon) {
+    MRange R;
+    if (mrange_quark(c, q2, Q2, msp, mk, R)) cc[0] = R.c;
+    return;
+  }
+  MRange G;
+  double cqq;
+  const bool ok = mrange_light(c, q2, Q2, mk, G, cqq);
+  if (ok) {
+    cc[0] = G.c;
+    cc[1] = cqq;
+  }
+#pragma unroll
+  for (int f = 4; f <= 5; ++f) {
+    MRange H;
+    if (mrange_heavy(c, Q2, quark_mass(qm, f), mk, ok, G, cqq, H)) cc[f - 2] = H.c;
+  }
+}
+
+// The trials of end_trials_massive from cached coefficients cc (same draws,
+// order, counts and winner).  Returns the winning kernel, or -1 if none beat
+// `best`.
+__device__ __forceinline__ int end_draws_massive(const TrialCtx& c, int i, int k, int pid_i, const double cc[4],
+                                                 double& best, uint32_t& trials, uint32_t& ends) {
+  int K = -1;
+  if (pid_i != kGluon) {
+    if (cc[0] == 0.0) return -1;
+    ends += 1;
+    const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
+    const double lt_try = c.lt + log_fast(unit(d.x, d.y)) / cc[0];
+    trials += 1;
+    if (lt_try > best) {
+      best = lt_try;
+      K = pid_i > 0 ? pid_i - 1 : 4 - pid_i;
+    }
+    return K;
+  }
+  if (cc[0] == 0.0 && cc[2] == 0.0 && cc[3] == 0.0) return -1;
+  ends += 1;
+  const U4 d0 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
+  const U4 d1 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 1));
+  const U4 d2 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 2));
+  if (cc[0] != 0.0) {
+    trials += 4;
+    const double lgg = c.lt + log_fast(unit(d0.x, d0.y)) / cc[0];
+    if (lgg > best) {
+      best = lgg;
+      K = 10;
+    }
+    double um = unit(d0.z, d0.w);
+    int fm = 1;
+    const double uu = unit(d1.x, d1.y), us = unit(d1.z, d1.w);
+    if (uu > um) {  // the first flavour wins ties, as in the kernel loop
+      um = uu;
+      fm = 2;
+    }
+    if (us > um) {
+      um = us;
+      fm = 3;
+    }
+    const double lqq = c.lt + log_fast(um) / cc[1];
+    if (lqq > best) {
+      best = lqq;
+      K = 10 + fm;
+    }
+  }
+  if (cc[2] != 0.0) {
+    trials += 1;
+    const double lt_try = c.lt + log_fast(unit(d2.x, d2.y)) / cc[2];
+    if (lt_try > best) {
+      best = lt_try;
+      K = 14;
+    }
+  }
+  if (cc[3] != 0.0) {
+    trials += 1;
+    const double lt_try = c.lt + log_fast(unit(d2.z, d2.w)) / cc[3];
+    if (lt_try > best) {
+      best = lt_try;
+      K = 15;
+    }
+  }
+  return K;
+}
+
 // The winner record of kernel K of the end (i, k) of the event in column e,
 // recomputed from the records with the arithmetic of the trials above (the
 // flattened forms, which keep only the winner's (i, k, K)).

@@ -77,11 +77,12 @@ static vsh_status autotune_persistent(vsh_ctx* ctx, const vsh_request* req) {
   const uint64_t m = std::min<uint64_t>(req->n_events, 1ull << 18);
   const uint32_t cap = req->max_partons;
   const Tuned keep = ctx->tuned;
-  const uint64_t need = batch_bytes(m, cap);
+  const bool massive = request_massive(*req) != 0;
+  const uint64_t need = batch_bytes(m, cap, massive);
   vsh_status rc = ctx->arena.reserve(ctx, need);
   if (rc) return rc;
   void* base = ctx->arena.ptr;
-  BatchLayout L = carve_batch(base, m, cap);
+  BatchLayout L = carve_batch(base, m, cap, massive);
   hipError_t err;
   const double* ecm_dev = nullptr;
   const double* tcut_dev = nullptr;
