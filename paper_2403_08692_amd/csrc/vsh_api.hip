@@ -167,6 +167,26 @@ void Arena::release() {
   size = 0;
 }
 
+vsh_status HostStage::reserve(vsh_ctx* ctx, uint64_t bytes) {
+  if (bytes <= size) return VSH_OK;
+  release();
+  hipError_t err = hipHostMalloc(&ptr, bytes, 0);
+  if (err != hipSuccess) {
+    ptr = nullptr;
+    (void)hipGetLastError();
+    set_error(ctx, "pinned host staging of %llu bytes: %s", (unsigned long long)bytes, hipGetErrorString(err));
+    return VSH_E_NOMEM;
+  }
+  size = bytes;
+  return VSH_OK;
+}
+
+void HostStage::release() {
+  if (ptr) (void)hipHostFree(ptr);
+  ptr = nullptr;
+  size = 0;
+}
+
 // ---------------------------------------------------------------------------
 // result assembly
 // ---------------------------------------------------------------------------
@@ -212,6 +232,9 @@ void finish_result(ResultBox* b) {
 }
 
 // Fold one chunk's per-event ints/doubles into the result counters.
+// The result's counts and sums over count events, from the summary fields
+// [field][stride] (only status, cycles, emissions, trials, active ends and
+// the weight are read).
 void tally_chunk(ResultBox* b, const int32_t* si, const double* sd, uint64_t stride, uint64_t count) {
   vsh_result& r = b->pub;
   for (uint64_t e = 0; e < count; ++e) {
@@ -231,6 +254,70 @@ void tally_chunk(ResultBox* b, const int32_t* si, const double* sd, uint64_t str
     r.total_ends += (uint32_t)si[kSiEnds * stride + e];
     r.total_emissions += (uint32_t)si[kSiEmit * stride + e];
   }
+}
+
+// Copy a chunk's results back through the pinned staging buffer: the
+// histogram, and either every summary field (requested summaries or records)
+// or only the fields the counts read (the weight, then the integer fields
+// from status to active ends); tally them, add the histogram and, with
+// summaries, place the fields in the result.  *n_host (optional) points at
+// the staged parton counts when all fields were copied.
+vsh_status copy_back_chunk(vsh_ctx* ctx, hipStream_t st, const double* dev_hist, const Summary& dev_sum,
+                           uint64_t stride, uint64_t count, bool all_fields, ResultBox* box, uint64_t first_idx,
+                           const int32_t** n_host) {
+  static_assert(kSiStatus == 1 && kSiEnds == kNSumI - 1, "the counted integer fields are the last ones");
+  const uint64_t hist_b = align_up(kHistDoubles * 8, 256);
+  const uint64_t d_fields = all_fields ? kNSumD : 1, i_fields = all_fields ? kNSumI : kNSumI - kSiStatus;
+  const uint64_t d_b = align_up(d_fields * stride * 8, 256), i_b = align_up(i_fields * stride * 4, 256);
+  const uint64_t h_b = all_fields ? align_up(stride * 8, 256) : 0;
+  vsh_status rc = ctx->stage.reserve(ctx, hist_b + d_b + i_b + h_b);
+  if (rc) return rc;
+  char* base = static_cast<char*>(ctx->stage.ptr);
+  double* hh = reinterpret_cast<double*>(base);
+  double* sd = reinterpret_cast<double*>(base + hist_b);
+  int32_t* si = reinterpret_cast<int32_t*>(base + hist_b + d_b);
+  uint64_t* hs = reinterpret_cast<uint64_t*>(base + hist_b + d_b + i_b);
+  hipError_t err = hipMemcpyAsync(hh, dev_hist, kHistDoubles * 8, hipMemcpyDeviceToHost, st);
+  if (all_fields) {
+    if (err == hipSuccess) err = hipMemcpyAsync(sd, dev_sum.d, kNSumD * stride * 8, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipMemcpyAsync(si, dev_sum.i, kNSumI * stride * 4, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipMemcpyAsync(hs, dev_sum.hash, stride * 8, hipMemcpyDeviceToHost, st);
+  } else {
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(sd, dev_sum.d + kSdW * stride, stride * 8, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(si, dev_sum.i + kSiStatus * stride, i_fields * stride * 4, hipMemcpyDeviceToHost, st);
+  }
+  if (err == hipSuccess) err = hipStreamSynchronize(st);
+  if (err != hipSuccess) return hip_fail(ctx, err, "result copy");
+  for (int a = 0; a < kHistDoubles; ++a) box->hist[a] += hh[a];
+  vsh_result& r = box->pub;
+  const int32_t* si0 = all_fields ? si + kSiStatus * stride : si;  // field kSiStatus onwards
+  const double* w = all_fields ? sd + kSdW * stride : sd;
+  for (uint64_t e = 0; e < count; ++e) {
+    const int s_ = si0[e];
+    r.n_done += s_ == kDone;
+    r.n_overflow += s_ == kOverflow;
+    r.n_nonfinite += s_ == kNonFinite;
+    r.n_conservation += s_ == kConservation;
+    r.n_cycle_limit += s_ == kCycleLimitHit;
+    r.sum_w += w[e];
+    r.sum_w2 += w[e] * w[e];
+    const uint32_t cyc = (uint32_t)si0[(kSiCycles - kSiStatus) * stride + e];
+    r.total_cycles += cyc;
+    r.max_cycles = std::max(r.max_cycles, cyc);
+    r.total_trials += (uint32_t)si0[(kSiTrials - kSiStatus) * stride + e];
+    r.total_ends += (uint32_t)si0[(kSiEnds - kSiStatus) * stride + e];
+    r.total_emissions += (uint32_t)si0[(kSiEmit - kSiStatus) * stride + e];
+  }
+  if (all_fields && !box->sum_d.empty()) {
+    const uint64_t N = box->pub.n_events;
+    for (int f = 0; f < kNSumD; ++f) std::memcpy(&box->sum_d[f * N + first_idx], &sd[f * stride], count * 8);
+    for (int f = 0; f < kNSumI; ++f) std::memcpy(&box->sum_i[f * N + first_idx], &si[f * stride], count * 4);
+    std::memcpy(&box->hash[first_idx], hs, count * 8);
+  }
+  if (n_host) *n_host = all_fields ? si + kSiN * stride : nullptr;
+  return VSH_OK;
 }
 
 // gather the final partons of a chunk into CSR order
@@ -399,16 +486,12 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
   launch_obs(L.rec, L.sum, in, L.sc, (uint32_t)count, L.hist, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(ctx->ev[3], st));
-  // copy back: histogram, summaries (always needed for the tallies)
-  std::vector<double> hh(kHistDoubles);
-  std::vector<double> sd((size_t)kNSumD * stride);
-  std::vector<int32_t> si((size_t)kNSumI * stride);
-  std::vector<uint64_t> hs(stride);
-  HIPCHK(hipMemcpyAsync(hh.data(), L.hist, kHistDoubles * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(sd.data(), L.sum.d, sd.size() * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(si.data(), L.sum.i, si.size() * 4, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(hs.data(), L.sum.hash, hs.size() * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  // copy back: the histogram and the summary fields the counts need (all of
+  // them for summaries or records)
+  const bool all_fields = !box->sum_d.empty() || (req->flags & VSH_RECORDS);
+  const int32_t* n_host = nullptr;
+  rc = copy_back_chunk(ctx, st, L.hist, L.sum, stride, count, all_fields, box, first_idx, &n_host);
+  if (rc) return rc;
   float ms;
   HIPCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
   tm.me += ms;
@@ -416,18 +499,8 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
   tm.shower += ms;
   HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
   tm.obs += ms;
-  for (int a = 0; a < kHistDoubles; ++a) box->hist[a] += hh[a];
-  tally_chunk(box, si.data(), sd.data(), stride, count);
-  if (!box->sum_d.empty()) {
-    const uint64_t N = box->pub.n_events;
-    for (int f = 0; f < kNSumD; ++f)
-      std::memcpy(&box->sum_d[f * N + first_idx], &sd[f * stride], count * 8);
-    for (int f = 0; f < kNSumI; ++f)
-      std::memcpy(&box->sum_i[f * N + first_idx], &si[f * stride], count * 4);
-    std::memcpy(&box->hash[first_idx], hs.data(), count * 8);
-  }
   if (req->flags & VSH_RECORDS) {
-    rc = gather_records(ctx, L.rec, L.sum.i + kSiN * stride, si.data() + kSiN * stride, count, box);
+    rc = gather_records(ctx, L.rec, L.sum.i + kSiN * stride, n_host, count, box);
     if (rc) return rc;
   }
 #undef HIPCHK
@@ -568,6 +641,7 @@ void vsh_destroy(vsh_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   ctx->arena.release();
   ctx->arena2.release();
+  ctx->stage.release();
   for (auto& e : ctx->timing_ev) (void)hipEventDestroy(e);
   destroy_graph(ctx->graph);
   for (auto& e : ctx->idle_ev)

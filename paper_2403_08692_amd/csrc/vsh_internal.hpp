@@ -36,6 +36,14 @@ struct Arena {
   void release();
 };
 
+// Pinned host memory for the copies back of vsh_generate (grown on demand).
+struct HostStage {
+  void* ptr = nullptr;
+  uint64_t size = 0;
+  vsh_status reserve(vsh_ctx* ctx, uint64_t bytes);
+  void release();
+};
+
 struct PlainLayout {
   Records rec;
   uint64_t* cache;  // end cache of the flattened kernel, [event][cap] entries of kCacheWords words
@@ -70,6 +78,7 @@ struct vsh_ctx {
   hipEvent_t idle_ev[4] = {nullptr, nullptr, nullptr, nullptr};  // graph event nodes when not timing
   vsh::BatchGraph graph;
   vsh::Arena arena, arena2;
+  vsh::HostStage stage;
   vsh::Tuned tuned;
   float tuned_ms = 0.0f;  // shower-kernel time of the autotuner's choice on its sample
   std::mutex mu;
@@ -99,6 +108,9 @@ vsh_status validate_request(vsh_ctx* ctx, const vsh_request* req, bool need_ener
 ResultBox* new_result(uint64_t n_events, bool summary);
 void finish_result(ResultBox* b);
 void tally_chunk(ResultBox* b, const int32_t* si, const double* sd, uint64_t stride, uint64_t count);
+vsh_status copy_back_chunk(vsh_ctx* ctx, hipStream_t st, const double* dev_hist, const Summary& dev_sum,
+                           uint64_t stride, uint64_t count, bool all_fields, ResultBox* box, uint64_t first_idx,
+                           const int32_t** n_host);
 uint64_t plain_layout_bytes(uint64_t stride, uint32_t cap, bool massive);
 PlainLayout carve_plain(void* base, uint64_t stride, uint32_t cap, bool massive);
 

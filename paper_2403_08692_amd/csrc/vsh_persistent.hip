@@ -1195,29 +1195,19 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     (void)hipEventRecord(ctx->ev[3], st);
     err = hipGetLastError();
     if (err != hipSuccess) { delete box; return hip_fail(ctx, err, "kernel launch"); }
-    std::vector<double> hh(kHistDoubles), sd((size_t)kNSumD * n);
-    std::vector<int32_t> si((size_t)kNSumI * n);
-    std::vector<uint64_t> hs(n);
-    err = hipMemcpyAsync(hh.data(), L.buf.hist, kHistDoubles * 8, hipMemcpyDeviceToHost, st);
-    if (err == hipSuccess) err = hipMemcpyAsync(sd.data(), L.buf.sum.d, sd.size() * 8, hipMemcpyDeviceToHost, st);
-    if (err == hipSuccess) err = hipMemcpyAsync(si.data(), L.buf.sum.i, si.size() * 4, hipMemcpyDeviceToHost, st);
-    if (err == hipSuccess) err = hipMemcpyAsync(hs.data(), L.buf.sum.hash, n * 8, hipMemcpyDeviceToHost, st);
-    if (err == hipSuccess) err = hipStreamSynchronize(st);
-    if (err != hipSuccess) { delete box; return hip_fail(ctx, err, "result copy"); }
+    const bool all_fields = !box->sum_d.empty() || (req->flags & VSH_RECORDS);
+    const int32_t* n_host = nullptr;
+    rc = copy_back_chunk(ctx, st, L.buf.hist, L.buf.sum, n, n, all_fields, box, a, &n_host);
+    if (rc) {
+      delete box;
+      return rc;
+    }
     float ms;
     if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) t_me += ms;
     if (hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]) == hipSuccess) t_sh += ms;
     if (hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]) == hipSuccess) t_obs += ms;
-    for (int k = 0; k < kHistDoubles; ++k) box->hist[k] += hh[k];
-    tally_chunk(box, si.data(), sd.data(), n, n);
-    if (!box->sum_d.empty()) {
-      const uint64_t N = box->pub.n_events;
-      for (int f = 0; f < kNSumD; ++f) std::memcpy(&box->sum_d[f * N + a], &sd[f * n], n * 8);
-      for (int f = 0; f < kNSumI; ++f) std::memcpy(&box->sum_i[f * N + a], &si[f * n], n * 4);
-      std::memcpy(&box->hash[a], hs.data(), n * 8);
-    }
     if (req->flags & VSH_RECORDS) {
-      vsh_status rc2 = gather_records(ctx, L.buf.out, L.buf.sum.i + kSiN * n, si.data() + kSiN * n, n, box);
+      vsh_status rc2 = gather_records(ctx, L.buf.out, L.buf.sum.i + kSiN * n, n_host, n, box);
       if (rc2) {
         delete box;
         return rc2;
