@@ -38,12 +38,13 @@ extern "C" {
 #endif
 
 #define VSH_VERSION_MAJOR 1
-#define VSH_VERSION_MINOR 1
+#define VSH_VERSION_MINOR 2
 
 typedef enum {
   VSH_OK = 0,
   VSH_E_INVALID = -1,   /* bad argument (message names it)                     */
-  VSH_E_NOMEM = -2,     /* the request can never fit the context's memory budget */
+  VSH_E_NOMEM = -2,     /* the request can never fit the memory budget, or an
+                           allocation (device arena, pinned staging) failed      */
   VSH_E_DEVICE = -3,    /* no usable gfx950 device, or a HIP runtime error      */
   VSH_E_BUSY = -4,      /* not finished yet (vsh_poll) / serving loop owns it   */
   VSH_E_NOTFOUND = -5,  /* unknown ticket                                       */
