@@ -351,7 +351,7 @@ def serving_bench(ctx, n_requests, rate_hz):
             "max_ms": float(lat.max()), "events_per_s": trace.total_events / span,
             "offered_events_per_s": trace.total_events / trace.requests[-1].arrival_s,
             "submit_lag_p99_ms": float(np.percentile(lag, 99) * 1e3), "makespan_s": span,
-            "trace": "Poisson 200/s, N = 10^U (U in [2,5]), sqrt(s) in {10,35,91.2,200,500}, "
+            "trace": f"Poisson {rate_hz:g}/s, N = 10^U (U in [2,5]), sqrt(s) in {{10,35,91.2,200,500}}, "
                      "t_C in {0.5,1,2}, cap 128, seed 1000+index"}
 
 
