@@ -256,6 +256,29 @@ void tally_chunk(ResultBox* b, const int32_t* si, const double* sd, uint64_t str
   }
 }
 
+// The counts and sums of count events from the integer summary fields
+// kSiStatus .. kSiEnds (field f at si0[(f - kSiStatus) * stride]) and the
+// weights w.
+void tally_fields(ResultBox* b, const int32_t* si0, uint64_t stride, const double* w, uint64_t count) {
+  vsh_result& r = b->pub;
+  for (uint64_t e = 0; e < count; ++e) {
+    const int s_ = si0[e];
+    r.n_done += s_ == kDone;
+    r.n_overflow += s_ == kOverflow;
+    r.n_nonfinite += s_ == kNonFinite;
+    r.n_conservation += s_ == kConservation;
+    r.n_cycle_limit += s_ == kCycleLimitHit;
+    r.sum_w += w[e];
+    r.sum_w2 += w[e] * w[e];
+    const uint32_t cyc = (uint32_t)si0[(kSiCycles - kSiStatus) * stride + e];
+    r.total_cycles += cyc;
+    r.max_cycles = std::max(r.max_cycles, cyc);
+    r.total_trials += (uint32_t)si0[(kSiTrials - kSiStatus) * stride + e];
+    r.total_ends += (uint32_t)si0[(kSiEnds - kSiStatus) * stride + e];
+    r.total_emissions += (uint32_t)si0[(kSiEmit - kSiStatus) * stride + e];
+  }
+}
+
 // Copy a chunk's results back through the pinned staging buffer: the
 // histogram, and either every summary field (requested summaries or records)
 // or only the fields the counts read (the weight, then the integer fields
@@ -291,25 +314,8 @@ vsh_status copy_back_chunk(vsh_ctx* ctx, hipStream_t st, const double* dev_hist,
   if (err == hipSuccess) err = hipStreamSynchronize(st);
   if (err != hipSuccess) return hip_fail(ctx, err, "result copy");
   for (int a = 0; a < kHistDoubles; ++a) box->hist[a] += hh[a];
-  vsh_result& r = box->pub;
   const int32_t* si0 = all_fields ? si + kSiStatus * stride : si;  // field kSiStatus onwards
-  const double* w = all_fields ? sd + kSdW * stride : sd;
-  for (uint64_t e = 0; e < count; ++e) {
-    const int s_ = si0[e];
-    r.n_done += s_ == kDone;
-    r.n_overflow += s_ == kOverflow;
-    r.n_nonfinite += s_ == kNonFinite;
-    r.n_conservation += s_ == kConservation;
-    r.n_cycle_limit += s_ == kCycleLimitHit;
-    r.sum_w += w[e];
-    r.sum_w2 += w[e] * w[e];
-    const uint32_t cyc = (uint32_t)si0[(kSiCycles - kSiStatus) * stride + e];
-    r.total_cycles += cyc;
-    r.max_cycles = std::max(r.max_cycles, cyc);
-    r.total_trials += (uint32_t)si0[(kSiTrials - kSiStatus) * stride + e];
-    r.total_ends += (uint32_t)si0[(kSiEnds - kSiStatus) * stride + e];
-    r.total_emissions += (uint32_t)si0[(kSiEmit - kSiStatus) * stride + e];
-  }
+  tally_fields(box, si0, stride, all_fields ? sd + kSdW * stride : sd, count);
   if (all_fields && !box->sum_d.empty()) {
     const uint64_t N = box->pub.n_events;
     for (int f = 0; f < kNSumD; ++f) std::memcpy(&box->sum_d[f * N + first_idx], &sd[f * stride], count * 8);

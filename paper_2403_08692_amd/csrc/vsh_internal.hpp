@@ -108,6 +108,7 @@ vsh_status validate_request(vsh_ctx* ctx, const vsh_request* req, bool need_ener
 ResultBox* new_result(uint64_t n_events, bool summary);
 void finish_result(ResultBox* b);
 void tally_chunk(ResultBox* b, const int32_t* si, const double* sd, uint64_t stride, uint64_t count);
+void tally_fields(ResultBox* b, const int32_t* si0, uint64_t stride, const double* w, uint64_t count);
 vsh_status copy_back_chunk(vsh_ctx* ctx, hipStream_t st, const double* dev_hist, const Summary& dev_sum,
                            uint64_t stride, uint64_t count, bool all_fields, ResultBox* box, uint64_t first_idx,
                            const int32_t** n_host);

@@ -44,9 +44,12 @@ struct Pool {
   uint64_t size = 0;
   std::map<uint64_t, uint64_t> free_;  // offset -> length
 
-  hipError_t init(uint64_t bytes) {
+  bool pinned = false;  // host memory (hipHostMalloc) instead of device memory
+
+  hipError_t init(uint64_t bytes, bool host = false) {
     size = align_up(bytes, 256);
-    hipError_t err = hipMalloc(&base, size);
+    pinned = host;
+    hipError_t err = host ? hipHostMalloc((void**)&base, size, 0) : hipMalloc(&base, size);
     if (err != hipSuccess) {
       base = nullptr;
       size = 0;
@@ -87,7 +90,7 @@ struct Pool {
     }
   }
   void destroy() {
-    if (base) (void)hipFree(base);
+    if (base) (void)(pinned ? hipHostFree(base) : hipFree(base));
     base = nullptr;
     size = 0;
     free_.clear();
@@ -108,9 +111,15 @@ struct ServeReq {
   uint64_t scheduled = 0, finished = 0;
   int inflight = 0;
   hipEvent_t drained = nullptr;
-  std::vector<double> hist, sd;
-  std::vector<int32_t> si;
-  std::vector<uint64_t> hs;
+  // the drain's copies land in pinned host memory (S.host): the histogram,
+  // then every summary field (with VSH_SUMMARY) or only the weight and the
+  // counted integer fields
+  uint64_t host_off = 0, host_bytes = 0;
+  char* own_host = nullptr;  // a staging of its own when the request outgrows the shared one
+  double* h_hist = nullptr;
+  double* h_sd = nullptr;
+  int32_t* h_si = nullptr;
+  uint64_t* h_hs = nullptr;
   ResultBox* box = nullptr;
   vsh_status fail_code = VSH_OK;  // set when the request failed (state kFailed once nothing is in flight)
   std::string fail_msg;
@@ -139,8 +148,12 @@ struct ServeState {
   std::vector<uint64_t> active;  // admitted, in admission order
   std::unordered_map<uint64_t, std::unique_ptr<ServeReq>> reqs;
   Pool pool;
+  Pool host;  // pinned host memory for the drains' copies
+  std::deque<uint64_t> to_drain;  // finished requests waiting for pinned staging
   Epoch ep[2];
   hipStream_t drain = nullptr;
+  hipStream_t admit_stream = nullptr;  // admissions' input copies and matrix elements
+  hipEvent_t admitted = nullptr;       // recorded after each admission; epochs wait on it
   char* scratch = nullptr;
   uint64_t scratch_bytes = 0;
   uint32_t fail_epochs = 0;  // testing: epochs still to report a device error without launching
@@ -152,6 +165,14 @@ static void finish_request(ServeState& S, ServeReq& r, int state) {
   if (r.pool_bytes) {
     S.pool.release(r.pool_off, r.pool_bytes);
     r.pool_bytes = 0;
+  }
+  if (r.host_bytes) {
+    S.host.release(r.host_off, r.host_bytes);
+    r.host_bytes = 0;
+  }
+  if (r.own_host) {
+    (void)hipHostFree(r.own_host);
+    r.own_host = nullptr;
   }
   if (r.drained) {
     (void)hipEventDestroy(r.drained);
@@ -195,10 +216,10 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     r.buf = carve_request(c, r.req.n_events, r.req.max_partons, false);
     const uint64_t n = r.req.n_events;
     hipError_t err = hipSuccess;
-    if (!r.ecm.empty()) err = hipMemcpyAsync(r.buf.ecm, r.ecm.data(), n * 8, hipMemcpyHostToDevice, S.drain);
+    if (!r.ecm.empty()) err = hipMemcpyAsync(r.buf.ecm, r.ecm.data(), n * 8, hipMemcpyHostToDevice, S.admit_stream);
     if (err == hipSuccess && !r.tcut.empty())
-      err = hipMemcpyAsync(r.buf.tcut, r.tcut.data(), n * 8, hipMemcpyHostToDevice, S.drain);
-    launch_zero(r.buf.hist, kHistDoubles, S.drain);
+      err = hipMemcpyAsync(r.buf.tcut, r.tcut.data(), n * 8, hipMemcpyHostToDevice, S.admit_stream);
+    launch_zero(r.buf.hist, kHistDoubles, S.admit_stream);
     EventInputs in{};
     in.ecm = r.ecm.empty() ? nullptr : r.buf.ecm;
     in.tcut = r.tcut.empty() ? nullptr : r.buf.tcut;
@@ -210,12 +231,12 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     in.t_over = r.req.t_over;
     in.qm = request_masses(r.req);
     in.massive = request_massive(r.req);
-    launch_me(r.buf.out, r.buf.sum, in, (uint32_t)n, S.drain);  // LO partons of every event
+    launch_me(r.buf.out, r.buf.sum, in, (uint32_t)n, S.admit_stream);  // LO partons of every event
     const hipError_t lerr = hipGetLastError();
     if (err == hipSuccess) err = lerr;
-    // inputs and LO events on the device before any epoch reads them
-    const hipError_t serr = hipStreamSynchronize(S.drain);
-    if (err == hipSuccess) err = serr;
+    // every later epoch waits for this event: inputs and LO events are on
+    // the device before an epoch reads them, with no host wait here
+    if (err == hipSuccess) err = hipEventRecord(S.admitted, S.admit_stream);
     r.state = kAdmitted;
     S.active.push_back(r.ticket);
     if (err != hipSuccess) fail_request(S, r, VSH_E_DEVICE, "admission", err);
@@ -307,7 +328,8 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
   Segment* sd = (Segment*)c.take(kMaxEpochReqs * sizeof(Segment));
   unsigned long long* counter = (unsigned long long*)c.take(256);
   Records slots = carve_slots(c, lanes, cap);
-  hipError_t err = hipMemcpyAsync(rd, E->reqs_host, nreq * sizeof(ReqDev), hipMemcpyHostToDevice, E->stream);
+  hipError_t err = hipStreamWaitEvent(E->stream, S.admitted, 0);
+  if (err == hipSuccess) err = hipMemcpyAsync(rd, E->reqs_host, nreq * sizeof(ReqDev), hipMemcpyHostToDevice, E->stream);
   if (err == hipSuccess) err = hipMemcpyAsync(sd, E->segs_host, nseg * sizeof(Segment), hipMemcpyHostToDevice, E->stream);
   if (err == hipSuccess) err = hipMemsetAsync(counter, 0, 8, E->stream);
   PersistArgs A;
@@ -345,9 +367,38 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
   return true;
 }
 
-static void start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
+// Start computing a finished request's observables and copying its results
+// back.  False (nothing started) while the pinned staging is full: the
+// request waits in S.to_drain.
+static bool start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
   const uint64_t n = r.req.n_events;
   const uint32_t cap = r.req.max_partons;
+  const bool all_fields = (r.req.flags & VSH_SUMMARY) != 0;
+  static_assert(kSiStatus == 1 && kSiEnds == kNSumI - 1, "the counted integer fields are the last ones");
+  const uint64_t i_fields = all_fields ? kNSumI : kNSumI - kSiStatus, d_fields = all_fields ? kNSumD : 1;
+  const uint64_t hb = align_up(kHistDoubles * 8, 256), db = align_up(d_fields * n * 8, 256),
+                 ib = align_up(i_fields * n * 4, 256), sb = all_fields ? align_up(n * 8, 256) : 0;
+  const uint64_t need_host = hb + db + ib + sb;
+  char* hbase = nullptr;
+  if (need_host > S.host.size) {  // larger than the whole shared staging: one of its own
+    if (hipHostMalloc((void**)&r.own_host, need_host, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      r.own_host = nullptr;
+      fail_request(S, r, VSH_E_NOMEM, "pinned staging of the results", hipSuccess);
+      return true;
+    }
+    hbase = r.own_host;
+  } else {
+    uint64_t off = 0;
+    if (!S.host.alloc(need_host, &off)) return false;
+    r.host_off = off;
+    r.host_bytes = need_host;
+    hbase = S.host.base + off;
+  }
+  r.h_hist = reinterpret_cast<double*>(hbase);
+  r.h_sd = reinterpret_cast<double*>(hbase + hb);
+  r.h_si = reinterpret_cast<int32_t*>(hbase + hb + db);
+  r.h_hs = all_fields ? reinterpret_cast<uint64_t*>(hbase + hb + db + ib) : nullptr;
   const uint64_t need = obs_scratch_bytes(n, cap);
   if (need > S.scratch_bytes) {
     (void)hipStreamSynchronize(S.drain);
@@ -359,7 +410,7 @@ static void start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
   }
   if (!S.scratch) {  // cannot compute its observables: fail the request
     fail_request(S, r, VSH_E_NOMEM, "observables scratch", hipSuccess);
-    return;
+    return true;
   }
   Carver c(S.scratch);
   Scratch sc = carve_scratch(c, n, cap);
@@ -375,26 +426,28 @@ static void start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
   in.qm = request_masses(r.req);
   in.massive = request_massive(r.req);
   launch_obs(r.buf.out, r.buf.sum, in, sc, (uint32_t)n, r.buf.hist, S.drain);
-  r.hist.resize(kHistDoubles);
-  r.sd.resize((size_t)kNSumD * n);
-  r.si.resize((size_t)kNSumI * n);
-  r.hs.resize(n);
   hipError_t err = hipGetLastError();
   if (err == hipSuccess)
-    err = hipMemcpyAsync(r.hist.data(), r.buf.hist, kHistDoubles * 8, hipMemcpyDeviceToHost, S.drain);
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(r.sd.data(), r.buf.sum.d, r.sd.size() * 8, hipMemcpyDeviceToHost, S.drain);
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(r.si.data(), r.buf.sum.i, r.si.size() * 4, hipMemcpyDeviceToHost, S.drain);
-  if (err == hipSuccess) err = hipMemcpyAsync(r.hs.data(), r.buf.sum.hash, n * 8, hipMemcpyDeviceToHost, S.drain);
+    err = hipMemcpyAsync(r.h_hist, r.buf.hist, kHistDoubles * 8, hipMemcpyDeviceToHost, S.drain);
+  if (all_fields) {
+    if (err == hipSuccess) err = hipMemcpyAsync(r.h_sd, r.buf.sum.d, kNSumD * n * 8, hipMemcpyDeviceToHost, S.drain);
+    if (err == hipSuccess) err = hipMemcpyAsync(r.h_si, r.buf.sum.i, kNSumI * n * 4, hipMemcpyDeviceToHost, S.drain);
+    if (err == hipSuccess) err = hipMemcpyAsync(r.h_hs, r.buf.sum.hash, n * 8, hipMemcpyDeviceToHost, S.drain);
+  } else {
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(r.h_sd, r.buf.sum.d + kSdW * n, n * 8, hipMemcpyDeviceToHost, S.drain);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(r.h_si, r.buf.sum.i + kSiStatus * n, i_fields * n * 4, hipMemcpyDeviceToHost, S.drain);
+  }
   if (err == hipSuccess) err = hipEventCreateWithFlags(&r.drained, hipEventDisableTiming);
   if (err == hipSuccess) err = hipEventRecord(r.drained, S.drain);
   if (err != hipSuccess) {
     fail_request(S, r, VSH_E_DEVICE, "observables launch", err);
-    return;
+    return true;
   }
   r.state = kDraining;
   (void)ctx;
+  return true;
 }
 
 static bool retire_epochs(vsh_ctx* ctx, ServeState& S) {
@@ -415,7 +468,7 @@ static bool retire_epochs(vsh_ctx* ctx, ServeState& S) {
         if (r.inflight == 0 && r.state == kAdmitted)
           finish_request(S, r, r.fail_code != VSH_OK ? kFailed : kCancelledState);
       } else if (r.finished == r.req.n_events) {
-        start_drain(ctx, S, r);
+        if (!start_drain(ctx, S, r)) S.to_drain.push_back(r.ticket);
       }
     }
     E.parts.clear();
@@ -445,21 +498,36 @@ static bool poll_drains(ServeState& S) {
     const uint64_t n = r.req.n_events;
     ResultBox* box = new_result(n, r.req.flags & VSH_SUMMARY);
     if (box) {
-      box->hist = r.hist;
-      tally_chunk(box, r.si.data(), r.sd.data(), n, n);
+      box->hist.assign(r.h_hist, r.h_hist + kHistDoubles);
+      const bool all_fields = r.h_hs != nullptr;
+      tally_fields(box, all_fields ? r.h_si + kSiStatus * n : r.h_si, n, all_fields ? r.h_sd + kSdW * n : r.h_sd, n);
       if (!box->sum_d.empty()) {
-        box->sum_d = r.sd;
-        box->sum_i = r.si;
-        box->hash = r.hs;
+        std::memcpy(box->sum_d.data(), r.h_sd, kNSumD * n * 8);
+        std::memcpy(box->sum_i.data(), r.h_si, kNSumI * n * 4);
+        std::memcpy(box->hash.data(), r.h_hs, n * 8);
       }
       box->pub.t_total_ms = std::chrono::duration<double, std::milli>(Clock::now() - r.t_arrival).count();
       finish_result(box);
     }
     r.box = box;
-    std::vector<double>().swap(r.sd);
-    std::vector<int32_t>().swap(r.si);
-    std::vector<uint64_t>().swap(r.hs);
     finish_request(S, r, kFinished);
+    progress = true;
+  }
+  return progress;
+}
+
+// Start the drains that waited for pinned staging, oldest first.
+static bool retry_drains(vsh_ctx* ctx, ServeState& S) {
+  bool progress = false;
+  while (!S.to_drain.empty()) {
+    auto it = S.reqs.find(S.to_drain.front());
+    if (it == S.reqs.end() || it->second->state != kAdmitted || it->second->cancel) {
+      S.to_drain.pop_front();  // gone, cancelled or failed meanwhile
+      progress = true;
+      continue;
+    }
+    if (!start_drain(ctx, S, *it->second)) break;  // still full
+    S.to_drain.pop_front();
     progress = true;
   }
   return progress;
@@ -474,6 +542,7 @@ static void serve_loop(vsh_ctx* ctx) {
     progress |= admit(ctx, S);
     progress |= retire_epochs(ctx, S);
     progress |= poll_drains(S);
+    progress |= retry_drains(ctx, S);
     while (launch_epoch(ctx, S)) progress = true;
     if (!progress) S.cv.wait_for(lk, std::chrono::microseconds(100));
   }
@@ -485,7 +554,11 @@ static vsh_status serve_start(vsh_ctx* ctx) {
   const uint64_t pool_bytes = std::min<uint64_t>(ctx->budget / 2, 32ull << 30);
   hipError_t err = S->pool.init(pool_bytes);
   if (err != hipSuccess) return hip_fail(ctx, err, "serving pool");
+  err = S->host.init(1ull << 30, true);
+  if (err != hipSuccess) return hip_fail(ctx, err, "serving pinned staging");
   err = hipStreamCreateWithFlags(&S->drain, hipStreamNonBlocking);
+  if (err == hipSuccess) err = hipStreamCreateWithFlags(&S->admit_stream, hipStreamNonBlocking);
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&S->admitted, hipEventDisableTiming);
   if (err != hipSuccess) return hip_fail(ctx, err, "hipStreamCreate");
   for (auto& E : S->ep) {
     err = hipStreamCreateWithFlags(&E.stream, hipStreamNonBlocking);
@@ -512,9 +585,11 @@ void serve_shutdown(vsh_ctx* ctx) {
     if (E.stream) (void)hipStreamSynchronize(E.stream);
   }
   if (S->drain) (void)hipStreamSynchronize(S->drain);
+  if (S->admit_stream) (void)hipStreamSynchronize(S->admit_stream);
   for (auto& kv : S->reqs) {
     ServeReq& r = *kv.second;
     if (r.drained) (void)hipEventDestroy(r.drained);
+    if (r.own_host) (void)hipHostFree(r.own_host);
     if (r.box) vsh_result_free(&r.box->pub);
   }
   for (auto& E : S->ep) {
@@ -526,7 +601,10 @@ void serve_shutdown(vsh_ctx* ctx) {
   }
   if (S->scratch) (void)hipFree(S->scratch);
   if (S->drain) (void)hipStreamDestroy(S->drain);
+  if (S->admitted) (void)hipEventDestroy(S->admitted);
+  if (S->admit_stream) (void)hipStreamDestroy(S->admit_stream);
   S->pool.destroy();
+  S->host.destroy();
   delete S;
   ctx->serve = nullptr;
 }
