@@ -520,6 +520,13 @@ def main():
                                "plain": time_form(ctx, P, torch, st_w, st_w.n_events, "plain", 3)}
         tuned = ctx.autotune(1 << 18, seed=1, max_partons=128, ecm=91.2, t_cut=1.0)
         extra["serving"] = serving_bench(ctx, args.serving_requests, 200.0)
+        # latency against offered load: the same trace statistics at higher arrival rates (2 s of arrivals each)
+        sweep = []
+        for rate in (1000.0, 2000.0, 4000.0):
+            sv = serving_bench(ctx, int(2 * rate), rate)
+            sv.pop("trace")
+            sweep.append(sv)
+        extra["serving_load"] = sweep
         line["extra"] = extra
         line["serving_p50_ms"] = extra["serving"]["p50_ms"]
         line["serving_p99_ms"] = extra["serving"]["p99_ms"]
