@@ -144,16 +144,17 @@ def traffic_from_profile(kernel, workload, kernel_src_hash):
 
 
 def kernel_source_hash():
-    """sha256 over the sources the shower kernels are compiled from (every
-    device header and vsh_persistent.hip, which defines them): a committed
+    """sha256 over the sources the shower kernels are compiled from (the
+    device headers and vsh_persistent.hip, which defines them): a committed
     counter summary counts only while the kernels are the ones it measured.
-    Host-only files (the C ABI, the serving loop, the tuner) do not enter."""
+    Host-only files (the C ABI, the serving loop, the tuner, and
+    vsh_internal.hpp, the host-side context and layouts) do not enter."""
     import hashlib
 
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2403_08692_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith(".hpp") or f == "vsh_persistent.hip":
+        if (f.endswith(".hpp") and f != "vsh_internal.hpp") or f == "vsh_persistent.hip":
             h.update(f.encode())
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()
