@@ -306,6 +306,15 @@ def validate(p, ecm):
     return lib().or_validate(n, _ptr(p, _dp), float(ecm))
 
 
+def validate_massive(p, pid, ecm, mass):
+    """Status of a finished event whose partons may carry quark masses
+    (mass: six doubles indexed by flavour, or None for massless)."""
+    p, n = _as_p(p)
+    f = np.ascontiguousarray(pid, np.intc)
+    assert len(f) == n
+    return lib().or_validate_massive(n, _ptr(p, _dp), _ptr(f, _ip), float(ecm), _ptr(_mass_table(mass), _dp))
+
+
 def observables(p, ecm):
     p, n = _as_p(p)
     o = np.zeros(7)

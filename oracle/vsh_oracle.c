@@ -927,9 +927,13 @@ void or_hemispheres(int n, const double *p, const double axis[3], double s,
   *b_w = bp > bm ? bp : bm;
 }
 
-/* Validate: every component finite; total four-momentum equal to
-   (ecm, 0, 0, 0) within 1e-10 ecm per component; every parton on its mass
-   shell (massless unless the table gives its flavour a mass) within 1e-10 s. */
+/* Validate (Table 1, "Validate Events"; the criterion is not printed, this is
+   the reading taken): every component finite; the total four-momentum equal
+   to (ecm, 0, 0, 0) within 1e-10 ecm per component; every parton on its mass
+   shell (massless unless the table gives its flavour a mass) within
+   1e-10 s.  Finiteness is checked first, so an event with a non-finite
+   component is NONFINITE whatever else is wrong with it.  pid may be NULL
+   when mass is NULL (every parton massless). */
 int or_validate_massive(int n, const double *p, const int *pid, double ecm, const double *mass) {
   double tot[4] = {0, 0, 0, 0};
   for (int a = 0; a < 4 * n; ++a)
@@ -940,25 +944,13 @@ int or_validate_massive(int n, const double *p, const int *pid, double ecm, cons
   if (fabs(tot[0] - ecm) > tol || fabs(tot[1]) > tol || fabs(tot[2]) > tol || fabs(tot[3]) > tol)
     return OR_CONSERVATION;
   for (int a = 0; a < n; ++a) {
-    double m = flavour_mass(mass, pid[a]);
+    double m = mass ? flavour_mass(mass, pid[a]) : 0.0;
     if (fabs(mdot(&p[4 * a], &p[4 * a]) - m * m) > 1e-10 * ecm * ecm) return OR_CONSERVATION;
   }
   return OR_DONE;
 }
 
-int or_validate(int n, const double *p, double ecm) {
-  double tot[4] = {0, 0, 0, 0};
-  for (int a = 0; a < 4 * n; ++a)
-    if (!isfinite(p[a])) return OR_NONFINITE;
-  for (int a = 0; a < n; ++a)
-    for (int c = 0; c < 4; ++c) tot[c] += p[4 * a + c];
-  double tol = 1e-10 * ecm;
-  if (fabs(tot[0] - ecm) > tol || fabs(tot[1]) > tol || fabs(tot[2]) > tol || fabs(tot[3]) > tol)
-    return OR_CONSERVATION;
-  for (int a = 0; a < n; ++a)
-    if (fabs(mdot(&p[4 * a], &p[4 * a])) > 1e-10 * ecm * ecm) return OR_CONSERVATION;
-  return OR_DONE;
-}
+int or_validate(int n, const double *p, double ecm) { return or_validate_massive(n, p, NULL, ecm, NULL); }
 
 /* obs = {y23, y34, tau = 1 - T, C, rho_H, B_T, B_W} */
 void or_observables(int n, const double *p, double ecm, double obs[7]) {

@@ -11,8 +11,13 @@ Bars (written here, used by every GPU parity test):
     density, each from the same kinematics as the momenta, so it gets the
     momenta's bar; observables to 1e-9 relative or 1e-12
     absolute (they are computed from momenta that agree to ~1e-15);
-  * histograms: chi^2/ndf < 1.5 over filled bins, with the entry counts
-    per bin allowed to differ only by events that differ.
+  * histograms: per observable and bin, the entry counts are equal except
+    for events that differ or whose observable lies within 1e-9 (in units of
+    the histogram's range) of a bin edge, where the two sides' roundings may
+    bin it differently: each such event may move one entry between its two
+    bins.  The GPU's entry counts are also exactly those of binning its own
+    per-event observables (the same edge allowance).  Weighted sums: chi^2/ndf
+    < 1.5 over filled bins.
 Where the shower compares floating-point trial scales (the winner, the veto),
 both sides decide in FP64; the GPU compares ln t, the oracle t, so a decision
 can flip only when two values agree to the last few bits.
@@ -75,7 +80,77 @@ def compare(gpu: dict, orc: dict, ecm, n: int, records: bool = True):
     rep = dict(n=n, identical=int(same.sum()), frac=float(frac), mom_err=float(mom_err), w_err=float(w_err),
                obs_bad=obs_bad)
     rep.update(hist_chi2(gpu["hist"], orc["hist"]))
+    rep.update(entry_check(gpu, orc, same))
     return rep, same
+
+
+# histogram ranges (reading R24): log10 y23, log10 y34, tau, C, rho_H, B_T,
+# B_W, cos(theta); 50 uniform bins [lo, hi) plus underflow and overflow
+HIST_LO = np.array([-4.3, -4.3, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0])
+HIST_HI = np.array([-0.3, -0.3, 0.5, 1.0, 0.5, 0.5, 0.35, 1.0])
+NBINS = 50
+EDGE_TOL = 1e-9
+
+
+def binned_values(sd):
+    """The eight histogrammed values per event from summaries [10][n]."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        l23 = np.where(sd[2] > 0, np.log10(np.where(sd[2] > 0, sd[2], 1.0)), -np.inf)
+        l34 = np.where(sd[3] > 0, np.log10(np.where(sd[3] > 0, sd[3], 1.0)), -np.inf)
+    return np.stack([l23, l34, sd[4], sd[5], sd[6], sd[7], sd[8], sd[1]])
+
+
+def bin_index(x, h):
+    """Bin of each value of observable h: 0 underflow, 1..50, 51 overflow
+    (NaN to overflow)."""
+    lo, hi = HIST_LO[h], HIST_HI[h]
+    with np.errstate(invalid="ignore"):
+        inner = np.minimum(1 + np.floor((x - lo) / (hi - lo) * NBINS), NBINS)
+        b = np.where(x < lo, 0, np.where(x >= hi, NBINS + 1, inner))
+    return np.where(np.isnan(x), NBINS + 1, b).astype(np.int64)
+
+
+def near_edge(x, h):
+    lo, hi = HIST_LO[h], HIST_HI[h]
+    u = (x - lo) / (hi - lo) * NBINS
+    with np.errstate(invalid="ignore"):
+        return np.isfinite(u) & (np.abs(u - np.round(u)) < EDGE_TOL * NBINS) & (u > -0.5) & (u < NBINS + 0.5)
+
+
+def entry_check(gpu, orc, same):
+    """Largest excess of a per-bin entry-count difference over what differing
+    and edge events allow: GPU against oracle, and GPU against binning its own
+    summaries.  Both must be <= 0."""
+    gd, od = gpu["sum_d"], orc["sum_d"].T
+    g_done = gpu["sum_i"][1] == 1
+    o_done = orc["sum_i"][:, 1] == 1
+    gv, ov = binned_values(gd), binned_values(od)
+    worst_o, worst_self = -np.inf, -np.inf
+    def counts(b, sel, spread):
+        c = np.bincount(b[sel], minlength=NBINS + 2).astype(np.float64)
+        if spread:  # an edge value may land in either neighbour
+            c = c + np.concatenate([[0.0], c[:-1]]) + np.concatenate([c[1:], [0.0]])
+        return c
+
+    # the summary field behind each histogram (log10 y is binned from y)
+    field = [2, 3, 4, 5, 6, 7, 8, 1]
+    for h in range(8):
+        gb, ob = bin_index(gv[h], h), bin_index(ov[h], h)
+        # equal values are binned identically by the same arithmetic on both
+        # sides; values that differ in their last bits may not be, near an edge
+        edge = (near_edge(gv[h], h) | near_edge(ov[h], h)) & (gd[field[h]] != od[field[h]])
+        differ = ~same
+        slack = (counts(gb, differ & g_done, False) + counts(ob, differ & o_done, False)
+                 + counts(gb, edge & same & g_done, True) + counts(ob, edge & same & o_done, True))
+        diff = np.abs(gpu["hist"][h, :, 2] - orc["hist"][h, :, 2])
+        worst_o = max(worst_o, float((diff - slack).max()))
+        own = counts(gb, g_done, False)
+        # the device's log10 and numpy's may round differently: only log10 y
+        # values next to an edge may bin differently from the GPU's own fill
+        own_edge = near_edge(gv[h], h) if h < 2 else np.zeros_like(g_done)
+        own_slack = counts(gb, g_done & own_edge, True)
+        worst_self = max(worst_self, float((np.abs(gpu["hist"][h, :, 2] - own) - own_slack).max()))
+    return dict(entry_excess=worst_o, entry_self_excess=worst_self)
 
 
 def hist_chi2(hg, ho):
@@ -96,3 +171,5 @@ def assert_parity(rep):
     assert rep["w_err"] <= W_RTOL, rep
     assert rep["obs_bad"] == 0, rep
     assert rep["chi2_ndf"] < 1.5, rep
+    assert rep["entry_excess"] <= 0, rep
+    assert rep["entry_self_excess"] <= 0, rep

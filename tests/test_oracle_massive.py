@@ -225,6 +225,51 @@ def test_massive_map_dalitz_jacobian(oracle, name, mi, mj, mk, mij):
         assert jac == pytest.approx(qb2 * qb2 * (1 - y), rel=1e-6)
 
 
+@pytest.mark.parametrize("name,mi,mj,mk,mij", CASES)
+def test_massive_map_at_the_phase_space_edge(oracle, name, mi, mj, mk, mij):
+    """At the edges of the Dalitz region the map's transverse momentum squared
+    (lower edge in t) or the Kallen function of the rescaled spectator (upper
+    edge, with a massive spectator; y -> 1 without one) reaches zero, and a
+    rounding can take it just below.  The reading: the map then takes it as
+    zero, the value at the edge.  Just outside the edge (by one bisection step
+    in t) the momenta are finite, conserve the dipole's momentum, sit on
+    their mass shells and agree with those just inside."""
+    rng = np.random.default_rng(10)
+    K = 0 if mij > 0 else 11
+    for _ in range(20):
+        Q2 = rng.uniform(30, 60) ** 2
+        pij, pk = _pair(rng, Q2, mij, mk)
+        qb2 = Q2 - mi * mi - mj * mj - mk * mk
+        z = rng.uniform(0.2, 0.8)
+        t_of = lambda y: y * qb2 * z * (1 - z) - (1 - z) ** 2 * mi * mi - z * z * mj * mj
+        inside = lambda t: oracle.massive_ratio(K, t, z, Q2, mi, mj, mk, 1.0) >= 0.0
+        t_in = t_of(0.3)
+        assert inside(t_in)
+        # below the lower edge, and above the upper one where a massive
+        # spectator bounds it (without a spectator mass the upper edge is
+        # y = 1, where the spectator's momentum vanishes and the map's p_k
+        # coefficient diverges; the (1 - y) factor gives it no weight)
+        for y_out in ((-1.0, 1.5) if mk > 0 else (-1.0,)):
+            lo, hi = t_in, t_of(y_out)
+            assert not inside(hi)
+            for _ in range(200):  # bisect to the edge: lo inside, hi outside
+                mid = 0.5 * (lo + hi)
+                if mid == lo or mid == hi:
+                    break
+                lo, hi = (mid, hi) if inside(mid) else (lo, mid)
+            phi = rng.uniform(0, 2 * np.pi)
+            a_in = oracle.split_kinematics_massive(pij, pk, mi, mj, mk, mij, lo, z, phi)
+            a_out = oracle.split_kinematics_massive(pij, pk, mi, mj, mk, mij, hi, z, phi)
+            sc = np.sqrt(Q2)
+            for v_in, v_out, m in zip(a_in, a_out, (mi, mj, mk)):
+                assert np.all(np.isfinite(v_out))
+                assert mdot(v_out, v_out) == pytest.approx(m * m, abs=1e-9 * Q2)
+                # continuous across the edge (the spectator's rescaling goes
+                # as the square root of the Kallen function there)
+                np.testing.assert_allclose(v_out, v_in, atol=1e-4 * sc)
+            np.testing.assert_allclose(sum(a_out), pij + pk, atol=1e-12 * sc)
+
+
 def test_massive_map_reduces_to_the_massless_one(oracle):
     rng = np.random.default_rng(9)
     for _ in range(200):

@@ -13,7 +13,10 @@ emission probability at sqrt(s) = 6 GeV, t_C = 4 GeV^2, about 3 standard
 deviations of the near-threshold pin.  A wider range only costs efficiency
 (the veto's y < 1 trims it to the true phase space).  For the same reason
 the massive z range taken without the spectator mass (a wider range) only
-costs efficiency.
+costs efficiency.  The massive map's clamp of the Kallen function at zero is
+no mutant either: where it would act, the map's p_k coefficient (which
+divides by that function) has no finite value anyway, and the phase-space
+factor gives that edge no weight.
 """
 import concurrent.futures as cf
 import os
@@ -26,7 +29,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "vsh_oracle.c")
 PINS = ["tests/test_oracle_rng.py", "tests/test_oracle_physics.py", "tests/test_oracle_shower.py",
-        "tests/test_oracle_observables.py", "tests/test_oracle_massive.py"]
+        "tests/test_oracle_observables.py", "tests/test_oracle_massive.py", "tests/test_oracle_validation.py"]
 
 # (name, text in vsh_oracle.c, replacement)
 MUTANTS = [
@@ -96,6 +99,20 @@ MUTANTS = [
      "if (fabs(mdot(&p[4 * a], &p[4 * a])) > 1e-10 * ecm * ecm)"),
     ("heavy-jet mass as the lighter hemisphere", "double rho = (mp > mm ? mp : mm) / s;",
      "double rho = (mp < mm ? mp : mm) / s;"),
+    ("validation always DONE", "  double tot[4] = {0, 0, 0, 0};\n  for (int a = 0; a < 4 * n; ++a)",
+     "  return OR_DONE;\n  double tot[4] = {0, 0, 0, 0};\n  for (int a = 0; a < 4 * n; ++a)"),
+    ("validation tolerance not scaled by sqrt(s)", "double tol = 1e-10 * ecm;", "double tol = 1e-10;"),
+    ("validation tolerance scaled by s", "double tol = 1e-10 * ecm;", "double tol = 1e-10 * ecm * ecm;"),
+    ("validation: massless partons' shells unchecked",
+     "if (fabs(mdot(&p[4 * a], &p[4 * a]) - m * m) > 1e-10 * ecm * ecm)",
+     "if (m > 0.0 && fabs(mdot(&p[4 * a], &p[4 * a]) - m * m) > 1e-10 * ecm * ecm)"),
+    ("validation: a non-finite component reported as non-conservation", "if (!isfinite(p[a])) return OR_NONFINITE;",
+     "if (!isfinite(p[a])) return OR_CONSERVATION;"),
+    ("q->qg soft term without y", "if (K < 10) return CF * (2.0 / (1.0 - z * (1.0 - y)) - (1.0 + z));",
+     "if (K < 10) return CF * (2.0 / (1.0 - z) - (1.0 + z));"),
+    ("g->gg soft term without y", "if (K == 10) return 0.5 * CA * (2.0 / (1.0 - z * (1.0 - y))",
+     "if (K == 10) return 0.5 * CA * (2.0 / (1.0 - z)"),
+    ("massive map: kT^2 not clamped at the edge", "double kt = sqrt(k2 > 0.0 ? k2 : 0.0)", "double kt = sqrt(k2)"),
 ]
 
 

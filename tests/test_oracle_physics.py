@@ -24,6 +24,16 @@ def golden(kind):
 MZ = 91.1876
 
 
+def test_golden_file_is_the_scripts_output():
+    """The committed closed-form and quadrature values are exactly what the
+    script next to them writes (numpy and scipy only, no oracle)."""
+    import subprocess
+    import sys
+
+    script = os.path.join(os.path.dirname(GOLDEN), "make_derived_physics.py")
+    assert subprocess.run([sys.executable, script, "--check"], timeout=300).returncode == 0
+
+
 def test_alpha_s_values(oracle):
     for t, ref in golden("alpha_s"):
         assert oracle.alpha_s(t) == pytest.approx(ref, abs=1.5e-6)
@@ -64,6 +74,49 @@ def test_kernels_collinear_limit_is_dglap(oracle):
         for K in range(11, 16):
             qq = lambda x: 2 * oracle.kernel_value(K, x, 0.0)
             assert 0.5 * (qq(z) + qq(1 - z)) == pytest.approx(TR * (z * z + (1 - z) ** 2), rel=1e-13)
+
+
+def _mdot(a, b):
+    return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3]
+
+
+def _null(rng, e):
+    u = rng.normal(size=3)
+    return np.array([e, *(e * u / np.linalg.norm(u))])
+
+
+def _end_vars(pe, pj, ps):
+    """(z, y) of the end with emitter pe, emission pj, spectator ps from the
+    final momenta (the inverse of the dipole map): y = pe.pj / (pe.pj + pe.ps
+    + pj.ps), z = pe.ps / (pe.ps + pj.ps)."""
+    ej, es, js = _mdot(pe, pj), _mdot(pe, ps), _mdot(pj, ps)
+    return es / (es + js), ej / (ej + es + js)
+
+
+@pytest.mark.parametrize("lam", [1e-3, 1e-4, 1e-5])
+def test_soft_limit_of_two_ends_is_eikonal(oracle, lam):
+    """A soft gluon j radiated inside the colour dipole (i, k): the two ends'
+    dipole terms V_{ij,k}/(p_i.p_j) + V_{kj,i}/(p_k.p_j) add up to the
+    eikonal factor C 2 p_i.p_k / ((p_i.p_j)(p_j.p_k)), C = C_F for a quark
+    dipole (two q -> q g ends) and C_A/2 for a dipole between two gluons (two
+    g -> g g ends, as for a soft gluon between the gluons of a q g g qbar
+    chain): the soft limit of the QCD matrix element that the kernels must
+    reproduce away from y = 0, which the collinear pin does not reach.
+    Corrections are of relative order lambda."""
+    rng = np.random.default_rng(int(1 / lam))
+    for _ in range(200):
+        pi, pk = _null(rng, rng.uniform(10, 45)), _null(rng, rng.uniform(10, 45))
+        pj = _null(rng, lam * 45.0)
+        # the expansion parameter is p_j.p_k / p_i.p_k (and i <-> k): keep the
+        # dipole wide open, 1 - cos(theta_ik) > 1/2
+        if _mdot(pi, pk) < 0.5 * pi[0] * pk[0]:
+            continue
+        eik = 2 * _mdot(pi, pk) / (_mdot(pi, pj) * _mdot(pj, pk))
+        zi, yi = _end_vars(pi, pj, pk)
+        zk, yk = _end_vars(pk, pj, pi)
+        for K_i, K_k, C in [(0, 5, CF), (3, 8, CF), (10, 10, CA / 2)]:
+            d = oracle.kernel_value(K_i, zi, yi) / _mdot(pi, pj) + oracle.kernel_value(K_k, zk, yk) / _mdot(pk, pj)
+            assert d / (C * eik) == pytest.approx(1.0, abs=60 * lam), (K_i, K_k)
 
 
 def test_overestimates_bound_kernels(oracle):
