@@ -303,7 +303,10 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
     int status = sm.i[kSiStatus * sm.stride + e];
     const int np = sm.i[kSiN * sm.stride + e];
     const double ecm = in.ecm_of(e), sh = ecm * ecm;
-    double tE = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, bad = 0.0, sum = 0.0;
+    // nonfin: partons with a non-finite component; offshell: finite partons
+    // off their mass shell (kept apart: one non-finite parton makes the
+    // event NONFINITE, any number of finite off-shell ones CONSERVATION)
+    double tE = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, nonfin = 0.0, offshell = 0.0, sum = 0.0;
     double mxx = 0.0, myy = 0.0, mzz = 0.0, mxy = 0.0, mxz = 0.0, myz = 0.0;
     for (int a = lane; a < np; a += G) {
       const uint64_t o = (uint64_t)a * r.stride + e;
@@ -312,8 +315,8 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
       px[a] = p.x;
       py[a] = p.y;
       pz[a] = p.z;
-      if (!(isfinite(p.e) && isfinite(p.x) && isfinite(p.y) && isfinite(p.z))) bad += 2.0;
-      else if (!(fabs(mdot(p, p) - shell2<kMassive>(in, r, a, e)) <= 1e-10 * sh)) bad += 1.0;
+      if (!(isfinite(p.e) && isfinite(p.x) && isfinite(p.y) && isfinite(p.z))) nonfin += 1.0;
+      else if (!(fabs(mdot(p, p) - shell2<kMassive>(in, r, a, e)) <= 1e-10 * sh)) offshell += 1.0;
       tE += p.e;
       tx += p.x;
       ty += p.y;
@@ -332,11 +335,12 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
     tx = group_sum<G>(tx);
     ty = group_sum<G>(ty);
     tz = group_sum<G>(tz);
-    bad = group_sum<G>(bad);
+    nonfin = group_sum<G>(nonfin);
+    offshell = group_sum<G>(offshell);
     if (status == kDone) {
       const double tol = 1e-10 * ecm;
-      if (bad >= 2.0) status = kNonFinite;
-      else if (fabs(tE - ecm) > tol || fabs(tx) > tol || fabs(ty) > tol || fabs(tz) > tol || bad > 0.0)
+      if (nonfin > 0.0) status = kNonFinite;
+      else if (fabs(tE - ecm) > tol || fabs(tx) > tol || fabs(ty) > tol || fabs(tz) > tol || offshell > 0.0)
         status = kConservation;
     }
     double v[7] = {0, 0, 0, 0, 0, 0, 0};

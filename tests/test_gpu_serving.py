@@ -151,3 +151,47 @@ def test_poll_reports_completion(ctx):
         assert time.time() - t0 < 60
         time.sleep(0.001)
     assert ctx.wait(t)["n_done"] == 20_000
+
+
+def test_served_in_mix_equal_the_oracle(ctx, oracle):
+    """Requests served in a mix, each compared with the oracle directly:
+    every per-event field (parity bar of tests/parity.py, histogram entry
+    counts included) with summaries; without summaries (the drain that copies
+    only the weight and the counted fields, as the benchmark's trace runs)
+    the histogram, sum_w and the totals, against the same request with
+    summaries and against the oracle."""
+    from paper_2403_08692_amd.workloads import serving_trace
+    from tests import parity
+
+    trace = serving_trace(30, min_log10_n=2.0, max_log10_n=3.4, master_seed=77)
+    picked = trace.requests[:8]
+    filler = [ctx.submit(r.n_events, seed=r.seed, ecm=r.ecm, t_cut=r.tcut, max_partons=r.cap)
+              for r in trace.requests[8:]]
+    with_sum = {r.index: ctx.submit(r.n_events, seed=r.seed, ecm=r.ecm, t_cut=r.tcut, max_partons=r.cap,
+                                    summary=True) for r in picked}
+    without = {r.index: ctx.submit(r.n_events, seed=r.seed, ecm=r.ecm, t_cut=r.tcut, max_partons=r.cap,
+                                   summary=False) for r in picked}
+    for r in picked:
+        print(f"case served request {r.index} n={r.n_events} ecm={r.ecm} tcut={r.tcut}", flush=True)
+        a, b = ctx.wait(with_sum[r.index]), ctx.wait(without[r.index])
+        o = oracle.generate(r.seed, 0, r.n_events, r.ecm, r.tcut, r.cap)
+        rep, same = parity.compare(a, o, r.ecm, r.n_events, records=False)
+        parity.assert_parity(rep)
+        assert same.all(), rep
+        oi, od = o["sum_i"], o["sum_d"]
+        for res in (a, b):
+            assert res["n_done"] == int((oi[:, 1] == 1).sum())
+            assert res["n_overflow"] == int((oi[:, 1] == 2).sum())
+            assert res["total_cycles"] == int(oi[:, 2].sum())
+            assert res["total_emissions"] == int(oi[:, 3].sum())
+            assert res["total_trials"] == int(oi[:, 5].sum())
+            assert res["total_ends"] == int(oi[:, 6].sum())
+            assert res["max_cycles"] == int(oi[:, 2].max())
+            assert res["sum_w"] == pytest.approx(od[:, 0].sum(), rel=1e-12)
+            assert res["sum_w2"] == pytest.approx((od[:, 0] ** 2).sum(), rel=1e-12)
+        # without summaries: the same histogram (entry counts exactly) as with them
+        np.testing.assert_array_equal(b["hist"][..., 2], a["hist"][..., 2])
+        np.testing.assert_allclose(b["hist"], a["hist"], rtol=1e-11, atol=1e-9)
+        assert "sum_d" not in b
+    for t in filler:
+        ctx.wait(t)
