@@ -100,6 +100,22 @@ enum {
                                       events evolving in their output records           */
 #define VSH_INPUTS_ON_DEVICE 0x8u  /* ecm_per_event / tcut_per_event are device pointers
                                       (vsh_generate_into only)                          */
+#define VSH_HIST_FIXEDPOINT 0x10u  /* histogram sums in int64 fixed point, so that they do
+                                      not depend on the order in which events are added
+                                      (the atomic histogramming of Sec. 3.2 / Table 1,
+                                      made order-independent): sum w is accumulated as
+                                      integers in units of 2^-fw with 2^(62 - fw) above
+                                      n |w|max (n the events of the request, |w|max the
+                                      largest event weight), sum w^2 likewise, and both
+                                      converted to FP64 once at the end.  The result is
+                                      then the same bits served alone, served in a mix,
+                                      through vsh_generate in either form or
+                                      vsh_generate_into, whenever the request is
+                                      processed in one piece (vsh_generate splits only
+                                      requests larger than its memory budget; each
+                                      piece then has its own scale).  The sums are
+                                      within 2^-(62 - ceil(log2 n)) |w|max per event of
+                                      the FP64 ones.  Weights must be finite.          */
 
 typedef struct vsh_ctx vsh_ctx; /* device arena, stream, kernel cache, serving state */
 
@@ -220,6 +236,7 @@ vsh_status vsh_generate_into(vsh_ctx *ctx, const vsh_request *req, void *stream,
                              int32_t *dev_sum_i, uint64_t *dev_hash);
 /* Workspace bytes vsh_generate_into needs for req (0 on invalid input). */
 uint64_t vsh_workspace_size(const vsh_request *req);
+
 
 /* Stage timing of vsh_generate_into.  After vsh_timing_start, each
    vsh_generate_into call (at most VSH_TIMING_MAX_CALLS) records HIP events on

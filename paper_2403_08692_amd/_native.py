@@ -22,6 +22,7 @@ VSH_RECORDS = 0x2
 VSH_FORM_PLAIN = 0x0
 VSH_FORM_PERSISTENT = 0x4
 VSH_INPUTS_ON_DEVICE = 0x8
+VSH_HIST_FIXEDPOINT = 0x10
 NOBS, NBINS = 8, 50
 NHCOL = NBINS + 2
 HIST_DOUBLES = NOBS * NHCOL * 3
@@ -238,9 +239,9 @@ class Context:
 
     def generate(self, n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=64,
                  summary=True, records=False, persistent=False, ecm_per_event=None, tcut_per_event=None,
-                 cycle_limit=0, t_over=0.0, mass_c=0.0, mass_b=0.0):
+                 cycle_limit=0, t_over=0.0, mass_c=0.0, mass_b=0.0, fixed_hist=False):
         flags = (VSH_SUMMARY if summary else 0) | (VSH_RECORDS if records else 0) | \
-                (VSH_FORM_PERSISTENT if persistent else 0)
+                (VSH_FORM_PERSISTENT if persistent else 0) | (VSH_HIST_FIXEDPOINT if fixed_hist else 0)
         req, keep = make_request(n_events, seed, first_event, ecm, t_cut, max_partons, flags,
                                  ecm_per_event, tcut_per_event, cycle_limit, t_over, mass_c, mass_b)
         res = C.POINTER(vsh_result)()
@@ -310,8 +311,9 @@ class Context:
         return np.array(buf[:3 * n.value], np.float64).reshape(n.value, 3)
 
     def submit(self, n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_partons=128, summary=False,
-               ecm_per_event=None, tcut_per_event=None, cycle_limit=0, t_over=0.0, mass_c=0.0, mass_b=0.0):
-        flags = VSH_SUMMARY if summary else 0
+               ecm_per_event=None, tcut_per_event=None, cycle_limit=0, t_over=0.0, mass_c=0.0, mass_b=0.0,
+               fixed_hist=False):
+        flags = (VSH_SUMMARY if summary else 0) | (VSH_HIST_FIXEDPOINT if fixed_hist else 0)
         req, keep = make_request(n_events, seed, first_event, ecm, t_cut, max_partons, flags,
                                  ecm_per_event, tcut_per_event, cycle_limit, t_over, mass_c, mass_b)
         t = C.c_uint64()

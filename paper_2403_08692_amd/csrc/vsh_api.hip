@@ -54,7 +54,7 @@ vsh_status validate_request(vsh_ctx* ctx, const vsh_request* req, bool need_ener
     set_error(ctx, "max_partons must be in 2..%u (got %u)", kMaxCap, req->max_partons);
     return VSH_E_INVALID;
   }
-  const uint32_t known = VSH_SUMMARY | VSH_RECORDS | VSH_FORM_PERSISTENT | VSH_INPUTS_ON_DEVICE;
+  const uint32_t known = VSH_SUMMARY | VSH_RECORDS | VSH_FORM_PERSISTENT | VSH_INPUTS_ON_DEVICE | VSH_HIST_FIXEDPOINT;
   if (req->flags & ~known) {
     set_error(ctx, "unknown request flags 0x%x", req->flags & ~known);
     return VSH_E_INVALID;
@@ -425,6 +425,7 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
   in.t_over = req->t_over;
   in.qm = request_masses(*req);
   in.massive = request_massive(*req);
+  in.fixed_hist = (req->flags & VSH_HIST_FIXEDPOINT) ? 1u : 0u;
   in.ecm0 = req->ecm;
   in.tcut0 = req->t_cut;
   const bool from_records = caller_offsets != nullptr;
@@ -519,8 +520,8 @@ uint64_t chunk_events(vsh_ctx* ctx, const vsh_request* req) {
   // leave room for the record-gather buffer when records are returned
   if (req->flags & VSH_RECORDS) budget = budget / 2;
   uint64_t n = budget / (per + 64);
-  n = std::min<uint64_t>(n, req->n_events);
   n = std::min<uint64_t>(n, 1ull << 26);
+  if (n >= req->n_events) return req->n_events;  // the whole request in one piece
   return n & ~63ull ? n & ~63ull : n;
 }
 
@@ -569,6 +570,58 @@ hipEvent_t* timing_slot(vsh_ctx* ctx) {
   }
   return &ctx->timing_ev[4 * (size_t)ctx->timing_calls++];
 }
+
+// The plain-form launch sequence of vsh_generate_into on stream st with the
+// workspace at `ws` (at least vsh_workspace_size bytes; nothing in it needs
+// to start at zero): matrix element, shower, observables and histogram
+// accumulated into dev_hist, then the summaries copied out in the caller's
+// [field][n_events] layout.  `timed`: record the stage events of
+// vsh_timing_start.  Launches and device-to-device copies only.
+vsh_status plain_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void* ws, double* dev_hist,
+                      double* dev_sum_d, int32_t* dev_sum_i, uint64_t* dev_hash, bool timed) {
+  const uint64_t n = req->n_events;
+  const uint64_t stride = align_up(n, 64);
+  PlainLayout L = carve_plain(ws, stride, req->max_partons, request_massive(*req) != 0);
+  EventInputs in{};
+  in.seed = req->seed;
+  in.first = req->first_event;
+  in.cycle_limit = effective_cycle_limit(req->cycle_limit);
+  in.t_over = req->t_over;
+  in.qm = request_masses(*req);
+  in.massive = request_massive(*req);
+  in.fixed_hist = (req->flags & VSH_HIST_FIXEDPOINT) ? 1u : 0u;
+  in.ecm0 = req->ecm;
+  in.tcut0 = req->t_cut;
+  in.ecm = req->ecm_per_event;
+  in.tcut = req->tcut_per_event;
+  Summary sum = L.sum;
+  hipEvent_t* tev = timed ? timing_slot(ctx) : nullptr;
+  if (tev) (void)hipEventRecord(tev[0], st);
+  launch_me(L.rec, sum, in, (uint32_t)n, st);
+  if (tev) (void)hipEventRecord(tev[1], st);
+  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, sum, in, (uint32_t)n, L.cache, st);
+  else launch_shower_plain(L.rec, sum, in, (uint32_t)n, ctx->tuned.plain_block, ctx->tuned.plain_waves, st);
+  if (tev) (void)hipEventRecord(tev[2], st);
+  launch_obs(L.rec, sum, in, L.sc, (uint32_t)n, dev_hist, st);
+  if (tev) (void)hipEventRecord(tev[3], st);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return hip_fail(ctx, err, "kernel launch");
+  // summaries out, in the caller's [field][n_events] layout
+  if (dev_sum_d) {
+    err = hipMemcpy2DAsync(dev_sum_d, n * 8, sum.d, stride * 8, n * 8, kNSumD, hipMemcpyDeviceToDevice, st);
+    if (err != hipSuccess) return hip_fail(ctx, err, "summary copy");
+  }
+  if (dev_sum_i) {
+    err = hipMemcpy2DAsync(dev_sum_i, n * 4, sum.i, stride * 4, n * 4, kNSumI, hipMemcpyDeviceToDevice, st);
+    if (err != hipSuccess) return hip_fail(ctx, err, "summary copy");
+  }
+  if (dev_hash) {
+    err = hipMemcpyAsync(dev_hash, sum.hash, n * 8, hipMemcpyDeviceToDevice, st);
+    if (err != hipSuccess) return hip_fail(ctx, err, "summary copy");
+  }
+  return VSH_OK;
+}
+
 
 }  // namespace vsh
 
@@ -771,46 +824,7 @@ vsh_status vsh_generate_into(vsh_ctx* ctx, const vsh_request* req, void* stream,
   hipStream_t st = (hipStream_t)stream;
   if (req->flags & VSH_FORM_PERSISTENT)
     return persistent_into(ctx, req, st, workspace, dev_hist, dev_sum_d, dev_sum_i, dev_hash);
-  const uint64_t n = req->n_events;
-  const uint64_t stride = align_up(n, 64);
-  PlainLayout L = carve_plain(workspace, stride, req->max_partons, request_massive(*req) != 0);
-  EventInputs in{};
-  in.seed = req->seed;
-  in.first = req->first_event;
-  in.cycle_limit = effective_cycle_limit(req->cycle_limit);
-  in.t_over = req->t_over;
-  in.qm = request_masses(*req);
-  in.massive = request_massive(*req);
-  in.ecm0 = req->ecm;
-  in.tcut0 = req->t_cut;
-  in.ecm = req->ecm_per_event;
-  in.tcut = req->tcut_per_event;
-  Summary sum = L.sum;
-  hipEvent_t* tev = timing_slot(ctx);
-  if (tev) (void)hipEventRecord(tev[0], st);
-  launch_me(L.rec, sum, in, (uint32_t)n, st);
-  if (tev) (void)hipEventRecord(tev[1], st);
-  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, sum, in, (uint32_t)n, L.cache, st);
-  else launch_shower_plain(L.rec, sum, in, (uint32_t)n, ctx->tuned.plain_block, ctx->tuned.plain_waves, st);
-  if (tev) (void)hipEventRecord(tev[2], st);
-  launch_obs(L.rec, sum, in, L.sc, (uint32_t)n, dev_hist, st);
-  if (tev) (void)hipEventRecord(tev[3], st);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return hip_fail(ctx, err, "kernel launch");
-  // summaries out, in the caller's [field][n_events] layout
-  if (dev_sum_d) {
-    err = hipMemcpy2DAsync(dev_sum_d, n * 8, sum.d, stride * 8, n * 8, kNSumD, hipMemcpyDeviceToDevice, st);
-    if (err != hipSuccess) return hip_fail(ctx, err, "summary copy");
-  }
-  if (dev_sum_i) {
-    err = hipMemcpy2DAsync(dev_sum_i, n * 4, sum.i, stride * 4, n * 4, kNSumI, hipMemcpyDeviceToDevice, st);
-    if (err != hipSuccess) return hip_fail(ctx, err, "summary copy");
-  }
-  if (dev_hash) {
-    err = hipMemcpyAsync(dev_hash, sum.hash, n * 8, hipMemcpyDeviceToDevice, st);
-    if (err != hipSuccess) return hip_fail(ctx, err, "summary copy");
-  }
-  return VSH_OK;
+  return plain_into(ctx, req, st, workspace, dev_hist, dev_sum_d, dev_sum_i, dev_hash, true);
 }
 
 vsh_status vsh_timing_start(vsh_ctx* ctx) {

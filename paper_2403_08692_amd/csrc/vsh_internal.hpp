@@ -135,6 +135,9 @@ vsh_status persistent_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st,
                            double* dev_hist, double* dev_sum_d, int32_t* dev_sum_i,
                            uint64_t* dev_hash);
 
+vsh_status plain_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void* ws, double* dev_hist,
+                      double* dev_sum_d, int32_t* dev_sum_i, uint64_t* dev_hash, bool timed);
+
 // serving (vsh_serve.hip)
 void serve_shutdown(vsh_ctx* ctx);
 

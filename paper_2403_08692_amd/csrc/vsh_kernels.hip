@@ -78,20 +78,49 @@ __global__ void k_zero_u32(uint32_t* p, uint32_t n) {
   if (i < n) p[i] = 0u;
 }
 
-// Per-block counts in LDS, one global atomic per non-empty count per block.
-__global__ void __launch_bounds__(256) k_obs_count(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt) {
+// Zero the counting sort's counters and, for fixed-point histograms, the
+// integer cells and the largest-weight word (a kernel, not a memset, so the
+// sequence can be captured in a graph).
+__global__ void k_obs_reset(uint32_t* cnt, uint32_t nb, unsigned long long* ihist, unsigned long long* wmax) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) cnt[i] = 0u;
+  if (ihist && i < (uint32_t)kHistDoubles) ihist[i] = 0ull;
+  if (wmax && i == 0) *wmax = 0ull;
+}
+
+// Per-block counts in LDS, one global atomic per non-empty count per block;
+// with wmax, also the largest |w| of the events (the bits of non-negative
+// doubles order like the integers, so the maximum does not depend on order).
+__global__ void __launch_bounds__(256) k_obs_count(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt,
+                                                   unsigned long long* wmax) {
   __shared__ uint32_t lc[kMaxCount + 1];
+  __shared__ unsigned long long lw;
   const uint32_t nb = cap + 1;
   for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) lc[k] = 0u;
+  if (threadIdx.x == 0) lw = 0ull;
   __syncthreads();
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) {
     const uint32_t np = (uint32_t)sm.i[kSiN * sm.stride + e];
     atomicAdd(&lc[cap - (np < cap ? np : cap)], 1u);
+    if (wmax) atomicMax(&lw, (unsigned long long)__double_as_longlong(fabs(sm.d[kSdW * sm.stride + e])));
   }
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x)
     if (lc[k]) atomicAdd(&cnt[k], lc[k]);
+  if (wmax && threadIdx.x == 0 && lw) atomicMax(wmax, lw);
+}
+
+// Fixed-point cells into the FP64 histogram (accumulated): sum w and sum w^2
+// scaled back by their powers of two, entries as they are.  The integer sums
+// do not depend on the order of the events, so neither does the result.
+__global__ void __launch_bounds__(256) k_hist_fixed_finalize(Scratch sc, double* hist) {
+  const FixScale fx = fix_scale(sc);
+  for (uint32_t a = threadIdx.x; a < (uint32_t)kHistDoubles; a += blockDim.x) {
+    const double q = (double)(long long)sc.ihist[a];
+    const int col = (int)(a % 3);
+    hist[a] += col == 0 ? ldexp(q, -fx.fw) : (col == 1 ? ldexp(q, -fx.fw2) : q);
+  }
 }
 
 // exclusive prefix sum of nb counters, in place (one block)
@@ -147,6 +176,10 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
                                              double* __restrict__ hist) {
   __shared__ double lh[kHistDoubles];
   for (int a = threadIdx.x; a < kHistDoubles; a += blockDim.x) lh[a] = 0.0;
+  const bool fixed = in.fixed_hist != 0;
+  FixScale fxs{0, 0};
+  if (fixed) fxs = fix_scale(sc);
+  const FixScale* fx = fixed ? &fxs : nullptr;
   __syncthreads();
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
@@ -182,7 +215,7 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
     if (ok) {
       const int status = sm.i[kSiStatus * sm.stride + e];
       const ObsOut o = reg_observables<kObsRegSlots, kMassive>(r, e, np, wmax, in.ecm_of(e), status, in);
-      if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
+      if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e], fx);
       for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
       sm.i[kSiStatus * sm.stride + e] = o.status;
     }
@@ -201,15 +234,12 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
       sc.z[to] = r.z[from];
     }
     const ObsOut o = scratch_observables<kMassive>(sc, t, np, in.ecm_of(e), status, in, r, e);
-    if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
+    if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e], fx);
     for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
     sm.i[kSiStatus * sm.stride + e] = o.status;
   }
   __syncthreads();
-  for (int a = threadIdx.x; a < kHistDoubles; a += blockDim.x) {
-    const double v = lh[a];
-    if (v != 0.0) unsafeAtomicAdd(&hist[a], v);
-  }
+  hist_flush(lh, hist, sc, fixed, threadIdx.x, blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -279,7 +309,7 @@ struct PairWalk {
 template <int G, int MV, bool kMassive>
 __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventInputs in, const uint32_t* perm,
                                                   const uint32_t* cnt, uint32_t cap, uint32_t lo_n, uint32_t hi_n,
-                                                  uint32_t slots, double* __restrict__ hist) {
+                                                  uint32_t slots, double* __restrict__ hist, Scratch sc) {
   constexpr uint32_t kGroups = 64 / G;
   constexpr uint64_t kGroupBits = G == 64 ? ~0ull : ((1ull << (G % 64)) - 1ull);
   extern __shared__ double lds[];
@@ -294,6 +324,10 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
   double* uz = uy + slots;
   uint16_t* list = (uint16_t*)(lh + kHistDoubles + (size_t)kGroups * 7 * slots) + (size_t)grp * slots;
   for (int a = threadIdx.x; a < kHistDoubles; a += 64) lh[a] = 0.0;
+  const bool fixed = in.fixed_hist != 0;
+  FixScale fxs{0, 0};
+  if (fixed) fxs = fix_scale(sc);
+  const FixScale* fx = fixed ? &fxs : nullptr;
   // cnt[cap - m] counts the events with at least m partons (see k_obs)
   const uint32_t q_lo = hi_n <= cap ? cnt[cap - hi_n] : 0u;
   const uint32_t q_hi = lo_n <= cap ? cnt[cap - lo_n] : 0u;
@@ -471,7 +505,7 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
         --m;
       }
       if (lane == 0) hist_fill_lds(lh, ObsOut{{v[0], v[1], v[2], v[3], v[4], v[5], v[6]}, status},
-                                   sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e]);
+                                   sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e], fx);
     }
 #pragma unroll
     for (uint32_t h = 0; h < 7; ++h)  // the group's lanes share the seven stores
@@ -479,10 +513,7 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
     if (lane == 0) sm.i[kSiStatus * sm.stride + e] = status;
   }
   __syncthreads();
-  for (int a = threadIdx.x; a < kHistDoubles; a += 64) {
-    const double val = lh[a];
-    if (val != 0.0) unsafeAtomicAdd(&hist[a], val);
-  }
+  hist_flush(lh, hist, sc, fixed, threadIdx.x, 64);
 }
 
 // The group launches for records of capacity cap: 16 lanes from
@@ -560,7 +591,8 @@ static inline uint64_t al256(uint64_t v) { return (v + 255) / 256 * 256; }
 
 uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap) {
   const uint64_t m = obs_threads(n, cap) * thread_slots(cap);
-  return 8 * al256(m * 8) + al256(m * 2) + al256(m) + al256(n * 4) + al256((cap + 2) * 4) + 256;
+  return 8 * al256(m * 8) + al256(m * 2) + al256(m) + al256(n * 4) + al256((cap + 2) * 4) +
+         al256(kHistDoubles * 8) + al256(8) + 256;
 }
 
 Scratch carve_obs_scratch(char*& p, uint64_t n, uint32_t cap) {
@@ -584,6 +616,10 @@ Scratch carve_obs_scratch(char*& p, uint64_t n, uint32_t cap) {
   s.dead = (uint8_t*)take(m);
   s.perm = (uint32_t*)take(n * 4);
   s.cnt = (uint32_t*)take((cap + 2) * 4);
+  s.ihist = (unsigned long long*)take(kHistDoubles * 8);
+  s.wmax = (unsigned long long*)take(8);
+  s.lbits = 0;
+  while ((1ull << s.lbits) < n) ++s.lbits;
   // events with at least `threshold` partons go to one wave each (LDS holds
   // up to kObsWaveMaxCap partons); smaller ones to one thread each
   s.threshold = cap <= kObsWaveMaxCap ? kObsWaveThreshold : 0xFFFFFFFFu;
@@ -594,8 +630,12 @@ void launch_obs(const Records& r, const Summary& s, const EventInputs& in, const
                 uint32_t n, double* hist, hipStream_t st) {
   if (!n) return;
   const uint32_t nb = r.cap + 1;
-  hipLaunchKernelGGL(k_zero_u32, dim3((nb + 255) / 256), dim3(256), 0, st, sc.cnt, nb);
-  hipLaunchKernelGGL(k_obs_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, n, r.cap, sc.cnt);
+  const bool fixed = in.fixed_hist != 0;
+  unsigned long long* ih = fixed ? sc.ihist : nullptr;
+  unsigned long long* wm = fixed ? sc.wmax : nullptr;
+  hipLaunchKernelGGL(k_obs_reset, dim3((std::max<uint32_t>(nb, kHistDoubles) + 255) / 256), dim3(256), 0, st, sc.cnt,
+                     nb, ih, wm);
+  hipLaunchKernelGGL(k_obs_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, n, r.cap, sc.cnt, wm);
   hipLaunchKernelGGL(k_obs_scan, dim3(1), dim3(256), 0, st, sc.cnt, nb);
   hipLaunchKernelGGL(k_obs_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, n, r.cap, sc.cnt, sc.perm);
   const uint32_t blocks = (uint32_t)(std::min<uint64_t>(sc.stride, ((uint64_t)n + 255) / 256 * 256) / 256);
@@ -612,9 +652,11 @@ void launch_obs(const Records& r, const Summary& s, const EventInputs& in, const
     Summary ss = s;
     EventInputs ii = in;
     double* hh = hist;
-    void* args[] = {&rr, &ss, &ii, &perm, &cnt, &cap, &lo, &hi, &slots, &hh};
+    Scratch sc2 = sc;
+    void* args[] = {&rr, &ss, &ii, &perm, &cnt, &cap, &lo, &hi, &slots, &hh, &sc2};
     (void)hipLaunchKernel(gl[k].fn, dim3(wb), dim3(64), args, gl[k].lds, st);
   }
+  if (fixed) hipLaunchKernelGGL(k_hist_fixed_finalize, dim3(1), dim3(256), 0, st, sc, hist);
 }
 
 

@@ -68,6 +68,7 @@ struct EventInputs {
   double t_over;         // scale of alpha_s in the trial density, 0 = the event's t_C
   QuarkMasses qm;        // quark masses (massive kernels only when `massive`)
   uint32_t massive;      // any quark mass above zero
+  uint32_t fixed_hist;   // histogram sums in int64 fixed point (order-independent)
   __device__ __forceinline__ double ecm_of(uint64_t e) const { return ecm ? ecm[e] : ecm0; }
   __device__ __forceinline__ double tcut_of(uint64_t e) const { return tcut ? tcut[e] : tcut0; }
 };
@@ -90,6 +91,12 @@ struct Scratch {
   uint32_t *perm;           // event indices by decreasing parton count [n]
   uint32_t *cnt;            // per-count offsets [cap + 2]
   uint32_t threshold;       // events with at least this many partons: one wave each
+  // fixed-point histogram (requests with VSH_HIST_FIXEDPOINT): the cells'
+  // int64 sums, the largest |w| of the launch's events (as the bits of a
+  // non-negative double, which order like the integers) and L = ceil(log2 n)
+  unsigned long long *ihist;  // [kHistDoubles]
+  unsigned long long *wmax;   // [1]
+  uint32_t lbits;
 };
 
 constexpr uint32_t kObsWaveThreshold = 9;
@@ -108,7 +115,9 @@ uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap);
 Scratch carve_obs_scratch(char*& p, uint64_t n, uint32_t cap);
 // k_obs for requests without (false) or with (true) quark masses
 const void* obs_kernel(bool massive);
-__global__ void k_obs_count(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt);
+__global__ void k_obs_count(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt, unsigned long long* wmax);
+__global__ void k_obs_reset(uint32_t* cnt, uint32_t nb, unsigned long long* ihist, unsigned long long* wmax);
+__global__ void k_hist_fixed_finalize(Scratch sc, double* hist);
 __global__ void k_obs_scan(uint32_t* cnt, uint32_t nb);
 __global__ void k_obs_scatter(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt, uint32_t* perm);
 __global__ void k_zero_u32(uint32_t* p, uint32_t n);

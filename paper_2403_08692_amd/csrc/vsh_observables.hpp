@@ -475,20 +475,65 @@ __device__ __forceinline__ double hist_hi(int h) {
   return h < 2 ? -0.3 : (h == 3 ? 1.0 : (h == 6 ? 0.35 : (h == 7 ? 1.0 : 0.5)));
 }
 
-// Fill one event into an LDS histogram set [kNObs][kNHCol][3].
-__device__ __forceinline__ void hist_fill_lds(double* lh, const ObsOut& o, double w, double cos_theta) {
+// Scales of the fixed-point histogram: a weight w is held as the integer
+// nearest to w 2^fw, w^2 as the one nearest to w^2 2^fw2, with 2^e above
+// the launch's largest |w| and L = ceil(log2 n), so that no sum over the
+// launch's n events leaves [-2^62, 2^62].
+struct FixScale {
+  int fw, fw2;
+};
+
+__device__ __forceinline__ FixScale fix_scale(const Scratch& sc) {
+  const double m = __longlong_as_double((long long)*sc.wmax);
+  int e = 0;
+  (void)frexp(m, &e);  // m < 2^e (e = 0 for m = 0)
+  return FixScale{62 - (int)sc.lbits - e, 62 - (int)sc.lbits - 2 * e};
+}
+
+// Fill one event into an LDS histogram set [kNObs][kNHCol][3]: FP64 sums,
+// or (fx non-null) the fixed-point sums of fix_scale in the same LDS words.
+__device__ __forceinline__ void hist_fill_lds(double* lh, const ObsOut& o, double w, double cos_theta,
+                                              const FixScale* fx = nullptr) {
   double vals[kNObs];
   vals[0] = o.v[0] > 0.0 ? log10(o.v[0]) : -INFINITY;
   vals[1] = o.v[1] > 0.0 ? log10(o.v[1]) : -INFINITY;
   for (int h = 2; h < 7; ++h) vals[h] = o.v[h];
   vals[7] = cos_theta;
+  unsigned long long qw = 0, qw2 = 0;
+  if (fx) {
+    qw = (unsigned long long)llrint(ldexp(w, fx->fw));
+    qw2 = (unsigned long long)llrint(ldexp(w * w, fx->fw2));
+  }
 #pragma unroll
   for (int h = 0; h < kNObs; ++h) {
     const int b = bin_of(vals[h], hist_lo(h), hist_hi(h));
     double* cell = &lh[3 * (kNHCol * h + b)];
-    atomicAdd(&cell[0], w);
-    atomicAdd(&cell[1], w * w);
-    atomicAdd(&cell[2], 1.0);
+    if (fx) {
+      unsigned long long* ic = reinterpret_cast<unsigned long long*>(cell);
+      atomicAdd(&ic[0], qw);
+      atomicAdd(&ic[1], qw2);
+      atomicAdd(&ic[2], 1ull);
+    } else {
+      atomicAdd(&cell[0], w);
+      atomicAdd(&cell[1], w * w);
+      atomicAdd(&cell[2], 1.0);
+    }
+  }
+}
+
+// One LDS histogram set into the global one: FP64 atomics, or integer
+// atomics into the fixed-point cells (sc.ihist).
+__device__ __forceinline__ void hist_flush(const double* lh, double* hist, const Scratch& sc, bool fixed,
+                                           uint32_t t0, uint32_t step) {
+  const unsigned long long* lq = reinterpret_cast<const unsigned long long*>(lh);
+  for (uint32_t a = t0; a < (uint32_t)kHistDoubles; a += step) {
+    if (fixed) {
+      const unsigned long long q = lq[a];  // integer words: never read as doubles
+      if (q) atomicAdd(&sc.ihist[a], q);
+    } else {
+      const double v = lh[a];
+      if (v != 0.0) unsafeAtomicAdd(&hist[a], v);
+    }
   }
 }
 

@@ -945,10 +945,14 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   GCHK(add_event(2));
   g.nb = L.buf.out.cap + 1;
   g.cap = L.buf.out.cap;
-  void* a_zero[] = {&g.sc.cnt, &g.nb};
-  GCHK(add_kernel((const void*)k_zero_u32, dim3((g.nb + 255) / 256), dim3(256), a_zero));
+  const bool fixed = g.in.fixed_hist != 0;
+  g.ih = fixed ? g.sc.ihist : nullptr;
+  g.wm = fixed ? g.sc.wmax : nullptr;
+  void* a_zero[] = {&g.sc.cnt, &g.nb, &g.ih, &g.wm};
+  GCHK(add_kernel((const void*)k_obs_reset, dim3((std::max<uint32_t>(g.nb, kHistDoubles) + 255) / 256), dim3(256),
+                  a_zero));
   const uint32_t eb = (uint32_t)((n + 255) / 256);
-  void* a_count[] = {&g.sum, &g.n, &g.cap, &g.sc.cnt};
+  void* a_count[] = {&g.sum, &g.n, &g.cap, &g.sc.cnt, &g.wm};
   GCHK(add_kernel((const void*)k_obs_count, dim3(eb), dim3(256), a_count));
   void* a_scan[] = {&g.sc.cnt, &g.nb};
   GCHK(add_kernel((const void*)k_obs_scan, dim3(1), dim3(256), a_scan));
@@ -965,9 +969,14 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
     g.glo[k] = gl[k].lo;
     g.ghi[k] = gl[k].hi;
     g.gslots[k] = gl[k].slots;
-    void* a_grp[] = {&g.rec, &g.sum, &g.in, &g.perm_c, &g.cnt_c, &g.cap, &g.glo[k], &g.ghi[k], &g.gslots[k], &g.hist};
+    void* a_grp[] = {&g.rec, &g.sum, &g.in, &g.perm_c, &g.cnt_c, &g.cap, &g.glo[k], &g.ghi[k], &g.gslots[k], &g.hist,
+                     &g.sc};
     const uint32_t wb = (uint32_t)std::min<uint64_t>(n, kObsWaveBlocks);
     GCHK(add_kernel(gl[k].fn, dim3(wb), dim3(64), a_grp, gl[k].lds));
+  }
+  if (fixed) {
+    void* a_fin[] = {&g.sc, &g.hist};
+    GCHK(add_kernel((const void*)k_hist_fixed_finalize, dim3(1), dim3(256), a_fin));
   }
   GCHK(add_event(3));
   GCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
@@ -1042,6 +1051,7 @@ vsh_status run_batch(vsh_ctx* ctx, const vsh_request* req, uint64_t first_idx, u
   in.t_over = req->t_over;
   in.qm = request_masses(*req);
   in.massive = request_massive(*req);
+  in.fixed_hist = (req->flags & VSH_HIST_FIXEDPOINT) ? 1u : 0u;
   hipEvent_t* tev = timing_slot(ctx);
   if (use_graph) {
     BatchGraph& g = ctx->graph;
@@ -1177,6 +1187,7 @@ vsh_status generate_persistent(vsh_ctx* ctx, const vsh_request* req, vsh_result*
     in.t_over = req->t_over;
     in.qm = request_masses(*req);
     in.massive = request_massive(*req);
+    in.fixed_hist = (req->flags & VSH_HIST_FIXEDPOINT) ? 1u : 0u;
     launch_me(L.buf.out, L.buf.sum, in, (uint32_t)n, st);
     A.slots = L.buf.out;  // in place
     A.reqs = L.reqs;

@@ -101,6 +101,8 @@ struct BatchGraph {
   const uint32_t* perm_c = nullptr;
   const uint32_t* cnt_c = nullptr;
   double* hist = nullptr;
+  unsigned long long* ih = nullptr;  // fixed-point cells and largest weight (null: FP64 sums)
+  unsigned long long* wm = nullptr;
   uint64_t lanes = 0;
   uint32_t block = 0;
   uint32_t mapping = 0;

@@ -231,6 +231,7 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     in.t_over = r.req.t_over;
     in.qm = request_masses(r.req);
     in.massive = request_massive(r.req);
+    in.fixed_hist = (r.req.flags & VSH_HIST_FIXEDPOINT) ? 1u : 0u;
     launch_me(r.buf.out, r.buf.sum, in, (uint32_t)n, S.admit_stream);  // LO partons of every event
     const hipError_t lerr = hipGetLastError();
     if (err == hipSuccess) err = lerr;
@@ -425,6 +426,7 @@ static bool start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
   in.t_over = r.req.t_over;
   in.qm = request_masses(r.req);
   in.massive = request_massive(r.req);
+  in.fixed_hist = (r.req.flags & VSH_HIST_FIXEDPOINT) ? 1u : 0u;
   launch_obs(r.buf.out, r.buf.sum, in, sc, (uint32_t)n, r.buf.hist, S.drain);
   hipError_t err = hipGetLastError();
   if (err == hipSuccess)

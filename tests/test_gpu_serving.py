@@ -195,3 +195,50 @@ def test_served_in_mix_equal_the_oracle(ctx, oracle):
         assert "sum_d" not in b
     for t in filler:
         ctx.wait(t)
+
+
+@pytest.mark.parametrize("ecm,tcut,cap,n", [(91.2, 1.0, 128, 20_000), (500.0, 0.25, 256, 4_000)])
+def test_fixed_point_histograms_are_the_same_bits_everywhere(ctx, oracle, ecm, tcut, cap, n):
+    """VSH_HIST_FIXEDPOINT: the histogram of a request is the same bits from
+    vsh_generate in both forms, from vsh_generate_into in both forms, served
+    alone and served in a mix; it equals the FP64 one to rounding (entry
+    counts exactly), and passes the parity bar against the oracle."""
+    import torch
+
+    import paper_2403_08692_amd as P
+    from paper_2403_08692_amd._native import make_request
+
+    kw = dict(seed=555, ecm=ecm, t_cut=tcut, max_partons=cap)
+    print(f"case fixed-point histograms ecm={ecm} n={n}", flush=True)
+    ref = ctx.generate(n, summary=True, fixed_hist=True, **kw)
+    hists = {"generate plain": ref["hist"],
+             "generate persistent": ctx.generate(n, summary=False, persistent=True, fixed_hist=True, **kw)["hist"]}
+    alone = ctx.wait(ctx.submit(n, fixed_hist=True, **kw))
+    hists["served alone"] = alone["hist"]
+    others = [ctx.submit(3000 + 500 * k, seed=900 + k, ecm=[10.0, 200.0, 500.0][k % 3], t_cut=0.5, max_partons=256)
+              for k in range(6)]
+    mixed = ctx.submit(n, fixed_hist=True, summary=True, **kw)
+    more = [ctx.submit(2000, seed=950 + k, ecm=35.0, t_cut=1.0, max_partons=128) for k in range(6)]
+    hists["served in a mix"] = ctx.wait(mixed)["hist"]
+    for t in others + more:
+        ctx.wait(t)
+    dev = torch.device("cuda:0")
+    for form in (P.VSH_FORM_PLAIN, P.VSH_FORM_PERSISTENT):
+        req, keep = make_request(n, 555, 0, ecm, tcut, cap, form | P.VSH_HIST_FIXEDPOINT)
+        ws_bytes = ctx.workspace_size(req)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        h = torch.zeros(P.HIST_DOUBLES, dtype=torch.float64, device=dev)
+        ctx.generate_into(req, torch.cuda.current_stream(dev).cuda_stream, ws.data_ptr(), ws_bytes, h.data_ptr())
+        torch.cuda.synchronize()
+        hists[f"generate_into form {form}"] = h.cpu().numpy().reshape(P.NOBS, P.NHCOL, 3)
+        del ws
+    for name, h in hists.items():
+        assert np.array_equal(h, ref["hist"]), name
+    fp = ctx.generate(n, summary=False, **kw)["hist"]
+    np.testing.assert_array_equal(fp[..., 2], ref["hist"][..., 2])
+    np.testing.assert_allclose(fp, ref["hist"], rtol=1e-11, atol=1e-9)
+    from tests import parity
+
+    o = oracle.generate(555, 0, n, ecm, tcut, cap)
+    rep, same = parity.compare(ref, o, ecm, n, records=False)
+    parity.assert_parity(rep)
