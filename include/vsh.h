@@ -237,6 +237,25 @@ vsh_status vsh_generate_into(vsh_ctx *ctx, const vsh_request *req, void *stream,
 /* Workspace bytes vsh_generate_into needs for req (0 on invalid input). */
 uint64_t vsh_workspace_size(const vsh_request *req);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, serving loops that must not call hipMalloc, harnesses that forbid
+   it): vsh_generate_into in the plain form, with its workspace in a device
+   array the library owns instead of a caller buffer.  The array holds
+   VSH_STATIC_SCRATCH_BYTES (64 MiB: about 10^4 LEP events at 64 partons;
+   vsh_workspace_size(req) must not exceed it); every device that runs the
+   library holds its own copy until the process ends.  The call allocates
+   nothing (no hipMalloc, no pinned memory, no library allocation), only
+   enqueues kernels and device-to-device copies on `stream`, and returns.
+   Arguments, outputs and per-event inputs as for vsh_generate_into.
+   All calls on one device share that device's array and nothing in it needs
+   to start at zero, but calls whose work overlaps on one device (two host
+   threads, or two streams without an ordering between them) race on it:
+   order them on one stream.
+   Errors: those of vsh_generate_into; VSH_E_INVALID for VSH_FORM_PERSISTENT
+   or VSH_RECORDS; VSH_E_NOMEM when the request needs more than the array. */
+#define VSH_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+vsh_status vsh_generate_into_static(vsh_ctx *ctx, const vsh_request *req, void *stream, double *dev_hist,
+                                    double *dev_sum_d, int32_t *dev_sum_i, uint64_t *dev_hash);
 
 /* Stage timing of vsh_generate_into.  After vsh_timing_start, each
    vsh_generate_into call (at most VSH_TIMING_MAX_CALLS) records HIP events on

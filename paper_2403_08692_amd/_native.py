@@ -27,6 +27,7 @@ NOBS, NBINS = 8, 50
 NHCOL = NBINS + 2
 HIST_DOUBLES = NOBS * NHCOL * 3
 NSUM_D, NSUM_I = 10, 7
+STATIC_SCRATCH_BYTES = 64 * 1024 * 1024  # VSH_STATIC_SCRATCH_BYTES
 EV_DONE, EV_OVERFLOW, EV_NONFINITE, EV_CONSERVATION = 1, 2, 3, 4
 
 
@@ -103,6 +104,8 @@ def load():
     L.vsh_shower_records.restype = C.c_int
     L.vsh_generate_into.argtypes = [P, C.POINTER(vsh_request), P, P, C.c_uint64, P, P, P, P]
     L.vsh_generate_into.restype = C.c_int
+    L.vsh_generate_into_static.argtypes = [P, C.POINTER(vsh_request), P, P, P, P, P]
+    L.vsh_generate_into_static.restype = C.c_int
     L.vsh_workspace_size.argtypes = [C.POINTER(vsh_request)]
     L.vsh_workspace_size.restype = C.c_uint64
     L.vsh_submit.argtypes = [P, C.POINTER(vsh_request), C.POINTER(C.c_uint64)]
@@ -132,7 +135,7 @@ def load():
 EXPORTS = ["vsh_create", "vsh_destroy", "vsh_last_error", "vsh_generate", "vsh_result_free",
            "vsh_shower_records", "vsh_generate_into", "vsh_workspace_size", "vsh_submit", "vsh_poll",
            "vsh_wait", "vsh_cancel", "vsh_timing_start", "vsh_timing_read", "vsh_get_tuning", "vsh_set_tuning",
-           "vsh_autotune", "vsh_test_fail_epochs"]
+           "vsh_autotune", "vsh_test_fail_epochs", "vsh_generate_into_static"]
 
 
 class VshError(RuntimeError):
@@ -278,6 +281,13 @@ class Context:
         """All buffer arguments are integer device addresses; stream a hipStream_t address."""
         _check(load().vsh_generate_into(self._ptr, C.byref(req), stream, workspace, int(workspace_bytes),
                                         dev_hist, dev_sum_d, dev_sum_i, dev_hash), self._ptr)
+
+    def generate_into_static(self, req, stream, dev_hist, dev_sum_d=None, dev_sum_i=None, dev_hash=None):
+        """vsh_generate_into_static: the plain form with the library's own
+        static device workspace (no allocation).  Buffer arguments are
+        integer device addresses; stream a hipStream_t address."""
+        _check(load().vsh_generate_into_static(self._ptr, C.byref(req), stream, dev_hist, dev_sum_d, dev_sum_i,
+                                               dev_hash), self._ptr)
 
     def get_tuning(self):
         t = vsh_tuning()

@@ -689,6 +689,10 @@ vsh_status vsh_create(const vsh_ctx_opts* opts, vsh_ctx** out) {
       return hip_fail(nullptr, err, "hipEventCreate");
     }
   }
+  // the static workspace's address on this device (vsh_generate_into_static
+  // looks it up itself if this fails; nothing else depends on it)
+  (void)static_scratch_init(ctx);
+  ctx->error.clear();
   *out = ctx;
   return VSH_OK;
 }

@@ -84,6 +84,7 @@ struct vsh_ctx {
   std::mutex mu;
   std::string error;
   vsh::ServeState* serve = nullptr;  // owned; torn down by serve_shutdown
+  void* static_scratch = nullptr;    // device address of the static workspace on this device
   // stage timing of vsh_generate_into: 4 events per call
   bool timing = false;
   uint32_t timing_calls = 0;
@@ -137,6 +138,10 @@ vsh_status persistent_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st,
 
 vsh_status plain_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void* ws, double* dev_hist,
                       double* dev_sum_d, int32_t* dev_sum_i, uint64_t* dev_hash, bool timed);
+
+// the library-owned workspace of vsh_generate_into_static (vsh_noalloc.hip):
+// its device address on the current device, looked up once per device
+vsh_status static_scratch_init(vsh_ctx* ctx);
 
 // serving (vsh_serve.hip)
 void serve_shutdown(vsh_ctx* ctx);

@@ -28,7 +28,7 @@ def lib():
 
 def test_header_declares_the_calls():
     names = declared()
-    for must in ("vsh_create", "vsh_destroy", "vsh_generate", "vsh_generate_into",
+    for must in ("vsh_create", "vsh_destroy", "vsh_generate", "vsh_generate_into", "vsh_generate_into_static",
                  "vsh_shower_records", "vsh_submit", "vsh_wait", "vsh_autotune"):
         assert must in names
 
