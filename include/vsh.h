@@ -38,7 +38,7 @@ extern "C" {
 #endif
 
 #define VSH_VERSION_MAJOR 1
-#define VSH_VERSION_MINOR 2
+#define VSH_VERSION_MINOR 3
 
 typedef enum {
   VSH_OK = 0,
@@ -123,11 +123,17 @@ typedef struct {
   int device;                /* HIP device ordinal                                      */
   uint64_t mem_budget_bytes; /* device memory the context may hold; 0 = 80% of free      */
   uint32_t flags;            /* reserved, 0                                              */
+  const char *tuner_cache_path; /* optional file of earlier vsh_autotune choices (read
+                                   by vsh_autotune, which appends each new choice);
+                                   NULL or "" = none.  Copied at vsh_create.        */
 } vsh_ctx_opts;
 
 /* Create a context on opts->device (opts may be NULL: device 0, default
-   budget).  Fails with VSH_E_DEVICE when the device is not gfx950 or HIP
-   reports an error.  *out is owned by the caller; release with vsh_destroy. */
+   budget).  The context holds what the paper's "device preparation" stage
+   (Table 1) allocates once: the device arena, reused by every later call and
+   grown on demand, the stream and the stage events.  Fails with VSH_E_DEVICE
+   when the device is not gfx950 or HIP reports an error.  *out is owned by
+   the caller; release with vsh_destroy. */
 vsh_status vsh_create(const vsh_ctx_opts *opts, vsh_ctx **out);
 void vsh_destroy(vsh_ctx *ctx);
 /* Last error message of ctx (or of the last failed vsh_create if ctx is
@@ -209,8 +215,10 @@ typedef struct {
 vsh_status vsh_generate(vsh_ctx *ctx, const vsh_request *req, vsh_result **out);
 void vsh_result_free(vsh_result *res);
 
-/* Shower caller-supplied initial states instead of LO events (a q g qbar
-   start, say).  offsets [n_events+1] index into p [total][4], pid, col,
+/* The main loop of App. A (select the winning trial emission, veto, emit,
+   until the cutoff) from caller-supplied initial states instead of LO events
+   (a q g qbar start, say), followed by the validation and observables of
+   Sec. 3.1.  offsets [n_events+1] index into p [total][4], pid, col,
    acol [total] (host memory, read during the call); the event's sqrt(s) is
    taken from the sum of its momenta' energies, t_cut from req; req->ecm and
    the per-event arrays are ignored.  Weights are 1.  The evolution starts at
@@ -222,7 +230,9 @@ vsh_status vsh_shower_records(vsh_ctx *ctx, const vsh_request *req, const uint64
 
 /* Device-side generation into caller-owned device memory, on the caller's
    HIP stream, with no allocation and no host synchronisation: the launch
-   sequence of vsh_generate without its copies.
+   sequence of vsh_generate without its copies, i.e. the problem statement of
+   Sec. 3 (matrix element of App. B, shower of App. A / C, observables of
+   Sec. 3.1 into histograms) with every result left on the device.
      stream      hipStream_t of the caller (NULL = the null stream)
      workspace   device buffer of at least vsh_workspace_size() bytes
      dev_hist    [VSH_HIST_DOUBLES] device doubles, accumulated into (clear first)
@@ -257,7 +267,8 @@ uint64_t vsh_workspace_size(const vsh_request *req);
 vsh_status vsh_generate_into_static(vsh_ctx *ctx, const vsh_request *req, void *stream, double *dev_hist,
                                     double *dev_sum_d, int32_t *dev_sum_i, uint64_t *dev_hash);
 
-/* Stage timing of vsh_generate_into.  After vsh_timing_start, each
+/* Stage timing of vsh_generate_into, per stage as in the paper's Table 1
+   and Fig. 6 (matrix element, shower, observables).  After vsh_timing_start, each
    vsh_generate_into call (at most VSH_TIMING_MAX_CALLS) records HIP events on
    its own stream before and after each of its three stages: matrix element,
    shower, observables + histograms.  vsh_timing_read waits for those events
@@ -268,7 +279,8 @@ vsh_status vsh_generate_into_static(vsh_ctx *ctx, const vsh_request *req, void *
 vsh_status vsh_timing_start(vsh_ctx *ctx);
 vsh_status vsh_timing_read(vsh_ctx *ctx, float *ms, uint32_t max_calls, uint32_t *n_calls);
 
-/* Launch parameters of the two forms.  vsh_autotune picks them by timing
+/* Launch parameters of the two forms of the parallel veto loop of Sec. 2
+   (one launch per batch, or persistent waves refilled from a work counter).  vsh_autotune picks them by timing
    candidates on a sample request; vsh_set_tuning sets them directly (values
    are clamped to the ranges below).  They change speed only: every event
    is the same for any setting. */
@@ -288,6 +300,8 @@ typedef struct {
                                 per SIMD: 2, 3 or 4 (more waves, fewer registers)     */
   uint32_t plain_mapping;    /* plain form: 0 = one lane per event, 1 = each wave's 64
                                 events with their cycle's trials spread over its lanes */
+  uint32_t from_cache;       /* set by vsh_autotune: 1 when the settings came from the
+                                context's tuner cache file (nothing was timed)       */
 } vsh_tuning;
 vsh_status vsh_get_tuning(vsh_ctx *ctx, vsh_tuning *out);
 vsh_status vsh_set_tuning(vsh_ctx *ctx, const vsh_tuning *t);
@@ -296,10 +310,19 @@ vsh_status vsh_set_tuning(vsh_ctx *ctx, const vsh_tuning *t);
    budget) on `sample`
    (its first min(n_events, 2^18) events) and keep the fastest in ctx;
    *chosen (optional) receives it.  Candidates whose summaries differ from
-   the first candidate's are rejected (VSH_E_INTERNAL). */
+   the first candidate's are rejected (VSH_E_INTERNAL).  With a tuner cache
+   (vsh_ctx_opts.tuner_cache_path), a sample whose key (library version,
+   device, form, capacity, sample size, sqrt(s), t_C or a hash of the
+   per-event arrays, masses, t_over, cycle limit) is in the file takes the
+   cached settings without timing (chosen->from_cache = 1); otherwise the new
+   choice is appended to the file.  An unreadable or unwritable cache file is
+   ignored. */
 vsh_status vsh_autotune(vsh_ctx *ctx, const vsh_request *sample, vsh_tuning *chosen);
 
-/* Serving (continuous batching).  vsh_submit copies the request (and its
+/* Serving (continuous batching).  Sec. 2's parallel form needs nothing but
+   independent events, so events of different requests (each its own sqrt(s),
+   t_C, seed and size) share the same launches; the per-request results are
+   those of the problem statement of Sec. 3.  vsh_submit copies the request (and its
    per-event arrays) and returns at once with a ticket; the context's serving
    loop admits requests by event-record memory, runs their events together in
    persistent launches as slots free up, and keeps one histogram set per

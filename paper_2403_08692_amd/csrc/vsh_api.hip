@@ -670,6 +670,7 @@ vsh_status vsh_create(const vsh_ctx_opts* opts, vsh_ctx** out) {
     return hip_fail(nullptr, err, "hipMemGetInfo");
   }
   ctx->budget = (opts && opts->mem_budget_bytes) ? opts->mem_budget_bytes : (uint64_t)(0.8 * (double)free_b);
+  if (opts && opts->tuner_cache_path) ctx->tuner_cache_path = opts->tuner_cache_path;
   err = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
   if (err != hipSuccess) {
     delete ctx;

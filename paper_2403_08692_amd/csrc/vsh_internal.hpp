@@ -81,6 +81,7 @@ struct vsh_ctx {
   vsh::HostStage stage;
   vsh::Tuned tuned;
   float tuned_ms = 0.0f;  // shower-kernel time of the autotuner's choice on its sample
+  std::string tuner_cache_path;  // file of earlier tunings (empty: none)
   std::mutex mu;
   std::string error;
   vsh::ServeState* serve = nullptr;  // owned; torn down by serve_shutdown

@@ -15,8 +15,14 @@
 
 namespace vsh {
 
-__global__ void __launch_bounds__(256) k_me(Records r, Summary s, EventInputs in, uint32_t n) {
+// zero_hist (optional): a histogram set to clear on the way (the first
+// min(n, 256) threads clear it), saving its own launch.
+__global__ void __launch_bounds__(256) k_me(Records r, Summary s, EventInputs in, uint32_t n, double* zero_hist) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (zero_hist && e < 256u) {
+    const uint32_t step = n < 256u ? n : 256u;
+    for (uint32_t a = e; a < (uint32_t)kHistDoubles; a += step) zero_hist[a] = 0.0;
+  }
   if (e >= n) return;
   const MEOut m = me_event(r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.qm, in.massive != 0);
   s.d[kSdW * s.stride + e] = m.w;
@@ -323,14 +329,17 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
   double* uy = ux + slots;
   double* uz = uy + slots;
   uint16_t* list = (uint16_t*)(lh + kHistDoubles + (size_t)kGroups * 7 * slots) + (size_t)grp * slots;
+  // cnt[cap - m] counts the events with at least m partons (see k_obs)
+  const uint32_t q_lo = hi_n <= cap ? cnt[cap - hi_n] : 0u;
+  const uint32_t q_hi = lo_n <= cap ? cnt[cap - lo_n] : 0u;
+  // the grid is sized for the worst case: blocks without an event of this
+  // range leave at once (the whole block, before touching LDS)
+  if (q_lo + blockIdx.x * kGroups >= q_hi) return;
   for (int a = threadIdx.x; a < kHistDoubles; a += 64) lh[a] = 0.0;
   const bool fixed = in.fixed_hist != 0;
   FixScale fxs{0, 0};
   if (fixed) fxs = fix_scale(sc);
   const FixScale* fx = fixed ? &fxs : nullptr;
-  // cnt[cap - m] counts the events with at least m partons (see k_obs)
-  const uint32_t q_lo = hi_n <= cap ? cnt[cap - hi_n] : 0u;
-  const uint32_t q_hi = lo_n <= cap ? cnt[cap - lo_n] : 0u;
   __syncthreads();
   for (uint32_t q = q_lo + blockIdx.x * kGroups + grp; q < q_hi; q += gridDim.x * kGroups) {
     const uint64_t e = perm[q];
@@ -548,9 +557,9 @@ size_t obs_group_lds(uint32_t g, uint32_t slots) {
 static inline uint32_t blocks_for(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
 
 void launch_me(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
-               hipStream_t st) {
+               hipStream_t st, double* zero_hist) {
   if (!n) return;
-  hipLaunchKernelGGL(k_me, dim3(blocks_for(n, 256)), dim3(256), 0, st, r, s, in, n);
+  hipLaunchKernelGGL(k_me, dim3(blocks_for(n, 256)), dim3(256), 0, st, r, s, in, n, zero_hist);
 }
 
 void launch_shower_init_records(const Records& r, const Summary& s, const EventInputs& in,

@@ -121,7 +121,7 @@ __global__ void k_hist_fixed_finalize(Scratch sc, double* hist);
 __global__ void k_obs_scan(uint32_t* cnt, uint32_t nb);
 __global__ void k_obs_scatter(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt, uint32_t* perm);
 __global__ void k_zero_u32(uint32_t* p, uint32_t n);
-__global__ void k_me(Records r, Summary s, EventInputs in, uint32_t n);
+__global__ void k_me(Records r, Summary s, EventInputs in, uint32_t n, double* zero_hist);
 // one launch of the group observables kernel: function, parton-count range
 // [lo, hi), LDS parton slots per group, dynamic LDS bytes
 struct ObsGroupLaunch {
@@ -131,7 +131,7 @@ struct ObsGroupLaunch {
 uint32_t obs_group_launches(uint32_t cap, bool massive, ObsGroupLaunch out[3]);
 size_t obs_group_lds(uint32_t g, uint32_t slots);
 void launch_me(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
-               hipStream_t st);
+               hipStream_t st, double* zero_hist = nullptr);
 void launch_shower_plain(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
                          uint32_t block, uint32_t waves, hipStream_t st);
 void launch_obs(const Records& r, const Summary& s, const EventInputs& in, const Scratch& sc,

@@ -703,7 +703,9 @@ void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInp
                        in, n, ec);
 }
 
-template <bool kInPlace, bool kMassive>
+// kCached: A.cache holds an end cache per lane (always when in place; the
+// serving epochs' staging slots have one unless it could not be allocated).
+template <bool kInPlace, bool kMassive, bool kCached>
 __global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
@@ -730,8 +732,8 @@ __global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
       busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle<kInPlace, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane,
-                                   A.reqs[req].qm);
+    flat_cycle<kCached, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane,
+                                  A.reqs[req].qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
@@ -811,13 +813,15 @@ ReqBuffers carve_request(Carver& c, uint64_t n, uint32_t cap, bool partners) {
   b.out.apart = partners ? (uint16_t*)c.take(m * 2) : nullptr;
   b.out.stride = n;
   b.out.cap = cap;
-  b.sum.d = (double*)c.take(kNSumD * n * 8);
+  // the results in one span, in the order the serving drain copies them
+  // back: histogram, integer fields, then the doubles (weight first), hash
+  b.hist = (double*)c.take(kHistDoubles * 8);
   b.sum.i = (int32_t*)c.take(kNSumI * n * 4);
+  b.sum.d = (double*)c.take(kNSumD * n * 8);
   b.sum.hash = (uint64_t*)c.take(n * 8);
   b.sum.stride = n;
   b.ecm = (double*)c.take(n * 8);
   b.tcut = (double*)c.take(n * 8);
-  b.hist = (double*)c.take(kHistDoubles * 8);
   return b;
 }
 
@@ -852,11 +856,14 @@ BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap, bool massive) {
 }
 
 // The kernel of a mapping, in place or not, for requests with or without
-// quark masses.
-const void* persistent_kernel(uint32_t mapping, bool in_place, bool massive) {
+// quark masses; the flattened mapping with or without an end cache (in place
+// always has one).
+const void* persistent_kernel(uint32_t mapping, bool in_place, bool massive, bool cached) {
   if (mapping == kMapFlat) {
-    if (massive) return in_place ? (const void*)k_shower_flat<true, true> : (const void*)k_shower_flat<false, true>;
-    return in_place ? (const void*)k_shower_flat<true, false> : (const void*)k_shower_flat<false, false>;
+    if (in_place) return massive ? (const void*)k_shower_flat<true, true, true> : (const void*)k_shower_flat<true, false, true>;
+    if (cached)
+      return massive ? (const void*)k_shower_flat<false, true, true> : (const void*)k_shower_flat<false, false, true>;
+    return massive ? (const void*)k_shower_flat<false, true, false> : (const void*)k_shower_flat<false, false, false>;
   }
   if (massive)
     return in_place ? (const void*)k_shower_persistent<true, true> : (const void*)k_shower_persistent<false, true>;
@@ -871,7 +878,8 @@ void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uin
   const dim3 grid((uint32_t)(lanes / block));
   const size_t lds = mapping == kMapFlat ? flat_lds_bytes(A.slots.cap) : 0;
   void* args[] = {const_cast<PersistArgs*>(&A)};
-  (void)hipLaunchKernel(persistent_kernel(mapping, in_place, massive), grid, dim3(block), args, lds, st);
+  (void)hipLaunchKernel(persistent_kernel(mapping, in_place, massive, A.cache.rec != nullptr), grid, dim3(block), args,
+                        lds, st);
 }
 
 void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, unsigned long long* counter,
@@ -935,12 +943,12 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   GCHK(add_event(0));
   void* a_setup[] = {&g.rd, &g.d, &g.sd, &g.s, &g.counter};
   GCHK(add_kernel((const void*)k_setup, dim3(1), dim3(64), a_setup));
-  void* a_me[] = {&g.rec, &g.sum, &g.in, &g.n};
+  void* a_me[] = {&g.rec, &g.sum, &g.in, &g.n, &g.no_hist};
   GCHK(add_kernel((const void*)k_me, dim3((uint32_t)((n + 255) / 256)), dim3(256), a_me));
   GCHK(add_event(1));
   void* a_pers[] = {&g.args};
   const bool massive = g.in.massive != 0;
-  GCHK(add_kernel(persistent_kernel(g.mapping, true, massive), dim3((uint32_t)(lanes / block)), dim3(block),
+  GCHK(add_kernel(persistent_kernel(g.mapping, true, massive, true), dim3((uint32_t)(lanes / block)), dim3(block),
                   a_pers, g.mapping == kMapFlat ? (unsigned)flat_lds_bytes(A.slots.cap) : 0u));
   GCHK(add_event(2));
   g.nb = L.buf.out.cap + 1;

@@ -101,6 +101,7 @@ struct BatchGraph {
   const uint32_t* perm_c = nullptr;
   const uint32_t* cnt_c = nullptr;
   double* hist = nullptr;
+  double* no_hist = nullptr;  // k_me's histogram to clear: none in a batch
   unsigned long long* ih = nullptr;  // fixed-point cells and largest weight (null: FP64 sums)
   unsigned long long* wm = nullptr;
   uint64_t lanes = 0;

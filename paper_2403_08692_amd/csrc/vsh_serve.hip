@@ -6,17 +6,21 @@
 //     memory (every event's final record at its request's capacity, the
 //     summaries and the histogram) fits a device pool; a request that does
 //     not fit yet waits, one that can never fit is rejected at submission;
-//   * launches bounded epochs of the persistent shower kernel whose work list
-//     holds segments of every admitted request with events left, oldest
-//     first, so requests that arrive while others run join the next epoch;
-//     two epochs may be in flight on two streams, the second filling compute
-//     units the first's tail frees;
-//   * when all events of a request are finished, computes its observables and
-//     histogram on a drain stream, copies the result to the host and completes
-//     the ticket, returning its memory to the pool.
+//   * launches bounded epochs whose work list holds segments of every
+//     admitted request with events left, oldest first, so requests that
+//     arrive while others run join the next epoch.  Two epochs are in flight
+//     on two streams, the second filling compute units the first's tail
+//     frees.  An epoch's stream runs, in order: the matrix elements of the
+//     requests it starts, the persistent shower kernel over its segments,
+//     then, for every request whose last events it holds, the observables,
+//     the histogram and one copy of the results into pinned host memory.
+//     Where a request's events span both epochs, the stream waits on the
+//     other epoch's event instead of on the host;
+//   * when an epoch's last event completes, hands its finished requests
+//     their results and returns their memory to the pool.
 // Every event is a pure function of (request seed, event id), so a request's
 // events are the same alone or in any mix; only the summation order of its
-// FP64 histogram can differ.
+// FP64 histogram can differ (none with VSH_HIST_FIXEDPOINT).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -97,7 +101,7 @@ struct Pool {
   }
 };
 
-enum ReqState { kQueued, kAdmitted, kDraining, kFinished, kCancelledState, kFailed };
+enum ReqState { kQueued, kAdmitted, kFinished, kCancelledState, kFailed };
 
 struct ServeReq {
   uint64_t ticket = 0;
@@ -109,11 +113,14 @@ struct ServeReq {
   uint64_t pool_off = 0, pool_bytes = 0;
   ReqBuffers buf{};
   uint64_t scheduled = 0, finished = 0;
-  int inflight = 0;
-  hipEvent_t drained = nullptr;
-  // the drain's copies land in pinned host memory (S.host): the histogram,
-  // then every summary field (with VSH_SUMMARY) or only the weight and the
-  // counted integer fields
+  int inflight = 0;       // epochs in flight that hold events of the request
+  int me_slot = -1;       // epoch (slot, generation) whose stream computes its LO events
+  uint64_t me_gen = 0;
+  uint64_t seg_gen[2] = {0, 0};  // latest generation of each slot holding some of its events
+  bool drained = false;   // its observables and copy have completed
+  // the drain's one copy lands in pinned host memory (S.host): the
+  // histogram, the integer fields and the weights, and with VSH_SUMMARY the
+  // other doubles and the hash
   uint64_t host_off = 0, host_bytes = 0;
   char* own_host = nullptr;  // a staging of its own when the request outgrows the shared one
   double* h_hist = nullptr;
@@ -129,13 +136,19 @@ constexpr uint32_t kMaxEpochReqs = 512;
 
 struct Epoch {
   hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
+  hipEvent_t me_done = nullptr;      // after the matrix elements of the requests it starts
+  hipEvent_t shower_done = nullptr;  // after its shower kernel
+  hipEvent_t done = nullptr;         // after its drains and copies
   bool busy = false;
+  uint64_t gen = 0;                  // launch generation of this slot
   std::vector<std::pair<uint64_t, uint64_t>> parts;  // (ticket, events)
-  ReqDev* reqs_host = nullptr;                       // pinned
-  Segment* segs_host = nullptr;                      // pinned
-  char* dev = nullptr;                               // descriptors, counter, slots
+  std::vector<uint64_t> finishing;   // tickets whose observables and copy it runs
+  ReqDev* reqs_host = nullptr;       // pinned
+  Segment* segs_host = nullptr;      // pinned
+  char* dev = nullptr;               // descriptors, counter, slots, end cache
   uint64_t dev_bytes = 0;
+  char* scratch = nullptr;           // observables scratch of its drains
+  uint64_t scratch_bytes = 0;
 };
 
 struct ServeState {
@@ -144,18 +157,13 @@ struct ServeState {
   std::thread th;
   bool stop = false;
   uint64_t next_ticket = 1;
+  uint64_t next_gen = 1;
   std::deque<uint64_t> pending;
   std::vector<uint64_t> active;  // admitted, in admission order
   std::unordered_map<uint64_t, std::unique_ptr<ServeReq>> reqs;
   Pool pool;
   Pool host;  // pinned host memory for the drains' copies
-  std::deque<uint64_t> to_drain;  // finished requests waiting for pinned staging
   Epoch ep[2];
-  hipStream_t drain = nullptr;
-  hipStream_t admit_stream = nullptr;  // admissions' input copies and matrix elements
-  hipEvent_t admitted = nullptr;       // recorded after each admission; epochs wait on it
-  char* scratch = nullptr;
-  uint64_t scratch_bytes = 0;
   uint32_t fail_epochs = 0;  // testing: epochs still to report a device error without launching
 };
 
@@ -173,10 +181,6 @@ static void finish_request(ServeState& S, ServeReq& r, int state) {
   if (r.own_host) {
     (void)hipHostFree(r.own_host);
     r.own_host = nullptr;
-  }
-  if (r.drained) {
-    (void)hipEventDestroy(r.drained);
-    r.drained = nullptr;
   }
   r.state = state;
   S.active.erase(std::remove(S.active.begin(), S.active.end(), r.ticket), S.active.end());
@@ -196,6 +200,9 @@ static void fail_request(ServeState& S, ServeReq& r, vsh_status code, const char
     finish_request(S, r, kFailed);
 }
 
+// Admission: a request whose event-record memory fits the pool (oldest
+// first) gets its device buffers; its matrix elements run in the first
+// epoch that schedules its events.
 static bool admit(vsh_ctx* ctx, ServeState& S) {
   bool progress = false;
   while (!S.pending.empty()) {
@@ -214,68 +221,106 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     r.pool_bytes = bytes;
     Carver c(S.pool.base + off);
     r.buf = carve_request(c, r.req.n_events, r.req.max_partons, false);
-    const uint64_t n = r.req.n_events;
-    hipError_t err = hipSuccess;
-    if (!r.ecm.empty()) err = hipMemcpyAsync(r.buf.ecm, r.ecm.data(), n * 8, hipMemcpyHostToDevice, S.admit_stream);
-    if (err == hipSuccess && !r.tcut.empty())
-      err = hipMemcpyAsync(r.buf.tcut, r.tcut.data(), n * 8, hipMemcpyHostToDevice, S.admit_stream);
-    launch_zero(r.buf.hist, kHistDoubles, S.admit_stream);
-    EventInputs in{};
-    in.ecm = r.ecm.empty() ? nullptr : r.buf.ecm;
-    in.tcut = r.tcut.empty() ? nullptr : r.buf.tcut;
-    in.ecm0 = r.req.ecm;
-    in.tcut0 = r.req.t_cut;
-    in.seed = r.req.seed;
-    in.first = r.req.first_event;
-    in.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
-    in.t_over = r.req.t_over;
-    in.qm = request_masses(r.req);
-    in.massive = request_massive(r.req);
-    in.fixed_hist = (r.req.flags & VSH_HIST_FIXEDPOINT) ? 1u : 0u;
-    launch_me(r.buf.out, r.buf.sum, in, (uint32_t)n, S.admit_stream);  // LO partons of every event
-    const hipError_t lerr = hipGetLastError();
-    if (err == hipSuccess) err = lerr;
-    // every later epoch waits for this event: inputs and LO events are on
-    // the device before an epoch reads them, with no host wait here
-    if (err == hipSuccess) err = hipEventRecord(S.admitted, S.admit_stream);
     r.state = kAdmitted;
     S.active.push_back(r.ticket);
-    if (err != hipSuccess) fail_request(S, r, VSH_E_DEVICE, "admission", err);
     progress = true;
   }
   (void)ctx;
   return progress;
 }
 
-static bool ensure_epoch_memory(vsh_ctx* ctx, Epoch& E, uint64_t lanes, uint32_t cap) {
-  const uint64_t need = align_up(kMaxEpochReqs * sizeof(ReqDev), 256) +
-                        align_up(kMaxEpochReqs * sizeof(Segment), 256) + 256 + slots_bytes(lanes, cap);
-  if (need <= E.dev_bytes) return true;
+// Device memory of an epoch: descriptors, work counter, the lanes' staging
+// slots and, when it fits, their end cache (cache_words words per parton
+// slot; without it the flattened kernel recomputes every end each cycle).
+// Grown on demand; *cached tells whether the cache is there.
+static bool ensure_epoch_memory(vsh_ctx* ctx, Epoch& E, uint64_t lanes, uint32_t cap, bool massive, bool* cached) {
+  const uint64_t base = align_up(kMaxEpochReqs * sizeof(ReqDev), 256) + align_up(kMaxEpochReqs * sizeof(Segment), 256) +
+                        256 + slots_bytes(lanes, cap);
+  const uint64_t with_cache = base + align_up(lanes * cap * cache_words(massive) * 8, 256);
+  *cached = true;
+  if (with_cache <= E.dev_bytes) return true;
   if (E.dev) (void)hipFree(E.dev);
   E.dev = nullptr;
   E.dev_bytes = 0;
-  if (hipMalloc(&E.dev, need) != hipSuccess) {
+  for (const uint64_t need : {with_cache, base}) {
+    if (hipMalloc(&E.dev, need) == hipSuccess) {
+      E.dev_bytes = need;
+      *cached = need == with_cache;
+      return true;
+    }
     (void)hipGetLastError();
     E.dev = nullptr;
-    return false;
   }
-  E.dev_bytes = need;
   (void)ctx;
-  return true;
+  return false;
+}
+
+static EventInputs request_inputs(const ServeReq& r) {
+  EventInputs in{};
+  in.ecm = r.ecm.empty() ? nullptr : r.buf.ecm;
+  in.tcut = r.tcut.empty() ? nullptr : r.buf.tcut;
+  in.ecm0 = r.req.ecm;
+  in.tcut0 = r.req.t_cut;
+  in.seed = r.req.seed;
+  in.first = r.req.first_event;
+  in.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
+  in.t_over = r.req.t_over;
+  in.qm = request_masses(r.req);
+  in.massive = request_massive(r.req);
+  in.fixed_hist = (r.req.flags & VSH_HIST_FIXEDPOINT) ? 1u : 0u;
+  return in;
+}
+
+// Pinned host memory for a finishing request's results (the span of
+// carve_request from the histogram to the weights, or to the hash with
+// VSH_SUMMARY), from the shared staging or, when it is full or too small,
+// an allocation of the request's own.
+static hipError_t reserve_staging(ServeState& S, ServeReq& r, uint64_t* bytes) {
+  static_assert(kSdW == 0, "the weight is the first double field");
+  const uint64_t n = r.req.n_events;
+  const char* dev0 = reinterpret_cast<const char*>(r.buf.hist);
+  const uint64_t off_i = reinterpret_cast<const char*>(r.buf.sum.i) - dev0;
+  const uint64_t off_d = reinterpret_cast<const char*>(r.buf.sum.d) - dev0;
+  const uint64_t off_h = reinterpret_cast<const char*>(r.buf.sum.hash) - dev0;
+  const bool all_fields = (r.req.flags & VSH_SUMMARY) != 0;
+  *bytes = all_fields ? off_h + n * 8 : off_d + n * 8;
+  char* hbase = nullptr;
+  uint64_t off = 0;
+  if (*bytes <= S.host.size && S.host.alloc(*bytes, &off)) {
+    r.host_off = off;
+    r.host_bytes = *bytes;
+    hbase = S.host.base + off;
+  } else {
+    const hipError_t err = hipHostMalloc((void**)&r.own_host, *bytes, 0);
+    if (err != hipSuccess) {
+      (void)hipGetLastError();
+      r.own_host = nullptr;
+      return err;
+    }
+    hbase = r.own_host;
+  }
+  r.h_hist = reinterpret_cast<double*>(hbase);
+  r.h_si = reinterpret_cast<int32_t*>(hbase + off_i);
+  r.h_sd = reinterpret_cast<double*>(hbase + off_d);
+  r.h_hs = all_fields ? reinterpret_cast<uint64_t*>(hbase + off_h) : nullptr;
+  return hipSuccess;
 }
 
 static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
-  Epoch* E = nullptr;
-  for (auto& e : S.ep)
-    if (!e.busy) {
-      E = &e;
+  int ei = -1;
+  for (int k = 0; k < 2; ++k)
+    if (!S.ep[k].busy) {
+      ei = k;
       break;
     }
-  if (!E) return false;
+  if (ei < 0) return false;
+  Epoch* E = &S.ep[ei];
+  const Epoch& O = S.ep[1 - ei];
   const Tuned tn = ctx->tuned;
   const uint64_t lanes = persistent_lanes(ctx);
   const uint64_t limit = std::max<uint64_t>(2 * lanes, 1 << 16);
   E->parts.clear();
+  E->finishing.clear();
   uint64_t total = 0;
   uint32_t nreq = 0, nseg = 0, cap = 2;
   bool massive = false;  // any request of the epoch with quark masses
@@ -305,8 +350,6 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
     sg.lo = r.scheduled;
     sg.hi = r.scheduled + take;
     sg.start = total;
-    r.scheduled += take;
-    r.inflight += 1;
     total += take;
     cap = std::max(cap, r.req.max_partons);
     E->parts.emplace_back(t, take);
@@ -314,22 +357,68 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
     ++nseg;
   }
   if (total == 0) return false;
-  if (!ensure_epoch_memory(ctx, *E, lanes, cap)) {
-    // give the events back; retry when memory frees up
+  bool cached = false;
+  if (!ensure_epoch_memory(ctx, *E, lanes, cap, massive, &cached)) {
+    E->parts.clear();  // nothing scheduled; retried when memory frees up
+    return false;
+  }
+  // from here on the parts belong to this epoch
+  E->gen = S.next_gen++;
+  for (auto& p : E->parts) {
+    ServeReq& r = *S.reqs[p.first];
+    r.scheduled += p.second;
+    r.inflight += 1;
+    r.seg_gen[ei] = E->gen;
+  }
+  auto fail_all = [&](const char* what, hipError_t err) {
+    // whatever was queued on the stream ends before its memory is reused
+    (void)hipStreamSynchronize(E->stream);
+    (void)hipGetLastError();
     for (auto& p : E->parts) {
       ServeReq& r = *S.reqs[p.first];
-      r.scheduled -= p.second;
       r.inflight -= 1;
+      fail_request(S, r, VSH_E_DEVICE, what, err);
     }
     E->parts.clear();
+    E->finishing.clear();
     return false;
+  };
+  if (S.fail_epochs > 0) {  // testing hook: report a device error, launch nothing
+    --S.fail_epochs;
+    return fail_all("epoch launch", hipErrorLaunchFailure);
   }
   Carver c(E->dev);
   ReqDev* rd = (ReqDev*)c.take(kMaxEpochReqs * sizeof(ReqDev));
   Segment* sd = (Segment*)c.take(kMaxEpochReqs * sizeof(Segment));
   unsigned long long* counter = (unsigned long long*)c.take(256);
   Records slots = carve_slots(c, lanes, cap);
-  hipError_t err = hipStreamWaitEvent(E->stream, S.admitted, 0);
+  const EndCache cache{cached ? (uint64_t*)c.take(lanes * cap * cache_words(massive) * 8) : nullptr, cap};
+  hipError_t err = hipSuccess;
+  // the LO events of the requests that start here; requests whose LO events
+  // the other epoch computes make this stream wait for them
+  bool wait_me = false;
+  for (auto& p : E->parts) {
+    const ServeReq& r = *S.reqs[p.first];
+    wait_me |= r.me_slot == 1 - ei && O.busy && r.me_gen == O.gen;
+  }
+  if (wait_me) err = hipStreamWaitEvent(E->stream, O.me_done, 0);
+  for (auto& p : E->parts) {
+    ServeReq& r = *S.reqs[p.first];
+    if (err != hipSuccess) break;
+    if (r.me_slot >= 0) continue;
+    const uint64_t n = r.req.n_events;
+    if (!r.ecm.empty()) err = hipMemcpyAsync(r.buf.ecm, r.ecm.data(), n * 8, hipMemcpyHostToDevice, E->stream);
+    if (err == hipSuccess && !r.tcut.empty())
+      err = hipMemcpyAsync(r.buf.tcut, r.tcut.data(), n * 8, hipMemcpyHostToDevice, E->stream);
+    if (err != hipSuccess) break;
+    // LO partons of every event; the request's histogram cleared on the way
+    launch_me(r.buf.out, r.buf.sum, request_inputs(r), (uint32_t)n, E->stream, r.buf.hist);
+    r.me_slot = ei;
+    r.me_gen = E->gen;
+  }
+  if (err == hipSuccess) err = hipGetLastError();
+  if (err == hipSuccess) err = hipEventRecord(E->me_done, E->stream);
+  // the shower
   if (err == hipSuccess) err = hipMemcpyAsync(rd, E->reqs_host, nreq * sizeof(ReqDev), hipMemcpyHostToDevice, E->stream);
   if (err == hipSuccess) err = hipMemcpyAsync(sd, E->segs_host, nseg * sizeof(Segment), hipMemcpyHostToDevice, E->stream);
   if (err == hipSuccess) err = hipMemsetAsync(counter, 0, 8, E->stream);
@@ -340,116 +429,76 @@ static bool launch_epoch(vsh_ctx* ctx, ServeState& S) {
   A.n_segs = nseg;
   A.threshold = tn.refill_threshold;
   A.pad = 0;
-  A.cache = EndCache{nullptr, 0};
+  A.cache = cache;
   A.total = total;
   A.next = counter;
   A.period = tn.refill_period;
-  if (err == hipSuccess && S.fail_epochs > 0) {  // testing hook: report a device error, launch nothing
-    --S.fail_epochs;
-    err = hipErrorLaunchFailure;
-  }
   if (err == hipSuccess) {
     launch_persistent(A, lanes, tn.pers_block, tn.mapping, false, massive, E->stream);
     err = hipGetLastError();
   }
-  if (err == hipSuccess) err = hipEventRecord(E->done, E->stream);
-  if (err != hipSuccess) {
-    // nothing of this epoch runs: its requests fail (work already queued on
-    // the stream finishes before the stream is used again)
-    for (auto& p : E->parts) {
-      ServeReq& r = *S.reqs[p.first];
-      r.inflight -= 1;
-      fail_request(S, r, VSH_E_DEVICE, "epoch launch", err);
-    }
-    E->parts.clear();
-    return false;
+  if (err == hipSuccess) err = hipEventRecord(E->shower_done, E->stream);
+  if (err != hipSuccess) return fail_all("epoch launch", err);
+  // the requests whose last events are here: observables, histogram and one
+  // copy of their results, after the other epoch's shower where it holds
+  // some of their events
+  bool wait_other = false;
+  for (auto& p : E->parts) {
+    ServeReq& r = *S.reqs[p.first];
+    if (r.scheduled != r.req.n_events) continue;
+    E->finishing.push_back(p.first);
+    wait_other |= O.busy && r.seg_gen[1 - ei] == O.gen;
   }
+  if (wait_other) err = hipStreamWaitEvent(E->stream, O.shower_done, 0);
+  uint64_t scratch_need = 0;
+  for (uint64_t t : E->finishing) {
+    const ServeReq& r = *S.reqs[t];
+    scratch_need = std::max(scratch_need, obs_scratch_bytes(r.req.n_events, r.req.max_partons));
+  }
+  if (err == hipSuccess && scratch_need > E->scratch_bytes) {
+    if (E->scratch) (void)hipFree(E->scratch);  // this stream's earlier work has completed
+    E->scratch = nullptr;
+    E->scratch_bytes = 0;
+    err = hipMalloc(&E->scratch, scratch_need);
+    if (err == hipSuccess) E->scratch_bytes = scratch_need;
+    else E->scratch = nullptr;
+  }
+  for (uint64_t t : E->finishing) {
+    ServeReq& r = *S.reqs[t];
+    if (err != hipSuccess) break;
+    uint64_t bytes = 0;
+    err = reserve_staging(S, r, &bytes);
+    if (err != hipSuccess) break;
+    Carver sc_c(E->scratch);
+    const Scratch sc = carve_scratch(sc_c, r.req.n_events, r.req.max_partons);
+    launch_obs(r.buf.out, r.buf.sum, request_inputs(r), sc, (uint32_t)r.req.n_events, r.buf.hist, E->stream);
+    err = hipGetLastError();
+    if (err == hipSuccess) err = hipMemcpyAsync(r.h_hist, r.buf.hist, bytes, hipMemcpyDeviceToHost, E->stream);
+  }
+  if (err == hipSuccess) err = hipEventRecord(E->done, E->stream);
+  if (err != hipSuccess) return fail_all("observables launch", err);
   E->busy = true;
   return true;
 }
 
-// Start computing a finished request's observables and copying its results
-// back.  False (nothing started) while the pinned staging is full: the
-// request waits in S.to_drain.
-static bool start_drain(vsh_ctx* ctx, ServeState& S, ServeReq& r) {
+// The result of a request whose events and drain have completed, from its
+// pinned staging.
+static void complete_request(ServeState& S, ServeReq& r) {
   const uint64_t n = r.req.n_events;
-  const uint32_t cap = r.req.max_partons;
-  const bool all_fields = (r.req.flags & VSH_SUMMARY) != 0;
-  static_assert(kSiStatus == 1 && kSiEnds == kNSumI - 1, "the counted integer fields are the last ones");
-  const uint64_t i_fields = all_fields ? kNSumI : kNSumI - kSiStatus, d_fields = all_fields ? kNSumD : 1;
-  const uint64_t hb = align_up(kHistDoubles * 8, 256), db = align_up(d_fields * n * 8, 256),
-                 ib = align_up(i_fields * n * 4, 256), sb = all_fields ? align_up(n * 8, 256) : 0;
-  const uint64_t need_host = hb + db + ib + sb;
-  char* hbase = nullptr;
-  if (need_host > S.host.size) {  // larger than the whole shared staging: one of its own
-    if (hipHostMalloc((void**)&r.own_host, need_host, 0) != hipSuccess) {
-      (void)hipGetLastError();
-      r.own_host = nullptr;
-      fail_request(S, r, VSH_E_NOMEM, "pinned staging of the results", hipSuccess);
-      return true;
+  ResultBox* box = new_result(n, r.req.flags & VSH_SUMMARY);
+  if (box) {
+    box->hist.assign(r.h_hist, r.h_hist + kHistDoubles);
+    tally_fields(box, r.h_si + kSiStatus * n, n, r.h_sd + kSdW * n, n);
+    if (!box->sum_d.empty()) {
+      std::memcpy(box->sum_d.data(), r.h_sd, kNSumD * n * 8);
+      std::memcpy(box->sum_i.data(), r.h_si, kNSumI * n * 4);
+      std::memcpy(box->hash.data(), r.h_hs, n * 8);
     }
-    hbase = r.own_host;
-  } else {
-    uint64_t off = 0;
-    if (!S.host.alloc(need_host, &off)) return false;
-    r.host_off = off;
-    r.host_bytes = need_host;
-    hbase = S.host.base + off;
+    box->pub.t_total_ms = std::chrono::duration<double, std::milli>(Clock::now() - r.t_arrival).count();
+    finish_result(box);
   }
-  r.h_hist = reinterpret_cast<double*>(hbase);
-  r.h_sd = reinterpret_cast<double*>(hbase + hb);
-  r.h_si = reinterpret_cast<int32_t*>(hbase + hb + db);
-  r.h_hs = all_fields ? reinterpret_cast<uint64_t*>(hbase + hb + db + ib) : nullptr;
-  const uint64_t need = obs_scratch_bytes(n, cap);
-  if (need > S.scratch_bytes) {
-    (void)hipStreamSynchronize(S.drain);
-    if (S.scratch) (void)hipFree(S.scratch);
-    S.scratch = nullptr;
-    S.scratch_bytes = 0;
-    if (hipMalloc(&S.scratch, need) == hipSuccess) S.scratch_bytes = need;
-    else (void)hipGetLastError();
-  }
-  if (!S.scratch) {  // cannot compute its observables: fail the request
-    fail_request(S, r, VSH_E_NOMEM, "observables scratch", hipSuccess);
-    return true;
-  }
-  Carver c(S.scratch);
-  Scratch sc = carve_scratch(c, n, cap);
-  EventInputs in{};
-  in.ecm = r.ecm.empty() ? nullptr : r.buf.ecm;
-  in.tcut = r.tcut.empty() ? nullptr : r.buf.tcut;
-  in.ecm0 = r.req.ecm;
-  in.tcut0 = r.req.t_cut;
-  in.seed = r.req.seed;
-  in.first = r.req.first_event;
-  in.cycle_limit = effective_cycle_limit(r.req.cycle_limit);
-  in.t_over = r.req.t_over;
-  in.qm = request_masses(r.req);
-  in.massive = request_massive(r.req);
-  in.fixed_hist = (r.req.flags & VSH_HIST_FIXEDPOINT) ? 1u : 0u;
-  launch_obs(r.buf.out, r.buf.sum, in, sc, (uint32_t)n, r.buf.hist, S.drain);
-  hipError_t err = hipGetLastError();
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(r.h_hist, r.buf.hist, kHistDoubles * 8, hipMemcpyDeviceToHost, S.drain);
-  if (all_fields) {
-    if (err == hipSuccess) err = hipMemcpyAsync(r.h_sd, r.buf.sum.d, kNSumD * n * 8, hipMemcpyDeviceToHost, S.drain);
-    if (err == hipSuccess) err = hipMemcpyAsync(r.h_si, r.buf.sum.i, kNSumI * n * 4, hipMemcpyDeviceToHost, S.drain);
-    if (err == hipSuccess) err = hipMemcpyAsync(r.h_hs, r.buf.sum.hash, n * 8, hipMemcpyDeviceToHost, S.drain);
-  } else {
-    if (err == hipSuccess)
-      err = hipMemcpyAsync(r.h_sd, r.buf.sum.d + kSdW * n, n * 8, hipMemcpyDeviceToHost, S.drain);
-    if (err == hipSuccess)
-      err = hipMemcpyAsync(r.h_si, r.buf.sum.i + kSiStatus * n, i_fields * n * 4, hipMemcpyDeviceToHost, S.drain);
-  }
-  if (err == hipSuccess) err = hipEventCreateWithFlags(&r.drained, hipEventDisableTiming);
-  if (err == hipSuccess) err = hipEventRecord(r.drained, S.drain);
-  if (err != hipSuccess) {
-    fail_request(S, r, VSH_E_DEVICE, "observables launch", err);
-    return true;
-  }
-  r.state = kDraining;
-  (void)ctx;
-  return true;
+  r.box = box;
+  finish_request(S, r, kFinished);
 }
 
 static bool retire_epochs(vsh_ctx* ctx, ServeState& S) {
@@ -458,80 +507,33 @@ static bool retire_epochs(vsh_ctx* ctx, ServeState& S) {
     if (!E.busy) continue;
     const hipError_t q = hipEventQuery(E.done);
     if (q == hipErrorNotReady) continue;
+    for (uint64_t t : E.finishing) {
+      auto it = S.reqs.find(t);
+      if (it != S.reqs.end() && q == hipSuccess) it->second->drained = true;
+    }
     for (auto& p : E.parts) {
       auto it = S.reqs.find(p.first);
       if (it == S.reqs.end()) continue;
       ServeReq& r = *it->second;
       r.finished += p.second;
       r.inflight -= 1;
-      if (q != hipSuccess) {
-        fail_request(S, r, VSH_E_DEVICE, "epoch", q);
-      } else if (r.cancel) {
-        if (r.inflight == 0 && r.state == kAdmitted)
-          finish_request(S, r, r.fail_code != VSH_OK ? kFailed : kCancelledState);
-      } else if (r.finished == r.req.n_events) {
-        if (!start_drain(ctx, S, r)) S.to_drain.push_back(r.ticket);
-      }
+      if (q != hipSuccess) fail_request(S, r, VSH_E_DEVICE, "epoch", q);
+    }
+    // requests with nothing in flight any more: done, cancelled or failed
+    for (auto& p : E.parts) {
+      auto it = S.reqs.find(p.first);
+      if (it == S.reqs.end()) continue;
+      ServeReq& r = *it->second;
+      if (r.inflight != 0 || r.state != kAdmitted) continue;
+      if (r.cancel) finish_request(S, r, r.fail_code != VSH_OK ? kFailed : kCancelledState);
+      else if (r.drained) complete_request(S, r);
     }
     E.parts.clear();
+    E.finishing.clear();
     E.busy = false;
     progress = true;
   }
-  return progress;
-}
-
-static bool poll_drains(ServeState& S) {
-  bool progress = false;
-  std::vector<uint64_t> done;
-  std::vector<std::pair<uint64_t, hipError_t>> failed;
-  for (uint64_t t : S.active) {
-    ServeReq& r = *S.reqs[t];
-    if (r.state != kDraining) continue;
-    const hipError_t q = hipEventQuery(r.drained);
-    if (q == hipSuccess) done.push_back(t);
-    else if (q != hipErrorNotReady) failed.emplace_back(t, q);
-  }
-  for (auto& f : failed) {
-    fail_request(S, *S.reqs[f.first], VSH_E_DEVICE, "observables", f.second);
-    progress = true;
-  }
-  for (uint64_t t : done) {
-    ServeReq& r = *S.reqs[t];
-    const uint64_t n = r.req.n_events;
-    ResultBox* box = new_result(n, r.req.flags & VSH_SUMMARY);
-    if (box) {
-      box->hist.assign(r.h_hist, r.h_hist + kHistDoubles);
-      const bool all_fields = r.h_hs != nullptr;
-      tally_fields(box, all_fields ? r.h_si + kSiStatus * n : r.h_si, n, all_fields ? r.h_sd + kSdW * n : r.h_sd, n);
-      if (!box->sum_d.empty()) {
-        std::memcpy(box->sum_d.data(), r.h_sd, kNSumD * n * 8);
-        std::memcpy(box->sum_i.data(), r.h_si, kNSumI * n * 4);
-        std::memcpy(box->hash.data(), r.h_hs, n * 8);
-      }
-      box->pub.t_total_ms = std::chrono::duration<double, std::milli>(Clock::now() - r.t_arrival).count();
-      finish_result(box);
-    }
-    r.box = box;
-    finish_request(S, r, kFinished);
-    progress = true;
-  }
-  return progress;
-}
-
-// Start the drains that waited for pinned staging, oldest first.
-static bool retry_drains(vsh_ctx* ctx, ServeState& S) {
-  bool progress = false;
-  while (!S.to_drain.empty()) {
-    auto it = S.reqs.find(S.to_drain.front());
-    if (it == S.reqs.end() || it->second->state != kAdmitted || it->second->cancel) {
-      S.to_drain.pop_front();  // gone, cancelled or failed meanwhile
-      progress = true;
-      continue;
-    }
-    if (!start_drain(ctx, S, *it->second)) break;  // still full
-    S.to_drain.pop_front();
-    progress = true;
-  }
+  (void)ctx;
   return progress;
 }
 
@@ -541,12 +543,10 @@ static void serve_loop(vsh_ctx* ctx) {
   std::unique_lock<std::mutex> lk(S.mu);
   while (!S.stop) {
     bool progress = false;
-    progress |= admit(ctx, S);
     progress |= retire_epochs(ctx, S);
-    progress |= poll_drains(S);
-    progress |= retry_drains(ctx, S);
+    progress |= admit(ctx, S);
     while (launch_epoch(ctx, S)) progress = true;
-    if (!progress) S.cv.wait_for(lk, std::chrono::microseconds(100));
+    if (!progress) S.cv.wait_for(lk, std::chrono::microseconds(50));
   }
 }
 
@@ -558,12 +558,10 @@ static vsh_status serve_start(vsh_ctx* ctx) {
   if (err != hipSuccess) return hip_fail(ctx, err, "serving pool");
   err = S->host.init(1ull << 30, true);
   if (err != hipSuccess) return hip_fail(ctx, err, "serving pinned staging");
-  err = hipStreamCreateWithFlags(&S->drain, hipStreamNonBlocking);
-  if (err == hipSuccess) err = hipStreamCreateWithFlags(&S->admit_stream, hipStreamNonBlocking);
-  if (err == hipSuccess) err = hipEventCreateWithFlags(&S->admitted, hipEventDisableTiming);
-  if (err != hipSuccess) return hip_fail(ctx, err, "hipStreamCreate");
   for (auto& E : S->ep) {
     err = hipStreamCreateWithFlags(&E.stream, hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&E.me_done, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&E.shower_done, hipEventDisableTiming);
     if (err == hipSuccess) err = hipEventCreateWithFlags(&E.done, hipEventDisableTiming);
     if (err == hipSuccess) err = hipHostMalloc((void**)&E.reqs_host, kMaxEpochReqs * sizeof(ReqDev), 0);
     if (err == hipSuccess) err = hipHostMalloc((void**)&E.segs_host, kMaxEpochReqs * sizeof(Segment), 0);
@@ -586,25 +584,20 @@ void serve_shutdown(vsh_ctx* ctx) {
   for (auto& E : S->ep) {
     if (E.stream) (void)hipStreamSynchronize(E.stream);
   }
-  if (S->drain) (void)hipStreamSynchronize(S->drain);
-  if (S->admit_stream) (void)hipStreamSynchronize(S->admit_stream);
   for (auto& kv : S->reqs) {
     ServeReq& r = *kv.second;
-    if (r.drained) (void)hipEventDestroy(r.drained);
     if (r.own_host) (void)hipHostFree(r.own_host);
     if (r.box) vsh_result_free(&r.box->pub);
   }
   for (auto& E : S->ep) {
     if (E.dev) (void)hipFree(E.dev);
+    if (E.scratch) (void)hipFree(E.scratch);
     if (E.reqs_host) (void)hipHostFree(E.reqs_host);
     if (E.segs_host) (void)hipHostFree(E.segs_host);
-    if (E.done) (void)hipEventDestroy(E.done);
+    for (hipEvent_t ev : {E.me_done, E.shower_done, E.done})
+      if (ev) (void)hipEventDestroy(ev);
     if (E.stream) (void)hipStreamDestroy(E.stream);
   }
-  if (S->scratch) (void)hipFree(S->scratch);
-  if (S->drain) (void)hipStreamDestroy(S->drain);
-  if (S->admitted) (void)hipEventDestroy(S->admitted);
-  if (S->admit_stream) (void)hipStreamDestroy(S->admit_stream);
   S->pool.destroy();
   S->host.destroy();
   delete S;

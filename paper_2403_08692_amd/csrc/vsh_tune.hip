@@ -7,8 +7,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cinttypes>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "vsh_internal.hpp"
@@ -20,7 +25,7 @@ static uint32_t clampu(uint32_t v, uint32_t lo, uint32_t hi) { return v < lo ? l
 static uint32_t block_choice(uint32_t b) { return b <= 64 ? 64 : (b <= 128 ? 128 : 256); }
 
 static vsh_tuning to_pub(const Tuned& t) {
-  vsh_tuning p;
+  vsh_tuning p{};
   p.plain_block = t.plain_block;
   p.plain_waves = t.plain_waves;
   p.plain_mapping = t.plain_mapping;
@@ -196,6 +201,69 @@ static vsh_status autotune_plain(vsh_ctx* ctx, const vsh_request* req) {
   return VSH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Tuner cache: one line per tuned sample, "<key> <8 settings> <ms>", appended
+// after each tuning; the last line with a matching key wins.  The key names
+// everything the choice depends on: library version, device (architecture
+// and compute units), form, record capacity, sample size and the sample's
+// physics (sqrt(s), t_C or a hash of the per-event arrays, masses, t_over,
+// cycle limit).
+// ---------------------------------------------------------------------------
+static uint64_t fnv_bytes(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 0x100000001b3ull;
+  return h;
+}
+
+static std::string cache_key(const vsh_ctx* ctx, const vsh_request* req) {
+  const uint64_t m = std::min<uint64_t>(req->n_events, 1ull << 18);
+  uint64_t h = 0xcbf29ce484222325ull;
+  if (req->ecm_per_event) h = fnv_bytes(h, req->ecm_per_event, m * 8);
+  if (req->tcut_per_event) h = fnv_bytes(h, req->tcut_per_event, m * 8);
+  char buf[512];
+  std::snprintf(buf, sizeof buf,
+                "vsh%d.%d|gfx950|cu=%d|form=%s|cap=%u|n=%" PRIu64 "|ecm=%.17g|tcut=%.17g|arrays=%016" PRIx64
+                "|mc=%.17g|mb=%.17g|tover=%.17g|climit=%u",
+                VSH_VERSION_MAJOR, VSH_VERSION_MINOR, ctx->n_cu,
+                (req->flags & VSH_FORM_PERSISTENT) ? "persistent" : "plain", req->max_partons, m,
+                req->ecm_per_event ? 0.0 : req->ecm, req->tcut_per_event ? 0.0 : req->t_cut,
+                (req->ecm_per_event || req->tcut_per_event) ? h : 0ull, req->mass_c, req->mass_b, req->t_over,
+                req->cycle_limit);
+  return buf;
+}
+
+// The cached settings of `key`, if the file has them.
+static bool cache_lookup(const std::string& path, const std::string& key, vsh_tuning* t) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string k;
+    vsh_tuning v{};
+    float ms = 0.0f;
+    if (!(is >> k) || k != key) continue;
+    if (is >> v.plain_block >> v.plain_waves >> v.plain_mapping >> v.mapping >> v.waves_per_cu >> v.block >>
+        v.refill_threshold >> v.refill_period >> ms) {
+      *t = v;
+      found = true;
+    }
+  }
+  return found;
+}
+
+static void cache_store(const std::string& path, const std::string& key, const vsh_tuning& v, float ms) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, " %u %u %u %u %u %u %u %u %.6g\n", v.plain_block, v.plain_waves, v.plain_mapping,
+                v.mapping, v.waves_per_cu, v.block, v.refill_threshold, v.refill_period, ms);
+  const std::string line = key + buf;
+  if (FILE* f = std::fopen(path.c_str(), "a")) {  // one write per line: concurrent appends stay whole lines
+    (void)std::fwrite(line.data(), 1, line.size(), f);
+    std::fclose(f);
+  }
+}
+
 }  // namespace vsh
 
 using namespace vsh;
@@ -227,9 +295,36 @@ vsh_status vsh_autotune(vsh_ctx* ctx, const vsh_request* sample, vsh_tuning* cho
     return VSH_E_INVALID;
   }
   (void)hipSetDevice(ctx->device);
-  rc = (sample->flags & VSH_FORM_PERSISTENT) ? autotune_persistent(ctx, sample) : autotune_plain(ctx, sample);
+  const bool persistent = (sample->flags & VSH_FORM_PERSISTENT) != 0;
+  const std::string key = ctx->tuner_cache_path.empty() ? std::string() : cache_key(ctx, sample);
+  vsh_tuning cached{};
+  if (!key.empty() && cache_lookup(ctx->tuner_cache_path, key, &cached)) {
+    const Tuned t = from_pub(cached);
+    if (persistent) {  // only the form that was tuned takes the cached settings
+      ctx->tuned.mapping = t.mapping;
+      ctx->tuned.pers_waves_per_cu = t.pers_waves_per_cu;
+      ctx->tuned.pers_block = t.pers_block;
+      ctx->tuned.refill_threshold = t.refill_threshold;
+      ctx->tuned.refill_period = t.refill_period;
+      destroy_graph(ctx->graph);
+    } else {
+      ctx->tuned.plain_block = t.plain_block;
+      ctx->tuned.plain_waves = t.plain_waves;
+      ctx->tuned.plain_mapping = t.plain_mapping;
+    }
+    if (chosen) {
+      *chosen = to_pub(ctx->tuned);
+      chosen->from_cache = 1;
+    }
+    return VSH_OK;
+  }
+  rc = persistent ? autotune_persistent(ctx, sample) : autotune_plain(ctx, sample);
   if (rc) return rc;
-  if (chosen) *chosen = to_pub(ctx->tuned);
+  if (!key.empty()) cache_store(ctx->tuner_cache_path, key, to_pub(ctx->tuned), persistent ? ctx->tuned_ms : 0.0f);
+  if (chosen) {
+    *chosen = to_pub(ctx->tuned);
+    chosen->from_cache = 0;
+  }
   return VSH_OK;
 }
 
