@@ -201,6 +201,10 @@ typedef struct {
   double t_me_ms, t_shower_ms, t_obs_ms, t_total_ms; /* device time per stage; total is
                                                         host wall clock of the call  */
   uint64_t n_cycle_limit;     /* events stopped by the request's cycle_limit        */
+  uint32_t queue_ahead;       /* served requests: requests waiting for admission ahead
+                                 of this one when it was submitted (0 otherwise)     */
+  double t_queue_ms;          /* served requests: submission to admission (memory
+                                 reserved), host wall clock (0 otherwise)            */
 } vsh_result;
 
 /* Blocking generation (Sec. 3 problem statement; App. C for the shower).

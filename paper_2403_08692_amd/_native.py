@@ -32,7 +32,8 @@ EV_DONE, EV_OVERFLOW, EV_NONFINITE, EV_CONSERVATION = 1, 2, 3, 4
 
 
 class vsh_ctx_opts(C.Structure):
-    _fields_ = [("device", C.c_int), ("mem_budget_bytes", C.c_uint64), ("flags", C.c_uint32)]
+    _fields_ = [("device", C.c_int), ("mem_budget_bytes", C.c_uint64), ("flags", C.c_uint32),
+                ("tuner_cache_path", C.c_char_p)]
 
 
 class vsh_request(C.Structure):
@@ -46,7 +47,7 @@ class vsh_request(C.Structure):
 class vsh_tuning(C.Structure):
     _fields_ = [("plain_block", C.c_uint32), ("mapping", C.c_uint32), ("waves_per_cu", C.c_uint32),
                 ("block", C.c_uint32), ("refill_threshold", C.c_uint32), ("refill_period", C.c_uint32),
-                ("plain_waves", C.c_uint32), ("plain_mapping", C.c_uint32)]
+                ("plain_waves", C.c_uint32), ("plain_mapping", C.c_uint32), ("from_cache", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -67,7 +68,8 @@ class vsh_result(C.Structure):
                 ("total_cycles", C.c_uint64), ("total_trials", C.c_uint64), ("total_ends", C.c_uint64),
                 ("total_emissions", C.c_uint64), ("max_cycles", C.c_uint32),
                 ("t_me_ms", C.c_double), ("t_shower_ms", C.c_double), ("t_obs_ms", C.c_double),
-                ("t_total_ms", C.c_double), ("n_cycle_limit", C.c_uint64)]
+                ("t_total_ms", C.c_double), ("n_cycle_limit", C.c_uint64), ("queue_ahead", C.c_uint32),
+                ("t_queue_ms", C.c_double)]
 
 
 _lib = None
@@ -163,7 +165,7 @@ def result_to_dict(res: vsh_result) -> dict:
                total_cycles=res.total_cycles, total_trials=res.total_trials, total_ends=res.total_ends,
                total_emissions=res.total_emissions, max_cycles=res.max_cycles,
                t_me_ms=res.t_me_ms, t_shower_ms=res.t_shower_ms, t_obs_ms=res.t_obs_ms,
-               t_total_ms=res.t_total_ms)
+               t_total_ms=res.t_total_ms, queue_ahead=res.queue_ahead, t_queue_ms=res.t_queue_ms)
     out["hist"] = _arr(res.hist, HIST_DOUBLES, np.float64).reshape(NOBS, NHCOL, 3)
     out["hist_lo"] = _arr(res.hist_lo, NOBS, np.float64)
     out["hist_hi"] = _arr(res.hist_hi, NOBS, np.float64)
@@ -210,10 +212,11 @@ def make_request(n_events, seed=1, first_event=0, ecm=91.2, t_cut=1.0, max_parto
 class Context:
     """One libvsh context on one device."""
 
-    def __init__(self, device: int = 0, mem_budget_bytes: int = 0):
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 0, tuner_cache_path: str | None = None):
         L = load()
         self._ptr = C.c_void_p()
-        opts = vsh_ctx_opts(device, mem_budget_bytes, 0)
+        opts = vsh_ctx_opts(device, mem_budget_bytes, 0,
+                            tuner_cache_path.encode() if tuner_cache_path else None)
         _check(L.vsh_create(C.byref(opts), C.byref(self._ptr)), None)
 
     @property

@@ -22,13 +22,15 @@ QUARTER = re.compile(r"^v_(mul_lo_u32|mul_hi_u32|mul_hi_i32|mul_lo_i32|mad_u64_u
 
 
 def kernel_counts(asm: str):
+    """Per probe kernel: [VALU instructions, issue slots, issue slots of the
+    FP64 instructions (mnemonics with an _f64 operand type)]."""
     out = {}
     cur = None
     for line in asm.splitlines():
         m = re.match(r"^(probe_\w+):", line)
         if m:
             cur = m.group(1)
-            out[cur] = [0, 0]
+            out[cur] = [0, 0, 0]
             continue
         if cur is None:
             continue
@@ -37,12 +39,17 @@ def kernel_counts(asm: str):
             continue
         ins = line.strip().split(" ")[0]
         if ins.startswith("v_"):
+            w = 4 if QUARTER.match(ins) else 1
             out[cur][0] += 1
-            out[cur][1] += 4 if QUARTER.match(ins) else 1
+            out[cur][1] += w
+            if "_f64" in ins:
+                out[cur][2] += w
     return out
 
 
-def measure():
+def measure(fp64: bool = False):
+    """Issue-slot cost per lane of each building block; with fp64, only its
+    FP64 instructions (the FP64 roofline's count)."""
     sys.path.insert(0, os.path.dirname(HERE))
     from build import FLAGS, HIPCC  # noqa: E402
 
@@ -53,20 +60,21 @@ def measure():
                        check=True, stderr=subprocess.DEVNULL)
         asm = open(s).read()
     c = kernel_counts(asm)
-    base = c["probe_base"][1]
+    col = 2 if fp64 else 1
+    base = c["probe_base"][col]
     costs = {}
-    for k, (_, w) in c.items():
+    for k, v in c.items():
         name = k[len("probe_"):]
         if name in ("base", "philox_base", "unit_base"):
             continue
         ref = base
         if name == "philox":
-            ref = c["probe_philox_base"][1]
+            ref = c["probe_philox_base"][col]
         if name == "unit":
-            ref = c["probe_unit_base"][1]
-        costs[name] = max(w - ref, 1)
+            ref = c["probe_unit_base"][col]
+        costs[name] = max(v[col] - ref, 0 if fp64 else 1)
     return costs
 
 
 if __name__ == "__main__":
-    print(json.dumps(measure(), indent=1, sort_keys=True))
+    print(json.dumps({"all": measure(), "fp64": measure(fp64=True)}, indent=1, sort_keys=True))

@@ -107,7 +107,8 @@ struct ServeReq {
   uint64_t ticket = 0;
   vsh_request req{};
   std::vector<double> ecm, tcut;
-  Clock::time_point t_arrival;
+  Clock::time_point t_arrival, t_admit;
+  uint32_t queue_ahead = 0;  // requests waiting for admission when it was submitted
   int state = kQueued;
   bool cancel = false;
   uint64_t pool_off = 0, pool_bytes = 0;
@@ -221,6 +222,7 @@ static bool admit(vsh_ctx* ctx, ServeState& S) {
     r.pool_bytes = bytes;
     Carver c(S.pool.base + off);
     r.buf = carve_request(c, r.req.n_events, r.req.max_partons, false);
+    r.t_admit = Clock::now();
     r.state = kAdmitted;
     S.active.push_back(r.ticket);
     progress = true;
@@ -495,6 +497,8 @@ static void complete_request(ServeState& S, ServeReq& r) {
       std::memcpy(box->hash.data(), r.h_hs, n * 8);
     }
     box->pub.t_total_ms = std::chrono::duration<double, std::milli>(Clock::now() - r.t_arrival).count();
+    box->pub.t_queue_ms = std::chrono::duration<double, std::milli>(r.t_admit - r.t_arrival).count();
+    box->pub.queue_ahead = r.queue_ahead;
     finish_result(box);
   }
   r.box = box;
@@ -649,6 +653,7 @@ vsh_status vsh_submit(vsh_ctx* ctx, const vsh_request* req, uint64_t* ticket) {
   {
     std::lock_guard<std::mutex> lk(S.mu);
     r->ticket = S.next_ticket++;
+    r->queue_ahead = (uint32_t)S.pending.size();
     *ticket = r->ticket;
     S.pending.push_back(r->ticket);
     S.reqs.emplace(r->ticket, std::move(r));

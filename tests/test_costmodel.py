@@ -14,6 +14,10 @@ def test_cost_table_matches_isa_probe():
     measured = isa_costs.measure()
     for k, v in bench.COST.items():
         assert measured[k] == v, (k, measured[k], v)
+    measured64 = isa_costs.measure(fp64=True)
+    for k, v in bench.COST_F64.items():
+        assert measured64[k] == v, (k, measured64[k], v)
+        assert v <= bench.COST[k]
 
 
 def test_algorithmic_ops_scale():
