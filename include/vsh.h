@@ -232,6 +232,32 @@ vsh_status vsh_shower_records(vsh_ctx *ctx, const vsh_request *req, const uint64
                               const double *p, const int8_t *pid, const uint16_t *col,
                               const uint16_t *acol, vsh_result **out);
 
+/* Initial-state shower (the step to hadron colliders that the paper's
+   conclusions name: PDFs evaluated in the shower).  Drell-Yan events
+   q qbar -> V at hadron centre-of-mass energy sqrt_s_hadron with V of mass
+   Q = req->ecm: flavour uniform over d, u, s, c, b, the quark from either
+   beam, the rapidity of V uniform in |y| < ln(sqrt_s_hadron / Q); each
+   incoming line evolves backwards from t = Q^2 to req->t_cut with the
+   density (alpha_s/2 pi) (dt/t) (dz/z) P_qq(z) f(x/z)/f(x), the other
+   incoming parton its spectator, emissions through the Catani-Seymour
+   initial-initial map (the final state takes the recoil); the emitted
+   gluons do not radiate.  No parton-density set is available, so f is a
+   closed-form stand-in, f(x) = (63/128) x^(-1/2) (1 - x)^3 for every quark
+   and antiquark (with a gluon 3 x^(-1) (1 - x)^5 the momentum sum rule holds).
+   Records: slot 0 the incoming parton from beam A (+z), 1 from beam B,
+   2 V (pid 23), then the emitted gluons.  Weights (arbitrary units): the
+   parton luminosity's rapidity density for a unit partonic cross-section,
+   10 (2Y) tau f(x_A) f(x_B).  Summary double fields: 0 w, 1 y_V, 2 p_T,V,
+   3 x_A, 4 x_B (final fractions), 5 p_T of the hardest gluon; int fields
+   as vsh_generate's (flavour +f with the quark from beam A, -f from B).
+   Histograms: 0 log10(p_T,V / GeV) [-1, 3], 1 y_V [-5, 5], 2 emitted gluons
+   [0, 50], 3 log10(p_T / GeV) of the hardest gluon [-1, 3] (rows 4-7 unused;
+   hist_lo / hist_hi give the ranges).  One lane per event, plain form.
+   Errors: those of vsh_generate, and VSH_E_INVALID for flags other than
+   VSH_SUMMARY | VSH_RECORDS, per-event arrays, a cycle limit, t_over or
+   masses, max_partons < 3, sqrt_s_hadron <= Q, or t_cut >= Q^2 / 4. */
+vsh_status vsh_generate_isr(vsh_ctx *ctx, const vsh_request *req, double sqrt_s_hadron, vsh_result **out);
+
 /* Device-side generation into caller-owned device memory, on the caller's
    HIP stream, with no allocation and no host synchronisation: the launch
    sequence of vsh_generate without its copies, i.e. the problem statement of

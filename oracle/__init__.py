@@ -108,6 +108,24 @@ def lib():
     L.or_generate.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, _dp, C.c_double, _dp, C.c_double,
                               C.c_int, C.c_int, C.c_double, _dp, _dp, _i32p, _u64p, _dp, _i32p, _dp, _i32p, _i32p, _i32p, _u64p]
     L.or_generate.restype = C.c_int
+    L.or_pdf_q.argtypes = [C.c_double]
+    L.or_pdf_q.restype = C.c_double
+    L.or_pdf_g.argtypes = [C.c_double]
+    L.or_pdf_g.restype = C.c_double
+    L.or_isr_zlimits.argtypes = [C.c_double] * 3 + [_dp, _dp]
+    L.or_isr_zlimits.restype = C.c_int
+    L.or_isr_ratio.argtypes = [C.c_double] * 4
+    L.or_isr_ratio.restype = C.c_double
+    L.or_isr_me.argtypes = [C.c_uint64, C.c_uint64, C.c_double, C.c_double, _ip, _ip, _dp, _dp, _dp, _dp, _dp]
+    L.or_isr_shower.argtypes = [C.c_uint64, C.c_uint64, C.c_double, C.c_double, C.c_int, C.c_int, _ip, _dp, _ip, _ip,
+                                _ip, _dp, _dp, _ip, _u64p, _ip, _dp, C.c_int, _u64p]
+    L.or_isr_shower.restype = C.c_int
+    L.or_isr_validate.argtypes = [C.c_int, _dp, C.c_double]
+    L.or_isr_validate.restype = C.c_int
+    L.or_isr_hist_ranges.argtypes = [_dp, _dp]
+    L.or_isr_generate.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_double, C.c_double, C.c_double, C.c_int,
+                                  _dp, _i32p, _u64p, _dp, _i32p, _dp, _i32p, _i32p, _i32p, _u64p]
+    L.or_isr_generate.restype = C.c_int
     _lib = L
     return L
 
@@ -358,6 +376,100 @@ def generate(seed, first, n_events, ecm=91.2, tcut=1.0, cap=64, records=False, e
                            int(cap), int(max_cycles), float(t_over), _ptr(_mass_table(mass), _dp), _ptr(sum_d, _dp), _ptr(sum_i, _i32p), _ptr(hsh, _u64p), _ptr(hist, _dp),
                            _ptr(rec.get("n"), _i32p), _ptr(rec.get("p"), _dp), _ptr(rec.get("pid"), _i32p),
                            _ptr(rec.get("col"), _i32p), _ptr(rec.get("acol"), _i32p), _ptr(work, _u64p))
+    if rc != 0:
+        raise ValueError("oracle: bad arguments")
+    out = dict(sum_d=sum_d, sum_i=sum_i, hash=hsh, hist=hist, work=work)
+    if records:
+        out["rec"] = rec
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Initial-state shower of Drell-Yan events (closed-form stand-in density)
+# ---------------------------------------------------------------------------
+def pdf_q(x):
+    return lib().or_pdf_q(float(x))
+
+
+def pdf_g(x):
+    return lib().or_pdf_g(float(x))
+
+
+def isr_zlimits(x, st, tcut):
+    lo, hi = C.c_double(), C.c_double()
+    ok = lib().or_isr_zlimits(float(x), float(st), float(tcut), C.byref(lo), C.byref(hi))
+    return (lo.value, hi.value) if ok else None
+
+
+def isr_ratio(t, z, x, st):
+    return lib().or_isr_ratio(float(t), float(z), float(x), float(st))
+
+
+def isr_me(seed, event, sqrt_s_had, q):
+    f, qa = C.c_int(), C.c_int()
+    y, w, xa, xb = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    p = np.zeros(12)
+    lib().or_isr_me(seed, event, float(sqrt_s_had), float(q), C.byref(f), C.byref(qa), C.byref(y), C.byref(w),
+                    C.byref(xa), C.byref(xb), _ptr(p, _dp))
+    return dict(flavour=f.value, quark_from_a=bool(qa.value), y=y.value, weight=w.value, xa=xa.value, xb=xb.value,
+                p=p.reshape(3, 4))
+
+
+def isr_shower(seed, event, q, tcut, p, pid, col, acol, xa, xb, cap=64, max_emit=-1, max_log=64):
+    """Backward evolution of one Drell-Yan event from the partons given
+    (incoming from A, incoming from B, then the final state)."""
+    n0 = len(pid)
+    P = np.zeros((cap, 4))
+    P[:n0] = np.asarray(p, np.float64).reshape(n0, 4)
+    PID = np.zeros(cap, np.intc)
+    COL = np.zeros(cap, np.intc)
+    ACOL = np.zeros(cap, np.intc)
+    PID[:n0], COL[:n0], ACOL[:n0] = pid, col, acol
+    n = C.c_int(n0)
+    XA, XB = C.c_double(xa), C.c_double(xb)
+    cyc, nemit = C.c_int(), C.c_int()
+    h = C.c_uint64()
+    log = np.zeros((max_log, NLOG))
+    work = np.zeros(NWORK, np.uint64)
+    st = lib().or_isr_shower(seed, event, float(q), float(tcut), cap, max_emit, C.byref(n), _ptr(P, _dp),
+                             _ptr(PID, _ip), _ptr(COL, _ip), _ptr(ACOL, _ip), C.byref(XA), C.byref(XB),
+                             C.byref(cyc), C.byref(h), C.byref(nemit), _ptr(log, _dp), max_log, _ptr(work, _u64p))
+    m = n.value
+    return dict(status=st, n=m, p=P[:m].copy(), pid=PID[:m].copy(), col=COL[:m].copy(), acol=ACOL[:m].copy(),
+                xa=XA.value, xb=XB.value, cycles=cyc.value, hash=h.value, n_emit=nemit.value,
+                log=log[:min(nemit.value, max_log)].copy(), work=work)
+
+
+def isr_validate(p, q):
+    p, n = _as_p(p)
+    return lib().or_isr_validate(n, _ptr(p, _dp), float(q))
+
+
+def isr_hist_ranges():
+    lo, hi = np.zeros(NOBS), np.zeros(NOBS)
+    lib().or_isr_hist_ranges(_ptr(lo, _dp), _ptr(hi, _dp))
+    return lo, hi
+
+
+def isr_generate(seed, first, n_events, sqrt_s_had, q, tcut, cap=64, records=False):
+    """Drell-Yan events through start, backward shower, validation,
+    observables and histograms; the layout of generate()'s outputs (sum_d
+    per event: w, y_V, p_T,V, x_A, x_B, hardest gluon p_T, 0...)."""
+    n_events = int(n_events)
+    sum_d = np.zeros((n_events, NSUM_D))
+    sum_i = np.zeros((n_events, NSUM_I), np.int32)
+    hsh = np.zeros(n_events, np.uint64)
+    hist = np.zeros((NOBS, NHCOL, 3))
+    work = np.zeros(NWORK, np.uint64)
+    rec = {}
+    if records:
+        rec = dict(n=np.zeros(n_events, np.int32), p=np.zeros((n_events, cap, 4)),
+                   pid=np.zeros((n_events, cap), np.int32), col=np.zeros((n_events, cap), np.int32),
+                   acol=np.zeros((n_events, cap), np.int32))
+    rc = lib().or_isr_generate(seed, first, n_events, float(sqrt_s_had), float(q), float(tcut), int(cap),
+                               _ptr(sum_d, _dp), _ptr(sum_i, _i32p), _ptr(hsh, _u64p), _ptr(hist, _dp),
+                               _ptr(rec.get("n"), _i32p), _ptr(rec.get("p"), _dp), _ptr(rec.get("pid"), _i32p),
+                               _ptr(rec.get("col"), _i32p), _ptr(rec.get("acol"), _i32p), _ptr(work, _u64p))
     if rc != 0:
         raise ValueError("oracle: bad arguments")
     out = dict(sum_d=sum_d, sum_i=sum_i, hash=hsh, hist=hist, work=work)

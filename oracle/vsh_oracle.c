@@ -952,6 +952,344 @@ int or_validate_massive(int n, const double *p, const int *pid, double ecm, cons
 
 int or_validate(int n, const double *p, double ecm) { return or_validate_massive(n, p, NULL, ecm, NULL); }
 
+/* ---------------------------------------------------------------------- */
+/* Initial-state shower (the step to hadron colliders that the conclusions */
+/* name: an extra step to evaluate PDFs).  No PDF set is available here, so */
+/* a closed-form density stands in for one: every light quark and          */
+/* antiquark flavour has f(x) = (63/128) x^(-1/2) (1 - x)^3 and the gluon   */
+/* g(x) = 3 x^(-1) (1 - x)^5, independent of the scale; the ten quark and   */
+/* antiquark densities carry half the momentum and the gluon the other      */
+/* half (momentum sum rule).                                               */
+/*                                                                          */
+/* Hard process: q qbar -> colour singlet V of mass Q (Drell-Yan) at hadron */
+/* centre-of-mass energy sqrt(S): flavour uniform over d, u, s, c, b, the   */
+/* quark from either beam, rapidity y of V uniform in |y| < ln(sqrt(S)/Q),  */
+/* x_A = sqrt(tau) e^y, x_B = sqrt(tau) e^-y, tau = Q^2/S; weight (arbitrary */
+/* units: the rapidity density of the parton luminosity for a unit partonic */
+/* cross-section) 10 (2 Y) tau f(x_A) f(x_B).                               */
+/*                                                                          */
+/* Shower: each incoming line evolves backwards from t = Q^2 with the       */
+/* density (alpha_s(t)/2 pi) (dt/t) (dz/z) P_qq(z) f(x/z)/f(x), P_qq(z) =    */
+/* C_F (1 + z^2)/(1 - z), x the line's current momentum fraction; the other */
+/* incoming parton is the spectator; the two lines' trials compete (largest */
+/* t wins) as the dipole ends of the final-state shower do.  An emission at */
+/* (t, z) uses the Catani-Seymour initial-initial map: the emitter becomes  */
+/* p_a/z (fraction x/z), the gluon p_j = (1 - z - v) p_a/z + v p_b + kT with */
+/* kT^2 = -t and v(1 - z - v) = t z / s~ (s~ = 2 p_a.p_b before the emission, */
+/* smaller root), and every final-state momentum is carried by the Lorentz  */
+/* transformation that takes the old final-state total to the new one.  The */
+/* emitted gluons do not radiate (this branch evolves the incoming lines    */
+/* only).  The overestimate 2 C_F x^(-1/2)/(1 - z) bounds the density      */
+/* (z^(-1/2) ((1 - x/z)/(1 - x))^3 <= x^(-1/2) for x <= z <= 1).            */
+/* ---------------------------------------------------------------------- */
+double or_pdf_q(double x) { return x > 0.0 && x < 1.0 ? (63.0 / 128.0) / sqrt(x) * pow(1.0 - x, 3.0) : 0.0; }
+double or_pdf_g(double x) { return x > 0.0 && x < 1.0 ? 3.0 / x * pow(1.0 - x, 5.0) : 0.0; }
+
+/* z range of the overestimate for a line at fraction x in a dipole of
+   s~ = 2 p_a.p_b: from x (the parent's fraction stays below 1) up to where
+   kT^2 = t_C needs (1 - z)^2 = 4 t_C z / s~.  Returns 0 without phase space. */
+int or_isr_zlimits(double x, double st, double tcut, double *zlo, double *zhi) {
+  double a = tcut / st;
+  double zmax = 1.0 + 2.0 * a - 2.0 * sqrt(a + a * a);
+  if (!(zmax > x)) return 0;
+  *zlo = x;
+  *zhi = zmax;
+  return 1;
+}
+
+/* true over trial density of an emission at (t, z) of a line at fraction x
+   (without alpha_s): P_qq(z)/z f(x/z)/f(x) / O(z); -1 outside the phase
+   space (no real v at this t) */
+double or_isr_ratio(double t, double z, double x, double st) {
+  double disc = (1.0 - z) * (1.0 - z) - 4.0 * t * z / st;
+  if (!(disc >= 0.0) || !(z > x)) return -1.0;
+  double p = CF * (1.0 + z * z) / (1.0 - z);
+  double dens = p / z * or_pdf_q(x / z) / or_pdf_q(x);
+  double over = 2.0 * CF / sqrt(x) / (1.0 - z);
+  return dens / over;
+}
+
+/* Catani-Seymour initial-initial map of an emission at (t, z) off the
+   incoming pa with spectator pb: new incoming pa/z, the gluon, and the
+   transformation of the final state (applied to k[0..nk-1] in place). */
+static void isr_map(double *pa, const double *pb, double t, double z, double phi, double *pj, double *k, int nk) {
+  double st = 2.0 * mdot(pa, pb);
+  double v = 0.5 * ((1.0 - z) - sqrt((1.0 - z) * (1.0 - z) - 4.0 * t * z / st));
+  double Kt[4], K[4], na[4];
+  for (int m = 0; m < 4; ++m) {
+    Kt[m] = pa[m] + pb[m];
+    na[m] = pa[m] / z;
+  }
+  /* transverse basis: both incoming momenta are along the beam axis */
+  double kt = sqrt(t);
+  double kp[4] = {0.0, kt * cos(phi), kt * sin(phi), 0.0};
+  for (int m = 0; m < 4; ++m) {
+    pj[m] = (1.0 - z - v) * na[m] + v * pb[m] + kp[m];
+    K[m] = na[m] + pb[m] - pj[m];
+  }
+  /* Lambda = g - 2 (K + Kt)(K + Kt)/(K + Kt)^2 + 2 K Kt / Kt^2 */
+  double S[4];
+  for (int m = 0; m < 4; ++m) S[m] = K[m] + Kt[m];
+  double s2 = mdot(S, S), kt2 = mdot(Kt, Kt);
+  for (int q = 0; q < nk; ++q) {
+    double *x = &k[4 * q];
+    double sx = mdot(S, x), ktx = mdot(Kt, x);
+    double y[4];
+    for (int m = 0; m < 4; ++m) y[m] = x[m] - 2.0 * S[m] * sx / s2 + 2.0 * K[m] * ktx / kt2;
+    for (int m = 0; m < 4; ++m) x[m] = y[m];
+  }
+  for (int m = 0; m < 4; ++m) pa[m] = na[m];
+}
+
+/* Start of a Drell-Yan event (above): partons [from beam A, from beam B, V]. */
+void or_isr_me(uint64_t seed, uint64_t event, double sqrt_s_had, double q, int *flavour, int *quark_from_a,
+               double *rapidity, double *weight, double *xa, double *xb, double p[12]) {
+  uint32_t w[4];
+  or_draw(seed, event, 0, OR_P_ME, 0, w);
+  int f = 1 + (int)(((uint64_t)w[0] * 5u) >> 32);
+  int qa = (w[1] & 1u) == 0;
+  double Y = log(sqrt_s_had / q);
+  double y = -Y + 2.0 * Y * or_uniform(w[2], w[3]);
+  double tau = q * q / (sqrt_s_had * sqrt_s_had);
+  double a = sqrt(tau) * exp(y), b = sqrt(tau) * exp(-y);
+  double e = 0.5 * sqrt_s_had;
+  double pa[4] = {a * e, 0.0, 0.0, a * e}, pb[4] = {b * e, 0.0, 0.0, -b * e};
+  for (int m = 0; m < 4; ++m) {
+    p[m] = pa[m];
+    p[4 + m] = pb[m];
+    p[8 + m] = pa[m] + pb[m];
+  }
+  *flavour = f;
+  *quark_from_a = qa;
+  *rapidity = y;
+  *xa = a;
+  *xb = b;
+  *weight = 10.0 * (2.0 * Y) * tau * or_pdf_q(a) * or_pdf_q(b);
+}
+
+/* Shower of one Drell-Yan event whose n partons (incoming a, incoming b,
+   then the final state) are in p/pid/col/acol (length cap), with the
+   current fractions *xa, *xb; updated in place.  Kernel id 16 marks an
+   initial-state q -> q g in the emission hash.  Returns the status. */
+int or_isr_shower(uint64_t seed, uint64_t event, double q, double tcut, int cap, int max_emit, int *n,
+                  double *p, int *pid, int *col, int *acol, double *xa, double *xb, int *cycles,
+                  uint64_t *emit_hash, int *n_emit, double *emit_log, int max_log, uint64_t *work) {
+  int np = *n;
+  double t = q * q;
+  double asmax = or_alpha_s(tcut);
+  int next_col = 1;
+  for (int i = 0; i < np; ++i) {
+    if (col[i] >= next_col) next_col = col[i] + 1;
+    if (acol[i] >= next_col) next_col = acol[i] + 1;
+  }
+  double x[2] = {*xa, *xb};
+  int status = OR_RUNNING;
+  uint32_t cycle = 0;
+  int nemit = 0;
+  uint64_t hash = 0xcbf29ce484222325ull;
+  while (status == OR_RUNNING) {
+    double st = 2.0 * mdot(&p[0], &p[4]);
+    double winner_t = tcut;
+    int wl = -1;
+    double wzlo = 0.0, wzhi = 0.0;
+    for (int l = 0; l < 2; ++l) { /* line l (slot l) with spectator slot 1 - l */
+      if (work) work[1]++;
+      double zlo, zhi;
+      if (!or_isr_zlimits(x[l], st, tcut, &zlo, &zhi)) continue;
+      if (work) work[2]++;
+      double c = asmax / (2.0 * OR_PI) * 2.0 * CF / sqrt(x[l]) * log((1.0 - zlo) / (1.0 - zhi));
+      uint32_t w[4];
+      or_draw(seed, event, cycle, OR_P_TRIAL, trial_slot(l, 1 - l, 0), w);
+      double t_try = t * pow(or_uniform(w[0], w[1]), 1.0 / c);
+      if (work) work[3]++;
+      if (t_try > winner_t) {
+        winner_t = t_try;
+        wl = l;
+        wzlo = zlo;
+        wzhi = zhi;
+      }
+    }
+    uint32_t this_cycle = cycle++;
+    if (work) work[0]++;
+    if (wl < 0) {
+      status = OR_DONE;
+      break;
+    }
+    t = winner_t;
+    uint32_t a4[4];
+    or_draw(seed, event, this_cycle, OR_P_ACCEPT, 0, a4);
+    double z = 1.0 - (1.0 - wzlo) * pow((1.0 - wzhi) / (1.0 - wzlo), or_uniform(a4[0], a4[1]));
+    double r = or_isr_ratio(t, z, x[wl], st);
+    if (r < 0.0) continue;
+    if (work) work[5]++;
+    if (!(or_uniform(a4[2], a4[3]) < or_alpha_s(t) / asmax * r)) continue;
+    if (np == cap) {
+      status = OR_OVERFLOW;
+      break;
+    }
+    uint32_t sd[4];
+    or_draw(seed, event, this_cycle, OR_P_SPLIT, 0, sd);
+    double phi = 2.0 * OR_PI * or_uniform(sd[0], sd[1]);
+    double pj[4];
+    isr_map(&p[4 * wl], &p[4 * (1 - wl)], t, z, phi, pj, &p[8], np - 2);
+    for (int m = 0; m < 4; ++m) p[4 * np + m] = pj[m];
+    x[wl] /= z;
+    /* the gluon goes onto the emitter's colour line */
+    int m = next_col++;
+    pid[np] = 21;
+    if (col[wl] != 0) {
+      col[np] = col[wl];
+      acol[np] = m;
+      col[wl] = m;
+    } else {
+      col[np] = m;
+      acol[np] = acol[wl];
+      acol[wl] = m;
+    }
+    if (emit_log && nemit < max_log) {
+      double *e = &emit_log[OR_NLOG * nemit];
+      e[0] = t;
+      e[1] = z;
+      e[2] = x[wl];
+      e[3] = 16.0;
+      e[4] = (double)wl;
+      e[5] = (double)(1 - wl);
+      e[6] = phi;
+    }
+    hash = fnv_step(hash, 16u);
+    hash = fnv_step(hash, (uint32_t)wl);
+    hash = fnv_step(hash, (uint32_t)(1 - wl));
+    ++np;
+    ++nemit;
+    if (work) work[4]++;
+    if (max_emit >= 0 && nemit >= max_emit) status = OR_STOPPED;
+  }
+  *n = np;
+  *xa = x[0];
+  *xb = x[1];
+  if (cycles) *cycles = (int)cycle;
+  if (emit_hash) *emit_hash = hash;
+  if (n_emit) *n_emit = nemit;
+  return status;
+}
+
+/* Validation of a Drell-Yan event: finite; the final state (slots 2..n-1)
+   carries the incoming total to 1e-10 of its energy per component; V on its
+   mass shell Q and the others massless within 1e-10 of the incoming s. */
+int or_isr_validate(int n, const double *p, double q) {
+  for (int a = 0; a < 4 * n; ++a) {
+    if (isfinite(p[a])) continue;
+    return OR_NONFINITE;
+  }
+  double in[4], out[4] = {0, 0, 0, 0};
+  for (int m = 0; m < 4; ++m) in[m] = p[m] + p[4 + m];
+  for (int a = 2; a < n; ++a)
+    for (int m = 0; m < 4; ++m) out[m] += p[4 * a + m];
+  double tol = 1e-10 * in[0], s = mdot(in, in);
+  for (int m = 0; m < 4; ++m)
+    if (fabs(out[m] - in[m]) > tol) return OR_CONSERVATION;
+  for (int a = 0; a < n; ++a) {
+    double m2 = a == 2 ? q * q : 0.0;
+    if (fabs(mdot(&p[4 * a], &p[4 * a]) - m2) > 1e-10 * s) return OR_CONSERVATION;
+  }
+  return OR_DONE;
+}
+
+/* Histogram ranges of the Drell-Yan branch: log10(p_T,V / GeV), y_V,
+   emitted gluons, log10(p_T / GeV) of the hardest gluon; the other four
+   rows are unused. */
+void or_isr_hist_ranges(double lo[OR_NOBS], double hi[OR_NOBS]) {
+  static const double L[OR_NOBS] = {-1.0, -5.0, 0.0, -1.0, 0.0, 0.0, 0.0, 0.0};
+  static const double H[OR_NOBS] = {3.0, 5.0, 50.0, 3.0, 1.0, 1.0, 1.0, 1.0};
+  for (int h = 0; h < OR_NOBS; ++h) {
+    lo[h] = L[h];
+    hi[h] = H[h];
+  }
+}
+
+static void hist_fill(double *hist, int h, double x, double w, const double *lo, const double *hi);
+
+/* Whole Drell-Yan pipeline over events first .. first+n_events-1: start,
+   shower, validation, observables (p_T,V, y_V, gluons, hardest gluon p_T),
+   histograms.  sum_d per event: w, y_V, p_T,V, x_A, x_B, hardest gluon p_T,
+   then 0; sum_i as or_generate (flavour = +f for the quark from beam A, -f
+   from beam B). */
+int or_isr_generate(uint64_t seed, uint64_t first, uint64_t n_events, double sqrt_s_had, double q, double tcut,
+                    int cap, double *sum_d, int32_t *sum_i, uint64_t *sum_hash, double *hist, int32_t *rec_n,
+                    double *rec_p, int32_t *rec_pid, int32_t *rec_col, int32_t *rec_acol, uint64_t *work) {
+  enum { MAXCAP = 1024 };
+  if (cap < 3 || cap > MAXCAP || !(sqrt_s_had > q) || !(q > 0.0)) return -1;
+  static double p[4 * MAXCAP];
+  static int pid[MAXCAP], col[MAXCAP], acol[MAXCAP];
+  double lo[OR_NOBS], hi[OR_NOBS];
+  or_isr_hist_ranges(lo, hi);
+  for (uint64_t e = 0; e < n_events; ++e) {
+    uint64_t ev = first + e;
+    int f, qa;
+    double y, w, xa, xb;
+    or_isr_me(seed, ev, sqrt_s_had, q, &f, &qa, &y, &w, &xa, &xb, p);
+    pid[0] = qa ? f : -f;
+    pid[1] = qa ? -f : f;
+    pid[2] = 23;
+    col[0] = qa ? 1 : 0;
+    acol[0] = qa ? 0 : 1;
+    col[1] = qa ? 0 : 1;
+    acol[1] = qa ? 1 : 0;
+    col[2] = acol[2] = 0;
+    int n = 3, cycles = 0, nemit = 0;
+    uint64_t hash = 0;
+    uint64_t ew[OR_NWORK] = {0, 0, 0, 0, 0, 0};
+    int status = or_isr_shower(seed, ev, q, tcut, cap, -1, &n, p, pid, col, acol, &xa, &xb, &cycles, &hash, &nemit,
+                               NULL, 0, ew);
+    if (work)
+      for (int k = 0; k < OR_NWORK; ++k) work[k] += ew[k];
+    if (status == OR_DONE) status = or_isr_validate(n, p, q);
+    double ptv = sqrt(p[9] * p[9] + p[10] * p[10]);
+    double yv = 0.5 * log((p[8] + p[11]) / (p[8] - p[11]));
+    double ptg = 0.0;
+    for (int a = 3; a < n; ++a) {
+      double pt = sqrt(p[4 * a + 1] * p[4 * a + 1] + p[4 * a + 2] * p[4 * a + 2]);
+      if (pt > ptg) ptg = pt;
+    }
+    if (status == OR_DONE && hist) {
+      hist_fill(hist, 0, ptv > 0.0 ? log10(ptv) : -INFINITY, w, lo, hi);
+      hist_fill(hist, 1, yv, w, lo, hi);
+      hist_fill(hist, 2, (double)nemit, w, lo, hi);
+      hist_fill(hist, 3, ptg > 0.0 ? log10(ptg) : -INFINITY, w, lo, hi);
+    }
+    if (sum_d) {
+      double *d = &sum_d[OR_NSUM_D * e];
+      for (int k = 0; k < OR_NSUM_D; ++k) d[k] = 0.0;
+      d[0] = w;
+      d[1] = yv;
+      d[2] = ptv;
+      d[3] = xa;
+      d[4] = xb;
+      d[5] = ptg;
+    }
+    if (sum_i) {
+      int32_t *si = &sum_i[OR_NSUM_I * e];
+      si[0] = n;
+      si[1] = status;
+      si[2] = cycles;
+      si[3] = nemit;
+      si[4] = qa ? f : -f;
+      si[5] = (int32_t)ew[3];
+      si[6] = (int32_t)ew[2];
+    }
+    if (sum_hash) sum_hash[e] = hash;
+    if (rec_n) rec_n[e] = n;
+    if (rec_p)
+      for (int a = 0; a < 4 * n; ++a) rec_p[(size_t)4 * cap * e + a] = p[a];
+    for (int a = 0; a < n; ++a) {
+      if (rec_pid) rec_pid[(size_t)cap * e + a] = pid[a];
+      if (rec_col) rec_col[(size_t)cap * e + a] = col[a];
+      if (rec_acol) rec_acol[(size_t)cap * e + a] = acol[a];
+    }
+  }
+  return 0;
+}
+
 /* obs = {y23, y34, tau = 1 - T, C, rho_H, B_T, B_W} */
 void or_observables(int n, const double *p, double ecm, double obs[7]) {
   double s = ecm * ecm;

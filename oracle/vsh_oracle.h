@@ -129,6 +129,23 @@ int or_shower(uint64_t seed, uint64_t event, double ecm, double tcut, int cap,
               int *col, int *acol, int *cycles, uint64_t *emit_hash, int *n_emit,
               double *weight, double *emit_log, int max_log, uint64_t *work);
 
+/* Initial-state shower of Drell-Yan events with a closed-form stand-in
+   parton density (no PDF set is available); see vsh_oracle.c. */
+double or_pdf_q(double x);
+double or_pdf_g(double x);
+int    or_isr_zlimits(double x, double st, double tcut, double *zlo, double *zhi);
+double or_isr_ratio(double t, double z, double x, double st);
+void   or_isr_me(uint64_t seed, uint64_t event, double sqrt_s_had, double q, int *flavour, int *quark_from_a,
+                 double *rapidity, double *weight, double *xa, double *xb, double p[12]);
+int    or_isr_shower(uint64_t seed, uint64_t event, double q, double tcut, int cap, int max_emit, int *n,
+                     double *p, int *pid, int *col, int *acol, double *xa, double *xb, int *cycles,
+                     uint64_t *emit_hash, int *n_emit, double *emit_log, int max_log, uint64_t *work);
+int    or_isr_validate(int n, const double *p, double q);
+void   or_isr_hist_ranges(double lo[OR_NOBS], double hi[OR_NOBS]);
+int    or_isr_generate(uint64_t seed, uint64_t first, uint64_t n_events, double sqrt_s_had, double q, double tcut,
+                       int cap, double *sum_d, int32_t *sum_i, uint64_t *sum_hash, double *hist, int32_t *rec_n,
+                       double *rec_p, int32_t *rec_pid, int32_t *rec_col, int32_t *rec_acol, uint64_t *work);
+
 /* observables */
 double or_thrust(int n, const double *p, double axis[3]);
 void   or_durham(int n, const double *p, double s, double *y23, double *y34);

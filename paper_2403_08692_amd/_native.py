@@ -108,6 +108,8 @@ def load():
     L.vsh_generate_into.restype = C.c_int
     L.vsh_generate_into_static.argtypes = [P, C.POINTER(vsh_request), P, P, P, P, P]
     L.vsh_generate_into_static.restype = C.c_int
+    L.vsh_generate_isr.argtypes = [P, C.POINTER(vsh_request), C.c_double, C.POINTER(C.POINTER(vsh_result))]
+    L.vsh_generate_isr.restype = C.c_int
     L.vsh_workspace_size.argtypes = [C.POINTER(vsh_request)]
     L.vsh_workspace_size.restype = C.c_uint64
     L.vsh_submit.argtypes = [P, C.POINTER(vsh_request), C.POINTER(C.c_uint64)]
@@ -137,7 +139,7 @@ def load():
 EXPORTS = ["vsh_create", "vsh_destroy", "vsh_last_error", "vsh_generate", "vsh_result_free",
            "vsh_shower_records", "vsh_generate_into", "vsh_workspace_size", "vsh_submit", "vsh_poll",
            "vsh_wait", "vsh_cancel", "vsh_timing_start", "vsh_timing_read", "vsh_get_tuning", "vsh_set_tuning",
-           "vsh_autotune", "vsh_test_fail_epochs", "vsh_generate_into_static"]
+           "vsh_autotune", "vsh_test_fail_epochs", "vsh_generate_into_static", "vsh_generate_isr"]
 
 
 class VshError(RuntimeError):
@@ -252,6 +254,19 @@ class Context:
                                  ecm_per_event, tcut_per_event, cycle_limit, t_over, mass_c, mass_b)
         res = C.POINTER(vsh_result)()
         _check(load().vsh_generate(self._ptr, C.byref(req), C.byref(res)), self._ptr)
+        try:
+            return result_to_dict(res.contents)
+        finally:
+            load().vsh_result_free(res)
+
+    def generate_isr(self, n_events, sqrt_s_hadron=1960.0, q=91.2, t_cut=1.0, seed=1, first_event=0, max_partons=64,
+                     summary=True, records=False):
+        """vsh_generate_isr: Drell-Yan events with the initial-state shower
+        (closed-form stand-in parton density)."""
+        flags = (VSH_SUMMARY if summary else 0) | (VSH_RECORDS if records else 0)
+        req, keep = make_request(n_events, seed, first_event, q, t_cut, max_partons, flags)
+        res = C.POINTER(vsh_result)()
+        _check(load().vsh_generate_isr(self._ptr, C.byref(req), float(sqrt_s_hadron), C.byref(res)), self._ptr)
         try:
             return result_to_dict(res.contents)
         finally:

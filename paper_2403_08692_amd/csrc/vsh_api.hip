@@ -486,7 +486,7 @@ static vsh_status run_plain_chunk(vsh_ctx* ctx, const vsh_request* req, uint64_t
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(ctx->ev[1], st));
-  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, L.sum, in, (uint32_t)count, L.cache, ctx->tuned.plain_waves, st);
+  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, L.sum, in, (uint32_t)count, L.cache, st);
   else launch_shower_plain(L.rec, L.sum, in, (uint32_t)count, ctx->tuned.plain_block, ctx->tuned.plain_waves, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(ctx->ev[2], st));
@@ -599,7 +599,7 @@ vsh_status plain_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void
   if (tev) (void)hipEventRecord(tev[0], st);
   launch_me(L.rec, sum, in, (uint32_t)n, st);
   if (tev) (void)hipEventRecord(tev[1], st);
-  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, sum, in, (uint32_t)n, L.cache, ctx->tuned.plain_waves, st);
+  if (ctx->tuned.plain_mapping == kMapFlat) launch_shower_plain_flat(L.rec, sum, in, (uint32_t)n, L.cache, st);
   else launch_shower_plain(L.rec, sum, in, (uint32_t)n, ctx->tuned.plain_block, ctx->tuned.plain_waves, st);
   if (tev) (void)hipEventRecord(tev[2], st);
   launch_obs(L.rec, sum, in, L.sc, (uint32_t)n, dev_hist, st);

@@ -658,12 +658,11 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
 // Plain one-launch form with the flattened mapping: wave w owns events
 // 64w .. 64w+63 of the batch (already started by k_me) from start to cutoff,
 // with no refill; finished lanes only stop contributing trial work.
-// Compiled for 2 and 3 resident waves per SIMD (register budgets 256 and
-// 168; the shared state of about 15 KB per wave lets at most 10 waves share
-// a CU); the autotuner picks by timing.
-template <bool kMassive, int kWaves>
-__global__ void __launch_bounds__(64, kWaves) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n,
-                                                                  EndCache ec) {
+// Two resident waves per SIMD (a budget of 256 registers): held to 168
+// registers for a third wave the kernel spills and ran 40% slower on LEP.
+template <bool kMassive>
+__global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n,
+                                                             EndCache ec) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
   const uint32_t words = mask_words(r.cap);
@@ -695,17 +694,13 @@ size_t flat_lds_bytes(uint32_t cap) { return (size_t)2 * 64 * ((cap + 63) / 64) 
 
 // cache: [event][cap] entries of kCacheWords words (column = event), or null
 void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
-                              uint64_t* cache, uint32_t waves, hipStream_t st) {
+                              uint64_t* cache, hipStream_t st) {
   if (!n) return;
   const EndCache ec{cache, r.cap};
   const dim3 g((n + 63) / 64), b(64);
   const size_t lds = flat_lds_bytes(r.cap);
-  if (in.massive)
-    hipLaunchKernelGGL((k_shower_plain_flat<true, 2>), g, b, lds, st, r, s, in, n, ec);
-  else if (waves >= 3)
-    hipLaunchKernelGGL((k_shower_plain_flat<false, 3>), g, b, lds, st, r, s, in, n, ec);
-  else
-    hipLaunchKernelGGL((k_shower_plain_flat<false, 2>), g, b, lds, st, r, s, in, n, ec);
+  if (in.massive) hipLaunchKernelGGL(k_shower_plain_flat<true>, g, b, lds, st, r, s, in, n, ec);
+  else hipLaunchKernelGGL(k_shower_plain_flat<false>, g, b, lds, st, r, s, in, n, ec);
 }
 
 // kCached: A.cache holds an end cache per lane (always when in place; the

@@ -122,7 +122,7 @@ void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, un
                   hipStream_t st);
 void launch_zero(double* p, uint32_t n, hipStream_t st);
 void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
-                              uint64_t* cache, uint32_t waves, hipStream_t st);
+                              uint64_t* cache, hipStream_t st);
 void destroy_graph(BatchGraph& g);
 
 }  // namespace vsh

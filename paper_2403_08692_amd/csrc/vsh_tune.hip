@@ -162,7 +162,7 @@ static vsh_status autotune_plain(vsh_ctx* ctx, const vsh_request* req) {
   struct Cand {
     uint32_t block, waves, mapping;
   };
-  std::vector<Cand> cands{{64, 2, kMapFlat}, {64, 3, kMapFlat}};
+  std::vector<Cand> cands{{64, 2, kMapFlat}};
   for (uint32_t w : {2u, 3u, 4u})
     for (uint32_t b : {256u, 64u}) cands.push_back({b, w, kMapLane});
   for (const Cand& cd : cands) {

@@ -44,7 +44,7 @@ def oracle_records(orc, n):
     return parts
 
 
-def compare(gpu: dict, orc: dict, ecm, n: int, records: bool = True):
+def compare(gpu: dict, orc: dict, ecm, n: int, records: bool = True, isr: bool = False):
     """Returns a report dict; raises AssertionError when a bar is missed."""
     gi = gpu["sum_i"]          # [6][n]
     oi = orc["sum_i"].T        # [7][n]
@@ -80,7 +80,7 @@ def compare(gpu: dict, orc: dict, ecm, n: int, records: bool = True):
     rep = dict(n=n, identical=int(same.sum()), frac=float(frac), mom_err=float(mom_err), w_err=float(w_err),
                obs_bad=obs_bad)
     rep.update(hist_chi2(gpu["hist"], orc["hist"]))
-    rep.update(entry_check(gpu, orc, same))
+    rep.update(entry_check(gpu, orc, same, isr=isr))
     return rep, same
 
 
@@ -100,54 +100,77 @@ def binned_values(sd):
     return np.stack([l23, l34, sd[4], sd[5], sd[6], sd[7], sd[8], sd[1]])
 
 
-def bin_index(x, h):
+def bin_index(x, h, lo=HIST_LO, hi=HIST_HI):
     """Bin of each value of observable h: 0 underflow, 1..50, 51 overflow
     (NaN to overflow)."""
-    lo, hi = HIST_LO[h], HIST_HI[h]
+    lo, hi = lo[h], hi[h]
     with np.errstate(invalid="ignore"):
         inner = np.minimum(1 + np.floor((x - lo) / (hi - lo) * NBINS), NBINS)
         b = np.where(x < lo, 0, np.where(x >= hi, NBINS + 1, inner))
     return np.where(np.isnan(x), NBINS + 1, b).astype(np.int64)
 
 
-def near_edge(x, h):
-    lo, hi = HIST_LO[h], HIST_HI[h]
+def near_edge(x, h, lo=HIST_LO, hi=HIST_HI):
+    lo, hi = lo[h], hi[h]
     u = (x - lo) / (hi - lo) * NBINS
     with np.errstate(invalid="ignore"):
         return np.isfinite(u) & (np.abs(u - np.round(u)) < EDGE_TOL * NBINS) & (u > -0.5) & (u < NBINS + 0.5)
 
 
-def entry_check(gpu, orc, same):
+# the initial-state branch's histograms: log10(p_T,V), y_V, emitted gluons,
+# log10(p_T) of the hardest gluon (rows 4-7 unused)
+ISR_LO = np.array([-1.0, -5.0, 0.0, -1.0, 0.0, 0.0, 0.0, 0.0])
+ISR_HI = np.array([3.0, 5.0, 50.0, 3.0, 1.0, 1.0, 1.0, 1.0])
+
+
+def isr_binned_values(sd, si):
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lpt = np.where(sd[2] > 0, np.log10(np.where(sd[2] > 0, sd[2], 1.0)), -np.inf)
+        lg = np.where(sd[5] > 0, np.log10(np.where(sd[5] > 0, sd[5], 1.0)), -np.inf)
+    return np.stack([lpt, sd[1], si[3].astype(np.float64), lg])
+
+
+def entry_check(gpu, orc, same, isr=False):
     """Largest excess of a per-bin entry-count difference over what differing
     and edge events allow: GPU against oracle, and GPU against binning its own
-    summaries.  Both must be <= 0."""
+    summaries.  Both must be <= 0.  isr: the initial-state branch's rows."""
     gd, od = gpu["sum_d"], orc["sum_d"].T
     g_done = gpu["sum_i"][1] == 1
     o_done = orc["sum_i"][:, 1] == 1
-    gv, ov = binned_values(gd), binned_values(od)
+    if isr:
+        gv, ov = isr_binned_values(gd, gpu["sum_i"]), isr_binned_values(od, orc["sum_i"].T)
+        lo, hi = ISR_LO, ISR_HI
+        gf = [gd[2], gd[1], gpu["sum_i"][3], gd[5]]  # the summary value behind each row
+        of = [od[2], od[1], orc["sum_i"][:, 3], od[5]]
+        logged = (0, 3)
+    else:
+        gv, ov = binned_values(gd), binned_values(od)
+        lo, hi = HIST_LO, HIST_HI
+        gf = [gd[k] for k in (2, 3, 4, 5, 6, 7, 8, 1)]
+        of = [od[k] for k in (2, 3, 4, 5, 6, 7, 8, 1)]
+        logged = (0, 1)
     worst_o, worst_self = -np.inf, -np.inf
+
     def counts(b, sel, spread):
         c = np.bincount(b[sel], minlength=NBINS + 2).astype(np.float64)
         if spread:  # an edge value may land in either neighbour
             c = c + np.concatenate([[0.0], c[:-1]]) + np.concatenate([c[1:], [0.0]])
         return c
 
-    # the summary field behind each histogram (log10 y is binned from y)
-    field = [2, 3, 4, 5, 6, 7, 8, 1]
-    for h in range(8):
-        gb, ob = bin_index(gv[h], h), bin_index(ov[h], h)
+    for h in range(len(gv)):
+        gb, ob = bin_index(gv[h], h, lo, hi), bin_index(ov[h], h, lo, hi)
         # equal values are binned identically by the same arithmetic on both
         # sides; values that differ in their last bits may not be, near an edge
-        edge = (near_edge(gv[h], h) | near_edge(ov[h], h)) & (gd[field[h]] != od[field[h]])
+        edge = (near_edge(gv[h], h, lo, hi) | near_edge(ov[h], h, lo, hi)) & (gf[h] != of[h])
         differ = ~same
         slack = (counts(gb, differ & g_done, False) + counts(ob, differ & o_done, False)
                  + counts(gb, edge & same & g_done, True) + counts(ob, edge & same & o_done, True))
         diff = np.abs(gpu["hist"][h, :, 2] - orc["hist"][h, :, 2])
         worst_o = max(worst_o, float((diff - slack).max()))
         own = counts(gb, g_done, False)
-        # the device's log10 and numpy's may round differently: only log10 y
+        # the device's log10 and numpy's may round differently: only logged
         # values next to an edge may bin differently from the GPU's own fill
-        own_edge = near_edge(gv[h], h) if h < 2 else np.zeros_like(g_done)
+        own_edge = near_edge(gv[h], h, lo, hi) if h in logged else np.zeros_like(g_done)
         own_slack = counts(gb, g_done & own_edge, True)
         worst_self = max(worst_self, float((np.abs(gpu["hist"][h, :, 2] - own) - own_slack).max()))
     return dict(entry_excess=worst_o, entry_self_excess=worst_self)

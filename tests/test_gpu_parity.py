@@ -321,3 +321,37 @@ def test_plain_settings_do_not_change_events(ctx, oracle, tuning):
         parity.assert_parity(rep)
     finally:
         ctx.set_tuning(**old)
+
+
+@pytest.mark.parametrize("persistent", [True, False])
+def test_tuner_cache_is_reused_across_contexts(tmp_path, persistent):
+    """A context given a tuner cache file records its tuning there; a second
+    context (as another process would) takes the same settings from the file
+    without timing anything, and a different sample is tuned afresh."""
+    import time
+
+    import paper_2403_08692_amd as P
+
+    path = str(tmp_path / "tuning.txt")
+    kw = dict(n_events=1 << 16, seed=4, ecm=91.2, t_cut=1.0, max_partons=64, persistent=persistent)
+    with P.Context(tuner_cache_path=path) as c1:
+        t0 = time.perf_counter()
+        a = c1.autotune(**kw)
+        t_tune = time.perf_counter() - t0
+    assert a["from_cache"] == 0
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and ("persistent" if persistent else "plain") in lines[0]
+    with P.Context(tuner_cache_path=path) as c2:
+        t0 = time.perf_counter()
+        b = c2.autotune(**kw)
+        t_hit = time.perf_counter() - t0
+        assert b["from_cache"] == 1
+        keys = ("mapping", "waves_per_cu", "refill_threshold", "refill_period") if persistent else \
+            ("plain_block", "plain_waves", "plain_mapping")
+        assert all(a[k] == b[k] for k in keys), (a, b)
+        assert c2.get_tuning()[keys[0]] == a[keys[0]]
+        c = c2.autotune(**dict(kw, ecm=200.0))
+        assert c["from_cache"] == 0
+    assert len(open(path).read().splitlines()) == 2
+    print(f"tuning {t_tune:.2f} s, from the cache {t_hit * 1e3:.2f} ms", flush=True)
+    assert t_hit < 0.1 * t_tune

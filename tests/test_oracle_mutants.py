@@ -29,7 +29,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "vsh_oracle.c")
 PINS = ["tests/test_oracle_rng.py", "tests/test_oracle_physics.py", "tests/test_oracle_shower.py",
-        "tests/test_oracle_observables.py", "tests/test_oracle_massive.py", "tests/test_oracle_validation.py"]
+        "tests/test_oracle_observables.py", "tests/test_oracle_massive.py", "tests/test_oracle_validation.py",
+        "tests/test_oracle_isr.py"]
 
 # (name, text in vsh_oracle.c, replacement)
 MUTANTS = [
@@ -113,6 +114,19 @@ MUTANTS = [
     ("g->gg soft term without y", "if (K == 10) return 0.5 * CA * (2.0 / (1.0 - z * (1.0 - y))",
      "if (K == 10) return 0.5 * CA * (2.0 / (1.0 - z)"),
     ("massive map: kT^2 not clamped at the edge", "double kt = sqrt(k2 > 0.0 ? k2 : 0.0)", "double kt = sqrt(k2)"),
+    ("ISR: PDF ratio dropped", "double dens = p / z * or_pdf_q(x / z) / or_pdf_q(x);", "double dens = p / z;"),
+    ("ISR: 1/z of the backward density dropped", "double dens = p / z * or_pdf_q(x / z) / or_pdf_q(x);",
+     "double dens = p * or_pdf_q(x / z) / or_pdf_q(x);"),
+    ("ISR: overestimate without x^(-1/2)", "double over = 2.0 * CF / sqrt(x) / (1.0 - z);",
+     "double over = 2.0 * CF / (1.0 - z);"),
+    ("ISR: the spectator's fraction in the PDF ratio", "double r = or_isr_ratio(t, z, x[wl], st);",
+     "double r = or_isr_ratio(t, z, x[1 - wl], st);"),
+    ("ISR: emitter's fraction not rescaled", "    x[wl] /= z;\n", "    x[wl] *= 1.0;\n"),
+    ("ISR: the larger root of v", "double v = 0.5 * ((1.0 - z) - sqrt(", "double v = 0.5 * ((1.0 - z) + sqrt("),
+    ("ISR: final state not boosted", "for (int m = 0; m < 4; ++m) x[m] = y[m];", "(void)y;"),
+    ("ISR: gluon density normalisation", "return x > 0.0 && x < 1.0 ? 3.0 / x * pow(1.0 - x, 5.0) : 0.0;",
+     "return x > 0.0 && x < 1.0 ? 2.0 / x * pow(1.0 - x, 5.0) : 0.0;"),
+    ("ISR: tau taken as Q / sqrt(S)", "double tau = q * q / (sqrt_s_had * sqrt_s_had);", "double tau = q / sqrt_s_had;"),
 ]
 
 

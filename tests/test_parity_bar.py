@@ -82,3 +82,19 @@ def test_a_differing_event_may_move_its_own_entries(run):
     rep, same = parity.compare(g, o, 91.2, n)
     assert not same[e]
     assert rep["entry_excess"] <= 0 and rep["entry_self_excess"] <= 0
+
+
+def test_isr_rows_are_checked(oracle):
+    n = 800
+    o = oracle.isr_generate(4, 0, n, 1960.0, 91.2, 1.0, 64, records=True)
+    g = _as_gpu(o, n)
+    rep, same = parity.compare(g, o, 91.2, n, isr=True)
+    parity.assert_parity(rep)
+    g2 = copy.deepcopy(g)
+    cell = g2["hist"][0]
+    b = int(np.flatnonzero(cell[1:-2, 2] > 0)[0]) + 1
+    cell[b, 2] -= 1
+    cell[b + 1, 2] += 1
+    rep, _ = parity.compare(g2, o, 91.2, n, isr=True)
+    with pytest.raises(AssertionError):
+        parity.assert_parity(rep)
