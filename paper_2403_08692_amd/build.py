@@ -24,6 +24,12 @@ FLAGS = [
     "-shared",
     "-munsafe-fp-atomics",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Machine-level loop-invariant code motion hoists the FP64 coefficients
+    # of the log, exp and sincos polynomials out of the shower kernels' event
+    # loops into some 70 long-lived registers: with it off they are
+    # materialised where used, and the flattened shower kernels fit three
+    # waves per SIMD instead of two.
+    "-mllvm", "-disable-machine-licm",
     "-Wall",
     "-Wno-unused-function",
     "-I" + os.path.join(ROOT, "include"),

@@ -161,16 +161,20 @@ struct FlatShared {
   uint32_t cycle[64];
   uint32_t gstart[65], qstart[65];  // per-owner item offsets in the gluon and quark sections
   uint32_t sstart[65];              // per-owner offsets in the list of stale partons
-  uint16_t item[2048];              // the cycle's items, owner << 10 | parton: gluons, then quarks
+  uint16_t item[1024];              // the cycle's items, owner << 10 | parton: gluons, then quarks
   uint16_t sitem[512];              // the cycle's stale partons, owner << 10 | parton
   double best_v[64];
   uint32_t best_idx[64];  // packed (i, k, K) << 6 | the lane whose item made it
-  double coef[2][64];     // per item lane: its best end's trial coefficients (ca, cb)
   double best_c[2][64];   // per owner: those of its running best
   uint32_t counts[64];  // the cycle's trials (low 16 bits) and active ends (high 16 bits) per owner
   uint32_t climit[64];  // each event's cycle limit
   double wsh[64];       // each event's shower weight (weighted veto)
-  double mc[64], mb[64];  // each event's charm and bottom masses (massive requests)
+  union {
+    double coef[2][64];     // massless: per item lane, its best end's trial coefficients (ca, cb)
+    struct {
+      double mc[64], mb[64];  // massive: each event's charm and bottom masses
+    };
+  };
 };
 
 // per-owner gluon masks, then per-owner stale masks (partons whose cached end
@@ -570,8 +574,10 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       if (widx != kNoTrial) {
         v = best;
         idx = (widx << 6) | lane;  // same order as widx: items of one owner differ in i
-        sh.coef[0][lane] = wca;
-        sh.coef[1][lane] = wcb;
+        if constexpr (!kMassive) {
+          sh.coef[0][lane] = wca;
+          sh.coef[1][lane] = wcb;
+        }
       }
       atomicAdd(&sh.counts[o], nt | (ne << 16));  // at most 12 x 1024 trials and 2048 ends per cycle
     }
@@ -588,14 +594,18 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     if (active && last && gsec && beats(v, idx, sh.best_v[o], sh.best_idx[o])) {
       sh.best_v[o] = v;
       sh.best_idx[o] = idx;
-      sh.best_c[0][o] = sh.coef[0][idx & 63u];
-      sh.best_c[1][o] = sh.coef[1][idx & 63u];
+      if constexpr (!kMassive) {
+        sh.best_c[0][o] = sh.coef[0][idx & 63u];
+        sh.best_c[1][o] = sh.coef[1][idx & 63u];
+      }
     }
     if (active && last && !gsec && beats(v, idx, sh.best_v[o], sh.best_idx[o])) {
       sh.best_v[o] = v;
       sh.best_idx[o] = idx;
-      sh.best_c[0][o] = sh.coef[0][idx & 63u];
-      sh.best_c[1][o] = sh.coef[1][idx & 63u];
+      if constexpr (!kMassive) {
+        sh.best_c[0][o] = sh.coef[0][idx & 63u];
+        sh.best_c[1][o] = sh.coef[1][idx & 63u];
+      }
     }
     __syncthreads();
   }
@@ -658,10 +668,11 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
 // Plain one-launch form with the flattened mapping: wave w owns events
 // 64w .. 64w+63 of the batch (already started by k_me) from start to cutoff,
 // with no refill; finished lanes only stop contributing trial work.
-// Two resident waves per SIMD (a budget of 256 registers): held to 168
-// registers for a third wave the kernel spills and ran 40% slower on LEP.
+// Three resident waves per SIMD (168 registers, 11.5 KB of LDS per wave)
+// for massless events, which fit them without spilling; with quark masses
+// two (the massive kernels spill at 168).
 template <bool kMassive>
-__global__ void __launch_bounds__(64, 2) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n,
+__global__ void __launch_bounds__(64, kMassive ? 2 : 3) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n,
                                                              EndCache ec) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
@@ -705,8 +716,10 @@ void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInp
 
 // kCached: A.cache holds an end cache per lane (always when in place; the
 // serving epochs' staging slots have one unless it could not be allocated).
+// Three resident waves per SIMD in place (no spills at 168 registers), two
+// for the staging slots of the serving epochs (which spill at 168).
 template <bool kInPlace, bool kMassive, bool kCached>
-__global__ void __launch_bounds__(64, 2) k_shower_flat(PersistArgs A) {
+__global__ void __launch_bounds__(64, kInPlace ? 3 : 2) k_shower_flat(PersistArgs A) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
   const uint32_t words = mask_words(A.slots.cap);

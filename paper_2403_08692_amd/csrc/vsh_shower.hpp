@@ -186,44 +186,38 @@ __device__ __forceinline__ double massless_ratio(int K, double lt, double t, dou
 // compared as ln t + ln(R)/c (App. A, trial-scale equation), strict maximum
 // above the running best.  A gluon end's five g -> f fbar kernels share c, so
 // only their largest uniform needs a log.  Returns the winning kernel (or -1
-// if none beat `best`).
+// if none beat `best`).  The first block serves a quark end's one kernel and
+// a gluon end's g -> g g alike, so lanes with quark and gluon ends share it;
+// only the gluon ends go on to blocks 1 and 2.
 __device__ __forceinline__ int end_draws(const TrialCtx& c, int i, int k, int pid_i, double ca, double cb,
                                          double& best, uint32_t& trials) {
+  // kernel list g->gg, g->d dbar, ..., g->b bbar: block g holds kernels 2g, 2g+1
+  const bool gluon = pid_i == kGluon;
+  const U4 d0 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
+  const double l1 = c.lt + log_fast(unit(d0.x, d0.y)) / ca;
   int K = -1;
-  if (pid_i != kGluon) {
-    const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
-    const double lt_try = c.lt + log_fast(unit(d.x, d.y)) / ca;
-    trials += 1;
-    if (lt_try > best) {
-      best = lt_try;
-      K = pid_i > 0 ? pid_i - 1 : 4 - pid_i;
-    }
-  } else {
-    // kernel list g->gg, g->d dbar, ..., g->b bbar: block g holds kernels 2g, 2g+1
-    trials += 6;
-    double ugg = 0.0, um = 0.0;
-    int fm = 0;
-#pragma unroll  // the three Philox blocks interleave
-    for (uint32_t g = 0; g < 3; ++g) {
+  if (l1 > best) {
+    best = l1;
+    K = gluon ? 10 : (pid_i > 0 ? pid_i - 1 : 4 - pid_i);
+  }
+  trials += gluon ? 6u : 1u;
+  if (gluon) {
+    double um = unit(d0.z, d0.w);
+    int fm = 1;
+#pragma unroll  // the two Philox blocks interleave
+    for (uint32_t g = 1; g < 3; ++g) {
       const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, g));
       const double u0 = unit(d.x, d.y), u1 = unit(d.z, d.w);
-      if (g == 0) {
-        ugg = u0;
-      } else if (u0 > um) {
+      if (u0 > um) {  // first flavour wins ties, as in the kernel loop
         um = u0;
         fm = 2 * g;
       }
-      if (u1 > um) {  // first flavour wins ties, as in the kernel loop
+      if (u1 > um) {
         um = u1;
         fm = 2 * g + 1;
       }
     }
-    const double lgg = c.lt + log_fast(ugg) / ca;
     const double lqq = c.lt + log_fast(um) / cb;
-    if (lgg > best) {
-      best = lgg;
-      K = 10;
-    }
     if (lqq > best) {
       best = lqq;
       K = 10 + fm;
