@@ -161,7 +161,8 @@ struct FlatShared {
   uint32_t cycle[64];
   uint32_t gstart[65], qstart[65];  // per-owner item offsets in the gluon and quark sections
   uint32_t sstart[65];              // per-owner offsets in the list of stale partons
-  uint16_t item[1024];              // the cycle's items, owner << 10 | parton: gluons, then quarks
+  uint16_t item[1024];              // the cycle's items, owner << 10 | parton: gluon items (a gluon
+                                    // twice, once per dipole end, when rounds allow), then quark items
   uint16_t sitem[512];              // the cycle's stale partons, owner << 10 | parton
   double best_v[64];
   uint32_t best_idx[64];  // packed (i, k, K) << 6 | the lane whose item made it
@@ -337,15 +338,19 @@ __device__ __forceinline__ void parton_trials_mcached(const TrialCtx& c, uint64_
   }
 }
 
-__device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Records& r, uint64_t slot, int i,
-                                                     const EndCache& ec, uint64_t col, bool stale, double& best,
-                                                     uint32_t& widx, double& wca, double& wcb, uint32_t& trials,
-                                                     uint32_t& ends) {
-  uint64_t* ent = ec.rec ? ec.rec + ((col * ec.cap) + (uint64_t)i) * kCacheWords : nullptr;
+// Trials of one item of a massless event: ends e_lo .. e_hi of parton i (a
+// gluon's item takes one or both of its ends; a quark's both, the second
+// empty as a quark has one colour partner), from the parton's fresh cache
+// entry (cached; the stale rounds rebuilt it) or from the records.
+__device__ __forceinline__ void item_trials(const TrialCtx& c, const Records& r, uint64_t slot, int i, int e_lo,
+                                            int e_hi, const EndCache& ec, uint64_t col, bool cached, double& best,
+                                            uint32_t& widx, double& wca, double& wcb, uint32_t& trials,
+                                            uint32_t& ends) {
   uint64_t w[kCacheWords];
   int pid_i, k1, k2;
   P4 pi{0.0, 0.0, 0.0, 0.0};
-  if (!stale) {
+  if (cached) {
+    const uint64_t* ent = ec.rec + ((col * ec.cap) + (uint64_t)i) * kCacheWords;
 #pragma unroll
     for (int q = 0; q < kCacheWords; ++q) w[q] = ent[q];
     pid_i = (int)(int8_t)(uint8_t)(w[0] & 0xFFu);
@@ -363,24 +368,23 @@ __device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Re
       k2 = t;
     }
     pi = r.load(i, slot);
-    w[0] = pack_meta(pid_i, k1, k2);
   }
+  // the q-th end of the item is end e_lo + q: lanes of gluon items with
+  // different ends and of quark items take their first end together
 #pragma unroll
-  for (int e = 0; e < 2; ++e) {
+  for (int q = 0; q < 2; ++q) {
+    const int e = e_lo + q;
     const int k = e == 0 ? k1 : k2;
-    double ca = 0.0, cb = 0.0;
-    if (k != kNoPartner) {
-      if (stale) {
-        double q2, zm, zp, L;
-        if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, r.load(k, slot), q2, zm, zp, L, ca, cb)) ca = cb = 0.0;
-        w[1 + 2 * e] = (uint64_t)__double_as_longlong(ca);
-        w[2 + 2 * e] = (uint64_t)__double_as_longlong(cb);
-      } else {
-        ca = __longlong_as_double((long long)w[1 + 2 * e]);
-        cb = __longlong_as_double((long long)w[2 + 2 * e]);
-      }
+    if (e > e_hi || k == kNoPartner) continue;
+    double ca, cb;
+    if (cached) {
+      ca = __longlong_as_double((long long)(e == 0 ? w[1] : w[3]));
+      cb = __longlong_as_double((long long)(e == 0 ? w[2] : w[4]));
+    } else {
+      double q2, zm, zp, L;
+      if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, r.load(k, slot), q2, zm, zp, L, ca, cb)) ca = cb = 0.0;
     }
-    if (ca == 0.0) continue;  // no partner, or no phase space above the cutoff
+    if (ca == 0.0) continue;  // no phase space above the cutoff
     ends += 1;
     const int K = end_draws(c, i, k, pid_i, ca, cb, best, trials);
     if (K >= 0) {
@@ -388,12 +392,6 @@ __device__ __forceinline__ void parton_trials_cached(const TrialCtx& c, const Re
       wca = ca;
       wcb = cb;
     }
-  }
-  if (stale && ent) {
-    if (k1 == kNoPartner) w[1] = w[2] = 0ull;
-    if (k2 == kNoPartner) w[3] = w[4] = 0ull;
-#pragma unroll
-    for (int q = 0; q < kCacheWords; ++q) ent[q] = w[q];
   }
 }
 
@@ -449,42 +447,56 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   uint32_t ng = 0, ns = 0;
   if (trial)
     for (uint32_t w = 0; w < words; ++w) {
-      ng += __popcll(mym[w]);
-      if (kCached) ns += __popcll(mys[w]);
+      const int lo = 64 * (int)w;
+      const uint64_t live = s.n >= lo + 64 ? ~0ull : (s.n > lo ? (1ull << (s.n - lo)) - 1ull : 0ull);
+      ng += __popcll(mym[w] & live);
+      if (kCached) ns += __popcll(mys[w] & live);
     }
   const uint64_t mine = trial ? ((uint64_t)ng | ((uint64_t)((uint32_t)s.n - ng) << 21) | ((uint64_t)ns << 42)) : 0ull;
   const uint64_t incl = wave_inclusive_sum(mine);  // every lane of the wave takes part
   const uint64_t excl = incl - mine;
-  sh.gstart[lane] = (uint32_t)(excl & kF);
+  const uint64_t tot = lane63(incl);
+  const uint32_t n_g1 = (uint32_t)(tot & kF), n_q = (uint32_t)((tot >> 21) & kF), n_s = (uint32_t)(tot >> 42);
+  // A massless gluon's two dipole ends become two items (half the longest
+  // lane's work in a round) whenever that takes no more rounds than one item
+  // per gluon; otherwise, and with quark masses, one item per gluon.
+  const uint32_t kge = !kMassive && (2 * n_g1 + n_q + 63) / 64 == (n_g1 + n_q + 63) / 64 ? 2u : 1u;
+  const uint32_t n_g = kge * n_g1;
+  sh.gstart[lane] = kge * (uint32_t)(excl & kF);
   sh.qstart[lane] = (uint32_t)((excl >> 21) & kF);
   sh.sstart[lane] = (uint32_t)(excl >> 42);
   if (lane == 63) {
-    sh.gstart[64] = (uint32_t)(incl & kF);
-    sh.qstart[64] = (uint32_t)((incl >> 21) & kF);
-    sh.sstart[64] = (uint32_t)(incl >> 42);
+    sh.gstart[64] = n_g;
+    sh.qstart[64] = n_q;
+    sh.sstart[64] = n_s;
   }
-  const uint64_t tot = lane63(incl);
-  const uint32_t n_g = (uint32_t)(tot & kF), n_q = (uint32_t)((tot >> 21) & kF), n_s = (uint32_t)(tot >> 42);
   // longest per-event run of items in either section: a round's segmented
   // max needs only the shuffle steps below it
-  const uint32_t gmax = wave_max((uint32_t)(mine & kF)), qmax = wave_max((uint32_t)((mine >> 21) & kF));
+  const uint32_t gmax = kge * wave_max((uint32_t)(mine & kF)), qmax = wave_max((uint32_t)((mine >> 21) & kF));
   constexpr uint32_t kItems = sizeof(sh.item) / sizeof(sh.item[0]);
   constexpr uint32_t kSItems = sizeof(sh.sitem) / sizeof(sh.sitem[0]);
   if (trial) {  // list this event's items (beyond the lists' lengths rounds search the offsets instead)
-    uint32_t gpos = (uint32_t)(excl & kF), qpos = n_g + (uint32_t)((excl >> 21) & kF), spos = (uint32_t)(excl >> 42);
-    uint64_t mw = 0, sw = 0;
-    for (int a = 0; a < s.n; ++a) {
-      if ((a & 63) == 0) {
-        mw = mym[a >> 6];
-        if (kCached) sw = mys[a >> 6];
+    uint32_t gpos = kge * (uint32_t)(excl & kF), qpos = n_g + (uint32_t)((excl >> 21) & kF),
+             spos = (uint32_t)(excl >> 42);
+    for (uint32_t w = 0; w < words; ++w) {
+      const int lo = 64 * (int)w;
+      const uint64_t live = s.n >= lo + 64 ? ~0ull : (s.n > lo ? (1ull << (s.n - lo)) - 1ull : 0ull);
+      const uint32_t top = (lane << 10) | (uint32_t)lo;
+      for (uint64_t x = mym[w] & live; x; x &= x - 1) {  // gluons, ascending
+        const uint16_t item = (uint16_t)(top | (uint32_t)__builtin_ctzll(x));
+        if (gpos < kItems) sh.item[gpos] = item;
+        if (kge == 2 && gpos + 1 < kItems) sh.item[gpos + 1] = item;
+        gpos += kge;
       }
-      const uint32_t item = (lane << 10) | (uint32_t)a;
-      const uint32_t pos = ((mw >> (a & 63)) & 1ull) ? gpos++ : qpos++;
-      if (pos < kItems) sh.item[pos] = (uint16_t)item;
-      if (kCached && ((sw >> (a & 63)) & 1ull)) {
-        if (spos < kSItems) sh.sitem[spos] = (uint16_t)item;
-        ++spos;
+      for (uint64_t x = ~mym[w] & live; x; x &= x - 1) {  // quarks, ascending
+        if (qpos < kItems) sh.item[qpos] = (uint16_t)(top | (uint32_t)__builtin_ctzll(x));
+        ++qpos;
       }
+      if (kCached)
+        for (uint64_t x = mys[w] & live; x; x &= x - 1) {  // stale partons
+          if (spos < kSItems) sh.sitem[spos] = (uint16_t)(top | (uint32_t)__builtin_ctzll(x));
+          ++spos;
+        }
     }
   }
   sh.lt[lane] = s.lt;
@@ -553,8 +565,11 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
         i = it & 1023u;
       } else {
         o = owner_of(st, j);
-        i = select_slot(gm + (uint64_t)o * words, words, j - st[o], gsec);
+        i = select_slot(gm + (uint64_t)o * words, words, gsec ? (j - st[o]) / kge : j - st[o], gsec);
       }
+      // a gluon item's ends: both, or (two items per gluon) the parity of
+      // its place in the owner's run
+      const int e_lo = gsec && kge == 2 ? (int)((j - st[o]) & 1u) : 0, e_hi = gsec && kge == 2 ? e_lo : 1;
       const uint32_t first = base + st[o];  // list position of the owner's first item in this section
       seg0 = (first > r0 ? first : r0) - r0;
       last = (j + 1 == st[o + 1]) || lane == 63;
@@ -569,8 +584,8 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
         parton_trials_mflat(c, slots, sh.slot[o], (int)i, QuarkMasses{0.0, 0.0, 0.0, sh.mc[o], sh.mb[o]}, best,
                             widx, nt, ne);
       else
-        parton_trials_cached(c, slots, sh.slot[o], (int)i, ec, wave_col + o, !kCached, best, widx, wca, wcb, nt,
-                             ne);
+        item_trials(c, slots, sh.slot[o], (int)i, e_lo, e_hi, ec, wave_col + o, kCached, best, widx, wca, wcb, nt,
+                    ne);
       if (widx != kNoTrial) {
         v = best;
         idx = (widx << 6) | lane;  // same order as widx: items of one owner differ in i
