@@ -76,6 +76,27 @@ def algorithmic_ops(n_events, ends, trials, cycles, emissions, cost=None):
             emissions * per_emission + n_events * per_event)
 
 
+def observable_flops(n_partons):
+    """FP64 operations (add, multiply, divide, square root and compare each
+    one; fused multiply-add two) of the event-shape step (Sec. 3.1) for one
+    event of n partons, as the observables kernels compute it: validation
+    (momentum sums, mass shells), |p| sums and the momentum tensor (C), exact
+    thrust over the candidate planes of every parton pair (cross product, the
+    other partons' signed sum, four sign choices), hemisphere masses and
+    broadenings, and Durham clustering (every pair of the current jets scanned
+    per merge, E-scheme recombination)."""
+    n = int(n_partons)
+    f = 13 * n + 25 * n + 15 + 25 * n + 20
+    if n >= 3:
+        pairs = n * (n - 1) // 2
+        f += pairs * (57 + 9 * (n - 2)) + 6
+        f += 9 * n + sum(13 * m * (m - 1) // 2 + 13 for m in range(3, n + 1))
+    return f
+
+
+FP64_PEAK_TFLOPS = 78.6
+
+
 def _oracle_init(lib_path):
     os.environ["VSH_ORACLE_LIB"] = lib_path
     import oracle as O
@@ -529,6 +550,16 @@ def main():
                          "(the paper's figure); its Table 1 kernel sum, 628.5 ms per 10^6 events, is "
                          "<= 1.59e6 events/s",
     }
+    # the observables stage against the FP64 vector peak (counts of the
+    # parton-count histogram of the last step times observable_flops)
+    npc = np.bincount(si[0])
+    obs_flops = float(sum(int(c) * observable_flops(k) for k, c in enumerate(npc) if c))
+    obs_ms = float(np.mean(stages[:, 2]))
+    line["observables"] = {"bound": "fp64", "kernels": "k_obs_count, k_obs_scatter, k_obs, k_obs_group",
+                           "stage_ms": obs_ms, "flops_per_event": obs_flops / n,
+                           "achieved": obs_flops / (obs_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": obs_flops / (obs_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                           "mean_partons": float(si[0].mean())}
     if cpu:
         line["gpu_over_serial_oracle"] = value / cpu["serial_value"]
     if not args.quick and args.workload == "lep":
