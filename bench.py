@@ -605,11 +605,22 @@ def main():
                                "persistent": dict(time_form(ctx, P, torch, st_w, st_w.n_events, "persistent", 3),
                                                   tuning=tuned),
                                "plain": time_form(ctx, P, torch, st_w, st_w.n_events, "plain", 3)}
+        # the initial-state shower with the stand-in parton density: Drell-Yan at 1960 GeV
+        # through vsh_generate_isr (one lane per event; host results: histograms and counts)
+        ctx.generate_isr(1 << 16, summary=False)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            r = ctx.generate_isr(n, summary=False)
+        dt = (time.perf_counter() - t0) / 3
+        extra["isr_drell_yan"] = {"n_events": n, "sqrt_s_hadron_GeV": 1960.0, "Q_GeV": 91.2, "t_cut_GeV2": 1.0,
+                                  "ms_per_call": dt * 1e3, "events_per_s": n / dt, "shower_ms": r["t_shower_ms"],
+                                  "n_done": r["n_done"], "mean_cycles": r["total_cycles"] / n,
+                                  "call": "vsh_generate_isr, histograms and counts copied to the host"}
         tuned = ctx.autotune(1 << 18, seed=1, max_partons=128, ecm=91.2, t_cut=1.0)
         extra["serving"] = serving_bench(ctx, args.serving_requests, 200.0)
         # latency against offered load: the same trace statistics at higher arrival rates (2 s of arrivals each)
         sweep = []
-        for rate in (1000.0, 2000.0, 4000.0):
+        for rate in (1000.0, 2000.0, 3000.0, 4000.0, 5000.0):
             sv = serving_bench(ctx, int(2 * rate), rate)
             sv.pop("trace")
             sweep.append(sv)
