@@ -161,9 +161,9 @@ struct FlatShared {
   uint32_t cycle[64];
   uint32_t gstart[65], qstart[65];  // per-owner item offsets in the gluon and quark sections
   uint32_t sstart[65];              // per-owner offsets in the list of stale partons
-  uint16_t item[1024];              // the cycle's items, owner << 10 | parton: gluon items (a gluon
+  uint16_t item[1024 + 2];          // the cycle's items, owner << 10 | parton: gluon items (a gluon
                                     // twice, once per dipole end, when rounds allow), then quark items
-  uint16_t sitem[384];              // the cycle's stale partons, owner << 10 | parton
+  uint16_t sitem[384 + 2];          // the cycle's stale partons, owner << 10 | parton
   double best_v[64];
   uint32_t best_idx[64];  // packed (i, k, K) << 6 | the lane whose item made it
   double best_c[2][64];   // per owner: those of its running best
@@ -473,8 +473,10 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   // longest per-event run of items in either section: a round's segmented
   // max needs only the shuffle steps below it
   const uint32_t gmax = kge * wave_max((uint32_t)(mine & kF)), qmax = wave_max((uint32_t)((mine >> 21) & kF));
-  constexpr uint32_t kItems = sizeof(sh.item) / sizeof(sh.item[0]);
-  constexpr uint32_t kSItems = sizeof(sh.sitem) / sizeof(sh.sitem[0]);
+  // list lengths; each array has a spare entry past its end that takes the
+  // writes beyond it, so the listing loops need no branch
+  constexpr uint32_t kItems = sizeof(sh.item) / sizeof(sh.item[0]) - 2;
+  constexpr uint32_t kSItems = sizeof(sh.sitem) / sizeof(sh.sitem[0]) - 2;
   if (trial) {  // list this event's items (beyond the lists' lengths rounds search the offsets instead)
     uint32_t gpos = kge * (uint32_t)(excl & kF), qpos = n_g + (uint32_t)((excl >> 21) & kF),
              spos = (uint32_t)(excl >> 42);
@@ -484,17 +486,17 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       const uint32_t top = (lane << 10) | (uint32_t)lo;
       for (uint64_t x = mym[w] & live; x; x &= x - 1) {  // gluons, ascending
         const uint16_t item = (uint16_t)(top | (uint32_t)__builtin_ctzll(x));
-        if (gpos < kItems) sh.item[gpos] = item;
-        if (kge == 2 && gpos + 1 < kItems) sh.item[gpos + 1] = item;
+        sh.item[gpos < kItems ? gpos : kItems] = item;
+        sh.item[gpos + kge - 1 < kItems ? gpos + kge - 1 : kItems] = item;  // the second end's item
         gpos += kge;
       }
       for (uint64_t x = ~mym[w] & live; x; x &= x - 1) {  // quarks, ascending
-        if (qpos < kItems) sh.item[qpos] = (uint16_t)(top | (uint32_t)__builtin_ctzll(x));
+        sh.item[qpos < kItems ? qpos : kItems] = (uint16_t)(top | (uint32_t)__builtin_ctzll(x));
         ++qpos;
       }
       if (kCached)
         for (uint64_t x = mys[w] & live; x; x &= x - 1) {  // stale partons
-          if (spos < kSItems) sh.sitem[spos] = (uint16_t)(top | (uint32_t)__builtin_ctzll(x));
+          sh.sitem[spos < kSItems ? spos : kSItems] = (uint16_t)(top | (uint32_t)__builtin_ctzll(x));
           ++spos;
         }
     }
