@@ -663,20 +663,24 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   const uint32_t n_busy = __popcll(__ballot(busy));
   if (n_pend > 0 && kEmitDiv * n_pend >= n_busy && pend) {
     const int j = s.n;
+    // i's and k's colour partners before the emission, loaded beside the
+    // emission's own reads: j takes the place of one partner of each, so
+    // with i, j and k they are the partners afterwards
+    const uint64_t oi = (uint64_t)pd.i * slots.stride + slot, ok = (uint64_t)pd.k * slots.stride + slot;
+    const int pci = slots.cpart[oi], pai = slots.apart[oi], pck = slots.cpart[ok], pak = slots.apart[ok];
     if constexpr (kMassive) emit_massive(s, slots, slot, pd, qm);
     else emit(s, slots, slot, pd);
     if (pd.K <= 10) mym[j >> 6] |= 1ull << (j & 63);               // gluon emitted
     else mym[pd.i >> 6] &= ~(1ull << (pd.i & 63));                 // g -> f fbar: i is now a quark
     // ends whose momenta or partners changed: those of i, j, k and of the
     // other colour partners of i and k (partner links are symmetric)
-    const uint64_t oi = (uint64_t)pd.i * slots.stride + slot, ok = (uint64_t)pd.k * slots.stride + slot;
     set_bit(mys, pd.i);
     set_bit(mys, j);
     set_bit(mys, pd.k);
-    set_bit(mys, slots.cpart[oi]);
-    set_bit(mys, slots.apart[oi]);
-    set_bit(mys, slots.cpart[ok]);
-    set_bit(mys, slots.apart[ok]);
+    set_bit(mys, pci);
+    set_bit(mys, pai);
+    set_bit(mys, pck);
+    set_bit(mys, pak);
     pend = false;
   }
   if (busy && !pend && s.status == kRunning && s.cycle >= sh.climit[lane]) s.status = kCycleLimitHit;
