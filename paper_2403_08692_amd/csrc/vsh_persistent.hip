@@ -342,17 +342,22 @@ __device__ __forceinline__ void parton_trials_mcached(const TrialCtx& c, uint64_
 // gluon's item takes one or both of its ends; a quark's both, the second
 // empty as a quark has one colour partner), from the parton's fresh cache
 // entry (cached; the stale rounds rebuilt it) or from the records.
+// An item's end-cache entry, when loaded ahead of its round.
+struct Ent5 {
+  uint64_t w[kCacheWords];
+};
+
 __device__ __forceinline__ void item_trials(const TrialCtx& c, const Records& r, uint64_t slot, int i, int e_lo,
-                                            int e_hi, const EndCache& ec, uint64_t col, bool cached, double& best,
-                                            uint32_t& widx, double& wca, double& wcb, uint32_t& trials,
-                                            uint32_t& ends) {
+                                            int e_hi, const EndCache& ec, uint64_t col, bool cached, bool pre,
+                                            const Ent5& pw, double& best, uint32_t& widx, double& wca, double& wcb,
+                                            uint32_t& trials, uint32_t& ends) {
   uint64_t w[kCacheWords];
   int pid_i, k1, k2;
   P4 pi{0.0, 0.0, 0.0, 0.0};
-  if (cached) {
+  if (cached) {  // the entry as loaded ahead (pre), or from the cache now
     const uint64_t* ent = ec.rec + ((col * ec.cap) + (uint64_t)i) * kCacheWords;
 #pragma unroll
-    for (int q = 0; q < kCacheWords; ++q) w[q] = ent[q];
+    for (int q = 0; q < kCacheWords; ++q) w[q] = pre ? pw.w[q] : ent[q];
     pid_i = (int)(int8_t)(uint8_t)(w[0] & 0xFFu);
     k1 = (int)((w[0] >> 8) & 0xFFFFu);
     k2 = (int)((w[0] >> 24) & 0xFFFFu);
@@ -406,6 +411,18 @@ __device__ __forceinline__ void parton_trials_mflat(const TrialCtx& c, const Rec
   if (W.w.i >= 0) widx = pack_trial(W.w.i, W.w.k, W.w.K);
 }
 
+// Load the end-cache entry of the item at list position `at` into pw; false
+// (nothing loaded) past the cycle's items or the list's end.
+__device__ __forceinline__ bool prefetch_entry(const uint16_t* item, uint32_t at, uint32_t n_items, uint32_t n_list,
+                                               const EndCache& ec, uint64_t wave_col, Ent5& pw) {
+  if (at >= n_items || at >= n_list) return false;
+  const uint32_t it = item[at];
+  const uint64_t* ent = ec.rec + (((wave_col + (it >> 10)) * ec.cap) + (uint64_t)(it & 1023u)) * kCacheWords;
+#pragma unroll
+  for (int q = 0; q < kCacheWords; ++q) pw.w[q] = ent[q];
+  return true;
+}
+
 // (v, idx) beats (w, jdx): larger ln t, or equal and earlier in loop order
 __device__ __forceinline__ bool beats(double v, uint32_t idx, double w, uint32_t jdx) {
   return idx != kNoTrial && (jdx == kNoTrial || v > w || (v == w && idx < jdx));
@@ -428,7 +445,11 @@ constexpr uint32_t kEmitDiv = 2;
 // parton's coefficients itself.  kMassive: the events carry quark masses
 // (qm, the calling lane's event's); no end cache, the owner recomputes its
 // winner's range from the records.
-template <bool kCached, bool kMassive = false>
+// kAhead (massless cached events): each round loads the end-cache entries
+// of the next round's items while it reduces its winners; the registers come
+// from the owner's trial constants, which are reloaded from LDS after the
+// rounds (faster for the persistent kernel, 1% slower for the plain one).
+template <bool kCached, bool kMassive = false, bool kAhead = false>
 __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_t words, EvState& s, bool busy,
                                            bool& pend, Pending& pd, const Records& slots, uint64_t slot,
                                            const EndCache& ec, uint64_t wave_col, uint32_t lane,
@@ -549,6 +570,13 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   // (a round may hold the end of one and the start of the other: its quark
   // lanes finish early, in time the round takes for its gluons anyway)
   const uint32_t run = gmax > qmax ? gmax : qmax;
+  // the end-cache entry of the lane's item in the coming round is loaded
+  // while the current round reduces its winners (an item past the list's
+  // end loads its own)
+  constexpr bool kPre = kAhead && kCached && !kMassive;
+  Ent5 pw{{0ull, 0ull, 0ull, 0ull, 0ull}};
+  bool pre = false;
+  if (kPre) pre = prefetch_entry(sh.item, 0u + lane, n_g + n_q, kItems, ec, wave_col, pw);
   for (uint32_t r0 = 0; r0 < n_g + n_q; r0 += 64) {
     const uint32_t at = r0 + lane;  // position in the item list
     const bool gsec = at < n_g;
@@ -586,8 +614,8 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
         parton_trials_mflat(c, slots, sh.slot[o], (int)i, QuarkMasses{0.0, 0.0, 0.0, sh.mc[o], sh.mb[o]}, best,
                             widx, nt, ne);
       else
-        item_trials(c, slots, sh.slot[o], (int)i, e_lo, e_hi, ec, wave_col + o, kCached, best, widx, wca, wcb, nt,
-                    ne);
+        item_trials(c, slots, sh.slot[o], (int)i, e_lo, e_hi, ec, wave_col + o, kCached, kPre && pre, pw, best, widx,
+                    wca, wcb, nt, ne);
       if (widx != kNoTrial) {
         v = best;
         idx = (widx << 6) | lane;  // same order as widx: items of one owner differ in i
@@ -598,6 +626,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       }
       atomicAdd(&sh.counts[o], nt | (ne << 16));  // at most 12 x 1024 trials and 2048 ends per cycle
     }
+    if (kPre) pre = prefetch_entry(sh.item, r0 + 64 + lane, n_g + n_q, kItems, ec, wave_col, pw);
     for (uint32_t d = 1; d < 64 && d < run; d <<= 1) {
       const double vn = __shfl_up(v, d);
       const uint32_t in = __shfl_up(idx, d);
@@ -625,6 +654,14 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       }
     }
     __syncthreads();
+  }
+  if (kPre) {  // the event's trial constants, published to LDS above, come back from there
+    s.key = Keyed{sh.key[0][lane], sh.key[1][lane], sh.key[2][lane], sh.key[3][lane]};
+    s.lt = sh.lt[lane];
+    s.tcut = sh.tcut[lane];
+    s.ltc = sh.ltc[lane];
+    s.cfac = sh.cfac[lane];
+    s.cycle = sh.cycle[lane];
   }
   // --- each owner that made trials decides its cycle
   if (trial && kMassive) {
@@ -768,8 +805,8 @@ __global__ void __launch_bounds__(64, kInPlace || (kCached && !kMassive) ? 3 : 2
       busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle<kCached, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane,
-                                  A.reqs[req].qm);
+    flat_cycle<kCached, kMassive, kInPlace>(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane,
+                                            lane, A.reqs[req].qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
