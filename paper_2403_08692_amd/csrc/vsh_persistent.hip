@@ -445,10 +445,12 @@ constexpr uint32_t kEmitDiv = 2;
 // parton's coefficients itself.  kMassive: the events carry quark masses
 // (qm, the calling lane's event's); no end cache, the owner recomputes its
 // winner's range from the records.
-// kAhead (massless cached events): each round loads the end-cache entries
-// of the next round's items while it reduces its winners; the registers come
-// from the owner's trial constants, which are reloaded from LDS after the
-// rounds (faster for the persistent kernel, 1% slower for the plain one).
+// kAhead: the owner's trial constants (key, scales, cycle) are reloaded from
+// LDS after the rounds, so their registers are free during them; for
+// massless cached events each round then loads the end-cache entries of the
+// next round's items while it reduces its winners (faster for the persistent
+// kernel, 1% slower for the plain one, which takes kAhead with quark masses
+// only, to fit three waves).
 template <bool kCached, bool kMassive = false, bool kAhead = false>
 __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_t words, EvState& s, bool busy,
                                            bool& pend, Pending& pd, const Records& slots, uint64_t slot,
@@ -655,7 +657,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     }
     __syncthreads();
   }
-  if (kPre) {  // the event's trial constants, published to LDS above, come back from there
+  if (kAhead) {  // the event's trial constants, published to LDS above, come back from there
     s.key = Keyed{sh.key[0][lane], sh.key[1][lane], sh.key[2][lane], sh.key[3][lane]};
     s.lt = sh.lt[lane];
     s.tcut = sh.tcut[lane];
@@ -726,11 +728,11 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
 // Plain one-launch form with the flattened mapping: wave w owns events
 // 64w .. 64w+63 of the batch (already started by k_me) from start to cutoff,
 // with no refill; finished lanes only stop contributing trial work.
-// Three resident waves per SIMD (168 registers, 11.5 KB of LDS per wave)
-// for massless events, which fit them without spilling; with quark masses
-// two (the massive kernels spill at 168).
+// Three resident waves per SIMD (168 registers, 11 KB of LDS per wave); the
+// massive instantiation reloads its trial constants from LDS after the
+// rounds (kAhead) to fit them without spilling.
 template <bool kMassive>
-__global__ void __launch_bounds__(64, kMassive ? 2 : 3) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n,
+__global__ void __launch_bounds__(64, 3) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n,
                                                              EndCache ec) {
   __shared__ FlatShared sh;
   const uint32_t lane = threadIdx.x;
@@ -749,7 +751,7 @@ __global__ void __launch_bounds__(64, kMassive ? 2 : 3) k_shower_plain_flat(Reco
     mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
   while (__any(busy)) {
-    flat_cycle<true, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane, in.qm);
+    flat_cycle<true, kMassive, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane, in.qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
       write_state(s, sm, e);
