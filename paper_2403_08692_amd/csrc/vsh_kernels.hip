@@ -94,9 +94,11 @@ __global__ void k_obs_reset(uint32_t* cnt, uint32_t nb, unsigned long long* ihis
   if (wmax && i == 0) *wmax = 0ull;
 }
 
-// Per-block counts in LDS, one global atomic per non-empty count per block;
-// with wmax, also the largest |w| of the events (the bits of non-negative
-// doubles order like the integers, so the maximum does not depend on order).
+// Per-block counts in LDS over kObsSortPer events per thread, one global
+// atomic per non-empty count per block (few blocks, so that the atomics of
+// the handful of occupied counts do not queue up); with wmax, also the
+// largest |w| of the events (the bits of non-negative doubles order like the
+// integers, so the maximum does not depend on order).
 __global__ void __launch_bounds__(256) k_obs_count(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt,
                                                    unsigned long long* wmax) {
   __shared__ uint32_t lc[kMaxCount + 1];
@@ -105,8 +107,9 @@ __global__ void __launch_bounds__(256) k_obs_count(Summary sm, uint32_t n, uint3
   for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) lc[k] = 0u;
   if (threadIdx.x == 0) lw = 0ull;
   __syncthreads();
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) {
+  const uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x * kObsSortPer;
+  const uint64_t e1 = e0 + (uint64_t)blockDim.x * kObsSortPer < n ? e0 + (uint64_t)blockDim.x * kObsSortPer : n;
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const uint32_t np = (uint32_t)sm.i[kSiN * sm.stride + e];
     atomicAdd(&lc[cap - (np < cap ? np : cap)], 1u);
     if (wmax) atomicMax(&lw, (unsigned long long)__double_as_longlong(fabs(sm.d[kSdW * sm.stride + e])));
@@ -155,26 +158,37 @@ __global__ void __launch_bounds__(256) k_obs_scan(uint32_t* cnt, uint32_t nb) {
   }
 }
 
-// Each block reserves one range per parton count with a single global
-// atomic and places its events by their LDS rank inside the range.
+// Each block (kObsSortPer events per thread, as k_obs_count) reserves one
+// range per parton count with a single global atomic and places its events
+// by their LDS rank inside the range.
 __global__ void __launch_bounds__(256) k_obs_scatter(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt,
                                                      uint32_t* perm) {
   __shared__ uint32_t lc[kMaxCount + 1];
   const uint32_t nb = cap + 1;
   for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) lc[k] = 0u;
   __syncthreads();
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t bin = 0, rank = 0;
-  if (e < n) {
-    const uint32_t np = (uint32_t)sm.i[kSiN * sm.stride + e];
-    bin = cap - (np < cap ? np : cap);
-    rank = atomicAdd(&lc[bin], 1u);
+  const uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x * kObsSortPer;
+  uint32_t bin[kObsSortPer], rank[kObsSortPer];
+#pragma unroll
+  for (uint32_t q = 0; q < kObsSortPer; ++q) {
+    const uint64_t e = e0 + (uint64_t)q * blockDim.x + threadIdx.x;
+    bin[q] = 0;
+    rank[q] = 0;
+    if (e < n) {
+      const uint32_t np = (uint32_t)sm.i[kSiN * sm.stride + e];
+      bin[q] = cap - (np < cap ? np : cap);
+      rank[q] = atomicAdd(&lc[bin[q]], 1u);
+    }
   }
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x)
     if (lc[k]) lc[k] = atomicAdd(&cnt[k], lc[k]);
   __syncthreads();
-  if (e < n) perm[lc[bin] + rank] = e;
+#pragma unroll
+  for (uint32_t q = 0; q < kObsSortPer; ++q) {
+    const uint64_t e = e0 + (uint64_t)q * blockDim.x + threadIdx.x;
+    if (e < n) perm[lc[bin[q]] + rank[q]] = (uint32_t)e;
+  }
 }
 
 template <bool kMassive>
@@ -556,6 +570,8 @@ size_t obs_group_lds(uint32_t g, uint32_t slots) {
 // ---------------------------------------------------------------------------
 static inline uint32_t blocks_for(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
 
+uint32_t obs_sort_blocks(uint64_t n) { return blocks_for(n, 256u * kObsSortPer); }
+
 void launch_me(const Records& r, const Summary& s, const EventInputs& in, uint32_t n,
                hipStream_t st, double* zero_hist) {
   if (!n) return;
@@ -644,9 +660,9 @@ void launch_obs(const Records& r, const Summary& s, const EventInputs& in, const
   unsigned long long* wm = fixed ? sc.wmax : nullptr;
   hipLaunchKernelGGL(k_obs_reset, dim3((std::max<uint32_t>(nb, kHistDoubles) + 255) / 256), dim3(256), 0, st, sc.cnt,
                      nb, ih, wm);
-  hipLaunchKernelGGL(k_obs_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, n, r.cap, sc.cnt, wm);
+  hipLaunchKernelGGL(k_obs_count, dim3(obs_sort_blocks(n)), dim3(256), 0, st, s, n, r.cap, sc.cnt, wm);
   hipLaunchKernelGGL(k_obs_scan, dim3(1), dim3(256), 0, st, sc.cnt, nb);
-  hipLaunchKernelGGL(k_obs_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, n, r.cap, sc.cnt, sc.perm);
+  hipLaunchKernelGGL(k_obs_scatter, dim3(obs_sort_blocks(n)), dim3(256), 0, st, s, n, r.cap, sc.cnt, sc.perm);
   const uint32_t blocks = (uint32_t)(std::min<uint64_t>(sc.stride, ((uint64_t)n + 255) / 256 * 256) / 256);
   if (in.massive) hipLaunchKernelGGL(k_obs<true>, dim3(blocks), dim3(256), 0, st, r, s, in, sc, n, hist);
   else hipLaunchKernelGGL(k_obs<false>, dim3(blocks), dim3(256), 0, st, r, s, in, sc, n, hist);

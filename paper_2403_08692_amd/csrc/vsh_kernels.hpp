@@ -102,6 +102,8 @@ struct Scratch {
 constexpr uint32_t kObsWaveThreshold = 9;
 constexpr int kObsRegSlots = 8;  // events of at most this many partons: observables in registers
 constexpr uint32_t kObsWaveMaxCap = 512;
+constexpr uint32_t kObsSortPer = 16;  // events per thread of the counting sort by parton count
+uint32_t obs_sort_blocks(uint64_t n);
 constexpr uint32_t kObsWaveBlocks = 8192;
 
 }  // namespace vsh

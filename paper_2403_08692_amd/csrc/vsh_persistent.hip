@@ -1034,7 +1034,7 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   void* a_zero[] = {&g.sc.cnt, &g.nb, &g.ih, &g.wm};
   GCHK(add_kernel((const void*)k_obs_reset, dim3((std::max<uint32_t>(g.nb, kHistDoubles) + 255) / 256), dim3(256),
                   a_zero));
-  const uint32_t eb = (uint32_t)((n + 255) / 256);
+  const uint32_t eb = obs_sort_blocks(n);
   void* a_count[] = {&g.sum, &g.n, &g.cap, &g.sc.cnt, &g.wm};
   GCHK(add_kernel((const void*)k_obs_count, dim3(eb), dim3(256), a_count));
   void* a_scan[] = {&g.sc.cnt, &g.nb};
