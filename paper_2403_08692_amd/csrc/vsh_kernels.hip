@@ -87,12 +87,18 @@ __global__ void k_zero_u32(uint32_t* p, uint32_t n) {
 // Zero the counting sort's counters and, for fixed-point histograms, the
 // integer cells and the largest-weight word (a kernel, not a memset, so the
 // sequence can be captured in a graph).
-__global__ void k_obs_reset(uint32_t* cnt, uint32_t nb, unsigned long long* ihist, unsigned long long* wmax) {
+__global__ void k_obs_reset(uint32_t* cnt, uint32_t nb, double* hcopy, unsigned long long* ihist,
+                            unsigned long long* wmax) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nb) cnt[i] = 0u;
-  if (ihist && i < (uint32_t)kHistDoubles) ihist[i] = 0ull;
+  if (i < kHistCopies * (uint32_t)kHistDoubles) {
+    hcopy[i] = 0.0;
+    if (ihist) ihist[i] = 0ull;
+  }
   if (wmax && i == 0) *wmax = 0ull;
 }
+
+uint32_t obs_reset_blocks(uint32_t nb) { return (std::max<uint32_t>(nb, kHistCopies * kHistDoubles) + 255) / 256; }
 
 // Per-block counts in LDS over kObsSortPer events per thread, one global
 // atomic per non-empty count per block (few blocks, so that the atomics of
@@ -120,15 +126,24 @@ __global__ void __launch_bounds__(256) k_obs_count(Summary sm, uint32_t n, uint3
   if (wmax && threadIdx.x == 0 && lw) atomicMax(wmax, lw);
 }
 
-// Fixed-point cells into the FP64 histogram (accumulated): sum w and sum w^2
-// scaled back by their powers of two, entries as they are.  The integer sums
-// do not depend on the order of the events, so neither does the result.
-__global__ void __launch_bounds__(256) k_hist_fixed_finalize(Scratch sc, double* hist) {
-  const FixScale fx = fix_scale(sc);
+// The histogram copies into the caller's histogram (accumulated).  Fixed
+// point: the copies' integer cells summed (exactly, in any order), then sum
+// w and sum w^2 scaled back by their powers of two, entries as they are, so
+// the result does not depend on the order of the events.
+__global__ void __launch_bounds__(256) k_hist_finalize(Scratch sc, double* hist, uint32_t fixed) {
+  const FixScale fx = fixed ? fix_scale(sc) : FixScale{0, 0};
   for (uint32_t a = threadIdx.x; a < (uint32_t)kHistDoubles; a += blockDim.x) {
-    const double q = (double)(long long)sc.ihist[a];
-    const int col = (int)(a % 3);
-    hist[a] += col == 0 ? ldexp(q, -fx.fw) : (col == 1 ? ldexp(q, -fx.fw2) : q);
+    if (fixed) {
+      unsigned long long s = 0;
+      for (uint32_t c = 0; c < kHistCopies; ++c) s += sc.ihist[c * kHistDoubles + a];
+      const double q = (double)(long long)s;
+      const int col = (int)(a % 3);
+      hist[a] += col == 0 ? ldexp(q, -fx.fw) : (col == 1 ? ldexp(q, -fx.fw2) : q);
+    } else {
+      double v = 0.0;
+      for (uint32_t c = 0; c < kHistCopies; ++c) v += sc.hcopy[c * kHistDoubles + a];
+      hist[a] += v;
+    }
   }
 }
 
@@ -259,7 +274,7 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
     sm.i[kSiStatus * sm.stride + e] = o.status;
   }
   __syncthreads();
-  hist_flush(lh, hist, sc, fixed, threadIdx.x, blockDim.x);
+  hist_flush(lh, sc, fixed, threadIdx.x, blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -536,7 +551,7 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
     if (lane == 0) sm.i[kSiStatus * sm.stride + e] = status;
   }
   __syncthreads();
-  hist_flush(lh, hist, sc, fixed, threadIdx.x, 64);
+  hist_flush(lh, sc, fixed, threadIdx.x, 64);
 }
 
 // The group launches for records of capacity cap: 16 lanes from
@@ -617,7 +632,7 @@ static inline uint64_t al256(uint64_t v) { return (v + 255) / 256 * 256; }
 uint64_t obs_scratch_bytes(uint64_t n, uint32_t cap) {
   const uint64_t m = obs_threads(n, cap) * thread_slots(cap);
   return 8 * al256(m * 8) + al256(m * 2) + al256(m) + al256(n * 4) + al256((cap + 2) * 4) +
-         al256(kHistDoubles * 8) + al256(8) + 256;
+         2 * al256(kHistCopies * kHistDoubles * 8) + al256(8) + 256;
 }
 
 Scratch carve_obs_scratch(char*& p, uint64_t n, uint32_t cap) {
@@ -641,7 +656,8 @@ Scratch carve_obs_scratch(char*& p, uint64_t n, uint32_t cap) {
   s.dead = (uint8_t*)take(m);
   s.perm = (uint32_t*)take(n * 4);
   s.cnt = (uint32_t*)take((cap + 2) * 4);
-  s.ihist = (unsigned long long*)take(kHistDoubles * 8);
+  s.hcopy = (double*)take(kHistCopies * kHistDoubles * 8);
+  s.ihist = (unsigned long long*)take(kHistCopies * kHistDoubles * 8);
   s.wmax = (unsigned long long*)take(8);
   s.lbits = 0;
   while ((1ull << s.lbits) < n) ++s.lbits;
@@ -658,8 +674,7 @@ void launch_obs(const Records& r, const Summary& s, const EventInputs& in, const
   const bool fixed = in.fixed_hist != 0;
   unsigned long long* ih = fixed ? sc.ihist : nullptr;
   unsigned long long* wm = fixed ? sc.wmax : nullptr;
-  hipLaunchKernelGGL(k_obs_reset, dim3((std::max<uint32_t>(nb, kHistDoubles) + 255) / 256), dim3(256), 0, st, sc.cnt,
-                     nb, ih, wm);
+  hipLaunchKernelGGL(k_obs_reset, dim3(obs_reset_blocks(nb)), dim3(256), 0, st, sc.cnt, nb, sc.hcopy, ih, wm);
   hipLaunchKernelGGL(k_obs_count, dim3(obs_sort_blocks(n)), dim3(256), 0, st, s, n, r.cap, sc.cnt, wm);
   hipLaunchKernelGGL(k_obs_scan, dim3(1), dim3(256), 0, st, sc.cnt, nb);
   hipLaunchKernelGGL(k_obs_scatter, dim3(obs_sort_blocks(n)), dim3(256), 0, st, s, n, r.cap, sc.cnt, sc.perm);
@@ -681,7 +696,7 @@ void launch_obs(const Records& r, const Summary& s, const EventInputs& in, const
     void* args[] = {&rr, &ss, &ii, &perm, &cnt, &cap, &lo, &hi, &slots, &hh, &sc2};
     (void)hipLaunchKernel(gl[k].fn, dim3(wb), dim3(64), args, gl[k].lds, st);
   }
-  if (fixed) hipLaunchKernelGGL(k_hist_fixed_finalize, dim3(1), dim3(256), 0, st, sc, hist);
+  hipLaunchKernelGGL(k_hist_finalize, dim3(1), dim3(256), 0, st, sc, hist, fixed ? 1u : 0u);
 }
 
 

@@ -91,10 +91,14 @@ struct Scratch {
   uint32_t *perm;           // event indices by decreasing parton count [n]
   uint32_t *cnt;            // per-count offsets [cap + 2]
   uint32_t threshold;       // events with at least this many partons: one wave each
-  // fixed-point histogram (requests with VSH_HIST_FIXEDPOINT): the cells'
-  // int64 sums, the largest |w| of the launch's events (as the bits of a
-  // non-negative double, which order like the integers) and L = ceil(log2 n)
-  unsigned long long *ihist;  // [kHistDoubles]
+  // the blocks' histograms meet in kHistCopies copies (block b adds into
+  // copy b mod kHistCopies, so that no cell's atomics queue up behind every
+  // block's), summed into the caller's histogram by k_hist_finalize: FP64
+  // cells, or (requests with VSH_HIST_FIXEDPOINT) the cells' int64 sums; the
+  // largest |w| of the launch's events (as the bits of a non-negative double,
+  // which order like the integers) and L = ceil(log2 n)
+  double *hcopy;              // [kHistCopies][kHistDoubles]
+  unsigned long long *ihist;  // [kHistCopies][kHistDoubles]
   unsigned long long *wmax;   // [1]
   uint32_t lbits;
 };
@@ -103,6 +107,7 @@ constexpr uint32_t kObsWaveThreshold = 9;
 constexpr int kObsRegSlots = 8;  // events of at most this many partons: observables in registers
 constexpr uint32_t kObsWaveMaxCap = 512;
 constexpr uint32_t kObsSortPer = 16;  // events per thread of the counting sort by parton count
+constexpr uint32_t kHistCopies = 16;  // copies of the histogram set that the blocks' atomics spread over
 uint32_t obs_sort_blocks(uint64_t n);
 constexpr uint32_t kObsWaveBlocks = 8192;
 
@@ -118,8 +123,10 @@ Scratch carve_obs_scratch(char*& p, uint64_t n, uint32_t cap);
 // k_obs for requests without (false) or with (true) quark masses
 const void* obs_kernel(bool massive);
 __global__ void k_obs_count(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt, unsigned long long* wmax);
-__global__ void k_obs_reset(uint32_t* cnt, uint32_t nb, unsigned long long* ihist, unsigned long long* wmax);
-__global__ void k_hist_fixed_finalize(Scratch sc, double* hist);
+__global__ void k_obs_reset(uint32_t* cnt, uint32_t nb, double* hcopy, unsigned long long* ihist,
+                            unsigned long long* wmax);
+__global__ void k_hist_finalize(Scratch sc, double* hist, uint32_t fixed);
+uint32_t obs_reset_blocks(uint32_t nb);
 __global__ void k_obs_scan(uint32_t* cnt, uint32_t nb);
 __global__ void k_obs_scatter(Summary sm, uint32_t n, uint32_t cap, uint32_t* cnt, uint32_t* perm);
 __global__ void k_zero_u32(uint32_t* p, uint32_t n);

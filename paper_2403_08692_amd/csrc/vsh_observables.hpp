@@ -521,18 +521,20 @@ __device__ __forceinline__ void hist_fill_lds(double* lh, const ObsOut& o, doubl
   }
 }
 
-// One LDS histogram set into the global one: FP64 atomics, or integer
-// atomics into the fixed-point cells (sc.ihist).
-__device__ __forceinline__ void hist_flush(const double* lh, double* hist, const Scratch& sc, bool fixed,
-                                           uint32_t t0, uint32_t step) {
+// One LDS histogram set into this block's copy of the global one (block b:
+// copy b mod kHistCopies): FP64 atomics, or integer atomics into the
+// fixed-point cells.
+__device__ __forceinline__ void hist_flush(const double* lh, const Scratch& sc, bool fixed, uint32_t t0,
+                                           uint32_t step) {
   const unsigned long long* lq = reinterpret_cast<const unsigned long long*>(lh);
+  const uint32_t c0 = (blockIdx.x % kHistCopies) * (uint32_t)kHistDoubles;
   for (uint32_t a = t0; a < (uint32_t)kHistDoubles; a += step) {
     if (fixed) {
       const unsigned long long q = lq[a];  // integer words: never read as doubles
-      if (q) atomicAdd(&sc.ihist[a], q);
+      if (q) atomicAdd(&sc.ihist[c0 + a], q);
     } else {
       const double v = lh[a];
-      if (v != 0.0) unsafeAtomicAdd(&hist[a], v);
+      if (v != 0.0) unsafeAtomicAdd(&sc.hcopy[c0 + a], v);
     }
   }
 }

@@ -1031,8 +1031,8 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   const bool fixed = g.in.fixed_hist != 0;
   g.ih = fixed ? g.sc.ihist : nullptr;
   g.wm = fixed ? g.sc.wmax : nullptr;
-  void* a_zero[] = {&g.sc.cnt, &g.nb, &g.ih, &g.wm};
-  GCHK(add_kernel((const void*)k_obs_reset, dim3((std::max<uint32_t>(g.nb, kHistDoubles) + 255) / 256), dim3(256),
+  void* a_zero[] = {&g.sc.cnt, &g.nb, &g.sc.hcopy, &g.ih, &g.wm};
+  GCHK(add_kernel((const void*)k_obs_reset, dim3(obs_reset_blocks(g.nb)), dim3(256),
                   a_zero));
   const uint32_t eb = obs_sort_blocks(n);
   void* a_count[] = {&g.sum, &g.n, &g.cap, &g.sc.cnt, &g.wm};
@@ -1057,10 +1057,9 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
     const uint32_t wb = (uint32_t)std::min<uint64_t>(n, kObsWaveBlocks);
     GCHK(add_kernel(gl[k].fn, dim3(wb), dim3(64), a_grp, gl[k].lds));
   }
-  if (fixed) {
-    void* a_fin[] = {&g.sc, &g.hist};
-    GCHK(add_kernel((const void*)k_hist_fixed_finalize, dim3(1), dim3(256), a_fin));
-  }
+  g.fixed = fixed ? 1u : 0u;
+  void* a_fin[] = {&g.sc, &g.hist, &g.fixed};
+  GCHK(add_kernel((const void*)k_hist_finalize, dim3(1), dim3(256), a_fin));
   GCHK(add_event(3));
   GCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
 #undef GCHK

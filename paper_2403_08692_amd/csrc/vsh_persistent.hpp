@@ -104,6 +104,7 @@ struct BatchGraph {
   double* no_hist = nullptr;  // k_me's histogram to clear: none in a batch
   unsigned long long* ih = nullptr;  // fixed-point cells and largest weight (null: FP64 sums)
   unsigned long long* wm = nullptr;
+  uint32_t fixed = 0;  // k_hist_finalize's fixed-point flag
   uint64_t lanes = 0;
   uint32_t block = 0;
   uint32_t mapping = 0;
