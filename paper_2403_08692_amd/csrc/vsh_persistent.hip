@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "vsh_internal.hpp"
@@ -451,7 +452,32 @@ constexpr uint32_t kEmitDiv = 2;
 // next round's items while it reduces its winners (faster for the persistent
 // kernel, 1% slower for the plain one, which takes kAhead with quark masses
 // only, to fit three waves).
-template <bool kCached, bool kMassive = false, bool kAhead = false>
+//
+// kAheadCycles (massless cached events): a wave cycle may evaluate K = 2^m
+// consecutive veto cycles of each event that makes trials.  A trial's scale
+// is ln t + ln(R)/c, with c fixed until an emission changes the event, so
+// between emissions the winner of a veto cycle (the largest ln(R)/c) does
+// not depend on the scale it starts from; only the decision does.  The
+// rounds therefore draw the trials of cycles c .. c+K-1 together (item j of
+// cycle k at position j K + k of its section, keyed by that cycle), each
+// (event, cycle) pair keeps its best ln(R)/c, then one lane per pair chains
+// the scales in order (ln t of cycle k = that of cycle k-1 plus the pair's
+// best, the same additions a cycle-by-cycle evaluation makes) and makes the
+// pair's CheckCutoff, alpha_s and AcceptOrVeto with the pair's accept block.
+// Each event then takes its pairs in order up to the first that ends the
+// cycle sequence (cutoff, acceptance, cycle limit); later pairs are dropped
+// and drawn again, keyed by the same cycles, after the emission.  K is the
+// largest power of two with at most 64 pairs, at most kAheadMax cycles and
+// at most kAheadRounds more rounds than one cycle's items take.
+constexpr uint32_t kAheadLgMax = 3;  // kAheadMax = 8
+constexpr uint32_t kAheadRounds = 3;
+enum : uint32_t { kPairVeto = 0, kPairAccept = 1, kPairDone = 2, kPairLimit = 3 };
+
+__device__ __forceinline__ uint32_t list_pos(uint32_t v, uint32_t vg, uint32_t n_g, uint32_t lg) {
+  return v < vg ? v >> lg : n_g + ((v - vg) >> lg);
+}
+
+template <bool kCached, bool kMassive = false, bool kAhead = false, bool kAheadCycles = false>
 __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_t words, EvState& s, bool busy,
                                            bool& pend, Pending& pd, const Records& slots, uint64_t slot,
                                            const EndCache& ec, uint64_t wave_col, uint32_t lane,
@@ -480,11 +506,23 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   const uint64_t excl = incl - mine;
   const uint64_t tot = lane63(incl);
   const uint32_t n_g1 = (uint32_t)(tot & kF), n_q = (uint32_t)((tot >> 21) & kF), n_s = (uint32_t)(tot >> 42);
+  // cycles evaluated ahead: K = 2^lg_ (1 without kAheadCycles); a trialing
+  // event's rank is the number of trialing lanes below its own
+  uint32_t lg_ = 0;
+  const uint64_t tmask = kAheadCycles ? __ballot(trial) : 0ull;
+  if (kAheadCycles) {
+    const uint32_t n_tr = (uint32_t)__popcll(tmask), n1 = n_g1 + n_q, r1 = (n1 + 63) / 64;
+    while (lg_ < kAheadLgMax && (n_tr << (lg_ + 1)) <= 64u && ((n1 << (lg_ + 1)) + 63) / 64 <= r1 + kAheadRounds)
+      ++lg_;
+  }
+  const uint32_t lg = lg_, K = 1u << lg_;
+  const bool ahead = kAheadCycles && lg_ > 0;  // one cycle at a time otherwise
   // A massless gluon's two dipole ends become two items (half the longest
   // lane's work in a round) whenever that takes no more rounds than one item
   // per gluon; otherwise, and with quark masses, one item per gluon.
-  const uint32_t kge = !kMassive && (2 * n_g1 + n_q + 63) / 64 == (n_g1 + n_q + 63) / 64 ? 2u : 1u;
+  const uint32_t kge = !kMassive && (K * (2 * n_g1 + n_q) + 63) / 64 == (K * (n_g1 + n_q) + 63) / 64 ? 2u : 1u;
   const uint32_t n_g = kge * n_g1;
+  const uint32_t vg = K * n_g, vt = vg + K * n_q;  // positions of the rounds: gluon items, then quark items
   sh.gstart[lane] = kge * (uint32_t)(excl & kF);
   sh.qstart[lane] = (uint32_t)((excl >> 21) & kF);
   sh.sstart[lane] = (uint32_t)(excl >> 42);
@@ -570,7 +608,9 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   }
   // --- trials, 64 items per round: the gluon items, then the quark items
   // (a round may hold the end of one and the start of the other: its quark
-  // lanes finish early, in time the round takes for its gluons anyway)
+  // lanes finish early, in time the round takes for its gluons anyway); with
+  // cycles evaluated ahead, item j of a section takes its positions j K ..
+  // j K + K - 1, one per cycle, so each (event, cycle) run strides by K
   const uint32_t run = gmax > qmax ? gmax : qmax;
   // the end-cache entry of the lane's item in the coming round is loaded
   // while the current round reduces its winners (an item past the list's
@@ -578,85 +618,97 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   constexpr bool kPre = kAhead && kCached && !kMassive;
   Ent5 pw{{0ull, 0ull, 0ull, 0ull, 0ull}};
   bool pre = false;
-  if (kPre) pre = prefetch_entry(sh.item, 0u + lane, n_g + n_q, kItems, ec, wave_col, pw);
-  for (uint32_t r0 = 0; r0 < n_g + n_q; r0 += 64) {
-    const uint32_t at = r0 + lane;  // position in the item list
-    const bool gsec = at < n_g;
-    const uint32_t* st = gsec ? sh.gstart : sh.qstart;
-    const uint32_t base = gsec ? 0u : n_g;  // list position of the section
-    const uint32_t j = at - base;           // index within the section
-    const bool active = at < n_g + n_q;
-    double v = -INFINITY;
-    uint32_t idx = kNoTrial;
-    uint32_t o = 63, seg0 = 64, last = 0;
-    if (active) {
-      uint32_t i;
-      if (at < kItems) {
-        const uint32_t it = sh.item[at];
-        o = it >> 10;
-        i = it & 1023u;
-      } else {
-        o = owner_of(st, j);
-        i = select_slot(gm + (uint64_t)o * words, words, gsec ? (j - st[o]) / kge : j - st[o], gsec);
+  if (kPre) pre = prefetch_entry(sh.item, list_pos(lane, vg, n_g, lg), n_g + n_q, kItems, ec, wave_col, pw);
+  // (the rounds' code compiled twice: one cycle at a time it takes no cycle
+  // index and no pair rank)
+  auto rounds = [&](auto kA) {
+    constexpr bool A = decltype(kA)::value;
+    const uint32_t lg = A ? lg_ : 0u, K = 1u << lg;
+    for (uint32_t r0 = 0; r0 < vt; r0 += 64) {
+      const uint32_t at = r0 + lane;  // position in the rounds
+      const bool gsec = at < vg;
+      const uint32_t* st = gsec ? sh.gstart : sh.qstart;
+      const uint32_t vbase = gsec ? 0u : vg;  // first position of the section
+      const uint32_t j = (at - vbase) >> lg;  // item index within the section
+      const uint32_t k = (at - vbase) & (K - 1u);  // cycle ahead
+      const bool active = at < vt;
+      double v = -INFINITY;
+      uint32_t idx = kNoTrial;
+      uint32_t o = 63, first = 0, last = 0, pr = 63;
+      if (active) {
+        uint32_t i;
+        const uint32_t lp = (gsec ? 0u : n_g) + j;  // list position
+        if (lp < kItems) {
+          const uint32_t it = sh.item[lp];
+          o = it >> 10;
+          i = it & 1023u;
+        } else {
+          o = owner_of(st, j);
+          i = select_slot(gm + (uint64_t)o * words, words, gsec ? (j - st[o]) / kge : j - st[o], gsec);
+        }
+        // a gluon item's ends: both, or (two items per gluon) the parity of
+        // its place in the owner's run
+        const int e_lo = gsec && kge == 2 ? (int)((j - st[o]) & 1u) : 0, e_hi = gsec && kge == 2 ? e_lo : 1;
+        first = vbase + (st[o] << lg) + k;  // position of the owner's first item of this cycle in the section
+        last = (j + 1 == st[o + 1]) || lane + K > 63u;
+        pr = A ? ((uint32_t)__popcll(tmask & ((1ull << o) - 1ull)) << lg) | k : o;
+        // ahead: trials compared by ln(R)/c alone (the scale added at the decision)
+        const TrialCtx c{Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]},
+                         A ? 0.0 : sh.lt[o], sh.tcut[o], sh.ltc[o], sh.cfac[o], sh.cycle[o] + k};
+        double best = A ? -INFINITY : c.ltc, wca = 0.0, wcb = 0.0;
+        uint32_t widx = kNoTrial;
+        uint32_t nt = 0, ne = 0;
+        if constexpr (kMassive && kCached)
+          parton_trials_mcached(c, wave_col + o, (int)i, ec, best, widx, nt, ne);
+        else if constexpr (kMassive)
+          parton_trials_mflat(c, slots, sh.slot[o], (int)i, QuarkMasses{0.0, 0.0, 0.0, sh.mc[o], sh.mb[o]}, best,
+                              widx, nt, ne);
+        else
+          item_trials(c, slots, sh.slot[o], (int)i, e_lo, e_hi, ec, wave_col + o, kCached, kPre && pre, pw, best, widx,
+                      wca, wcb, nt, ne);
+        if (widx != kNoTrial) {
+          v = best;
+          idx = (widx << 6) | lane;  // same order as widx: items of one pair differ in i
+          if constexpr (!kMassive) {
+            sh.coef[0][lane] = wca;
+            sh.coef[1][lane] = wcb;
+          }
+        }
+        atomicAdd(&sh.counts[pr], nt | (ne << 16));  // at most 12 x 1024 trials and 2048 ends per cycle
       }
-      // a gluon item's ends: both, or (two items per gluon) the parity of
-      // its place in the owner's run
-      const int e_lo = gsec && kge == 2 ? (int)((j - st[o]) & 1u) : 0, e_hi = gsec && kge == 2 ? e_lo : 1;
-      const uint32_t first = base + st[o];  // list position of the owner's first item in this section
-      seg0 = (first > r0 ? first : r0) - r0;
-      last = (j + 1 == st[o + 1]) || lane == 63;
-      const TrialCtx c{Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]}, sh.lt[o], sh.tcut[o],
-                       sh.ltc[o], sh.cfac[o], sh.cycle[o]};
-      double best = c.ltc, wca = 0.0, wcb = 0.0;
-      uint32_t widx = kNoTrial;
-      uint32_t nt = 0, ne = 0;
-      if constexpr (kMassive && kCached)
-        parton_trials_mcached(c, wave_col + o, (int)i, ec, best, widx, nt, ne);
-      else if constexpr (kMassive)
-        parton_trials_mflat(c, slots, sh.slot[o], (int)i, QuarkMasses{0.0, 0.0, 0.0, sh.mc[o], sh.mb[o]}, best,
-                            widx, nt, ne);
-      else
-        item_trials(c, slots, sh.slot[o], (int)i, e_lo, e_hi, ec, wave_col + o, kCached, kPre && pre, pw, best, widx,
-                    wca, wcb, nt, ne);
-      if (widx != kNoTrial) {
-        v = best;
-        idx = (widx << 6) | lane;  // same order as widx: items of one owner differ in i
-        if constexpr (!kMassive) {
-          sh.coef[0][lane] = wca;
-          sh.coef[1][lane] = wcb;
+      if (kPre) pre = prefetch_entry(sh.item, list_pos(r0 + 64 + lane, vg, n_g, lg), n_g + n_q, kItems, ec, wave_col, pw);
+      for (uint32_t d = 1; (d << lg) < 64 && d < run; d <<= 1) {
+        const uint32_t dd = d << lg;
+        const double vn = __shfl_up(v, dd);
+        const uint32_t in = __shfl_up(idx, dd);
+        if (active && lane >= dd && at - dd >= first && beats(vn, in, v, idx)) {
+          v = vn;
+          idx = in;
         }
       }
-      atomicAdd(&sh.counts[o], nt | (ne << 16));  // at most 12 x 1024 trials and 2048 ends per cycle
-    }
-    if (kPre) pre = prefetch_entry(sh.item, r0 + 64 + lane, n_g + n_q, kItems, ec, wave_col, pw);
-    for (uint32_t d = 1; d < 64 && d < run; d <<= 1) {
-      const double vn = __shfl_up(v, d);
-      const uint32_t in = __shfl_up(idx, d);
-      if (active && lane >= d && lane - d >= seg0 && beats(vn, in, v, idx)) {
-        v = vn;
-        idx = in;
+      // fold each run's best into its pair's: gluon runs first, then quark
+      // runs (one pair may end a run of each kind in the same round)
+      if (active && last && gsec && beats(v, idx, sh.best_v[pr], sh.best_idx[pr])) {
+        sh.best_v[pr] = v;
+        sh.best_idx[pr] = idx;
+        if constexpr (!kMassive) {
+          sh.best_c[0][pr] = sh.coef[0][idx & 63u];
+          sh.best_c[1][pr] = sh.coef[1][idx & 63u];
+        }
       }
-    }
-    // fold each run's best into its owner's: gluon runs first, then quark
-    // runs (one owner may end a run of each kind in the same round)
-    if (active && last && gsec && beats(v, idx, sh.best_v[o], sh.best_idx[o])) {
-      sh.best_v[o] = v;
-      sh.best_idx[o] = idx;
-      if constexpr (!kMassive) {
-        sh.best_c[0][o] = sh.coef[0][idx & 63u];
-        sh.best_c[1][o] = sh.coef[1][idx & 63u];
+      if (active && last && !gsec && beats(v, idx, sh.best_v[pr], sh.best_idx[pr])) {
+        sh.best_v[pr] = v;
+        sh.best_idx[pr] = idx;
+        if constexpr (!kMassive) {
+          sh.best_c[0][pr] = sh.coef[0][idx & 63u];
+          sh.best_c[1][pr] = sh.coef[1][idx & 63u];
+        }
       }
+      __syncthreads();
     }
-    if (active && last && !gsec && beats(v, idx, sh.best_v[o], sh.best_idx[o])) {
-      sh.best_v[o] = v;
-      sh.best_idx[o] = idx;
-      if constexpr (!kMassive) {
-        sh.best_c[0][o] = sh.coef[0][idx & 63u];
-        sh.best_c[1][o] = sh.coef[1][idx & 63u];
-      }
-    }
-    __syncthreads();
-  }
+  };
+  if (ahead) rounds(std::true_type{});
+  else rounds(std::false_type{});
   if (kAhead) {  // the event's trial constants, published to LDS above, come back from there
     s.key = Keyed{sh.key[0][lane], sh.key[1][lane], sh.key[2][lane], sh.key[3][lane]};
     s.lt = sh.lt[lane];
@@ -666,7 +718,78 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     s.cycle = sh.cycle[lane];
   }
   // --- each owner that made trials decides its cycle
-  if (trial && kMassive) {
+  if (ahead) {
+    // one lane per (event, cycle) pair: the pair's scale, cutoff and veto;
+    // its outcome goes into the low bits of its best_idx entry (the lane
+    // of the winning item is not needed any more)
+    const uint32_t n_pairs = (uint32_t)__popcll(tmask) << lg;
+    const uint32_t o = lane < n_pairs ? select64(tmask, lane >> lg) : lane;  // the pair's event
+    const double asmax = __shfl(s.asmax, (int)o);                              // its trial alpha_s
+    if (lane < n_pairs) {
+      const uint32_t rk = lane >> lg, k = lane & (K - 1u);
+      const uint32_t cyc = sh.cycle[o] + k, bi = sh.best_idx[lane];
+      uint32_t f = kPairVeto;
+      double l = sh.lt[o], t = 0.0, z = 0.0, wf = 1.0;
+      if (cyc >= sh.climit[o]) {
+        f = kPairLimit;
+      } else if (bi == kNoTrial) {
+        f = kPairDone;  // no end with phase space above the cutoff
+      } else {
+        for (uint32_t q = 0; q <= k; ++q) l += sh.best_v[(rk << lg) | q];  // the winners' scales, in cycle order
+        if (!(l > sh.ltc[o])) {
+          f = kPairDone;
+        } else {
+          Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
+          w.K = (int)((bi >> 6) & 15u);
+          end_from_coeffs(sh.cfac[o], sh.tcut[o], w.K, sh.best_c[0][lane], sh.best_c[1][lane], w);
+          t = exp(l);
+          const U4 a = Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]}.draw(cyc, kPurposeAccept, 0);
+          z = trial_z(w, unit(a.x, a.y));
+          const double prob = massless_ratio(w.K, l, t, z, w.rq2, asmax);
+          if (prob >= 0.0 && accept_test(prob, a, wf)) f = kPairAccept;
+        }
+      }
+      sh.best_idx[lane] = (bi & ~63u) | f;
+      sh.coef[0][lane] = l;  // the cycle's scale (its own reads of coef are over)
+      sh.coef[1][lane] = wf;
+      sh.best_c[0][lane] = t;
+      sh.best_c[1][lane] = z;
+    }
+    __syncthreads();
+    // each event takes its pairs in cycle order up to the first that ends
+    // the sequence: the steps of a cycle-by-cycle decision
+    if (trial) {
+      const uint32_t rk = (uint32_t)__popcll(tmask & ((1ull << lane) - 1ull));
+      for (uint32_t k = 0; k < K; ++k) {
+        const uint32_t pr = (rk << lg) | k;
+        const uint32_t f = sh.best_idx[pr] & 63u;
+        if (f == kPairLimit) {
+          s.status = kCycleLimitHit;
+          break;
+        }
+        s.trials += sh.counts[pr] & 0xFFFFu;
+        s.ends += sh.counts[pr] >> 16;
+        const uint32_t this_cycle = s.cycle++;
+        if (f == kPairDone) {
+          s.status = kDone;
+          break;
+        }
+        s.lt = sh.coef[0][pr];
+        sh.wsh[lane] *= sh.coef[1][pr];
+        if (f == kPairAccept) {
+          if (s.n == s.cap) {
+            s.status = kOverflow;
+          } else {
+            const uint32_t wi = sh.best_idx[pr] >> 6;
+            pd = Pending{sh.best_c[0][pr], sh.best_c[1][pr], (int)(wi >> 14), (int)((wi >> 4) & 1023u),
+                         (int)(wi & 15u), this_cycle};
+            pend = true;
+          }
+          break;
+        }
+      }
+    }
+  } else if (trial && kMassive) {
     s.trials += sh.counts[lane] & 0xFFFFu;
     s.ends += sh.counts[lane] >> 16;
     const uint32_t bi = sh.best_idx[lane];
@@ -751,7 +874,8 @@ __global__ void __launch_bounds__(64, 3) k_shower_plain_flat(Records r, Summary 
     mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
   while (__any(busy)) {
-    flat_cycle<true, kMassive, kMassive>(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane, in.qm);
+    flat_cycle<true, kMassive, kMassive, !kMassive>(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane,
+                                                    in.qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
       write_state(s, sm, e);
@@ -807,8 +931,8 @@ __global__ void __launch_bounds__(64, kInPlace || (kCached && !kMassive) ? 3 : 2
       busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle<kCached, kMassive, kInPlace>(sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane,
-                                            lane, A.reqs[req].qm);
+    flat_cycle<kCached, kMassive, kInPlace, kInPlace && kCached && !kMassive>(
+        sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane, A.reqs[req].qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);

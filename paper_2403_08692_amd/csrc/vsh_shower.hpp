@@ -147,8 +147,12 @@ __device__ __forceinline__ bool end_coeffs(double cfac, double tcut, int pid_i, 
 // recovered from its trial coefficients (the numbers the flattened kernels
 // cache), so that every form decides from the same bits.  cb / (cfac T_R/2)
 // = z+ - z- = sqrt(1 - 4 t_C / Q^2), ca / (cfac C) = L with C = 2 C_F or C_A.
-// The divisions by cfac and t_C do not wait for the coefficients.
+// The divisions by cfac and t_C do not wait for the coefficients.  The
+// decision's arithmetic (this, trial_z, massless_ratio) is evaluated as
+// written, with no multiply-add fused by the compiler, so that the bits do
+// not depend on where it is inlined.
 __device__ __forceinline__ void end_from_coeffs(double cfac, double tcut, int K, double ca, double cb, Winner& w) {
+#pragma clang fp contract(off)
   const double rcf = 1.0 / cfac, rt4 = 0.25 / tcut;
   const double dz = cb * (rcf * (1.0 / (0.5 * kTR)));
   w.zp = 0.5 * (1.0 + dz);
@@ -163,6 +167,7 @@ __device__ __forceinline__ void end_from_coeffs(double cfac, double tcut, int K,
 // y >= 1 (outside the phase space).
 __device__ __forceinline__ double massless_ratio(int K, double lt, double t, double z, double rq2,
                                                  double asmax) {
+#pragma clang fp contract(off)
   const double omz = 1.0 - z;
   const double yn = t * rq2, yd = z * omz;
   if (!(yn < yd)) return -1.0;
@@ -180,6 +185,14 @@ __device__ __forceinline__ double massless_ratio(int K, double lt, double t, dou
     den = yd;
   }
   return kAlphaSMZ * num / (asmax * da * den);
+}
+
+// z of the winner from the accept block's uniform uz, by the overestimate's
+// inverse integral: for the 1/(1-z) kernels 1 - z = (1 - zm) ((1 - zp)/(1 -
+// zm))^uz = (1 - zm) exp(-uz L); uniform in [zm, zp] for g -> f fbar.
+__device__ __forceinline__ double trial_z(const Winner& w, double uz) {
+#pragma clang fp contract(off)
+  return w.K <= 10 ? 1.0 - (1.0 - w.zm) * exp(-uz * w.L) : w.zm + (w.zp - w.zm) * uz;
 }
 
 // The trials of an end with coefficients (ca, cb): t_try = t R^(1/c)
@@ -295,10 +308,7 @@ __device__ __forceinline__ bool veto_decide_drawn(EvState& s, double best, const
   }
   s.lt = best;  // the winner's scale bounds every later trial
   const double t = exp(best);
-  // z from the overestimate's inverse integral: for the 1/(1-z) kernels
-  // 1 - z = (1 - zm) ((1 - zp)/(1 - zm))^u = (1 - zm) exp(-u L)
-  const double uz = unit(a.x, a.y);
-  const double z = w.K <= 10 ? 1.0 - (1.0 - w.zm) * exp(-uz * w.L) : w.zm + (w.zp - w.zm) * uz;
+  const double z = trial_z(w, unit(a.x, a.y));
   const double prob = massless_ratio(w.K, best, t, z, w.rq2, s.asmax);
   if (prob < 0.0) return false;  // y >= 1
   if (!accept_test(prob, a, wsh)) return false;
@@ -750,8 +760,7 @@ __device__ __forceinline__ bool veto_decide_massive(EvState& s, double best, con
   }
   s.lt = best;
   const double t = exp(best);
-  const double uz = unit(a.x, a.y);
-  const double z = w.K <= 10 ? 1.0 - (1.0 - w.zm) * exp(-uz * w.L) : w.zm + (w.zp - w.zm) * uz;
+  const double z = trial_z(w, unit(a.x, a.y));
   double prob;
   if (!W.massive) {
     prob = massless_ratio(w.K, best, t, z, w.rq2, s.asmax);

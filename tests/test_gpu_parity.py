@@ -355,3 +355,35 @@ def test_tuner_cache_is_reused_across_contexts(tmp_path, persistent):
     assert len(open(path).read().splitlines()) == 2
     print(f"tuning {t_tune:.2f} s, from the cache {t_hit * 1e3:.2f} ms", flush=True)
     assert t_hit < 0.1 * t_tune
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("ecm,tcut,cap,limit,t_over", [(91.2, 1.0, 64, 0, 0.0), (91.2, 1.0, 64, 25, 10.0),
+                                                        (500.0, 0.25, 12, 0, 0.0), (500.0, 0.25, 256, 90, 20.0)])
+def test_cycles_ahead_sparse_waves(ctx, oracle, persistent, ecm, tcut, cap, limit, t_over):
+    # waves of a few events evaluate up to eight veto cycles per pass: the
+    # events, counts, cycle limits, overflows and weights stay the oracle's
+    for n, first in ((3, 0), (9, 1000), (40, 77)):
+        print(f"case cycles ahead n={n} first={first} ecm={ecm} tcut={tcut} cap={cap} limit={limit} "
+              f"t_over={t_over} persistent={persistent}", flush=True)
+        g = ctx.generate(n, seed=12, first_event=first, ecm=ecm, t_cut=tcut, max_partons=cap, summary=True,
+                         records=True, persistent=persistent, cycle_limit=limit, t_over=t_over)
+        o = oracle.generate(12, first, n, ecm, tcut, cap, records=True, max_cycles=limit, t_over=t_over)
+        rep, same = parity.compare(g, o, ecm, n)
+        print(rep, flush=True)
+        parity.assert_parity(rep)
+        assert rep["frac"] == 1.0  # cycles, trials, ends, statuses and emission hashes all equal
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_cycles_ahead_same_bits_as_full_waves(ctx, persistent):
+    # the first events of a full batch (waves of 64 busy events: mostly one
+    # cycle per pass) against the same events alone (a few events per wave:
+    # several cycles per pass): identical summaries and weights, bit for bit
+    kw = dict(seed=31, ecm=200.0, t_cut=0.5, max_partons=128, summary=True, persistent=persistent, t_over=20.0)
+    full = ctx.generate(6400, **kw)
+    for n in (2, 5, 33):
+        alone = ctx.generate(n, **kw)
+        np.testing.assert_array_equal(alone["sum_i"], full["sum_i"][:, :n])
+        np.testing.assert_array_equal(alone["hash"], full["hash"][:n])
+        np.testing.assert_array_equal(alone["sum_d"], full["sum_d"][:, :n])
