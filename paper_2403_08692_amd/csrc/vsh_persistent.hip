@@ -931,7 +931,7 @@ __global__ void __launch_bounds__(64, kInPlace || (kCached && !kMassive) ? 3 : 2
       busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle<kCached, kMassive, kInPlace, kInPlace && kCached && !kMassive>(
+    flat_cycle<kCached, kMassive, kInPlace, kCached && !kMassive>(
         sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane, A.reqs[req].qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
