@@ -155,10 +155,22 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
 // order keeps the first of equal trials, and this rule picks that one in
 // whatever order the items come.  Each owner then decides its own cycle.
 // ---------------------------------------------------------------------------
+// Launch-wide constants of the kernels whose events all belong to one
+// request: each event's key is make_keyed(seed, first + its record column)
+// and the cycle limit is one, so neither is kept per event in LDS (kOne),
+// which leaves room for one more block per CU with 128- and 256-parton
+// records.
+struct OneRequest {
+  uint64_t seed, first;
+  uint32_t climit;
+};
+constexpr uint32_t kOneAboveCap = 64;
+
+template <bool kOne>
 struct FlatShared {
   double lt[64], tcut[64], ltc[64], cfac[64];
   uint32_t slot[64];  // record columns (a launch covers fewer than 2^32)
-  uint32_t key[4][64];
+  uint32_t key[4][kOne ? 1 : 64];
   uint32_t cycle[64];
   uint32_t gstart[65], qstart[65];  // per-owner item offsets in the gluon and quark sections
   uint32_t sstart[65];              // per-owner offsets in the list of stale partons
@@ -169,7 +181,7 @@ struct FlatShared {
   uint32_t best_idx[64];  // packed (i, k, K) << 6 | the lane whose item made it
   double best_c[2][64];   // per owner: those of its running best
   uint32_t counts[64];  // the cycle's trials (low 16 bits) and active ends (high 16 bits) per owner
-  uint32_t climit[64];  // each event's cycle limit
+  uint32_t climit[kOne ? 1 : 64];  // each event's cycle limit
   double wsh[64];       // each event's shower weight (weighted veto)
   union {
     double coef[2][64];     // massless: per item lane, its best end's trial coefficients (ca, cb)
@@ -477,12 +489,27 @@ __device__ __forceinline__ uint32_t list_pos(uint32_t v, uint32_t vg, uint32_t n
   return v < vg ? v >> lg : n_g + ((v - vg) >> lg);
 }
 
-template <bool kCached, bool kMassive = false, bool kAhead = false, bool kAheadCycles = false>
-__device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_t words, EvState& s, bool busy,
+template <bool kCached, bool kMassive = false, bool kAhead = false, bool kAheadCycles = false, bool kOne = false>
+__device__ __forceinline__ void flat_cycle(FlatShared<kOne>& sh, const OneRequest& one, uint64_t* gm, uint32_t words, EvState& s, bool busy,
                                            bool& pend, Pending& pd, const Records& slots, uint64_t slot,
                                            const EndCache& ec, uint64_t wave_col, uint32_t lane,
                                            const QuarkMasses& qm = QuarkMasses{0.0, 0.0, 0.0, 0.0, 0.0}) {
   const bool trial = busy && !pend;
+  // the key and cycle limit of the event in column o of this wave
+  // (kOne: the seed's words come from LDS at each use, so that the
+  // compiler does not hold Philox's round keys in registers for the kernel)
+  auto key_of = [&](uint32_t o) -> Keyed {
+    if constexpr (kOne) {
+      const uint64_t ev = one.first + sh.slot[o];
+      return Keyed{(uint32_t)ev, (uint32_t)(ev >> 32), sh.key[2][0], sh.key[3][0]};
+    } else {
+      return Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]};
+    }
+  };
+  auto climit_of = [&](uint32_t o) -> uint32_t {
+    if constexpr (kOne) return one.climit;
+    else return sh.climit[o];
+  };
   uint64_t* mym = gm + (uint64_t)lane * words;
   uint64_t* sm = gm + (uint64_t)64 * words;  // stale masks
   uint64_t* mys = sm + (uint64_t)lane * words;
@@ -567,10 +594,15 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   sh.ltc[lane] = s.ltc;
   sh.cfac[lane] = s.cfac;
   sh.slot[lane] = (uint32_t)slot;
-  sh.key[0][lane] = s.key.ev_lo;
-  sh.key[1][lane] = s.key.ev_hi;
-  sh.key[2][lane] = s.key.k0;
-  sh.key[3][lane] = s.key.k1;
+  if constexpr (!kOne) {
+    sh.key[0][lane] = s.key.ev_lo;
+    sh.key[1][lane] = s.key.ev_hi;
+    sh.key[2][lane] = s.key.k0;
+    sh.key[3][lane] = s.key.k1;
+  } else if (lane == 0) {
+    sh.key[2][0] = (uint32_t)one.seed;
+    sh.key[3][0] = (uint32_t)(one.seed >> 32);
+  }
   sh.cycle[lane] = s.cycle;
   sh.best_v[lane] = -INFINITY;
   sh.best_idx[lane] = kNoTrial;
@@ -653,7 +685,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
         last = (j + 1 == st[o + 1]) || lane + K > 63u;
         pr = A ? ((uint32_t)__popcll(tmask & ((1ull << o) - 1ull)) << lg) | k : o;
         // ahead: trials compared by ln(R)/c alone (the scale added at the decision)
-        const TrialCtx c{Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]},
+        const TrialCtx c{key_of(o),
                          A ? 0.0 : sh.lt[o], sh.tcut[o], sh.ltc[o], sh.cfac[o], sh.cycle[o] + k};
         double best = A ? -INFINITY : c.ltc, wca = 0.0, wcb = 0.0;
         uint32_t widx = kNoTrial;
@@ -710,7 +742,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
   if (ahead) rounds(std::true_type{});
   else rounds(std::false_type{});
   if (kAhead) {  // the event's trial constants, published to LDS above, come back from there
-    s.key = Keyed{sh.key[0][lane], sh.key[1][lane], sh.key[2][lane], sh.key[3][lane]};
+    s.key = key_of(lane);
     s.lt = sh.lt[lane];
     s.tcut = sh.tcut[lane];
     s.ltc = sh.ltc[lane];
@@ -730,7 +762,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
       const uint32_t cyc = sh.cycle[o] + k, bi = sh.best_idx[lane];
       uint32_t f = kPairVeto;
       double l = sh.lt[o], t = 0.0, z = 0.0, wf = 1.0;
-      if (cyc >= sh.climit[o]) {
+      if (cyc >= climit_of(o)) {
         f = kPairLimit;
       } else if (bi == kNoTrial) {
         f = kPairDone;  // no end with phase space above the cutoff
@@ -743,7 +775,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
           w.K = (int)((bi >> 6) & 15u);
           end_from_coeffs(sh.cfac[o], sh.tcut[o], w.K, sh.best_c[0][lane], sh.best_c[1][lane], w);
           t = exp(l);
-          const U4 a = Keyed{sh.key[0][o], sh.key[1][o], sh.key[2][o], sh.key[3][o]}.draw(cyc, kPurposeAccept, 0);
+          const U4 a = key_of(o).draw(cyc, kPurposeAccept, 0);
           z = trial_z(w, unit(a.x, a.y));
           const double prob = massless_ratio(w.K, l, t, z, w.rq2, asmax);
           if (prob >= 0.0 && accept_test(prob, a, wf)) f = kPairAccept;
@@ -845,7 +877,7 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
     set_bit(mys, pak);
     pend = false;
   }
-  if (busy && !pend && s.status == kRunning && s.cycle >= sh.climit[lane]) s.status = kCycleLimitHit;
+  if (busy && !pend && s.status == kRunning && s.cycle >= climit_of(lane)) s.status = kCycleLimitHit;
 }
 
 // Plain one-launch form with the flattened mapping: wave w owns events
@@ -854,10 +886,11 @@ __device__ __forceinline__ void flat_cycle(FlatShared& sh, uint64_t* gm, uint32_
 // Three resident waves per SIMD (168 registers, 11 KB of LDS per wave); the
 // massive instantiation reloads its trial constants from LDS after the
 // rounds (kAhead) to fit them without spilling.
-template <bool kMassive>
+template <bool kMassive, bool kOne>
 __global__ void __launch_bounds__(64, 3) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n,
                                                              EndCache ec) {
-  __shared__ FlatShared sh;
+  __shared__ FlatShared<kOne> sh;
+  const OneRequest one{in.seed, in.first, in.cycle_limit};
   const uint32_t lane = threadIdx.x;
   const uint32_t words = mask_words(r.cap);
   const uint64_t e = (uint64_t)blockIdx.x * 64 + lane;
@@ -869,13 +902,13 @@ __global__ void __launch_bounds__(64, 3) k_shower_plain_flat(Records r, Summary 
   if (busy) {
     init_state(s, r, e, make_keyed(in.seed, in.first + e), in.ecm_of(e), in.tcut_of(e), in.t_over,
                sm.i[kSiN * sm.stride + e], (int)r.cap);
-    sh.climit[lane] = in.cycle_limit;
+    if constexpr (!kOne) sh.climit[lane] = in.cycle_limit;
     sh.wsh[lane] = 1.0;
     mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
   while (__any(busy)) {
-    flat_cycle<true, kMassive, kMassive, !kMassive>(sh, flat_gmask, words, s, busy, pend, pd, r, e, ec, e - lane, lane,
-                                                    in.qm);
+    flat_cycle<true, kMassive, kMassive, !kMassive, kOne>(sh, one, flat_gmask, words, s, busy, pend, pd, r, e, ec,
+                                                          e - lane, lane, in.qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
       write_state(s, sm, e);
@@ -894,8 +927,16 @@ void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInp
   const EndCache ec{cache, r.cap};
   const dim3 g((n + 63) / 64), b(64);
   const size_t lds = flat_lds_bytes(r.cap);
-  if (in.massive) hipLaunchKernelGGL(k_shower_plain_flat<true>, g, b, lds, st, r, s, in, n, ec);
-  else hipLaunchKernelGGL(k_shower_plain_flat<false>, g, b, lds, st, r, s, in, n, ec);
+  // records above 64 partons: the LDS layout without per-event keys and
+  // limits (one more block per CU); at 64 the per-event layout measures faster
+  const bool one = r.cap > kOneAboveCap;
+  if (in.massive) {
+    if (one) hipLaunchKernelGGL((k_shower_plain_flat<true, true>), g, b, lds, st, r, s, in, n, ec);
+    else hipLaunchKernelGGL((k_shower_plain_flat<true, false>), g, b, lds, st, r, s, in, n, ec);
+  } else {
+    if (one) hipLaunchKernelGGL((k_shower_plain_flat<false, true>), g, b, lds, st, r, s, in, n, ec);
+    else hipLaunchKernelGGL((k_shower_plain_flat<false, false>), g, b, lds, st, r, s, in, n, ec);
+  }
 }
 
 // kCached: A.cache holds an end cache per lane (always when in place; the
@@ -904,9 +945,12 @@ void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInp
 // for massless events in the serving epochs' cached staging slots (a few
 // spilled registers, outweighed by the third wave: 4000 requests/s of the
 // serving mix keep p99 below 40 ms instead of 80); two otherwise.
-template <bool kInPlace, bool kMassive, bool kCached>
+template <bool kInPlace, bool kMassive, bool kCached, bool kOne = false>
 __global__ void __launch_bounds__(64, kInPlace || (kCached && !kMassive) ? 3 : 2) k_shower_flat(PersistArgs A) {
-  __shared__ FlatShared sh;
+  static_assert(kInPlace || !kOne, "one request per launch only in place");
+  __shared__ FlatShared<kOne> sh;
+  const OneRequest one = kOne ? OneRequest{A.reqs[0].seed, A.reqs[0].first, A.reqs[0].cycle_limit}
+                              : OneRequest{0ull, 0ull, 0u};
   const uint32_t lane = threadIdx.x;
   const uint32_t words = mask_words(A.slots.cap);
   const uint64_t L = (uint64_t)blockIdx.x * 64 + lane;
@@ -924,15 +968,15 @@ __global__ void __launch_bounds__(64, kInPlace || (kCached && !kMassive) ? 3 : 2
     if (refill<(kInPlace ? 16u : 1u)>(A, busy, 64, lane, since, drained, req, ev)) {
       slot = kInPlace ? ev : L;
       start_event<kInPlace>(s, A, A.reqs[req], ev, slot);
-      sh.climit[lane] = A.reqs[req].cycle_limit;
+      if constexpr (!kOne) sh.climit[lane] = A.reqs[req].cycle_limit;
       sh.wsh[lane] = 1.0;
       mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, A.slots,
                 slot, s.n);
       busy = true;
     }
     if (!__any(busy)) break;
-    flat_cycle<kCached, kMassive, kInPlace, kCached && !kMassive>(
-        sh, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane, A.reqs[req].qm);
+    flat_cycle<kCached, kMassive, kInPlace, kCached && !kMassive, kOne>(
+        sh, one, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane, A.reqs[req].qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
@@ -1057,8 +1101,10 @@ BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap, bool massive) {
 // The kernel of a mapping, in place or not, for requests with or without
 // quark masses; the flattened mapping with or without an end cache (in place
 // always has one).
-const void* persistent_kernel(uint32_t mapping, bool in_place, bool massive, bool cached) {
+const void* persistent_kernel(uint32_t mapping, bool in_place, bool massive, bool cached, uint32_t cap) {
   if (mapping == kMapFlat) {
+    if (in_place && cap > kOneAboveCap)
+      return massive ? (const void*)k_shower_flat<true, true, true, true> : (const void*)k_shower_flat<true, false, true, true>;
     if (in_place) return massive ? (const void*)k_shower_flat<true, true, true> : (const void*)k_shower_flat<true, false, true>;
     if (cached)
       return massive ? (const void*)k_shower_flat<false, true, true> : (const void*)k_shower_flat<false, false, true>;
@@ -1077,8 +1123,8 @@ void launch_persistent(const PersistArgs& A, uint64_t lanes, uint32_t block, uin
   const dim3 grid((uint32_t)(lanes / block));
   const size_t lds = mapping == kMapFlat ? flat_lds_bytes(A.slots.cap) : 0;
   void* args[] = {const_cast<PersistArgs*>(&A)};
-  (void)hipLaunchKernel(persistent_kernel(mapping, in_place, massive, A.cache.rec != nullptr), grid, dim3(block), args,
-                        lds, st);
+  (void)hipLaunchKernel(persistent_kernel(mapping, in_place, massive, A.cache.rec != nullptr, A.slots.cap), grid,
+                        dim3(block), args, lds, st);
 }
 
 void launch_setup(ReqDev* rd, const ReqDev& d, Segment* sd, const Segment& s, unsigned long long* counter,
@@ -1147,7 +1193,8 @@ static vsh_status build_batch_graph(vsh_ctx* ctx, BatchGraph& g, const PersistAr
   GCHK(add_event(1));
   void* a_pers[] = {&g.args};
   const bool massive = g.in.massive != 0;
-  GCHK(add_kernel(persistent_kernel(g.mapping, true, massive, true), dim3((uint32_t)(lanes / block)), dim3(block),
+  GCHK(add_kernel(persistent_kernel(g.mapping, true, massive, true, A.slots.cap), dim3((uint32_t)(lanes / block)),
+                  dim3(block),
                   a_pers, g.mapping == kMapFlat ? (unsigned)flat_lds_bytes(A.slots.cap) : 0u));
   GCHK(add_event(2));
   g.nb = L.buf.out.cap + 1;
