@@ -227,7 +227,7 @@ static std::string cache_key(const vsh_ctx* ctx, const vsh_request* req) {
                 VSH_VERSION_MAJOR, VSH_VERSION_MINOR, ctx->n_cu,
                 (req->flags & VSH_FORM_PERSISTENT) ? "persistent" : "plain", req->max_partons, m,
                 req->ecm_per_event ? 0.0 : req->ecm, req->tcut_per_event ? 0.0 : req->t_cut,
-                (req->ecm_per_event || req->tcut_per_event) ? h : 0ull, req->mass_c, req->mass_b, req->t_over,
+                (req->ecm_per_event || req->tcut_per_event) ? h : (uint64_t)0, req->mass_c, req->mass_b, req->t_over,
                 req->cycle_limit);
   return buf;
 }
