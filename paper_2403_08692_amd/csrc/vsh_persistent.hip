@@ -158,8 +158,11 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
 // Launch-wide constants of the kernels whose events all belong to one
 // request: each event's key is make_keyed(seed, first + its record column)
 // and the cycle limit is one, so neither is kept per event in LDS (kOne),
-// which leaves room for one more block per CU with 128- and 256-parton
-// records.
+// and the stale list is shorter (its overflow takes the offsets' path).
+// The batched kernel in place then fits four waves per SIMD with 64-parton
+// records (128 registers, 9.2 KB + 1 KB of LDS) and one more block per CU
+// with 128- and 256-parton records; the plain kernel takes it above 64
+// partons only.
 struct OneRequest {
   uint64_t seed, first;
   uint32_t climit;
@@ -176,7 +179,7 @@ struct FlatShared {
   uint32_t sstart[65];              // per-owner offsets in the list of stale partons
   uint16_t item[1024 + 2];          // the cycle's items, owner << 10 | parton: gluon items (a gluon
                                     // twice, once per dipole end, when rounds allow), then quark items
-  uint16_t sitem[384 + 2];          // the cycle's stale partons, owner << 10 | parton
+  uint16_t sitem[(kOne ? 100 : 384) + 2];  // the cycle's stale partons, owner << 10 | parton
   double best_v[64];
   uint32_t best_idx[64];  // packed (i, k, K) << 6 | the lane whose item made it
   double best_c[2][64];   // per owner: those of its running best
@@ -883,12 +886,13 @@ __device__ __forceinline__ void flat_cycle(FlatShared<kOne>& sh, const OneReques
 // Plain one-launch form with the flattened mapping: wave w owns events
 // 64w .. 64w+63 of the batch (already started by k_me) from start to cutoff,
 // with no refill; finished lanes only stop contributing trial work.
-// Three resident waves per SIMD (168 registers, 11 KB of LDS per wave); the
-// massive instantiation reloads its trial constants from LDS after the
-// rounds (kAhead) to fit them without spilling.
-template <bool kMassive, bool kOne>
-__global__ void __launch_bounds__(64, 3) k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n,
-                                                             EndCache ec) {
+// kFour (massless, at most 64 partons): four resident waves per SIMD (128
+// registers, a few spilled; 9.2 + 1 KB of LDS), the trial constants
+// reloaded from LDS after the rounds (kAhead); otherwise three waves, the
+// massive instantiation reloading them too to fit without spilling.
+template <bool kMassive, bool kOne, bool kFour = false>
+__global__ void __launch_bounds__(64, kFour ? 4 : 3)
+    k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n, EndCache ec) {
   __shared__ FlatShared<kOne> sh;
   const OneRequest one{in.seed, in.first, in.cycle_limit};
   const uint32_t lane = threadIdx.x;
@@ -907,7 +911,7 @@ __global__ void __launch_bounds__(64, 3) k_shower_plain_flat(Records r, Summary 
     mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, r, e, s.n);
   }
   while (__any(busy)) {
-    flat_cycle<true, kMassive, kMassive, !kMassive, kOne>(sh, one, flat_gmask, words, s, busy, pend, pd, r, e, ec,
+    flat_cycle<true, kMassive, kMassive || kFour, !kMassive, kOne>(sh, one, flat_gmask, words, s, busy, pend, pd, r, e, ec,
                                                           e - lane, lane, in.qm);
     if (busy && s.status != kRunning) {
       s.wsh = sh.wsh[lane];
@@ -927,26 +931,33 @@ void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInp
   const EndCache ec{cache, r.cap};
   const dim3 g((n + 63) / 64), b(64);
   const size_t lds = flat_lds_bytes(r.cap);
-  // records above 64 partons: the LDS layout without per-event keys and
-  // limits (one more block per CU); at 64 the per-event layout measures faster
-  const bool one = r.cap > kOneAboveCap;
+  // Massless events: the single-request LDS layout; up to 64 partons per
+  // record it leaves room for four blocks per SIMD, which the kernel fills
+  // with 128 registers by reloading its trial constants from LDS after the
+  // rounds (and loading the next round's cache entries ahead); above 64
+  // the masks make LDS the bound and the three-wave build is faster.  With
+  // quark masses: the per-event layout up to 64 partons, single-request
+  // above.
+  const bool wide = r.cap > kOneAboveCap;
   if (in.massive) {
-    if (one) hipLaunchKernelGGL((k_shower_plain_flat<true, true>), g, b, lds, st, r, s, in, n, ec);
+    if (wide) hipLaunchKernelGGL((k_shower_plain_flat<true, true>), g, b, lds, st, r, s, in, n, ec);
     else hipLaunchKernelGGL((k_shower_plain_flat<true, false>), g, b, lds, st, r, s, in, n, ec);
   } else {
-    if (one) hipLaunchKernelGGL((k_shower_plain_flat<false, true>), g, b, lds, st, r, s, in, n, ec);
-    else hipLaunchKernelGGL((k_shower_plain_flat<false, false>), g, b, lds, st, r, s, in, n, ec);
+    if (wide) hipLaunchKernelGGL((k_shower_plain_flat<false, true>), g, b, lds, st, r, s, in, n, ec);
+    else hipLaunchKernelGGL((k_shower_plain_flat<false, true, true>), g, b, lds, st, r, s, in, n, ec);
   }
 }
 
 // kCached: A.cache holds an end cache per lane (always when in place; the
 // serving epochs' staging slots have one unless it could not be allocated).
-// Three resident waves per SIMD in place (no spills at 168 registers) and
-// for massless events in the serving epochs' cached staging slots (a few
+// In place (one request, kOne): four resident waves per SIMD for massless
+// events (128 registers, no spills), three with quark masses.  Three for
+// massless events in the serving epochs' cached staging slots (a few
 // spilled registers, outweighed by the third wave: 4000 requests/s of the
 // serving mix keep p99 below 40 ms instead of 80); two otherwise.
 template <bool kInPlace, bool kMassive, bool kCached, bool kOne = false>
-__global__ void __launch_bounds__(64, kInPlace || (kCached && !kMassive) ? 3 : 2) k_shower_flat(PersistArgs A) {
+__global__ void __launch_bounds__(64, kOne && !kMassive ? 4 : (kInPlace || (kCached && !kMassive) ? 3 : 2))
+    k_shower_flat(PersistArgs A) {
   static_assert(kInPlace || !kOne, "one request per launch only in place");
   __shared__ FlatShared<kOne> sh;
   const OneRequest one = kOne ? OneRequest{A.reqs[0].seed, A.reqs[0].first, A.reqs[0].cycle_limit}
@@ -1103,9 +1114,8 @@ BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap, bool massive) {
 // always has one).
 const void* persistent_kernel(uint32_t mapping, bool in_place, bool massive, bool cached, uint32_t cap) {
   if (mapping == kMapFlat) {
-    if (in_place && cap > kOneAboveCap)
+    if (in_place)
       return massive ? (const void*)k_shower_flat<true, true, true, true> : (const void*)k_shower_flat<true, false, true, true>;
-    if (in_place) return massive ? (const void*)k_shower_flat<true, true, true> : (const void*)k_shower_flat<true, false, true>;
     if (cached)
       return massive ? (const void*)k_shower_flat<false, true, true> : (const void*)k_shower_flat<false, false, true>;
     return massive ? (const void*)k_shower_flat<false, true, false> : (const void*)k_shower_flat<false, false, false>;
