@@ -158,18 +158,18 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
 // Launch-wide constants of the kernels whose events all belong to one
 // request: each event's key is make_keyed(seed, first + its record column)
 // and the cycle limit is one, so neither is kept per event in LDS (kOne),
-// and the stale list is shorter (its overflow takes the offsets' path).
-// The batched kernel in place then fits four waves per SIMD with 64-parton
-// records (128 registers, 9.2 KB + 1 KB of LDS) and one more block per CU
-// with 128- and 256-parton records; the plain kernel takes it above 64
-// partons only.
+// and, for four waves per SIMD (kFour, records of at most 128 partons), the
+// stale list is shorter (its overflow takes the offsets' path): 9.2 KB + 1
+// KB of masks, sixteen blocks per CU at 64 partons, fourteen at 128.  With
+// 256-parton records the layout leaves room for one more block per CU.
 struct OneRequest {
   uint64_t seed, first;
   uint32_t climit;
 };
-constexpr uint32_t kOneAboveCap = 64;
+constexpr uint32_t kOneAboveCap = 64;  // massive plain kernel: the per-event layout up to here
+constexpr uint32_t kFourMaxCap = 128;  // massless: four-wave builds up to here (LDS-bound above)
 
-template <bool kOne>
+template <bool kOne, bool kFour = false>
 struct FlatShared {
   double lt[64], tcut[64], ltc[64], cfac[64];
   uint32_t slot[64];  // record columns (a launch covers fewer than 2^32)
@@ -179,7 +179,7 @@ struct FlatShared {
   uint32_t sstart[65];              // per-owner offsets in the list of stale partons
   uint16_t item[1024 + 2];          // the cycle's items, owner << 10 | parton: gluon items (a gluon
                                     // twice, once per dipole end, when rounds allow), then quark items
-  uint16_t sitem[(kOne ? 100 : 384) + 2];  // the cycle's stale partons, owner << 10 | parton
+  uint16_t sitem[(kFour ? 100 : 384) + 2];  // the cycle's stale partons, owner << 10 | parton
   double best_v[64];
   uint32_t best_idx[64];  // packed (i, k, K) << 6 | the lane whose item made it
   double best_c[2][64];   // per owner: those of its running best
@@ -492,8 +492,9 @@ __device__ __forceinline__ uint32_t list_pos(uint32_t v, uint32_t vg, uint32_t n
   return v < vg ? v >> lg : n_g + ((v - vg) >> lg);
 }
 
-template <bool kCached, bool kMassive = false, bool kAhead = false, bool kAheadCycles = false, bool kOne = false>
-__device__ __forceinline__ void flat_cycle(FlatShared<kOne>& sh, const OneRequest& one, uint64_t* gm, uint32_t words, EvState& s, bool busy,
+template <bool kCached, bool kMassive = false, bool kAhead = false, bool kAheadCycles = false, bool kOne = false,
+          class SH>
+__device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64_t* gm, uint32_t words, EvState& s, bool busy,
                                            bool& pend, Pending& pd, const Records& slots, uint64_t slot,
                                            const EndCache& ec, uint64_t wave_col, uint32_t lane,
                                            const QuarkMasses& qm = QuarkMasses{0.0, 0.0, 0.0, 0.0, 0.0}) {
@@ -886,14 +887,14 @@ __device__ __forceinline__ void flat_cycle(FlatShared<kOne>& sh, const OneReques
 // Plain one-launch form with the flattened mapping: wave w owns events
 // 64w .. 64w+63 of the batch (already started by k_me) from start to cutoff,
 // with no refill; finished lanes only stop contributing trial work.
-// kFour (massless, at most 64 partons): four resident waves per SIMD (128
+// kFour (massless, at most 128 partons): four resident waves per SIMD (128
 // registers, a few spilled; 9.2 + 1 KB of LDS), the trial constants
 // reloaded from LDS after the rounds (kAhead); otherwise three waves, the
 // massive instantiation reloading them too to fit without spilling.
 template <bool kMassive, bool kOne, bool kFour = false>
 __global__ void __launch_bounds__(64, kFour ? 4 : 3)
     k_shower_plain_flat(Records r, Summary sm, EventInputs in, uint32_t n, EndCache ec) {
-  __shared__ FlatShared<kOne> sh;
+  __shared__ FlatShared<kOne, kFour> sh;
   const OneRequest one{in.seed, in.first, in.cycle_limit};
   const uint32_t lane = threadIdx.x;
   const uint32_t words = mask_words(r.cap);
@@ -931,19 +932,18 @@ void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInp
   const EndCache ec{cache, r.cap};
   const dim3 g((n + 63) / 64), b(64);
   const size_t lds = flat_lds_bytes(r.cap);
-  // Massless events: the single-request LDS layout; up to 64 partons per
-  // record it leaves room for four blocks per SIMD, which the kernel fills
-  // with 128 registers by reloading its trial constants from LDS after the
-  // rounds (and loading the next round's cache entries ahead); above 64
-  // the masks make LDS the bound and the three-wave build is faster.  With
-  // quark masses: the per-event layout up to 64 partons, single-request
-  // above.
-  const bool wide = r.cap > kOneAboveCap;
+  // Massless events: the single-request LDS layout; up to 128 partons per
+  // record it leaves room for 3.5 to 4 blocks per SIMD, which the four-wave
+  // build fills with 128 registers by reloading its trial constants from
+  // LDS after the rounds (and loading the next round's cache entries
+  // ahead); above that the masks make LDS the bound and the three-wave
+  // build is faster.  With quark masses: the per-event layout up to 64
+  // partons, single-request above.
   if (in.massive) {
-    if (wide) hipLaunchKernelGGL((k_shower_plain_flat<true, true>), g, b, lds, st, r, s, in, n, ec);
+    if (r.cap > kOneAboveCap) hipLaunchKernelGGL((k_shower_plain_flat<true, true>), g, b, lds, st, r, s, in, n, ec);
     else hipLaunchKernelGGL((k_shower_plain_flat<true, false>), g, b, lds, st, r, s, in, n, ec);
   } else {
-    if (wide) hipLaunchKernelGGL((k_shower_plain_flat<false, true>), g, b, lds, st, r, s, in, n, ec);
+    if (r.cap > kFourMaxCap) hipLaunchKernelGGL((k_shower_plain_flat<false, true>), g, b, lds, st, r, s, in, n, ec);
     else hipLaunchKernelGGL((k_shower_plain_flat<false, true, true>), g, b, lds, st, r, s, in, n, ec);
   }
 }
@@ -951,15 +951,17 @@ void launch_shower_plain_flat(const Records& r, const Summary& s, const EventInp
 // kCached: A.cache holds an end cache per lane (always when in place; the
 // serving epochs' staging slots have one unless it could not be allocated).
 // In place (one request, kOne): four resident waves per SIMD for massless
-// events (128 registers, no spills), three with quark masses.  Three for
+// events with at most 128 partons (kFour: 128 registers, no spills; LDS
+// allows 3.5 at 128), three with more partons or with quark masses.  Three for
 // massless events in the serving epochs' cached staging slots (a few
 // spilled registers, outweighed by the third wave: 4000 requests/s of the
 // serving mix keep p99 below 40 ms instead of 80); two otherwise.
-template <bool kInPlace, bool kMassive, bool kCached, bool kOne = false>
-__global__ void __launch_bounds__(64, kOne && !kMassive ? 4 : (kInPlace || (kCached && !kMassive) ? 3 : 2))
+template <bool kInPlace, bool kMassive, bool kCached, bool kOne = false, bool kFour = false>
+__global__ void __launch_bounds__(64, kFour ? 4 : (kInPlace || (kCached && !kMassive) ? 3 : 2))
     k_shower_flat(PersistArgs A) {
   static_assert(kInPlace || !kOne, "one request per launch only in place");
-  __shared__ FlatShared<kOne> sh;
+  static_assert(kOne || !kFour, "four waves need the single-request layout");
+  __shared__ FlatShared<kOne, kFour> sh;
   const OneRequest one = kOne ? OneRequest{A.reqs[0].seed, A.reqs[0].first, A.reqs[0].cycle_limit}
                               : OneRequest{0ull, 0ull, 0u};
   const uint32_t lane = threadIdx.x;
@@ -1114,8 +1116,10 @@ BatchLayout carve_batch(void* base, uint64_t n, uint32_t cap, bool massive) {
 // always has one).
 const void* persistent_kernel(uint32_t mapping, bool in_place, bool massive, bool cached, uint32_t cap) {
   if (mapping == kMapFlat) {
-    if (in_place)
-      return massive ? (const void*)k_shower_flat<true, true, true, true> : (const void*)k_shower_flat<true, false, true, true>;
+    if (in_place && massive) return (const void*)k_shower_flat<true, true, true, true>;
+    if (in_place)  // four-wave build up to 128 partons (LDS-bound above)
+      return cap > kFourMaxCap ? (const void*)k_shower_flat<true, false, true, true>
+                               : (const void*)k_shower_flat<true, false, true, true, true>;
     if (cached)
       return massive ? (const void*)k_shower_flat<false, true, true> : (const void*)k_shower_flat<false, false, true>;
     return massive ? (const void*)k_shower_flat<false, true, false> : (const void*)k_shower_flat<false, false, false>;
