@@ -464,9 +464,9 @@ constexpr uint32_t kEmitDiv = 2;
 // kAhead: the owner's trial constants (key, scales, cycle) are reloaded from
 // LDS after the rounds, so their registers are free during them; for
 // massless cached events each round then loads the end-cache entries of the
-// next round's items while it reduces its winners (faster for the persistent
-// kernel, 1% slower for the plain one, which takes kAhead with quark masses
-// only, to fit three waves).
+// next round's items while it reduces its winners.  The four-wave builds
+// take it to fit 128 registers; at three waves the plain kernel takes it
+// with quark masses only (for massless events it measured 1% slower there).
 //
 // kAheadCycles (massless cached events): a wave cycle may evaluate K = 2^m
 // consecutive veto cycles of each event that makes trials.  A trial's scale
