@@ -169,8 +169,9 @@ struct OneRequest {
 constexpr uint32_t kOneAboveCap = 64;  // massive plain kernel: the per-event layout up to here
 constexpr uint32_t kFourMaxCap = 128;  // massless: four-wave builds up to here (LDS-bound above)
 
-template <bool kOne, bool kFour = false>
+template <bool kOne_, bool kFour_ = false, bool kRegW_ = false>
 struct FlatShared {
+  static constexpr bool kOne = kOne_, kFour = kFour_, kRegW = kRegW_;
   double lt[64], tcut[64], ltc[64], cfac[64];
   uint32_t slot[64];  // record columns (a launch covers fewer than 2^32)
   uint32_t key[4][kOne ? 1 : 64];
@@ -179,13 +180,13 @@ struct FlatShared {
   uint32_t sstart[65];              // per-owner offsets in the list of stale partons
   uint16_t item[1024 + 2];          // the cycle's items, owner << 10 | parton: gluon items (a gluon
                                     // twice, once per dipole end, when rounds allow), then quark items
-  uint16_t sitem[(kFour ? 100 : 384) + 2];  // the cycle's stale partons, owner << 10 | parton
+  uint16_t sitem[(kFour || kRegW ? 100 : 384) + 2];  // the cycle's stale partons, owner << 10 | parton
   double best_v[64];
   uint32_t best_idx[64];  // packed (i, k, K) << 6 | the lane whose item made it
   double best_c[2][64];   // per owner: those of its running best
   uint32_t counts[64];  // the cycle's trials (low 16 bits) and active ends (high 16 bits) per owner
   uint32_t climit[kOne ? 1 : 64];  // each event's cycle limit
-  double wsh[64];       // each event's shower weight (weighted veto)
+  double wsh[kRegW ? 1 : 64];  // each event's shower weight (weighted veto), unless held in a register
   union {
     double coef[2][64];     // massless: per item lane, its best end's trial coefficients (ca, cb)
     struct {
@@ -499,6 +500,11 @@ __device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64
                                            const EndCache& ec, uint64_t wave_col, uint32_t lane,
                                            const QuarkMasses& qm = QuarkMasses{0.0, 0.0, 0.0, 0.0, 0.0}) {
   const bool trial = busy && !pend;
+  // this lane's event's shower weight: in LDS, or (kRegW) in the event state
+  auto wsh = [&]() -> double& {
+    if constexpr (SH::kRegW) return s.wsh;
+    else return sh.wsh[lane];
+  };
   // the key and cycle limit of the event in column o of this wave
   // (kOne: the seed's words come from LDS at each use, so that the
   // compiler does not hold Philox's round keys in registers for the kernel)
@@ -811,7 +817,7 @@ __device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64
           break;
         }
         s.lt = sh.coef[0][pr];
-        sh.wsh[lane] *= sh.coef[1][pr];
+        wsh() *= sh.coef[1][pr];
         if (f == kPairAccept) {
           if (s.n == s.cap) {
             s.status = kOverflow;
@@ -836,7 +842,7 @@ __device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64
       best = sh.best_v[lane];
       W = massive_winner(trial_ctx(s), slots, slot, (int)(wi >> 14), (int)((wi >> 4) & 1023u), (int)(wi & 15u), qm);
     }
-    pend = veto_decide_massive(s, best, W, acc, pd, sh.wsh[lane]);
+    pend = veto_decide_massive(s, best, W, acc, pd, wsh());
   } else if (trial) {
     s.trials += sh.counts[lane] & 0xFFFFu;
     s.ends += sh.counts[lane] >> 16;
@@ -854,7 +860,7 @@ __device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64
       // computed from the records, the same numbers)
       end_from_coeffs(s.cfac, s.tcut, w.K, sh.best_c[0][lane], sh.best_c[1][lane], w);
     }
-    pend = veto_decide_drawn(s, best, w, acc, pd, sh.wsh[lane]);
+    pend = veto_decide_drawn(s, best, w, acc, pd, wsh());
   }
   // --- pending emissions, built together; the new parton's type goes into the mask
   const uint32_t n_pend = __popcll(__ballot(pend));
@@ -961,7 +967,10 @@ __global__ void __launch_bounds__(64, kFour ? 4 : (kInPlace || (kCached && !kMas
     k_shower_flat(PersistArgs A) {
   static_assert(kInPlace || !kOne, "one request per launch only in place");
   static_assert(kOne || !kFour, "four waves need the single-request layout");
-  __shared__ FlatShared<kOne, kFour> sh;
+  // three waves in place: the shower weight in a register and the short
+  // stale list, so that 256-parton records fit twelve blocks per CU
+  constexpr bool kRegW = kOne && !kFour;
+  __shared__ FlatShared<kOne, kFour, kRegW> sh;
   const OneRequest one = kOne ? OneRequest{A.reqs[0].seed, A.reqs[0].first, A.reqs[0].cycle_limit}
                               : OneRequest{0ull, 0ull, 0u};
   const uint32_t lane = threadIdx.x;
@@ -982,7 +991,8 @@ __global__ void __launch_bounds__(64, kFour ? 4 : (kInPlace || (kCached && !kMas
       slot = kInPlace ? ev : L;
       start_event<kInPlace>(s, A, A.reqs[req], ev, slot);
       if constexpr (!kOne) sh.climit[lane] = A.reqs[req].cycle_limit;
-      sh.wsh[lane] = 1.0;
+      if constexpr (kRegW) s.wsh = 1.0;
+      else sh.wsh[lane] = 1.0;
       mask_init(flat_gmask + (uint64_t)lane * words, flat_gmask + (uint64_t)(64 + lane) * words, words, A.slots,
                 slot, s.n);
       busy = true;
@@ -991,7 +1001,7 @@ __global__ void __launch_bounds__(64, kFour ? 4 : (kInPlace || (kCached && !kMas
     flat_cycle<kCached, kMassive, kInPlace, kCached && !kMassive, kOne>(
         sh, one, flat_gmask, words, s, busy, pend, pd, A.slots, slot, A.cache, L - lane, lane, A.reqs[req].qm);
     if (busy && s.status != kRunning) {
-      s.wsh = sh.wsh[lane];
+      if constexpr (!kRegW) s.wsh = sh.wsh[lane];
       finish_event<kInPlace>(s, A, A.reqs[req], ev, slot);
       busy = false;
     }
