@@ -168,7 +168,7 @@ def cpu_baseline(w, serial_events=160_000, per_proc=40_000):
             "sample": (f"{w.name}: serial ids [0,{serial_events}) and {cores} processes x {per_proc} "
                        f"consecutive ids; full pipeline (ME, shower, observables, histograms)"),
             "processes": f"{cores} processes on a host of {logical} logical CPUs ({usable} usable by this "
-                         f"process; the GPU box's share for one GPU is 16)",
+                         f"process)",
             "host_logical_cpus": logical, "host_usable_cpus": usable,
             "serial_value": serial_events / t_ser, "serial_cores": 1,
             "merged_histograms_equal_serial": same, "host_cpu": model or platform.processor()}
