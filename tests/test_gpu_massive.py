@@ -98,3 +98,18 @@ def test_options_together(ctx, oracle, persistent, masses):
     st = o["sum_i"][:, 1]
     assert (st == 5).any() and (o["sum_d"][:, 0] < 0).any()
     assert g["n_cycle_limit"] == int((st == 5).sum())
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("cap", [64, 65])
+def test_massive_layout_boundary(ctx, oracle, persistent, cap):
+    # with quark masses the kernels keep the per-event layout up to 64
+    # partons and take the single-request one above: the same events in both
+    n = 600
+    print(f"case massive layout boundary cap={cap} persistent={persistent}", flush=True)
+    g = ctx.generate(n, seed=29, ecm=91.2, t_cut=1.0, max_partons=cap, summary=True, records=True,
+                     persistent=persistent, mass_c=MC, mass_b=MB, t_over=20.0, cycle_limit=40)
+    o = oracle.generate(29, 0, n, 91.2, 1.0, cap, records=True, mass=TABLE, t_over=20.0, max_cycles=40)
+    rep, same = parity.compare(g, o, 91.2, n)
+    print(rep, flush=True)
+    parity.assert_parity(rep)

@@ -387,3 +387,20 @@ def test_cycles_ahead_same_bits_as_full_waves(ctx, persistent):
         np.testing.assert_array_equal(alone["sum_i"], full["sum_i"][:, :n])
         np.testing.assert_array_equal(alone["hash"], full["hash"][:n])
         np.testing.assert_array_equal(alone["sum_d"], full["sum_d"][:, :n])
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("cap", [64, 65, 128, 129])
+def test_layout_boundaries(ctx, oracle, persistent, cap):
+    # record capacities on either side of the kernels' layout choices (the
+    # per-event layout with quark masses up to 64 partons, the four-wave
+    # builds up to 128): the same events in every build
+    n = 400
+    print(f"case layout boundary cap={cap} persistent={persistent}", flush=True)
+    g = ctx.generate(n, seed=17, ecm=200.0, t_cut=0.5, max_partons=cap, summary=True, records=True,
+                     persistent=persistent, t_over=20.0, cycle_limit=60)
+    o = oracle.generate(17, 0, n, 200.0, 0.5, cap, records=True, t_over=20.0, max_cycles=60)
+    rep, same = parity.compare(g, o, 200.0, n)
+    print(rep, flush=True)
+    parity.assert_parity(rep)
+    assert rep["frac"] == 1.0
