@@ -575,8 +575,10 @@ hipEvent_t* timing_slot(vsh_ctx* ctx) {
 // workspace at `ws` (at least vsh_workspace_size bytes; nothing in it needs
 // to start at zero): matrix element, shower, observables and histogram
 // accumulated into dev_hist, then the summaries copied out in the caller's
-// [field][n_events] layout.  `timed`: record the stage events of
-// vsh_timing_start.  Launches and device-to-device copies only.
+// [field][n_events] layout; when n is a multiple of 64 that layout is the
+// kernels' own, so they work in the caller's summary buffers directly and
+// nothing is copied.  `timed`: record the stage events of vsh_timing_start.
+// Launches and device-to-device copies only.
 vsh_status plain_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void* ws, double* dev_hist,
                       double* dev_sum_d, int32_t* dev_sum_i, uint64_t* dev_hash, bool timed) {
   const uint64_t n = req->n_events;
@@ -595,6 +597,10 @@ vsh_status plain_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void
   in.ecm = req->ecm_per_event;
   in.tcut = req->tcut_per_event;
   Summary sum = L.sum;
+  const bool direct = stride == n;  // the caller's [field][n] arrays have the kernels' stride
+  if (direct && dev_sum_d) sum.d = dev_sum_d;
+  if (direct && dev_sum_i) sum.i = dev_sum_i;
+  if (direct && dev_hash) sum.hash = dev_hash;
   hipEvent_t* tev = timed ? timing_slot(ctx) : nullptr;
   if (tev) (void)hipEventRecord(tev[0], st);
   launch_me(L.rec, sum, in, (uint32_t)n, st);
@@ -607,6 +613,7 @@ vsh_status plain_into(vsh_ctx* ctx, const vsh_request* req, hipStream_t st, void
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return hip_fail(ctx, err, "kernel launch");
   // summaries out, in the caller's [field][n_events] layout
+  if (direct) return VSH_OK;
   if (dev_sum_d) {
     err = hipMemcpy2DAsync(dev_sum_d, n * 8, sum.d, stride * 8, n * 8, kNSumD, hipMemcpyDeviceToDevice, st);
     if (err != hipSuccess) return hip_fail(ctx, err, "summary copy");
