@@ -118,6 +118,15 @@ __device__ __forceinline__ double unit(uint32_t hi, uint32_t lo) {
   return one_m - 0x1.fffffffffffffp-1;
 }
 
+// the same 52 bits as an integer m (unit() is strictly increasing in m, so
+// uniforms compare as their m), and unit() of such an m
+__device__ __forceinline__ uint64_t unit_bits(uint32_t hi, uint32_t lo) {
+  return ((uint64_t)(hi >> 12) << 32) | lo;
+}
+__device__ __forceinline__ double unit_of_bits(uint64_t m) {
+  return unit((uint32_t)(m >> 32) << 12, (uint32_t)m);
+}
+
 // trial slot: splitter i, spectator k (both < 1024), block g of the kernel list
 __device__ __forceinline__ uint32_t trial_slot(uint32_t i, uint32_t k, uint32_t g) {
   return (i << 14) | (k << 4) | g;

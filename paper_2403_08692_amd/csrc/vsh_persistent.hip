@@ -188,7 +188,7 @@ struct FlatShared {
   uint32_t climit[kOne ? 1 : 64];  // each event's cycle limit
   double wsh[kRegW ? 1 : 64];  // each event's shower weight (weighted veto), unless held in a register
   union {
-    double coef[2][64];     // massless: per item lane, its best end's trial coefficients (ca, cb)
+    double coef[2][64];     // massless: per item lane, its best end's 1/ca, 1/cb
     struct {
       double mc[64], mb[64];  // massive: each event's charm and bottom masses
     };
@@ -290,13 +290,13 @@ __device__ __forceinline__ void entry_build(double cfac, double tcut, const Reco
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int k = e == 0 ? k1 : k2;
-    double ca = 0.0, cb = 0.0;
+    double ia = 0.0, ib = 0.0;  // 0: no end, or no phase space above the cutoff
     if (k != kNoPartner) {
       double q2, zm, zp, L;
-      if (!end_coeffs(cfac, tcut, pid_i, pi, r.load(k, slot), q2, zm, zp, L, ca, cb)) ca = cb = 0.0;
+      if (!end_coeffs(cfac, tcut, pid_i, pi, r.load(k, slot), q2, zm, zp, L, ia, ib)) ia = ib = 0.0;
     }
-    w[1 + 2 * e] = (uint64_t)__double_as_longlong(ca);
-    w[2 + 2 * e] = (uint64_t)__double_as_longlong(cb);
+    w[1 + 2 * e] = (uint64_t)__double_as_longlong(ia);
+    w[2 + 2 * e] = (uint64_t)__double_as_longlong(ib);
   }
 #pragma unroll
   for (int q = 0; q < kCacheWords; ++q) ent[q] = w[q];
@@ -398,21 +398,21 @@ __device__ __forceinline__ void item_trials(const TrialCtx& c, const Records& r,
     const int e = e_lo + q;
     const int k = e == 0 ? k1 : k2;
     if (e > e_hi || k == kNoPartner) continue;
-    double ca, cb;
+    double ia, ib;
     if (cached) {
-      ca = __longlong_as_double((long long)(e == 0 ? w[1] : w[3]));
-      cb = __longlong_as_double((long long)(e == 0 ? w[2] : w[4]));
+      ia = __longlong_as_double((long long)(e == 0 ? w[1] : w[3]));
+      ib = __longlong_as_double((long long)(e == 0 ? w[2] : w[4]));
     } else {
       double q2, zm, zp, L;
-      if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, r.load(k, slot), q2, zm, zp, L, ca, cb)) ca = cb = 0.0;
+      if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, r.load(k, slot), q2, zm, zp, L, ia, ib)) ia = ib = 0.0;
     }
-    if (ca == 0.0) continue;  // no phase space above the cutoff
+    if (ia == 0.0) continue;  // no phase space above the cutoff
     ends += 1;
-    const int K = end_draws(c, i, k, pid_i, ca, cb, best, trials);
+    const int K = end_draws(c, i, k, pid_i, ia, ib, best, trials);
     if (K >= 0) {
       widx = pack_trial(i, k, K);
-      wca = ca;
-      wcb = cb;
+      wca = ia;
+      wcb = ib;
     }
   }
 }
@@ -783,7 +783,7 @@ __device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64
         } else {
           Winner w{0.0, 0.0, 0.0, 0.0, -1, 0, 0};
           w.K = (int)((bi >> 6) & 15u);
-          end_from_coeffs(sh.cfac[o], sh.tcut[o], w.K, sh.best_c[0][lane], sh.best_c[1][lane], w);
+          end_from_inverse(sh.cfac[o], sh.tcut[o], w.K, sh.best_c[0][lane], sh.best_c[1][lane], w);
           t = exp(l);
           const U4 a = key_of(o).draw(cyc, kPurposeAccept, 0);
           z = trial_z(w, unit(a.x, a.y));
@@ -858,7 +858,7 @@ __device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64
       // the winning end's coefficients, passed on by the item that drew the
       // winner: its cache entry's numbers (or, without a cache, what the item
       // computed from the records, the same numbers)
-      end_from_coeffs(s.cfac, s.tcut, w.K, sh.best_c[0][lane], sh.best_c[1][lane], w);
+      end_from_inverse(s.cfac, s.tcut, w.K, sh.best_c[0][lane], sh.best_c[1][lane], w);
     }
     pend = veto_decide_drawn(s, best, w, acc, pd, wsh());
   }

@@ -33,9 +33,9 @@ struct Segment {
 
 // Per-lane cache of each parton's dipole ends (flattened mapping): entry
 // [(lane * cap) + a] of kCacheWords words holds parton a's id and ordered
-// spectators, then per end its trial coefficients (two; four by kernel class
-// for events with quark masses, in entries of kMCacheWords words).  Null: no
-// cache.
+// spectators, then per end its trial coefficients (the reciprocals of two;
+// four coefficients by kernel class for events with quark masses, in entries
+// of kMCacheWords words).  Null: no cache.
 constexpr int kCacheWords = 5;
 constexpr int kMCacheWords = 9;
 inline int cache_words(bool massive) { return massive ? kMCacheWords : kCacheWords; }

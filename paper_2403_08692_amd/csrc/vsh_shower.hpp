@@ -128,24 +128,29 @@ __device__ __forceinline__ bool end_limits(const P4& pi, const P4& pk, double tc
   return true;
 }
 
-// Trial coefficients c = alpha_s^over/(2 pi) * I of the dipole end (i, k):
-// for a quark end ca = its one kernel's; for a gluon end ca = g -> g g's; cb
-// = the common one of the five g -> f fbar kernels (kept for a quark end too:
-// the decision recovers the end's range from it).  False (and no
-// coefficients) for an end without phase space above the cutoff.
+// Trial coefficients c = alpha_s^over/(2 pi) * I of the dipole end (i, k),
+// returned as their reciprocals ia = 1/ca, ib = 1/cb, the factors a trial's
+// ln(R)/c is taken with: for a quark end ca = its one kernel's; for a gluon
+// end ca = g -> g g's; cb = the common one of the five g -> f fbar kernels
+// (kept for a quark end too: the decision recovers the end's range from it).
+// False (and no coefficients) for an end without phase space above the
+// cutoff.
 __device__ __forceinline__ bool end_coeffs(double cfac, double tcut, int pid_i, const P4& pi, const P4& pk,
-                                           double& q2, double& zm, double& zp, double& L, double& ca,
-                                           double& cb) {
+                                           double& q2, double& zm, double& zp, double& L, double& ia,
+                                           double& ib) {
   if (!end_limits(pi, pk, tcut, q2, zm, zp)) return false;
   L = log_fast((1.0 - zm) / (1.0 - zp));
-  ca = pid_i != kGluon ? cfac * ((2.0 * kCF) * L) : cfac * (kCA * L);
-  cb = cfac * ((0.5 * kTR) * (zp - zm));
+  const double ca = pid_i != kGluon ? cfac * ((2.0 * kCF) * L) : cfac * (kCA * L);
+  const double cb = cfac * ((0.5 * kTR) * (zp - zm));
+  ia = 1.0 / ca;
+  ib = 1.0 / cb;
   return true;
 }
 
 // The winning end's z range, mass and log range as the decision takes them:
-// recovered from its trial coefficients (the numbers the flattened kernels
-// cache), so that every form decides from the same bits.  cb / (cfac T_R/2)
+// recovered from its trial coefficients (the numbers the kernels keep: the
+// massive ends' own, the massless ends' reciprocals in end_from_inverse
+// below), so that every form decides from the same bits.  cb / (cfac T_R/2)
 // = z+ - z- = sqrt(1 - 4 t_C / Q^2), ca / (cfac C) = L with C = 2 C_F or C_A.
 // The divisions by cfac and t_C do not wait for the coefficients.  The
 // decision's arithmetic (this, trial_z, massless_ratio) is evaluated as
@@ -159,6 +164,19 @@ __device__ __forceinline__ void end_from_coeffs(double cfac, double tcut, int K,
   w.zm = 1.0 - w.zp;
   w.rq2 = ((1.0 - dz) * (1.0 + dz)) * rt4;
   w.L = ca * (rcf * (K <= 9 ? 1.0 / (2.0 * kCF) : 1.0 / kCA));
+}
+
+// The same from the reciprocals (ia, ib) that end_coeffs returns and the
+// massless forms keep: cb / (cfac T_R/2) = 1 / (ib cfac T_R/2), ca / (cfac C)
+// = 1 / (ia cfac C), one division each.
+__device__ __forceinline__ void end_from_inverse(double cfac, double tcut, int K, double ia, double ib, Winner& w) {
+#pragma clang fp contract(off)
+  const double rcf = 1.0 / cfac, rt4 = 0.25 / tcut;
+  const double dz = (rcf * (1.0 / (0.5 * kTR))) / ib;
+  w.zp = 0.5 * (1.0 + dz);
+  w.zm = 1.0 - w.zp;
+  w.rq2 = ((1.0 - dz) * (1.0 + dz)) * rt4;
+  w.L = (rcf * (K <= 9 ? 1.0 / (2.0 * kCF) : 1.0 / kCA)) / ia;
 }
 
 // True over trial density of a massless kernel at scale t = e^lt (App. A:
@@ -195,19 +213,23 @@ __device__ __forceinline__ double trial_z(const Winner& w, double uz) {
   return w.K <= 10 ? 1.0 - (1.0 - w.zm) * exp(-uz * w.L) : w.zm + (w.zp - w.zm) * uz;
 }
 
-// The trials of an end with coefficients (ca, cb): t_try = t R^(1/c)
-// compared as ln t + ln(R)/c (App. A, trial-scale equation), strict maximum
+// The trials of an end with coefficients (ca, cb) = (1/ia, 1/ib): t_try = t
+// R^(1/c) compared as ln t + ln(R)/c (App. A, trial-scale equation), taken
+// as ln t + ln(R) ia (within an ulp of the quotient), strict maximum
 // above the running best.  A gluon end's five g -> f fbar kernels share c, so
 // only their largest uniform needs a log.  Returns the winning kernel (or -1
 // if none beat `best`).  The first block serves a quark end's one kernel and
 // a gluon end's g -> g g alike, so lanes with quark and gluon ends share it;
 // only the gluon ends go on to blocks 1 and 2.
-__device__ __forceinline__ int end_draws(const TrialCtx& c, int i, int k, int pid_i, double ca, double cb,
+__device__ __forceinline__ int end_draws(const TrialCtx& c, int i, int k, int pid_i, double ia, double ib,
                                          double& best, uint32_t& trials) {
+  // the sums are not fused with the products: a scale drawn ahead (lt = 0)
+  // and chained later has the bits of one drawn at its own scale
+#pragma clang fp contract(off)
   // kernel list g->gg, g->d dbar, ..., g->b bbar: block g holds kernels 2g, 2g+1
   const bool gluon = pid_i == kGluon;
   const U4 d0 = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, 0));
-  const double l1 = c.lt + log_fast(unit(d0.x, d0.y)) / ca;
+  const double l1 = c.lt + log_fast(unit(d0.x, d0.y)) * ia;
   int K = -1;
   if (l1 > best) {
     best = l1;
@@ -215,22 +237,24 @@ __device__ __forceinline__ int end_draws(const TrialCtx& c, int i, int k, int pi
   }
   trials += gluon ? 6u : 1u;
   if (gluon) {
-    double um = unit(d0.z, d0.w);
+    // the five uniforms compared by their random bits (unit() is strictly
+    // increasing in them): only the largest is converted
+    uint64_t bm = unit_bits(d0.z, d0.w);
     int fm = 1;
 #pragma unroll  // the two Philox blocks interleave
     for (uint32_t g = 1; g < 3; ++g) {
       const U4 d = c.key.draw(c.cycle, kPurposeTrial, trial_slot(i, k, g));
-      const double u0 = unit(d.x, d.y), u1 = unit(d.z, d.w);
-      if (u0 > um) {  // first flavour wins ties, as in the kernel loop
-        um = u0;
+      const uint64_t b0 = unit_bits(d.x, d.y), b1 = unit_bits(d.z, d.w);
+      if (b0 > bm) {  // first flavour wins ties, as in the kernel loop
+        bm = b0;
         fm = 2 * g;
       }
-      if (u1 > um) {
-        um = u1;
+      if (b1 > bm) {
+        bm = b1;
         fm = 2 * g + 1;
       }
     }
-    const double lqq = c.lt + log_fast(um) / cb;
+    const double lqq = c.lt + log_fast(unit_of_bits(bm)) * ib;
     if (lqq > best) {
       best = lqq;
       K = 10 + fm;
@@ -243,15 +267,15 @@ __device__ __forceinline__ int end_draws(const TrialCtx& c, int i, int k, int pi
 __device__ __forceinline__ void end_trials(const TrialCtx& c, int i, int k, int pid_i, const P4& pi,
                                            const P4& pk, double& best, Winner& w, uint32_t& trials,
                                            uint32_t& ends) {
-  double q2, zm, zp, L, ca, cb;
-  if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, pk, q2, zm, zp, L, ca, cb)) return;
+  double q2, zm, zp, L, ia, ib;
+  if (!end_coeffs(c.cfac, c.tcut, pid_i, pi, pk, q2, zm, zp, L, ia, ib)) return;
   ends += 1;
-  const int K = end_draws(c, i, k, pid_i, ca, cb, best, trials);
+  const int K = end_draws(c, i, k, pid_i, ia, ib, best, trials);
   if (K >= 0) {
     w.i = i;
     w.k = k;
     w.K = K;
-    end_from_coeffs(c.cfac, c.tcut, K, ca, cb, w);
+    end_from_inverse(c.cfac, c.tcut, K, ia, ib, w);
   }
 }
 
