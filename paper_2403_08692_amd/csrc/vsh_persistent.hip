@@ -355,18 +355,19 @@ __device__ __forceinline__ void parton_trials_mcached(const TrialCtx& c, uint64_
   }
 }
 
-// Trials of one item of a massless event: ends e_lo .. e_hi of parton i (a
-// gluon's item takes one or both of its ends; a quark's both, the second
-// empty as a quark has one colour partner), from the parton's fresh cache
-// entry (cached; the stale rounds rebuilt it) or from the records.
 // An item's end-cache entry, when loaded ahead of its round.
 struct Ent5 {
   uint64_t w[kCacheWords];
 };
 
+// Trials of one item of a massless event: ends e_lo .. e_hi of parton i (a
+// gluon's item takes one or both of its ends; a quark's both, the second
+// empty as a quark has one colour partner), from the parton's fresh cache
+// entry (cached; the stale rounds rebuilt it) or from the records.  The
+// winning end's reciprocal coefficients come back in (wia, wib).
 __device__ __forceinline__ void item_trials(const TrialCtx& c, const Records& r, uint64_t slot, int i, int e_lo,
                                             int e_hi, const EndCache& ec, uint64_t col, bool cached, bool pre,
-                                            const Ent5& pw, double& best, uint32_t& widx, double& wca, double& wcb,
+                                            const Ent5& pw, double& best, uint32_t& widx, double& wia, double& wib,
                                             uint32_t& trials, uint32_t& ends) {
   uint64_t w[kCacheWords];
   int pid_i, k1, k2;
@@ -411,8 +412,8 @@ __device__ __forceinline__ void item_trials(const TrialCtx& c, const Records& r,
     const int K = end_draws(c, i, k, pid_i, ia, ib, best, trials);
     if (K >= 0) {
       widx = pack_trial(i, k, K);
-      wca = ia;
-      wcb = ib;
+      wia = ia;
+      wib = ib;
     }
   }
 }
@@ -697,7 +698,7 @@ __device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64
         // ahead: trials compared by ln(R)/c alone (the scale added at the decision)
         const TrialCtx c{key_of(o),
                          A ? 0.0 : sh.lt[o], sh.tcut[o], sh.ltc[o], sh.cfac[o], sh.cycle[o] + k};
-        double best = A ? -INFINITY : c.ltc, wca = 0.0, wcb = 0.0;
+        double best = A ? -INFINITY : c.ltc, wia = 0.0, wib = 0.0;
         uint32_t widx = kNoTrial;
         uint32_t nt = 0, ne = 0;
         if constexpr (kMassive && kCached)
@@ -707,13 +708,13 @@ __device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64
                               widx, nt, ne);
         else
           item_trials(c, slots, sh.slot[o], (int)i, e_lo, e_hi, ec, wave_col + o, kCached, kPre && pre, pw, best, widx,
-                      wca, wcb, nt, ne);
+                      wia, wib, nt, ne);
         if (widx != kNoTrial) {
           v = best;
           idx = (widx << 6) | lane;  // same order as widx: items of one pair differ in i
           if constexpr (!kMassive) {
-            sh.coef[0][lane] = wca;
-            sh.coef[1][lane] = wcb;
+            sh.coef[0][lane] = wia;
+            sh.coef[1][lane] = wib;
           }
         }
         atomicAdd(&sh.counts[pr], nt | (ne << 16));  // at most 12 x 1024 trials and 2048 ends per cycle
