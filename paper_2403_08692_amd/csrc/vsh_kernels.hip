@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
     if (ok) {
       const int status = sm.i[kSiStatus * sm.stride + e];
       const ObsOut o = reg_observables<kObsRegSlots, kMassive>(r, e, np, wmax, in.ecm_of(e), status, in);
-      if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e], fx);
+      if (o.status == kDone) hist_fill(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e], fx);
       for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
       sm.i[kSiStatus * sm.stride + e] = o.status;
     }
@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(256) k_obs(Records r, Summary sm, EventInputs 
       sc.z[to] = r.z[from];
     }
     const ObsOut o = scratch_observables<kMassive>(sc, t, np, in.ecm_of(e), status, in, r, e);
-    if (o.status == kDone) hist_fill_lds(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e], fx);
+    if (o.status == kDone) hist_fill(lh, o, sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e], fx);
     for (int h = 0; h < 7; ++h) sm.d[(kSdY23 + h) * sm.stride + e] = o.v[h];
     sm.i[kSiStatus * sm.stride + e] = o.status;
   }
@@ -348,23 +348,27 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
   constexpr uint32_t kGroups = 64 / G;
   constexpr uint64_t kGroupBits = G == 64 ? ~0ull : ((1ull << (G % 64)) - 1ull);
   extern __shared__ double lds[];
-  double* lh = lds;  // [kHistDoubles]
+  // this block's copy of the global histogram set (block b: copy b mod
+  // kHistCopies), filled with each event's atomics directly: FP64 sums, or
+  // the fixed-point integer cells.  A group block holds a few events, so an
+  // LDS set would cost more to clear and flush than it saves (k_obs, with
+  // 256 events per block, keeps one)
+  const uint32_t c0 = (blockIdx.x % kHistCopies) * (uint32_t)kHistDoubles;
   const uint32_t lane = threadIdx.x % G, grp = threadIdx.x / G;
-  double* pE = lh + kHistDoubles + (size_t)grp * 7 * slots;  // [slots] each
+  double* pE = lds + (size_t)grp * 7 * slots;  // [slots] each
   double* px = pE + slots;
   double* py = px + slots;
   double* pz = py + slots;
   double* ux = pz + slots;
   double* uy = ux + slots;
   double* uz = uy + slots;
-  uint16_t* list = (uint16_t*)(lh + kHistDoubles + (size_t)kGroups * 7 * slots) + (size_t)grp * slots;
+  uint16_t* list = (uint16_t*)(lds + (size_t)kGroups * 7 * slots) + (size_t)grp * slots;
   // cnt[cap - m] counts the events with at least m partons (see k_obs)
   const uint32_t q_lo = hi_n <= cap ? cnt[cap - hi_n] : 0u;
   const uint32_t q_hi = lo_n <= cap ? cnt[cap - lo_n] : 0u;
   // the grid is sized for the worst case: blocks without an event of this
   // range leave at once (the whole block, before touching LDS)
   if (q_lo + blockIdx.x * kGroups >= q_hi) return;
-  for (int a = threadIdx.x; a < kHistDoubles; a += 64) lh[a] = 0.0;
   const bool fixed = in.fixed_hist != 0;
   FixScale fxs{0, 0};
   if (fixed) fxs = fix_scale(sc);
@@ -542,7 +546,8 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
         }
         --m;
       }
-      if (lane == 0) hist_fill_lds(lh, ObsOut{{v[0], v[1], v[2], v[3], v[4], v[5], v[6]}, status},
+      double* gh = fixed ? reinterpret_cast<double*>(sc.ihist + c0) : sc.hcopy + c0;
+      if (lane == 0) hist_fill(gh, ObsOut{{v[0], v[1], v[2], v[3], v[4], v[5], v[6]}, status},
                                    sm.d[kSdW * sm.stride + e], sm.d[kSdCos * sm.stride + e], fx);
     }
 #pragma unroll
@@ -550,8 +555,6 @@ __global__ void __launch_bounds__(64) k_obs_group(Records r, Summary sm, EventIn
       if (h % G == lane) sm.d[(kSdY23 + h) * sm.stride + e] = v[h];
     if (lane == 0) sm.i[kSiStatus * sm.stride + e] = status;
   }
-  __syncthreads();
-  hist_flush(lh, sc, fixed, threadIdx.x, 64);
 }
 
 // The group launches for records of capacity cap: 16 lanes from
@@ -577,7 +580,7 @@ uint32_t obs_group_launches(uint32_t cap, bool massive, ObsGroupLaunch out[3]) {
 }
 
 size_t obs_group_lds(uint32_t g, uint32_t slots) {
-  return (size_t)kHistDoubles * 8 + (size_t)(64 / g) * slots * (7 * 8 + 2) + 64;
+  return (size_t)(64 / g) * slots * (7 * 8 + 2) + 64;
 }
 
 // ---------------------------------------------------------------------------

@@ -112,7 +112,7 @@ uint32_t obs_sort_blocks(uint64_t n);
 // blocks of the group launches (each block's groups stride over the events
 // of their size range): many short blocks end more evenly than a grid of
 // one or a few rounds of resident blocks (stress, 10^6 events: 8192 blocks
-// 9.3 ms, 32768 blocks 8.6 ms; empty blocks leave at once)
+// 7.3 ms, 32768 blocks 6.9 ms; empty blocks leave at once)
 constexpr uint32_t kObsWaveBlocks = 32768;
 
 }  // namespace vsh

@@ -490,9 +490,10 @@ __device__ __forceinline__ FixScale fix_scale(const Scratch& sc) {
   return FixScale{62 - (int)sc.lbits - e, 62 - (int)sc.lbits - 2 * e};
 }
 
-// Fill one event into an LDS histogram set [kNObs][kNHCol][3]: FP64 sums,
-// or (fx non-null) the fixed-point sums of fix_scale in the same LDS words.
-__device__ __forceinline__ void hist_fill_lds(double* lh, const ObsOut& o, double w, double cos_theta,
+// Fill one event into a histogram set [kNObs][kNHCol][3], in LDS or a
+// global copy: FP64 sums, or (fx non-null) the fixed-point sums of
+// fix_scale in the same words.
+__device__ __forceinline__ void hist_fill(double* lh, const ObsOut& o, double w, double cos_theta,
                                               const FixScale* fx = nullptr) {
   double vals[kNObs];
   vals[0] = o.v[0] > 0.0 ? log10(o.v[0]) : -INFINITY;
