@@ -167,16 +167,18 @@ __device__ __forceinline__ void end_from_coeffs(double cfac, double tcut, int K,
 }
 
 // The same from the reciprocals (ia, ib) that end_coeffs returns and the
-// massless forms keep: cb / (cfac T_R/2) = 1 / (ib cfac T_R/2), ca / (cfac C)
-// = 1 / (ia cfac C), one division each.
+// massless forms keep: z+ - z- = cb / (cfac T_R/2) = 1/X with X = ib cfac
+// T_R/2, L = ca / (cfac C) = 1/Y with Y = ia cfac C; with 1/(4 t_C) the three
+// quotients come from one division, r = 1/(X Y t_C).
 __device__ __forceinline__ void end_from_inverse(double cfac, double tcut, int K, double ia, double ib, Winner& w) {
 #pragma clang fp contract(off)
-  const double rcf = 1.0 / cfac, rt4 = 0.25 / tcut;
-  const double dz = (rcf * (1.0 / (0.5 * kTR))) / ib;
+  const double X = ib * (cfac * (0.5 * kTR)), Y = ia * (cfac * (K <= 9 ? 2.0 * kCF : kCA));
+  const double r = 1.0 / ((X * Y) * tcut);
+  const double dz = (Y * tcut) * r;
   w.zp = 0.5 * (1.0 + dz);
   w.zm = 1.0 - w.zp;
-  w.rq2 = ((1.0 - dz) * (1.0 + dz)) * rt4;
-  w.L = (rcf * (K <= 9 ? 1.0 / (2.0 * kCF) : 1.0 / kCA)) / ia;
+  w.rq2 = ((1.0 - dz) * (1.0 + dz)) * ((0.25 * (X * Y)) * r);
+  w.L = (X * tcut) * r;
 }
 
 // True over trial density of a massless kernel at scale t = e^lt (App. A:
