@@ -142,8 +142,9 @@ __device__ __forceinline__ bool end_coeffs(double cfac, double tcut, int pid_i, 
   L = log_fast((1.0 - zm) / (1.0 - zp));
   const double ca = pid_i != kGluon ? cfac * ((2.0 * kCF) * L) : cfac * (kCA * L);
   const double cb = cfac * ((0.5 * kTR) * (zp - zm));
-  ia = 1.0 / ca;
-  ib = 1.0 / cb;
+  const double r = 1.0 / (ca * cb);  // both reciprocals from one division
+  ia = cb * r;
+  ib = ca * r;
   return true;
 }
 
