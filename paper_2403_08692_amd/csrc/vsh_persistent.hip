@@ -178,9 +178,10 @@ struct FlatShared {
   uint32_t cycle[64];
   uint32_t gstart[65], qstart[65];  // per-owner item offsets in the gluon and quark sections
   uint32_t sstart[65];              // per-owner offsets in the list of stale partons
-  uint16_t item[1024 + 2];          // the cycle's items, owner << 10 | parton: gluon items (a gluon
-                                    // twice, once per dipole end, when rounds allow), then quark items
-  uint16_t sitem[(kFour || kRegW ? 100 : 384) + 2];  // the cycle's stale partons, owner << 10 | parton
+  // the cycle's items, owner << 10 | parton: gluon items (a gluon twice,
+  // once per dipole end, when rounds allow), then quark items, then the
+  // stale partons in what the items leave free (two spare entries)
+  uint16_t item[1024 + (kFour || kRegW ? 100 : 384) + 4];
   double best_v[64];
   uint32_t best_idx[64];  // packed (i, k, K) << 6 | the lane whose item made it
   double best_c[2][64];   // per owner: those of its running best
@@ -572,10 +573,10 @@ __device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64
   // longest per-event run of items in either section: a round's segmented
   // max needs only the shuffle steps below it
   const uint32_t gmax = kge * wave_max((uint32_t)(mine & kF)), qmax = wave_max((uint32_t)((mine >> 21) & kF));
-  // list lengths; each array has a spare entry past its end that takes the
-  // writes beyond it, so the listing loops need no branch
+  // list length; a spare entry past its end takes the writes beyond it, so
+  // the listing loops need no branch.  The stale partons follow the items.
   constexpr uint32_t kItems = sizeof(sh.item) / sizeof(sh.item[0]) - 2;
-  constexpr uint32_t kSItems = sizeof(sh.sitem) / sizeof(sh.sitem[0]) - 2;
+  const uint32_t sbase = n_g + n_q < kItems ? n_g + n_q : kItems;
   if (trial) {  // list this event's items (beyond the lists' lengths rounds search the offsets instead)
     uint32_t gpos = kge * (uint32_t)(excl & kF), qpos = n_g + (uint32_t)((excl >> 21) & kF),
              spos = (uint32_t)(excl >> 42);
@@ -595,7 +596,7 @@ __device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64
       }
       if (kCached)
         for (uint64_t x = mys[w] & live; x; x &= x - 1) {  // stale partons
-          sh.sitem[spos < kSItems ? spos : kSItems] = (uint16_t)(top | (uint32_t)__builtin_ctzll(x));
+          sh.item[sbase + spos < kItems ? sbase + spos : kItems] = (uint16_t)(top | (uint32_t)__builtin_ctzll(x));
           ++spos;
         }
     }
@@ -629,8 +630,8 @@ __device__ __forceinline__ void flat_cycle(SH& sh, const OneRequest& one, uint64
       const uint32_t at = r0 + lane;
       if (at < n_s) {
         uint32_t o, i;
-        if (at < kSItems) {
-          const uint32_t it = sh.sitem[at];
+        if (sbase + at < kItems) {
+          const uint32_t it = sh.item[sbase + at];
           o = it >> 10;
           i = it & 1023u;
         } else {
