@@ -159,8 +159,9 @@ __global__ void __launch_bounds__(256) k_shower_persistent(PersistArgs A) {
 // request: each event's key is make_keyed(seed, first + its record column)
 // and the cycle limit is one, so neither is kept per event in LDS (kOne),
 // and, for four waves per SIMD (kFour, records of at most 128 partons), the
-// stale list is shorter (its overflow takes the offsets' path): 9.2 KB + 1
-// KB of masks, sixteen blocks per CU at 64 partons, fourteen at 128.  With
+// item list (whose free tail holds the stale partons) is shorter (its
+// overflow takes the offsets' path): 9.2 KB + 1 KB of masks, sixteen blocks
+// per CU at 64 partons, fourteen at 128.  With
 // 256-parton records the layout leaves room for one more block per CU.
 struct OneRequest {
   uint64_t seed, first;
@@ -970,7 +971,7 @@ __global__ void __launch_bounds__(64, kFour ? 4 : (kInPlace || (kCached && !kMas
   static_assert(kInPlace || !kOne, "one request per launch only in place");
   static_assert(kOne || !kFour, "four waves need the single-request layout");
   // three waves in place: the shower weight in a register and the short
-  // stale list, so that 256-parton records fit twelve blocks per CU
+  // item list, so that 256-parton records fit twelve blocks per CU
   constexpr bool kRegW = kOne && !kFour;
   __shared__ FlatShared<kOne, kFour, kRegW> sh;
   const OneRequest one = kOne ? OneRequest{A.reqs[0].seed, A.reqs[0].first, A.reqs[0].cycle_limit}
